@@ -1,0 +1,223 @@
+/*
+ * ietidp.h -- C ABI of the MI355X (gfx950) tree-cotree gauged IETI-DP solver
+ * for 3D curl-curl magnetostatics on multi-patch subdomains.
+ *
+ * The method is the dual-primal isogeometric tearing and interconnecting
+ * solver of Mally & Merkel, "On Domain Decomposition for Magnetostatic
+ * Problems in 3D" (arXiv 2501.04340).  Section numbers and equation labels
+ * below refer to that paper.
+ *
+ * Conventions for every call:
+ *   - Return value 0 on success, a negative IETI_ERR_* code on failure;
+ *     ieti_last_error() then returns a thread-local, NUL-terminated message
+ *     (valid until the next failing call on the same thread).
+ *   - All pointer arguments are host pointers unless the name starts with d_
+ *     (device pointers on the handle's GPU).  Input arrays are read during
+ *     the call only and remain owned by the caller; the library copies what
+ *     it needs.  Output arrays are caller-allocated with the sizes reported by
+ *     ieti_get_sizes().
+ *   - A handle owns all its device memory and is not thread-safe; distinct
+ *     handles may be used from distinct threads.
+ *   - Floating-point data is IEEE binary64 unless stated otherwise; integer
+ *     maps are exact and identical to any conforming implementation of the
+ *     numbering described below.
+ */
+#ifndef IETIDP_H
+#define IETIDP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IETI_ABI_VERSION 1
+
+enum {
+  IETI_OK = 0,
+  IETI_ERR_INVALID_ARG = -1,      /* bad sizes, version mismatch, NULL pointer */
+  IETI_ERR_PARTITION = -2,        /* a subdomain is empty or not face-connected */
+  IETI_ERR_TREE = -3,             /* tree restricted to the Dirichlet boundary is not a tree (Section 3) */
+  IETI_ERR_NOT_SPD = -4,          /* non-positive pivot in a local factorisation; message names the subdomain */
+  IETI_ERR_BREAKDOWN = -5,        /* PCG breakdown: p^T F p <= 0 */
+  IETI_ERR_NOT_CONVERGED = -6,    /* maxit reached; outputs and stats are still filled */
+  IETI_ERR_HIP = -7,              /* a HIP runtime call failed */
+  IETI_ERR_STATE = -8             /* call order violated (e.g. solve before factor) */
+};
+
+enum { IETI_GEOM_BOX = 0, IETI_GEOM_ANNULUS = 1 };
+enum { IETI_PREC_FP64 = 0, IETI_PREC_MIXED = 1 };
+
+typedef struct ieti_handle ieti_handle; /* opaque, library-owned */
+
+/* Source current density J (Eq. strongMS).  Called with npts physical
+ * points xyz[3*i+0..2] (array of structures) and must write J at each point
+ * into out_vec3[3*i+0..2].  Called from the thread that calls
+ * ieti_assemble, any number of times, with arbitrary point batches. */
+typedef void (*ieti_field_fn)(const double* xyz, int64_t npts, double* out_vec3, void* user);
+
+/* Problem statement (Section 2): a multi-patch domain with patches on a
+ * structured P0 x P1 x P2 grid (patch (i,j,k) has index i + P0*(j + P1*k)),
+ * curl-conforming B-spline spaces of degree p with n_el elements per patch
+ * and direction, the grouping of patches into subdomains, a constant
+ * reluctivity per patch, the source J, and n x A = 0 on the whole boundary.
+ *   geom_kind  IETI_GEOM_BOX:     geom_params = {x0,x1,y0,y1,z0,z1}, uniform
+ *                                 axis-aligned patches.
+ *              IETI_GEOM_ANNULUS: direction 0 = azimuth (periodic, P0 equal
+ *                                 sectors, each one rational quadratic arc),
+ *                                 1 = radius, 2 = height;
+ *                                 geom_params = {z0, z1, r_0, ..., r_P1}.
+ *   periodic   1 where the patch grid wraps (annulus azimuth), else 0.
+ *   degree_p   degree of the H^1 B-splines (curl components have degree p-1
+ *              along their own direction), 1 <= p <= 6.
+ *   patch_to_subdomain [n_patches] values 0..N_sub-1, every id used.
+ *   nu_per_patch       [n_patches], > 0. */
+typedef struct {
+  int32_t version;             /* must equal IETI_ABI_VERSION */
+  int32_t geom_kind;
+  int32_t patches[3];
+  int32_t periodic[3];
+  double geom_params[16];
+  int32_t degree_p;
+  int32_t n_el;
+  const int32_t* patch_to_subdomain;
+  const double* nu_per_patch;
+  ieti_field_fn J;
+  void* J_user;
+} ieti_problem;
+
+typedef struct {
+  int32_t precision;   /* IETI_PREC_FP64 or IETI_PREC_MIXED (FP32 local factors) */
+  int32_t tile;        /* factor tile size: 0 = default (64) */
+  int32_t ordering;    /* 0 = nested dissection of r_V (default), 1 = natural order */
+  int32_t reserved;
+  void* hip_stream;    /* hipStream_t to run on; NULL = the library's own stream */
+} ieti_factor_opts;
+
+typedef struct {
+  double rtol;               /* stop when ||b - F lambda||_2 <= rtol ||b||_2 */
+  int32_t maxit;             /* PCG iteration cap (0 = 1000) */
+  int32_t check_every;       /* iterations between host convergence checks (0 = 8) */
+  const double* lambda0;     /* host initial multipliers [m_r] or NULL (= 0) */
+  int32_t use_graph;         /* 1 = replay PCG iterations from a captured hipGraph */
+  int32_t reserved;
+} ieti_solve_opts;
+
+typedef struct {
+  int64_t n_global;      /* n_g: free (non-Dirichlet, non-tree) global DOFs */
+  int64_t n_multipliers; /* m_r */
+  int64_t n_primal;      /* n_gp */
+  int64_t n_sub;
+  int32_t iters;         /* PCG iterations */
+  int32_t outer_iters;   /* iterative-refinement steps (MIXED) */
+  int32_t status;        /* IETI_OK or IETI_ERR_NOT_CONVERGED */
+  int32_t f_applies;     /* applications of the interface operator */
+  double rel_residual;   /* ||b - F lambda|| / ||b|| at exit */
+  double t_factor_s;     /* device time of ieti_factor */
+  double t_solve_s;      /* device time of ieti_solve (rhs + PCG + recovery) */
+  double t_pcg_s;        /* device time of the PCG loop */
+  double factor_flops;   /* algorithmic flops of the local factorisations */
+} ieti_stats;
+
+/* Assemble the problem on the host: spline spaces, Galerkin matrices of
+ * Eq. discrMS per subdomain, facets and wire basket (Section 2), edge
+ * weights and Kruskal spanning tree (Section 3, Fig. weights), primal DOFs
+ * (cotree edges of weight 2), multipliers (Eq. gloDP with redundant
+ * constraints removed), and uploads everything to the current HIP device.
+ *
+ * Numbering (exact, shared by every conforming implementation):
+ *   control nodes (I,J,K) on an N0 x N1 x N2 grid, N_d = P_d (n_el+p-1) + 1
+ *   (P_d (n_el+p-1) if periodic); edge (d,I,J,K) joins node (I,J,K) to
+ *   (I,J,K)+e_d; edge id = off_d + I + E_d0 (J + E_d1 K) with E_dc the number
+ *   of positions of direction-d edges along axis c, directions stacked
+ *   0,1,2.  Kruskal takes edges in increasing (weight, edge id).  Local DOFs
+ *   of a subdomain are its non-Dirichlet, non-tree, non-primal edges in
+ *   increasing edge id.  Multiplier rows are the remaining interface edges in
+ *   increasing edge id, +1 in the lower and -1 in the higher subdomain. */
+int ieti_assemble(const ieti_problem* prob, ieti_handle** out);
+
+/* Local factorisations and coarse setup on the GPU (Section 2.1): for every
+ * subdomain one partial Cholesky factorisation of the augmented matrix
+ * [K_rr K_rp E_I; K_pr K_pp 0; E_I^T 0 0] eliminating the r block, which
+ * yields the Dirichlet-preconditioner Schur complement S_rIrI (Eq. DirPrec),
+ * the local inverse block (K_rr^{-1})_{II}, the primal coupling
+ * (K_rr^{-1} K_rp)_{I} and the local coarse contribution; then the coarse
+ * matrix (minus F of the paper, positive definite) and its Cholesky factor.
+ * Returns IETI_ERR_NOT_SPD if a pivot is not positive. */
+int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts);
+
+/* Solve the interface problem (Eq. intProb) by PCG with the Dirichlet
+ * preconditioner (D_s = I), then recover a_p (Eq. coarseProb) and a_r
+ * (Eq. localProb).  a_out: host [n_edges] (every global edge; Dirichlet and
+ * tree edges are 0) or NULL.  stats may be NULL. */
+int ieti_solve(ieti_handle* h, const ieti_solve_opts* opts, double* a_out, ieti_stats* stats);
+
+/* As ieti_solve, but writes the coefficient vector to device memory
+ * d_a_out [n_edges] (e.g. a torch tensor's storage on the same device). */
+int ieti_solve_device(ieti_handle* h, const ieti_solve_opts* opts, double* d_a_out, ieti_stats* stats);
+
+/* sizes[0..7] = {n_edges, n_global, sum_n_r, m_r, n_gp, N_sub, n_nodes, max_n_I} */
+int ieti_get_sizes(const ieti_handle* h, int64_t* sizes);
+
+/* Exact integer maps (any argument may be NULL):
+ *   weight       [n_edges]  edge weights 1..5 (Fig. weights)
+ *   tree_mask    [n_edges]  1 = tree edge
+ *   dirichlet    [n_edges]  1 = Dirichlet edge
+ *   primal_edges [n_gp]     global primal edge ids, increasing
+ *   mult_rows    [m_r*5]    per row: edge id, k, l, local index in k, local index in l
+ *   sub_offsets  [N_sub+1]  offsets into sub_r_edges
+ *   sub_r_edges  [sum n_r]  remaining local DOFs of each subdomain (edge ids) */
+int ieti_get_maps(const ieti_handle* h, uint8_t* weight, uint8_t* tree_mask, uint8_t* dirichlet,
+                  int64_t* primal_edges, int64_t* mult_rows, int64_t* sub_offsets, int64_t* sub_r_edges);
+
+/* Subdomain k's assembled blocks in local numbering (r DOFs, then primal
+ * DOFs in increasing edge id) as CSR over the (n_r+n_p) x (n_r+n_p) matrix,
+ * and its load vector.  Call first with NULL arrays to get n and nnz. */
+int ieti_get_local_system(const ieti_handle* h, int32_t k, int64_t* n, int64_t* nnz,
+                          int64_t* indptr, int32_t* indices, double* values, double* load);
+
+/* Device results of ieti_factor for subdomain k (host copies), interface
+ * DOFs in multiplier-row order: S [n_I*n_I] the Schur complement S_rIrI,
+ * Sinv [n_I*n_I] = (K_rr^{-1})_{II}, both row-major; either may be NULL.
+ * n_I_out receives n_I. */
+int ieti_get_schur(const ieti_handle* h, int32_t k, int64_t* n_I_out, double* S, double* Sinv);
+
+/* One application q = F lambda of the interface operator (positive definite
+ * form, = -S of Eq. intProb) on host vectors [m_r]; for parity tests. */
+int ieti_apply_F(ieti_handle* h, const double* lambda, double* q);
+
+/* One application z = M_D^{-1} r of the Dirichlet preconditioner (Eq. DirPrec). */
+int ieti_apply_M(ieti_handle* h, const double* r, double* z);
+
+/* Right-hand side b = e - G S_c^{-1} d of the interface problem [m_r]. */
+int ieti_get_rhs(ieti_handle* h, double* b);
+
+/* Factorisation plan statistics, info[0..9] = {tile pool elements, S/Sinv
+ * elements, algorithmic flops of the tile factorisation, flops of the same
+ * factorisation done densely, sequential steps, update tasks, sum of n_I^2
+ * (interface-block entries read per operator application), number of
+ * interface slots (padded), max padded n_I, tile size}. */
+int ieti_get_plan_info(const ieti_handle* h, double* info);
+
+/* Kernel timing for roofline measurements.  enable = 1 clears the counters
+ * and records a pair of HIP events on the handle's stream around every
+ * launch of the interface GEMV (operator and preconditioner) and of the
+ * tile-update kernel of the factorisation; enable = 0 stops recording. */
+int ieti_set_profiling(ieti_handle* h, int32_t enable);
+
+/* times[0..5] = {GEMV launches, GEMV total ms, update launches, update total
+ * ms, update tasks executed, interface-block bytes read per GEMV launch}. */
+int ieti_get_kernel_times(const ieti_handle* h, double* times);
+
+/* Multipliers of the last solve [m_r]. */
+int ieti_get_lambda(const ieti_handle* h, double* lambda_out);
+
+void ieti_destroy(ieti_handle* h);
+
+const char* ieti_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IETIDP_H */

@@ -1,0 +1,784 @@
+// C ABI of the IETI-DP library: host assembly, device factorisation and
+// the PCG solve of the interface problem (Section 2.1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device/kernels.hpp"
+#include "host/model.hpp"
+#include "host/plan.hpp"
+#include "ietidp.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(IETI_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+template <class T>
+struct DBuf {
+  T* ptr = nullptr;
+  int64_t n = 0;
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    n = 0;
+  }
+};
+
+template <class T>
+int dalloc(DBuf<T>& b, int64_t n) {
+  b.release();
+  b.n = n;
+  if (n <= 0) return IETI_OK;
+  HIP_TRY(hipMalloc(&b.ptr, size_t(n) * sizeof(T)));
+  return IETI_OK;
+}
+
+template <class T>
+int dupload(DBuf<T>& b, const std::vector<T>& h) {
+  int rc = dalloc(b, int64_t(h.size()));
+  if (rc) return rc;
+  if (!h.empty()) HIP_TRY(hipMemcpy(b.ptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return IETI_OK;
+}
+
+}  // namespace
+
+struct ieti_handle {
+  ieti::Model model;
+  ieti::Plan plan;
+  int plan_T = 0, plan_ordering = -1;
+  bool uploaded = false, factored = false;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  int device = -1;
+  int64_t max_ld = 0;
+  int nblk = 0;
+  std::vector<int64_t> gemv_task_h;
+  // device buffers
+  DBuf<double> pool, scatter_val, S, Sinv, Phi, SPi, Spi_glob, G, H, Ht, I_sign, b_aug0, y;
+  DBuf<int64_t> scatter_dst, potrf, trsm, upd, copyS, xsinv, xphi, xspi, fdiag, ffull, fr, bdiag, bupd;
+  DBuf<int64_t> spi_ptr, spi_src, row_src, I_aug, A_aug, slot_phi_row, dsrc_ptr, dsrc_idx, krp_ptr, krp_pos;
+  DBuf<int64_t> out_src, out_edge, primal_edges, gemv_task;
+  DBuf<int32_t> I_row, I_sub, glob2loc, krp_col;
+  DBuf<double> krp_val;
+  DBuf<double> lam, r, z, p, q, v, b, e, dtil, w, t, pglob, part, scal, aout, tmp;
+  DBuf<int> flags;  // [0] err (factor), [1] done, [2] iters, [3] pcg err, [4] coarse err
+  int* flags_h = nullptr;
+  double factor_ms = 0.0;
+  double bnorm = 0.0;
+  std::vector<double> lambda_h;
+  bool rhs_ready = false;
+  // kernel timing (event pairs around launches); kind 0 = GEMV, 1 = update
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;  // (kind, index of start event)
+  double k_count[2] = {0, 0}, k_ms[2] = {0, 0}, upd_tasks = 0;
+
+  ~ieti_handle() {
+    DBuf<double>* ds[] = {&pool, &scatter_val, &S, &Sinv, &Phi, &SPi, &Spi_glob, &G, &H, &Ht, &I_sign, &b_aug0, &y,
+                          &krp_val, &lam, &r, &z, &p, &q, &v, &b, &e, &dtil, &w, &t, &pglob, &part, &scal, &aout,
+                          &tmp};
+    for (auto* d : ds) d->release();
+    DBuf<int64_t>* is[] = {&scatter_dst, &potrf, &trsm, &upd, &copyS, &xsinv, &xphi, &xspi, &fdiag, &ffull, &fr,
+                           &bdiag, &bupd, &spi_ptr, &spi_src, &row_src, &I_aug, &A_aug, &slot_phi_row, &dsrc_ptr,
+                           &dsrc_idx, &krp_ptr, &krp_pos, &out_src, &out_edge, &primal_edges, &gemv_task};
+    for (auto* d : is) d->release();
+    I_row.release();
+    I_sub.release();
+    glob2loc.release();
+    krp_col.release();
+    flags.release();
+    if (flags_h) (void)hipHostFree(flags_h);
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (ev2) (void)hipEventDestroy(ev2);
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+  }
+};
+
+namespace {
+
+int validate(const ieti_problem* pr) {
+  if (!pr) return fail(IETI_ERR_INVALID_ARG, "problem is NULL");
+  if (pr->version != IETI_ABI_VERSION) return fail(IETI_ERR_INVALID_ARG, "ABI version mismatch");
+  if (pr->geom_kind != IETI_GEOM_BOX && pr->geom_kind != IETI_GEOM_ANNULUS)
+    return fail(IETI_ERR_INVALID_ARG, "unknown geometry kind");
+  for (int d = 0; d < 3; ++d)
+    if (pr->patches[d] < 1) return fail(IETI_ERR_INVALID_ARG, "patch counts must be >= 1");
+  if (pr->degree_p < 1 || pr->degree_p > 6) return fail(IETI_ERR_INVALID_ARG, "degree must be in 1..6");
+  if (pr->n_el < 1) return fail(IETI_ERR_INVALID_ARG, "n_el must be >= 1");
+  if (!pr->patch_to_subdomain || !pr->nu_per_patch || !pr->J)
+    return fail(IETI_ERR_INVALID_ARG, "partition, reluctivity and source are required");
+  if (pr->geom_kind == IETI_GEOM_ANNULUS) {
+    if (!pr->periodic[0] || pr->periodic[1] || pr->periodic[2] || pr->patches[1] + 3 > 16)
+      return fail(IETI_ERR_INVALID_ARG, "annulus needs periodic azimuth and at most 13 radial patches");
+  } else {
+    for (int d = 0; d < 3; ++d)
+      if (pr->periodic[d]) return fail(IETI_ERR_INVALID_ARG, "box geometry cannot be periodic");
+  }
+  for (int d = 0; d < 3; ++d)
+    if (pr->periodic[d] && pr->patches[d] < 3) return fail(IETI_ERR_INVALID_ARG, "periodic direction needs >= 3 patches");
+  return IETI_OK;
+}
+
+int build_plan_if_needed(ieti_handle* h, int T, int ordering) {
+  if (h->plan_T == T && h->plan_ordering == ordering) return IETI_OK;
+  ieti::Error err{0, ""};
+  int rc = ieti::build_plan(h->model, T, ordering, h->plan, err);
+  if (rc) return fail(rc, err.msg);
+  h->plan_T = T;
+  h->plan_ordering = ordering;
+  h->uploaded = false;
+  h->factored = false;
+  return IETI_OK;
+}
+
+int upload(ieti_handle* h) {
+  if (h->uploaded) return IETI_OK;
+  const ieti::Plan& P = h->plan;
+  const ieti::Model& M = h->model;
+  HIP_TRY(hipGetDevice(&h->device));
+  if (!h->own_stream) HIP_TRY(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
+  if (!h->ev0) {
+    HIP_TRY(hipEventCreate(&h->ev0));
+    HIP_TRY(hipEventCreate(&h->ev1));
+    HIP_TRY(hipEventCreate(&h->ev2));
+  }
+  if (!h->flags_h) HIP_TRY(hipHostMalloc(&h->flags_h, 8 * sizeof(int)));
+  int rc = 0;
+#define UP(buf, vec) \
+  if ((rc = dupload(h->buf, vec))) return rc;
+  UP(scatter_dst, P.scatter_dst);
+  UP(scatter_val, P.scatter_val);
+  UP(potrf, P.potrf_task);
+  UP(trsm, P.trsm_task);
+  UP(upd, P.upd_task);
+  UP(copyS, P.copy_task);
+  UP(xsinv, P.xsinv_task);
+  UP(xphi, P.xphi_task);
+  UP(xspi, P.xspi_task);
+  UP(fdiag, P.fdiag_task);
+  UP(ffull, P.ffull_task);
+  UP(fr, P.fr_task);
+  UP(bdiag, P.bdiag_task);
+  UP(bupd, P.bupd_task);
+  UP(spi_ptr, P.spi_ptr);
+  UP(spi_src, P.spi_src);
+  for (int64_t v : P.row_src)
+    if (v < 0) return fail(IETI_ERR_TREE, "a multiplier row does not join two interface slots");
+  UP(row_src, P.row_src);
+  UP(I_aug, P.I_aug);
+  UP(A_aug, P.A_aug);
+  UP(I_row, P.I_row);
+  UP(I_sign, P.I_sign);
+  UP(I_sub, P.I_sub);
+  UP(glob2loc, P.glob2loc);
+  UP(krp_ptr, P.krp_ptr);
+  UP(krp_pos, P.krp_pos);
+  UP(krp_col, P.krp_col);
+  UP(krp_val, P.krp_val);
+  UP(out_src, P.out_src);
+  UP(out_edge, P.out_edge);
+  UP(primal_edges, M.primal_edges);
+  UP(b_aug0, P.b_aug0);
+  // per interface slot: start of its row in Phi
+  std::vector<int64_t> phirow(P.I_total, 0);
+  h->max_ld = 0;
+  h->gemv_task_h.clear();
+  for (const auto& sp : P.sub) {
+    for (int64_t t = 0; t < sp.nIp; ++t) phirow[sp.I_off + t] = sp.Phi_off + t * sp.nPp;
+    h->max_ld = std::max(h->max_ld, sp.nIp);
+    for (int64_t r0 = 0; r0 < sp.nIp; r0 += ieti::dev::GEMV_ROWS)
+      h->gemv_task_h.insert(h->gemv_task_h.end(), {sp.S_off + r0 * sp.nIp, sp.I_off + r0,
+                                                   std::min<int64_t>(ieti::dev::GEMV_ROWS, sp.nIp - r0), sp.nIp,
+                                                   sp.I_off});
+  }
+  UP(slot_phi_row, phirow);
+  UP(gemv_task, h->gemv_task_h);
+  // d~ assembly sources: for each global primal, the augmented indices of its local copies
+  {
+    std::vector<std::vector<int64_t>> src(M.n_gp);
+    for (size_t s = 0; s < P.P_glob.size(); ++s) src[P.P_glob[s]].push_back(P.P_aug[s]);
+    std::vector<int64_t> ptr(1, 0), idx;
+    for (auto& v : src) {
+      idx.insert(idx.end(), v.begin(), v.end());
+      ptr.push_back(int64_t(idx.size()));
+    }
+    UP(dsrc_ptr, ptr);
+    UP(dsrc_idx, idx);
+  }
+#undef UP
+  const int64_t m_r = M.m_r, n_gp = M.n_gp;
+  h->nblk = std::max(1, ieti::dev::combine_blocks(m_r));
+  if ((rc = dalloc(h->pool, P.pool_elems))) return rc;
+  if ((rc = dalloc(h->S, P.S_elems))) return rc;
+  if ((rc = dalloc(h->Sinv, P.S_elems))) return rc;
+  if ((rc = dalloc(h->Phi, std::max<int64_t>(P.Phi_elems, 1)))) return rc;
+  if ((rc = dalloc(h->SPi, std::max<int64_t>(P.SPi_elems, 1)))) return rc;
+  if ((rc = dalloc(h->Spi_glob, std::max<int64_t>(n_gp * n_gp, 1)))) return rc;
+  if ((rc = dalloc(h->G, std::max<int64_t>(m_r * n_gp, 1)))) return rc;
+  if ((rc = dalloc(h->H, std::max<int64_t>(m_r * n_gp, 1)))) return rc;
+  if ((rc = dalloc(h->Ht, std::max<int64_t>(m_r * n_gp, 1)))) return rc;
+  if ((rc = dalloc(h->y, P.r_total))) return rc;
+  const int64_t mm = std::max<int64_t>(m_r, 1), gg = std::max<int64_t>(n_gp, 1);
+  DBuf<double>* vecs_m[] = {&h->lam, &h->r, &h->z, &h->p, &h->q, &h->b, &h->e, &h->tmp};
+  for (auto* d : vecs_m)
+    if ((rc = dalloc(*d, mm))) return rc;
+  if ((rc = dalloc(h->v, std::max<int64_t>(P.I_total, 1)))) return rc;
+  DBuf<double>* vecs_g[] = {&h->dtil, &h->w, &h->t, &h->pglob};
+  for (auto* d : vecs_g)
+    if ((rc = dalloc(*d, gg))) return rc;
+  if ((rc = dalloc(h->part, 3 * int64_t(h->nblk)))) return rc;
+  if ((rc = dalloc(h->scal, 8))) return rc;
+  if ((rc = dalloc(h->flags, 8))) return rc;
+  if ((rc = dalloc(h->aout, M.mesh.n_edges))) return rc;
+  h->uploaded = true;
+  return IETI_OK;
+}
+
+hipStream_t pick_stream(ieti_handle* h, void* user) {
+  return user ? reinterpret_cast<hipStream_t>(user) : h->own_stream;
+}
+
+hipEvent_t next_event(ieti_handle* h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+// Record the start event of a timed launch; returns the slot or SIZE_MAX.
+size_t prof_begin(ieti_handle* h) {
+  if (!h->profiling) return SIZE_MAX;
+  const size_t i = h->ev_used;
+  hipEvent_t a = next_event(h), b = next_event(h);
+  if (!a || !b) return SIZE_MAX;
+  (void)hipEventRecord(a, h->stream);
+  return i;
+}
+
+void prof_end(ieti_handle* h, size_t slot, int kind) {
+  if (slot == SIZE_MAX) return;
+  (void)hipEventRecord(h->ev_pool[slot + 1], h->stream);
+  h->ev_marks.emplace_back(kind, slot);
+}
+
+// After the stream is synchronised: accumulate the recorded durations.
+void prof_collect(ieti_handle* h) {
+  for (const auto& m : h->ev_marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev_pool[m.second], h->ev_pool[m.second + 1]) == hipSuccess) {
+      h->k_count[m.first] += 1.0;
+      h->k_ms[m.first] += ms;
+    }
+  }
+  h->ev_marks.clear();
+  h->ev_used = 0;
+}
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(IETI_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return IETI_OK;
+}
+
+// F x = sum_k B_k Sinv_k B_k^T x + H (H^T x) -> out; optional partial dot(dotx, out)
+void apply_F(ieti_handle* h, const double* x, double* out, const double* dotx, double* partial, const int* done) {
+  namespace D = ieti::dev;
+  const auto& M = h->model;
+  hipStream_t s = h->stream;
+  const size_t ev = prof_begin(h);
+  D::gemv_interface(h->Sinv.ptr, h->gemv_task.ptr, int64_t(h->gemv_task_h.size() / 5), h->I_row.ptr, h->I_sign.ptr,
+                    x, h->v.ptr, done, h->max_ld, s);
+  prof_end(h, ev, 0);
+  if (M.n_gp > 0) D::coarse_project(h->Ht.ptr, M.n_gp, M.m_r, x, h->t.ptr, done, s);
+  D::combine(h->v.ptr, h->row_src.ptr, M.m_r, M.n_gp > 0 ? h->H.ptr : nullptr, h->t.ptr, M.n_gp, out, dotx, partial,
+             done, s);
+}
+
+void apply_M(ieti_handle* h, const double* x, double* out, const double* dotx, double* partial, const int* done) {
+  namespace D = ieti::dev;
+  const auto& M = h->model;
+  hipStream_t s = h->stream;
+  const size_t ev = prof_begin(h);
+  D::gemv_interface(h->S.ptr, h->gemv_task.ptr, int64_t(h->gemv_task_h.size() / 5), h->I_row.ptr, h->I_sign.ptr, x,
+                    h->v.ptr, done, h->max_ld, s);
+  prof_end(h, ev, 0);
+  D::combine(h->v.ptr, h->row_src.ptr, M.m_r, nullptr, nullptr, 0, out, dotx, partial, done, s);
+}
+
+// Forward solve with the factor over all augmented rows (full) or r rows only.
+void forward_solve(ieti_handle* h, bool full) {
+  namespace D = ieti::dev;
+  const auto& P = h->plan;
+  for (int64_t j = 0; j < P.n_steps; ++j) {
+    D::trsv_diag(h->pool.ptr, h->fdiag.ptr + 2 * P.fdiag_ptr[j], P.fdiag_ptr[j + 1] - P.fdiag_ptr[j], h->y.ptr, false,
+                 h->stream);
+    if (full)
+      D::trsv_update(h->pool.ptr, h->ffull.ptr + 3 * P.ffull_ptr[j], P.ffull_ptr[j + 1] - P.ffull_ptr[j], h->y.ptr,
+                     false, h->stream);
+    else
+      D::trsv_update(h->pool.ptr, h->fr.ptr + 3 * P.fr_ptr[j], P.fr_ptr[j + 1] - P.fr_ptr[j], h->y.ptr, false,
+                     h->stream);
+  }
+}
+
+void backward_solve(ieti_handle* h) {
+  namespace D = ieti::dev;
+  const auto& P = h->plan;
+  for (int64_t s = 0; s < P.n_steps; ++s) {
+    D::trsv_diag(h->pool.ptr, h->bdiag.ptr + 2 * P.bdiag_ptr[s], P.bdiag_ptr[s + 1] - P.bdiag_ptr[s], h->y.ptr, true,
+                 h->stream);
+    D::trsv_update(h->pool.ptr, h->bupd.ptr + 3 * P.bupd_ptr[s], P.bupd_ptr[s + 1] - P.bupd_ptr[s], h->y.ptr, true,
+                   h->stream);
+  }
+}
+
+// Right-hand side b = e - G S_c^{-1} d~ (positive definite form of Eq. intProb).
+int compute_rhs(ieti_handle* h) {
+  namespace D = ieti::dev;
+  const auto& P = h->plan;
+  const auto& M = h->model;
+  hipStream_t s = h->stream;
+  D::vec_copy(h->b_aug0.ptr, h->y.ptr, P.r_total, s);
+  forward_solve(h, true);
+  D::rhs_assemble(h->y.ptr, h->A_aug.ptr, h->row_src.ptr, M.m_r, h->e.ptr, s);
+  if (M.n_gp > 0) {
+    D::sum_sources(h->y.ptr, h->dsrc_ptr.ptr, h->dsrc_idx.ptr, M.n_gp, h->dtil.ptr, s);
+    D::tri_small(h->Spi_glob.ptr, M.n_gp, h->dtil.ptr, h->w.ptr, false, s);
+    D::axpy_rows(h->H.ptr, h->w.ptr, M.m_r, M.n_gp, h->e.ptr, h->b.ptr, s);
+  } else {
+    D::vec_copy(h->e.ptr, h->b.ptr, M.m_r, s);
+  }
+  h->rhs_ready = true;
+  return check_launch();
+}
+
+double host_dot(ieti_handle* h, const double* x, const double* y, int64_t n) {
+  if (n <= 0) return 0.0;
+  ieti::dev::dot_partial(x, y, n, h->part.ptr, h->stream);
+  std::vector<double> part(h->nblk);
+  (void)hipMemcpyAsync(part.data(), h->part.ptr, h->nblk * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  (void)hipStreamSynchronize(h->stream);
+  double s = 0.0;
+  for (double v : part) s += v;
+  return s;
+}
+
+int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, double* a_dev, ieti_stats* st) {
+  namespace D = ieti::dev;
+  if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
+  if (!h->factored) return fail(IETI_ERR_STATE, "ieti_solve called before ieti_factor");
+  const auto& M = h->model;
+  const auto& P = h->plan;
+  const double rtol = (opts && opts->rtol > 0) ? opts->rtol : 1e-8;
+  const int maxit = (opts && opts->maxit > 0) ? opts->maxit : 1000;
+  const int every = (opts && opts->check_every > 0) ? opts->check_every : 8;
+  hipStream_t s = h->stream;
+  const int64_t m_r = M.m_r;
+  HIP_TRY(hipEventRecord(h->ev0, s));
+  int rc = compute_rhs(h);
+  if (rc) return rc;
+  double* part_pq = h->part.ptr;
+  double* part_rr = h->part.ptr + h->nblk;
+  double* part_rz = h->part.ptr + 2 * h->nblk;
+  int* done = h->flags.ptr + 1;
+  int* iters = h->flags.ptr + 2;
+  int* perr = h->flags.ptr + 3;
+  HIP_TRY(hipMemsetAsync(h->flags.ptr + 1, 0, 3 * sizeof(int), s));
+  int it = 0;
+  double rr = 0.0;
+  const double bb = host_dot(h, h->b.ptr, h->b.ptr, m_r);
+  h->bnorm = std::sqrt(bb);
+  HIP_TRY(hipEventRecord(h->ev1, s));
+  int status = IETI_OK;
+  int applies = 0;
+  if (m_r > 0) {
+    // lambda_0, r_0 = b - F lambda_0
+    if (opts && opts->lambda0) {
+      HIP_TRY(hipMemcpyAsync(h->lam.ptr, opts->lambda0, m_r * sizeof(double), hipMemcpyHostToDevice, s));
+      apply_F(h, h->lam.ptr, h->q.ptr, nullptr, nullptr, nullptr);
+      ++applies;
+      D::axpby(h->b.ptr, h->q.ptr, h->r.ptr, 1.0, -1.0, m_r, s);
+    } else {
+      D::fill(h->lam.ptr, m_r, 0.0, s);
+      D::vec_copy(h->b.ptr, h->r.ptr, m_r, s);
+    }
+    rr = host_dot(h, h->r.ptr, h->r.ptr, m_r);
+    if (rr > rtol * rtol * bb && bb > 0.0) {
+      apply_M(h, h->r.ptr, h->z.ptr, nullptr, nullptr, nullptr);
+      D::vec_copy(h->z.ptr, h->p.ptr, m_r, s);
+      const double rz = host_dot(h, h->r.ptr, h->z.ptr, m_r);
+      const double sc[8] = {rz, 0.0, 0.0, 0.0, rtol * rtol * bb, rr, 0.0, 0.0};
+      HIP_TRY(hipMemcpyAsync(h->scal.ptr, sc, sizeof(sc), hipMemcpyHostToDevice, s));
+      for (it = 0; it < maxit;) {
+        const int par = it & 1;
+        apply_F(h, h->p.ptr, h->q.ptr, h->p.ptr, part_pq, done);
+        D::pcg_update_lambda(h->lam.ptr, h->r.ptr, h->p.ptr, h->q.ptr, m_r, part_pq, h->nblk, h->scal.ptr, par,
+                             part_rr, done, perr, s);
+        apply_M(h, h->r.ptr, h->z.ptr, h->r.ptr, part_rz, done);
+        D::pcg_update_p(h->p.ptr, h->z.ptr, m_r, part_rz, part_rr, h->nblk, h->scal.ptr, par, done, iters, maxit, s);
+        ++it;
+        if (it % every == 0 || it >= maxit) {
+          HIP_TRY(hipMemcpyAsync(h->flags_h, h->flags.ptr, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+          HIP_TRY(hipStreamSynchronize(s));
+          if (h->flags_h[1]) break;
+        }
+      }
+      rc = check_launch();
+      if (rc) return rc;
+      HIP_TRY(hipMemcpyAsync(h->flags_h, h->flags.ptr, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+      double sc_h[8];
+      HIP_TRY(hipMemcpyAsync(sc_h, h->scal.ptr, sizeof(sc_h), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      it = h->flags_h[2];
+      applies += it;
+      rr = sc_h[5];
+      if (h->flags_h[3]) return fail(IETI_ERR_BREAKDOWN, "PCG breakdown: p^T F p <= 0");
+      if (h->flags_h[1] != 1) status = IETI_ERR_NOT_CONVERGED;
+    }
+  }
+  HIP_TRY(hipEventRecord(h->ev2, s));
+  // ---- recovery: p = S_c^{-1}(d~ + G^T lambda), a_r = K_rr^{-1}(j_r - K_rp C p - B^T lambda)
+  if (M.n_gp > 0) {
+    // u = L_c^{-1} d~ + H^T lambda, p = L_c^{-T} u  (H = G L_c^{-T}, S_c = L_c L_c^T)
+    D::coarse_project(h->Ht.ptr, M.n_gp, m_r, h->lam.ptr, h->t.ptr, nullptr, s);
+    D::axpby(h->w.ptr, h->t.ptr, h->dtil.ptr, 1.0, 1.0, M.n_gp, s);
+    D::tri_small(h->Spi_glob.ptr, M.n_gp, h->dtil.ptr, h->pglob.ptr, true, s);
+  }
+  D::vec_copy(h->b_aug0.ptr, h->y.ptr, P.r_total, s);
+  D::recovery_rhs(h->y.ptr, h->krp_ptr.ptr, h->krp_pos.ptr, h->krp_col.ptr, h->krp_val.ptr,
+                  int64_t(P.krp_pos.size()), h->pglob.ptr, h->I_aug.ptr, h->I_row.ptr, h->I_sign.ptr, P.I_total,
+                  h->lam.ptr, s);
+  forward_solve(h, false);
+  backward_solve(h);
+  double* aout = a_dev ? a_dev : h->aout.ptr;
+  D::fill(aout, M.mesh.n_edges, 0.0, s);
+  D::write_output(h->y.ptr, h->out_src.ptr, h->out_edge.ptr, int64_t(P.out_src.size()), h->pglob.ptr,
+                  h->primal_edges.ptr, M.n_gp, aout, s);
+  hipEvent_t evend;
+  HIP_TRY(hipEventCreate(&evend));
+  HIP_TRY(hipEventRecord(evend, s));
+  rc = check_launch();
+  if (rc) return rc;
+  if (a_host) HIP_TRY(hipMemcpyAsync(a_host, aout, M.mesh.n_edges * sizeof(double), hipMemcpyDeviceToHost, s));
+  h->lambda_h.assign(m_r, 0.0);
+  if (m_r > 0) HIP_TRY(hipMemcpyAsync(h->lambda_h.data(), h->lam.ptr, m_r * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  prof_collect(h);
+  float ms_total = 0.f, ms_pcg = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms_total, h->ev0, evend));
+  HIP_TRY(hipEventElapsedTime(&ms_pcg, h->ev1, h->ev2));
+  HIP_TRY(hipEventDestroy(evend));
+  if (st) {
+    st->n_global = M.n_g;
+    st->n_multipliers = M.m_r;
+    st->n_primal = M.n_gp;
+    st->n_sub = M.n_sub;
+    st->iters = it;
+    st->outer_iters = 0;
+    st->status = status;
+    st->f_applies = applies;
+    st->rel_residual = h->bnorm > 0 ? std::sqrt(rr) / h->bnorm : 0.0;
+    st->t_factor_s = h->factor_ms * 1e-3;
+    st->t_solve_s = ms_total * 1e-3;
+    st->t_pcg_s = ms_pcg * 1e-3;
+    st->factor_flops = h->plan.flops;
+  }
+  if (status != IETI_OK) return fail(status, "PCG did not reach the tolerance within maxit");
+  return IETI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ieti_last_error(void) { return g_last_error.c_str(); }
+
+int ieti_assemble(const ieti_problem* prob, ieti_handle** out) {
+  if (!out) return fail(IETI_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate(prob);
+  if (rc) return rc;
+  auto* h = new ieti_handle();
+  ieti::Model& m = h->model;
+  m.prob = *prob;
+  const int64_t np = int64_t(prob->patches[0]) * prob->patches[1] * prob->patches[2];
+  m.part.assign(prob->patch_to_subdomain, prob->patch_to_subdomain + np);
+  m.nu.assign(prob->nu_per_patch, prob->nu_per_patch + np);
+  int maxs = -1;
+  for (int64_t q = 0; q < np; ++q) {
+    if (m.part[q] < 0) {
+      delete h;
+      return fail(IETI_ERR_INVALID_ARG, "negative subdomain id");
+    }
+    if (!(m.nu[q] > 0.0)) {
+      delete h;
+      return fail(IETI_ERR_INVALID_ARG, "reluctivity must be positive");
+    }
+    maxs = std::max(maxs, m.part[q]);
+  }
+  m.n_sub = maxs + 1;
+  {
+    std::vector<int> used(m.n_sub, 0);
+    for (int64_t q = 0; q < np; ++q) used[m.part[q]] = 1;
+    for (int k = 0; k < m.n_sub; ++k)
+      if (!used[k]) {
+        delete h;
+        return fail(IETI_ERR_PARTITION, "subdomain " + std::to_string(k) + " has no patch");
+      }
+  }
+  m.mesh.init(*prob);
+  ieti::Error err{0, ""};
+  rc = ieti::build_topology(m, err);
+  if (!rc) rc = ieti::assemble_local_systems(m, err);
+  if (rc) {
+    delete h;
+    return fail(rc, err.msg);
+  }
+  m.prob.J = nullptr;  // the callback is not kept beyond this call
+  m.prob.J_user = nullptr;
+  rc = build_plan_if_needed(h, ieti::dev::TILE, 0);
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return IETI_OK;
+}
+
+int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
+  namespace D = ieti::dev;
+  if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
+  const int T = (opts && opts->tile) ? opts->tile : D::TILE;
+  if (T != D::TILE) return fail(IETI_ERR_INVALID_ARG, "only tile size 64 is built");
+  if (opts && opts->precision != IETI_PREC_FP64) return fail(IETI_ERR_INVALID_ARG, "only FP64 factors are built");
+  int rc = build_plan_if_needed(h, T, opts ? opts->ordering : 0);
+  if (rc) return rc;
+  rc = upload(h);
+  if (rc) return rc;
+  h->stream = pick_stream(h, opts ? opts->hip_stream : nullptr);
+  hipStream_t s = h->stream;
+  const auto& P = h->plan;
+  const auto& M = h->model;
+  h->factored = false;
+  h->rhs_ready = false;
+  HIP_TRY(hipMemsetAsync(h->flags.ptr, 0, 8 * sizeof(int), s));
+  HIP_TRY(hipEventRecord(h->ev0, s));
+  D::fill(h->pool.ptr, P.pool_elems, 0.0, s);
+  D::scatter(h->pool.ptr, h->scatter_dst.ptr, h->scatter_val.ptr, int64_t(P.scatter_dst.size()), s);
+  for (int64_t j = 0; j < P.n_steps; ++j) {
+    D::copy_tiles(h->pool.ptr, h->copyS.ptr + 5 * P.copy_ptr[j], P.copy_ptr[j + 1] - P.copy_ptr[j], 1.0, h->S.ptr, s);
+    D::potrf_tiles(h->pool.ptr, h->potrf.ptr + 2 * P.potrf_ptr[j], P.potrf_ptr[j + 1] - P.potrf_ptr[j], h->flags.ptr,
+                   s);
+    D::trsm_tiles(h->pool.ptr, h->trsm.ptr + 2 * P.trsm_ptr[j], P.trsm_ptr[j + 1] - P.trsm_ptr[j], s);
+    const int64_t nupd = P.upd_ptr[j + 1] - P.upd_ptr[j];
+    const size_t ev = nupd > 0 ? prof_begin(h) : SIZE_MAX;
+    D::update_tiles(h->pool.ptr, h->upd.ptr + 3 * P.upd_ptr[j], nupd, s);
+    prof_end(h, ev, 1);
+    if (ev != SIZE_MAX) h->upd_tasks += double(nupd);
+  }
+  D::copy_tiles(h->pool.ptr, h->xsinv.ptr, int64_t(P.xsinv_task.size() / 5), -1.0, h->Sinv.ptr, s);
+  D::copy_tiles(h->pool.ptr, h->xphi.ptr, int64_t(P.xphi_task.size() / 5), -1.0, h->Phi.ptr, s);
+  D::copy_tiles(h->pool.ptr, h->xspi.ptr, int64_t(P.xspi_task.size() / 5), 1.0, h->SPi.ptr, s);
+  if (M.n_gp > 0) {
+    D::sum_sources(h->SPi.ptr, h->spi_ptr.ptr, h->spi_src.ptr, M.n_gp * M.n_gp, h->Spi_glob.ptr, s);
+    D::chol_small(h->Spi_glob.ptr, M.n_gp, h->flags.ptr + 4, s);
+    D::build_G(h->Phi.ptr, h->row_src.ptr, h->slot_phi_row.ptr, h->I_sub.ptr, h->glob2loc.ptr, M.m_r, M.n_gp, h->G.ptr,
+               s);
+    D::solve_rows_LT(h->Spi_glob.ptr, M.n_gp, h->G.ptr, M.m_r, h->H.ptr, h->Ht.ptr, s);
+  }
+  HIP_TRY(hipEventRecord(h->ev1, s));
+  rc = check_launch();
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(h->flags_h, h->flags.ptr, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  h->factor_ms = ms;
+  prof_collect(h);
+  if (h->flags_h[0] > 0)
+    return fail(IETI_ERR_NOT_SPD, "non-positive pivot in the local factorisation of subdomain " +
+                                      std::to_string(h->flags_h[0] - 1));
+  if (h->flags_h[4] > 0) return fail(IETI_ERR_NOT_SPD, "coarse matrix is not positive definite");
+  h->factored = true;
+  return IETI_OK;
+}
+
+int ieti_solve(ieti_handle* h, const ieti_solve_opts* opts, double* a_out, ieti_stats* stats) {
+  return solve_impl(h, opts, a_out, nullptr, stats);
+}
+
+int ieti_solve_device(ieti_handle* h, const ieti_solve_opts* opts, double* d_a_out, ieti_stats* stats) {
+  if (!d_a_out) return fail(IETI_ERR_INVALID_ARG, "d_a_out is NULL");
+  return solve_impl(h, opts, nullptr, d_a_out, stats);
+}
+
+int ieti_get_sizes(const ieti_handle* h, int64_t* sizes) {
+  if (!h || !sizes) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  const auto& m = h->model;
+  int64_t sum_r = 0, max_nI = 0;
+  for (const auto& s : m.sd) {
+    sum_r += int64_t(s.r_edges.size());
+    max_nI = std::max<int64_t>(max_nI, int64_t(s.I_local.size()));
+  }
+  const int64_t v[8] = {m.mesh.n_edges, m.n_g, sum_r, m.m_r, m.n_gp, m.n_sub, m.mesh.n_nodes, max_nI};
+  std::memcpy(sizes, v, sizeof(v));
+  return IETI_OK;
+}
+
+int ieti_get_maps(const ieti_handle* h, uint8_t* weight, uint8_t* tree_mask, uint8_t* dirichlet,
+                  int64_t* primal_edges, int64_t* mult_rows, int64_t* sub_offsets, int64_t* sub_r_edges) {
+  if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
+  const auto& m = h->model;
+  if (weight) std::copy(m.weight.begin(), m.weight.end(), weight);
+  if (tree_mask) std::copy(m.tree.begin(), m.tree.end(), tree_mask);
+  if (dirichlet) std::copy(m.dirichlet.begin(), m.dirichlet.end(), dirichlet);
+  if (primal_edges) std::copy(m.primal_edges.begin(), m.primal_edges.end(), primal_edges);
+  if (mult_rows) std::copy(m.mult.begin(), m.mult.end(), mult_rows);
+  int64_t acc = 0;
+  for (int k = 0; k < m.n_sub; ++k) {
+    if (sub_offsets) sub_offsets[k] = acc;
+    if (sub_r_edges) std::copy(m.sd[k].r_edges.begin(), m.sd[k].r_edges.end(), sub_r_edges + acc);
+    acc += int64_t(m.sd[k].r_edges.size());
+  }
+  if (sub_offsets) sub_offsets[m.n_sub] = acc;
+  return IETI_OK;
+}
+
+int ieti_get_local_system(const ieti_handle* h, int32_t k, int64_t* n, int64_t* nnz, int64_t* indptr,
+                          int32_t* indices, double* values, double* load) {
+  if (!h || !n || !nnz) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  if (k < 0 || k >= h->model.n_sub) return fail(IETI_ERR_INVALID_ARG, "subdomain out of range");
+  const auto& s = h->model.sd[k];
+  *n = s.n_loc;
+  *nnz = int64_t(s.indices.size());
+  if (indptr) std::copy(s.indptr.begin(), s.indptr.end(), indptr);
+  if (indices) std::copy(s.indices.begin(), s.indices.end(), indices);
+  if (values) std::copy(s.values.begin(), s.values.end(), values);
+  if (load) std::copy(s.load.begin(), s.load.end(), load);
+  return IETI_OK;
+}
+
+int ieti_get_schur(const ieti_handle* h, int32_t k, int64_t* n_I_out, double* S, double* Sinv) {
+  if (!h || !n_I_out) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  if (k < 0 || k >= h->model.n_sub) return fail(IETI_ERR_INVALID_ARG, "subdomain out of range");
+  if (!h->factored) return fail(IETI_ERR_STATE, "not factored");
+  const auto& sp = h->plan.sub[k];
+  *n_I_out = sp.nI;
+  std::vector<double> buf(sp.nIp * sp.nIp);
+  const DBuf<double>* srcs[2] = {&h->S, &h->Sinv};
+  double* dsts[2] = {S, Sinv};
+  for (int w = 0; w < 2; ++w) {
+    if (!dsts[w] || sp.nI == 0) continue;
+    HIP_TRY(hipMemcpy(buf.data(), srcs[w]->ptr + sp.S_off, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < sp.nI; ++i)
+      for (int64_t j = 0; j < sp.nI; ++j) dsts[w][i * sp.nI + j] = buf[i * sp.nIp + j];
+  }
+  return IETI_OK;
+}
+
+int ieti_apply_F(ieti_handle* h, const double* lambda, double* q) {
+  if (!h || !lambda || !q) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  if (!h->factored) return fail(IETI_ERR_STATE, "not factored");
+  const int64_t m_r = h->model.m_r;
+  if (m_r == 0) return IETI_OK;
+  HIP_TRY(hipMemcpyAsync(h->tmp.ptr, lambda, m_r * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  apply_F(h, h->tmp.ptr, h->q.ptr, nullptr, nullptr, nullptr);
+  int rc = check_launch();
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(q, h->q.ptr, m_r * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return IETI_OK;
+}
+
+int ieti_apply_M(ieti_handle* h, const double* r, double* z) {
+  if (!h || !r || !z) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  if (!h->factored) return fail(IETI_ERR_STATE, "not factored");
+  const int64_t m_r = h->model.m_r;
+  if (m_r == 0) return IETI_OK;
+  HIP_TRY(hipMemcpyAsync(h->tmp.ptr, r, m_r * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  apply_M(h, h->tmp.ptr, h->z.ptr, nullptr, nullptr, nullptr);
+  int rc = check_launch();
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(z, h->z.ptr, m_r * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return IETI_OK;
+}
+
+int ieti_get_rhs(ieti_handle* h, double* b) {
+  if (!h || !b) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  if (!h->factored) return fail(IETI_ERR_STATE, "not factored");
+  int rc = compute_rhs(h);
+  if (rc) return rc;
+  const int64_t m_r = h->model.m_r;
+  if (m_r > 0) HIP_TRY(hipMemcpyAsync(b, h->b.ptr, m_r * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return IETI_OK;
+}
+
+int ieti_get_plan_info(const ieti_handle* h, double* info) {
+  if (!h || !info) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  const auto& P = h->plan;
+  double sum_nI2 = 0.0, max_ld = 0.0;
+  for (const auto& sp : P.sub) {
+    sum_nI2 += double(sp.nI) * double(sp.nI);
+    max_ld = std::max(max_ld, double(sp.nIp));
+  }
+  const double v[10] = {double(P.pool_elems), double(P.S_elems), P.flops, P.dense_flops, double(P.n_steps),
+                        double(P.n_update_tasks), sum_nI2, double(P.I_total), max_ld, double(P.T)};
+  std::memcpy(info, v, sizeof(v));
+  return IETI_OK;
+}
+
+int ieti_set_profiling(ieti_handle* h, int32_t enable) {
+  if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
+  h->profiling = enable != 0;
+  h->k_count[0] = h->k_count[1] = 0.0;
+  h->k_ms[0] = h->k_ms[1] = 0.0;
+  h->upd_tasks = 0.0;
+  h->ev_marks.clear();
+  h->ev_used = 0;
+  return IETI_OK;
+}
+
+int ieti_get_kernel_times(const ieti_handle* h, double* times) {
+  if (!h || !times) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  double bytes = 0.0;
+  for (const auto& sp : h->plan.sub) bytes += double(sp.nIp) * double(sp.nIp) * sizeof(double);
+  const double v[6] = {h->k_count[0], h->k_ms[0], h->k_count[1], h->k_ms[1], h->upd_tasks, bytes};
+  std::memcpy(times, v, sizeof(v));
+  return IETI_OK;
+}
+
+int ieti_get_lambda(const ieti_handle* h, double* lambda_out) {
+  if (!h || !lambda_out) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  std::copy(h->lambda_h.begin(), h->lambda_h.end(), lambda_out);
+  return IETI_OK;
+}
+
+void ieti_destroy(ieti_handle* h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,645 @@
+// gfx950 kernels of the tree-cotree gauged IETI-DP hot path.
+//
+// Factor side: batched right-looking tile Cholesky over 64x64 FP64 tiles
+// (column-major inside a tile) of every subdomain's augmented matrix,
+// driven by host-built task lists (one launch per kernel kind and step).
+// The trailing update C -= A B^T runs on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64).
+//
+// Solve side: the interface operator F = sum_k B_k (K_rr^(k))^{-1}_{II} B_k^T
+// + G S_c^{-1} G^T and the Dirichlet preconditioner sum_k B_k S_rIrI B_k^T
+// (Section 2.1, Eqs. intProb and DirPrec) as batched dense GEMVs over the
+// per-subdomain interface blocks with the signed Boolean gather fused in,
+// followed by a deterministic two-term combine per multiplier row.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace ieti {
+namespace dev {
+
+namespace {
+
+constexpr int T = TILE;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over a 256-thread block, result valid in every thread (fixed order).
+__device__ inline double block_sum256(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  const double s = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return s;
+}
+
+// Reduce a partials array of length n (small) in a fixed order by one block.
+__device__ inline double reduce_partials(const double* part, int n, double* red) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) v += part[i];
+  return block_sum256(v, red);
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_scatter(double* pool, const int64_t* dst, const double* val, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    pool[dst[i]] = val[i];
+}
+
+// Unblocked Cholesky of one diagonal tile in LDS.  A non-positive pivot
+// records the subdomain (1-based) in err and continues with pivot 1.
+__global__ __launch_bounds__(256) void k_potrf(double* pool, const int64_t* task, int* err) {
+  __shared__ double A[T][T + 1];
+  __shared__ int bad;
+  const int64_t off = task[2 * blockIdx.x];
+  const int sub = int(task[2 * blockIdx.x + 1]);
+  double* t = pool + off;
+  for (int idx = threadIdx.x; idx < T * T; idx += 256) A[idx & (T - 1)][idx >> 6] = t[idx];
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < T; ++k) {
+    const double d = A[k][k];
+    const double piv = d > 0.0 ? sqrt(d) : 1.0;
+    if (!(d > 0.0) && threadIdx.x == 0) bad = 1;
+    __syncthreads();
+    if (threadIdx.x < T) {
+      const int i = threadIdx.x;
+      if (i > k) A[i][k] /= piv;
+      else if (i == k) A[k][k] = piv;
+    }
+    __syncthreads();
+    const int n = T - 1 - k;
+    for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+      const int i = k + 1 + idx / n, j = k + 1 + idx % n;
+      if (j <= i) A[i][j] -= A[i][k] * A[j][k];
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < T * T; idx += 256) {
+    const int a = idx & (T - 1), b = idx >> 6;
+    t[idx] = (a >= b) ? A[a][b] : 0.0;
+  }
+  if (threadIdx.x == 0 && bad) atomicMax(err, sub + 1);
+}
+
+// X = A L^{-T} for an off-diagonal tile A below the factored diagonal tile L.
+__global__ __launch_bounds__(256) void k_trsm(double* pool, const int64_t* task) {
+  __shared__ double L[T][T + 1];
+  __shared__ double X[T][T + 1];
+  const double* Lg = pool + task[2 * blockIdx.x];
+  double* Ag = pool + task[2 * blockIdx.x + 1];
+  for (int idx = threadIdx.x; idx < T * T; idx += 256) {
+    const int a = idx & (T - 1), b = idx >> 6;
+    L[a][b] = Lg[idx];
+    X[a][b] = Ag[idx];
+  }
+  __syncthreads();
+  for (int c = 0; c < T; ++c) {
+    if (threadIdx.x < T) X[threadIdx.x][c] /= L[c][c];
+    __syncthreads();
+    const int n = T - 1 - c;
+    for (int idx = threadIdx.x; idx < T * n; idx += 256) {
+      const int r = idx & (T - 1), cc = c + 1 + (idx >> 6);
+      X[r][cc] -= X[r][c] * L[cc][c];
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < T * T; idx += 256) Ag[idx] = X[idx & (T - 1)][idx >> 6];
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// C -= A B^T for 64x64 tiles on the FP64 matrix cores.  Four waves, each
+// owning a 32x32 quadrant as 2x2 blocks of 16x16 MFMA accumulators.
+// Operand layout of v_mfma_f64_16x16x4f64 (per lane l):
+//   A: row l%16, k l/16;  B: k l/16, col l%16;  D (accumulator element r):
+//   row l/16 + 4r, col l%16 (checked on gfx950 with an in-bounds probe).
+__global__ __launch_bounds__(256) void k_update(double* pool, const int64_t* task) {
+  __shared__ __align__(16) double As[T * T];
+  __shared__ __align__(16) double Bs[T * T];
+  const int64_t* tk = task + 3 * blockIdx.x;
+  double* C = pool + tk[0];
+  const double* A = pool + tk[1];
+  const double* B = pool + tk[2];
+  const double2* A2 = reinterpret_cast<const double2*>(A);
+  const double2* B2 = reinterpret_cast<const double2*>(B);
+  double2* As2 = reinterpret_cast<double2*>(As);
+  double2* Bs2 = reinterpret_cast<double2*>(Bs);
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int idx = threadIdx.x + 256 * s;
+    As2[idx] = A2[idx];
+    Bs2[idx] = B2[idx];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  v4d acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
+#pragma unroll
+  for (int kk = 0; kk < T / 4; ++kk) {
+    const int k = 4 * kk + lk;
+    const double a0 = As[k * T + 32 * wr + li];
+    const double a1 = As[k * T + 32 * wr + 16 + li];
+    const double b0 = Bs[k * T + 32 * wc + li];
+    const double b1 = Bs[k * T + 32 * wc + 16 + li];
+    acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+    acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+    acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+    acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+  }
+  const int r0 = 32 * wr + lk, c0 = 32 * wc + li;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    C[(c0)*T + r0 + 4 * r] -= acc00[r];
+    C[(c0 + 16) * T + r0 + 4 * r] -= acc01[r];
+    C[(c0)*T + r0 + 16 + 4 * r] -= acc10[r];
+    C[(c0 + 16) * T + r0 + 16 + 4 * r] -= acc11[r];
+  }
+}
+
+// Copy (scaled) tiles into dense row-major blocks; optional mirrored copy.
+__global__ void k_copy_tiles(const double* pool, const int64_t* task, double scale, double* dst) {
+  const int64_t* tk = task + 5 * blockIdx.x;
+  const double* t = pool + tk[0];
+  const int64_t d0 = tk[1], dt = tk[2], ld = tk[3];
+  const bool diag = tk[4] != 0;
+  for (int idx = threadIdx.x; idx < T * T; idx += blockDim.x) {
+    const int a = idx & (T - 1), b = idx >> 6;
+    if (diag && a < b) continue;
+    const double v = scale * t[idx];
+    dst[d0 + a * ld + b] = v;
+    if (dt >= 0 && !(diag && a == b)) dst[dt + b * ld + a] = v;
+  }
+}
+
+// Diagonal-tile triangular solve on a 64-vector of the augmented vectors.
+__global__ __launch_bounds__(64) void k_trsv_diag(const double* pool, const int64_t* task, double* y, int transposed) {
+  __shared__ double L[T][T + 1];
+  __shared__ double v[T];
+  const double* Lg = pool + task[2 * blockIdx.x];
+  double* yv = y + task[2 * blockIdx.x + 1];
+  for (int idx = threadIdx.x; idx < T * T; idx += 64) L[idx & (T - 1)][idx >> 6] = Lg[idx];
+  v[threadIdx.x] = yv[threadIdx.x];
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (!transposed) {
+    for (int c = 0; c < T; ++c) {
+      if (i == c) v[c] /= L[c][c];
+      __syncthreads();
+      if (i > c) v[i] -= L[i][c] * v[c];
+      __syncthreads();
+    }
+  } else {
+    for (int c = T - 1; c >= 0; --c) {
+      if (i == c) v[c] /= L[c][c];
+      __syncthreads();
+      if (i < c) v[i] -= L[c][i] * v[c];
+      __syncthreads();
+    }
+  }
+  yv[i] = v[i];
+}
+
+// y_dst -= L y_src (forward) or y_dst -= L^T y_src (transposed), one tile.
+__global__ __launch_bounds__(256) void k_trsv_update(const double* pool, const int64_t* task, double* y,
+                                                     int transposed) {
+  __shared__ double L[T][T + 1];
+  __shared__ double x[T];
+  const int64_t* tk = task + 3 * blockIdx.x;
+  const double* Lg = pool + tk[0];
+  double* yd = y + tk[1];
+  const double* ys = y + tk[2];
+  for (int idx = threadIdx.x; idx < T * T; idx += 256) L[idx & (T - 1)][idx >> 6] = Lg[idx];
+  if (threadIdx.x < T) x[threadIdx.x] = ys[threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x < T) {
+    const int a = threadIdx.x;
+    double s = 0.0;
+    if (!transposed) {
+      for (int b = 0; b < T; ++b) s += L[a][b] * x[b];
+    } else {
+      for (int b = 0; b < T; ++b) s += L[b][a] * x[b];
+    }
+    yd[a] -= s;
+  }
+}
+
+__global__ void k_sum_sources(const double* src, const int64_t* ptr, const int64_t* idx, int64_t nout, double* out) {
+  const int64_t o = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (o >= nout) return;
+  double s = 0.0;
+  for (int64_t q = ptr[o]; q < ptr[o + 1]; ++q) s += src[idx[q]];
+  out[o] = s;
+}
+
+__global__ void k_build_G(const double* Phi, const int64_t* row_src, const int64_t* slot_phi_row,
+                          const int32_t* I_sub, const int32_t* glob2loc, int64_t m_r, int64_t n_gp, double* G) {
+  const int64_t gid = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (gid >= m_r * n_gp) return;
+  const int64_t row = gid / n_gp, c = gid % n_gp;
+  double g = 0.0;
+  for (int side = 0; side < 2; ++side) {
+    const int64_t slot = row_src[2 * row + side];
+    const int k = I_sub[slot];
+    const int loc = glob2loc[int64_t(k) * n_gp + c];
+    if (loc >= 0) g += (side == 0 ? 1.0 : -1.0) * Phi[slot_phi_row[slot] + loc];
+  }
+  G[gid] = g;
+}
+
+// Cholesky of a small dense row-major matrix by one block (lower factor).
+__global__ __launch_bounds__(256) void k_chol_small(double* A, int64_t n, int* err) {
+  for (int64_t k = 0; k < n; ++k) {
+    const double d = A[k * n + k];
+    const double piv = d > 0.0 ? sqrt(d) : 1.0;
+    if (!(d > 0.0) && threadIdx.x == 0) atomicMax(err, 1);
+    __syncthreads();
+    for (int64_t i = k + threadIdx.x; i < n; i += 256) {
+      if (i == k) A[k * n + k] = piv;
+      else A[i * n + k] /= piv;
+    }
+    __syncthreads();
+    const int64_t m = n - 1 - k;
+    for (int64_t idx = threadIdx.x; idx < m * m; idx += 256) {
+      const int64_t i = k + 1 + idx / m, j = k + 1 + idx % m;
+      if (j <= i) A[i * n + j] -= A[i * n + k] * A[j * n + k];
+    }
+    __syncthreads();
+  }
+  for (int64_t idx = threadIdx.x; idx < n * n; idx += 256) {
+    const int64_t i = idx / n, j = idx % n;
+    if (j > i) A[idx] = 0.0;
+  }
+}
+
+// H[row] = G[row] L^{-T} (each row independently), also stored transposed.
+__global__ void k_solve_rows_LT(const double* L, int64_t n, const double* G, int64_t m, double* H, double* Ht) {
+  const int64_t row = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (row >= m) return;
+  for (int64_t c = 0; c < n; ++c) {
+    double s = G[row * n + c];
+    for (int64_t q = 0; q < c; ++q) s -= H[row * n + q] * L[c * n + q];
+    const double h = s / L[c * n + c];
+    H[row * n + c] = h;
+    Ht[c * m + row] = h;
+  }
+}
+
+__global__ void k_tri_small(const double* L, int64_t n, const double* in, double* out, int transposed) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  if (!transposed) {
+    for (int64_t c = 0; c < n; ++c) {
+      double s = in[c];
+      for (int64_t q = 0; q < c; ++q) s -= L[c * n + q] * out[q];
+      out[c] = s / L[c * n + c];
+    }
+  } else {
+    for (int64_t c = n - 1; c >= 0; --c) {
+      double s = in[c];
+      for (int64_t q = c + 1; q < n; ++q) s -= L[q * n + c] * out[q];
+      out[c] = s / L[c * n + c];
+    }
+  }
+}
+
+// Batched GEMV over the dense interface blocks with the signed Boolean
+// gather fused in.  task: [matrix row start, first output slot, nrows,
+// ld (= padded n_I), first interface slot of the subdomain].
+constexpr int GEMV_ROWS_PER_WAVE = 4;
+
+__global__ __launch_bounds__(256) void k_gemv_interface(const double* M, const int64_t* task, const int32_t* I_row,
+                                                        const double* I_sign, const double* x, double* v,
+                                                        const int* done) {
+  if (done && *done) return;
+  extern __shared__ __align__(16) double xs[];
+  const int64_t* tk = task + 5 * blockIdx.x;
+  const int64_t mrow0 = tk[0], out0 = tk[1], nrows = tk[2], ld = tk[3], islot0 = tk[4];
+  for (int64_t j = threadIdx.x; j < ld; j += 256) {
+    const int32_t row = I_row[islot0 + j];
+    xs[j] = row >= 0 ? I_sign[islot0 + j] * x[row] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double2* xs2 = reinterpret_cast<const double2*>(xs);
+  for (int rb = w * GEMV_ROWS_PER_WAVE; rb < nrows; rb += 4 * GEMV_ROWS_PER_WAVE) {
+    double acc[GEMV_ROWS_PER_WAVE];
+#pragma unroll
+    for (int r = 0; r < GEMV_ROWS_PER_WAVE; ++r) acc[r] = 0.0;
+    const int64_t half = ld / 2;
+    for (int64_t j = lane; j < half; j += 64) {
+      const double2 xv = xs2[j];
+#pragma unroll
+      for (int r = 0; r < GEMV_ROWS_PER_WAVE; ++r) {
+        if (rb + r < nrows) {
+          const double2 mv = reinterpret_cast<const double2*>(M + mrow0 + (rb + r) * ld)[j];
+          acc[r] += mv.x * xv.x + mv.y * xv.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < GEMV_ROWS_PER_WAVE; ++r) {
+      const double s = wave_sum(acc[r]);
+      if (lane == 0 && rb + r < nrows) v[out0 + rb + r] = s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x,
+                                                        double* out, const int* done) {
+  if (done && *done) return;
+  __shared__ double red[4];
+  const int64_t c = blockIdx.x;
+  double s = 0.0;
+  for (int64_t row = threadIdx.x; row < m_r; row += 256) s += Ht[c * m_r + row] * x[row];
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) out[c] = s;
+}
+
+__global__ __launch_bounds__(256) void k_combine(const double* v, const int64_t* row_src, int64_t m_r, const double* H,
+                                                 const double* t, int64_t n_gp, double* q, const double* dotx,
+                                                 double* partial, const int* done) {
+  if (done && *done) return;
+  __shared__ double red[4];
+  const int64_t row = blockIdx.x * int64_t(256) + threadIdx.x;
+  double prod = 0.0;
+  if (row < m_r) {
+    double val = v[row_src[2 * row]] - v[row_src[2 * row + 1]];
+    if (H) {
+      double c = 0.0;
+      for (int64_t k = 0; k < n_gp; ++k) c += H[row * n_gp + k] * t[k];
+      val += c;
+    }
+    q[row] = val;
+    if (dotx) prod = dotx[row] * val;
+  }
+  if (partial) {
+    const double s = block_sum256(prod, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// scal layout: [0..1] rz (ping-pong), [2] alpha, [3] beta, [4] tol^2 * ||b||^2, [5] last ||r||^2
+__global__ __launch_bounds__(256) void k_pcg_update_lambda(double* lam, double* r, const double* p, const double* q,
+                                                           int64_t m_r, const double* part_pq, int nblk, double* scal,
+                                                           int par, double* part_rr, int* done, int* err) {
+  if (*done) return;
+  __shared__ double red[4];
+  const double pq = reduce_partials(part_pq, nblk, red);
+  if (!(pq > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *err = 1;
+      *done = 3;
+    }
+    return;
+  }
+  const double alpha = scal[par] / pq;
+  const int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
+  double rr = 0.0;
+  if (i < m_r) {
+    lam[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    rr = ri * ri;
+  }
+  const double s = block_sum256(rr, red);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal[2] = alpha;
+}
+
+__global__ __launch_bounds__(256) void k_pcg_update_p(double* p, const double* z, int64_t m_r, const double* part_rz,
+                                                      const double* part_rr, int nblk, double* scal, int par,
+                                                      int* done, int* iters, int maxit) {
+  if (*done) return;
+  __shared__ double red[4];
+  const double rz = reduce_partials(part_rz, nblk, red);
+  const double rr = reduce_partials(part_rr, nblk, red);
+  const int it = *iters + 1;
+  const bool conv = rr <= scal[4];
+  const bool cap = it >= maxit;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *iters = it;
+    scal[5] = rr;
+    scal[1 - par] = rz;
+    scal[3] = rz / scal[par];
+  }
+  if (conv || cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *done = conv ? 1 : 2;
+    return;
+  }
+  const double beta = rz / scal[par];
+  const int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
+  if (i < m_r) p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i < n) out[i] += sgn * y[idx[i]];
+}
+
+// e[row] = sum_k s_k (K_rr^{-1} j_r)_I = -(y[A(src0)] - y[A(src1)]) with y the forward solve.
+__global__ void k_rhs_assemble(const double* y, const int64_t* A_aug, const int64_t* row_src, int64_t m_r, double* e) {
+  const int64_t row = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (row >= m_r) return;
+  e[row] = -(y[A_aug[row_src[2 * row]]] - y[A_aug[row_src[2 * row + 1]]]);
+}
+
+__global__ void k_recovery_rhs_krp(double* y, const int64_t* krp_ptr, const int64_t* krp_pos, const int32_t* krp_col,
+                                   const double* krp_val, int64_t nrows, const double* pglob) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= nrows) return;
+  double s = 0.0;
+  for (int64_t q = krp_ptr[i]; q < krp_ptr[i + 1]; ++q) s += krp_val[q] * pglob[krp_col[q]];
+  y[krp_pos[i]] -= s;
+}
+
+__global__ void k_recovery_rhs_lam(double* y, const int64_t* I_aug, const int32_t* I_row, const double* I_sign,
+                                   int64_t nslots, const double* lam) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= nslots) return;
+  const int32_t row = I_row[i];
+  if (row >= 0) y[I_aug[i]] -= I_sign[i] * lam[row];
+}
+
+__global__ void k_write_output(const double* y, const int64_t* src, const int64_t* edge, int64_t n, double* a) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i < n) a[edge[i]] = y[src[i]];
+}
+
+__global__ void k_write_primal(const double* pglob, const int64_t* primal_edges, int64_t n_gp, double* a) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i < n_gp) a[primal_edges[i]] = pglob[i];
+}
+
+// b[row] = e[row] - sum_c H[row][c] w[c]
+__global__ void k_axpy_rows(const double* H, const double* w, int64_t m, int64_t n, const double* e, double* b) {
+  const int64_t row = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (row >= m) return;
+  double s = 0.0;
+  for (int64_t c = 0; c < n; ++c) s += H[row * n + c] * w[c];
+  b[row] = e[row] - s;
+}
+
+__global__ void k_axpby(const double* x, const double* y, double* out, double a, double b, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = a * x[i] + b * y[i];
+}
+
+__global__ void k_vec_copy(const double* x, double* y, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = x[i];
+}
+
+__global__ __launch_bounds__(256) void k_dot_partial(const double* x, const double* y, int64_t n, double* part) {
+  __shared__ double red[4];
+  const int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
+  const double v = (i < n) ? x[i] * y[i] : 0.0;
+  const double s = block_sum256(v, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return int(g);
+}
+
+}  // namespace
+
+void fill(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+}
+void scatter(double* pool, const int64_t* dst, const double* val, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, pool, dst, val, n);
+}
+void potrf_tiles(double* pool, const int64_t* task, int64_t ntask, int* err, hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(k_potrf, dim3(ntask), dim3(256), 0, s, pool, task, err);
+}
+void trsm_tiles(double* pool, const int64_t* task, int64_t ntask, hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(k_trsm, dim3(ntask), dim3(256), 0, s, pool, task);
+}
+void update_tiles(double* pool, const int64_t* task, int64_t ntask, hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(k_update, dim3(ntask), dim3(256), 0, s, pool, task);
+}
+void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(k_copy_tiles, dim3(ntask), dim3(256), 0, s, pool, task, scale, dst);
+}
+void trsv_diag(const double* pool, const int64_t* task, int64_t ntask, double* y, bool transposed, hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(k_trsv_diag, dim3(ntask), dim3(64), 0, s, pool, task, y, transposed ? 1 : 0);
+}
+void trsv_update(const double* pool, const int64_t* task, int64_t ntask, double* y, bool transposed, hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(k_trsv_update, dim3(ntask), dim3(256), 0, s, pool, task, y, transposed ? 1 : 0);
+}
+void sum_sources(const double* src, const int64_t* ptr, const int64_t* idx, int64_t nout, double* out, hipStream_t s) {
+  if (nout <= 0) return;
+  hipLaunchKernelGGL(k_sum_sources, dim3(grid_for(nout, 256)), dim3(256), 0, s, src, ptr, idx, nout, out);
+}
+void build_G(const double* Phi, const int64_t* row_src, const int64_t* slot_phi_row, const int32_t* I_sub,
+             const int32_t* glob2loc, int64_t m_r, int64_t n_gp, double* G, hipStream_t s) {
+  const int64_t n = m_r * n_gp;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_build_G, dim3((n + 255) / 256), dim3(256), 0, s, Phi, row_src, slot_phi_row, I_sub, glob2loc,
+                     m_r, n_gp, G);
+}
+void chol_small(double* A, int64_t n, int* err, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(256), 0, s, A, n, err);
+}
+void solve_rows_LT(const double* L, int64_t n, const double* G, int64_t m, double* H, double* Ht, hipStream_t s) {
+  if (n <= 0 || m <= 0) return;
+  hipLaunchKernelGGL(k_solve_rows_LT, dim3((m + 255) / 256), dim3(256), 0, s, L, n, G, m, H, Ht);
+}
+void tri_small(const double* L, int64_t n, const double* in, double* out, bool transposed, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_tri_small, dim3(1), dim3(64), 0, s, L, n, in, out, transposed ? 1 : 0);
+}
+void gemv_interface(const double* M, const int64_t* task, int64_t ntask, const int32_t* I_row, const double* I_sign,
+                    const double* x, double* v, const int* done, int64_t max_ld, hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(k_gemv_interface, dim3(ntask), dim3(256), size_t(max_ld) * sizeof(double), s, M, task, I_row,
+                     I_sign, x, v, done);
+}
+void coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x, double* out, const int* done,
+                    hipStream_t s) {
+  if (n_gp <= 0) return;
+  hipLaunchKernelGGL(k_coarse_project, dim3(n_gp), dim3(256), 0, s, Ht, n_gp, m_r, x, out, done);
+}
+int combine_blocks(int64_t m_r) { return int((m_r + 255) / 256); }
+void combine(const double* v, const int64_t* row_src, int64_t m_r, const double* H, const double* t, int64_t n_gp,
+             double* q, const double* dotx, double* partial, const int* done, hipStream_t s) {
+  if (m_r <= 0) return;
+  hipLaunchKernelGGL(k_combine, dim3(combine_blocks(m_r)), dim3(256), 0, s, v, row_src, m_r, H, t, n_gp, q, dotx,
+                     partial, done);
+}
+void pcg_update_lambda(double* lam, double* r, const double* p, const double* q, int64_t m_r, const double* part_pq,
+                       int nblk, double* scal, int par, double* part_rr, int* done, int* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_update_lambda, dim3(combine_blocks(m_r)), dim3(256), 0, s, lam, r, p, q, m_r, part_pq,
+                     nblk, scal, par, part_rr, done, err);
+}
+void pcg_update_p(double* p, const double* z, int64_t m_r, const double* part_rz, const double* part_rr, int nblk,
+                  double* scal, int par, int* done, int* iters, int maxit, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_update_p, dim3(combine_blocks(m_r)), dim3(256), 0, s, p, z, m_r, part_rz, part_rr, nblk,
+                     scal, par, done, iters, maxit);
+}
+void gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gather_add, dim3((n + 255) / 256), dim3(256), 0, s, y, idx, sgn, n, out);
+}
+void rhs_assemble(const double* y, const int64_t* A_aug, const int64_t* row_src, int64_t m_r, double* e, hipStream_t s) {
+  if (m_r <= 0) return;
+  hipLaunchKernelGGL(k_rhs_assemble, dim3((m_r + 255) / 256), dim3(256), 0, s, y, A_aug, row_src, m_r, e);
+}
+void recovery_rhs(double* y, const int64_t* krp_ptr, const int64_t* krp_pos, const int32_t* krp_col,
+                  const double* krp_val, int64_t nrows, const double* pglob, const int64_t* I_aug,
+                  const int32_t* I_row, const double* I_sign, int64_t nslots, const double* lam, hipStream_t s) {
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_recovery_rhs_krp, dim3((nrows + 255) / 256), dim3(256), 0, s, y, krp_ptr, krp_pos, krp_col,
+                       krp_val, nrows, pglob);
+  if (nslots > 0)
+    hipLaunchKernelGGL(k_recovery_rhs_lam, dim3((nslots + 255) / 256), dim3(256), 0, s, y, I_aug, I_row, I_sign,
+                       nslots, lam);
+}
+void write_output(const double* y, const int64_t* src, const int64_t* edge, int64_t n, const double* pglob,
+                  const int64_t* primal_edges, int64_t n_gp, double* a, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_write_output, dim3((n + 255) / 256), dim3(256), 0, s, y, src, edge, n, a);
+  if (n_gp > 0)
+    hipLaunchKernelGGL(k_write_primal, dim3((n_gp + 255) / 256), dim3(256), 0, s, pglob, primal_edges, n_gp, a);
+}
+void axpy_rows(const double* H, const double* w, int64_t m, int64_t n, const double* e, double* b, hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_axpy_rows, dim3((m + 255) / 256), dim3(256), 0, s, H, w, m, n, e, b);
+}
+void axpby(const double* x, const double* y, double* out, double a, double b, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, out, a, b, n);
+}
+void vec_copy(const double* x, double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_vec_copy, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
+}
+void dot_partial(const double* x, const double* y, int64_t n, double* part, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_dot_partial, dim3((n + 255) / 256), dim3(256), 0, s, x, y, n, part);
+}
+
+}  // namespace dev
+}  // namespace ieti

@@ -1,0 +1,69 @@
+// Launch wrappers of the gfx950 kernels of the IETI-DP hot path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ieti {
+namespace dev {
+
+constexpr int TILE = 64;
+
+// ---- factorisation (tile pool, column-major 64x64 tiles)
+void fill(double* p, int64_t n, double v, hipStream_t s);
+void scatter(double* pool, const int64_t* dst, const double* val, int64_t n, hipStream_t s);
+void potrf_tiles(double* pool, const int64_t* task, int64_t ntask, int* err, hipStream_t s);
+void trsm_tiles(double* pool, const int64_t* task, int64_t ntask, hipStream_t s);
+void update_tiles(double* pool, const int64_t* task, int64_t ntask, hipStream_t s);
+void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s);
+
+// ---- triangular solves with the tile factor (augmented vectors)
+void trsv_diag(const double* pool, const int64_t* task, int64_t ntask, double* y, bool transposed, hipStream_t s);
+void trsv_update(const double* pool, const int64_t* task, int64_t ntask, double* y, bool transposed, hipStream_t s);
+
+// ---- coarse problem
+void sum_sources(const double* src, const int64_t* ptr, const int64_t* idx, int64_t nout, double* out, hipStream_t s);
+void build_G(const double* Phi, const int64_t* row_src, const int64_t* slot_phi_row, const int32_t* I_sub,
+             const int32_t* glob2loc, int64_t m_r, int64_t n_gp, double* G, hipStream_t s);
+void chol_small(double* A, int64_t n, int* err, hipStream_t s);
+void solve_rows_LT(const double* L, int64_t n, const double* G, int64_t m, double* H, double* Ht, hipStream_t s);
+void tri_small(const double* L, int64_t n, const double* in, double* out, bool transposed, hipStream_t s);
+
+// ---- interface operators
+// v[slot] = sum_j M_k[i][j] * sign_j * x[row_j] for every interface slot
+constexpr int GEMV_ROWS = 16;  // matrix rows per workgroup (4 waves x 4 rows)
+void gemv_interface(const double* M, const int64_t* task, int64_t ntask, const int32_t* I_row, const double* I_sign,
+                    const double* x, double* v, const int* done, int64_t max_ld, hipStream_t s);
+// out[c] = sum_row Ht[c][row] * x[row]
+void coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x, double* out, const int* done,
+                    hipStream_t s);
+// q[row] = v[src0] - v[src1] + sum_c H[row][c] t[c]  (H may be null); partial dot(x, q) per block
+void combine(const double* v, const int64_t* row_src, int64_t m_r, const double* H, const double* t, int64_t n_gp,
+             double* q, const double* dotx, double* partial, const int* done, hipStream_t s);
+int combine_blocks(int64_t m_r);
+
+// ---- PCG recurrences (FP64)
+// scal: [0..1] rz (ping-pong by iteration parity par), [2] alpha, [3] beta,
+// [4] rtol^2 ||b||^2, [5] last ||r||^2
+void pcg_update_lambda(double* lam, double* r, const double* p, const double* q, int64_t m_r, const double* part_pq,
+                       int nblk, double* scal, int par, double* part_rr, int* done, int* err, hipStream_t s);
+void pcg_update_p(double* p, const double* z, int64_t m_r, const double* part_rz, const double* part_rr, int nblk,
+                  double* scal, int par, int* done, int* iters, int maxit, hipStream_t s);
+
+// ---- recovery / rhs helpers
+void gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out, hipStream_t s);
+void rhs_assemble(const double* y, const int64_t* A_aug, const int64_t* row_src, int64_t m_r, double* e, hipStream_t s);
+void recovery_rhs(double* y, const int64_t* krp_ptr, const int64_t* krp_pos, const int32_t* krp_col,
+                  const double* krp_val, int64_t nrows, const double* pglob, const int64_t* I_aug,
+                  const int32_t* I_row, const double* I_sign, int64_t nslots, const double* lam, hipStream_t s);
+void write_output(const double* y, const int64_t* src, const int64_t* edge, int64_t n, const double* pglob,
+                  const int64_t* primal_edges, int64_t n_gp, double* a, hipStream_t s);
+void axpy_rows(const double* H, const double* w, int64_t m, int64_t n, const double* e, double* b, hipStream_t s);
+void vec_copy(const double* x, double* y, int64_t n, hipStream_t s);
+// out = a x + b y
+void axpby(const double* x, const double* y, double* out, double a, double b, int64_t n, hipStream_t s);
+void dot_partial(const double* x, const double* y, int64_t n, double* part, hipStream_t s);
+
+}  // namespace dev
+}  // namespace ieti

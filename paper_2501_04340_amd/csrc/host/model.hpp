@@ -1,0 +1,78 @@
+// Host-side model of one IETI-DP problem: numbering, topology, gauge,
+// dual-primal maps, assembled local blocks and the GPU factorisation plan.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ietidp.h"
+
+namespace ieti {
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+// Structured control mesh of the multipatch domain (Section 2).
+struct Mesh {
+  int p = 0, n_el = 0, n = 0;  // n = B-splines per patch and direction
+  int P[3] = {0, 0, 0};
+  bool per[3] = {false, false, false};
+  int64_t N[3] = {0, 0, 0};     // control nodes per axis
+  int64_t ext[3][3] = {};       // ext[d][c]: positions of direction-d edges along axis c
+  int64_t off[3] = {0, 0, 0};
+  int64_t n_edges = 0, n_nodes = 0;
+
+  void init(const ieti_problem& pr);
+  int64_t edge_id(int d, int64_t I, int64_t J, int64_t K) const {
+    return off[d] + I + ext[d][0] * (J + ext[d][1] * K);
+  }
+  int64_t node_id(int64_t I, int64_t J, int64_t K) const { return I + N[0] * (J + N[1] * K); }
+  void decode_edge(int64_t e, int& d, int64_t X[3]) const;
+  int64_t wrap(int c, int64_t X) const { return per[c] ? ((X % N[c]) + N[c]) % N[c] : X; }
+  bool on_boundary_node(int c, int64_t X) const { return !per[c] && (X == 0 || X == N[c] - 1); }
+};
+
+// Per-subdomain dual-primal data.
+struct Subdomain {
+  std::vector<int64_t> r_edges;   // remaining DOFs, increasing edge id
+  std::vector<int64_t> p_edges;   // primal DOFs, increasing edge id
+  std::vector<int32_t> p_global;  // global primal index of each primal DOF
+  std::vector<uint8_t> is_I;      // per r DOF: on an interface
+  std::vector<int32_t> I_local;   // local r index of each interface DOF (multiplier order)
+  std::vector<int32_t> I_row;     // multiplier row of each interface DOF
+  std::vector<int8_t> I_sign;     // +1 / -1 entry of B
+  std::vector<int32_t> V_local;   // local r index of each non-interface DOF
+  // assembled blocks over [r, p] local numbering (CSR, full symmetric)
+  int64_t n_loc = 0;
+  std::vector<int64_t> indptr;
+  std::vector<int32_t> indices;
+  std::vector<double> values;
+  std::vector<double> load;
+  std::vector<uint8_t> owner;     // per r DOF: 1 if this subdomain writes the global value
+};
+
+struct Model {
+  ieti_problem prob{};
+  std::vector<int32_t> part;
+  std::vector<double> nu;
+  Mesh mesh;
+  int n_sub = 0;
+  // per edge
+  std::vector<uint8_t> dirichlet, weight, tree, primal;
+  std::vector<int32_t> subs;     // up to 4 subdomain ids per edge (-1 padded), sorted
+  std::vector<uint8_t> nsubs;
+  std::vector<int64_t> primal_edges;
+  std::vector<int64_t> mult;     // m_r x 5: edge, k, l, loc_k, loc_l
+  int64_t m_r = 0, n_gp = 0, n_g = 0;
+  std::vector<Subdomain> sd;
+};
+
+// mesh_topology.cpp
+int build_topology(Model& m, Error& err);
+// assemble.cpp
+int assemble_local_systems(Model& m, Error& err);
+
+}  // namespace ieti

@@ -1,0 +1,407 @@
+// Ordering, padding, tile-level symbolic factorisation and task lists.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace ieti {
+
+namespace {
+
+// Nested dissection of the r_V DOFs by recursive coordinate bisection with
+// one-sided vertex separators taken from the sparsity graph of K_VV.
+void nested_dissection(const std::vector<std::vector<int32_t>>& adj, const std::vector<double>& xyz,
+                       std::vector<int32_t>& ids, std::vector<int32_t>& out, std::vector<int8_t>& side,
+                       int leaf) {
+  if (int(ids.size()) <= leaf) {
+    out.insert(out.end(), ids.begin(), ids.end());
+    return;
+  }
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int32_t v : ids)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], xyz[3 * v + a]);
+      hi[a] = std::max(hi[a], xyz[3 * v + a]);
+    }
+  int ax = 0;
+  for (int a = 1; a < 3; ++a)
+    if (hi[a] - lo[a] > hi[ax] - lo[ax]) ax = a;
+  std::vector<double> c(ids.size());
+  for (size_t i = 0; i < ids.size(); ++i) c[i] = xyz[3 * ids[i] + ax];
+  std::vector<double> cs = c;
+  std::nth_element(cs.begin(), cs.begin() + cs.size() / 2, cs.end());
+  const double mid = cs[cs.size() / 2];
+  std::vector<int32_t> left, right, sep;
+  for (size_t i = 0; i < ids.size(); ++i) {
+    if (c[i] < mid) {
+      left.push_back(ids[i]);
+      side[ids[i]] = 1;
+    } else {
+      right.push_back(ids[i]);
+      side[ids[i]] = 2;
+    }
+  }
+  if (left.empty() || right.empty()) {
+    for (int32_t v : ids) side[v] = 0;
+    out.insert(out.end(), ids.begin(), ids.end());
+    return;
+  }
+  std::vector<int32_t> right2;
+  for (int32_t v : right) {
+    bool touches = false;
+    for (int32_t u : adj[v])
+      if (side[u] == 1) {
+        touches = true;
+        break;
+      }
+    (touches ? sep : right2).push_back(v);
+  }
+  for (int32_t v : ids) side[v] = 0;
+  nested_dissection(adj, xyz, left, out, side, leaf);
+  nested_dissection(adj, xyz, right2, out, side, leaf);
+  out.insert(out.end(), sep.begin(), sep.end());
+}
+
+int64_t round_up(int64_t x, int64_t t) { return (x + t - 1) / t * t; }
+
+}  // namespace
+
+int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
+  plan = Plan();
+  plan.T = T;
+  const int S = m.n_sub;
+  plan.sub.resize(S);
+  const Mesh& M = m.mesh;
+  // ---------------------------------------------------------------- per subdomain
+  std::vector<std::vector<std::vector<uint64_t>>> present(S);  // column bitsets
+  int64_t pool = 0, S_elems = 0, I_total = 0, P_total = 0, r_total = 0;
+  for (int k = 0; k < S; ++k) {
+    const Subdomain& s = m.sd[k];
+    SubPlan& sp = plan.sub[k];
+    sp.nV = int64_t(s.V_local.size());
+    sp.nI = int64_t(s.I_local.size());
+    sp.nP = int64_t(s.p_edges.size());
+    sp.nVp = round_up(sp.nV, T);
+    sp.nIp = round_up(sp.nI, T);
+    sp.nPp = round_up(sp.nP, T);
+    sp.ntV = sp.nVp / T;
+    sp.ntr = sp.ntV + sp.nIp / T;
+    sp.nt = sp.ntr + sp.nPp / T + sp.nIp / T;
+    const int64_t nr = int64_t(s.r_edges.size());
+    // ---- ordering of r_V
+    std::vector<int32_t> vorder;
+    if (ordering == 0 && sp.nV > 0) {
+      std::vector<int32_t> vidx(nr, -1);
+      for (int32_t t = 0; t < int32_t(sp.nV); ++t) vidx[s.V_local[t]] = t;
+      std::vector<std::vector<int32_t>> adj(sp.nV);
+      for (int32_t t = 0; t < int32_t(sp.nV); ++t) {
+        const int32_t r = s.V_local[t];
+        for (int64_t q = s.indptr[r]; q < s.indptr[r + 1]; ++q) {
+          const int32_t c = s.indices[q];
+          if (c < nr && vidx[c] >= 0 && vidx[c] != t) adj[t].push_back(vidx[c]);
+        }
+      }
+      std::vector<double> xyz(3 * sp.nV);
+      for (int32_t t = 0; t < int32_t(sp.nV); ++t) {
+        int d;
+        int64_t X[3];
+        M.decode_edge(s.r_edges[s.V_local[t]], d, X);
+        for (int a = 0; a < 3; ++a) xyz[3 * t + a] = double(X[a]) + (a == d ? 0.5 : 0.0);
+        // periodic axes: unwrap around the subdomain's first DOF
+        for (int a = 0; a < 3; ++a)
+          if (M.per[a] && t > 0) {
+            const double ref = xyz[a];
+            const double L = double(M.N[a]);
+            while (xyz[3 * t + a] - ref > 0.5 * L) xyz[3 * t + a] -= L;
+            while (xyz[3 * t + a] - ref < -0.5 * L) xyz[3 * t + a] += L;
+          }
+      }
+      std::vector<int32_t> ids(sp.nV);
+      std::iota(ids.begin(), ids.end(), 0);
+      std::vector<int8_t> side(sp.nV, 0);
+      nested_dissection(adj, xyz, ids, vorder, side, 4 * T);
+    } else {
+      vorder.resize(sp.nV);
+      std::iota(vorder.begin(), vorder.end(), 0);
+    }
+    // ---- augmented positions of local [r, p] DOFs
+    sp.pos_of_local.assign(s.n_loc, -1);
+    for (int64_t t = 0; t < sp.nV; ++t) sp.pos_of_local[s.V_local[vorder[t]]] = int32_t(t);
+    for (int64_t t = 0; t < sp.nI; ++t) sp.pos_of_local[s.I_local[t]] = int32_t(sp.nVp + t);
+    for (int64_t t = 0; t < sp.nP; ++t) sp.pos_of_local[nr + t] = int32_t(sp.nVp + sp.nIp + t);
+    const int64_t a0 = sp.nVp + sp.nIp + sp.nPp;  // first augmented (E_I) position
+    // ---- tile structure: initial nonzero tiles
+    const int64_t nt = sp.nt;
+    const int64_t words = (nt + 63) / 64;
+    auto& col = present[k];
+    col.assign(nt, std::vector<uint64_t>(words, 0));
+    auto mark = [&](int64_t i, int64_t j) { col[j][i >> 6] |= (uint64_t(1) << (i & 63)); };
+    auto has = [&](int64_t i, int64_t j) { return (col[j][i >> 6] >> (i & 63)) & 1; };
+    for (int64_t t = 0; t < nt; ++t) mark(t, t);
+    for (int64_t r = 0; r < s.n_loc; ++r) {
+      const int64_t pr = sp.pos_of_local[r];
+      for (int64_t q = s.indptr[r]; q < s.indptr[r + 1]; ++q) {
+        const int64_t pc = sp.pos_of_local[s.indices[q]];
+        if (pr >= pc) mark(pr / T, pc / T);
+      }
+    }
+    for (int64_t t = 0; t < sp.nI; ++t) mark((a0 + t) / T, (sp.nVp + t) / T);
+    // ---- symbolic right-looking fill over the r tiles
+    for (int64_t j = 0; j < sp.ntr; ++j) {
+      std::vector<int64_t> rows;
+      for (int64_t i = j + 1; i < nt; ++i)
+        if (has(i, j)) rows.push_back(i);
+      for (size_t x = 0; x < rows.size(); ++x)
+        for (size_t y = 0; y <= x; ++y) mark(rows[x], rows[y]);
+    }
+    // ---- pool offsets
+    sp.tile_off.assign(nt * nt, -1);
+    for (int64_t j = 0; j < nt; ++j)
+      for (int64_t i = j; i < nt; ++i)
+        if (has(i, j)) {
+          sp.tile_off[i * nt + j] = pool;
+          pool += int64_t(T) * T;
+        }
+    sp.S_off = S_elems;
+    S_elems += sp.nIp * sp.nIp;
+    sp.I_off = I_total;
+    I_total += sp.nIp;
+    sp.P_off = P_total;
+    P_total += sp.nP;
+    sp.r_off = r_total;
+    r_total += nt * T;
+    sp.Phi_off = plan.Phi_elems;
+    plan.Phi_elems += sp.nIp * sp.nPp;
+    sp.SPi_off = plan.SPi_elems;
+    plan.SPi_elems += sp.nPp * sp.nPp;
+  }
+  plan.pool_elems = pool;
+  plan.S_elems = S_elems;
+  plan.I_total = I_total;
+  plan.P_total = P_total;
+  plan.r_total = r_total;
+  // ---------------------------------------------------------------- scatter list
+  for (int k = 0; k < S; ++k) {
+    const Subdomain& s = m.sd[k];
+    const SubPlan& sp = plan.sub[k];
+    const int64_t nt = sp.nt;
+    auto put = [&](int64_t pr, int64_t pc, double v) {
+      const int64_t ti = pr / T, tj = pc / T;
+      const int64_t off = sp.tile_off[ti * nt + tj];
+      plan.scatter_dst.push_back(off + (pc % T) * T + (pr % T));
+      plan.scatter_val.push_back(v);
+    };
+    for (int64_t r = 0; r < s.n_loc; ++r) {
+      const int64_t pr = sp.pos_of_local[r];
+      for (int64_t q = s.indptr[r]; q < s.indptr[r + 1]; ++q) {
+        const int64_t pc = sp.pos_of_local[s.indices[q]];
+        if (pr / T > pc / T || (pr / T == pc / T)) put(pr, pc, s.values[q]);
+      }
+    }
+    for (int64_t t = sp.nV; t < sp.nVp; ++t) put(t, t, 1.0);
+    for (int64_t t = sp.nVp + sp.nI; t < sp.nVp + sp.nIp; ++t) put(t, t, 1.0);
+    const int64_t a0 = sp.nVp + sp.nIp + sp.nPp;
+    for (int64_t t = 0; t < sp.nI; ++t) put(a0 + t, sp.nVp + t, 1.0);
+  }
+  // ---------------------------------------------------------------- step task lists
+  int64_t n_steps = 0;
+  for (const auto& sp : plan.sub) n_steps = std::max(n_steps, sp.ntr);
+  plan.n_steps = n_steps;
+  plan.potrf_ptr.assign(1, 0);
+  plan.trsm_ptr.assign(1, 0);
+  plan.upd_ptr.assign(1, 0);
+  plan.copy_ptr.assign(1, 0);
+  const double T3 = double(T) * T * T;
+  for (int64_t j = 0; j < n_steps; ++j) {
+    for (int k = 0; k < S; ++k) {
+      const SubPlan& sp = plan.sub[k];
+      const int64_t nt = sp.nt;
+      auto off = [&](int64_t i, int64_t l) { return sp.tile_off[i * nt + l]; };
+      // Schur complement S_rIrI is complete once the r_V columns are eliminated
+      if (j == sp.ntV && sp.nIp > 0) {
+        for (int64_t i = sp.ntV; i < sp.ntr; ++i)
+          for (int64_t l = sp.ntV; l <= i; ++l) {
+            const int64_t o = off(i, l);
+            if (o < 0) continue;
+            const int64_t r0 = (i - sp.ntV) * T, c0 = (l - sp.ntV) * T;
+            plan.copy_task.insert(plan.copy_task.end(),
+                                  {o, sp.S_off + r0 * sp.nIp + c0, sp.S_off + c0 * sp.nIp + r0, sp.nIp, i == l ? 1 : 0});
+          }
+      }
+      if (j >= sp.ntr) continue;
+      plan.potrf_task.insert(plan.potrf_task.end(), {off(j, j), int64_t(k)});
+      plan.flops += T3 / 3.0;
+      std::vector<int64_t> rows;
+      for (int64_t i = j + 1; i < nt; ++i)
+        if (off(i, j) >= 0) rows.push_back(i);
+      for (int64_t i : rows) {
+        plan.trsm_task.insert(plan.trsm_task.end(), {off(j, j), off(i, j)});
+        plan.flops += T3;
+      }
+      for (size_t x = 0; x < rows.size(); ++x)
+        for (size_t y = 0; y <= x; ++y) {
+          const int64_t i = rows[x], l = rows[y];
+          plan.upd_task.insert(plan.upd_task.end(), {off(i, l), off(i, j), off(l, j)});
+          plan.flops += 2.0 * T3;
+        }
+    }
+    plan.potrf_ptr.push_back(int64_t(plan.potrf_task.size() / 2));
+    plan.trsm_ptr.push_back(int64_t(plan.trsm_task.size() / 2));
+    plan.upd_ptr.push_back(int64_t(plan.upd_task.size() / 3));
+    plan.copy_ptr.push_back(int64_t(plan.copy_task.size() / 5));
+  }
+  plan.n_update_tasks = int64_t(plan.upd_task.size() / 3);
+  // ---------------------------------------------------------------- extraction lists
+  for (int k = 0; k < S; ++k) {
+    const SubPlan& sp = plan.sub[k];
+    const int64_t nt = sp.nt;
+    const int64_t tP = sp.ntr, tA = sp.ntr + sp.nPp / T;
+    auto off = [&](int64_t i, int64_t l) { return sp.tile_off[i * nt + l]; };
+    for (int64_t i = tA; i < nt; ++i)
+      for (int64_t l = tA; l <= i; ++l) {
+        const int64_t o = off(i, l);
+        if (o < 0) continue;
+        const int64_t r0 = (i - tA) * T, c0 = (l - tA) * T;
+        plan.xsinv_task.insert(plan.xsinv_task.end(),
+                               {o, sp.S_off + r0 * sp.nIp + c0, sp.S_off + c0 * sp.nIp + r0, sp.nIp, i == l ? 1 : 0});
+      }
+    for (int64_t i = tA; i < nt; ++i)
+      for (int64_t l = tP; l < tA; ++l) {
+        const int64_t o = off(i, l);
+        if (o < 0) continue;
+        const int64_t r0 = (i - tA) * T, c0 = (l - tP) * T;
+        plan.xphi_task.insert(plan.xphi_task.end(), {o, sp.Phi_off + r0 * sp.nPp + c0, -1, sp.nPp, 0});
+      }
+    for (int64_t i = tP; i < tA; ++i)
+      for (int64_t l = tP; l <= i; ++l) {
+        const int64_t o = off(i, l);
+        if (o < 0) continue;
+        const int64_t r0 = (i - tP) * T, c0 = (l - tP) * T;
+        plan.xspi_task.insert(plan.xspi_task.end(),
+                              {o, sp.SPi_off + r0 * sp.nPp + c0, sp.SPi_off + c0 * sp.nPp + r0, sp.nPp, i == l ? 1 : 0});
+      }
+  }
+  // ---------------------------------------------------------------- triangular-solve lists
+  plan.fdiag_ptr.assign(1, 0);
+  plan.ffull_ptr.assign(1, 0);
+  plan.fr_ptr.assign(1, 0);
+  for (int64_t j = 0; j < n_steps; ++j) {
+    for (int k = 0; k < S; ++k) {
+      const SubPlan& sp = plan.sub[k];
+      if (j >= sp.ntr) continue;
+      const int64_t nt = sp.nt;
+      plan.fdiag_task.insert(plan.fdiag_task.end(), {sp.tile_off[j * nt + j], sp.r_off + j * T});
+      for (int64_t i = j + 1; i < nt; ++i) {
+        const int64_t o = sp.tile_off[i * nt + j];
+        if (o < 0) continue;
+        plan.ffull_task.insert(plan.ffull_task.end(), {o, sp.r_off + i * T, sp.r_off + j * T});
+        if (i < sp.ntr) plan.fr_task.insert(plan.fr_task.end(), {o, sp.r_off + i * T, sp.r_off + j * T});
+      }
+    }
+    plan.fdiag_ptr.push_back(int64_t(plan.fdiag_task.size() / 2));
+    plan.ffull_ptr.push_back(int64_t(plan.ffull_task.size() / 3));
+    plan.fr_ptr.push_back(int64_t(plan.fr_task.size() / 3));
+  }
+  plan.bdiag_ptr.assign(1, 0);
+  plan.bupd_ptr.assign(1, 0);
+  for (int64_t j = n_steps - 1; j >= 0; --j) {
+    for (int k = 0; k < S; ++k) {
+      const SubPlan& sp = plan.sub[k];
+      if (j >= sp.ntr) continue;
+      const int64_t nt = sp.nt;
+      plan.bdiag_task.insert(plan.bdiag_task.end(), {sp.tile_off[j * nt + j], sp.r_off + j * T});
+      for (int64_t i = 0; i < j; ++i) {
+        const int64_t o = sp.tile_off[j * nt + i];
+        if (o < 0) continue;
+        plan.bupd_task.insert(plan.bupd_task.end(), {o, sp.r_off + i * T, sp.r_off + j * T});
+      }
+    }
+    plan.bdiag_ptr.push_back(int64_t(plan.bdiag_task.size() / 2));
+    plan.bupd_ptr.push_back(int64_t(plan.bupd_task.size() / 3));
+  }
+  // ---------------------------------------------------------------- interface and primal maps
+  const int64_t n_gp = m.n_gp;
+  plan.I_row.assign(I_total, -1);
+  plan.I_sign.assign(I_total, 0.0);
+  plan.I_aug.assign(I_total, 0);
+  plan.A_aug.assign(I_total, 0);
+  plan.I_sub.assign(I_total, 0);
+  plan.row_src.assign(2 * m.m_r, -1);
+  plan.glob2loc.assign(size_t(S) * n_gp, -1);
+  for (int k = 0; k < S; ++k) {
+    const Subdomain& s = m.sd[k];
+    const SubPlan& sp = plan.sub[k];
+    const int64_t a0 = sp.nVp + sp.nIp + sp.nPp;
+    for (int64_t t = 0; t < sp.nIp; ++t) {
+      const int64_t slot = sp.I_off + t;
+      plan.I_aug[slot] = sp.r_off + sp.nVp + t;
+      plan.A_aug[slot] = sp.r_off + a0 + t;
+      plan.I_sub[slot] = k;
+      if (t < sp.nI) {
+        plan.I_row[slot] = s.I_row[t];
+        plan.I_sign[slot] = double(s.I_sign[t]);
+        plan.row_src[2 * s.I_row[t] + (s.I_sign[t] > 0 ? 0 : 1)] = slot;
+      }
+    }
+    for (int64_t t = 0; t < sp.nP; ++t) {
+      plan.P_glob.push_back(s.p_global[t]);
+      plan.P_aug.push_back(sp.r_off + sp.nVp + sp.nIp + t);
+      plan.P_sub.push_back(k);
+      plan.glob2loc[size_t(k) * n_gp + s.p_global[t]] = int32_t(t);
+    }
+  }
+  // coarse matrix: sum over subdomains of C_k^T SPi_k C_k, sources in fixed order
+  {
+    std::vector<std::vector<int64_t>> src(size_t(n_gp) * n_gp);
+    for (int k = 0; k < S; ++k) {
+      const Subdomain& s = m.sd[k];
+      const SubPlan& sp = plan.sub[k];
+      for (int64_t a = 0; a < sp.nP; ++a)
+        for (int64_t b = 0; b < sp.nP; ++b)
+          src[size_t(s.p_global[a]) * n_gp + s.p_global[b]].push_back(sp.SPi_off + a * sp.nPp + b);
+    }
+    plan.spi_ptr.assign(1, 0);
+    for (auto& v : src) {
+      plan.spi_src.insert(plan.spi_src.end(), v.begin(), v.end());
+      plan.spi_ptr.push_back(int64_t(plan.spi_src.size()));
+    }
+  }
+  // recovery rows of K_rp and the output map
+  plan.krp_ptr.assign(1, 0);
+  plan.b_aug0.assign(r_total, 0.0);
+  for (int k = 0; k < S; ++k) {
+    const Subdomain& s = m.sd[k];
+    const SubPlan& sp = plan.sub[k];
+    const int64_t nr = int64_t(s.r_edges.size());
+    for (int64_t r = 0; r < s.n_loc; ++r) plan.b_aug0[sp.r_off + sp.pos_of_local[r]] = s.load[r];
+    for (int64_t r = 0; r < nr; ++r) {
+      bool any = false;
+      for (int64_t q = s.indptr[r]; q < s.indptr[r + 1]; ++q) {
+        const int32_t c = s.indices[q];
+        if (c >= nr) {
+          plan.krp_col.push_back(s.p_global[c - nr]);
+          plan.krp_val.push_back(s.values[q]);
+          any = true;
+        }
+      }
+      if (any) {
+        plan.krp_pos.push_back(sp.r_off + sp.pos_of_local[r]);
+        plan.krp_ptr.push_back(int64_t(plan.krp_col.size()));
+      }
+      if (s.owner[r]) {
+        plan.out_src.push_back(sp.r_off + sp.pos_of_local[r]);
+        plan.out_edge.push_back(s.r_edges[r]);
+      }
+    }
+  }
+  for (const auto& sp : plan.sub) {
+    const double n = double(sp.nVp + sp.nIp);
+    const double a = double(sp.nPp + sp.nIp);
+    plan.dense_flops += n * n * n / 3.0 + n * n * a;
+  }
+  (void)err;
+  return IETI_OK;
+}
+
+}  // namespace ieti

@@ -1,0 +1,95 @@
+// Factorisation plan: ordering, tile structure and task lists of the batched
+// partial Cholesky factorisation of every subdomain's augmented matrix
+//
+//     [ K_rr   K_rp   E_I ]      r = [r_V (nested dissection), r_I]
+//     [ K_pr   K_pp   0   ]      p = local primal DOFs
+//     [ E_I^T  0      0   ]      E_I selects the interface DOFs r_I
+//
+// Eliminating the r block leaves the trailing block
+//
+//     [ K_pp - K_pr K_rr^{-1} K_rp     -(K_rr^{-1} K_rp)_I^T ]
+//     [ -(K_rr^{-1} K_rp)_I            -(K_rr^{-1})_II        ]
+//
+// i.e. the local coarse contribution (minus the paper's F, Section 2.1), the
+// primal coupling of G and the local inverse block that W needs; after the
+// r_V columns are eliminated the r_I block holds the Schur complement
+// S_rIrI of the Dirichlet preconditioner (Eq. DirPrec).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "model.hpp"
+
+namespace ieti {
+
+struct SubPlan {
+  int64_t nV = 0, nI = 0, nP = 0;      // true sizes
+  int64_t nVp = 0, nIp = 0, nPp = 0;   // padded to the tile size
+  int64_t nt = 0, ntV = 0, ntr = 0;    // tiles: total, r_V, r (= r_V + r_I)
+  std::vector<int32_t> pos_of_local;   // local [r,p] index -> augmented position
+  std::vector<int64_t> tile_off;       // nt*nt, lower tiles: pool offset or -1
+  int64_t S_off = 0;                   // offset of the dense nIp x nIp S / Sinv blocks
+  int64_t I_off = 0;                   // offset into the concatenated interface vectors
+  int64_t P_off = 0;                   // offset into the concatenated local primal vectors
+  int64_t r_off = 0;                   // offset into concatenated augmented vectors (nt*T each)
+  int64_t Phi_off = 0;                 // dense nIp x nPp block (K_rr^{-1} K_rp)_I
+  int64_t SPi_off = 0;                 // dense nPp x nPp local coarse block
+};
+
+struct Plan {
+  int T = 64;
+  int64_t pool_elems = 0;
+  int64_t n_steps = 0;
+  std::vector<SubPlan> sub;
+  // per step, ranges into flat task arrays
+  std::vector<int64_t> potrf_ptr, trsm_ptr, upd_ptr, copy_ptr;
+  std::vector<int64_t> potrf_task;   // [off_jj, sub]
+  std::vector<int64_t> trsm_task;    // [off_jj, off_ij]
+  std::vector<int64_t> upd_task;     // [off_il, off_ij, off_lj]
+  std::vector<int64_t> copy_task;    // [off_tile, dst_offset_in_S, ld (= nIp), transpose-needed]
+  // scatter of the assembled entries into the tile pool
+  std::vector<int64_t> scatter_dst;
+  std::vector<double> scatter_val;
+  // dense S / Sinv storage
+  int64_t S_elems = 0;
+  int64_t I_total = 0;   // sum nIp
+  int64_t P_total = 0;   // sum nP
+  int64_t r_total = 0;   // sum (nVp + nIp + nPp + nIp): augmented vectors
+  int64_t Phi_elems = 0, SPi_elems = 0;
+  // extraction after the factorisation: [off_tile, dst, dst_transposed or -1, ld, is_diag]
+  std::vector<int64_t> xsinv_task, xphi_task, xspi_task;
+  // triangular solves with the factor, per step: diag [off_jj, vec_j], update [off_tile, vec_dst, vec_src]
+  std::vector<int64_t> fdiag_ptr, fdiag_task, ffull_ptr, ffull_task, fr_ptr, fr_task;
+  std::vector<int64_t> bdiag_ptr, bdiag_task, bupd_ptr, bupd_task;
+  // interface gather/scatter: per padded interface slot, multiplier row (-1 = pad) and sign
+  std::vector<int32_t> I_row;
+  std::vector<double> I_sign;
+  std::vector<int64_t> row_src;        // 2 per multiplier row: slots in the +1 and -1 subdomain
+  std::vector<int64_t> I_aug;          // per padded interface slot: index into augmented vectors (I block)
+  std::vector<int64_t> A_aug;          // per padded interface slot: index into augmented vectors (E_I block)
+  // primal maps
+  std::vector<int32_t> P_glob;         // per local primal slot: global primal index
+  std::vector<int64_t> P_aug;          // per local primal slot: index into augmented vectors
+  std::vector<int32_t> P_sub;          // per local primal slot: subdomain
+  std::vector<int32_t> glob2loc;       // N_sub x n_gp: local primal slot index within the subdomain or -1
+  std::vector<int32_t> I_sub;          // per padded interface slot: subdomain
+  // coarse matrix assembly: CSR over the n_gp*n_gp entries, sources in the SPi array
+  std::vector<int64_t> spi_ptr, spi_src;
+  // recovery: K_rp rows (augmented index), entries (global primal, value)
+  std::vector<int64_t> krp_ptr, krp_pos;
+  std::vector<int32_t> krp_col;
+  std::vector<double> krp_val;
+  // output: augmented index and edge id of every owned r DOF
+  std::vector<int64_t> out_src, out_edge;
+  // initial augmented right-hand side [j_r; j_p; 0]
+  std::vector<double> b_aug0;
+  double flops = 0.0;    // algorithmic flops of the tile factorisation
+  double dense_flops = 0.0;
+  int64_t n_update_tasks = 0;
+};
+
+// ordering: 0 = nested dissection, 1 = natural
+int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err);
+
+}  // namespace ieti

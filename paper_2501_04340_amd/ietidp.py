@@ -1,0 +1,318 @@
+"""Thin ctypes binding of the C ABI in ``include/ietidp.h``.
+
+Argument marshalling only: every step of assembly, factorisation and solve
+runs inside ``lib/libietidp.so``.  Loading fails loudly if the library has not
+been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libietidp.so")
+_lib = None
+
+ABI_VERSION = 1
+PREC_FP64, PREC_MIXED = 0, 1
+ERRORS = {
+    -1: "INVALID_ARG", -2: "PARTITION", -3: "TREE", -4: "NOT_SPD", -5: "BREAKDOWN",
+    -6: "NOT_CONVERGED", -7: "HIP", -8: "STATE",
+}
+
+FIELD_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double), C.c_void_p)
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("version", C.c_int32),
+        ("geom_kind", C.c_int32),
+        ("patches", C.c_int32 * 3),
+        ("periodic", C.c_int32 * 3),
+        ("geom_params", C.c_double * 16),
+        ("degree_p", C.c_int32),
+        ("n_el", C.c_int32),
+        ("patch_to_subdomain", C.POINTER(C.c_int32)),
+        ("nu_per_patch", C.POINTER(C.c_double)),
+        ("J", FIELD_FN),
+        ("J_user", C.c_void_p),
+    ]
+
+
+class FactorOpts(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32),
+        ("tile", C.c_int32),
+        ("ordering", C.c_int32),
+        ("reserved", C.c_int32),
+        ("hip_stream", C.c_void_p),
+    ]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [
+        ("rtol", C.c_double),
+        ("maxit", C.c_int32),
+        ("check_every", C.c_int32),
+        ("lambda0", C.POINTER(C.c_double)),
+        ("use_graph", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("n_global", C.c_int64),
+        ("n_multipliers", C.c_int64),
+        ("n_primal", C.c_int64),
+        ("n_sub", C.c_int64),
+        ("iters", C.c_int32),
+        ("outer_iters", C.c_int32),
+        ("status", C.c_int32),
+        ("f_applies", C.c_int32),
+        ("rel_residual", C.c_double),
+        ("t_factor_s", C.c_double),
+        ("t_solve_s", C.c_double),
+        ("t_pcg_s", C.c_double),
+        ("factor_flops", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+EXPORTS = [
+    "ieti_assemble", "ieti_factor", "ieti_solve", "ieti_solve_device", "ieti_get_sizes", "ieti_get_maps",
+    "ieti_get_local_system", "ieti_get_schur", "ieti_apply_F", "ieti_apply_M", "ieti_get_rhs",
+    "ieti_get_lambda", "ieti_get_plan_info", "ieti_set_profiling", "ieti_get_kernel_times", "ieti_destroy",
+    "ieti_last_error",
+]
+
+
+class IetiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def load_library():
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -m paper_2501_04340_amd.build`")
+    try:  # load torch's HIP runtime first so the process holds exactly one runtime
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(_LIB_PATH)
+    P = C.POINTER
+    lib.ieti_assemble.argtypes = [P(Problem), P(C.c_void_p)]
+    lib.ieti_factor.argtypes = [C.c_void_p, P(FactorOpts)]
+    lib.ieti_solve.argtypes = [C.c_void_p, P(SolveOpts), P(C.c_double), P(Stats)]
+    lib.ieti_solve_device.argtypes = [C.c_void_p, P(SolveOpts), C.c_void_p, P(Stats)]
+    lib.ieti_get_sizes.argtypes = [C.c_void_p, P(C.c_int64)]
+    lib.ieti_get_maps.argtypes = [C.c_void_p, P(C.c_uint8), P(C.c_uint8), P(C.c_uint8), P(C.c_int64),
+                                  P(C.c_int64), P(C.c_int64), P(C.c_int64)]
+    lib.ieti_get_local_system.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int64), P(C.c_int64),
+                                          P(C.c_int32), P(C.c_double), P(C.c_double)]
+    lib.ieti_get_schur.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)]
+    lib.ieti_apply_F.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
+    lib.ieti_apply_M.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
+    lib.ieti_get_rhs.argtypes = [C.c_void_p, P(C.c_double)]
+    lib.ieti_get_lambda.argtypes = [C.c_void_p, P(C.c_double)]
+    lib.ieti_get_plan_info.argtypes = [C.c_void_p, P(C.c_double)]
+    lib.ieti_set_profiling.argtypes = [C.c_void_p, C.c_int32]
+    lib.ieti_get_kernel_times.argtypes = [C.c_void_p, P(C.c_double)]
+    lib.ieti_destroy.argtypes = [C.c_void_p]
+    lib.ieti_destroy.restype = None
+    lib.ieti_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("ieti_destroy", "ieti_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _check(lib, rc):
+    if rc != 0:
+        raise IetiError(rc, lib.ieti_last_error().decode())
+
+
+class Solver:
+    """One assembled problem on the current HIP device."""
+
+    def __init__(self, prob):
+        self.lib = load_library()
+        self.prob = prob
+        self._part = np.ascontiguousarray(prob.patch_to_sub, dtype=np.int32)
+        self._nu = np.ascontiguousarray(prob.nu, dtype=np.float64)
+        src = prob.source
+
+        def _field(xyz, npts, out, user):
+            X = np.ctypeslib.as_array(xyz, shape=(int(npts), 3))
+            O = np.ctypeslib.as_array(out, shape=(int(npts), 3))
+            O[:] = src(np.array(X))
+
+        self._cb = FIELD_FN(_field)
+        pr = Problem()
+        pr.version = ABI_VERSION
+        pr.geom_kind = int(prob.geom_kind)
+        for d in range(3):
+            pr.patches[d] = int(prob.patches[d])
+            pr.periodic[d] = int(prob.periodic[d])
+        gp = np.zeros(16)
+        gp[:len(prob.geom_params)] = prob.geom_params
+        for i in range(16):
+            pr.geom_params[i] = float(gp[i])
+        pr.degree_p = int(prob.degree)
+        pr.n_el = int(prob.n_el)
+        pr.patch_to_subdomain = _ptr(self._part, C.c_int32)
+        pr.nu_per_patch = _ptr(self._nu, C.c_double)
+        pr.J = self._cb
+        pr.J_user = None
+        h = C.c_void_p()
+        _check(self.lib, self.lib.ieti_assemble(C.byref(pr), C.byref(h)))
+        self.h = h
+        s = np.zeros(8, dtype=np.int64)
+        _check(self.lib, self.lib.ieti_get_sizes(self.h, _ptr(s, C.c_int64)))
+        self.n_edges, self.n_global, self.sum_n_r, self.m_r, self.n_gp, self.n_sub, self.n_nodes, self.max_n_I = map(int, s)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ieti_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sizes(self):
+        return {"n_edges": self.n_edges, "n_g": self.n_global, "sum_n_r": self.sum_n_r, "m_r": self.m_r,
+                "n_gp": self.n_gp, "n_sub": self.n_sub, "n_nodes": self.n_nodes, "max_n_I": self.max_n_I}
+
+    def maps(self):
+        ne = self.n_edges
+        weight = np.zeros(ne, np.uint8)
+        tree = np.zeros(ne, np.uint8)
+        dirichlet = np.zeros(ne, np.uint8)
+        primal = np.zeros(max(self.n_gp, 1), np.int64)
+        mult = np.zeros(max(self.m_r, 1) * 5, np.int64)
+        offs = np.zeros(self.n_sub + 1, np.int64)
+        redges = np.zeros(max(self.sum_n_r, 1), np.int64)
+        _check(self.lib, self.lib.ieti_get_maps(self.h, _ptr(weight, C.c_uint8), _ptr(tree, C.c_uint8),
+                                                _ptr(dirichlet, C.c_uint8), _ptr(primal, C.c_int64),
+                                                _ptr(mult, C.c_int64), _ptr(offs, C.c_int64),
+                                                _ptr(redges, C.c_int64)))
+        return {
+            "weight": weight, "tree": tree.astype(bool), "dirichlet": dirichlet.astype(bool),
+            "primal_edges": primal[:self.n_gp], "mult": mult[:self.m_r * 5].reshape(-1, 5),
+            "sub_r": [redges[offs[k]:offs[k + 1]] for k in range(self.n_sub)],
+        }
+
+    def local_system(self, k):
+        n = C.c_int64()
+        nnz = C.c_int64()
+        _check(self.lib, self.lib.ieti_get_local_system(self.h, k, C.byref(n), C.byref(nnz), None, None, None, None))
+        indptr = np.zeros(n.value + 1, np.int64)
+        indices = np.zeros(max(nnz.value, 1), np.int32)
+        values = np.zeros(max(nnz.value, 1), np.float64)
+        load = np.zeros(max(n.value, 1), np.float64)
+        _check(self.lib, self.lib.ieti_get_local_system(self.h, k, C.byref(n), C.byref(nnz), _ptr(indptr, C.c_int64),
+                                                        _ptr(indices, C.c_int32), _ptr(values, C.c_double),
+                                                        _ptr(load, C.c_double)))
+        import scipy.sparse as sp
+        K = sp.csr_matrix((values[:nnz.value], indices[:nnz.value], indptr), shape=(n.value, n.value))
+        return K, load[:n.value]
+
+    def factor(self, precision=PREC_FP64, ordering=0, stream=None):
+        o = FactorOpts()
+        o.precision = precision
+        o.tile = 0
+        o.ordering = ordering
+        o.hip_stream = stream
+        _check(self.lib, self.lib.ieti_factor(self.h, C.byref(o)))
+
+    def _solve_opts(self, rtol, maxit, lambda0, check_every):
+        o = SolveOpts()
+        o.rtol = rtol
+        o.maxit = maxit
+        o.check_every = check_every
+        self._lam0 = None
+        if lambda0 is not None:
+            self._lam0 = np.ascontiguousarray(lambda0, dtype=np.float64)
+            o.lambda0 = _ptr(self._lam0, C.c_double)
+        return o
+
+    def solve(self, rtol=1e-8, maxit=1000, lambda0=None, check_every=8, raise_on_nonconv=True):
+        o = self._solve_opts(rtol, maxit, lambda0, check_every)
+        a = np.zeros(self.n_edges)
+        st = Stats()
+        rc = self.lib.ieti_solve(self.h, C.byref(o), _ptr(a, C.c_double), C.byref(st))
+        if rc != 0 and not (rc == -6 and not raise_on_nonconv):
+            _check(self.lib, rc)
+        return a, st.as_dict()
+
+    def solve_device(self, out_ptr, rtol=1e-8, maxit=1000, lambda0=None, check_every=8):
+        o = self._solve_opts(rtol, maxit, lambda0, check_every)
+        st = Stats()
+        _check(self.lib, self.lib.ieti_solve_device(self.h, C.byref(o), C.c_void_p(out_ptr), C.byref(st)))
+        return st.as_dict()
+
+    def schur(self, k):
+        n = C.c_int64()
+        _check(self.lib, self.lib.ieti_get_schur(self.h, k, C.byref(n), None, None))
+        S = np.zeros((n.value, n.value))
+        Sinv = np.zeros((n.value, n.value))
+        _check(self.lib, self.lib.ieti_get_schur(self.h, k, C.byref(n), _ptr(S, C.c_double), _ptr(Sinv, C.c_double)))
+        return S, Sinv
+
+    def apply_F(self, lam):
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        q = np.zeros(self.m_r)
+        _check(self.lib, self.lib.ieti_apply_F(self.h, _ptr(lam, C.c_double), _ptr(q, C.c_double)))
+        return q
+
+    def apply_M(self, r):
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.zeros(self.m_r)
+        _check(self.lib, self.lib.ieti_apply_M(self.h, _ptr(r, C.c_double), _ptr(z, C.c_double)))
+        return z
+
+    def rhs(self):
+        b = np.zeros(self.m_r)
+        _check(self.lib, self.lib.ieti_get_rhs(self.h, _ptr(b, C.c_double)))
+        return b
+
+    def plan_info(self):
+        v = np.zeros(10)
+        _check(self.lib, self.lib.ieti_get_plan_info(self.h, _ptr(v, C.c_double)))
+        keys = ["pool_elems", "S_elems", "flops", "dense_flops", "n_steps", "n_update_tasks", "sum_nI2",
+                "I_total", "max_ld", "tile"]
+        return dict(zip(keys, v.tolist()))
+
+    def set_profiling(self, enable=True):
+        _check(self.lib, self.lib.ieti_set_profiling(self.h, 1 if enable else 0))
+
+    def kernel_times(self):
+        v = np.zeros(6)
+        _check(self.lib, self.lib.ieti_get_kernel_times(self.h, _ptr(v, C.c_double)))
+        keys = ["gemv_launches", "gemv_ms", "update_launches", "update_ms", "update_tasks", "gemv_bytes"]
+        return dict(zip(keys, v.tolist()))
+
+    def lambda_(self):
+        lam = np.zeros(self.m_r)
+        _check(self.lib, self.lib.ieti_get_lambda(self.h, _ptr(lam, C.c_double)))
+        return lam

@@ -83,20 +83,31 @@ class TrigCurlSource:
         self.phase = rng.uniform(0.0, 2.0 * np.pi, size=(3, ks.shape[0], 3))
 
     def T_and_grad(self, xyz):
-        """T_d and dT_d/dx_j at points: returns (n,3), (n,3,3) [d, j]."""
+        """T_d and dT_d/dx_j at points: returns (n,3), (n,3,3) [d, j].
+
+        sin(pi k x + th) and cos(pi k x + th) are formed from the per-axis
+        tables sin(pi k x), cos(pi k x) by the angle-addition identities.
+        """
         n = xyz.shape[0]
         T = np.zeros((n, 3))
         dT = np.zeros((n, 3, 3))
         pk = np.pi * self.k  # (M,3)
+        ki = self.k.astype(np.int64) - 1  # (M,3) table index
+        kmax = int(self.k.max())
+        ang = np.pi * xyz[:, :, None] * np.arange(1, kmax + 1)[None, None, :]  # (n,3,K)
+        st, ct = np.sin(ang), np.cos(ang)
+        s_ax = [st[:, i, :][:, ki[:, i]] for i in range(3)]  # (n,M)
+        c_ax = [ct[:, i, :][:, ki[:, i]] for i in range(3)]
         for d in range(3):
-            arg = xyz[:, None, :] * pk[None, :, :] + self.phase[d][None, :, :]  # (n,M,3)
-            s = np.sin(arg)
-            c = np.cos(arg)
+            cth = np.cos(self.phase[d])  # (M,3)
+            sth = np.sin(self.phase[d])
+            S = [s_ax[i] * cth[None, :, i] + c_ax[i] * sth[None, :, i] for i in range(3)]
+            Cc = [c_ax[i] * cth[None, :, i] - s_ax[i] * sth[None, :, i] for i in range(3)]
             a = self.amp[d][None, :]
-            T[:, d] = np.sum(a * s[:, :, 0] * s[:, :, 1] * s[:, :, 2], axis=1)
-            dT[:, d, 0] = np.sum(a * pk[None, :, 0] * c[:, :, 0] * s[:, :, 1] * s[:, :, 2], axis=1)
-            dT[:, d, 1] = np.sum(a * pk[None, :, 1] * s[:, :, 0] * c[:, :, 1] * s[:, :, 2], axis=1)
-            dT[:, d, 2] = np.sum(a * pk[None, :, 2] * s[:, :, 0] * s[:, :, 1] * c[:, :, 2], axis=1)
+            T[:, d] = np.sum(a * S[0] * S[1] * S[2], axis=1)
+            dT[:, d, 0] = np.sum(a * pk[None, :, 0] * Cc[0] * S[1] * S[2], axis=1)
+            dT[:, d, 1] = np.sum(a * pk[None, :, 1] * S[0] * Cc[1] * S[2], axis=1)
+            dT[:, d, 2] = np.sum(a * pk[None, :, 2] * S[0] * S[1] * Cc[2], axis=1)
         return T, dT
 
     def __call__(self, xyz):
