@@ -28,6 +28,7 @@ SOURCES = [
 ]
 
 ARCH = "gfx950"
+COMPILE_TIMEOUT_S = 600
 COMMON = [
     "-O3",
     "-std=c++17",
@@ -52,7 +53,10 @@ def _compile(src, verbose):
     cmd = [_hipcc(), *COMMON, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd.insert(1, "-xhip")
-    res = subprocess.run(cmd, capture_output=True, text=True)
+    try:
+        res = subprocess.run(cmd, capture_output=True, text=True, timeout=COMPILE_TIMEOUT_S)
+    except subprocess.TimeoutExpired:
+        raise RuntimeError(f"compilation of {src} exceeded {COMPILE_TIMEOUT_S}s") from None
     out = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
         raise RuntimeError(f"compilation of {src} failed:\n{out}")

@@ -73,8 +73,9 @@ struct ieti_handle {
   int nblk = 0;
   std::vector<int64_t> gemv_task_h;
   // device buffers
-  DBuf<double> pool, scatter_val, S, Sinv, Phi, SPi, Spi_glob, G, H, Ht, I_sign, b_aug0, y;
-  DBuf<int64_t> scatter_dst, potrf, trsm, upd, copyS, xsinv, xphi, xspi, fdiag, ffull, fr, bdiag, bupd;
+  DBuf<double> pool, inv, scatter_val, S, Sinv, Phi, SPi, Spi_glob, G, H, Ht, I_sign, b_aug0, y;
+  DBuf<int64_t> scatter_dst, potrf, trsm, upd, upd_pair, copyS, xsinv, xphi, xspi, fdiag, ffull, ffull_pair, fr, fr_pair;
+  DBuf<int64_t> bdiag, bupd, bupd_pair;
   DBuf<int64_t> spi_ptr, spi_src, row_src, I_aug, A_aug, slot_phi_row, dsrc_ptr, dsrc_idx, krp_ptr, krp_pos;
   DBuf<int64_t> out_src, out_edge, primal_edges, gemv_task;
   DBuf<int32_t> I_row, I_sub, glob2loc, krp_col;
@@ -94,12 +95,12 @@ struct ieti_handle {
   double k_count[2] = {0, 0}, k_ms[2] = {0, 0}, upd_tasks = 0;
 
   ~ieti_handle() {
-    DBuf<double>* ds[] = {&pool, &scatter_val, &S, &Sinv, &Phi, &SPi, &Spi_glob, &G, &H, &Ht, &I_sign, &b_aug0, &y,
+    DBuf<double>* ds[] = {&pool, &inv, &scatter_val, &S, &Sinv, &Phi, &SPi, &Spi_glob, &G, &H, &Ht, &I_sign, &b_aug0, &y,
                           &krp_val, &lam, &r, &z, &p, &q, &v, &b, &e, &dtil, &w, &t, &pglob, &part, &scal, &aout,
                           &tmp};
     for (auto* d : ds) d->release();
-    DBuf<int64_t>* is[] = {&scatter_dst, &potrf, &trsm, &upd, &copyS, &xsinv, &xphi, &xspi, &fdiag, &ffull, &fr,
-                           &bdiag, &bupd, &spi_ptr, &spi_src, &row_src, &I_aug, &A_aug, &slot_phi_row, &dsrc_ptr,
+    DBuf<int64_t>* is[] = {&scatter_dst, &potrf, &trsm, &upd, &upd_pair, &copyS, &xsinv, &xphi, &xspi, &fdiag,
+                           &ffull, &ffull_pair, &fr, &fr_pair, &bdiag, &bupd, &bupd_pair, &spi_ptr, &spi_src, &row_src, &I_aug, &A_aug, &slot_phi_row, &dsrc_ptr,
                            &dsrc_idx, &krp_ptr, &krp_pos, &out_src, &out_edge, &primal_edges, &gemv_task};
     for (auto* d : is) d->release();
     I_row.release();
@@ -173,6 +174,10 @@ int upload(ieti_handle* h) {
   UP(potrf, P.potrf_task);
   UP(trsm, P.trsm_task);
   UP(upd, P.upd_task);
+  UP(upd_pair, P.upd_pair);
+  UP(ffull_pair, P.ffull_pair);
+  UP(fr_pair, P.fr_pair);
+  UP(bupd_pair, P.bupd_pair);
   UP(copyS, P.copy_task);
   UP(xsinv, P.xsinv_task);
   UP(xphi, P.xphi_task);
@@ -231,6 +236,7 @@ int upload(ieti_handle* h) {
   const int64_t m_r = M.m_r, n_gp = M.n_gp;
   h->nblk = std::max(1, ieti::dev::combine_blocks(m_r));
   if ((rc = dalloc(h->pool, P.pool_elems))) return rc;
+  if ((rc = dalloc(h->inv, std::max<int64_t>(P.inv_elems, 1)))) return rc;
   if ((rc = dalloc(h->S, P.S_elems))) return rc;
   if ((rc = dalloc(h->Sinv, P.S_elems))) return rc;
   if ((rc = dalloc(h->Phi, std::max<int64_t>(P.Phi_elems, 1)))) return rc;
@@ -334,14 +340,14 @@ void forward_solve(ieti_handle* h, bool full) {
   namespace D = ieti::dev;
   const auto& P = h->plan;
   for (int64_t j = 0; j < P.n_steps; ++j) {
-    D::trsv_diag(h->pool.ptr, h->fdiag.ptr + 2 * P.fdiag_ptr[j], P.fdiag_ptr[j + 1] - P.fdiag_ptr[j], h->y.ptr, false,
+    D::trsv_diag(h->inv.ptr, h->fdiag.ptr + 2 * P.fdiag_ptr[j], P.fdiag_ptr[j + 1] - P.fdiag_ptr[j], h->y.ptr, false,
                  h->stream);
     if (full)
-      D::trsv_update(h->pool.ptr, h->ffull.ptr + 3 * P.ffull_ptr[j], P.ffull_ptr[j + 1] - P.ffull_ptr[j], h->y.ptr,
-                     false, h->stream);
+      D::trsv_update(h->pool.ptr, h->ffull.ptr + 3 * P.ffull_ptr[j], h->ffull_pair.ptr,
+                     P.ffull_ptr[j + 1] - P.ffull_ptr[j], h->y.ptr, false, h->stream);
     else
-      D::trsv_update(h->pool.ptr, h->fr.ptr + 3 * P.fr_ptr[j], P.fr_ptr[j + 1] - P.fr_ptr[j], h->y.ptr, false,
-                     h->stream);
+      D::trsv_update(h->pool.ptr, h->fr.ptr + 3 * P.fr_ptr[j], h->fr_pair.ptr, P.fr_ptr[j + 1] - P.fr_ptr[j],
+                     h->y.ptr, false, h->stream);
   }
 }
 
@@ -349,10 +355,10 @@ void backward_solve(ieti_handle* h) {
   namespace D = ieti::dev;
   const auto& P = h->plan;
   for (int64_t s = 0; s < P.n_steps; ++s) {
-    D::trsv_diag(h->pool.ptr, h->bdiag.ptr + 2 * P.bdiag_ptr[s], P.bdiag_ptr[s + 1] - P.bdiag_ptr[s], h->y.ptr, true,
+    D::trsv_diag(h->inv.ptr, h->bdiag.ptr + 2 * P.bdiag_ptr[s], P.bdiag_ptr[s + 1] - P.bdiag_ptr[s], h->y.ptr, true,
                  h->stream);
-    D::trsv_update(h->pool.ptr, h->bupd.ptr + 3 * P.bupd_ptr[s], P.bupd_ptr[s + 1] - P.bupd_ptr[s], h->y.ptr, true,
-                   h->stream);
+    D::trsv_update(h->pool.ptr, h->bupd.ptr + 3 * P.bupd_ptr[s], h->bupd_pair.ptr, P.bupd_ptr[s + 1] - P.bupd_ptr[s],
+                   h->y.ptr, true, h->stream);
   }
 }
 
@@ -591,14 +597,17 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   D::scatter(h->pool.ptr, h->scatter_dst.ptr, h->scatter_val.ptr, int64_t(P.scatter_dst.size()), s);
   for (int64_t j = 0; j < P.n_steps; ++j) {
     D::copy_tiles(h->pool.ptr, h->copyS.ptr + 5 * P.copy_ptr[j], P.copy_ptr[j + 1] - P.copy_ptr[j], 1.0, h->S.ptr, s);
-    D::potrf_tiles(h->pool.ptr, h->potrf.ptr + 2 * P.potrf_ptr[j], P.potrf_ptr[j + 1] - P.potrf_ptr[j], h->flags.ptr,
-                   s);
-    D::trsm_tiles(h->pool.ptr, h->trsm.ptr + 2 * P.trsm_ptr[j], P.trsm_ptr[j + 1] - P.trsm_ptr[j], s);
+    D::potrf_tiles(h->pool.ptr, h->inv.ptr, h->potrf.ptr + 3 * P.potrf_ptr[j], P.potrf_ptr[j + 1] - P.potrf_ptr[j],
+                   h->flags.ptr, s);
+    D::trsm_tiles(h->pool.ptr, h->inv.ptr, h->trsm.ptr + 2 * P.trsm_ptr[j], P.trsm_ptr[j + 1] - P.trsm_ptr[j], s);
     const int64_t nupd = P.upd_ptr[j + 1] - P.upd_ptr[j];
     const size_t ev = nupd > 0 ? prof_begin(h) : SIZE_MAX;
-    D::update_tiles(h->pool.ptr, h->upd.ptr + 3 * P.upd_ptr[j], nupd, s);
+    D::update_tiles(h->pool.ptr, h->upd.ptr + 3 * P.upd_ptr[j], h->upd_pair.ptr, nupd, s);
     prof_end(h, ev, 1);
-    if (ev != SIZE_MAX) h->upd_tasks += double(nupd);
+    if (ev != SIZE_MAX) {
+      const int64_t* t = P.upd_task.data() + 3 * P.upd_ptr[j];
+      for (int64_t q = 0; q < nupd; ++q) h->upd_tasks += double(t[3 * q + 2]);
+    }
   }
   D::copy_tiles(h->pool.ptr, h->xsinv.ptr, int64_t(P.xsinv_task.size() / 5), -1.0, h->Sinv.ptr, s);
   D::copy_tiles(h->pool.ptr, h->xphi.ptr, int64_t(P.xphi_task.size() / 5), -1.0, h->Phi.ptr, s);

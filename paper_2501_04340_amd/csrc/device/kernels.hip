@@ -2,9 +2,9 @@
 //
 // Factor side: batched right-looking tile Cholesky over 64x64 FP64 tiles
 // (column-major inside a tile) of every subdomain's augmented matrix,
-// driven by host-built task lists (one launch per kernel kind and step).
-// The trailing update C -= A B^T runs on the FP64 matrix cores
-// (v_mfma_f64_16x16x4f64).
+// driven by host-built task lists: one launch per kernel kind and level of
+// the tile elimination tree, all subdomains batched together.  Panel solves
+// and trailing updates run on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
 //
 // Solve side: the interface operator F = sum_k B_k (K_rr^(k))^{-1}_{II} B_k^T
 // + G S_c^{-1} G^T and the Dirichlet preconditioner sum_k B_k S_rIrI B_k^T
@@ -56,81 +56,72 @@ __global__ void k_scatter(double* pool, const int64_t* dst, const double* val, i
     pool[dst[i]] = val[i];
 }
 
-// Unblocked Cholesky of one diagonal tile in LDS.  A non-positive pivot
-// records the subdomain (1-based) in err and continues with pivot 1.
-__global__ __launch_bounds__(256) void k_potrf(double* pool, const int64_t* task, int* err) {
+// Cholesky of one 64x64 diagonal tile in LDS followed by the inverse of the
+// lower factor, written to `inv`.  Thread t owns row t/4 and columns
+// t%4 + 4m (m = 0..15); each column step reads the pivot column, then
+// updates, with two barriers per column.  A non-positive pivot records the
+// subdomain (1-based) in err and continues with pivot 1.
+__global__ __launch_bounds__(256) void k_potrf_inv(double* pool, double* inv, const int64_t* task, int* err) {
   __shared__ double A[T][T + 1];
+  __shared__ double X[T][T + 1];
   __shared__ int bad;
-  const int64_t off = task[2 * blockIdx.x];
-  const int sub = int(task[2 * blockIdx.x + 1]);
-  double* t = pool + off;
-  for (int idx = threadIdx.x; idx < T * T; idx += 256) A[idx & (T - 1)][idx >> 6] = t[idx];
-  if (threadIdx.x == 0) bad = 0;
+  const int64_t* tk = task + 3 * blockIdx.x;
+  double* t = pool + tk[0];
+  const int sub = int(tk[1]);
+  double* tinv = inv + tk[2];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < T * T; idx += 256) A[idx & (T - 1)][idx >> 6] = t[idx];
+  if (tid == 0) bad = 0;
+  const int i = tid >> 2, j0 = tid & 3;
   __syncthreads();
   for (int k = 0; k < T; ++k) {
-    const double d = A[k][k];
-    const double piv = d > 0.0 ? sqrt(d) : 1.0;
-    if (!(d > 0.0) && threadIdx.x == 0) bad = 1;
+    const double akk = A[k][k];
+    const double aik = A[i][k];
+    double ajk[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) ajk[m] = A[j0 + 4 * m][k];
     __syncthreads();
-    if (threadIdx.x < T) {
-      const int i = threadIdx.x;
-      if (i > k) A[i][k] /= piv;
-      else if (i == k) A[k][k] = piv;
-    }
-    __syncthreads();
-    const int n = T - 1 - k;
-    for (int idx = threadIdx.x; idx < n * n; idx += 256) {
-      const int i = k + 1 + idx / n, j = k + 1 + idx % n;
-      if (j <= i) A[i][j] -= A[i][k] * A[j][k];
+    const bool ok = akk > 0.0;
+    if (!ok && tid == 0) bad = 1;
+    const double d = ok ? akk : 1.0;
+    const double piv = sqrt(d);
+    if ((k & 3) == j0 && i >= k) A[i][k] = (i == k) ? piv : aik / piv;
+    const double f = aik / d;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int j = j0 + 4 * m;
+      if (j > k && j <= i) A[i][j] -= f * ajk[m];
     }
     __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < T * T; idx += 256) {
-    const int a = idx & (T - 1), b = idx >> 6;
-    t[idx] = (a >= b) ? A[a][b] : 0.0;
-  }
-  if (threadIdx.x == 0 && bad) atomicMax(err, sub + 1);
-}
-
-// X = A L^{-T} for an off-diagonal tile A below the factored diagonal tile L.
-__global__ __launch_bounds__(256) void k_trsm(double* pool, const int64_t* task) {
-  __shared__ double L[T][T + 1];
-  __shared__ double X[T][T + 1];
-  const double* Lg = pool + task[2 * blockIdx.x];
-  double* Ag = pool + task[2 * blockIdx.x + 1];
-  for (int idx = threadIdx.x; idx < T * T; idx += 256) {
-    const int a = idx & (T - 1), b = idx >> 6;
-    L[a][b] = Lg[idx];
-    X[a][b] = Ag[idx];
+  // inverse of the lower factor, one column per thread: X L^{-1}
+  if (tid < T) {
+    const int c = tid;
+    for (int r = 0; r < c; ++r) X[r][c] = 0.0;
+    X[c][c] = 1.0 / A[c][c];
+    for (int r = c + 1; r < T; ++r) {
+      double v = 0.0;
+      for (int m = c; m < r; ++m) v += A[r][m] * X[m][c];
+      X[r][c] = -v / A[r][r];
+    }
   }
   __syncthreads();
-  for (int c = 0; c < T; ++c) {
-    if (threadIdx.x < T) X[threadIdx.x][c] /= L[c][c];
-    __syncthreads();
-    const int n = T - 1 - c;
-    for (int idx = threadIdx.x; idx < T * n; idx += 256) {
-      const int r = idx & (T - 1), cc = c + 1 + (idx >> 6);
-      X[r][cc] -= X[r][c] * L[cc][c];
-    }
-    __syncthreads();
+  for (int idx = tid; idx < T * T; idx += 256) {
+    const int a = idx & (T - 1), b = idx >> 6;
+    t[idx] = (a >= b) ? A[a][b] : 0.0;
+    tinv[idx] = X[a][b];
   }
-  for (int idx = threadIdx.x; idx < T * T; idx += 256) Ag[idx] = X[idx & (T - 1)][idx >> 6];
+  if (tid == 0 && bad) atomicMax(err, sub + 1);
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// C -= A B^T for 64x64 tiles on the FP64 matrix cores.  Four waves, each
-// owning a 32x32 quadrant as 2x2 blocks of 16x16 MFMA accumulators.
-// Operand layout of v_mfma_f64_16x16x4f64 (per lane l):
-//   A: row l%16, k l/16;  B: k l/16, col l%16;  D (accumulator element r):
+// Accumulate A B^T (64x64 tiles, column-major) into the calling wave's
+// 32x32 quadrant on the FP64 matrix cores.  Four waves, 2x2 blocks of 16x16
+// accumulators each.  Operand layout of v_mfma_f64_16x16x4f64 (lane l):
+//   A: row l%16, k l/16;  B: k l/16, col l%16;  accumulator element r:
 //   row l/16 + 4r, col l%16 (checked on gfx950 with an in-bounds probe).
-__global__ __launch_bounds__(256) void k_update(double* pool, const int64_t* task) {
-  __shared__ __align__(16) double As[T * T];
-  __shared__ __align__(16) double Bs[T * T];
-  const int64_t* tk = task + 3 * blockIdx.x;
-  double* C = pool + tk[0];
-  const double* A = pool + tk[1];
-  const double* B = pool + tk[2];
+__device__ inline void mfma_abt(const double* A, const double* B, double* As, double* Bs, v4d acc[4]) {
   const double2* A2 = reinterpret_cast<const double2*>(A);
   const double2* B2 = reinterpret_cast<const double2*>(B);
   double2* As2 = reinterpret_cast<double2*>(As);
@@ -145,7 +136,6 @@ __global__ __launch_bounds__(256) void k_update(double* pool, const int64_t* tas
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int li = lane & 15, lk = lane >> 4;
-  v4d acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
 #pragma unroll
   for (int kk = 0; kk < T / 4; ++kk) {
     const int k = 4 * kk + lk;
@@ -153,19 +143,54 @@ __global__ __launch_bounds__(256) void k_update(double* pool, const int64_t* tas
     const double a1 = As[k * T + 32 * wr + 16 + li];
     const double b0 = Bs[k * T + 32 * wc + li];
     const double b1 = Bs[k * T + 32 * wc + 16 + li];
-    acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
-    acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
-    acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
-    acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+    acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[1], 0, 0, 0);
+    acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[2], 0, 0, 0);
+    acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[3], 0, 0, 0);
   }
-  const int r0 = 32 * wr + lk, c0 = 32 * wc + li;
+  __syncthreads();
+}
+
+// C = beta * C + sign * acc for the calling wave's quadrant.
+__device__ inline void store_quadrant(double* C, const v4d acc[4], double beta, double sign) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1) + (lane >> 4), c0 = 32 * (w & 1) + (lane & 15);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    C[(c0)*T + r0 + 4 * r] -= acc00[r];
-    C[(c0 + 16) * T + r0 + 4 * r] -= acc01[r];
-    C[(c0)*T + r0 + 16 + 4 * r] -= acc10[r];
-    C[(c0 + 16) * T + r0 + 16 + 4 * r] -= acc11[r];
+    const int rr = r0 + 4 * r;
+    double* c00 = C + (c0)*T + rr;
+    double* c01 = C + (c0 + 16) * T + rr;
+    double* c10 = C + (c0)*T + rr + 16;
+    double* c11 = C + (c0 + 16) * T + rr + 16;
+    *c00 = beta * *c00 + sign * acc[0][r];
+    *c01 = beta * *c01 + sign * acc[1][r];
+    *c10 = beta * *c10 + sign * acc[2][r];
+    *c11 = beta * *c11 + sign * acc[3][r];
   }
+}
+
+// Panel solve as a product with the inverted diagonal tile: X = A L_jj^{-T}.
+__global__ __launch_bounds__(256) void k_trsm_inv(double* pool, const double* inv, const int64_t* task) {
+  __shared__ __align__(16) double As[T * T];
+  __shared__ __align__(16) double Bs[T * T];
+  const int64_t* tk = task + 2 * blockIdx.x;
+  double* A = pool + tk[0];
+  v4d acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  mfma_abt(A, inv + tk[1], As, Bs, acc);
+  store_quadrant(A, acc, 0.0, 1.0);
+}
+
+// C -= sum_p A_p B_p^T over the pairs of one target tile (all contributing
+// columns of one level), accumulated in registers and written once.
+__global__ __launch_bounds__(256) void k_update_multi(double* pool, const int64_t* task, const int64_t* pair) {
+  __shared__ __align__(16) double As[T * T];
+  __shared__ __align__(16) double Bs[T * T];
+  const int64_t* tk = task + 3 * blockIdx.x;
+  double* C = pool + tk[0];
+  const int64_t p0 = tk[1], np = tk[2];
+  v4d acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int64_t q = 0; q < np; ++q) mfma_abt(pool + pair[2 * (p0 + q)], pool + pair[2 * (p0 + q) + 1], As, Bs, acc);
+  store_quadrant(C, acc, 1.0, -1.0);
 }
 
 // Copy (scaled) tiles into dense row-major blocks; optional mirrored copy.
@@ -183,56 +208,49 @@ __global__ void k_copy_tiles(const double* pool, const int64_t* task, double sca
   }
 }
 
-// Diagonal-tile triangular solve on a 64-vector of the augmented vectors.
-__global__ __launch_bounds__(64) void k_trsv_diag(const double* pool, const int64_t* task, double* y, int transposed) {
-  __shared__ double L[T][T + 1];
-  __shared__ double v[T];
-  const double* Lg = pool + task[2 * blockIdx.x];
-  double* yv = y + task[2 * blockIdx.x + 1];
-  for (int idx = threadIdx.x; idx < T * T; idx += 64) L[idx & (T - 1)][idx >> 6] = Lg[idx];
-  v[threadIdx.x] = yv[threadIdx.x];
-  __syncthreads();
-  const int i = threadIdx.x;
-  if (!transposed) {
-    for (int c = 0; c < T; ++c) {
-      if (i == c) v[c] /= L[c][c];
-      __syncthreads();
-      if (i > c) v[i] -= L[i][c] * v[c];
-      __syncthreads();
-    }
-  } else {
-    for (int c = T - 1; c >= 0; --c) {
-      if (i == c) v[c] /= L[c][c];
-      __syncthreads();
-      if (i < c) v[i] -= L[c][i] * v[c];
-      __syncthreads();
-    }
-  }
-  yv[i] = v[i];
-}
-
-// y_dst -= L y_src (forward) or y_dst -= L^T y_src (transposed), one tile.
-__global__ __launch_bounds__(256) void k_trsv_update(const double* pool, const int64_t* task, double* y,
-                                                     int transposed) {
+// y_j <- L_jj^{-1} y_j (or L_jj^{-T} y_j) with the inverted diagonal tile.
+__global__ __launch_bounds__(256) void k_trsv_diag_inv(const double* inv, const int64_t* task, double* y,
+                                                       int transposed) {
   __shared__ double L[T][T + 1];
   __shared__ double x[T];
-  const int64_t* tk = task + 3 * blockIdx.x;
-  const double* Lg = pool + tk[0];
-  double* yd = y + tk[1];
-  const double* ys = y + tk[2];
+  __shared__ double part[4][T];
+  const double* Lg = inv + task[2 * blockIdx.x];
+  double* yv = y + task[2 * blockIdx.x + 1];
   for (int idx = threadIdx.x; idx < T * T; idx += 256) L[idx & (T - 1)][idx >> 6] = Lg[idx];
-  if (threadIdx.x < T) x[threadIdx.x] = ys[threadIdx.x];
+  if (threadIdx.x < T) x[threadIdx.x] = yv[threadIdx.x];
   __syncthreads();
-  if (threadIdx.x < T) {
-    const int a = threadIdx.x;
-    double s = 0.0;
-    if (!transposed) {
-      for (int b = 0; b < T; ++b) s += L[a][b] * x[b];
-    } else {
-      for (int b = 0; b < T; ++b) s += L[b][a] * x[b];
-    }
-    yd[a] -= s;
+  const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
+  double s = 0.0;
+  for (int b = 16 * q; b < 16 * q + 16; ++b) s += (transposed ? L[b][a] : L[a][b]) * x[b];
+  part[q][a] = s;
+  __syncthreads();
+  if (threadIdx.x < T) yv[a] = (part[0][a] + part[1][a]) + (part[2][a] + part[3][a]);
+}
+
+// y_dst -= sum_p L_p x_p (forward) or sum_p L_p^T x_p (transposed) over the
+// pairs [tile, vec_src] of one target.
+__global__ __launch_bounds__(256) void k_trsv_update_multi(const double* pool, const int64_t* task,
+                                                           const int64_t* pair, double* y, int transposed) {
+  __shared__ double L[T][T + 1];
+  __shared__ double x[T];
+  __shared__ double part[4][T];
+  const int64_t* tk = task + 3 * blockIdx.x;
+  double* yd = y + tk[0];
+  const int64_t p0 = tk[1], np = tk[2];
+  const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
+  double s = 0.0;
+  for (int64_t pp = 0; pp < np; ++pp) {
+    const double* Lg = pool + pair[2 * (p0 + pp)];
+    const double* ys = y + pair[2 * (p0 + pp) + 1];
+    for (int idx = threadIdx.x; idx < T * T; idx += 256) L[idx & (T - 1)][idx >> 6] = Lg[idx];
+    if (threadIdx.x < T) x[threadIdx.x] = ys[threadIdx.x];
+    __syncthreads();
+    for (int b = 16 * q; b < 16 * q + 16; ++b) s += (transposed ? L[b][a] : L[a][b]) * x[b];
+    __syncthreads();
   }
+  part[q][a] = s;
+  __syncthreads();
+  if (threadIdx.x < T) yd[a] -= (part[0][a] + part[1][a]) + (part[2][a] + part[3][a]);
 }
 
 __global__ void k_sum_sources(const double* src, const int64_t* ptr, const int64_t* idx, int64_t nout, double* out) {
@@ -525,29 +543,30 @@ void scatter(double* pool, const int64_t* dst, const double* val, int64_t n, hip
   if (n <= 0) return;
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, pool, dst, val, n);
 }
-void potrf_tiles(double* pool, const int64_t* task, int64_t ntask, int* err, hipStream_t s) {
+void potrf_tiles(double* pool, double* inv, const int64_t* task, int64_t ntask, int* err, hipStream_t s) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(k_potrf, dim3(ntask), dim3(256), 0, s, pool, task, err);
+  hipLaunchKernelGGL(k_potrf_inv, dim3(ntask), dim3(256), 0, s, pool, inv, task, err);
 }
-void trsm_tiles(double* pool, const int64_t* task, int64_t ntask, hipStream_t s) {
+void trsm_tiles(double* pool, const double* inv, const int64_t* task, int64_t ntask, hipStream_t s) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(k_trsm, dim3(ntask), dim3(256), 0, s, pool, task);
+  hipLaunchKernelGGL(k_trsm_inv, dim3(ntask), dim3(256), 0, s, pool, inv, task);
 }
-void update_tiles(double* pool, const int64_t* task, int64_t ntask, hipStream_t s) {
+void update_tiles(double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, hipStream_t s) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(k_update, dim3(ntask), dim3(256), 0, s, pool, task);
+  hipLaunchKernelGGL(k_update_multi, dim3(ntask), dim3(256), 0, s, pool, task, pair);
 }
 void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s) {
   if (ntask <= 0) return;
   hipLaunchKernelGGL(k_copy_tiles, dim3(ntask), dim3(256), 0, s, pool, task, scale, dst);
 }
-void trsv_diag(const double* pool, const int64_t* task, int64_t ntask, double* y, bool transposed, hipStream_t s) {
+void trsv_diag(const double* inv, const int64_t* task, int64_t ntask, double* y, bool transposed, hipStream_t s) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(k_trsv_diag, dim3(ntask), dim3(64), 0, s, pool, task, y, transposed ? 1 : 0);
+  hipLaunchKernelGGL(k_trsv_diag_inv, dim3(ntask), dim3(256), 0, s, inv, task, y, transposed ? 1 : 0);
 }
-void trsv_update(const double* pool, const int64_t* task, int64_t ntask, double* y, bool transposed, hipStream_t s) {
+void trsv_update(const double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, double* y,
+                 bool transposed, hipStream_t s) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(k_trsv_update, dim3(ntask), dim3(256), 0, s, pool, task, y, transposed ? 1 : 0);
+  hipLaunchKernelGGL(k_trsv_update_multi, dim3(ntask), dim3(256), 0, s, pool, task, pair, y, transposed ? 1 : 0);
 }
 void sum_sources(const double* src, const int64_t* ptr, const int64_t* idx, int64_t nout, double* out, hipStream_t s) {
   if (nout <= 0) return;

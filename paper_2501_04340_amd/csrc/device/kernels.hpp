@@ -13,14 +13,20 @@ constexpr int TILE = 64;
 // ---- factorisation (tile pool, column-major 64x64 tiles)
 void fill(double* p, int64_t n, double v, hipStream_t s);
 void scatter(double* pool, const int64_t* dst, const double* val, int64_t n, hipStream_t s);
-void potrf_tiles(double* pool, const int64_t* task, int64_t ntask, int* err, hipStream_t s);
-void trsm_tiles(double* pool, const int64_t* task, int64_t ntask, hipStream_t s);
-void update_tiles(double* pool, const int64_t* task, int64_t ntask, hipStream_t s);
+// potrf task [off_jj, subdomain, off of the inverse]; writes L_jj and L_jj^{-1}
+void potrf_tiles(double* pool, double* inv, const int64_t* task, int64_t ntask, int* err, hipStream_t s);
+// trsm task [off_ij, off of L_jj^{-1}]: L_ij = A_ij L_jj^{-T}
+void trsm_tiles(double* pool, const double* inv, const int64_t* task, int64_t ntask, hipStream_t s);
+// update task [off_C, first pair, pair count], pairs [off_A, off_B]: C -= sum A B^T
+void update_tiles(double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, hipStream_t s);
 void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s);
 
 // ---- triangular solves with the tile factor (augmented vectors)
-void trsv_diag(const double* pool, const int64_t* task, int64_t ntask, double* y, bool transposed, hipStream_t s);
-void trsv_update(const double* pool, const int64_t* task, int64_t ntask, double* y, bool transposed, hipStream_t s);
+// diag task [off of L_jj^{-1}, vec_j]: y_j <- L_jj^{-1} y_j (or ^{-T})
+void trsv_diag(const double* inv, const int64_t* task, int64_t ntask, double* y, bool transposed, hipStream_t s);
+// update task [vec_dst, first pair, count], pairs [off_tile, vec_src]: y_dst -= sum L x (or L^T x)
+void trsv_update(const double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, double* y,
+                 bool transposed, hipStream_t s);
 
 // ---- coarse problem
 void sum_sources(const double* src, const int64_t* ptr, const int64_t* idx, int64_t nout, double* out, hipStream_t s);

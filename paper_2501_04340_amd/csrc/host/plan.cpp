@@ -11,11 +11,12 @@ namespace {
 
 // Nested dissection of the r_V DOFs by recursive coordinate bisection with
 // one-sided vertex separators taken from the sparsity graph of K_VV.
+// Blocks (leaves and separators) are appended to `out` in elimination order.
 void nested_dissection(const std::vector<std::vector<int32_t>>& adj, const std::vector<double>& xyz,
-                       std::vector<int32_t>& ids, std::vector<int32_t>& out, std::vector<int8_t>& side,
+                       std::vector<int32_t>& ids, std::vector<std::vector<int32_t>>& out, std::vector<int8_t>& side,
                        int leaf) {
   if (int(ids.size()) <= leaf) {
-    out.insert(out.end(), ids.begin(), ids.end());
+    if (!ids.empty()) out.push_back(ids);
     return;
   }
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -44,7 +45,7 @@ void nested_dissection(const std::vector<std::vector<int32_t>>& adj, const std::
   }
   if (left.empty() || right.empty()) {
     for (int32_t v : ids) side[v] = 0;
-    out.insert(out.end(), ids.begin(), ids.end());
+    out.push_back(ids);
     return;
   }
   std::vector<int32_t> right2;
@@ -60,7 +61,7 @@ void nested_dissection(const std::vector<std::vector<int32_t>>& adj, const std::
   for (int32_t v : ids) side[v] = 0;
   nested_dissection(adj, xyz, left, out, side, leaf);
   nested_dissection(adj, xyz, right2, out, side, leaf);
-  out.insert(out.end(), sep.begin(), sep.end());
+  if (!sep.empty()) out.push_back(sep);
 }
 
 int64_t round_up(int64_t x, int64_t t) { return (x + t - 1) / t * t; }
@@ -82,15 +83,13 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
     sp.nV = int64_t(s.V_local.size());
     sp.nI = int64_t(s.I_local.size());
     sp.nP = int64_t(s.p_edges.size());
-    sp.nVp = round_up(sp.nV, T);
     sp.nIp = round_up(sp.nI, T);
     sp.nPp = round_up(sp.nP, T);
-    sp.ntV = sp.nVp / T;
-    sp.ntr = sp.ntV + sp.nIp / T;
-    sp.nt = sp.ntr + sp.nPp / T + sp.nIp / T;
     const int64_t nr = int64_t(s.r_edges.size());
-    // ---- ordering of r_V
-    std::vector<int32_t> vorder;
+    // ---- ordering of r_V: nested-dissection blocks, each padded to whole
+    // tiles with identity dummies so that independent subtrees never share
+    // a tile (their columns then sit on independent levels of the schedule)
+    std::vector<int32_t> vslot;  // augmented position -> V index, -1 = dummy
     if (ordering == 0 && sp.nV > 0) {
       std::vector<int32_t> vidx(nr, -1);
       for (int32_t t = 0; t < int32_t(sp.nV); ++t) vidx[s.V_local[t]] = t;
@@ -120,14 +119,27 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
       std::vector<int32_t> ids(sp.nV);
       std::iota(ids.begin(), ids.end(), 0);
       std::vector<int8_t> side(sp.nV, 0);
-      nested_dissection(adj, xyz, ids, vorder, side, 4 * T);
+      std::vector<std::vector<int32_t>> blocks;
+      nested_dissection(adj, xyz, ids, blocks, side, 4 * T);
+      for (const auto& b : blocks) {
+        vslot.insert(vslot.end(), b.begin(), b.end());
+        while (vslot.size() % T) vslot.push_back(-1);
+      }
     } else {
-      vorder.resize(sp.nV);
-      std::iota(vorder.begin(), vorder.end(), 0);
+      for (int32_t t = 0; t < int32_t(sp.nV); ++t) vslot.push_back(t);
+      while (vslot.size() % T) vslot.push_back(-1);
     }
+    sp.nVp = int64_t(vslot.size());
+    sp.ntV = sp.nVp / T;
+    sp.ntr = sp.ntV + sp.nIp / T;
+    sp.nt = sp.ntr + sp.nPp / T + sp.nIp / T;
+    sp.vdummy.clear();
+    for (int64_t q = 0; q < sp.nVp; ++q)
+      if (vslot[q] < 0) sp.vdummy.push_back(q);
     // ---- augmented positions of local [r, p] DOFs
     sp.pos_of_local.assign(s.n_loc, -1);
-    for (int64_t t = 0; t < sp.nV; ++t) sp.pos_of_local[s.V_local[vorder[t]]] = int32_t(t);
+    for (int64_t q = 0; q < sp.nVp; ++q)
+      if (vslot[q] >= 0) sp.pos_of_local[s.V_local[vslot[q]]] = int32_t(q);
     for (int64_t t = 0; t < sp.nI; ++t) sp.pos_of_local[s.I_local[t]] = int32_t(sp.nVp + t);
     for (int64_t t = 0; t < sp.nP; ++t) sp.pos_of_local[nr + t] = int32_t(sp.nVp + sp.nIp + t);
     const int64_t a0 = sp.nVp + sp.nIp + sp.nPp;  // first augmented (E_I) position
@@ -199,27 +211,60 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
         if (pr / T > pc / T || (pr / T == pc / T)) put(pr, pc, s.values[q]);
       }
     }
-    for (int64_t t = sp.nV; t < sp.nVp; ++t) put(t, t, 1.0);
+    for (int64_t q : sp.vdummy) put(q, q, 1.0);
     for (int64_t t = sp.nVp + sp.nI; t < sp.nVp + sp.nIp; ++t) put(t, t, 1.0);
     const int64_t a0 = sp.nVp + sp.nIp + sp.nPp;
     for (int64_t t = 0; t < sp.nI; ++t) put(a0 + t, sp.nVp + t, 1.0);
   }
-  // ---------------------------------------------------------------- step task lists
-  int64_t n_steps = 0;
-  for (const auto& sp : plan.sub) n_steps = std::max(n_steps, sp.ntr);
-  plan.n_steps = n_steps;
+  // ---------------------------------------------------------------- level schedule
+  // Column j of the tile factor depends on every column k < j with a tile
+  // (j, k); level(j) = 1 + max level(k).  Columns of one level are
+  // independent, so each level is one batched potrf, trsm and update launch.
+  // The r_I columns (a dense block) follow all r_V columns, so that S_rIrI
+  // is complete at the start of the first r_I level.
+  std::vector<std::vector<int32_t>> lev(S);
+  std::vector<std::vector<int64_t>> inv_off(S);
+  int64_t n_levels = 0, inv_elems = 0;
+  for (int k = 0; k < S; ++k) {
+    SubPlan& sp = plan.sub[k];
+    const int64_t nt = sp.nt;
+    auto& L = lev[k];
+    L.assign(sp.ntr, 0);
+    int32_t maxV = -1;
+    for (int64_t j = 0; j < sp.ntV; ++j) {
+      maxV = std::max(maxV, L[j]);
+      for (int64_t i = j + 1; i < sp.ntV; ++i)
+        if (sp.tile_off[i * nt + j] >= 0) L[i] = std::max(L[i], L[j] + 1);
+    }
+    for (int64_t j = sp.ntV; j < sp.ntr; ++j) L[j] = maxV + 1 + int32_t(j - sp.ntV);
+    sp.levS = maxV + 1;
+    sp.nlev = sp.ntr > 0 ? (sp.ntr > sp.ntV ? L[sp.ntr - 1] + 1 : maxV + 1) : 0;
+    n_levels = std::max<int64_t>(n_levels, sp.nlev);
+    inv_off[k].assign(sp.ntr, 0);
+    for (int64_t j = 0; j < sp.ntr; ++j) {
+      inv_off[k][j] = inv_elems;
+      inv_elems += int64_t(T) * T;
+    }
+  }
+  plan.n_steps = n_levels;
+  plan.inv_elems = inv_elems;
+  // columns of each level, per subdomain
+  std::vector<std::vector<std::vector<int64_t>>> cols(S);
+  for (int k = 0; k < S; ++k) {
+    cols[k].assign(n_levels, {});
+    for (int64_t j = 0; j < plan.sub[k].ntr; ++j) cols[k][lev[k][j]].push_back(j);
+  }
   plan.potrf_ptr.assign(1, 0);
   plan.trsm_ptr.assign(1, 0);
   plan.upd_ptr.assign(1, 0);
   plan.copy_ptr.assign(1, 0);
   const double T3 = double(T) * T * T;
-  for (int64_t j = 0; j < n_steps; ++j) {
+  for (int64_t lv = 0; lv < n_levels; ++lv) {
     for (int k = 0; k < S; ++k) {
       const SubPlan& sp = plan.sub[k];
       const int64_t nt = sp.nt;
       auto off = [&](int64_t i, int64_t l) { return sp.tile_off[i * nt + l]; };
-      // Schur complement S_rIrI is complete once the r_V columns are eliminated
-      if (j == sp.ntV && sp.nIp > 0) {
+      if (lv == sp.levS && sp.nIp > 0) {
         for (int64_t i = sp.ntV; i < sp.ntr; ++i)
           for (int64_t l = sp.ntV; l <= i; ++l) {
             const int64_t o = off(i, l);
@@ -229,29 +274,48 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
                                   {o, sp.S_off + r0 * sp.nIp + c0, sp.S_off + c0 * sp.nIp + r0, sp.nIp, i == l ? 1 : 0});
           }
       }
-      if (j >= sp.ntr) continue;
-      plan.potrf_task.insert(plan.potrf_task.end(), {off(j, j), int64_t(k)});
-      plan.flops += T3 / 3.0;
-      std::vector<int64_t> rows;
-      for (int64_t i = j + 1; i < nt; ++i)
-        if (off(i, j) >= 0) rows.push_back(i);
-      for (int64_t i : rows) {
-        plan.trsm_task.insert(plan.trsm_task.end(), {off(j, j), off(i, j)});
-        plan.flops += T3;
-      }
-      for (size_t x = 0; x < rows.size(); ++x)
-        for (size_t y = 0; y <= x; ++y) {
-          const int64_t i = rows[x], l = rows[y];
-          plan.upd_task.insert(plan.upd_task.end(), {off(i, l), off(i, j), off(l, j)});
-          plan.flops += 2.0 * T3;
+      // targets of this level's updates, each with its contributing columns
+      std::vector<std::pair<int64_t, int64_t>> contrib;  // (target index i*nt+l, column j)
+      for (int64_t j : cols[k][lv]) {
+        plan.potrf_task.insert(plan.potrf_task.end(), {off(j, j), int64_t(k), inv_off[k][j]});
+        plan.flops += T3 / 3.0;
+        std::vector<int64_t> rows;
+        for (int64_t i = j + 1; i < nt; ++i)
+          if (off(i, j) >= 0) rows.push_back(i);
+        for (int64_t i : rows) {
+          plan.trsm_task.insert(plan.trsm_task.end(), {off(i, j), inv_off[k][j]});
+          plan.flops += T3;
         }
+        for (size_t x = 0; x < rows.size(); ++x)
+          for (size_t y = 0; y <= x; ++y) {
+            contrib.emplace_back(rows[x] * nt + rows[y], j);
+            plan.flops += 2.0 * T3;
+          }
+      }
+      std::stable_sort(contrib.begin(), contrib.end(),
+                       [](const std::pair<int64_t, int64_t>& a, const std::pair<int64_t, int64_t>& b) {
+                         return a.first < b.first;
+                       });
+      size_t q = 0;
+      while (q < contrib.size()) {
+        size_t e = q;
+        const int64_t tgt = contrib[q].first, i = tgt / nt, l = tgt % nt;
+        const int64_t p0 = int64_t(plan.upd_pair.size() / 2);
+        while (e < contrib.size() && contrib[e].first == tgt) {
+          const int64_t j = contrib[e].second;
+          plan.upd_pair.insert(plan.upd_pair.end(), {off(i, j), off(l, j)});
+          ++e;
+        }
+        plan.upd_task.insert(plan.upd_task.end(), {off(i, l), p0, int64_t(e - q)});
+        q = e;
+      }
     }
-    plan.potrf_ptr.push_back(int64_t(plan.potrf_task.size() / 2));
+    plan.potrf_ptr.push_back(int64_t(plan.potrf_task.size() / 3));
     plan.trsm_ptr.push_back(int64_t(plan.trsm_task.size() / 2));
     plan.upd_ptr.push_back(int64_t(plan.upd_task.size() / 3));
     plan.copy_ptr.push_back(int64_t(plan.copy_task.size() / 5));
   }
-  plan.n_update_tasks = int64_t(plan.upd_task.size() / 3);
+  plan.n_update_tasks = int64_t(plan.upd_pair.size() / 2);
   // ---------------------------------------------------------------- extraction lists
   for (int k = 0; k < S; ++k) {
     const SubPlan& sp = plan.sub[k];
@@ -283,21 +347,43 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
       }
   }
   // ---------------------------------------------------------------- triangular-solve lists
+  // Forward: per level, x_j = L_jj^{-1} y_j for the level's columns, then every
+  // target row tile i gets y_i -= sum_j L_ij x_j over the level's columns.
+  // Backward: levels in reverse, x_j = L_jj^{-T} y_j, then y_k -= sum_j L_jk^T x_j.
   plan.fdiag_ptr.assign(1, 0);
   plan.ffull_ptr.assign(1, 0);
   plan.fr_ptr.assign(1, 0);
-  for (int64_t j = 0; j < n_steps; ++j) {
+  auto emit_targets = [&](std::vector<std::pair<int64_t, std::pair<int64_t, int64_t>>>& c, std::vector<int64_t>& task,
+                          std::vector<int64_t>& pair) {
+    std::stable_sort(c.begin(), c.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    size_t q = 0;
+    while (q < c.size()) {
+      size_t e = q;
+      const int64_t p0 = int64_t(pair.size() / 2);
+      while (e < c.size() && c[e].first == c[q].first) {
+        pair.insert(pair.end(), {c[e].second.first, c[e].second.second});
+        ++e;
+      }
+      task.insert(task.end(), {c[q].first, p0, int64_t(e - q)});
+      q = e;
+    }
+  };
+  for (int64_t lv = 0; lv < n_levels; ++lv) {
     for (int k = 0; k < S; ++k) {
       const SubPlan& sp = plan.sub[k];
-      if (j >= sp.ntr) continue;
       const int64_t nt = sp.nt;
-      plan.fdiag_task.insert(plan.fdiag_task.end(), {sp.tile_off[j * nt + j], sp.r_off + j * T});
-      for (int64_t i = j + 1; i < nt; ++i) {
-        const int64_t o = sp.tile_off[i * nt + j];
-        if (o < 0) continue;
-        plan.ffull_task.insert(plan.ffull_task.end(), {o, sp.r_off + i * T, sp.r_off + j * T});
-        if (i < sp.ntr) plan.fr_task.insert(plan.fr_task.end(), {o, sp.r_off + i * T, sp.r_off + j * T});
+      std::vector<std::pair<int64_t, std::pair<int64_t, int64_t>>> full, ronly;  // (vec_i, (tile, vec_j))
+      for (int64_t j : cols[k][lv]) {
+        plan.fdiag_task.insert(plan.fdiag_task.end(), {inv_off[k][j], sp.r_off + j * T});
+        for (int64_t i = j + 1; i < nt; ++i) {
+          const int64_t o = sp.tile_off[i * nt + j];
+          if (o < 0) continue;
+          full.push_back({sp.r_off + i * T, {o, sp.r_off + j * T}});
+          if (i < sp.ntr) ronly.push_back({sp.r_off + i * T, {o, sp.r_off + j * T}});
+        }
       }
+      emit_targets(full, plan.ffull_task, plan.ffull_pair);
+      emit_targets(ronly, plan.fr_task, plan.fr_pair);
     }
     plan.fdiag_ptr.push_back(int64_t(plan.fdiag_task.size() / 2));
     plan.ffull_ptr.push_back(int64_t(plan.ffull_task.size() / 3));
@@ -305,17 +391,20 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
   }
   plan.bdiag_ptr.assign(1, 0);
   plan.bupd_ptr.assign(1, 0);
-  for (int64_t j = n_steps - 1; j >= 0; --j) {
+  for (int64_t lv = n_levels - 1; lv >= 0; --lv) {
     for (int k = 0; k < S; ++k) {
       const SubPlan& sp = plan.sub[k];
-      if (j >= sp.ntr) continue;
       const int64_t nt = sp.nt;
-      plan.bdiag_task.insert(plan.bdiag_task.end(), {sp.tile_off[j * nt + j], sp.r_off + j * T});
-      for (int64_t i = 0; i < j; ++i) {
-        const int64_t o = sp.tile_off[j * nt + i];
-        if (o < 0) continue;
-        plan.bupd_task.insert(plan.bupd_task.end(), {o, sp.r_off + i * T, sp.r_off + j * T});
+      std::vector<std::pair<int64_t, std::pair<int64_t, int64_t>>> c;  // (vec_k, (tile (j,k), vec_j))
+      for (int64_t j : cols[k][lv]) {
+        plan.bdiag_task.insert(plan.bdiag_task.end(), {inv_off[k][j], sp.r_off + j * T});
+        for (int64_t i = 0; i < j; ++i) {
+          const int64_t o = sp.tile_off[j * nt + i];
+          if (o < 0) continue;
+          c.push_back({sp.r_off + i * T, {o, sp.r_off + j * T}});
+        }
       }
+      emit_targets(c, plan.bupd_task, plan.bupd_pair);
     }
     plan.bdiag_ptr.push_back(int64_t(plan.bdiag_task.size() / 2));
     plan.bupd_ptr.push_back(int64_t(plan.bupd_task.size() / 3));

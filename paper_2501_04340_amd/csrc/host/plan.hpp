@@ -28,6 +28,7 @@ struct SubPlan {
   int64_t nVp = 0, nIp = 0, nPp = 0;   // padded to the tile size
   int64_t nt = 0, ntV = 0, ntr = 0;    // tiles: total, r_V, r (= r_V + r_I)
   std::vector<int32_t> pos_of_local;   // local [r,p] index -> augmented position
+  std::vector<int64_t> vdummy;         // augmented positions of identity dummies in the r_V block
   std::vector<int64_t> tile_off;       // nt*nt, lower tiles: pool offset or -1
   int64_t S_off = 0;                   // offset of the dense nIp x nIp S / Sinv blocks
   int64_t I_off = 0;                   // offset into the concatenated interface vectors
@@ -35,18 +36,22 @@ struct SubPlan {
   int64_t r_off = 0;                   // offset into concatenated augmented vectors (nt*T each)
   int64_t Phi_off = 0;                 // dense nIp x nPp block (K_rr^{-1} K_rp)_I
   int64_t SPi_off = 0;                 // dense nPp x nPp local coarse block
+  int32_t levS = 0;                    // level at whose start S_rIrI is complete
+  int32_t nlev = 0;                    // number of levels of this subdomain
 };
 
 struct Plan {
   int T = 64;
   int64_t pool_elems = 0;
-  int64_t n_steps = 0;
+  int64_t n_steps = 0;   // number of levels of the schedule
+  int64_t inv_elems = 0;  // inverses of the factored diagonal tiles
   std::vector<SubPlan> sub;
   // per step, ranges into flat task arrays
   std::vector<int64_t> potrf_ptr, trsm_ptr, upd_ptr, copy_ptr;
-  std::vector<int64_t> potrf_task;   // [off_jj, sub]
-  std::vector<int64_t> trsm_task;    // [off_jj, off_ij]
-  std::vector<int64_t> upd_task;     // [off_il, off_ij, off_lj]
+  std::vector<int64_t> potrf_task;   // [off_jj, sub, off of L_jj^{-1}]
+  std::vector<int64_t> trsm_task;    // [off_ij, off of L_jj^{-1}]
+  std::vector<int64_t> upd_task;     // [off_il, first pair, pair count]
+  std::vector<int64_t> upd_pair;     // [off_ij, off_lj]
   std::vector<int64_t> copy_task;    // [off_tile, dst_offset_in_S, ld (= nIp), transpose-needed]
   // scatter of the assembled entries into the tile pool
   std::vector<int64_t> scatter_dst;
@@ -59,9 +64,10 @@ struct Plan {
   int64_t Phi_elems = 0, SPi_elems = 0;
   // extraction after the factorisation: [off_tile, dst, dst_transposed or -1, ld, is_diag]
   std::vector<int64_t> xsinv_task, xphi_task, xspi_task;
-  // triangular solves with the factor, per step: diag [off_jj, vec_j], update [off_tile, vec_dst, vec_src]
-  std::vector<int64_t> fdiag_ptr, fdiag_task, ffull_ptr, ffull_task, fr_ptr, fr_task;
-  std::vector<int64_t> bdiag_ptr, bdiag_task, bupd_ptr, bupd_task;
+  // triangular solves with the factor, per level: diag [off of L_jj^{-1}, vec_j],
+  // update targets [vec_dst, first pair, pair count] with pairs [off_tile, vec_src]
+  std::vector<int64_t> fdiag_ptr, fdiag_task, ffull_ptr, ffull_task, ffull_pair, fr_ptr, fr_task, fr_pair;
+  std::vector<int64_t> bdiag_ptr, bdiag_task, bupd_ptr, bupd_task, bupd_pair;
   // interface gather/scatter: per padded interface slot, multiplier row (-1 = pad) and sign
   std::vector<int32_t> I_row;
   std::vector<double> I_sign;
