@@ -200,9 +200,10 @@ int ieti_get_rhs(ieti_handle* h, double* b);
 int ieti_get_plan_info(const ieti_handle* h, double* info);
 
 /* Kernel timing for roofline measurements.  enable = 1 clears the counters
- * and records a pair of HIP events on the handle's stream around every
- * launch of the interface GEMV (operator and preconditioner) and of the
- * tile-update kernel of the factorisation; enable = 0 stops recording. */
+ * and records HIP events at the boundaries of every launch of the interface
+ * GEMV (operator and preconditioner) and of the tile-update kernel of the
+ * factorisation; while enabled, solves launch PCG kernels directly instead of
+ * replaying the captured graph.  enable = 0 stops recording. */
 int ieti_set_profiling(ieti_handle* h, int32_t enable);
 
 /* times[0..5] = {GEMV launches, GEMV total ms, update launches, update total

@@ -81,6 +81,11 @@ struct ieti_handle {
   DBuf<int32_t> I_row, I_sub, glob2loc, krp_col;
   DBuf<double> krp_val;
   DBuf<double> lam, r, z, p, q, v, b, e, dtil, w, t, pglob, part, scal, aout, tmp;
+  DBuf<double> xgp, xgr, part_g, part_t;  // gathered B^T p and B^T r, GEMV and coarse partials
+  int ngemv = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+
   DBuf<int> flags;  // [0] err (factor), [1] done, [2] iters, [3] pcg err, [4] coarse err
   int* flags_h = nullptr;
   double factor_ms = 0.0;
@@ -97,7 +102,7 @@ struct ieti_handle {
   ~ieti_handle() {
     DBuf<double>* ds[] = {&pool, &inv, &scatter_val, &S, &Sinv, &Phi, &SPi, &Spi_glob, &G, &H, &Ht, &I_sign, &b_aug0, &y,
                           &krp_val, &lam, &r, &z, &p, &q, &v, &b, &e, &dtil, &w, &t, &pglob, &part, &scal, &aout,
-                          &tmp};
+                          &tmp, &xgp, &xgr, &part_g, &part_t};
     for (auto* d : ds) d->release();
     DBuf<int64_t>* is[] = {&scatter_dst, &potrf, &trsm, &upd, &upd_pair, &copyS, &xsinv, &xphi, &xspi, &fdiag,
                            &ffull, &ffull_pair, &fr, &fr_pair, &bdiag, &bupd, &bupd_pair, &spi_ptr, &spi_src, &row_src, &I_aug, &A_aug, &slot_phi_row, &dsrc_ptr,
@@ -113,6 +118,8 @@ struct ieti_handle {
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     if (ev2) (void)hipEventDestroy(ev2);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (own_stream) (void)hipStreamDestroy(own_stream);
   }
 };
@@ -255,6 +262,21 @@ int upload(ieti_handle* h) {
   for (auto* d : vecs_g)
     if ((rc = dalloc(*d, gg))) return rc;
   if ((rc = dalloc(h->part, 3 * int64_t(h->nblk)))) return rc;
+  h->ngemv = int(h->gemv_task_h.size() / 5);
+  if ((rc = dalloc(h->xgp, std::max<int64_t>(P.I_total, 1)))) return rc;
+  if ((rc = dalloc(h->xgr, std::max<int64_t>(P.I_total, 1)))) return rc;
+  HIP_TRY(hipMemset(h->xgp.ptr, 0, h->xgp.n * sizeof(double)));
+  HIP_TRY(hipMemset(h->xgr.ptr, 0, h->xgr.n * sizeof(double)));
+  if ((rc = dalloc(h->part_g, std::max(h->ngemv, 1)))) return rc;
+  if ((rc = dalloc(h->part_t, std::max<int64_t>(int64_t(h->nblk) * n_gp, 1)))) return rc;
+  if (h->graph_exec) {
+    (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+  }
+  if (h->graph) {
+    (void)hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
   if ((rc = dalloc(h->scal, 8))) return rc;
   if ((rc = dalloc(h->flags, 8))) return rc;
   if ((rc = dalloc(h->aout, M.mesh.n_edges))) return rc;
@@ -310,29 +332,76 @@ int check_launch() {
   return IETI_OK;
 }
 
-// F x = sum_k B_k Sinv_k B_k^T x + H (H^T x) -> out; optional partial dot(dotx, out)
-void apply_F(ieti_handle* h, const double* x, double* out, const double* dotx, double* partial, const int* done) {
-  namespace D = ieti::dev;
-  const auto& M = h->model;
-  hipStream_t s = h->stream;
-  const size_t ev = prof_begin(h);
-  D::gemv_interface(h->Sinv.ptr, h->gemv_task.ptr, int64_t(h->gemv_task_h.size() / 5), h->I_row.ptr, h->I_sign.ptr,
-                    x, h->v.ptr, done, h->max_ld, s);
-  prof_end(h, ev, 0);
-  if (M.n_gp > 0) D::coarse_project(h->Ht.ptr, M.n_gp, M.m_r, x, h->t.ptr, done, s);
-  D::combine(h->v.ptr, h->row_src.ptr, M.m_r, M.n_gp > 0 ? h->H.ptr : nullptr, h->t.ptr, M.n_gp, out, dotx, partial,
-             done, s);
+// Interface GEMV over all subdomains, timed with launch events when profiling.
+void gemv_timed(ieti_handle* h, const double* M, const double* xg, double* v, const int* done = nullptr) {
+  hipEvent_t a = nullptr, b = nullptr;
+  size_t slot = SIZE_MAX;
+  if (h->profiling) {
+    slot = h->ev_used;
+    a = next_event(h);
+    b = next_event(h);
+    if (!a || !b) a = b = nullptr;
+  }
+  ieti::dev::gemv(M, h->gemv_task.ptr, h->ngemv, h->max_ld, xg, v, h->part_g.ptr, done, h->stream, a, b);
+  if (a) h->ev_marks.emplace_back(0, slot);
 }
 
-void apply_M(ieti_handle* h, const double* x, double* out, const double* dotx, double* partial, const int* done) {
+// q = F x = sum_k B_k (K_rr^(k))^{-1}_II B_k^T x + H (H^T x)
+void apply_F(ieti_handle* h, const double* x, double* out) {
   namespace D = ieti::dev;
   const auto& M = h->model;
   hipStream_t s = h->stream;
-  const size_t ev = prof_begin(h);
-  D::gemv_interface(h->S.ptr, h->gemv_task.ptr, int64_t(h->gemv_task_h.size() / 5), h->I_row.ptr, h->I_sign.ptr, x,
-                    h->v.ptr, done, h->max_ld, s);
-  prof_end(h, ev, 0);
-  D::combine(h->v.ptr, h->row_src.ptr, M.m_r, nullptr, nullptr, 0, out, dotx, partial, done, s);
+  D::gather_rows(x, h->row_src.ptr, M.m_r, h->xgp.ptr, s);
+  gemv_timed(h, h->Sinv.ptr, h->xgp.ptr, h->v.ptr);
+  if (M.n_gp > 0) D::coarse_project(h->Ht.ptr, M.n_gp, M.m_r, x, h->t.ptr, s);
+  D::combine(h->v.ptr, h->row_src.ptr, M.m_r, M.n_gp > 0 ? h->H.ptr : nullptr, h->t.ptr, M.n_gp, out, s);
+}
+
+// z = M_D^{-1} x = sum_k B_k S_rIrI^(k) B_k^T x  (D_s = I)
+void apply_M(ieti_handle* h, const double* x, double* out) {
+  namespace D = ieti::dev;
+  const auto& M = h->model;
+  hipStream_t s = h->stream;
+  D::gather_rows(x, h->row_src.ptr, M.m_r, h->xgr.ptr, s);
+  gemv_timed(h, h->S.ptr, h->xgr.ptr, h->v.ptr);
+  D::combine(h->v.ptr, h->row_src.ptr, M.m_r, nullptr, nullptr, 0, out, s);
+}
+
+// One PCG iteration of parity `par` as four launches; events around the
+// two GEMVs are recorded when `ev` is given (graph capture with profiling).
+void pcg_iteration(ieti_handle* h, int par, hipEvent_t* ev) {
+  namespace D = ieti::dev;
+  const auto& M = h->model;
+  hipStream_t s = h->stream;
+  const int64_t m_r = M.m_r;
+  int* done = h->flags.ptr + 1;
+  int* iters = h->flags.ptr + 2;
+  int* perr = h->flags.ptr + 3;
+  double* part_rr = h->part.ptr + h->nblk;
+  const double* H = M.n_gp > 0 ? h->H.ptr : nullptr;
+  if (ev) (void)hipEventRecord(ev[0], s);
+  if (ev) D::gemv(h->Sinv.ptr, h->gemv_task.ptr, h->ngemv, h->max_ld, h->xgp.ptr, h->v.ptr, h->part_g.ptr, done, s);
+  else gemv_timed(h, h->Sinv.ptr, h->xgp.ptr, h->v.ptr, done);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  D::pcg_F(h->v.ptr, h->row_src.ptr, m_r, H, h->part_t.ptr, M.n_gp, h->nblk, h->part_g.ptr, h->ngemv, h->p.ptr,
+           h->lam.ptr, h->r.ptr, h->xgr.ptr, part_rr, h->scal.ptr, par, done, perr, s);
+  if (ev) (void)hipEventRecord(ev[2], s);
+  if (ev) D::gemv(h->S.ptr, h->gemv_task.ptr, h->ngemv, h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, done, s);
+  else gemv_timed(h, h->S.ptr, h->xgr.ptr, h->v.ptr, done);
+  if (ev) (void)hipEventRecord(ev[3], s);
+  D::pcg_M(h->v.ptr, h->row_src.ptr, m_r, H, M.n_gp, h->part_g.ptr, h->ngemv, part_rr, h->nblk, h->p.ptr, h->z.ptr,
+           h->xgp.ptr, h->part_t.ptr, h->scal.ptr, par, done, iters, 0, s);
+}
+
+// Capture two PCG iterations (parities 0 and 1) as one graph.
+int capture_graph(ieti_handle* h) {
+  if (h->graph_exec) return IETI_OK;
+  HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  pcg_iteration(h, 0, nullptr);
+  pcg_iteration(h, 1, nullptr);
+  HIP_TRY(hipStreamEndCapture(h->stream, &h->graph));
+  HIP_TRY(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+  return IETI_OK;
 }
 
 // Forward solve with the factor over all augmented rows (full) or r rows only.
@@ -407,12 +476,11 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   HIP_TRY(hipEventRecord(h->ev0, s));
   int rc = compute_rhs(h);
   if (rc) return rc;
-  double* part_pq = h->part.ptr;
-  double* part_rr = h->part.ptr + h->nblk;
-  double* part_rz = h->part.ptr + 2 * h->nblk;
   int* done = h->flags.ptr + 1;
   int* iters = h->flags.ptr + 2;
-  int* perr = h->flags.ptr + 3;
+  double* part_rr = h->part.ptr + h->nblk;
+  // profiled runs use direct launches so every GEMV carries launch events
+  const bool use_graph = (!opts || opts->use_graph != 0) && !h->profiling;
   HIP_TRY(hipMemsetAsync(h->flags.ptr + 1, 0, 3 * sizeof(int), s));
   int it = 0;
   double rr = 0.0;
@@ -425,7 +493,7 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
     // lambda_0, r_0 = b - F lambda_0
     if (opts && opts->lambda0) {
       HIP_TRY(hipMemcpyAsync(h->lam.ptr, opts->lambda0, m_r * sizeof(double), hipMemcpyHostToDevice, s));
-      apply_F(h, h->lam.ptr, h->q.ptr, nullptr, nullptr, nullptr);
+      apply_F(h, h->lam.ptr, h->q.ptr);
       ++applies;
       D::axpby(h->b.ptr, h->q.ptr, h->r.ptr, 1.0, -1.0, m_r, s);
     } else {
@@ -434,20 +502,27 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
     }
     rr = host_dot(h, h->r.ptr, h->r.ptr, m_r);
     if (rr > rtol * rtol * bb && bb > 0.0) {
-      apply_M(h, h->r.ptr, h->z.ptr, nullptr, nullptr, nullptr);
-      D::vec_copy(h->z.ptr, h->p.ptr, m_r, s);
-      const double rz = host_dot(h, h->r.ptr, h->z.ptr, m_r);
-      const double sc[8] = {rz, 0.0, 0.0, 0.0, rtol * rtol * bb, rr, 0.0, 0.0};
+      const double sc[8] = {0.0, 0.0, 0.0, 0.0, rtol * rtol * bb, rr, 0.0, 0.0};
       HIP_TRY(hipMemcpyAsync(h->scal.ptr, sc, sizeof(sc), hipMemcpyHostToDevice, s));
-      for (it = 0; it < maxit;) {
-        const int par = it & 1;
-        apply_F(h, h->p.ptr, h->q.ptr, h->p.ptr, part_pq, done);
-        D::pcg_update_lambda(h->lam.ptr, h->r.ptr, h->p.ptr, h->q.ptr, m_r, part_pq, h->nblk, h->scal.ptr, par,
-                             part_rr, done, perr, s);
-        apply_M(h, h->r.ptr, h->z.ptr, h->r.ptr, part_rz, done);
-        D::pcg_update_p(h->p.ptr, h->z.ptr, m_r, part_rz, part_rr, h->nblk, h->scal.ptr, par, done, iters, maxit, s);
-        ++it;
-        if (it % every == 0 || it >= maxit) {
+      // z_0 = M r_0, p_0 = z_0, rz_0, partials of H^T p_0
+      D::gather_rows(h->r.ptr, h->row_src.ptr, m_r, h->xgr.ptr, s);
+      D::gemv(h->S.ptr, h->gemv_task.ptr, h->ngemv, h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, s);
+      D::pcg_M(h->v.ptr, h->row_src.ptr, m_r, M.n_gp > 0 ? h->H.ptr : nullptr, M.n_gp, h->part_g.ptr, h->ngemv,
+               part_rr, h->nblk, h->p.ptr, h->z.ptr, h->xgp.ptr, h->part_t.ptr, h->scal.ptr, 0, done, iters, 1, s);
+      if (use_graph) {
+        int rc2 = capture_graph(h);
+        if (rc2) return rc2;
+      }
+      const int every2 = std::max(2, every + (every & 1));
+      for (it = 0; it < maxit; it += 2) {
+        if (use_graph) {
+          HIP_TRY(hipGraphLaunch(h->graph_exec, s));
+        } else {
+          for (int par = 0; par < 2; ++par) {
+            pcg_iteration(h, par, nullptr);
+          }
+        }
+        if ((it + 2) % every2 == 0 || it + 2 >= maxit) {
           HIP_TRY(hipMemcpyAsync(h->flags_h, h->flags.ptr, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
           HIP_TRY(hipStreamSynchronize(s));
           if (h->flags_h[1]) break;
@@ -470,7 +545,7 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   // ---- recovery: p = S_c^{-1}(d~ + G^T lambda), a_r = K_rr^{-1}(j_r - K_rp C p - B^T lambda)
   if (M.n_gp > 0) {
     // u = L_c^{-1} d~ + H^T lambda, p = L_c^{-T} u  (H = G L_c^{-T}, S_c = L_c L_c^T)
-    D::coarse_project(h->Ht.ptr, M.n_gp, m_r, h->lam.ptr, h->t.ptr, nullptr, s);
+    D::coarse_project(h->Ht.ptr, M.n_gp, m_r, h->lam.ptr, h->t.ptr, s);
     D::axpby(h->w.ptr, h->t.ptr, h->dtil.ptr, 1.0, 1.0, M.n_gp, s);
     D::tri_small(h->Spi_glob.ptr, M.n_gp, h->dtil.ptr, h->pglob.ptr, true, s);
   }
@@ -715,7 +790,7 @@ int ieti_apply_F(ieti_handle* h, const double* lambda, double* q) {
   const int64_t m_r = h->model.m_r;
   if (m_r == 0) return IETI_OK;
   HIP_TRY(hipMemcpyAsync(h->tmp.ptr, lambda, m_r * sizeof(double), hipMemcpyHostToDevice, h->stream));
-  apply_F(h, h->tmp.ptr, h->q.ptr, nullptr, nullptr, nullptr);
+  apply_F(h, h->tmp.ptr, h->q.ptr);
   int rc = check_launch();
   if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(q, h->q.ptr, m_r * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -729,7 +804,7 @@ int ieti_apply_M(ieti_handle* h, const double* r, double* z) {
   const int64_t m_r = h->model.m_r;
   if (m_r == 0) return IETI_OK;
   HIP_TRY(hipMemcpyAsync(h->tmp.ptr, r, m_r * sizeof(double), hipMemcpyHostToDevice, h->stream));
-  apply_M(h, h->tmp.ptr, h->z.ptr, nullptr, nullptr, nullptr);
+  apply_M(h, h->tmp.ptr, h->z.ptr);
   int rc = check_launch();
   if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(z, h->z.ptr, m_r * sizeof(double), hipMemcpyDeviceToHost, h->stream));

@@ -11,6 +11,7 @@
 // (Section 2.1, Eqs. intProb and DirPrec) as batched dense GEMVs over the
 // per-subdomain interface blocks with the signed Boolean gather fused in,
 // followed by a deterministic two-term combine per multiplier row.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -331,34 +332,48 @@ __global__ void k_tri_small(const double* L, int64_t n, const double* in, double
   }
 }
 
-// Batched GEMV over the dense interface blocks with the signed Boolean
-// gather fused in.  task: [matrix row start, first output slot, nrows,
-// ld (= padded n_I), first interface slot of the subdomain].
-constexpr int GEMV_ROWS_PER_WAVE = 4;
+// Signed Boolean gather of a multiplier vector into interface slots:
+// xg[slot(+1 side)] = x[row], xg[slot(-1 side)] = -x[row]  (xg = B^T x).
+__global__ void k_gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg) {
+  const int64_t row = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (row >= m_r) return;
+  const double v = x[row];
+  xg[row_src[2 * row]] = v;
+  xg[row_src[2 * row + 1]] = -v;
+}
 
-__global__ __launch_bounds__(256) void k_gemv_interface(const double* M, const int64_t* task, const int32_t* I_row,
-                                                        const double* I_sign, const double* x, double* v,
-                                                        const int* done) {
+// Batched dense GEMV over the per-subdomain interface blocks, v = M_k xg_k
+// for every interface slot, plus one partial of sum_slot xg * v per block.
+// task: [matrix row start, first slot of the rows, nrows, ld (= padded n_I),
+// first slot of the subdomain].  Each wave owns GEMV_RPW rows and streams
+// them with 16-byte loads; the gathered vector is read from L2/L1.
+constexpr int GEMV_RPW = 4;
+
+__global__ __launch_bounds__(256) void k_gemv(const double* M, const int64_t* task, const double* xg, double* v,
+                                              double* part, const int* done) {
   if (done && *done) return;
   extern __shared__ __align__(16) double xs[];
+  __shared__ double red[4];
   const int64_t* tk = task + 5 * blockIdx.x;
-  const int64_t mrow0 = tk[0], out0 = tk[1], nrows = tk[2], ld = tk[3], islot0 = tk[4];
-  for (int64_t j = threadIdx.x; j < ld; j += 256) {
-    const int32_t row = I_row[islot0 + j];
-    xs[j] = row >= 0 ? I_sign[islot0 + j] * x[row] : 0.0;
+  const int64_t mrow0 = tk[0], slot0 = tk[1], nrows = tk[2], ld = tk[3], xslot0 = tk[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t half = ld / 2;
+  {
+    const double2* src = reinterpret_cast<const double2*>(xg + xslot0);
+    double2* dst = reinterpret_cast<double2*>(xs);
+    for (int64_t j = threadIdx.x; j < half; j += 256) dst[j] = src[j];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const double2* xs2 = reinterpret_cast<const double2*>(xs);
-  for (int rb = w * GEMV_ROWS_PER_WAVE; rb < nrows; rb += 4 * GEMV_ROWS_PER_WAVE) {
-    double acc[GEMV_ROWS_PER_WAVE];
+  const double2* x2 = reinterpret_cast<const double2*>(xs);
+  double dsum = 0.0;
+  for (int64_t rb = w * GEMV_RPW; rb < nrows; rb += 4 * GEMV_RPW) {
+    double acc[GEMV_RPW];
 #pragma unroll
-    for (int r = 0; r < GEMV_ROWS_PER_WAVE; ++r) acc[r] = 0.0;
-    const int64_t half = ld / 2;
+    for (int r = 0; r < GEMV_RPW; ++r) acc[r] = 0.0;
     for (int64_t j = lane; j < half; j += 64) {
-      const double2 xv = xs2[j];
+      const double2 xv = x2[j];
 #pragma unroll
-      for (int r = 0; r < GEMV_ROWS_PER_WAVE; ++r) {
+      for (int r = 0; r < GEMV_RPW; ++r) {
         if (rb + r < nrows) {
           const double2 mv = reinterpret_cast<const double2*>(M + mrow0 + (rb + r) * ld)[j];
           acc[r] += mv.x * xv.x + mv.y * xv.y;
@@ -366,16 +381,62 @@ __global__ __launch_bounds__(256) void k_gemv_interface(const double* M, const i
       }
     }
 #pragma unroll
-    for (int r = 0; r < GEMV_ROWS_PER_WAVE; ++r) {
-      const double s = wave_sum(acc[r]);
-      if (lane == 0 && rb + r < nrows) v[out0 + rb + r] = s;
+    for (int r = 0; r < GEMV_RPW; ++r) {
+      const double sres = wave_sum(acc[r]);
+      if (lane == 0 && rb + r < nrows) {
+        v[slot0 + rb + r] = sres;
+        dsum += sres * xs[slot0 - xslot0 + rb + r];
+      }
     }
   }
+  if (lane == 0) red[w] = dsum;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Sum of n partials by one block with several loads in flight per thread;
+// the result (fixed summation order) is returned to every thread.
+__device__ inline double reduce_partials_fast(const double* part, int n, double* red) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 768 < n; i += 1024) {
+    a0 += part[i];
+    a1 += part[i + 256];
+    a2 += part[i + 512];
+    a3 += part[i + 768];
+  }
+  for (; i < n; i += 256) a0 += part[i];
+  return block_sum256((a0 + a1) + (a2 + a3), red);
+}
+
+// t[c] = sum_b part_t[b][c] into LDS, 64 columns per pass, four thread
+// groups splitting the blocks and combined in fixed order; returns the
+// calling thread's share of t.t.
+__device__ inline double coarse_from_partials(const double* part_t, int64_t n_gp, int nblk, double* tl,
+                                              double (*acc4)[64]) {
+  double tt = 0.0;
+  const int c0 = threadIdx.x & 63, q = threadIdx.x >> 6;
+  for (int64_t cb = 0; cb < n_gp; cb += 64) {
+    const int64_t c = cb + c0;
+    double sc = 0.0;
+    if (c < n_gp) {
+#pragma unroll 4
+      for (int b = q; b < nblk; b += 4) sc += part_t[int64_t(b) * n_gp + c];
+    }
+    acc4[q][c0] = sc;
+    __syncthreads();
+    if (q == 0 && c < n_gp) {
+      const double vv = (acc4[0][c0] + acc4[1][c0]) + (acc4[2][c0] + acc4[3][c0]);
+      tl[c] = vv;
+      tt += vv * vv;
+    }
+    __syncthreads();
+  }
+  return tt;
 }
 
 __global__ __launch_bounds__(256) void k_coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x,
-                                                        double* out, const int* done) {
-  if (done && *done) return;
+                                                        double* out) {
   __shared__ double red[4];
   const int64_t c = blockIdx.x;
   double s = 0.0;
@@ -384,36 +445,33 @@ __global__ __launch_bounds__(256) void k_coarse_project(const double* Ht, int64_
   if (threadIdx.x == 0) out[c] = s;
 }
 
-__global__ __launch_bounds__(256) void k_combine(const double* v, const int64_t* row_src, int64_t m_r, const double* H,
-                                                 const double* t, int64_t n_gp, double* q, const double* dotx,
-                                                 double* partial, const int* done) {
-  if (done && *done) return;
-  __shared__ double red[4];
-  const int64_t row = blockIdx.x * int64_t(256) + threadIdx.x;
-  double prod = 0.0;
-  if (row < m_r) {
-    double val = v[row_src[2 * row]] - v[row_src[2 * row + 1]];
-    if (H) {
-      double c = 0.0;
-      for (int64_t k = 0; k < n_gp; ++k) c += H[row * n_gp + k] * t[k];
-      val += c;
-    }
-    q[row] = val;
-    if (dotx) prod = dotx[row] * val;
-  }
-  if (partial) {
-    const double s = block_sum256(prod, red);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
-  }
+// q[row] = v[+1 slot] - v[-1 slot] + sum_c H[row][c] t[c]  (H may be null)
+__global__ void k_combine(const double* v, const int64_t* row_src, int64_t m_r, const double* H, const double* t,
+                          int64_t n_gp, double* q) {
+  const int64_t row = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (row >= m_r) return;
+  double val = v[row_src[2 * row]] - v[row_src[2 * row + 1]];
+  if (H)
+    for (int64_t c = 0; c < n_gp; ++c) val += H[row * n_gp + c] * t[c];
+  q[row] = val;
 }
 
-// scal layout: [0..1] rz (ping-pong), [2] alpha, [3] beta, [4] tol^2 * ||b||^2, [5] last ||r||^2
-__global__ __launch_bounds__(256) void k_pcg_update_lambda(double* lam, double* r, const double* p, const double* q,
-                                                           int64_t m_r, const double* part_pq, int nblk, double* scal,
-                                                           int par, double* part_rr, int* done, int* err) {
+// PCG, first half of an iteration (after v = Sinv_k B_k^T p):
+// t = H^T p from the block partials, p^T F p = sum xg.v + t.t,
+// alpha = rz / p^T F p, q = B v + H t, lambda += alpha p, r -= alpha q,
+// gather B^T r for the preconditioner, partials of ||r||^2.
+// scal: [0..1] rz (ping-pong by parity), [2] alpha, [3] beta, [4] tol^2, [5] ||r||^2
+__global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* row_src, int64_t m_r, const double* H,
+                                               const double* part_t, int64_t n_gp, int nblk, const double* part_g,
+                                               int ngemv, const double* p, double* lam, double* r, double* xg_r,
+                                               double* part_rr, double* scal, int par, int* done, int* err) {
   if (*done) return;
+  extern __shared__ double tl[];
   __shared__ double red[4];
-  const double pq = reduce_partials(part_pq, nblk, red);
+  __shared__ double acc4[4][64];
+  const double tt = coarse_from_partials(part_t, n_gp, nblk, tl, acc4);
+  const double tt_all = block_sum256(tt, red);
+  const double pq = reduce_partials_fast(part_g, ngemv, red) + tt_all;
   if (!(pq > 0.0)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       *err = 1;
@@ -422,42 +480,94 @@ __global__ __launch_bounds__(256) void k_pcg_update_lambda(double* lam, double* 
     return;
   }
   const double alpha = scal[par] / pq;
-  const int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
+  const int64_t row = blockIdx.x * int64_t(256) + threadIdx.x;
   double rr = 0.0;
-  if (i < m_r) {
-    lam[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    rr = ri * ri;
+  if (row < m_r) {
+    const int64_t s0 = row_src[2 * row], s1 = row_src[2 * row + 1];
+    double q = v[s0] - v[s1];
+    const double* Hr = H + row * n_gp;
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    int64_t c = 0;
+    for (; c + 3 < n_gp; c += 4) {
+      c0 += Hr[c] * tl[c];
+      c1 += Hr[c + 1] * tl[c + 1];
+      c2 += Hr[c + 2] * tl[c + 2];
+      c3 += Hr[c + 3] * tl[c + 3];
+    }
+    for (; c < n_gp; ++c) c0 += Hr[c] * tl[c];
+    q += (c0 + c1) + (c2 + c3);
+    lam[row] += alpha * p[row];
+    const double rn = r[row] - alpha * q;
+    r[row] = rn;
+    rr = rn * rn;
+    xg_r[s0] = rn;
+    xg_r[s1] = -rn;
   }
-  const double s = block_sum256(rr, red);
-  if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+  const double srr = block_sum256(rr, red);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = srr;
   if (blockIdx.x == 0 && threadIdx.x == 0) scal[2] = alpha;
 }
 
-__global__ __launch_bounds__(256) void k_pcg_update_p(double* p, const double* z, int64_t m_r, const double* part_rz,
-                                                      const double* part_rr, int nblk, double* scal, int par,
-                                                      int* done, int* iters, int maxit) {
+// PCG, second half (after w = S_k B_k^T r): convergence test on ||r||^2,
+// rz = sum xg_r.w, z = B w, beta = rz / rz_old, p = z + beta p, gather
+// B^T p for the next operator GEMV and the block partials of H^T p.
+// init = 1 starts the recurrence (beta = 0, no convergence test).
+__global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* row_src, int64_t m_r, const double* H,
+                                               int64_t n_gp, const double* part_g, int ngemv, const double* part_rr,
+                                               int nblk, double* p, double* z, double* xg_p, double* part_t,
+                                               double* scal, int par, int* done, int* iters, int init) {
   if (*done) return;
   __shared__ double red[4];
-  const double rz = reduce_partials(part_rz, nblk, red);
-  const double rr = reduce_partials(part_rr, nblk, red);
-  const int it = *iters + 1;
-  const bool conv = rr <= scal[4];
-  const bool cap = it >= maxit;
+  __shared__ double pl[256];
+  const double rz = reduce_partials_fast(part_g, ngemv, red);
+  if (!init) {
+    const double rr = reduce_partials_fast(part_rr, nblk, red);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *iters += 1;
+      scal[5] = rr;
+    }
+    if (rr <= scal[4]) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) *done = 1;
+      return;
+    }
+  }
+  const double beta = init ? 0.0 : rz / scal[par];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *iters = it;
-    scal[5] = rr;
-    scal[1 - par] = rz;
-    scal[3] = rz / scal[par];
+    scal[init ? 0 : 1 - par] = rz;
+    scal[3] = beta;
   }
-  if (conv || cap) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *done = conv ? 1 : 2;
-    return;
+  const int64_t base = blockIdx.x * int64_t(256);
+  const int64_t row = base + threadIdx.x;
+  double pv = 0.0;
+  if (row < m_r) {
+    const int64_t s0 = row_src[2 * row], s1 = row_src[2 * row + 1];
+    const double zz = w[s0] - w[s1];
+    z[row] = zz;
+    pv = zz + beta * p[row];
+    p[row] = pv;
+    xg_p[s0] = pv;
+    xg_p[s1] = -pv;
   }
-  const double beta = rz / scal[par];
-  const int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
-  if (i < m_r) p[i] = z[i] + beta * p[i];
+  pl[threadIdx.x] = pv;
+  __syncthreads();
+  // block partials of H^T p: 64 columns per pass, four row quarters per column
+  __shared__ double acc4[4][64];
+  const int64_t nrow = (m_r - base) < 256 ? (m_r - base) : 256;
+  const int c0 = threadIdx.x & 63, q = threadIdx.x >> 6;
+  for (int64_t cb = 0; cb < n_gp; cb += 64) {
+    const int64_t c = cb + c0;
+    double sc = 0.0;
+    if (c < n_gp) {
+      const int64_t i0 = 64 * q, i1 = (64 * q + 64) < nrow ? 64 * q + 64 : nrow;
+#pragma unroll 8
+      for (int64_t i = i0; i < i1; ++i) sc += H[(base + i) * n_gp + c] * pl[i];
+    }
+    acc4[q][c0] = sc;
+    __syncthreads();
+    if (q == 0 && c < n_gp)
+      part_t[blockIdx.x * n_gp + c] = (acc4[0][c0] + acc4[1][c0]) + (acc4[2][c0] + acc4[3][c0]);
+    __syncthreads();
+  }
 }
 
 __global__ void k_gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out) {
@@ -591,33 +701,41 @@ void tri_small(const double* L, int64_t n, const double* in, double* out, bool t
   if (n <= 0) return;
   hipLaunchKernelGGL(k_tri_small, dim3(1), dim3(64), 0, s, L, n, in, out, transposed ? 1 : 0);
 }
-void gemv_interface(const double* M, const int64_t* task, int64_t ntask, const int32_t* I_row, const double* I_sign,
-                    const double* x, double* v, const int* done, int64_t max_ld, hipStream_t s) {
-  if (ntask <= 0) return;
-  hipLaunchKernelGGL(k_gemv_interface, dim3(ntask), dim3(256), size_t(max_ld) * sizeof(double), s, M, task, I_row,
-                     I_sign, x, v, done);
+void gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg, hipStream_t s) {
+  if (m_r <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3((m_r + 255) / 256), dim3(256), 0, s, x, row_src, m_r, xg);
 }
-void coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x, double* out, const int* done,
-                    hipStream_t s) {
+void gemv(const double* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
+          double* part, const int* done, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  if (ntask <= 0) return;
+  const size_t lds = size_t(max_ld) * sizeof(double);
+  if (ev_start)
+    hipExtLaunchKernelGGL(k_gemv, dim3(ntask), dim3(256), lds, s, ev_start, ev_stop, 0, M, task, xg, v, part, done);
+  else
+    hipLaunchKernelGGL(k_gemv, dim3(ntask), dim3(256), lds, s, M, task, xg, v, part, done);
+}
+void coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x, double* out, hipStream_t s) {
   if (n_gp <= 0) return;
-  hipLaunchKernelGGL(k_coarse_project, dim3(n_gp), dim3(256), 0, s, Ht, n_gp, m_r, x, out, done);
+  hipLaunchKernelGGL(k_coarse_project, dim3(n_gp), dim3(256), 0, s, Ht, n_gp, m_r, x, out);
 }
 int combine_blocks(int64_t m_r) { return int((m_r + 255) / 256); }
 void combine(const double* v, const int64_t* row_src, int64_t m_r, const double* H, const double* t, int64_t n_gp,
-             double* q, const double* dotx, double* partial, const int* done, hipStream_t s) {
+             double* q, hipStream_t s) {
   if (m_r <= 0) return;
-  hipLaunchKernelGGL(k_combine, dim3(combine_blocks(m_r)), dim3(256), 0, s, v, row_src, m_r, H, t, n_gp, q, dotx,
-                     partial, done);
+  hipLaunchKernelGGL(k_combine, dim3(combine_blocks(m_r)), dim3(256), 0, s, v, row_src, m_r, H, t, n_gp, q);
 }
-void pcg_update_lambda(double* lam, double* r, const double* p, const double* q, int64_t m_r, const double* part_pq,
-                       int nblk, double* scal, int par, double* part_rr, int* done, int* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_update_lambda, dim3(combine_blocks(m_r)), dim3(256), 0, s, lam, r, p, q, m_r, part_pq,
-                     nblk, scal, par, part_rr, done, err);
+void pcg_F(const double* v, const int64_t* row_src, int64_t m_r, const double* H, const double* part_t,
+           int64_t n_gp, int nblk, const double* part_g, int ngemv, const double* p, double* lam, double* r,
+           double* xg_r, double* part_rr, double* scal, int par, int* done, int* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_F, dim3(combine_blocks(m_r)), dim3(256), size_t(n_gp > 0 ? n_gp : 1) * sizeof(double), s,
+                     v, row_src, m_r, H, part_t, n_gp, nblk, part_g, ngemv, p, lam, r, xg_r, part_rr, scal, par, done,
+                     err);
 }
-void pcg_update_p(double* p, const double* z, int64_t m_r, const double* part_rz, const double* part_rr, int nblk,
-                  double* scal, int par, int* done, int* iters, int maxit, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_update_p, dim3(combine_blocks(m_r)), dim3(256), 0, s, p, z, m_r, part_rz, part_rr, nblk,
-                     scal, par, done, iters, maxit);
+void pcg_M(const double* w, const int64_t* row_src, int64_t m_r, const double* H, int64_t n_gp, const double* part_g,
+           int ngemv, const double* part_rr, int nblk, double* p, double* z, double* xg_p, double* part_t,
+           double* scal, int par, int* done, int* iters, int init, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_M, dim3(combine_blocks(m_r)), dim3(256), 0, s, w, row_src, m_r, H, n_gp, part_g, ngemv,
+                     part_rr, nblk, p, z, xg_p, part_t, scal, par, done, iters, init);
 }
 void gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out, hipStream_t s) {
   if (n <= 0) return;

@@ -36,26 +36,27 @@ void chol_small(double* A, int64_t n, int* err, hipStream_t s);
 void solve_rows_LT(const double* L, int64_t n, const double* G, int64_t m, double* H, double* Ht, hipStream_t s);
 void tri_small(const double* L, int64_t n, const double* in, double* out, bool transposed, hipStream_t s);
 
-// ---- interface operators
-// v[slot] = sum_j M_k[i][j] * sign_j * x[row_j] for every interface slot
+// ---- interface operators and PCG (FP64 recurrences)
+// xg[slot(+1)] = x[row], xg[slot(-1)] = -x[row]
+void gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg, hipStream_t s);
+// v[slot] = (M_k xg_k)[slot] for every interface slot; part[block] = sum xg.v over the block's rows.
+// task [matrix row start, first slot, nrows, ld, first slot of the subdomain]; ev_* may be null.
 constexpr int GEMV_ROWS = 16;  // matrix rows per workgroup (4 waves x 4 rows)
-void gemv_interface(const double* M, const int64_t* task, int64_t ntask, const int32_t* I_row, const double* I_sign,
-                    const double* x, double* v, const int* done, int64_t max_ld, hipStream_t s);
+void gemv(const double* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
+          double* part, const int* done, hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // out[c] = sum_row Ht[c][row] * x[row]
-void coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x, double* out, const int* done,
-                    hipStream_t s);
-// q[row] = v[src0] - v[src1] + sum_c H[row][c] t[c]  (H may be null); partial dot(x, q) per block
+void coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x, double* out, hipStream_t s);
+// q[row] = v[src0] - v[src1] + sum_c H[row][c] t[c]  (H may be null)
 void combine(const double* v, const int64_t* row_src, int64_t m_r, const double* H, const double* t, int64_t n_gp,
-             double* q, const double* dotx, double* partial, const int* done, hipStream_t s);
+             double* q, hipStream_t s);
 int combine_blocks(int64_t m_r);
-
-// ---- PCG recurrences (FP64)
-// scal: [0..1] rz (ping-pong by iteration parity par), [2] alpha, [3] beta,
-// [4] rtol^2 ||b||^2, [5] last ||r||^2
-void pcg_update_lambda(double* lam, double* r, const double* p, const double* q, int64_t m_r, const double* part_pq,
-                       int nblk, double* scal, int par, double* part_rr, int* done, int* err, hipStream_t s);
-void pcg_update_p(double* p, const double* z, int64_t m_r, const double* part_rz, const double* part_rr, int nblk,
-                  double* scal, int par, int* done, int* iters, int maxit, hipStream_t s);
+// scal: [0..1] rz (ping-pong by iteration parity par), [2] alpha, [3] beta, [4] rtol^2 ||b||^2, [5] ||r||^2
+void pcg_F(const double* v, const int64_t* row_src, int64_t m_r, const double* H, const double* part_t,
+           int64_t n_gp, int nblk, const double* part_g, int ngemv, const double* p, double* lam, double* r,
+           double* xg_r, double* part_rr, double* scal, int par, int* done, int* err, hipStream_t s);
+void pcg_M(const double* w, const int64_t* row_src, int64_t m_r, const double* H, int64_t n_gp, const double* part_g,
+           int ngemv, const double* part_rr, int nblk, double* p, double* z, double* xg_p, double* part_t,
+           double* scal, int par, int* done, int* iters, int init, hipStream_t s);
 
 // ---- recovery / rhs helpers
 void gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out, hipStream_t s);

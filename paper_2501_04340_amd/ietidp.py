@@ -245,19 +245,20 @@ class Solver:
         o.hip_stream = stream
         _check(self.lib, self.lib.ieti_factor(self.h, C.byref(o)))
 
-    def _solve_opts(self, rtol, maxit, lambda0, check_every):
+    def _solve_opts(self, rtol, maxit, lambda0, check_every, use_graph=True):
         o = SolveOpts()
         o.rtol = rtol
         o.maxit = maxit
         o.check_every = check_every
+        o.use_graph = 1 if use_graph else 0
         self._lam0 = None
         if lambda0 is not None:
             self._lam0 = np.ascontiguousarray(lambda0, dtype=np.float64)
             o.lambda0 = _ptr(self._lam0, C.c_double)
         return o
 
-    def solve(self, rtol=1e-8, maxit=1000, lambda0=None, check_every=8, raise_on_nonconv=True):
-        o = self._solve_opts(rtol, maxit, lambda0, check_every)
+    def solve(self, rtol=1e-8, maxit=1000, lambda0=None, check_every=8, raise_on_nonconv=True, use_graph=True):
+        o = self._solve_opts(rtol, maxit, lambda0, check_every, use_graph)
         a = np.zeros(self.n_edges)
         st = Stats()
         rc = self.lib.ieti_solve(self.h, C.byref(o), _ptr(a, C.c_double), C.byref(st))

@@ -131,3 +131,13 @@ def test_device_output_matches_host_output(runs):
     torch.cuda.synchronize()
     S.solve_device(out.data_ptr(), rtol=1e-10)
     assert np.array_equal(out.cpu().numpy(), a)
+
+
+def test_graph_replay_matches_direct_launches_bitwise(runs):
+    """The PCG loop replayed from a captured hipGraph equals direct launches."""
+    prob, S, O = _get(runs, "cube64_small")
+    a1, st1 = S.solve(rtol=1e-10, use_graph=True)
+    a2, st2 = S.solve(rtol=1e-10, use_graph=False)
+    a3, st3 = S.solve(rtol=1e-10, use_graph=True)
+    assert st1["iters"] == st2["iters"] == st3["iters"]
+    assert np.array_equal(a1, a2) and np.array_equal(a1, a3)
