@@ -82,9 +82,12 @@ struct ieti_handle {
   DBuf<double> krp_val;
   DBuf<double> lam, r, z, p, q, v, b, e, dtil, w, t, pglob, part, scal, aout, tmp;
   DBuf<double> xgp, xgr, part_g, part_t;  // gathered B^T p and B^T r, GEMV and coarse partials
+  DBuf<double> lam_acc, rtrue;            // outer multipliers and FP64 residual (mixed precision)
+  DBuf<float> S32, Sinv32;                // FP32 copies of S_rIrI and (K_rr^{-1})_II (mixed precision)
+  bool mixed = false;
   int ngemv = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr, graph32 = nullptr;
+  hipGraphExec_t graph_exec = nullptr, graph_exec32 = nullptr;
 
   DBuf<int> flags;  // [0] err (factor), [1] done, [2] iters, [3] pcg err, [4] coarse err
   int* flags_h = nullptr;
@@ -102,7 +105,7 @@ struct ieti_handle {
   ~ieti_handle() {
     DBuf<double>* ds[] = {&pool, &inv, &scatter_val, &S, &Sinv, &Phi, &SPi, &Spi_glob, &G, &H, &Ht, &I_sign, &b_aug0, &y,
                           &krp_val, &lam, &r, &z, &p, &q, &v, &b, &e, &dtil, &w, &t, &pglob, &part, &scal, &aout,
-                          &tmp, &xgp, &xgr, &part_g, &part_t};
+                          &tmp, &xgp, &xgr, &part_g, &part_t, &lam_acc, &rtrue};
     for (auto* d : ds) d->release();
     DBuf<int64_t>* is[] = {&scatter_dst, &potrf, &trsm, &upd, &upd_pair, &copyS, &xsinv, &xphi, &xspi, &fdiag,
                            &ffull, &ffull_pair, &fr, &fr_pair, &bdiag, &bupd, &bupd_pair, &spi_ptr, &spi_src, &row_src, &I_aug, &A_aug, &slot_phi_row, &dsrc_ptr,
@@ -120,6 +123,10 @@ struct ieti_handle {
     if (ev2) (void)hipEventDestroy(ev2);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (graph_exec32) (void)hipGraphExecDestroy(graph_exec32);
+    if (graph32) (void)hipGraphDestroy(graph32);
+    S32.release();
+    Sinv32.release();
     if (own_stream) (void)hipStreamDestroy(own_stream);
   }
 };
@@ -269,6 +276,18 @@ int upload(ieti_handle* h) {
   HIP_TRY(hipMemset(h->xgr.ptr, 0, h->xgr.n * sizeof(double)));
   if ((rc = dalloc(h->part_g, std::max(h->ngemv, 1)))) return rc;
   if ((rc = dalloc(h->part_t, std::max<int64_t>(int64_t(h->nblk) * n_gp, 1)))) return rc;
+  if ((rc = dalloc(h->lam_acc, mm))) return rc;
+  if ((rc = dalloc(h->rtrue, mm))) return rc;
+  for (hipGraphExec_t* g : {&h->graph_exec, &h->graph_exec32})
+    if (*g) {
+      (void)hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
+  for (hipGraph_t* g : {&h->graph, &h->graph32})
+    if (*g) {
+      (void)hipGraphDestroy(*g);
+      *g = nullptr;
+    }
   if (h->graph_exec) {
     (void)hipGraphExecDestroy(h->graph_exec);
     h->graph_exec = nullptr;
@@ -333,7 +352,8 @@ int check_launch() {
 }
 
 // Interface GEMV over all subdomains, timed with launch events when profiling.
-void gemv_timed(ieti_handle* h, const double* M, const double* xg, double* v, const int* done = nullptr) {
+template <typename MT>
+void gemv_timed(ieti_handle* h, const MT* M, const double* xg, double* v, const int* done = nullptr) {
   hipEvent_t a = nullptr, b = nullptr;
   size_t slot = SIZE_MAX;
   if (h->profiling) {
@@ -367,9 +387,10 @@ void apply_M(ieti_handle* h, const double* x, double* out) {
   D::combine(h->v.ptr, h->row_src.ptr, M.m_r, nullptr, nullptr, 0, out, s);
 }
 
-// One PCG iteration of parity `par` as four launches; events around the
-// two GEMVs are recorded when `ev` is given (graph capture with profiling).
-void pcg_iteration(ieti_handle* h, int par, hipEvent_t* ev) {
+// One PCG iteration of parity `par` as four launches, with the interface
+// blocks stored as MT (FP64, or FP32 in the inner solves of the mixed path).
+template <typename MT>
+void pcg_iteration(ieti_handle* h, int par, const MT* Sinv, const MT* S) {
   namespace D = ieti::dev;
   const auto& M = h->model;
   hipStream_t s = h->stream;
@@ -379,28 +400,29 @@ void pcg_iteration(ieti_handle* h, int par, hipEvent_t* ev) {
   int* perr = h->flags.ptr + 3;
   double* part_rr = h->part.ptr + h->nblk;
   const double* H = M.n_gp > 0 ? h->H.ptr : nullptr;
-  if (ev) (void)hipEventRecord(ev[0], s);
-  if (ev) D::gemv(h->Sinv.ptr, h->gemv_task.ptr, h->ngemv, h->max_ld, h->xgp.ptr, h->v.ptr, h->part_g.ptr, done, s);
-  else gemv_timed(h, h->Sinv.ptr, h->xgp.ptr, h->v.ptr, done);
-  if (ev) (void)hipEventRecord(ev[1], s);
+  gemv_timed(h, Sinv, h->xgp.ptr, h->v.ptr, done);
   D::pcg_F(h->v.ptr, h->row_src.ptr, m_r, H, h->part_t.ptr, M.n_gp, h->nblk, h->part_g.ptr, h->ngemv, h->p.ptr,
            h->lam.ptr, h->r.ptr, h->xgr.ptr, part_rr, h->scal.ptr, par, done, perr, s);
-  if (ev) (void)hipEventRecord(ev[2], s);
-  if (ev) D::gemv(h->S.ptr, h->gemv_task.ptr, h->ngemv, h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, done, s);
-  else gemv_timed(h, h->S.ptr, h->xgr.ptr, h->v.ptr, done);
-  if (ev) (void)hipEventRecord(ev[3], s);
+  gemv_timed(h, S, h->xgr.ptr, h->v.ptr, done);
   D::pcg_M(h->v.ptr, h->row_src.ptr, m_r, H, M.n_gp, h->part_g.ptr, h->ngemv, part_rr, h->nblk, h->p.ptr, h->z.ptr,
            h->xgp.ptr, h->part_t.ptr, h->scal.ptr, par, done, iters, 0, s);
 }
 
-// Capture two PCG iterations (parities 0 and 1) as one graph.
-int capture_graph(ieti_handle* h) {
-  if (h->graph_exec) return IETI_OK;
+void pcg_iteration_prec(ieti_handle* h, int par, bool fp32) {
+  if (fp32) pcg_iteration<float>(h, par, h->Sinv32.ptr, h->S32.ptr);
+  else pcg_iteration<double>(h, par, h->Sinv.ptr, h->S.ptr);
+}
+
+// Capture two PCG iterations (parities 0 and 1) as one graph per precision.
+int capture_graph(ieti_handle* h, bool fp32) {
+  hipGraph_t& g = fp32 ? h->graph32 : h->graph;
+  hipGraphExec_t& ge = fp32 ? h->graph_exec32 : h->graph_exec;
+  if (ge) return IETI_OK;
   HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-  pcg_iteration(h, 0, nullptr);
-  pcg_iteration(h, 1, nullptr);
-  HIP_TRY(hipStreamEndCapture(h->stream, &h->graph));
-  HIP_TRY(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+  pcg_iteration_prec(h, 0, fp32);
+  pcg_iteration_prec(h, 1, fp32);
+  HIP_TRY(hipStreamEndCapture(h->stream, &g));
+  HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
   return IETI_OK;
 }
 
@@ -462,6 +484,61 @@ double host_dot(ieti_handle* h, const double* x, const double* y, int64_t n) {
   return s;
 }
 
+// PCG on F x = r_0 from the state prepared by the caller (x in h->lam, r_0 in
+// h->r with ||r_0||^2 = rr0), until ||r||^2 <= tol2 or maxit iterations.
+int run_pcg(ieti_handle* h, double tol2, double rr0, int maxit, int every, bool fp32, bool use_graph, int* iters_out,
+            double* rr_out, int* status) {
+  namespace D = ieti::dev;
+  const auto& M = h->model;
+  hipStream_t s = h->stream;
+  const int64_t m_r = M.m_r;
+  int* done = h->flags.ptr + 1;
+  int* iters = h->flags.ptr + 2;
+  double* part_rr = h->part.ptr + h->nblk;
+  *iters_out = 0;
+  *rr_out = rr0;
+  *status = IETI_OK;
+  if (rr0 <= tol2) return IETI_OK;
+  HIP_TRY(hipMemsetAsync(h->flags.ptr + 1, 0, 3 * sizeof(int), s));
+  const double sc[8] = {0.0, 0.0, 0.0, 0.0, tol2, rr0, 0.0, 0.0};
+  HIP_TRY(hipMemcpyAsync(h->scal.ptr, sc, sizeof(sc), hipMemcpyHostToDevice, s));
+  // z_0 = M r_0, p_0 = z_0, rz_0, partials of H^T p_0
+  D::gather_rows(h->r.ptr, h->row_src.ptr, m_r, h->xgr.ptr, s);
+  if (fp32) D::gemv(h->S32.ptr, h->gemv_task.ptr, h->ngemv, h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, s);
+  else D::gemv(h->S.ptr, h->gemv_task.ptr, h->ngemv, h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, s);
+  D::pcg_M(h->v.ptr, h->row_src.ptr, m_r, M.n_gp > 0 ? h->H.ptr : nullptr, M.n_gp, h->part_g.ptr, h->ngemv, part_rr,
+           h->nblk, h->p.ptr, h->z.ptr, h->xgp.ptr, h->part_t.ptr, h->scal.ptr, 0, done, iters, 1, s);
+  if (use_graph) {
+    int rc = capture_graph(h, fp32);
+    if (rc) return rc;
+  }
+  const int every2 = std::max(2, every + (every & 1));
+  for (int it = 0; it < maxit; it += 2) {
+    if (use_graph) {
+      HIP_TRY(hipGraphLaunch(fp32 ? h->graph_exec32 : h->graph_exec, s));
+    } else {
+      pcg_iteration_prec(h, 0, fp32);
+      pcg_iteration_prec(h, 1, fp32);
+    }
+    if ((it + 2) % every2 == 0 || it + 2 >= maxit) {
+      HIP_TRY(hipMemcpyAsync(h->flags_h, h->flags.ptr, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (h->flags_h[1]) break;
+    }
+  }
+  int rc = check_launch();
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(h->flags_h, h->flags.ptr, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  double sc_h[8];
+  HIP_TRY(hipMemcpyAsync(sc_h, h->scal.ptr, sizeof(sc_h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *iters_out = h->flags_h[2];
+  *rr_out = sc_h[5];
+  if (h->flags_h[3]) return fail(IETI_ERR_BREAKDOWN, "PCG breakdown: p^T F p <= 0");
+  if (h->flags_h[1] != 1) *status = IETI_ERR_NOT_CONVERGED;
+  return IETI_OK;
+}
+
 int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, double* a_dev, ieti_stats* st) {
   namespace D = ieti::dev;
   if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
@@ -476,13 +553,9 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   HIP_TRY(hipEventRecord(h->ev0, s));
   int rc = compute_rhs(h);
   if (rc) return rc;
-  int* done = h->flags.ptr + 1;
-  int* iters = h->flags.ptr + 2;
-  double* part_rr = h->part.ptr + h->nblk;
   // profiled runs use direct launches so every GEMV carries launch events
   const bool use_graph = (!opts || opts->use_graph != 0) && !h->profiling;
-  HIP_TRY(hipMemsetAsync(h->flags.ptr + 1, 0, 3 * sizeof(int), s));
-  int it = 0;
+  int it = 0, outer = 0;
   double rr = 0.0;
   const double bb = host_dot(h, h->b.ptr, h->b.ptr, m_r);
   h->bnorm = std::sqrt(bb);
@@ -490,55 +563,55 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   int status = IETI_OK;
   int applies = 0;
   if (m_r > 0) {
-    // lambda_0, r_0 = b - F lambda_0
-    if (opts && opts->lambda0) {
-      HIP_TRY(hipMemcpyAsync(h->lam.ptr, opts->lambda0, m_r * sizeof(double), hipMemcpyHostToDevice, s));
-      apply_F(h, h->lam.ptr, h->q.ptr);
-      ++applies;
-      D::axpby(h->b.ptr, h->q.ptr, h->r.ptr, 1.0, -1.0, m_r, s);
-    } else {
-      D::fill(h->lam.ptr, m_r, 0.0, s);
-      D::vec_copy(h->b.ptr, h->r.ptr, m_r, s);
-    }
-    rr = host_dot(h, h->r.ptr, h->r.ptr, m_r);
-    if (rr > rtol * rtol * bb && bb > 0.0) {
-      const double sc[8] = {0.0, 0.0, 0.0, 0.0, rtol * rtol * bb, rr, 0.0, 0.0};
-      HIP_TRY(hipMemcpyAsync(h->scal.ptr, sc, sizeof(sc), hipMemcpyHostToDevice, s));
-      // z_0 = M r_0, p_0 = z_0, rz_0, partials of H^T p_0
-      D::gather_rows(h->r.ptr, h->row_src.ptr, m_r, h->xgr.ptr, s);
-      D::gemv(h->S.ptr, h->gemv_task.ptr, h->ngemv, h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, s);
-      D::pcg_M(h->v.ptr, h->row_src.ptr, m_r, M.n_gp > 0 ? h->H.ptr : nullptr, M.n_gp, h->part_g.ptr, h->ngemv,
-               part_rr, h->nblk, h->p.ptr, h->z.ptr, h->xgp.ptr, h->part_t.ptr, h->scal.ptr, 0, done, iters, 1, s);
-      if (use_graph) {
-        int rc2 = capture_graph(h);
-        if (rc2) return rc2;
+    if (!h->mixed) {
+      // plain FP64: PCG on F lambda = b from lambda_0
+      if (opts && opts->lambda0) {
+        HIP_TRY(hipMemcpyAsync(h->lam.ptr, opts->lambda0, m_r * sizeof(double), hipMemcpyHostToDevice, s));
+        apply_F(h, h->lam.ptr, h->q.ptr);
+        ++applies;
+        D::axpby(h->b.ptr, h->q.ptr, h->r.ptr, 1.0, -1.0, m_r, s);
+      } else {
+        D::fill(h->lam.ptr, m_r, 0.0, s);
+        D::vec_copy(h->b.ptr, h->r.ptr, m_r, s);
       }
-      const int every2 = std::max(2, every + (every & 1));
-      for (it = 0; it < maxit; it += 2) {
-        if (use_graph) {
-          HIP_TRY(hipGraphLaunch(h->graph_exec, s));
-        } else {
-          for (int par = 0; par < 2; ++par) {
-            pcg_iteration(h, par, nullptr);
-          }
-        }
-        if ((it + 2) % every2 == 0 || it + 2 >= maxit) {
-          HIP_TRY(hipMemcpyAsync(h->flags_h, h->flags.ptr, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-          HIP_TRY(hipStreamSynchronize(s));
-          if (h->flags_h[1]) break;
-        }
-      }
-      rc = check_launch();
+      rr = host_dot(h, h->r.ptr, h->r.ptr, m_r);
+      int n = 0;
+      rc = run_pcg(h, rtol * rtol * bb, rr, maxit, every, false, use_graph, &n, &rr, &status);
       if (rc) return rc;
-      HIP_TRY(hipMemcpyAsync(h->flags_h, h->flags.ptr, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-      double sc_h[8];
-      HIP_TRY(hipMemcpyAsync(sc_h, h->scal.ptr, sizeof(sc_h), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      it = h->flags_h[2];
-      applies += it;
-      rr = sc_h[5];
-      if (h->flags_h[3]) return fail(IETI_ERR_BREAKDOWN, "PCG breakdown: p^T F p <= 0");
-      if (h->flags_h[1] != 1) status = IETI_ERR_NOT_CONVERGED;
+      it = n;
+      applies += n;
+    } else {
+      // mixed: outer refinement on the FP64 residual r = b - F lambda, inner PCG
+      // with FP32-stored interface blocks on F d = r, lambda += d
+      if (opts && opts->lambda0)
+        HIP_TRY(hipMemcpyAsync(h->lam_acc.ptr, opts->lambda0, m_r * sizeof(double), hipMemcpyHostToDevice, s));
+      else
+        D::fill(h->lam_acc.ptr, m_r, 0.0, s);
+      const int max_outer = 20;
+      status = IETI_ERR_NOT_CONVERGED;
+      for (outer = 0; outer < max_outer && it < maxit; ++outer) {
+        apply_F(h, h->lam_acc.ptr, h->q.ptr);
+        ++applies;
+        D::axpby(h->b.ptr, h->q.ptr, h->rtrue.ptr, 1.0, -1.0, m_r, s);
+        rr = host_dot(h, h->rtrue.ptr, h->rtrue.ptr, m_r);
+        if (rr <= rtol * rtol * bb || bb == 0.0) {
+          status = IETI_OK;
+          break;
+        }
+        // inner tolerance: a fixed factor below the current true residual,
+        // never tighter than what the final step needs
+        const double inner_rel = std::max(1e-4, 0.5 * rtol * std::sqrt(bb / rr));
+        D::fill(h->lam.ptr, m_r, 0.0, s);
+        D::vec_copy(h->rtrue.ptr, h->r.ptr, m_r, s);
+        int n = 0, st_in = IETI_OK;
+        double rr_in = rr;
+        rc = run_pcg(h, inner_rel * inner_rel * rr, rr, maxit - it, every, true, use_graph, &n, &rr_in, &st_in);
+        if (rc) return rc;
+        it += n;
+        applies += n;
+        D::axpby(h->lam_acc.ptr, h->lam.ptr, h->lam_acc.ptr, 1.0, 1.0, m_r, s);
+      }
+      D::vec_copy(h->lam_acc.ptr, h->lam.ptr, m_r, s);
     }
   }
   HIP_TRY(hipEventRecord(h->ev2, s));
@@ -579,7 +652,7 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
     st->n_primal = M.n_gp;
     st->n_sub = M.n_sub;
     st->iters = it;
-    st->outer_iters = 0;
+    st->outer_iters = outer;
     st->status = status;
     st->f_applies = applies;
     st->rel_residual = h->bnorm > 0 ? std::sqrt(rr) / h->bnorm : 0.0;
@@ -655,7 +728,8 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
   const int T = (opts && opts->tile) ? opts->tile : D::TILE;
   if (T != D::TILE) return fail(IETI_ERR_INVALID_ARG, "only tile size 64 is built");
-  if (opts && opts->precision != IETI_PREC_FP64) return fail(IETI_ERR_INVALID_ARG, "only FP64 factors are built");
+  if (opts && opts->precision != IETI_PREC_FP64 && opts->precision != IETI_PREC_MIXED)
+    return fail(IETI_ERR_INVALID_ARG, "unknown precision");
   int rc = build_plan_if_needed(h, T, opts ? opts->ordering : 0);
   if (rc) return rc;
   rc = upload(h);
@@ -693,6 +767,16 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
     D::build_G(h->Phi.ptr, h->row_src.ptr, h->slot_phi_row.ptr, h->I_sub.ptr, h->glob2loc.ptr, M.m_r, M.n_gp, h->G.ptr,
                s);
     D::solve_rows_LT(h->Spi_glob.ptr, M.n_gp, h->G.ptr, M.m_r, h->H.ptr, h->Ht.ptr, s);
+  }
+  // mixed precision: FP32 copies of the interface blocks for the inner PCG
+  h->mixed = opts && opts->precision == IETI_PREC_MIXED;
+  if (h->mixed) {
+    if (!h->S32.ptr) {
+      if ((rc = dalloc(h->S32, P.S_elems))) return rc;
+      if ((rc = dalloc(h->Sinv32, P.S_elems))) return rc;
+    }
+    D::to_float(h->S.ptr, h->S32.ptr, P.S_elems, s);
+    D::to_float(h->Sinv.ptr, h->Sinv32.ptr, P.S_elems, s);
   }
   HIP_TRY(hipEventRecord(h->ev1, s));
   rc = check_launch();

@@ -349,34 +349,54 @@ __global__ void k_gather_rows(const double* x, const int64_t* row_src, int64_t m
 // them with 16-byte loads; the gathered vector is read from L2/L1.
 constexpr int GEMV_RPW = 4;
 
-__global__ __launch_bounds__(256) void k_gemv(const double* M, const int64_t* task, const double* xg, double* v,
+// 16-byte vectors of stored matrix entries (FP64: 2 entries, FP32: 4)
+template <typename MT>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  using T = double2;
+  static constexpr int N = 2;
+  __device__ static inline double dot(const T& m, const double* x) { return m.x * x[0] + m.y * x[1]; }
+};
+template <>
+struct Vec16<float> {
+  using T = float4;
+  static constexpr int N = 4;
+  __device__ static inline double dot(const T& m, const double* x) {
+    return (double(m.x) * x[0] + double(m.y) * x[1]) + (double(m.z) * x[2] + double(m.w) * x[3]);
+  }
+};
+
+// Matrix entries stored as MT (double or float), vector and accumulation in FP64.
+template <typename MT>
+__global__ __launch_bounds__(256) void k_gemv(const MT* M, const int64_t* task, const double* xg, double* v,
                                               double* part, const int* done) {
   if (done && *done) return;
+  using V = Vec16<MT>;
   extern __shared__ __align__(16) double xs[];
   __shared__ double red[4];
   const int64_t* tk = task + 5 * blockIdx.x;
   const int64_t mrow0 = tk[0], slot0 = tk[1], nrows = tk[2], ld = tk[3], xslot0 = tk[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t half = ld / 2;
   {
     const double2* src = reinterpret_cast<const double2*>(xg + xslot0);
     double2* dst = reinterpret_cast<double2*>(xs);
-    for (int64_t j = threadIdx.x; j < half; j += 256) dst[j] = src[j];
+    for (int64_t j = threadIdx.x; j < ld / 2; j += 256) dst[j] = src[j];
   }
   __syncthreads();
-  const double2* x2 = reinterpret_cast<const double2*>(xs);
+  const int64_t nvec = ld / V::N;
   double dsum = 0.0;
   for (int64_t rb = w * GEMV_RPW; rb < nrows; rb += 4 * GEMV_RPW) {
     double acc[GEMV_RPW];
 #pragma unroll
     for (int r = 0; r < GEMV_RPW; ++r) acc[r] = 0.0;
-    for (int64_t j = lane; j < half; j += 64) {
-      const double2 xv = x2[j];
+    for (int64_t j = lane; j < nvec; j += 64) {
+      const double* xv = xs + V::N * j;
 #pragma unroll
       for (int r = 0; r < GEMV_RPW; ++r) {
         if (rb + r < nrows) {
-          const double2 mv = reinterpret_cast<const double2*>(M + mrow0 + (rb + r) * ld)[j];
-          acc[r] += mv.x * xv.x + mv.y * xv.y;
+          const typename V::T mv = reinterpret_cast<const typename V::T*>(M + mrow0 + (rb + r) * ld)[j];
+          acc[r] += V::dot(mv, xv);
         }
       }
     }
@@ -392,6 +412,11 @@ __global__ __launch_bounds__(256) void k_gemv(const double* M, const int64_t* ta
   if (lane == 0) red[w] = dsum;
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void k_to_float(const double* in, float* out, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = float(in[i]);
 }
 
 // Sum of n partials by one block with several loads in flight per thread;
@@ -705,14 +730,28 @@ void gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* x
   if (m_r <= 0) return;
   hipLaunchKernelGGL(k_gather_rows, dim3((m_r + 255) / 256), dim3(256), 0, s, x, row_src, m_r, xg);
 }
-void gemv(const double* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
-          double* part, const int* done, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+template <typename MT>
+void gemv_impl(const MT* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
+               double* part, const int* done, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (ntask <= 0) return;
   const size_t lds = size_t(max_ld) * sizeof(double);
   if (ev_start)
-    hipExtLaunchKernelGGL(k_gemv, dim3(ntask), dim3(256), lds, s, ev_start, ev_stop, 0, M, task, xg, v, part, done);
+    hipExtLaunchKernelGGL(k_gemv<MT>, dim3(ntask), dim3(256), lds, s, ev_start, ev_stop, 0, M, task, xg, v, part,
+                          done);
   else
-    hipLaunchKernelGGL(k_gemv, dim3(ntask), dim3(256), lds, s, M, task, xg, v, part, done);
+    hipLaunchKernelGGL(k_gemv<MT>, dim3(ntask), dim3(256), lds, s, M, task, xg, v, part, done);
+}
+void gemv(const double* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
+          double* part, const int* done, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  gemv_impl(M, task, ntask, max_ld, xg, v, part, done, s, ev_start, ev_stop);
+}
+void gemv(const float* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
+          double* part, const int* done, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  gemv_impl(M, task, ntask, max_ld, xg, v, part, done, s, ev_start, ev_stop);
+}
+void to_float(const double* in, float* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_to_float, dim3(grid_for(n, 256)), dim3(256), 0, s, in, out, n);
 }
 void coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x, double* out, hipStream_t s) {
   if (n_gp <= 0) return;

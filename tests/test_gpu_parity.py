@@ -141,3 +141,22 @@ def test_graph_replay_matches_direct_launches_bitwise(runs):
     a3, st3 = S.solve(rtol=1e-10, use_graph=True)
     assert st1["iters"] == st2["iters"] == st3["iters"]
     assert np.array_equal(a1, a2) and np.array_equal(a1, a3)
+
+
+@pytest.mark.parametrize("name", ["uneven_nu", "cube64_small"])
+def test_mixed_precision_meets_the_fp64_residual(runs, name):
+    """Mixed path: FP32-stored interface blocks in the inner PCG, outer
+    refinement on the FP64 residual; the final FP64 residual meets rtol and
+    the B field matches the oracle's monolithic solve."""
+    from paper_2501_04340_amd.ietidp import PREC_FP64, PREC_MIXED
+    prob, S, O = _get(runs, name)
+    S.factor(precision=PREC_MIXED)
+    a, st = S.solve(rtol=1e-11, maxit=4000)
+    assert st["status"] == 0 and st["outer_iters"] >= 1
+    lam = S.lambda_()
+    b = S.rhs()
+    res = np.linalg.norm(b - S.apply_F(lam)) / np.linalg.norm(b)
+    assert res <= 1e-11
+    a_mono = O.monolithic()
+    assert b_error(O.space, a, a_ref=a_mono)[1] <= 1e-9
+    S.factor(precision=PREC_FP64)
