@@ -87,7 +87,8 @@ typedef struct {
 } ieti_problem;
 
 typedef struct {
-  int32_t precision;   /* IETI_PREC_FP64 or IETI_PREC_MIXED (FP32 local factors) */
+  int32_t precision;   /* IETI_PREC_FP64, or IETI_PREC_MIXED: FP64 factorisation, FP32 copies of the
+                          interface blocks for the inner PCG of an FP64 iterative refinement */
   int32_t tile;        /* factor tile size: 0 = default (64) */
   int32_t ordering;    /* 0 = nested dissection of r_V (default), 1 = natural order */
   int32_t reserved;
@@ -100,7 +101,9 @@ typedef struct {
   int32_t check_every;       /* iterations between host convergence checks (0 = 8) */
   const double* lambda0;     /* host initial multipliers [m_r] or NULL (= 0) */
   int32_t use_graph;         /* 1 = replay PCG iterations from a captured hipGraph */
-  int32_t reserved;
+  int32_t warm_start;        /* 1 = lambda_0 from the network set by ieti_set_warm_start (ignored
+                                when lambda0 is given); rejected in favour of lambda_0 = 0 when
+                                ||b - F lambda_0|| >= ||b|| or not finite */
 } ieti_solve_opts;
 
 typedef struct {
@@ -117,6 +120,9 @@ typedef struct {
   double t_solve_s;      /* device time of ieti_solve (rhs + PCG + recovery) */
   double t_pcg_s;        /* device time of the PCG loop */
   double factor_flops;   /* algorithmic flops of the local factorisations */
+  double rel_residual0;  /* ||b - F lambda_0|| / ||b|| of the initial multipliers used */
+  int32_t warm_start;    /* 1 = network prediction used, -1 = prediction rejected, 0 = not asked */
+  int32_t reserved;
 } ieti_stats;
 
 /* Assemble the problem on the host: spline spaces, Galerkin matrices of
@@ -210,10 +216,99 @@ int ieti_set_profiling(ieti_handle* h, int32_t enable);
  * ms, update tasks executed, interface-block bytes read per GEMV launch}. */
 int ieti_get_kernel_times(const ieti_handle* h, double* times);
 
+/* Change the reluctivity of every patch and scale every patch's load
+ * vector without repeating the assembly: the Galerkin matrix of Eq. discrMS
+ * is linear in the piecewise-constant reluctivity, so the library keeps the
+ * per-patch contributions and re-sums them (bit-identical to assembling with
+ * the new reluctivity).  load_scale[q] multiplies the load of patch q, which
+ * equals assembling with the source scaled by load_scale[q] on patch q; the
+ * caller keeps the scaled source divergence-free (e.g. one factor per coil
+ * ring).  nu_per_patch [n_patches] > 0, load_scale [n_patches] finite; either
+ * may be NULL to keep the current values.  The next solve needs a new
+ * ieti_factor. */
+int ieti_set_coefficients(ieti_handle* h, const double* nu_per_patch, const double* load_scale);
+
 /* Multipliers of the last solve [m_r]. */
 int ieti_get_lambda(const ieti_handle* h, double* lambda_out);
 
 void ieti_destroy(ieti_handle* h);
+
+/* ---- learned warm start ---------------------------------------------------
+ * A multilayer perceptron, trained on multipliers that the solver itself
+ * computed, predicts the initial multipliers lambda_0 of the PCG from the
+ * per-patch reluctivity and load scales.  The PCG then runs as before from
+ * lambda_0; the stopping test is the same, so a poor prediction costs
+ * iterations, not accuracy.
+ *
+ * Network: n_layers hidden layers of width n_hidden with tanh, a linear
+ * output of n_comb * n_out values; the prediction of a row is
+ * pred[o] = sum_r c[r] * out[r * n_out + o] with the row's n_comb
+ * coefficients c (the solution is linear in the source, so c carries source
+ * amplitudes).  Parameters: for each layer l the matrix W'_l = [W_l b_l]
+ * (d_l x (d_{l-1} + 1), row-major, bias in the last column), layers in order,
+ * FP32.  Training minimises the mean of (pred - target)^2 over rows and
+ * outputs with Adam (Kingma & Ba 2015, Algorithm 1) on shuffled minibatches;
+ * forward, backward and the update run on the GPU in FP32. */
+typedef struct ieti_nn ieti_nn; /* opaque, library-owned, on the current HIP device */
+
+typedef struct {
+  int32_t n_in;      /* input features per row, >= 1 */
+  int32_t n_hidden;  /* width of every hidden layer, >= 1 */
+  int32_t n_layers;  /* hidden layers, >= 1 */
+  int32_t n_comb;    /* coefficients per row, >= 1 */
+  int32_t n_out;     /* outputs per row, >= 1 */
+} ieti_nn_arch;
+
+typedef struct {
+  int32_t epochs;    /* passes over the data */
+  int32_t batch;     /* rows per Adam step (0 = 256) */
+  float lr;          /* step size alpha */
+  float beta1;       /* 0 = 0.9 */
+  float beta2;       /* 0 = 0.999 */
+  float eps;         /* 0 = 1e-8 */
+  uint64_t seed;     /* shuffling: Fisher-Yates driven by SplitMix64 (Steele et al. 2014) */
+} ieti_nn_train_opts;
+
+/* New network with all parameters 0 (set them with ieti_nn_set_params). */
+int ieti_nn_create(const ieti_nn_arch* arch, ieti_nn** out);
+int ieti_nn_num_params(const ieti_nn* nn, int64_t* n_params);
+/* Copy parameters in / out [n_params]; setting them also resets Adam's state. */
+int ieti_nn_set_params(ieti_nn* nn, const float* params);
+int ieti_nn_get_params(const ieti_nn* nn, float* params);
+/* Training data (host, copied to the device): X [n][n_in], C [n][n_comb],
+ * Y [n][n_out] row-major. */
+int ieti_nn_set_data(ieti_nn* nn, const float* X, const float* C, const float* Y, int64_t n);
+/* Mean squared error over rows [row0, row0 + nrows) of the data and its
+ * gradient grad [n_params] (host) at the current parameters. */
+int ieti_nn_loss_grad(ieti_nn* nn, int64_t row0, int64_t nrows, double* loss, float* grad);
+/* Adam training on the data; epoch_loss [epochs] (mean squared error of the
+ * minibatches of each epoch, before their steps) may be NULL. */
+int ieti_nn_train(ieti_nn* nn, const ieti_nn_train_opts* opts, double* epoch_loss);
+/* pred [n][n_out] for host inputs X [n][n_in], C [n][n_comb]. */
+int ieti_nn_predict(ieti_nn* nn, const float* X, const float* C, int64_t n, float* pred);
+void ieti_nn_destroy(ieti_nn* nn);
+
+/* How the solver forms the network's rows and places its predictions: one
+ * row per facet f (e.g. one interface facet of two subdomains), features
+ * x[j] = (log(nu[feat_patch[f][j]]) - feat_shift[j]) * feat_scale[j],
+ * coefficients c[r] = load_scale[comb_patch[f][r]], and
+ * lambda_0[out_row[f][o]] = out_scale * out_sign[f][o] * pred[f][o]
+ * (out_row -1 = unused output; rows not covered start at 0). */
+typedef struct {
+  int32_t n_facets, n_feat, n_comb, n_out;
+  const int32_t* feat_patch;   /* [n_facets * n_feat] */
+  const float* feat_shift;     /* [n_feat] */
+  const float* feat_scale;     /* [n_feat] */
+  const int32_t* comb_patch;   /* [n_facets * n_comb] */
+  const int32_t* out_row;      /* [n_facets * n_out], distinct rows in [0, m_r) or -1 */
+  const int8_t* out_sign;      /* [n_facets * n_out], +1 or -1 */
+  double out_scale;
+} ieti_warm_layout;
+
+/* Attach a copy of the network's current parameters and the layout to the
+ * handle (nn may be destroyed afterwards); solves with warm_start = 1 then
+ * predict lambda_0 on the GPU. */
+int ieti_set_warm_start(ieti_handle* h, const ieti_nn* nn, const ieti_warm_layout* layout);
 
 const char* ieti_last_error(void);
 

@@ -22,6 +22,8 @@ following the paper's steps in its order and notation:
                  localProb), the Dirichlet preconditioner (Eq. DirPrec) and PCG.
 * ``monolithic`` direct sparse solve of the gauged global system.
 * ``post``       B = curl A at quadrature points and the error of Section 4.
+* ``nn``         the warm-start network: forward pass, backpropagation and
+                 Adam, in float64.
 
 Parity-unpinned items are listed in the module docstrings where they occur.
 """

@@ -21,10 +21,12 @@ BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = [
     os.path.join(CSRC, "api.cpp"),
+    os.path.join(CSRC, "nn_api.cpp"),
     os.path.join(CSRC, "host", "mesh_topology.cpp"),
     os.path.join(CSRC, "host", "assemble.cpp"),
     os.path.join(CSRC, "host", "plan.cpp"),
     os.path.join(CSRC, "device", "kernels.hip"),
+    os.path.join(CSRC, "device", "nn_kernels.hip"),
 ]
 
 ARCH = "gfx950"

@@ -9,54 +9,20 @@
 #include <string>
 #include <vector>
 
+#include "common.hpp"
 #include "device/kernels.hpp"
+#include "device/nn.hpp"
 #include "host/model.hpp"
 #include "host/plan.hpp"
 #include "ietidp.h"
+#include "nn_model.hpp"
 
 namespace {
 
-thread_local std::string g_last_error;
-
-int fail(int code, const std::string& msg) {
-  g_last_error = msg;
-  return code;
-}
-
-#define HIP_TRY(expr)                                                                     \
-  do {                                                                                    \
-    hipError_t e_ = (expr);                                                               \
-    if (e_ != hipSuccess)                                                                 \
-      return fail(IETI_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
-  } while (0)
-
-template <class T>
-struct DBuf {
-  T* ptr = nullptr;
-  int64_t n = 0;
-  void release() {
-    if (ptr) (void)hipFree(ptr);
-    ptr = nullptr;
-    n = 0;
-  }
-};
-
-template <class T>
-int dalloc(DBuf<T>& b, int64_t n) {
-  b.release();
-  b.n = n;
-  if (n <= 0) return IETI_OK;
-  HIP_TRY(hipMalloc(&b.ptr, size_t(n) * sizeof(T)));
-  return IETI_OK;
-}
-
-template <class T>
-int dupload(DBuf<T>& b, const std::vector<T>& h) {
-  int rc = dalloc(b, int64_t(h.size()));
-  if (rc) return rc;
-  if (!h.empty()) HIP_TRY(hipMemcpy(b.ptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
-  return IETI_OK;
-}
+using ieti::rt::DBuf;
+using ieti::rt::dalloc;
+using ieti::rt::dupload;
+using ieti::rt::fail;
 
 }  // namespace
 
@@ -88,6 +54,26 @@ struct ieti_handle {
   int ngemv = 0;
   hipGraph_t graph = nullptr, graph32 = nullptr;
   hipGraphExec_t graph_exec = nullptr, graph_exec32 = nullptr;
+
+  // learned warm start: a copy of the network, its row layout and work space
+  struct Warm {
+    bool on = false;
+    ieti::nn::Mlp mlp;
+    DBuf<float> theta, shift, scale, Cf;
+    DBuf<int32_t> feat_patch, comb_patch, out_row;
+    DBuf<int8_t> out_sign;
+    ieti::nn::Work work;
+    int n_facets = 0, n_feat = 0, n_comb = 0, n_out = 0;
+    double out_scale = 1.0;
+    void release() {
+      for (auto* b : {&theta, &shift, &scale, &Cf}) b->release();
+      for (auto* b : {&feat_patch, &comb_patch, &out_row}) b->release();
+      out_sign.release();
+      work.release();
+      on = false;
+    }
+  } warm;
+  DBuf<double> nu_d, lscale_d;  // per-patch reluctivity and load scale (warm-start features)
 
   DBuf<int> flags;  // [0] err (factor), [1] done, [2] iters, [3] pcg err, [4] coarse err
   int* flags_h = nullptr;
@@ -127,6 +113,9 @@ struct ieti_handle {
     if (graph32) (void)hipGraphDestroy(graph32);
     S32.release();
     Sinv32.release();
+    warm.release();
+    nu_d.release();
+    lscale_d.release();
     if (own_stream) (void)hipStreamDestroy(own_stream);
   }
 };
@@ -484,6 +473,60 @@ double host_dot(ieti_handle* h, const double* x, const double* y, int64_t n) {
   return s;
 }
 
+// lambda_0 from the attached network: features from the per-patch
+// coefficients, forward pass, weighted sum of the output groups, scatter
+// into the multiplier rows.
+void warm_predict(ieti_handle* h, double* lam) {
+  namespace N = ieti::nn;
+  auto& W = h->warm;
+  hipStream_t s = h->stream;
+  N::features(h->nu_d.ptr, h->lscale_d.ptr, W.feat_patch.ptr, W.shift.ptr, W.scale.ptr, W.n_facets, W.n_feat,
+              W.comb_patch.ptr, W.n_comb, W.work.H[0].ptr, W.Cf.ptr, s);
+  N::forward(W.mlp, W.theta.ptr, W.n_facets, W.work, s);
+  N::combine_loss(W.work.Y.ptr, W.Cf.ptr, nullptr, W.n_facets, W.n_comb, W.n_out, W.work.pred.ptr, nullptr, nullptr,
+                  s);
+  ieti::dev::fill(lam, h->model.m_r, 0.0, s);
+  N::scatter_prediction(W.work.pred.ptr, W.out_row.ptr, W.out_sign.ptr, int64_t(W.n_facets) * W.n_out, W.out_scale,
+                        lam, s);
+}
+
+// Initial multipliers lam0 and residual r0 = b - F lam0 (rr0 = ||r0||^2):
+// the caller's lambda0, else the network's prediction (dropped for 0 when
+// its residual is not below ||b|| or not finite), else 0.
+int init_lambda(ieti_handle* h, const ieti_solve_opts* opts, double bb, double* lam0, double* r0, double* rr0,
+                int* applies, int* warm_flag) {
+  namespace D = ieti::dev;
+  const int64_t m_r = h->model.m_r;
+  hipStream_t s = h->stream;
+  *warm_flag = 0;
+  bool have = false;
+  if (opts && opts->lambda0) {
+    HIP_TRY(hipMemcpyAsync(lam0, opts->lambda0, m_r * sizeof(double), hipMemcpyHostToDevice, s));
+    have = true;
+  } else if (opts && opts->warm_start) {
+    if (!h->warm.on) return fail(IETI_ERR_STATE, "warm_start requested but no network is attached");
+    warm_predict(h, lam0);
+    have = true;
+    *warm_flag = 1;
+  }
+  if (have) {
+    apply_F(h, lam0, h->q.ptr);
+    ++*applies;
+    D::axpby(h->b.ptr, h->q.ptr, r0, 1.0, -1.0, m_r, s);
+    *rr0 = host_dot(h, r0, r0, m_r);
+    if (*warm_flag == 1 && !(std::isfinite(*rr0) && *rr0 < bb)) {
+      *warm_flag = -1;
+      have = false;
+    }
+  }
+  if (!have) {
+    D::fill(lam0, m_r, 0.0, s);
+    D::vec_copy(h->b.ptr, r0, m_r, s);
+    *rr0 = bb;
+  }
+  return check_launch();
+}
+
 // PCG on F x = r_0 from the state prepared by the caller (x in h->lam, r_0 in
 // h->r with ||r_0||^2 = rr0), until ||r||^2 <= tol2 or maxit iterations.
 int run_pcg(ieti_handle* h, double tol2, double rr0, int maxit, int every, bool fp32, bool use_graph, int* iters_out,
@@ -561,20 +604,14 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   h->bnorm = std::sqrt(bb);
   HIP_TRY(hipEventRecord(h->ev1, s));
   int status = IETI_OK;
-  int applies = 0;
+  int applies = 0, warm_flag = 0;
+  double rr0 = 0.0;
   if (m_r > 0) {
     if (!h->mixed) {
       // plain FP64: PCG on F lambda = b from lambda_0
-      if (opts && opts->lambda0) {
-        HIP_TRY(hipMemcpyAsync(h->lam.ptr, opts->lambda0, m_r * sizeof(double), hipMemcpyHostToDevice, s));
-        apply_F(h, h->lam.ptr, h->q.ptr);
-        ++applies;
-        D::axpby(h->b.ptr, h->q.ptr, h->r.ptr, 1.0, -1.0, m_r, s);
-      } else {
-        D::fill(h->lam.ptr, m_r, 0.0, s);
-        D::vec_copy(h->b.ptr, h->r.ptr, m_r, s);
-      }
-      rr = host_dot(h, h->r.ptr, h->r.ptr, m_r);
+      rc = init_lambda(h, opts, bb, h->lam.ptr, h->r.ptr, &rr, &applies, &warm_flag);
+      if (rc) return rc;
+      rr0 = rr;
       int n = 0;
       rc = run_pcg(h, rtol * rtol * bb, rr, maxit, every, false, use_graph, &n, &rr, &status);
       if (rc) return rc;
@@ -583,21 +620,23 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
     } else {
       // mixed: outer refinement on the FP64 residual r = b - F lambda, inner PCG
       // with FP32-stored interface blocks on F d = r, lambda += d
-      if (opts && opts->lambda0)
-        HIP_TRY(hipMemcpyAsync(h->lam_acc.ptr, opts->lambda0, m_r * sizeof(double), hipMemcpyHostToDevice, s));
-      else
-        D::fill(h->lam_acc.ptr, m_r, 0.0, s);
+      rc = init_lambda(h, opts, bb, h->lam_acc.ptr, h->rtrue.ptr, &rr, &applies, &warm_flag);
+      if (rc) return rc;
+      rr0 = rr;
       const int max_outer = 20;
       status = IETI_ERR_NOT_CONVERGED;
-      for (outer = 0; outer < max_outer && it < maxit; ++outer) {
-        apply_F(h, h->lam_acc.ptr, h->q.ptr);
-        ++applies;
-        D::axpby(h->b.ptr, h->q.ptr, h->rtrue.ptr, 1.0, -1.0, m_r, s);
-        rr = host_dot(h, h->rtrue.ptr, h->rtrue.ptr, m_r);
+      for (outer = 0;; ++outer) {
+        if (outer > 0) {
+          apply_F(h, h->lam_acc.ptr, h->q.ptr);
+          ++applies;
+          D::axpby(h->b.ptr, h->q.ptr, h->rtrue.ptr, 1.0, -1.0, m_r, s);
+          rr = host_dot(h, h->rtrue.ptr, h->rtrue.ptr, m_r);
+        }
         if (rr <= rtol * rtol * bb || bb == 0.0) {
           status = IETI_OK;
           break;
         }
+        if (outer >= max_outer || it >= maxit) break;
         // inner tolerance: a fixed factor below the current true residual,
         // never tighter than what the final step needs
         const double inner_rel = std::max(1e-4, 0.5 * rtol * std::sqrt(bb / rr));
@@ -660,6 +699,9 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
     st->t_solve_s = ms_total * 1e-3;
     st->t_pcg_s = ms_pcg * 1e-3;
     st->factor_flops = h->plan.flops;
+    st->rel_residual0 = h->bnorm > 0 ? std::sqrt(rr0) / h->bnorm : 0.0;
+    st->warm_start = warm_flag;
+    st->reserved = 0;
   }
   if (status != IETI_OK) return fail(status, "PCG did not reach the tolerance within maxit");
   return IETI_OK;
@@ -669,7 +711,7 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
 
 extern "C" {
 
-const char* ieti_last_error(void) { return g_last_error.c_str(); }
+const char* ieti_last_error(void) { return ieti::rt::last_error().c_str(); }
 
 int ieti_assemble(const ieti_problem* prob, ieti_handle** out) {
   if (!out) return fail(IETI_ERR_INVALID_ARG, "out is NULL");
@@ -948,5 +990,86 @@ int ieti_get_lambda(const ieti_handle* h, double* lambda_out) {
 }
 
 void ieti_destroy(ieti_handle* h) { delete h; }
+
+int ieti_set_coefficients(ieti_handle* h, const double* nu_per_patch, const double* load_scale) {
+  if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
+  auto& M = h->model;
+  if (h->stream) HIP_TRY(hipStreamSynchronize(h->stream));
+  const std::vector<double> nu(nu_per_patch ? std::vector<double>(nu_per_patch, nu_per_patch + M.part.size()) : M.nu);
+  const std::vector<double> sc(load_scale ? std::vector<double>(load_scale, load_scale + M.part.size())
+                                          : M.load_scale);
+  ieti::Error err{0, ""};
+  if (ieti::set_coefficients(M, nu.data(), sc.data(), err)) return fail(err.code, err.msg);
+  h->factored = false;
+  h->rhs_ready = false;
+  if (h->plan_T > 0) {
+    ieti::refill_values(M, h->plan);
+    if (h->uploaded) {
+      const auto& P = h->plan;
+      HIP_TRY(hipMemcpy(h->scatter_val.ptr, P.scatter_val.data(), P.scatter_val.size() * sizeof(double),
+                        hipMemcpyHostToDevice));
+      if (!P.krp_val.empty())
+        HIP_TRY(hipMemcpy(h->krp_val.ptr, P.krp_val.data(), P.krp_val.size() * sizeof(double), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(h->b_aug0.ptr, P.b_aug0.data(), P.b_aug0.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+  }
+  if (h->nu_d.ptr) {
+    HIP_TRY(hipMemcpy(h->nu_d.ptr, M.nu.data(), M.nu.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->lscale_d.ptr, M.load_scale.data(), M.load_scale.size() * sizeof(double),
+                      hipMemcpyHostToDevice));
+  }
+  return IETI_OK;
+}
+
+int ieti_set_warm_start(ieti_handle* h, const ieti_nn* nn, const ieti_warm_layout* L) {
+  if (!h || !nn || !L) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  const auto& mlp = ieti::nn::mlp_of(nn);
+  const auto& M = h->model;
+  const int64_t np = int64_t(M.part.size());
+  if (L->n_facets < 1 || L->n_feat != mlp.arch.n_in || L->n_comb != mlp.arch.n_comb || L->n_out != mlp.arch.n_out)
+    return fail(IETI_ERR_INVALID_ARG, "layout sizes do not match the network");
+  if (!L->feat_patch || !L->feat_shift || !L->feat_scale || !L->comb_patch || !L->out_row || !L->out_sign)
+    return fail(IETI_ERR_INVALID_ARG, "layout arrays are required");
+  const int64_t nf = L->n_facets;
+  for (int64_t i = 0; i < nf * L->n_feat; ++i)
+    if (L->feat_patch[i] < 0 || L->feat_patch[i] >= np) return fail(IETI_ERR_INVALID_ARG, "feature patch out of range");
+  for (int64_t i = 0; i < nf * L->n_comb; ++i)
+    if (L->comb_patch[i] < 0 || L->comb_patch[i] >= np)
+      return fail(IETI_ERR_INVALID_ARG, "coefficient patch out of range");
+  std::vector<uint8_t> seen(M.m_r, 0);
+  for (int64_t i = 0; i < nf * L->n_out; ++i) {
+    const int32_t r = L->out_row[i];
+    if (r < -1 || r >= M.m_r) return fail(IETI_ERR_INVALID_ARG, "output row out of range");
+    if (r >= 0 && seen[r]++) return fail(IETI_ERR_INVALID_ARG, "output rows must be distinct");
+    if (L->out_sign[i] != 1 && L->out_sign[i] != -1) return fail(IETI_ERR_INVALID_ARG, "output signs must be +-1");
+  }
+  if (!std::isfinite(L->out_scale)) return fail(IETI_ERR_INVALID_ARG, "output scale must be finite");
+  auto& W = h->warm;
+  W.release();
+  W.mlp = mlp;
+  W.n_facets = L->n_facets;
+  W.n_feat = L->n_feat;
+  W.n_comb = L->n_comb;
+  W.n_out = L->n_out;
+  W.out_scale = L->out_scale;
+  int rc = 0;
+  HIP_TRY(hipStreamSynchronize(ieti::nn::stream_of(nn)));
+  if ((rc = dalloc(W.theta, mlp.n_params))) return rc;
+  HIP_TRY(hipMemcpy(W.theta.ptr, ieti::nn::params_of(nn), mlp.n_params * sizeof(float), hipMemcpyDeviceToDevice));
+  if ((rc = dupload(W.feat_patch, L->feat_patch, nf * L->n_feat))) return rc;
+  if ((rc = dupload(W.shift, L->feat_shift, L->n_feat))) return rc;
+  if ((rc = dupload(W.scale, L->feat_scale, L->n_feat))) return rc;
+  if ((rc = dupload(W.comb_patch, L->comb_patch, nf * L->n_comb))) return rc;
+  if ((rc = dupload(W.out_row, L->out_row, nf * L->n_out))) return rc;
+  if ((rc = dupload(W.out_sign, L->out_sign, nf * L->n_out))) return rc;
+  if ((rc = dalloc(W.Cf, nf * L->n_comb))) return rc;
+  if ((rc = W.work.reserve(W.mlp, nf, nullptr))) return rc;
+  if ((rc = dupload(h->nu_d, M.nu))) return rc;
+  if ((rc = dupload(h->lscale_d, M.load_scale))) return rc;
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(nullptr));
+  W.on = true;
+  return IETI_OK;
+}
 
 }  // extern "C"

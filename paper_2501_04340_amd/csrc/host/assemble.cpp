@@ -11,6 +11,7 @@
 // Cox-de Boor scheme (Piegl & Tiller, The NURBS Book, Alg. A2.2).
 #include <algorithm>
 #include <cmath>
+#include <string>
 #include <vector>
 
 #include "model.hpp"
@@ -252,7 +253,6 @@ int assemble_local_systems(Model& m, Error& err) {
 #pragma omp for schedule(dynamic, 1)
     for (int64_t q = 0; q < n_patches; ++q) {
       const int k = m.part[q];
-      const double nu = m.nu[q];
       const int64_t pc[3] = {q % M.P[0], (q / M.P[0]) % M.P[1], q / (int64_t(M.P[0]) * M.P[1])};
       // local -> global edge ids and subdomain-local ids
       for (int c = 0; c < 3; ++c) {
@@ -373,7 +373,7 @@ int assemble_local_systems(Model& m, Error& err) {
         const double* row = &Kp[size_t(a) * nloc];
         for (int64_t b = 0; b < nloc; ++b) {
           if (lid[b] < 0 || row[b] == 0.0) continue;
-          local_trips.push_back({lid[a], lid[b], int32_t(q), nu * row[b]});
+          local_trips.push_back({lid[a], lid[b], int32_t(q), row[b]});
         }
       }
       auto& PL = patch_load[q];
@@ -390,9 +390,7 @@ int assemble_local_systems(Model& m, Error& err) {
     err = {IETI_ERR_INVALID_ARG, "assembly failed"};
     return err.code;
   }
-  // loads summed in patch order (deterministic)
-  for (int64_t q = 0; q < n_patches; ++q)
-    for (const auto& pr : patch_load[q]) m.sd[m.part[q]].load[pr.first] += pr.second;
+  m.patch_load = std::move(patch_load);
   // ---- merge triplets into CSR per subdomain (deterministic order)
 #pragma omp parallel for schedule(dynamic, 1)
   for (int k = 0; k < m.n_sub; ++k) {
@@ -405,19 +403,56 @@ int assemble_local_systems(Model& m, Error& err) {
     Subdomain& s = m.sd[k];
     s.indptr.assign(s.n_loc + 1, 0);
     s.indices.clear();
-    s.values.clear();
+    s.tr_seg.assign(1, 0);
+    s.tr_patch.resize(T.size());
+    s.tr_val.resize(T.size());
     size_t i = 0;
     while (i < T.size()) {
       size_t j = i;
-      double v = 0.0;
-      while (j < T.size() && T[j].r == T[i].r && T[j].c == T[i].c) v += T[j++].v;
+      while (j < T.size() && T[j].r == T[i].r && T[j].c == T[i].c) {
+        s.tr_patch[j] = T[j].patch;
+        s.tr_val[j] = T[j].v;
+        ++j;
+      }
       s.indices.push_back(T[i].c);
-      s.values.push_back(v);
+      s.tr_seg.push_back(int64_t(j));
       s.indptr[T[i].r + 1]++;
       i = j;
     }
     for (int64_t r = 0; r < s.n_loc; ++r) s.indptr[r + 1] += s.indptr[r];
     std::vector<Trip>().swap(T);
+  }
+  std::vector<double> ones(n_patches, 1.0);
+  return set_coefficients(m, m.nu.data(), ones.data(), err);
+}
+
+int set_coefficients(Model& m, const double* nu, const double* load_scale, Error& err) {
+  const int64_t n_patches = int64_t(m.part.size());
+  for (int64_t q = 0; q < n_patches; ++q)
+    if (!(nu[q] > 0.0) || !std::isfinite(nu[q]) || !std::isfinite(load_scale[q])) {
+      err = {IETI_ERR_INVALID_ARG, "reluctivity must be positive and finite, load scales finite (patch " +
+                                       std::to_string(q) + ")"};
+      return err.code;
+    }
+  if (m.nu.data() != nu) m.nu.assign(nu, nu + n_patches);
+  m.load_scale.assign(load_scale, load_scale + n_patches);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < m.n_sub; ++k) {
+    Subdomain& s = m.sd[k];
+    const int64_t nnz = int64_t(s.tr_seg.size()) - 1;
+    s.values.resize(nnz);
+    for (int64_t i = 0; i < nnz; ++i) {
+      double v = 0.0;
+      for (int64_t t = s.tr_seg[i]; t < s.tr_seg[i + 1]; ++t) v += m.nu[s.tr_patch[t]] * s.tr_val[t];
+      s.values[i] = v;
+    }
+    std::fill(s.load.begin(), s.load.end(), 0.0);
+  }
+  // loads summed in patch order (deterministic)
+  for (int64_t q = 0; q < n_patches; ++q) {
+    Subdomain& s = m.sd[m.part[q]];
+    const double c = m.load_scale[q];
+    for (const auto& pr : m.patch_load[q]) s.load[pr.first] += c * pr.second;
   }
   return IETI_OK;
 }

@@ -51,6 +51,13 @@ struct Subdomain {
   std::vector<int32_t> indices;
   std::vector<double> values;
   std::vector<double> load;
+  // unscaled per-patch contributions of every CSR entry, in increasing patch
+  // order: values[i] = sum over t in [tr_seg[i], tr_seg[i+1]) of
+  // nu[tr_patch[t]] * tr_val[t] (the Galerkin matrix is linear in the
+  // piecewise-constant reluctivity)
+  std::vector<int64_t> tr_seg;
+  std::vector<int32_t> tr_patch;
+  std::vector<double> tr_val;
   std::vector<uint8_t> owner;     // per r DOF: 1 if this subdomain writes the global value
 };
 
@@ -58,6 +65,9 @@ struct Model {
   ieti_problem prob{};
   std::vector<int32_t> part;
   std::vector<double> nu;
+  std::vector<double> load_scale;  // per patch, multiplies the patch's assembled load
+  // per patch: unscaled load entries (local DOF in the patch's subdomain, value)
+  std::vector<std::vector<std::pair<int32_t, double>>> patch_load;
   Mesh mesh;
   int n_sub = 0;
   // per edge
@@ -74,5 +84,7 @@ struct Model {
 int build_topology(Model& m, Error& err);
 // assemble.cpp
 int assemble_local_systems(Model& m, Error& err);
+// new reluctivity and load scale per patch, from the stored contributions
+int set_coefficients(Model& m, const double* nu, const double* load_scale, Error& err);
 
 }  // namespace ieti

@@ -194,27 +194,28 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
   plan.P_total = P_total;
   plan.r_total = r_total;
   // ---------------------------------------------------------------- scatter list
-  for (int k = 0; k < S; ++k) {
+  for (int64_t k = 0, voff = 0; k < S; ++k) {
     const Subdomain& s = m.sd[k];
     const SubPlan& sp = plan.sub[k];
     const int64_t nt = sp.nt;
-    auto put = [&](int64_t pr, int64_t pc, double v) {
+    auto put = [&](int64_t pr, int64_t pc, int64_t src) {
       const int64_t ti = pr / T, tj = pc / T;
       const int64_t off = sp.tile_off[ti * nt + tj];
       plan.scatter_dst.push_back(off + (pc % T) * T + (pr % T));
-      plan.scatter_val.push_back(v);
+      plan.scatter_src.push_back(src);
     };
     for (int64_t r = 0; r < s.n_loc; ++r) {
       const int64_t pr = sp.pos_of_local[r];
       for (int64_t q = s.indptr[r]; q < s.indptr[r + 1]; ++q) {
         const int64_t pc = sp.pos_of_local[s.indices[q]];
-        if (pr / T > pc / T || (pr / T == pc / T)) put(pr, pc, s.values[q]);
+        if (pr / T > pc / T || (pr / T == pc / T)) put(pr, pc, voff + q);
       }
     }
-    for (int64_t q : sp.vdummy) put(q, q, 1.0);
-    for (int64_t t = sp.nVp + sp.nI; t < sp.nVp + sp.nIp; ++t) put(t, t, 1.0);
+    for (int64_t q : sp.vdummy) put(q, q, -1);
+    for (int64_t t = sp.nVp + sp.nI; t < sp.nVp + sp.nIp; ++t) put(t, t, -1);
     const int64_t a0 = sp.nVp + sp.nIp + sp.nPp;
-    for (int64_t t = 0; t < sp.nI; ++t) put(a0 + t, sp.nVp + t, 1.0);
+    for (int64_t t = 0; t < sp.nI; ++t) put(a0 + t, sp.nVp + t, -1);
+    voff += s.indptr[s.n_loc];
   }
   // ---------------------------------------------------------------- level schedule
   // Column j of the tile factor depends on every column k < j with a tile
@@ -458,19 +459,17 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
   }
   // recovery rows of K_rp and the output map
   plan.krp_ptr.assign(1, 0);
-  plan.b_aug0.assign(r_total, 0.0);
-  for (int k = 0; k < S; ++k) {
+  for (int64_t k = 0, voff = 0; k < S; ++k) {
     const Subdomain& s = m.sd[k];
     const SubPlan& sp = plan.sub[k];
     const int64_t nr = int64_t(s.r_edges.size());
-    for (int64_t r = 0; r < s.n_loc; ++r) plan.b_aug0[sp.r_off + sp.pos_of_local[r]] = s.load[r];
     for (int64_t r = 0; r < nr; ++r) {
       bool any = false;
       for (int64_t q = s.indptr[r]; q < s.indptr[r + 1]; ++q) {
         const int32_t c = s.indices[q];
         if (c >= nr) {
           plan.krp_col.push_back(s.p_global[c - nr]);
-          plan.krp_val.push_back(s.values[q]);
+          plan.krp_src.push_back(voff + q);
           any = true;
         }
       }
@@ -483,7 +482,9 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
         plan.out_edge.push_back(s.r_edges[r]);
       }
     }
+    voff += s.indptr[s.n_loc];
   }
+  refill_values(m, plan);
   for (const auto& sp : plan.sub) {
     const double n = double(sp.nVp + sp.nIp);
     const double a = double(sp.nPp + sp.nIp);
@@ -491,6 +492,30 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
   }
   (void)err;
   return IETI_OK;
+}
+
+void refill_values(const Model& m, Plan& plan) {
+  std::vector<const double*> vals;
+  std::vector<int64_t> voff(1, 0);
+  for (const auto& s : m.sd) {
+    vals.push_back(s.values.data());
+    voff.push_back(voff.back() + s.indptr[s.n_loc]);
+  }
+  auto value = [&](int64_t src) {
+    const int64_t k = std::upper_bound(voff.begin(), voff.end(), src) - voff.begin() - 1;
+    return vals[k][src - voff[k]];
+  };
+  plan.scatter_val.resize(plan.scatter_src.size());
+  for (size_t i = 0; i < plan.scatter_src.size(); ++i)
+    plan.scatter_val[i] = plan.scatter_src[i] < 0 ? 1.0 : value(plan.scatter_src[i]);
+  plan.krp_val.resize(plan.krp_src.size());
+  for (size_t i = 0; i < plan.krp_src.size(); ++i) plan.krp_val[i] = value(plan.krp_src[i]);
+  plan.b_aug0.assign(plan.r_total, 0.0);
+  for (size_t k = 0; k < m.sd.size(); ++k) {
+    const Subdomain& s = m.sd[k];
+    const SubPlan& sp = plan.sub[k];
+    for (int64_t r = 0; r < s.n_loc; ++r) plan.b_aug0[sp.r_off + sp.pos_of_local[r]] = s.load[r];
+  }
 }
 
 }  // namespace ieti

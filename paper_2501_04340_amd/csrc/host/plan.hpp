@@ -56,6 +56,7 @@ struct Plan {
   // scatter of the assembled entries into the tile pool
   std::vector<int64_t> scatter_dst;
   std::vector<double> scatter_val;
+  std::vector<int64_t> scatter_src;  // per entry: index into the concatenated CSR values, -1 = constant 1
   // dense S / Sinv storage
   int64_t S_elems = 0;
   int64_t I_total = 0;   // sum nIp
@@ -86,6 +87,7 @@ struct Plan {
   std::vector<int64_t> krp_ptr, krp_pos;
   std::vector<int32_t> krp_col;
   std::vector<double> krp_val;
+  std::vector<int64_t> krp_src;        // per entry: index into the concatenated CSR values
   // output: augmented index and edge id of every owned r DOF
   std::vector<int64_t> out_src, out_edge;
   // initial augmented right-hand side [j_r; j_p; 0]
@@ -97,5 +99,8 @@ struct Plan {
 
 // ordering: 0 = nested dissection, 1 = natural
 int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err);
+// recompute the value arrays (scatter_val, krp_val, b_aug0) from the model's
+// current matrix values and loads; the structure is unchanged
+void refill_values(const Model& m, Plan& plan);
 
 }  // namespace ieti

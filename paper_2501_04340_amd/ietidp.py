@@ -57,7 +57,7 @@ class SolveOpts(C.Structure):
         ("check_every", C.c_int32),
         ("lambda0", C.POINTER(C.c_double)),
         ("use_graph", C.c_int32),
-        ("reserved", C.c_int32),
+        ("warm_start", C.c_int32),
     ]
 
 
@@ -76,17 +76,41 @@ class Stats(C.Structure):
         ("t_solve_s", C.c_double),
         ("t_pcg_s", C.c_double),
         ("factor_flops", C.c_double),
+        ("rel_residual0", C.c_double),
+        ("warm_start", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class NNArch(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_hidden", C.c_int32), ("n_layers", C.c_int32), ("n_comb", C.c_int32),
+                ("n_out", C.c_int32)]
+
+
+class NNTrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64)]
+
+
+class WarmLayout(C.Structure):
+    _fields_ = [
+        ("n_facets", C.c_int32), ("n_feat", C.c_int32), ("n_comb", C.c_int32), ("n_out", C.c_int32),
+        ("feat_patch", C.POINTER(C.c_int32)), ("feat_shift", C.POINTER(C.c_float)),
+        ("feat_scale", C.POINTER(C.c_float)), ("comb_patch", C.POINTER(C.c_int32)),
+        ("out_row", C.POINTER(C.c_int32)), ("out_sign", C.POINTER(C.c_int8)), ("out_scale", C.c_double),
+    ]
+
+
 EXPORTS = [
     "ieti_assemble", "ieti_factor", "ieti_solve", "ieti_solve_device", "ieti_get_sizes", "ieti_get_maps",
     "ieti_get_local_system", "ieti_get_schur", "ieti_apply_F", "ieti_apply_M", "ieti_get_rhs",
     "ieti_get_lambda", "ieti_get_plan_info", "ieti_set_profiling", "ieti_get_kernel_times", "ieti_destroy",
-    "ieti_last_error",
+    "ieti_last_error", "ieti_set_coefficients", "ieti_set_warm_start", "ieti_nn_create", "ieti_nn_num_params",
+    "ieti_nn_set_params", "ieti_nn_get_params", "ieti_nn_set_data", "ieti_nn_loss_grad", "ieti_nn_train",
+    "ieti_nn_predict", "ieti_nn_destroy",
 ]
 
 
@@ -133,8 +157,20 @@ def load_library():
     lib.ieti_destroy.argtypes = [C.c_void_p]
     lib.ieti_destroy.restype = None
     lib.ieti_last_error.restype = C.c_char_p
+    lib.ieti_set_coefficients.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
+    lib.ieti_set_warm_start.argtypes = [C.c_void_p, C.c_void_p, P(WarmLayout)]
+    lib.ieti_nn_create.argtypes = [P(NNArch), P(C.c_void_p)]
+    lib.ieti_nn_num_params.argtypes = [C.c_void_p, P(C.c_int64)]
+    lib.ieti_nn_set_params.argtypes = [C.c_void_p, P(C.c_float)]
+    lib.ieti_nn_get_params.argtypes = [C.c_void_p, P(C.c_float)]
+    lib.ieti_nn_set_data.argtypes = [C.c_void_p, P(C.c_float), P(C.c_float), P(C.c_float), C.c_int64]
+    lib.ieti_nn_loss_grad.argtypes = [C.c_void_p, C.c_int64, C.c_int64, P(C.c_double), P(C.c_float)]
+    lib.ieti_nn_train.argtypes = [C.c_void_p, P(NNTrainOpts), P(C.c_double)]
+    lib.ieti_nn_predict.argtypes = [C.c_void_p, P(C.c_float), P(C.c_float), C.c_int64, P(C.c_float)]
+    lib.ieti_nn_destroy.argtypes = [C.c_void_p]
+    lib.ieti_nn_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("ieti_destroy", "ieti_last_error"):
+        if name not in ("ieti_destroy", "ieti_last_error", "ieti_nn_destroy"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -245,20 +281,52 @@ class Solver:
         o.hip_stream = stream
         _check(self.lib, self.lib.ieti_factor(self.h, C.byref(o)))
 
-    def _solve_opts(self, rtol, maxit, lambda0, check_every, use_graph=True):
+    def set_coefficients(self, nu=None, load_scale=None):
+        """New per-patch reluctivity and load scales (no re-assembly); factor() again before solving."""
+        self._coef = [None if v is None else np.ascontiguousarray(v, dtype=np.float64) for v in (nu, load_scale)]
+        for v in self._coef:
+            if v is not None and v.shape != (len(self._part),):
+                raise ValueError("one value per patch expected")
+        args = [None if v is None else _ptr(v, C.c_double) for v in self._coef]
+        _check(self.lib, self.lib.ieti_set_coefficients(self.h, *args))
+
+    def set_warm_start(self, net, feat_patch, feat_shift, feat_scale, comb_patch, out_row, out_sign, out_scale):
+        """Attach a copy of ``net`` (an NN) with the row layout of the warm start."""
+        fp = np.ascontiguousarray(feat_patch, dtype=np.int32)
+        cp = np.ascontiguousarray(comb_patch, dtype=np.int32)
+        orow = np.ascontiguousarray(out_row, dtype=np.int32)
+        osg = np.ascontiguousarray(out_sign, dtype=np.int8)
+        fsh = np.ascontiguousarray(feat_shift, dtype=np.float32)
+        fsc = np.ascontiguousarray(feat_scale, dtype=np.float32)
+        L = WarmLayout()
+        L.n_facets, L.n_feat = fp.shape
+        L.n_comb = cp.shape[1]
+        L.n_out = orow.shape[1]
+        if cp.shape[0] != fp.shape[0] or orow.shape != osg.shape or orow.shape[0] != fp.shape[0]:
+            raise ValueError("layout arrays disagree in the number of facets")
+        if fsh.shape != (L.n_feat,) or fsc.shape != (L.n_feat,):
+            raise ValueError("one shift and scale per feature expected")
+        L.feat_patch, L.feat_shift, L.feat_scale = _ptr(fp, C.c_int32), _ptr(fsh, C.c_float), _ptr(fsc, C.c_float)
+        L.comb_patch, L.out_row, L.out_sign = _ptr(cp, C.c_int32), _ptr(orow, C.c_int32), _ptr(osg, C.c_int8)
+        L.out_scale = float(out_scale)
+        _check(self.lib, self.lib.ieti_set_warm_start(self.h, net.h, C.byref(L)))
+
+    def _solve_opts(self, rtol, maxit, lambda0, check_every, use_graph=True, warm_start=False):
         o = SolveOpts()
         o.rtol = rtol
         o.maxit = maxit
         o.check_every = check_every
         o.use_graph = 1 if use_graph else 0
+        o.warm_start = 1 if warm_start else 0
         self._lam0 = None
         if lambda0 is not None:
             self._lam0 = np.ascontiguousarray(lambda0, dtype=np.float64)
             o.lambda0 = _ptr(self._lam0, C.c_double)
         return o
 
-    def solve(self, rtol=1e-8, maxit=1000, lambda0=None, check_every=8, raise_on_nonconv=True, use_graph=True):
-        o = self._solve_opts(rtol, maxit, lambda0, check_every, use_graph)
+    def solve(self, rtol=1e-8, maxit=1000, lambda0=None, check_every=8, raise_on_nonconv=True, use_graph=True,
+              warm_start=False):
+        o = self._solve_opts(rtol, maxit, lambda0, check_every, use_graph, warm_start)
         a = np.zeros(self.n_edges)
         st = Stats()
         rc = self.lib.ieti_solve(self.h, C.byref(o), _ptr(a, C.c_double), C.byref(st))
@@ -317,3 +385,73 @@ class Solver:
         lam = np.zeros(self.m_r)
         _check(self.lib, self.lib.ieti_get_lambda(self.h, _ptr(lam, C.c_double)))
         return lam
+
+
+class NN:
+    """The warm-start network on the current HIP device (see ``ieti_nn_*``)."""
+
+    def __init__(self, n_in, n_hidden, n_layers, n_comb, n_out):
+        self.lib = load_library()
+        a = NNArch(n_in, n_hidden, n_layers, n_comb, n_out)
+        self.arch = (n_in, n_hidden, n_layers, n_comb, n_out)
+        h = C.c_void_p()
+        _check(self.lib, self.lib.ieti_nn_create(C.byref(a), C.byref(h)))
+        self.h = h
+        n = C.c_int64()
+        _check(self.lib, self.lib.ieti_nn_num_params(self.h, C.byref(n)))
+        self.n_params = int(n.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ieti_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        if theta.shape != (self.n_params,):
+            raise ValueError(f"{self.n_params} parameters expected")
+        _check(self.lib, self.lib.ieti_nn_set_params(self.h, _ptr(theta, C.c_float)))
+
+    def params(self):
+        theta = np.zeros(self.n_params, np.float32)
+        _check(self.lib, self.lib.ieti_nn_get_params(self.h, _ptr(theta, C.c_float)))
+        return theta
+
+    def set_data(self, X, Cc, Y):
+        n_in, _, _, n_comb, n_out = self.arch
+        self._X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, n_in)
+        n = self._X.shape[0]
+        self._C = np.ascontiguousarray(Cc, dtype=np.float32).reshape(n, n_comb)
+        self._Y = np.ascontiguousarray(Y, dtype=np.float32).reshape(n, n_out)
+        _check(self.lib, self.lib.ieti_nn_set_data(self.h, _ptr(self._X, C.c_float), _ptr(self._C, C.c_float),
+                                                   _ptr(self._Y, C.c_float), n))
+        self.n_data = n
+
+    def loss_grad(self, row0=0, nrows=None):
+        nrows = self.n_data - row0 if nrows is None else nrows
+        loss = C.c_double()
+        g = np.zeros(self.n_params, np.float32)
+        _check(self.lib, self.lib.ieti_nn_loss_grad(self.h, row0, nrows, C.byref(loss), _ptr(g, C.c_float)))
+        return float(loss.value), g
+
+    def train(self, epochs, lr, batch=256, seed=0, beta1=0.9, beta2=0.999, eps=1e-8):
+        o = NNTrainOpts(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps), int(seed))
+        losses = np.zeros(max(int(epochs), 1))
+        _check(self.lib, self.lib.ieti_nn_train(self.h, C.byref(o), _ptr(losses, C.c_double)))
+        return losses[:int(epochs)]
+
+    def predict(self, X, Cc):
+        n_in, _, _, n_comb, n_out = self.arch
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, n_in)
+        n = X.shape[0]
+        Cc = np.ascontiguousarray(Cc, dtype=np.float32).reshape(n, n_comb)
+        out = np.zeros((n, n_out), np.float32)
+        _check(self.lib, self.lib.ieti_nn_predict(self.h, _ptr(X, C.c_float), _ptr(Cc, C.c_float), n,
+                                                  _ptr(out, C.c_float)))
+        return out

@@ -1,0 +1,170 @@
+"""GPU parity of the warm-start network kernels against the FP64 oracle
+(oracle/nn.py), and the warm start inside the solver on a small ring.
+
+Tolerances: the kernels compute in FP32 (products on the FP32 matrix cores,
+FP32 accumulation over at most a few hundred terms), so outputs and
+gradients are compared at 1e-4 relative to their largest magnitude.
+"""
+import numpy as np
+import pytest
+
+from oracle import nn as onn
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+ARCH = (37, 70, 2, 3, 45)  # ragged: no size is a multiple of the 64-wide tiles
+N_ROWS = 130
+
+
+def _setup(seed=0, n=N_ROWS, arch=ARCH):
+    from paper_2501_04340_amd import NN
+    rng = np.random.default_rng(seed)
+    d = onn.dims(*arch)
+    npar = sum(b * (a + 1) for a, b in zip(d[:-1], d[1:]))
+    theta = (rng.standard_normal(npar) * 0.3).astype(np.float32)
+    X = rng.standard_normal((n, arch[0])).astype(np.float32)
+    Cc = rng.uniform(0.5, 1.5, size=(n, arch[3])).astype(np.float32)
+    T = rng.standard_normal((n, arch[4])).astype(np.float32)
+    net = NN(*arch)
+    assert net.n_params == npar
+    net.set_params(theta)
+    return net, theta, X, Cc, T
+
+
+def test_forward_matches_oracle(ietilib):
+    net, theta, X, Cc, T = _setup()
+    pred = net.predict(X, Cc)
+    _, _, ref = onn.forward(ARCH, theta.astype(np.float64), X.astype(np.float64), Cc.astype(np.float64))
+    assert np.abs(pred - ref).max() <= 1e-4 * np.abs(ref).max()
+    assert np.array_equal(net.params(), theta)
+
+
+def test_loss_and_gradient_match_oracle(ietilib):
+    net, theta, X, Cc, T = _setup(1)
+    net.set_data(X, Cc, T)
+    loss, g = net.loss_grad()
+    th = theta.astype(np.float64)
+    args = (X.astype(np.float64), Cc.astype(np.float64), T.astype(np.float64))
+    ref_loss = onn.loss(ARCH, th, *args)
+    ref_g = onn.grad(ARCH, th, *args)
+    assert abs(loss - ref_loss) <= 1e-5 * ref_loss
+    assert np.abs(g - ref_g).max() <= 1e-4 * np.abs(ref_g).max()
+    # a sub-range of rows
+    loss2, g2 = net.loss_grad(17, 50)
+    ref2 = onn.grad(ARCH, th, *(a[17:67] for a in args))
+    assert np.abs(g2 - ref2).max() <= 1e-4 * np.abs(ref2).max()
+
+
+def test_one_full_batch_adam_step_matches_oracle(ietilib):
+    net, theta, X, Cc, T = _setup(2)
+    net.set_data(X, Cc, T)
+    th = theta.astype(np.float64)
+    args = (X.astype(np.float64), Cc.astype(np.float64), T.astype(np.float64))
+    g = onn.grad(ARCH, th, *args)
+    lr = 1e-3
+    ref, _, _ = onn.adam_step(th, g, np.zeros_like(th), np.zeros_like(th), 1, lr)
+    losses = net.train(1, lr, batch=N_ROWS, seed=5)
+    new = net.params().astype(np.float64)
+    # Adam's first step is lr * g / (|g| + eps): compare where g is not at rounding level
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    assert np.abs(new - ref)[big].max() <= 1e-3 * lr + 1e-7
+    assert np.all(np.abs(new - th) <= lr * (1 + 1e-3) + 1e-7)
+    assert abs(losses[0] - onn.loss(ARCH, th, *args)) <= 1e-5 * losses[0]
+
+
+def test_training_fits_a_teacher_network(ietilib):
+    arch = (12, 64, 2, 2, 20)
+    teacher, th_t, X, Cc, _ = _setup(3, n=2048, arch=arch)
+    Y = teacher.predict(X, Cc)
+    student, _, _, _, _ = _setup(4, n=8, arch=arch)
+    student.set_data(X, Cc, Y)
+    l0, _ = student.loss_grad()
+    losses = student.train(60, 3e-3, batch=128, seed=1)
+    l1, _ = student.loss_grad()
+    print(f"[gpu-nn] teacher fit: loss {l0:.3e} -> {l1:.3e}")
+    assert np.all(np.isfinite(losses)) and l1 <= 0.05 * l0
+
+
+RING = dict(degree=2, n_el=2, n_theta=12)
+
+
+@pytest.fixture(scope="module")
+def ring(ietilib):
+    from paper_2501_04340_amd import Solver
+    from paper_2501_04340_amd.warmstart import RingWarmStart
+    prob = configs.ring576(**RING)
+    S = Solver(prob)
+    W = RingWarmStart(S, prob, window=2, hidden=64, layers=2)
+    draws = []
+    for i in range(72):
+        nu, cur = configs.ring_coefficients(configs.ring_sample_seed(i), n_theta=RING["n_theta"])
+        draws.append((nu, configs.ring_load_scale(cur, n_theta=RING["n_theta"])))
+    X, Cc, T, _ = W.generate(draws[:64], rtol=1e-11)
+    losses = W.fit(X, Cc, T, epochs=150, lr=2e-3, batch=64, seed=0)
+    print(f"[gpu-nn] ring fit: loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    W.attach()
+    return prob, S, W, draws[64:]
+
+
+def test_warm_start_saves_iterations_on_held_out_draws(ring):
+    prob, S, W, held = ring
+    cold_it, warm_it = [], []
+    for nu, scale in held:
+        S.set_coefficients(nu, scale)
+        S.factor()
+        a_c, st_c = S.solve(rtol=1e-8)
+        lam_c = S.lambda_()
+        a_w, st_w = S.solve(rtol=1e-8, warm_start=True)
+        assert st_w["warm_start"] == 1 and st_w["rel_residual0"] < 1.0
+        assert st_c["status"] == 0 and st_w["status"] == 0 and st_w["rel_residual"] <= 1e-8
+        # the prediction the solver used is the network's
+        pred = W.predict_lambda(nu, scale)
+        r0 = np.linalg.norm(S.rhs() - S.apply_F(pred)) / np.linalg.norm(S.rhs())
+        assert abs(r0 - st_w["rel_residual0"]) <= 1e-3 * r0
+        assert np.abs(a_w - a_c).max() <= 1e-5 * np.abs(a_c).max()
+        cold_it.append(st_c["iters"])
+        warm_it.append(st_w["iters"])
+    print(f"[gpu-nn] held-out: cold iters {np.mean(cold_it):.1f}, warm iters {np.mean(warm_it):.1f}")
+    assert np.mean(warm_it) < np.mean(cold_it)
+
+
+def test_bad_prediction_falls_back_to_zero(ring):
+    prob, S, W, held = ring
+    nu, scale = held[0]
+    S.set_coefficients(nu, scale)
+    S.factor()
+    a_c, st_c = S.solve(rtol=1e-8)
+    scale_keep = W.out_scale
+    W.out_scale = 1e8 * scale_keep
+    W.attach()
+    try:
+        a_w, st_w = S.solve(rtol=1e-8, warm_start=True)
+    finally:
+        W.out_scale = scale_keep
+        W.attach()
+    assert st_w["warm_start"] == -1 and st_w["rel_residual0"] == 1.0
+    assert st_w["iters"] == st_c["iters"] and np.array_equal(a_w, a_c)
+
+
+def test_warm_start_with_mixed_precision(ring):
+    from paper_2501_04340_amd.ietidp import PREC_FP64, PREC_MIXED
+    prob, S, W, held = ring
+    nu, scale = held[1]
+    S.set_coefficients(nu, scale)
+    S.factor(precision=PREC_MIXED)
+    try:
+        a_w, st_w = S.solve(rtol=1e-8, warm_start=True)
+        a_c, st_c = S.solve(rtol=1e-8)
+    finally:
+        S.factor(precision=PREC_FP64)
+    assert st_w["warm_start"] == 1 and st_w["status"] == 0 and st_w["rel_residual"] <= 1e-8
+    assert np.abs(a_w - a_c).max() <= 1e-5 * np.abs(a_c).max()
+
+
+def test_layout_mismatch_is_rejected(ring):
+    from paper_2501_04340_amd import NN
+    prob, S, W, held = ring
+    other = NN(W.n_feat + 1, 8, 1, W.n_comb, W.n_out)
+    with pytest.raises(Exception, match="INVALID_ARG"):
+        S.set_warm_start(other, W.feat_patch, W.shift, W.scale, W.comb_patch, W.out_row, W.out_sign, 1.0)

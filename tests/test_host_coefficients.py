@@ -1,0 +1,87 @@
+"""Host-side (no GPU) checks of the coefficient update and the ring
+warm-start layout.
+
+* ieti_set_coefficients re-sums the stored per-patch contributions: the
+  local matrices equal a fresh assembly with the new reluctivity bit for
+  bit, and the loads equal a fresh assembly with the coil current scaled per
+  axial ring to rounding (the load is linear in the source).
+* The warm-start layout covers every multiplier row of the ring once, with
+  the sign of the facet's lower sector.
+"""
+import numpy as np
+import pytest
+
+from paper_2501_04340_amd import Solver
+from paper_2501_04340_amd.warmstart import RingWarmStart, decode_edges
+from workloads import configs
+
+KW = dict(degree=2, n_el=2, n_theta=12)
+
+
+@pytest.fixture(scope="module")
+def nominal(ietilib):
+    prob = configs.ring576(**KW)
+    return prob, Solver(prob)
+
+
+def test_set_coefficients_equals_fresh_assembly(nominal):
+    prob, S = nominal
+    seed = configs.ring_sample_seed(3)
+    nu, cur = configs.ring_coefficients(seed, n_theta=KW["n_theta"])
+    S.set_coefficients(nu, configs.ring_load_scale(cur, n_theta=KW["n_theta"]))
+    fresh = Solver(configs.ring576(sample=seed, **KW))
+    for k in range(S.n_sub):
+        K1, j1 = S.local_system(k)
+        K2, j2 = fresh.local_system(k)
+        assert np.array_equal(K1.indptr, K2.indptr) and np.array_equal(K1.indices, K2.indices)
+        assert np.array_equal(K1.data, K2.data)
+        assert np.abs(j1 - j2).max() <= 1e-14 * np.abs(j2).max()
+    # back to the nominal coefficients: bit-identical to the original assembly
+    nu0, cur0 = configs.ring_coefficients(None, n_theta=KW["n_theta"])
+    S.set_coefficients(nu0, configs.ring_load_scale(cur0, n_theta=KW["n_theta"]))
+    base = Solver(prob)
+    for k in range(S.n_sub):
+        K1, j1 = S.local_system(k)
+        K2, j2 = base.local_system(k)
+        assert np.array_equal(K1.data, K2.data) and np.array_equal(j1, j2)
+
+
+def test_set_coefficients_rejects_bad_values(nominal):
+    prob, S = nominal
+    nu = np.array(prob.nu, dtype=np.float64)
+    bad = nu.copy()
+    bad[5] = -1.0
+    with pytest.raises(Exception, match="INVALID_ARG"):
+        S.set_coefficients(bad, None)
+    bad[5] = np.nan
+    with pytest.raises(Exception, match="INVALID_ARG"):
+        S.set_coefficients(None, bad)
+    S.set_coefficients(nu, None)
+
+
+def test_ring_layout_covers_every_multiplier_once(nominal):
+    prob, S = nominal
+    W = RingWarmStart(S, prob, window=2)
+    rows = W.out_row.ravel()
+    assert np.array_equal(np.sort(rows), np.arange(S.m_r))
+    mult = S.maps()["mult"]
+    step = prob.n_el + prob.degree - 1
+    _, I, _, _ = decode_edges(mult[:, 0], prob.patches, prob.periodic, prob.degree, prob.n_el)
+    for f in range(W.P0):
+        r = W.out_row[f]
+        assert np.all(I[r] == f * step)
+        lower = (f - 1) % W.P0
+        assert np.array_equal(W.out_sign[f] == 1, mult[r, 1] == lower)
+    # the wrap facet: the lower sector is the last one, B has +1 in sector 0
+    assert np.all(W.out_sign[0] == -1) and np.all(W.out_sign[1:] == 1)
+    assert W.feat_patch.shape == (W.P0, 4 * W.P1 * W.P2) and W.n_out * W.P0 == S.m_r
+
+
+def test_targets_and_prediction_scatter_are_inverse(nominal):
+    prob, S = nominal
+    W = RingWarmStart(S, prob, window=1)
+    lam = np.random.default_rng(0).standard_normal(S.m_r)
+    T = W.targets(lam)
+    back = np.zeros(S.m_r)
+    back[W.out_row] = W.out_sign * T
+    assert np.array_equal(back, lam)

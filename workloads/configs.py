@@ -88,21 +88,48 @@ def cube256(degree=2, n_el=6):
 RING_RADII = (1.00, 1.25, 1.50, 1.75)
 
 
-def ring576(degree=2, n_el=5, sample=None, n_theta=48):
-    """Motor-like annulus.  ``sample`` selects a seeded perturbation draw:
-    None = nominal, else the integer seed of a +-30% draw of the per-patch
-    reluctivity and the per-axial-ring coil current."""
+RING_TRAIN = 512
+RING_HELD_OUT = 64
+
+
+def ring_sample_seed(i):
+    """Seed of ring sample i: i < 512 training draws, 512 <= i < 576 held out."""
+    return MASTER_SEEDS["ring576"] * 1000 + int(i)
+
+
+def ring_coefficients(sample=None, n_theta=48):
+    """Per-patch reluctivity and per-axial-ring coil current of the annulus:
+    iron (1e-3) in the inner radial layer, air gap and coil (1) outside;
+    ``sample`` = None gives the nominal values, an integer seed a draw with
+    both multiplied by U(0.7, 1.3) (reluctivity per patch, current per ring)."""
     P = (n_theta, 3, 4)
     n = int(np.prod(P))
-    radial = np.array([(idx // P[0]) % P[1] for idx in range(n)])
-    axial = np.array([idx // (P[0] * P[1]) for idx in range(n)])
-    theta = np.array([idx % P[0] for idx in range(n)])
+    radial = (np.arange(n) // P[0]) % P[1]
     nu = np.where(radial == 0, 1e-3, 1.0)
     ring_current = np.ones(P[2])
     if sample is not None:
         rng = np.random.default_rng(sample)
         nu = nu * rng.uniform(0.7, 1.3, size=n)
         ring_current = rng.uniform(0.7, 1.3, size=P[2])
+    return nu, ring_current
+
+
+def ring_load_scale(ring_current, n_theta=48):
+    """Per-patch load factor of a coil-current draw: the current of the
+    patch's axial ring (the source is zero outside the coil layer)."""
+    P = (n_theta, 3, 4)
+    axial = np.arange(int(np.prod(P))) // (P[0] * P[1])
+    return np.asarray(ring_current, dtype=np.float64)[axial]
+
+
+def ring576(degree=2, n_el=5, sample=None, n_theta=48):
+    """Motor-like annulus.  ``sample`` selects a seeded perturbation draw:
+    None = nominal, else the integer seed of a +-30% draw of the per-patch
+    reluctivity and the per-axial-ring coil current."""
+    P = (n_theta, 3, 4)
+    n = int(np.prod(P))
+    theta = np.arange(n) % P[0]
+    nu, ring_current = ring_coefficients(sample, n_theta)
     z_edges = np.linspace(0.0, 1.0, P[2] + 1)
     src = sources.CoilSource(RING_RADII[2], RING_RADII[3], z_edges, ring_current)
     part = theta.astype(np.int32)
