@@ -36,6 +36,26 @@ WORKLOADS = {
 }
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "cube64_hbm_traffic_pmc.md")
+KERNELS_SRC = os.path.join(ROOT, "paper_2501_04340_amd", "csrc", "device", "kernels.hip")
+
+
+def measured_gemv_traffic():
+    """HBM bytes per FP64 GEMV launch from the committed PMC summary, or None
+    when the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        m = re.search(r"traffic_per_launch k_gemv fp64: .*total_bytes=(\d+) kernels_hip_sha256=([0-9a-f]+)", text)
+        sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if not m or m.group(2) != sha:
+        return None
+    return float(m.group(1))
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -112,6 +132,92 @@ def cpu_baseline(prob, iters, budget_s=20.0):
     }
 
 
+def ring_warm_start(args):
+    """ring576: train the warm-start network on 512 solver-generated solves,
+    then time 64 held-out draws cold and warm, plain FP64 and mixed."""
+    import torch
+
+    from paper_2501_04340_amd import Solver
+    from paper_2501_04340_amd.ietidp import PREC_FP64, PREC_MIXED
+    from paper_2501_04340_amd.warmstart import RingWarmStart
+    from workloads import configs
+
+    torch.cuda.set_device(0)
+    prob = configs.ring576()
+    t0 = time.perf_counter()
+    S = Solver(prob)
+    log(f"host assembly {time.perf_counter() - t0:.1f}s sizes {S.sizes()}")
+    W = RingWarmStart(S, prob, window=2, hidden=args.nn_hidden, layers=2)
+
+    def draw(i):
+        nu, cur = configs.ring_coefficients(configs.ring_sample_seed(i))
+        return nu, configs.ring_load_scale(cur)
+
+    n_train, n_test = args.ring_train, args.ring_test
+    t0 = time.perf_counter()
+    X, Cc, T, gst = W.generate([draw(i) for i in range(n_train)], rtol=1e-10, log=log)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    losses = W.fit(X, Cc, T, epochs=args.nn_epochs, lr=args.nn_lr, batch=256, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"data {t_gen:.1f}s, training {t_train:.1f}s, loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    W.attach()
+    variants = {"plain_cold": (PREC_FP64, False), "plain_warm": (PREC_FP64, True),
+                "mixed_cold": (PREC_MIXED, False), "mixed_warm": (PREC_MIXED, True)}
+    res = {k: {"tts_ms": [], "iters": [], "r0": [], "fallback": 0, "applies": 0, "pcg_s": 0.0} for k in variants}
+    lam_err = []
+    for i in range(n_train, n_train + n_test):
+        nu, scale = draw(i)
+        S.set_coefficients(nu, scale)
+        lam_ref = None
+        for name, (prec, warm) in variants.items():
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            S.factor(precision=prec)
+            _, st = S.solve(rtol=args.rtol, warm_start=warm)
+            torch.cuda.synchronize()
+            r = res[name]
+            r["tts_ms"].append((time.perf_counter() - t1) * 1e3)
+            r["iters"].append(st["iters"])
+            r["r0"].append(st["rel_residual0"])
+            r["fallback"] += int(st["warm_start"] == -1)
+            r["applies"] += st["f_applies"]
+            r["pcg_s"] += st["t_pcg_s"]
+            lam = S.lambda_()
+            if lam_ref is None:
+                lam_ref = lam
+            else:
+                lam_err.append(float(np.linalg.norm(lam - lam_ref) / np.linalg.norm(lam_ref)))
+        if (i - n_train + 1) % 16 == 0:
+            log(f"held-out {i - n_train + 1}/{n_test}: " + ", ".join(
+                f"{k} {np.median(v['tts_ms']):.1f}ms/{np.mean(v['iters']):.1f}it" for k, v in res.items()))
+    S.factor(precision=PREC_FP64)
+    summ = {}
+    for k, v in res.items():
+        summ[k] = {"tts_ms_p50": float(np.median(v["tts_ms"])), "tts_ms_p99": float(np.percentile(v["tts_ms"], 99)),
+                   "pcg_iters_mean": float(np.mean(v["iters"])), "rel_residual0_median": float(np.median(v["r0"])),
+                   "fallbacks": v["fallback"], "f_applies_per_s": v["applies"] / v["pcg_s"] if v["pcg_s"] else None}
+    base = summ["plain_cold"]["tts_ms_p50"]
+    for k in summ:
+        summ[k]["speedup_vs_plain_cold"] = base / summ[k]["tts_ms_p50"]
+    ms = summ["mixed_warm"]["tts_ms_p50"]
+    out = {
+        "metric": "IETI-DP time-to-solution and F·λ applies/s at rtol 1e-8, mixed+warm vs plain FP64",
+        "value": 1e3 / ms, "unit": "solves/s", "n_gpus": 1, "steps": n_test, "warmup": 0, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["ring576"], "variant": "mixed + warm start, held-out draws",
+                   "n_g": S.n_global, "n_sub": S.n_sub, "m_r": S.m_r, "n_gp": S.n_gp, "rtol": args.rtol},
+        "variants": summ,
+        "warm_start": {"train_solves": n_train, "held_out": n_test, "data_s": t_gen, "train_s": t_train,
+                       "epochs": args.nn_epochs, "hidden": args.nn_hidden, "params": W.net.n_params,
+                       "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                       "loss_curve": [float(x) for x in losses[:: max(1, len(losses) // 20)]],
+                       "lambda_rel_diff_vs_plain_cold_max": max(lam_err) if lam_err else None},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +227,13 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 3 device-to-device copies of MIB MiB (HBM counter calibration) and exit")
+    ap.add_argument("--ring-train", type=int, default=512)
+    ap.add_argument("--ring-test", type=int, default=64)
+    ap.add_argument("--nn-epochs", type=int, default=300)
+    ap.add_argument("--nn-hidden", type=int, default=256)
+    ap.add_argument("--nn-lr", type=float, default=1e-3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU sharding "
@@ -133,6 +246,17 @@ def main():
     from workloads import configs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20)
+        x = torch.ones(n, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": n, "launches": 3}), flush=True)
+        return
+    if args.workload == "ring576":
+        return ring_warm_start(args)
     torch.cuda.set_device(0)
     prob = configs.make_config(args.workload)
     t0 = time.perf_counter()
@@ -172,8 +296,9 @@ def main():
     upd_ms_total, gemv_ms_total = kt["update_ms"], kt["gemv_ms"]
     if gemv_ms_total >= upd_ms_total:
         achieved = kt["gemv_bytes"] / (gemv_ms * 1e-3) / 1e9
-        roof = {"kernel": "k_gemv<double>", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        roof = {"kernel": "k_gemv<double> (autotuned shape)", "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_gemv_traffic(),
                 "avg_launch_ms": gemv_ms, "bytes_per_launch": kt["gemv_bytes"]}
     else:
         flops_per_task = 2.0 * 64 ** 3
@@ -183,6 +308,8 @@ def main():
         roof = {"kernel": "k_update", "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
                 "avg_launch_ms": avg, "flops_per_launch": per_launch}
+    chosen, tune_ms = S.gemv_tuning()
+    log(f"GEMV autotuner (FP64 blocks): chosen shape {chosen[0]}, ms per shape {np.round(tune_ms[0], 4).tolist()}")
     # mixed-precision variant of the same step (FP32-stored interface blocks in
     # the inner PCG, outer refinement on the FP64 residual)
     from paper_2501_04340_amd.ietidp import PREC_FP64, PREC_MIXED
@@ -197,6 +324,7 @@ def main():
         mstats.append(st_m)
     torch.cuda.synchronize()
     ms_mixed = (time.perf_counter() - t0m) * 1e3 / args.steps
+    chosen32, tune_ms32 = S.gemv_tuning()
     S.factor(precision=PREC_FP64)
     log(f"mixed: {ms_mixed:.2f} ms/step, iters {mstats[-1]['iters']}, outer {mstats[-1]['outer_iters']}, "
         f"rel residual {mstats[-1]['rel_residual']:.2e}")
@@ -223,6 +351,8 @@ def main():
         "rel_residual": float(stats[-1]["rel_residual"]),
         "factor_tflops": info["flops"] / (factor_ms * 1e-3) / 1e12,
         "roofline": roof,
+        "gemv_autotune": {"fp64_shape": int(chosen[0]), "fp64_ms": [float(x) for x in tune_ms[0]],
+                          "fp32_shape": int(chosen32[1]), "fp32_ms": [float(x) for x in tune_ms32[1]]},
         "variants": {
             "plain_fp64": {"tts_ms": ms_per_step, "pcg_iters": iters},
             "mixed_fp32_blocks_fp64_refinement": {

@@ -91,7 +91,8 @@ typedef struct {
                           interface blocks for the inner PCG of an FP64 iterative refinement */
   int32_t tile;        /* factor tile size: 0 = default (64) */
   int32_t ordering;    /* 0 = nested dissection of r_V (default), 1 = natural order */
-  int32_t reserved;
+  int32_t gemv_variant; /* 0 = autotune the interface GEMV launch shape on the first factorisation
+                           of the handle (kept afterwards); 1..12 = use shape gemv_variant - 1 */
   void* hip_stream;    /* hipStream_t to run on; NULL = the library's own stream */
 } ieti_factor_opts;
 
@@ -211,6 +212,15 @@ int ieti_get_plan_info(const ieti_handle* h, double* info);
  * factorisation; while enabled, solves launch PCG kernels directly instead of
  * replaying the captured graph.  enable = 0 stops recording. */
 int ieti_set_profiling(ieti_handle* h, int32_t enable);
+
+/* Launch shape of the interface GEMV chosen for FP64 (variant[0]) and FP32
+ * (variant[1]) blocks, -1 if not chosen yet, and the autotuner's average
+ * launch time in ms of each of the 12 shapes (timed alternating the
+ * operator and preconditioner blocks), ms[12 * precision + shape]
+ * (0 if not timed).  Shape s: 4 waves of rows_per_wave = {2,4,8}[s / 4]
+ * rows, (s / 2) % 2 + 1 16-byte vectors in flight per lane and row,
+ * non-temporal loads if s is odd.  Either argument may be NULL. */
+int ieti_get_gemv_tuning(const ieti_handle* h, int32_t* variant, float* ms);
 
 /* times[0..5] = {GEMV launches, GEMV total ms, update launches, update total
  * ms, update tasks executed, interface-block bytes read per GEMV launch}. */

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -37,13 +38,17 @@ struct ieti_handle {
   int device = -1;
   int64_t max_ld = 0;
   int nblk = 0;
-  std::vector<int64_t> gemv_task_h;
+  std::vector<int64_t> gemv_task_h[3];  // GEMV task lists for 8, 16 and 32 rows per workgroup
   // device buffers
   DBuf<double> pool, inv, scatter_val, S, Sinv, Phi, SPi, Spi_glob, G, H, Ht, I_sign, b_aug0, y;
   DBuf<int64_t> scatter_dst, potrf, trsm, upd, upd_pair, copyS, xsinv, xphi, xspi, fdiag, ffull, ffull_pair, fr, fr_pair;
   DBuf<int64_t> bdiag, bupd, bupd_pair;
   DBuf<int64_t> spi_ptr, spi_src, row_src, I_aug, A_aug, slot_phi_row, dsrc_ptr, dsrc_idx, krp_ptr, krp_pos;
-  DBuf<int64_t> out_src, out_edge, primal_edges, gemv_task;
+  DBuf<int64_t> out_src, out_edge, primal_edges;
+  DBuf<int64_t> gemv_tasks[3];
+  int ngemv_r[3] = {0, 0, 0};
+  int gvar[2] = {-1, -1};                              // GEMV launch shape for FP64 / FP32 blocks (-1 = untuned)
+  float gtime[2][ieti::dev::GEMV_VARIANTS] = {};      // autotuner: ms per launch of each shape
   DBuf<int32_t> I_row, I_sub, glob2loc, krp_col;
   DBuf<double> krp_val;
   DBuf<double> lam, r, z, p, q, v, b, e, dtil, w, t, pglob, part, scal, aout, tmp;
@@ -51,7 +56,6 @@ struct ieti_handle {
   DBuf<double> lam_acc, rtrue;            // outer multipliers and FP64 residual (mixed precision)
   DBuf<float> S32, Sinv32;                // FP32 copies of S_rIrI and (K_rr^{-1})_II (mixed precision)
   bool mixed = false;
-  int ngemv = 0;
   hipGraph_t graph = nullptr, graph32 = nullptr;
   hipGraphExec_t graph_exec = nullptr, graph_exec32 = nullptr;
 
@@ -95,7 +99,8 @@ struct ieti_handle {
     for (auto* d : ds) d->release();
     DBuf<int64_t>* is[] = {&scatter_dst, &potrf, &trsm, &upd, &upd_pair, &copyS, &xsinv, &xphi, &xspi, &fdiag,
                            &ffull, &ffull_pair, &fr, &fr_pair, &bdiag, &bupd, &bupd_pair, &spi_ptr, &spi_src, &row_src, &I_aug, &A_aug, &slot_phi_row, &dsrc_ptr,
-                           &dsrc_idx, &krp_ptr, &krp_pos, &out_src, &out_edge, &primal_edges, &gemv_task};
+                           &dsrc_idx, &krp_ptr, &krp_pos, &out_src, &out_edge, &primal_edges,
+                           &gemv_tasks[0], &gemv_tasks[1], &gemv_tasks[2]};
     for (auto* d : is) d->release();
     I_row.release();
     I_sub.release();
@@ -212,17 +217,22 @@ int upload(ieti_handle* h) {
   // per interface slot: start of its row in Phi
   std::vector<int64_t> phirow(P.I_total, 0);
   h->max_ld = 0;
-  h->gemv_task_h.clear();
+  for (auto& v : h->gemv_task_h) v.clear();
   for (const auto& sp : P.sub) {
     for (int64_t t = 0; t < sp.nIp; ++t) phirow[sp.I_off + t] = sp.Phi_off + t * sp.nPp;
     h->max_ld = std::max(h->max_ld, sp.nIp);
-    for (int64_t r0 = 0; r0 < sp.nIp; r0 += ieti::dev::GEMV_ROWS)
-      h->gemv_task_h.insert(h->gemv_task_h.end(), {sp.S_off + r0 * sp.nIp, sp.I_off + r0,
-                                                   std::min<int64_t>(ieti::dev::GEMV_ROWS, sp.nIp - r0), sp.nIp,
-                                                   sp.I_off});
+    for (int ri = 0; ri < 3; ++ri) {
+      const int64_t rows = 8 << ri;
+      for (int64_t r0 = 0; r0 < sp.nIp; r0 += rows)
+        h->gemv_task_h[ri].insert(h->gemv_task_h[ri].end(), {sp.S_off + r0 * sp.nIp, sp.I_off + r0,
+                                                             std::min<int64_t>(rows, sp.nIp - r0), sp.nIp, sp.I_off});
+    }
   }
   UP(slot_phi_row, phirow);
-  UP(gemv_task, h->gemv_task_h);
+  for (int ri = 0; ri < 3; ++ri) {
+    UP(gemv_tasks[ri], h->gemv_task_h[ri]);
+    h->ngemv_r[ri] = int(h->gemv_task_h[ri].size() / 5);
+  }
   // d~ assembly sources: for each global primal, the augmented indices of its local copies
   {
     std::vector<std::vector<int64_t>> src(M.n_gp);
@@ -258,12 +268,11 @@ int upload(ieti_handle* h) {
   for (auto* d : vecs_g)
     if ((rc = dalloc(*d, gg))) return rc;
   if ((rc = dalloc(h->part, 3 * int64_t(h->nblk)))) return rc;
-  h->ngemv = int(h->gemv_task_h.size() / 5);
   if ((rc = dalloc(h->xgp, std::max<int64_t>(P.I_total, 1)))) return rc;
   if ((rc = dalloc(h->xgr, std::max<int64_t>(P.I_total, 1)))) return rc;
   HIP_TRY(hipMemset(h->xgp.ptr, 0, h->xgp.n * sizeof(double)));
   HIP_TRY(hipMemset(h->xgr.ptr, 0, h->xgr.n * sizeof(double)));
-  if ((rc = dalloc(h->part_g, std::max(h->ngemv, 1)))) return rc;
+  if ((rc = dalloc(h->part_g, std::max(h->ngemv_r[0], 1)))) return rc;
   if ((rc = dalloc(h->part_t, std::max<int64_t>(int64_t(h->nblk) * n_gp, 1)))) return rc;
   if ((rc = dalloc(h->lam_acc, mm))) return rc;
   if ((rc = dalloc(h->rtrue, mm))) return rc;
@@ -340,9 +349,15 @@ int check_launch() {
   return IETI_OK;
 }
 
+// GEMV launch shape in use for FP64 (fp32 = 0) or FP32 (1) blocks, its task list and task count
+int gvariant(const ieti_handle* h, int fp32) { return h->gvar[fp32] >= 0 ? h->gvar[fp32] : ieti::dev::GEMV_DEFAULT; }
+const int64_t* gtasks(const ieti_handle* h, int fp32) { return h->gemv_tasks[gvariant(h, fp32) / 4].ptr; }
+int gcount(const ieti_handle* h, int fp32) { return h->ngemv_r[gvariant(h, fp32) / 4]; }
+
 // Interface GEMV over all subdomains, timed with launch events when profiling.
 template <typename MT>
 void gemv_timed(ieti_handle* h, const MT* M, const double* xg, double* v, const int* done = nullptr) {
+  const int fp32 = std::is_same<MT, float>::value ? 1 : 0;
   hipEvent_t a = nullptr, b = nullptr;
   size_t slot = SIZE_MAX;
   if (h->profiling) {
@@ -351,7 +366,8 @@ void gemv_timed(ieti_handle* h, const MT* M, const double* xg, double* v, const 
     b = next_event(h);
     if (!a || !b) a = b = nullptr;
   }
-  ieti::dev::gemv(M, h->gemv_task.ptr, h->ngemv, h->max_ld, xg, v, h->part_g.ptr, done, h->stream, a, b);
+  ieti::dev::gemv(M, gtasks(h, fp32), gcount(h, fp32), h->max_ld, xg, v, h->part_g.ptr, done, h->stream,
+                  gvariant(h, fp32), a, b);
   if (a) h->ev_marks.emplace_back(0, slot);
 }
 
@@ -389,17 +405,80 @@ void pcg_iteration(ieti_handle* h, int par, const MT* Sinv, const MT* S) {
   int* perr = h->flags.ptr + 3;
   double* part_rr = h->part.ptr + h->nblk;
   const double* H = M.n_gp > 0 ? h->H.ptr : nullptr;
+  const int ng = gcount(h, std::is_same<MT, float>::value ? 1 : 0);
   gemv_timed(h, Sinv, h->xgp.ptr, h->v.ptr, done);
-  D::pcg_F(h->v.ptr, h->row_src.ptr, m_r, H, h->part_t.ptr, M.n_gp, h->nblk, h->part_g.ptr, h->ngemv, h->p.ptr,
+  D::pcg_F(h->v.ptr, h->row_src.ptr, m_r, H, h->part_t.ptr, M.n_gp, h->nblk, h->part_g.ptr, ng, h->p.ptr,
            h->lam.ptr, h->r.ptr, h->xgr.ptr, part_rr, h->scal.ptr, par, done, perr, s);
   gemv_timed(h, S, h->xgr.ptr, h->v.ptr, done);
-  D::pcg_M(h->v.ptr, h->row_src.ptr, m_r, H, M.n_gp, h->part_g.ptr, h->ngemv, part_rr, h->nblk, h->p.ptr, h->z.ptr,
+  D::pcg_M(h->v.ptr, h->row_src.ptr, m_r, H, M.n_gp, h->part_g.ptr, ng, part_rr, h->nblk, h->p.ptr, h->z.ptr,
            h->xgp.ptr, h->part_t.ptr, h->scal.ptr, par, done, iters, 0, s);
 }
 
 void pcg_iteration_prec(ieti_handle* h, int par, bool fp32) {
   if (fp32) pcg_iteration<float>(h, par, h->Sinv32.ptr, h->S32.ptr);
   else pcg_iteration<double>(h, par, h->Sinv.ptr, h->S.ptr);
+}
+
+void drop_graphs(ieti_handle* h) {
+  for (hipGraphExec_t* g : {&h->graph_exec, &h->graph_exec32})
+    if (*g) {
+      (void)hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
+  for (hipGraph_t* g : {&h->graph, &h->graph32})
+    if (*g) {
+      (void)hipGraphDestroy(*g);
+      *g = nullptr;
+    }
+}
+
+// Autotuner of the interface GEMV: every launch shape is timed on the
+// handle's own blocks, alternating the operator and preconditioner blocks as
+// the PCG does (so the caches see the same working set), 2 warm-up and 5
+// timed pairs each, HIP events on the solve stream; the fastest is kept.
+// Runs once per handle and precision, after the first factorisation, so
+// later solves are repeatable.
+template <typename MT>
+int tune_gemv(ieti_handle* h, const MT* Ma, const MT* Mb, int fp32) {
+  namespace D = ieti::dev;
+  hipStream_t s = h->stream;
+  float best = 1e30f;
+  int bv = D::GEMV_DEFAULT;
+  for (int v = 0; v < D::GEMV_VARIANTS; ++v) {
+    const int ri = v / 4;
+    auto launch = [&]() {
+      D::gemv(Ma, h->gemv_tasks[ri].ptr, h->ngemv_r[ri], h->max_ld, h->xgp.ptr, h->v.ptr, h->part_g.ptr, nullptr, s, v);
+      D::gemv(Mb, h->gemv_tasks[ri].ptr, h->ngemv_r[ri], h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, s, v);
+    };
+    launch();
+    launch();
+    HIP_TRY(hipEventRecord(h->ev0, s));
+    for (int k = 0; k < 5; ++k) launch();
+    HIP_TRY(hipEventRecord(h->ev1, s));
+    HIP_TRY(hipEventSynchronize(h->ev1));
+    int rc = check_launch();
+    if (rc) return rc;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->gtime[fp32][v] = ms / 10.f;
+    if (ms < best) {
+      best = ms;
+      bv = v;
+    }
+  }
+  if (h->gvar[fp32] != bv) drop_graphs(h);
+  h->gvar[fp32] = bv;
+  return IETI_OK;
+}
+
+int choose_gemv(ieti_handle* h, int forced, int fp32) {
+  if (forced > 0) {
+    if (h->gvar[fp32] != forced - 1) drop_graphs(h);
+    h->gvar[fp32] = forced - 1;
+    return IETI_OK;
+  }
+  if (h->gvar[fp32] >= 0 || h->plan.S_elems == 0) return IETI_OK;
+  return fp32 ? tune_gemv(h, h->Sinv32.ptr, h->S32.ptr, 1) : tune_gemv(h, h->Sinv.ptr, h->S.ptr, 0);
 }
 
 // Capture two PCG iterations (parities 0 and 1) as one graph per precision.
@@ -547,9 +626,14 @@ int run_pcg(ieti_handle* h, double tol2, double rr0, int maxit, int every, bool 
   HIP_TRY(hipMemcpyAsync(h->scal.ptr, sc, sizeof(sc), hipMemcpyHostToDevice, s));
   // z_0 = M r_0, p_0 = z_0, rz_0, partials of H^T p_0
   D::gather_rows(h->r.ptr, h->row_src.ptr, m_r, h->xgr.ptr, s);
-  if (fp32) D::gemv(h->S32.ptr, h->gemv_task.ptr, h->ngemv, h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, s);
-  else D::gemv(h->S.ptr, h->gemv_task.ptr, h->ngemv, h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, s);
-  D::pcg_M(h->v.ptr, h->row_src.ptr, m_r, M.n_gp > 0 ? h->H.ptr : nullptr, M.n_gp, h->part_g.ptr, h->ngemv, part_rr,
+  const int pf = fp32 ? 1 : 0;
+  if (fp32)
+    D::gemv(h->S32.ptr, gtasks(h, pf), gcount(h, pf), h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, s,
+            gvariant(h, pf));
+  else
+    D::gemv(h->S.ptr, gtasks(h, pf), gcount(h, pf), h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, s,
+            gvariant(h, pf));
+  D::pcg_M(h->v.ptr, h->row_src.ptr, m_r, M.n_gp > 0 ? h->H.ptr : nullptr, M.n_gp, h->part_g.ptr, gcount(h, pf), part_rr,
            h->nblk, h->p.ptr, h->z.ptr, h->xgp.ptr, h->part_t.ptr, h->scal.ptr, 0, done, iters, 1, s);
   if (use_graph) {
     int rc = capture_graph(h, fp32);
@@ -833,6 +917,10 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
     return fail(IETI_ERR_NOT_SPD, "non-positive pivot in the local factorisation of subdomain " +
                                       std::to_string(h->flags_h[0] - 1));
   if (h->flags_h[4] > 0) return fail(IETI_ERR_NOT_SPD, "coarse matrix is not positive definite");
+  const int forced = opts ? opts->gemv_variant : 0;
+  if (forced < 0 || forced > D::GEMV_VARIANTS) return fail(IETI_ERR_INVALID_ARG, "gemv_variant out of range");
+  if ((rc = choose_gemv(h, forced, 0))) return rc;
+  if (h->mixed && (rc = choose_gemv(h, forced, 1))) return rc;
   h->factored = true;
   return IETI_OK;
 }
@@ -960,6 +1048,18 @@ int ieti_get_plan_info(const ieti_handle* h, double* info) {
   const double v[10] = {double(P.pool_elems), double(P.S_elems), P.flops, P.dense_flops, double(P.n_steps),
                         double(P.n_update_tasks), sum_nI2, double(P.I_total), max_ld, double(P.T)};
   std::memcpy(info, v, sizeof(v));
+  return IETI_OK;
+}
+
+int ieti_get_gemv_tuning(const ieti_handle* h, int32_t* variant, float* ms) {
+  if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
+  if (variant) {
+    variant[0] = h->gvar[0];
+    variant[1] = h->gvar[1];
+  }
+  if (ms)
+    for (int f = 0; f < 2; ++f)
+      for (int v = 0; v < ieti::dev::GEMV_VARIANTS; ++v) ms[f * ieti::dev::GEMV_VARIANTS + v] = h->gtime[f][v];
   return IETI_OK;
 }
 

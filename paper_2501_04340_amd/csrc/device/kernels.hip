@@ -345,22 +345,27 @@ __global__ void k_gather_rows(const double* x, const int64_t* row_src, int64_t m
 // Batched dense GEMV over the per-subdomain interface blocks, v = M_k xg_k
 // for every interface slot, plus one partial of sum_slot xg * v per block.
 // task: [matrix row start, first slot of the rows, nrows, ld (= padded n_I),
-// first slot of the subdomain].  Each wave owns GEMV_RPW rows and streams
-// them with 16-byte loads; the gathered vector is read from L2/L1.
-constexpr int GEMV_RPW = 4;
+// first slot of the subdomain].  The subdomain's slice of xg is staged in
+// LDS; each wave owns RPW rows at a time and streams them with 16-byte
+// loads, U vectors per lane in flight per row, optionally non-temporal (the
+// blocks are read once per application and do not fit the caches).  Every
+// variant sums each row in the same order, so results are identical; only
+// the per-block partials of xg.v are grouped differently.
 
 // 16-byte vectors of stored matrix entries (FP64: 2 entries, FP32: 4)
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf4 __attribute__((ext_vector_type(4)));
 template <typename MT>
 struct Vec16;
 template <>
 struct Vec16<double> {
-  using T = double2;
+  using T = nd2;
   static constexpr int N = 2;
   __device__ static inline double dot(const T& m, const double* x) { return m.x * x[0] + m.y * x[1]; }
 };
 template <>
 struct Vec16<float> {
-  using T = float4;
+  using T = nf4;
   static constexpr int N = 4;
   __device__ static inline double dot(const T& m, const double* x) {
     return (double(m.x) * x[0] + double(m.y) * x[1]) + (double(m.z) * x[2] + double(m.w) * x[3]);
@@ -368,11 +373,12 @@ struct Vec16<float> {
 };
 
 // Matrix entries stored as MT (double or float), vector and accumulation in FP64.
-template <typename MT>
+template <typename MT, int RPW, int U, bool NT>
 __global__ __launch_bounds__(256) void k_gemv(const MT* M, const int64_t* task, const double* xg, double* v,
                                               double* part, const int* done) {
   if (done && *done) return;
   using V = Vec16<MT>;
+  using T = typename V::T;
   extern __shared__ __align__(16) double xs[];
   __shared__ double red[4];
   const int64_t* tk = task + 5 * blockIdx.x;
@@ -386,22 +392,37 @@ __global__ __launch_bounds__(256) void k_gemv(const MT* M, const int64_t* task, 
   __syncthreads();
   const int64_t nvec = ld / V::N;
   double dsum = 0.0;
-  for (int64_t rb = w * GEMV_RPW; rb < nrows; rb += 4 * GEMV_RPW) {
-    double acc[GEMV_RPW];
+  for (int64_t rb = w * RPW; rb < nrows; rb += 4 * RPW) {
+    double acc[RPW];
 #pragma unroll
-    for (int r = 0; r < GEMV_RPW; ++r) acc[r] = 0.0;
-    for (int64_t j = lane; j < nvec; j += 64) {
-      const double* xv = xs + V::N * j;
+    for (int r = 0; r < RPW; ++r) acc[r] = 0.0;
+    for (int64_t j0 = lane; j0 < nvec; j0 += 64 * U) {
+      T mv[U][RPW];
 #pragma unroll
-      for (int r = 0; r < GEMV_RPW; ++r) {
-        if (rb + r < nrows) {
-          const typename V::T mv = reinterpret_cast<const typename V::T*>(M + mrow0 + (rb + r) * ld)[j];
-          acc[r] += V::dot(mv, xv);
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          const int64_t j = j0 + 64 * u;
+          if (j < nvec && rb + r < nrows) {
+            const T* row = reinterpret_cast<const T*>(M + mrow0 + (rb + r) * ld);
+            if constexpr (NT) mv[u][r] = __builtin_nontemporal_load(row + j);
+            else mv[u][r] = row[j];
+          } else {
+            mv[u][r] = T(0);
+          }
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = j0 + 64 * u;
+        if (j < nvec) {
+          const double* xv = xs + V::N * j;
+#pragma unroll
+          for (int r = 0; r < RPW; ++r) acc[r] += V::dot(mv[u][r], xv);
         }
       }
     }
 #pragma unroll
-    for (int r = 0; r < GEMV_RPW; ++r) {
+    for (int r = 0; r < RPW; ++r) {
       const double sres = wave_sum(acc[r]);
       if (lane == 0 && rb + r < nrows) {
         v[slot0 + rb + r] = sres;
@@ -730,24 +751,49 @@ void gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* x
   if (m_r <= 0) return;
   hipLaunchKernelGGL(k_gather_rows, dim3((m_r + 255) / 256), dim3(256), 0, s, x, row_src, m_r, xg);
 }
+GemvShape gemv_shape(int variant) {
+  static const int rpw[3] = {2, 4, 8};
+  if (variant < 0 || variant >= GEMV_VARIANTS) variant = GEMV_DEFAULT;
+  return GemvShape{rpw[variant / 4], 1 + (variant / 2) % 2, variant % 2};
+}
+
+template <typename MT, int RPW, int U, bool NT>
+void gemv_launch(const MT* M, const int64_t* task, int64_t ntask, size_t lds, const double* xg, double* v,
+                 double* part, const int* done, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  if (ev_start)
+    hipExtLaunchKernelGGL((k_gemv<MT, RPW, U, NT>), dim3(ntask), dim3(256), lds, s, ev_start, ev_stop, 0, M, task,
+                          xg, v, part, done);
+  else
+    hipLaunchKernelGGL((k_gemv<MT, RPW, U, NT>), dim3(ntask), dim3(256), lds, s, M, task, xg, v, part, done);
+}
+
+template <typename MT, int RPW>
+void gemv_dispatch_u(int u, int nt, const MT* M, const int64_t* task, int64_t ntask, size_t lds, const double* xg,
+                     double* v, double* part, const int* done, hipStream_t s, hipEvent_t a, hipEvent_t b) {
+  if (u == 1 && !nt) gemv_launch<MT, RPW, 1, false>(M, task, ntask, lds, xg, v, part, done, s, a, b);
+  else if (u == 1) gemv_launch<MT, RPW, 1, true>(M, task, ntask, lds, xg, v, part, done, s, a, b);
+  else if (!nt) gemv_launch<MT, RPW, 2, false>(M, task, ntask, lds, xg, v, part, done, s, a, b);
+  else gemv_launch<MT, RPW, 2, true>(M, task, ntask, lds, xg, v, part, done, s, a, b);
+}
+
 template <typename MT>
 void gemv_impl(const MT* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
-               double* part, const int* done, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+               double* part, const int* done, hipStream_t s, int variant, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (ntask <= 0) return;
   const size_t lds = size_t(max_ld) * sizeof(double);
-  if (ev_start)
-    hipExtLaunchKernelGGL(k_gemv<MT>, dim3(ntask), dim3(256), lds, s, ev_start, ev_stop, 0, M, task, xg, v, part,
-                          done);
-  else
-    hipLaunchKernelGGL(k_gemv<MT>, dim3(ntask), dim3(256), lds, s, M, task, xg, v, part, done);
+  const GemvShape g = gemv_shape(variant);
+  if (g.rpw == 2) gemv_dispatch_u<MT, 2>(g.unroll, g.nt, M, task, ntask, lds, xg, v, part, done, s, ev_start, ev_stop);
+  else if (g.rpw == 4)
+    gemv_dispatch_u<MT, 4>(g.unroll, g.nt, M, task, ntask, lds, xg, v, part, done, s, ev_start, ev_stop);
+  else gemv_dispatch_u<MT, 8>(g.unroll, g.nt, M, task, ntask, lds, xg, v, part, done, s, ev_start, ev_stop);
 }
 void gemv(const double* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
-          double* part, const int* done, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  gemv_impl(M, task, ntask, max_ld, xg, v, part, done, s, ev_start, ev_stop);
+          double* part, const int* done, hipStream_t s, int variant, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  gemv_impl(M, task, ntask, max_ld, xg, v, part, done, s, variant, ev_start, ev_stop);
 }
 void gemv(const float* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
-          double* part, const int* done, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  gemv_impl(M, task, ntask, max_ld, xg, v, part, done, s, ev_start, ev_stop);
+          double* part, const int* done, hipStream_t s, int variant, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  gemv_impl(M, task, ntask, max_ld, xg, v, part, done, s, variant, ev_start, ev_stop);
 }
 void to_float(const double* in, float* out, int64_t n, hipStream_t s) {
   if (n <= 0) return;

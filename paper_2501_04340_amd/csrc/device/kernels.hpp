@@ -41,12 +41,23 @@ void tri_small(const double* L, int64_t n, const double* in, double* out, bool t
 void gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg, hipStream_t s);
 // v[slot] = (M_k xg_k)[slot] for every interface slot; part[block] = sum xg.v over the block's rows.
 // task [matrix row start, first slot, nrows, ld, first slot of the subdomain]; ev_* may be null.
-constexpr int GEMV_ROWS = 16;  // matrix rows per workgroup (4 waves x 4 rows)
+// Launch shapes: 4 waves, each owning rpw rows at a time (4 rpw rows per
+// workgroup = per task), unroll vectors in flight per lane and row, nt =
+// non-temporal loads.  Variant index = 4 * (rpw index in {2,4,8}) + 2 * (unroll - 1) + nt.
+struct GemvShape {
+  int rpw, unroll, nt;
+};
+constexpr int GEMV_VARIANTS = 12;
+constexpr int GEMV_DEFAULT = 4;  // rpw 4, unroll 1, cached loads
+GemvShape gemv_shape(int variant);
+inline int gemv_rows(int variant) { return 4 * gemv_shape(variant).rpw; }
 // Matrix entries stored in FP64 or FP32; vectors and accumulation in FP64.
 void gemv(const double* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
-          double* part, const int* done, hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+          double* part, const int* done, hipStream_t s, int variant, hipEvent_t ev_start = nullptr,
+          hipEvent_t ev_stop = nullptr);
 void gemv(const float* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
-          double* part, const int* done, hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+          double* part, const int* done, hipStream_t s, int variant, hipEvent_t ev_start = nullptr,
+          hipEvent_t ev_stop = nullptr);
 void to_float(const double* in, float* out, int64_t n, hipStream_t s);
 // out[c] = sum_row Ht[c][row] * x[row]
 void coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x, double* out, hipStream_t s);

@@ -45,7 +45,7 @@ class FactorOpts(C.Structure):
         ("precision", C.c_int32),
         ("tile", C.c_int32),
         ("ordering", C.c_int32),
-        ("reserved", C.c_int32),
+        ("gemv_variant", C.c_int32),
         ("hip_stream", C.c_void_p),
     ]
 
@@ -110,7 +110,7 @@ EXPORTS = [
     "ieti_get_lambda", "ieti_get_plan_info", "ieti_set_profiling", "ieti_get_kernel_times", "ieti_destroy",
     "ieti_last_error", "ieti_set_coefficients", "ieti_set_warm_start", "ieti_nn_create", "ieti_nn_num_params",
     "ieti_nn_set_params", "ieti_nn_get_params", "ieti_nn_set_data", "ieti_nn_loss_grad", "ieti_nn_train",
-    "ieti_nn_predict", "ieti_nn_destroy",
+    "ieti_nn_predict", "ieti_nn_destroy", "ieti_get_gemv_tuning",
 ]
 
 
@@ -157,6 +157,7 @@ def load_library():
     lib.ieti_destroy.argtypes = [C.c_void_p]
     lib.ieti_destroy.restype = None
     lib.ieti_last_error.restype = C.c_char_p
+    lib.ieti_get_gemv_tuning.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_float)]
     lib.ieti_set_coefficients.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
     lib.ieti_set_warm_start.argtypes = [C.c_void_p, C.c_void_p, P(WarmLayout)]
     lib.ieti_nn_create.argtypes = [P(NNArch), P(C.c_void_p)]
@@ -273,11 +274,12 @@ class Solver:
         K = sp.csr_matrix((values[:nnz.value], indices[:nnz.value], indptr), shape=(n.value, n.value))
         return K, load[:n.value]
 
-    def factor(self, precision=PREC_FP64, ordering=0, stream=None):
+    def factor(self, precision=PREC_FP64, ordering=0, stream=None, gemv_variant=None):
         o = FactorOpts()
         o.precision = precision
         o.tile = 0
         o.ordering = ordering
+        o.gemv_variant = 0 if gemv_variant is None else int(gemv_variant) + 1
         o.hip_stream = stream
         _check(self.lib, self.lib.ieti_factor(self.h, C.byref(o)))
 
@@ -371,6 +373,13 @@ class Solver:
         keys = ["pool_elems", "S_elems", "flops", "dense_flops", "n_steps", "n_update_tasks", "sum_nI2",
                 "I_total", "max_ld", "tile"]
         return dict(zip(keys, v.tolist()))
+
+    def gemv_tuning(self):
+        """(chosen shape for FP64 and FP32 blocks, ms per shape [2, 12]) of the GEMV autotuner."""
+        v = np.zeros(2, np.int32)
+        ms = np.zeros(24, np.float32)
+        _check(self.lib, self.lib.ieti_get_gemv_tuning(self.h, _ptr(v, C.c_int32), _ptr(ms, C.c_float)))
+        return v.tolist(), ms.reshape(2, 12)
 
     def set_profiling(self, enable=True):
         _check(self.lib, self.lib.ieti_set_profiling(self.h, 1 if enable else 0))

@@ -160,3 +160,22 @@ def test_mixed_precision_meets_the_fp64_residual(runs, name):
     a_mono = O.monolithic()
     assert b_error(O.space, a, a_ref=a_mono)[1] <= 1e-9
     S.factor(precision=PREC_FP64)
+
+
+def test_gemv_launch_shapes_agree_bitwise(runs):
+    """Every GEMV launch shape sums each row in the same order: the operator
+    and preconditioner applications are bitwise identical across shapes, and
+    the autotuner timed every shape."""
+    prob, S, O = _get(runs, "cube64_small")
+    chosen, ms = S.gemv_tuning()
+    assert 0 <= chosen[0] < 12 and np.all(ms[0] > 0)
+    x = np.random.default_rng(5).standard_normal(S.m_r)
+    ref = None
+    for v in range(12):
+        S.factor(gemv_variant=v)
+        assert S.gemv_tuning()[0][0] == v
+        out = (S.apply_F(x), S.apply_M(x))
+        if ref is None:
+            ref = out
+        assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
+    S.factor(gemv_variant=chosen[0])
