@@ -57,65 +57,103 @@ __global__ void k_scatter(double* pool, const int64_t* dst, const double* val, i
     pool[dst[i]] = val[i];
 }
 
-// Cholesky of one 64x64 diagonal tile in LDS followed by the inverse of the
-// lower factor, written to `inv`.  Thread t owns row t/4 and columns
-// t%4 + 4m (m = 0..15); each column step reads the pivot column, then
-// updates, with two barriers per column.  A non-positive pivot records the
-// subdomain (1-based) in err and continues with pivot 1.
+// Cholesky of one 64x64 diagonal tile followed by the inverse of its lower
+// factor, written to `inv`.  Four waves; lane i holds row i, wave w the 16
+// columns 16w..16w+15 of it in registers.  Column k is finished by the wave
+// that owns it and broadcast through LDS (two alternating buffers, so one
+// barrier per column); every wave then updates its columns right of k with
+// unconditional FMAs and selects, so the broadcast reads issue together.
+// The inverse runs the same way column-oriented: lane c holds column c of
+// L^{-1}, wave w its rows 16w..16w+15, reading column k of L from a
+// transposed LDS copy and multiplying by the stored reciprocal pivots.  A
+// non-positive pivot records the subdomain (1-based) in err and continues
+// with pivot 1.
 __global__ __launch_bounds__(256) void k_potrf_inv(double* pool, double* inv, const int64_t* task, int* err) {
-  __shared__ double A[T][T + 1];
-  __shared__ double X[T][T + 1];
-  __shared__ int bad;
+  __shared__ __align__(16) double Lt[T][T + 2];  // Lt[j][i] = L[i][j]; later X staging
+  __shared__ __align__(16) double bc[2][T];
+  __shared__ double dinv[T];
   const int64_t* tk = task + 3 * blockIdx.x;
   double* t = pool + tk[0];
   const int sub = int(tk[1]);
   double* tinv = inv + tk[2];
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < T * T; idx += 256) A[idx & (T - 1)][idx >> 6] = t[idx];
-  if (tid == 0) bad = 0;
-  const int i = tid >> 2, j0 = tid & 3;
-  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c0 = 16 * w;
+  double a[16];
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) a[jj] = t[(c0 + jj) * T + lane];
+  bool bad = false;
+#pragma unroll
   for (int k = 0; k < T; ++k) {
-    const double akk = A[k][k];
-    const double aik = A[i][k];
-    double ajk[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) ajk[m] = A[j0 + 4 * m][k];
-    __syncthreads();
-    const bool ok = akk > 0.0;
-    if (!ok && tid == 0) bad = 1;
-    const double d = ok ? akk : 1.0;
-    const double piv = sqrt(d);
-    if ((k & 3) == j0 && i >= k) A[i][k] = (i == k) ? piv : aik / piv;
-    const double f = aik / d;
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int j = j0 + 4 * m;
-      if (j > k && j <= i) A[i][j] -= f * ajk[m];
+    double* col = bc[k & 1];
+    if (w == (k >> 4)) {
+      const double akk = __shfl(a[k & 15], k, 64);
+      const bool ok = akk > 0.0;
+      bad = bad || !ok;
+      const double piv = sqrt(ok ? akk : 1.0);
+      const double rp = 1.0 / piv;
+      const double lik = (lane == k) ? piv : (lane > k ? a[k & 15] * rp : 0.0);
+      a[k & 15] = lik;
+      col[lane] = lik;
+      if (lane == 0) dinv[k] = rp;
     }
     __syncthreads();
+    const double li = col[lane];
+    double cj[16];
+#pragma unroll
+    for (int jj = 0; jj < 16; jj += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(&col[c0 + jj]);
+      cj[jj] = v.x;
+      cj[jj + 1] = v.y;
+    }
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const double u = a[jj] - li * cj[jj];
+      a[jj] = (c0 + jj > k) ? u : a[jj];
+    }
   }
-  // inverse of the lower factor, one column per thread: X L^{-1}
-  if (tid < T) {
-    const int c = tid;
-    for (int r = 0; r < c; ++r) X[r][c] = 0.0;
-    X[c][c] = 1.0 / A[c][c];
-    for (int r = c + 1; r < T; ++r) {
-      double v = 0.0;
-      for (int m = c; m < r; ++m) v += A[r][m] * X[m][c];
-      X[r][c] = -v / A[r][r];
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) {
+    const double v = (c0 + jj <= lane) ? a[jj] : 0.0;
+    t[(c0 + jj) * T + lane] = v;
+    Lt[c0 + jj][lane] = v;
+  }
+  __syncthreads();
+  double x[16];
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) x[rr] = (c0 + rr == lane) ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    double* xk = bc[k & 1];
+    if (w == (k >> 4)) {
+      const double v = x[k & 15] * dinv[k];
+      x[k & 15] = v;
+      xk[lane] = v;
+    }
+    __syncthreads();
+    const double xv = xk[lane];
+    double lk[16];
+#pragma unroll
+    for (int rr = 0; rr < 16; rr += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(&Lt[k][c0 + rr]);
+      lk[rr] = v.x;
+      lk[rr + 1] = v.y;
+    }
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      const double u = x[rr] - lk[rr] * xv;
+      x[rr] = (c0 + rr > k) ? u : x[rr];
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < T * T; idx += 256) {
-    const int a = idx & (T - 1), b = idx >> 6;
-    t[idx] = (a >= b) ? A[a][b] : 0.0;
-    tinv[idx] = X[a][b];
-  }
-  if (tid == 0 && bad) atomicMax(err, sub + 1);
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) Lt[lane][c0 + rr] = x[rr];  // Lt[c][r] = X[r][c]
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < T * T; idx += 256) tinv[idx] = Lt[idx >> 6][idx & (T - 1)];
+  if (bad && lane == 0) atomicMax(err, sub + 1);
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double pd2 __attribute__((ext_vector_type(2)));
 
 // Accumulate A B^T (64x64 tiles, column-major) into the calling wave's
 // 32x32 quadrant on the FP64 matrix cores.  Four waves, 2x2 blocks of 16x16
@@ -182,16 +220,88 @@ __global__ __launch_bounds__(256) void k_trsm_inv(double* pool, const double* in
 }
 
 // C -= sum_p A_p B_p^T over the pairs of one target tile (all contributing
-// columns of one level), accumulated in registers and written once.
-__global__ __launch_bounds__(256) void k_update_multi(double* pool, const int64_t* task, const int64_t* pair) {
+// columns of one level), accumulated in registers and written once.  Each
+// workgroup walks tasks b, b + gridDim.x, ... and their pairs as one
+// sequence, software-pipelined: the next pair's two tiles are loaded into
+// registers while the matrix cores consume the current pair from LDS, so
+// the global latency hides behind the MFMAs (tasks mostly have one or two
+// pairs, so the pipeline runs across tasks).
+__device__ __attribute__((always_inline)) inline void load_pair(const double* A, const double* B, pd2 ra[8], pd2 rb[8]) {
+  const pd2* A2 = reinterpret_cast<const pd2*>(A);
+  const pd2* B2 = reinterpret_cast<const pd2*>(B);
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    ra[s] = A2[threadIdx.x + 256 * s];
+    rb[s] = B2[threadIdx.x + 256 * s];
+  }
+}
+
+__device__ __attribute__((always_inline)) inline void mfma_abt_lds(const double* As, const double* Bs, v4d acc[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < T / 4; ++kk) {
+    const int k = 4 * kk + lk;
+    const double a0 = As[k * T + 32 * wr + li];
+    const double a1 = As[k * T + 32 * wr + 16 + li];
+    const double b0 = Bs[k * T + 32 * wc + li];
+    const double b1 = Bs[k * T + 32 * wc + 16 + li];
+    acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[1], 0, 0, 0);
+    acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[2], 0, 0, 0);
+    acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[3], 0, 0, 0);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_update_multi(double* pool, const int64_t* task, const int64_t* pair,
+                                                      int64_t ntask) {
   __shared__ __align__(16) double As[T * T];
   __shared__ __align__(16) double Bs[T * T];
-  const int64_t* tk = task + 3 * blockIdx.x;
-  double* C = pool + tk[0];
-  const int64_t p0 = tk[1], np = tk[2];
+  pd2* As2 = reinterpret_cast<pd2*>(As);
+  pd2* Bs2 = reinterpret_cast<pd2*>(Bs);
+  const int64_t stride = gridDim.x;
+  int64_t t = blockIdx.x;
+  // first task with at least one pair
+  while (t < ntask && task[3 * t + 2] == 0) t += stride;
+  if (t >= ntask) return;
+  int64_t p0 = task[3 * t + 1], np = task[3 * t + 2], q = 0;
+  pd2 ra[8], rb[8];
+  load_pair(pool + pair[2 * p0], pool + pair[2 * p0 + 1], ra, rb);
   v4d acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-  for (int64_t q = 0; q < np; ++q) mfma_abt(pool + pair[2 * (p0 + q)], pool + pair[2 * (p0 + q) + 1], As, Bs, acc);
-  store_quadrant(C, acc, 1.0, -1.0);
+  while (true) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      As2[threadIdx.x + 256 * s] = ra[s];
+      Bs2[threadIdx.x + 256 * s] = rb[s];
+    }
+    __syncthreads();
+    // next item of this workgroup's sequence
+    int64_t tn = t, qn = q + 1, p0n = p0, npn = np;
+    if (qn == np) {
+      tn = t + stride;
+      while (tn < ntask && task[3 * tn + 2] == 0) tn += stride;
+      qn = 0;
+      if (tn < ntask) {
+        p0n = task[3 * tn + 1];
+        npn = task[3 * tn + 2];
+      }
+    }
+    const bool more = tn < ntask;
+    if (more) load_pair(pool + pair[2 * (p0n + qn)], pool + pair[2 * (p0n + qn) + 1], ra, rb);
+    mfma_abt_lds(As, Bs, acc);
+    if (q + 1 == np) {
+      store_quadrant(pool + task[3 * t], acc, 1.0, -1.0);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[m] = v4d{0, 0, 0, 0};
+    }
+    if (!more) break;
+    t = tn;
+    q = qn;
+    p0 = p0n;
+    np = npn;
+  }
 }
 
 // Copy (scaled) tiles into dense row-major blocks; optional mirrored copy.
@@ -709,7 +819,8 @@ void trsm_tiles(double* pool, const double* inv, const int64_t* task, int64_t nt
 }
 void update_tiles(double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, hipStream_t s) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(k_update_multi, dim3(ntask), dim3(256), 0, s, pool, task, pair);
+  const int64_t nwg = ntask < UPDATE_WGS ? ntask : UPDATE_WGS;
+  hipLaunchKernelGGL(k_update_multi, dim3(nwg), dim3(256), 0, s, pool, task, pair, ntask);
 }
 void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s) {
   if (ntask <= 0) return;

@@ -17,7 +17,9 @@ void scatter(double* pool, const int64_t* dst, const double* val, int64_t n, hip
 void potrf_tiles(double* pool, double* inv, const int64_t* task, int64_t ntask, int* err, hipStream_t s);
 // trsm task [off_ij, off of L_jj^{-1}]: L_ij = A_ij L_jj^{-T}
 void trsm_tiles(double* pool, const double* inv, const int64_t* task, int64_t ntask, hipStream_t s);
-// update task [off_C, first pair, pair count], pairs [off_A, off_B]: C -= sum A B^T
+// update task [off_C, first pair, pair count], pairs [off_A, off_B]: C -= sum A B^T;
+// at most UPDATE_WGS workgroups, each walking its share of the tasks
+constexpr int64_t UPDATE_WGS = 1024;
 void update_tiles(double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, hipStream_t s);
 void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s);
 
