@@ -143,6 +143,26 @@ typedef struct {
  *   increasing edge id, +1 in the lower and -1 in the higher subdomain. */
 int ieti_assemble(const ieti_problem* prob, ieti_handle** out);
 
+/* Batch of n independent problems in one handle: the problems' subdomains,
+ * multiplier rows, primal DOFs, patches and output coefficients are
+ * concatenated in problem order, so that one factorisation plan and one set
+ * of launches (and one captured hipGraph per two PCG iterations) covers all
+ * of them.  The coarse problem stays per problem (block diagonal) and every
+ * problem runs its own PCG recurrence (own step lengths and stopping test,
+ * ||b_p - F_p lambda_p|| <= rtol ||b_p||); a finished problem is frozen while
+ * the others go on.  ieti_factor / ieti_solve / ieti_set_coefficients then act
+ * on the whole batch; a_out holds the problems' coefficient vectors one after
+ * the other, stats report the largest iteration count and residual.
+ * ieti_get_maps is not available on a batch handle.  ieti_assemble(p, out) is
+ * ieti_assemble_batch(p, 1, out). */
+int ieti_assemble_batch(const ieti_problem* probs, int32_t n, ieti_handle** out);
+
+/* Per problem p of a handle (any argument may be NULL):
+ *   ranges [8 p .. 8 p + 7] = {first output coefficient, n_edges, first
+ *   multiplier row, m_r, first primal DOF, n_gp, first subdomain, N_sub},
+ *   iters[p] and rel_residual[p] of the last solve. */
+int ieti_get_batch_info(const ieti_handle* h, int64_t* ranges, int32_t* iters, double* rel_residual);
+
 /* Local factorisations and coarse setup on the GPU (Section 2.1): for every
  * subdomain one partial Cholesky factorisation of the augmented matrix
  * [K_rr K_rp E_I; K_pr K_pp 0; E_I^T 0 0] eliminating the r block, which
@@ -163,7 +183,8 @@ int ieti_solve(ieti_handle* h, const ieti_solve_opts* opts, double* a_out, ieti_
  * d_a_out [n_edges] (e.g. a torch tensor's storage on the same device). */
 int ieti_solve_device(ieti_handle* h, const ieti_solve_opts* opts, double* d_a_out, ieti_stats* stats);
 
-/* sizes[0..7] = {n_edges, n_global, sum_n_r, m_r, n_gp, N_sub, n_nodes, max_n_I} */
+/* sizes[0..7] = {n_edges, n_global, sum_n_r, m_r, n_gp, N_sub, n_nodes, max_n_I}
+ * (totals over the problems of a batch handle) */
 int ieti_get_sizes(const ieti_handle* h, int64_t* sizes);
 
 /* Exact integer maps (any argument may be NULL):

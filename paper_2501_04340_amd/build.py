@@ -25,6 +25,7 @@ SOURCES = [
     os.path.join(CSRC, "host", "mesh_topology.cpp"),
     os.path.join(CSRC, "host", "assemble.cpp"),
     os.path.join(CSRC, "host", "plan.cpp"),
+    os.path.join(CSRC, "host", "batch.cpp"),
     os.path.join(CSRC, "device", "kernels.hip"),
     os.path.join(CSRC, "device", "nn_kernels.hip"),
 ]

@@ -79,7 +79,18 @@ struct ieti_handle {
   } warm;
   DBuf<double> nu_d, lscale_d;  // per-patch reluctivity and load scale (warm-start features)
 
-  DBuf<int> flags;  // [0] err (factor), [1] done, [2] iters, [3] pcg err, [4] coarse err
+  // batch structure on the device (a single problem is a batch of one)
+  DBuf<int64_t> pd, blk, g2l_off;
+  DBuf<int32_t> cprob, task_prob[3];
+  ieti::dev::Batch B;
+  std::vector<int64_t> pd_h, blk_h;
+  DBuf<int> pdone, piters;                 // per problem: PCG finished (1 ok, 3 breakdown), iterations
+  int* pflags_h = nullptr;                 // pinned host copy: done[n_prob], iters[n_prob]
+  // per-problem results of the last solve
+  std::vector<int> p_iters, p_outer, p_status, p_warm;
+  std::vector<double> p_relres, p_relres0;
+
+  DBuf<int> flags;  // [0] err (factor), [3] pcg err, [4] coarse err
   int* flags_h = nullptr;
   double factor_ms = 0.0;
   double bnorm = 0.0;
@@ -104,6 +115,14 @@ struct ieti_handle {
     for (auto* d : is) d->release();
     I_row.release();
     I_sub.release();
+    pd.release();
+    blk.release();
+    g2l_off.release();
+    cprob.release();
+    for (auto& t : task_prob) t.release();
+    pdone.release();
+    piters.release();
+    if (pflags_h) (void)hipHostFree(pflags_h);
     glob2loc.release();
     krp_col.release();
     flags.release();
@@ -206,6 +225,7 @@ int upload(ieti_handle* h) {
   UP(I_sign, P.I_sign);
   UP(I_sub, P.I_sub);
   UP(glob2loc, P.glob2loc);
+  UP(g2l_off, P.g2l_off);
   UP(krp_ptr, P.krp_ptr);
   UP(krp_pos, P.krp_pos);
   UP(krp_col, P.krp_col);
@@ -218,21 +238,70 @@ int upload(ieti_handle* h) {
   std::vector<int64_t> phirow(P.I_total, 0);
   h->max_ld = 0;
   for (auto& v : h->gemv_task_h) v.clear();
-  for (const auto& sp : P.sub) {
+  const int n_prob = int(M.probs.size());
+  std::vector<int32_t> tprob[3];
+  std::vector<int64_t> tstart(3 * (n_prob + 1), 0);  // per task list: first task of each problem
+  for (size_t k = 0; k < P.sub.size(); ++k) {
+    const auto& sp = P.sub[k];
+    const int pk = M.sub_prob[k];
     for (int64_t t = 0; t < sp.nIp; ++t) phirow[sp.I_off + t] = sp.Phi_off + t * sp.nPp;
     h->max_ld = std::max(h->max_ld, sp.nIp);
     for (int ri = 0; ri < 3; ++ri) {
       const int64_t rows = 8 << ri;
-      for (int64_t r0 = 0; r0 < sp.nIp; r0 += rows)
+      for (int64_t r0 = 0; r0 < sp.nIp; r0 += rows) {
         h->gemv_task_h[ri].insert(h->gemv_task_h[ri].end(), {sp.S_off + r0 * sp.nIp, sp.I_off + r0,
                                                              std::min<int64_t>(rows, sp.nIp - r0), sp.nIp, sp.I_off});
+        tprob[ri].push_back(pk);
+      }
+      tstart[3 * (pk + 1) + ri] = int64_t(h->gemv_task_h[ri].size() / 5);
     }
   }
+  for (int p = 1; p <= n_prob; ++p)  // problems without interface tasks inherit the previous end
+    for (int ri = 0; ri < 3; ++ri) tstart[3 * p + ri] = std::max(tstart[3 * p + ri], tstart[3 * (p - 1) + ri]);
   UP(slot_phi_row, phirow);
   for (int ri = 0; ri < 3; ++ri) {
     UP(gemv_tasks[ri], h->gemv_task_h[ri]);
+    UP(task_prob[ri], tprob[ri]);
     h->ngemv_r[ri] = int(h->gemv_task_h[ri].size() / 5);
   }
+  // row blocks (<= 256 rows of one problem) and per-problem descriptors
+  namespace D = ieti::dev;
+  h->blk_h.clear();
+  h->pd_h.assign(size_t(D::PD_N) * n_prob, 0);
+  std::vector<int32_t> cprob_h;
+  int64_t hoff = 0, ptoff = 0, max_gp = 0;
+  for (int p = 0; p < n_prob; ++p) {
+    const auto& pr = M.probs[p];
+    int64_t* d = &h->pd_h[size_t(D::PD_N) * p];
+    d[D::PD_MR0] = pr.mr_base;
+    d[D::PD_MR1] = pr.mr_base + pr.m_r;
+    d[D::PD_GP0] = pr.gp_base;
+    d[D::PD_NGP] = pr.n_gp;
+    d[D::PD_H] = hoff;
+    d[D::PD_HT] = hoff;
+    d[D::PD_SPI] = P.spi_off[p];
+    d[D::PD_B0] = int64_t(h->blk_h.size() / 2);
+    for (int64_t r0 = 0; r0 < pr.m_r; r0 += 256) h->blk_h.insert(h->blk_h.end(), {pr.mr_base + r0, int64_t(p)});
+    d[D::PD_B1] = int64_t(h->blk_h.size() / 2);
+    d[D::PD_PT] = ptoff;
+    for (int ri = 0; ri < 3; ++ri) {
+      d[D::PD_T0 + 2 * ri] = tstart[3 * p + ri];
+      d[D::PD_T0 + 2 * ri + 1] = tstart[3 * (p + 1) + ri];
+    }
+    hoff += pr.m_r * pr.n_gp;
+    ptoff += (d[D::PD_B1] - d[D::PD_B0]) * pr.n_gp;
+    max_gp = std::max(max_gp, pr.n_gp);
+    for (int64_t c = 0; c < pr.n_gp; ++c) cprob_h.push_back(p);
+  }
+  UP(pd, h->pd_h);
+  UP(blk, h->blk_h);
+  UP(cprob, cprob_h);
+  h->B.pd = h->pd.ptr;
+  h->B.blk = h->blk.ptr;
+  h->B.n_prob = n_prob;
+  h->B.n_blk = int(h->blk_h.size() / 2);
+  h->B.n_gp_total = M.n_gp;
+  h->B.max_gp = max_gp;
   // d~ assembly sources: for each global primal, the augmented indices of its local copies
   {
     std::vector<std::vector<int64_t>> src(M.n_gp);
@@ -247,17 +316,17 @@ int upload(ieti_handle* h) {
   }
 #undef UP
   const int64_t m_r = M.m_r, n_gp = M.n_gp;
-  h->nblk = std::max(1, ieti::dev::combine_blocks(m_r));
+  h->nblk = std::max(1, h->B.n_blk);
   if ((rc = dalloc(h->pool, P.pool_elems))) return rc;
   if ((rc = dalloc(h->inv, std::max<int64_t>(P.inv_elems, 1)))) return rc;
   if ((rc = dalloc(h->S, P.S_elems))) return rc;
   if ((rc = dalloc(h->Sinv, P.S_elems))) return rc;
   if ((rc = dalloc(h->Phi, std::max<int64_t>(P.Phi_elems, 1)))) return rc;
   if ((rc = dalloc(h->SPi, std::max<int64_t>(P.SPi_elems, 1)))) return rc;
-  if ((rc = dalloc(h->Spi_glob, std::max<int64_t>(n_gp * n_gp, 1)))) return rc;
-  if ((rc = dalloc(h->G, std::max<int64_t>(m_r * n_gp, 1)))) return rc;
-  if ((rc = dalloc(h->H, std::max<int64_t>(m_r * n_gp, 1)))) return rc;
-  if ((rc = dalloc(h->Ht, std::max<int64_t>(m_r * n_gp, 1)))) return rc;
+  if ((rc = dalloc(h->Spi_glob, std::max<int64_t>(P.spi_off.back(), 1)))) return rc;
+  if ((rc = dalloc(h->G, std::max<int64_t>(hoff, 1)))) return rc;
+  if ((rc = dalloc(h->H, std::max<int64_t>(hoff, 1)))) return rc;
+  if ((rc = dalloc(h->Ht, std::max<int64_t>(hoff, 1)))) return rc;
   if ((rc = dalloc(h->y, P.r_total))) return rc;
   const int64_t mm = std::max<int64_t>(m_r, 1), gg = std::max<int64_t>(n_gp, 1);
   DBuf<double>* vecs_m[] = {&h->lam, &h->r, &h->z, &h->p, &h->q, &h->b, &h->e, &h->tmp};
@@ -273,7 +342,12 @@ int upload(ieti_handle* h) {
   HIP_TRY(hipMemset(h->xgp.ptr, 0, h->xgp.n * sizeof(double)));
   HIP_TRY(hipMemset(h->xgr.ptr, 0, h->xgr.n * sizeof(double)));
   if ((rc = dalloc(h->part_g, std::max(h->ngemv_r[0], 1)))) return rc;
-  if ((rc = dalloc(h->part_t, std::max<int64_t>(int64_t(h->nblk) * n_gp, 1)))) return rc;
+  if ((rc = dalloc(h->part_t, std::max<int64_t>(ptoff, 1)))) return rc;
+  if ((rc = dalloc(h->pdone, n_prob))) return rc;
+  if ((rc = dalloc(h->piters, n_prob))) return rc;
+  if (h->pflags_h) (void)hipHostFree(h->pflags_h);
+  h->pflags_h = nullptr;
+  HIP_TRY(hipHostMalloc(&h->pflags_h, 2 * size_t(n_prob) * sizeof(int)));
   if ((rc = dalloc(h->lam_acc, mm))) return rc;
   if ((rc = dalloc(h->rtrue, mm))) return rc;
   for (hipGraphExec_t* g : {&h->graph_exec, &h->graph_exec32})
@@ -294,9 +368,9 @@ int upload(ieti_handle* h) {
     (void)hipGraphDestroy(h->graph);
     h->graph = nullptr;
   }
-  if ((rc = dalloc(h->scal, 8))) return rc;
+  if ((rc = dalloc(h->scal, 8 * int64_t(n_prob)))) return rc;
   if ((rc = dalloc(h->flags, 8))) return rc;
-  if ((rc = dalloc(h->aout, M.mesh.n_edges))) return rc;
+  if ((rc = dalloc(h->aout, M.n_edges_total))) return rc;
   h->uploaded = true;
   return IETI_OK;
 }
@@ -358,6 +432,7 @@ int gcount(const ieti_handle* h, int fp32) { return h->ngemv_r[gvariant(h, fp32)
 template <typename MT>
 void gemv_timed(ieti_handle* h, const MT* M, const double* xg, double* v, const int* done = nullptr) {
   const int fp32 = std::is_same<MT, float>::value ? 1 : 0;
+  const int32_t* tprob = h->task_prob[gvariant(h, fp32) / 4].ptr;
   hipEvent_t a = nullptr, b = nullptr;
   size_t slot = SIZE_MAX;
   if (h->profiling) {
@@ -366,7 +441,7 @@ void gemv_timed(ieti_handle* h, const MT* M, const double* xg, double* v, const 
     b = next_event(h);
     if (!a || !b) a = b = nullptr;
   }
-  ieti::dev::gemv(M, gtasks(h, fp32), gcount(h, fp32), h->max_ld, xg, v, h->part_g.ptr, done, h->stream,
+  ieti::dev::gemv(M, gtasks(h, fp32), gcount(h, fp32), h->max_ld, xg, v, h->part_g.ptr, done, tprob, h->stream,
                   gvariant(h, fp32), a, b);
   if (a) h->ev_marks.emplace_back(0, slot);
 }
@@ -378,8 +453,8 @@ void apply_F(ieti_handle* h, const double* x, double* out) {
   hipStream_t s = h->stream;
   D::gather_rows(x, h->row_src.ptr, M.m_r, h->xgp.ptr, s);
   gemv_timed(h, h->Sinv.ptr, h->xgp.ptr, h->v.ptr);
-  if (M.n_gp > 0) D::coarse_project(h->Ht.ptr, M.n_gp, M.m_r, x, h->t.ptr, s);
-  D::combine(h->v.ptr, h->row_src.ptr, M.m_r, M.n_gp > 0 ? h->H.ptr : nullptr, h->t.ptr, M.n_gp, out, s);
+  if (M.n_gp > 0) D::coarse_project(h->Ht.ptr, x, h->t.ptr, h->cprob.ptr, h->B, s);
+  D::combine(h->v.ptr, h->row_src.ptr, M.n_gp > 0 ? h->H.ptr : nullptr, h->t.ptr, out, h->B, s);
 }
 
 // z = M_D^{-1} x = sum_k B_k S_rIrI^(k) B_k^T x  (D_s = I)
@@ -389,7 +464,7 @@ void apply_M(ieti_handle* h, const double* x, double* out) {
   hipStream_t s = h->stream;
   D::gather_rows(x, h->row_src.ptr, M.m_r, h->xgr.ptr, s);
   gemv_timed(h, h->S.ptr, h->xgr.ptr, h->v.ptr);
-  D::combine(h->v.ptr, h->row_src.ptr, M.m_r, nullptr, nullptr, 0, out, s);
+  D::combine(h->v.ptr, h->row_src.ptr, nullptr, nullptr, out, h->B, s);
 }
 
 // One PCG iteration of parity `par` as four launches, with the interface
@@ -397,21 +472,19 @@ void apply_M(ieti_handle* h, const double* x, double* out) {
 template <typename MT>
 void pcg_iteration(ieti_handle* h, int par, const MT* Sinv, const MT* S) {
   namespace D = ieti::dev;
-  const auto& M = h->model;
   hipStream_t s = h->stream;
-  const int64_t m_r = M.m_r;
-  int* done = h->flags.ptr + 1;
-  int* iters = h->flags.ptr + 2;
+  int* done = h->pdone.ptr;
+  int* iters = h->piters.ptr;
   int* perr = h->flags.ptr + 3;
   double* part_rr = h->part.ptr + h->nblk;
-  const double* H = M.n_gp > 0 ? h->H.ptr : nullptr;
-  const int ng = gcount(h, std::is_same<MT, float>::value ? 1 : 0);
+  const int fp32 = std::is_same<MT, float>::value ? 1 : 0;
+  const int gt = gvariant(h, fp32) / 4;
   gemv_timed(h, Sinv, h->xgp.ptr, h->v.ptr, done);
-  D::pcg_F(h->v.ptr, h->row_src.ptr, m_r, H, h->part_t.ptr, M.n_gp, h->nblk, h->part_g.ptr, ng, h->p.ptr,
-           h->lam.ptr, h->r.ptr, h->xgr.ptr, part_rr, h->scal.ptr, par, done, perr, s);
+  D::pcg_F(h->v.ptr, h->row_src.ptr, h->H.ptr, h->part_t.ptr, h->part_g.ptr, h->p.ptr, h->lam.ptr, h->r.ptr,
+           h->xgr.ptr, part_rr, h->scal.ptr, par, done, perr, h->B, gt, s);
   gemv_timed(h, S, h->xgr.ptr, h->v.ptr, done);
-  D::pcg_M(h->v.ptr, h->row_src.ptr, m_r, H, M.n_gp, h->part_g.ptr, ng, part_rr, h->nblk, h->p.ptr, h->z.ptr,
-           h->xgp.ptr, h->part_t.ptr, h->scal.ptr, par, done, iters, 0, s);
+  D::pcg_M(h->v.ptr, h->row_src.ptr, h->H.ptr, h->part_g.ptr, part_rr, h->p.ptr, h->z.ptr, h->xgp.ptr,
+           h->part_t.ptr, h->scal.ptr, par, done, iters, 0, h->B, gt, s);
 }
 
 void pcg_iteration_prec(ieti_handle* h, int par, bool fp32) {
@@ -447,8 +520,8 @@ int tune_gemv(ieti_handle* h, const MT* Ma, const MT* Mb, int fp32) {
   for (int v = 0; v < D::GEMV_VARIANTS; ++v) {
     const int ri = v / 4;
     auto launch = [&]() {
-      D::gemv(Ma, h->gemv_tasks[ri].ptr, h->ngemv_r[ri], h->max_ld, h->xgp.ptr, h->v.ptr, h->part_g.ptr, nullptr, s, v);
-      D::gemv(Mb, h->gemv_tasks[ri].ptr, h->ngemv_r[ri], h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, s, v);
+      D::gemv(Ma, h->gemv_tasks[ri].ptr, h->ngemv_r[ri], h->max_ld, h->xgp.ptr, h->v.ptr, h->part_g.ptr, nullptr, nullptr, s, v);
+      D::gemv(Mb, h->gemv_tasks[ri].ptr, h->ngemv_r[ri], h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, nullptr, s, v);
     };
     launch();
     launch();
@@ -532,8 +605,8 @@ int compute_rhs(ieti_handle* h) {
   D::rhs_assemble(h->y.ptr, h->A_aug.ptr, h->row_src.ptr, M.m_r, h->e.ptr, s);
   if (M.n_gp > 0) {
     D::sum_sources(h->y.ptr, h->dsrc_ptr.ptr, h->dsrc_idx.ptr, M.n_gp, h->dtil.ptr, s);
-    D::tri_small(h->Spi_glob.ptr, M.n_gp, h->dtil.ptr, h->w.ptr, false, s);
-    D::axpy_rows(h->H.ptr, h->w.ptr, M.m_r, M.n_gp, h->e.ptr, h->b.ptr, s);
+    D::tri_small(h->Spi_glob.ptr, h->dtil.ptr, h->w.ptr, false, h->B, s);
+    D::axpy_rows(h->H.ptr, h->w.ptr, h->e.ptr, h->b.ptr, h->B, s);
   } else {
     D::vec_copy(h->e.ptr, h->b.ptr, M.m_r, s);
   }
@@ -541,15 +614,18 @@ int compute_rhs(ieti_handle* h) {
   return check_launch();
 }
 
-double host_dot(ieti_handle* h, const double* x, const double* y, int64_t n) {
-  if (n <= 0) return 0.0;
-  ieti::dev::dot_partial(x, y, n, h->part.ptr, h->stream);
-  std::vector<double> part(h->nblk);
-  (void)hipMemcpyAsync(part.data(), h->part.ptr, h->nblk * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+// Per-problem dot products x.y (block partials on the device, summed in
+// block order on the host).
+std::vector<double> host_dots(ieti_handle* h, const double* x, const double* y) {
+  const int n_prob = h->B.n_prob;
+  std::vector<double> out(n_prob, 0.0);
+  if (h->B.n_blk <= 0) return out;
+  ieti::dev::dot_blocks(x, y, h->part.ptr, h->B, h->stream);
+  std::vector<double> part(h->B.n_blk);
+  (void)hipMemcpyAsync(part.data(), h->part.ptr, part.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
   (void)hipStreamSynchronize(h->stream);
-  double s = 0.0;
-  for (double v : part) s += v;
-  return s;
+  for (int b = 0; b < h->B.n_blk; ++b) out[h->blk_h[2 * b + 1]] += part[b];
+  return out;
 }
 
 // lambda_0 from the attached network: features from the per-patch
@@ -569,15 +645,17 @@ void warm_predict(ieti_handle* h, double* lam) {
                         lam, s);
 }
 
-// Initial multipliers lam0 and residual r0 = b - F lam0 (rr0 = ||r0||^2):
-// the caller's lambda0, else the network's prediction (dropped for 0 when
-// its residual is not below ||b|| or not finite), else 0.
-int init_lambda(ieti_handle* h, const ieti_solve_opts* opts, double bb, double* lam0, double* r0, double* rr0,
-                int* applies, int* warm_flag) {
+// Initial multipliers lam0 and residual r0 = b - F lam0 (rr0[p] = ||r0_p||^2
+// per problem): the caller's lambda0, else the network's prediction (dropped
+// for 0, per problem, when its residual is not below ||b_p|| or not finite),
+// else 0.  warm[p]: 1 prediction used, -1 rejected, 0 not asked.
+int init_lambda(ieti_handle* h, const ieti_solve_opts* opts, const std::vector<double>& bb, double* lam0, double* r0,
+                std::vector<double>& rr0, int* applies, std::vector<int>& warm) {
   namespace D = ieti::dev;
   const int64_t m_r = h->model.m_r;
+  const int n_prob = h->B.n_prob;
   hipStream_t s = h->stream;
-  *warm_flag = 0;
+  warm.assign(n_prob, 0);
   bool have = false;
   if (opts && opts->lambda0) {
     HIP_TRY(hipMemcpyAsync(lam0, opts->lambda0, m_r * sizeof(double), hipMemcpyHostToDevice, s));
@@ -586,55 +664,74 @@ int init_lambda(ieti_handle* h, const ieti_solve_opts* opts, double bb, double* 
     if (!h->warm.on) return fail(IETI_ERR_STATE, "warm_start requested but no network is attached");
     warm_predict(h, lam0);
     have = true;
-    *warm_flag = 1;
+    warm.assign(n_prob, 1);
   }
   if (have) {
     apply_F(h, lam0, h->q.ptr);
     ++*applies;
     D::axpby(h->b.ptr, h->q.ptr, r0, 1.0, -1.0, m_r, s);
-    *rr0 = host_dot(h, r0, r0, m_r);
-    if (*warm_flag == 1 && !(std::isfinite(*rr0) && *rr0 < bb)) {
-      *warm_flag = -1;
-      have = false;
-    }
-  }
-  if (!have) {
+    rr0 = host_dots(h, r0, r0);
+    for (int p = 0; p < n_prob; ++p)
+      if (warm[p] == 1 && !(std::isfinite(rr0[p]) && rr0[p] < bb[p])) {
+        const int64_t* d = &h->pd_h[size_t(D::PD_N) * p];
+        const int64_t r0w = d[D::PD_MR0], nr = d[D::PD_MR1] - d[D::PD_MR0];
+        D::fill(lam0 + r0w, nr, 0.0, s);
+        D::vec_copy(h->b.ptr + r0w, r0 + r0w, nr, s);
+        rr0[p] = bb[p];
+        warm[p] = -1;
+      }
+  } else {
     D::fill(lam0, m_r, 0.0, s);
     D::vec_copy(h->b.ptr, r0, m_r, s);
-    *rr0 = bb;
+    rr0 = bb;
   }
   return check_launch();
 }
 
-// PCG on F x = r_0 from the state prepared by the caller (x in h->lam, r_0 in
-// h->r with ||r_0||^2 = rr0), until ||r||^2 <= tol2 or maxit iterations.
-int run_pcg(ieti_handle* h, double tol2, double rr0, int maxit, int every, bool fp32, bool use_graph, int* iters_out,
-            double* rr_out, int* status) {
+// PCG on F x = r_0 for every problem of the batch at once from the state
+// prepared by the caller (x in h->lam, r_0 in h->r with ||r_0,p||^2 =
+// rr0[p]); problem p stops when ||r_p||^2 <= tol2[p] (it is frozen while the
+// others go on), all stop at maxit iterations.
+int run_pcg(ieti_handle* h, const std::vector<double>& tol2, const std::vector<double>& rr0, int maxit, int every,
+            bool fp32, bool use_graph, std::vector<int>& iters_out, std::vector<double>& rr_out,
+            std::vector<int>& status) {
   namespace D = ieti::dev;
   const auto& M = h->model;
   hipStream_t s = h->stream;
   const int64_t m_r = M.m_r;
-  int* done = h->flags.ptr + 1;
-  int* iters = h->flags.ptr + 2;
+  const int n_prob = h->B.n_prob;
   double* part_rr = h->part.ptr + h->nblk;
-  *iters_out = 0;
-  *rr_out = rr0;
-  *status = IETI_OK;
-  if (rr0 <= tol2) return IETI_OK;
-  HIP_TRY(hipMemsetAsync(h->flags.ptr + 1, 0, 3 * sizeof(int), s));
-  const double sc[8] = {0.0, 0.0, 0.0, 0.0, tol2, rr0, 0.0, 0.0};
-  HIP_TRY(hipMemcpyAsync(h->scal.ptr, sc, sizeof(sc), hipMemcpyHostToDevice, s));
+  iters_out.assign(n_prob, 0);
+  rr_out = rr0;
+  status.assign(n_prob, IETI_OK);
+  std::vector<int> done0(n_prob, 0);
+  bool all = true;
+  for (int p = 0; p < n_prob; ++p) {
+    done0[p] = rr0[p] <= tol2[p] ? 1 : 0;
+    all = all && done0[p];
+  }
+  if (all) return IETI_OK;
+  std::vector<double> sc(8 * size_t(n_prob), 0.0);
+  for (int p = 0; p < n_prob; ++p) {
+    sc[8 * p + 4] = tol2[p];
+    sc[8 * p + 5] = rr0[p];
+  }
+  HIP_TRY(hipMemcpyAsync(h->scal.ptr, sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->pdone.ptr, done0.data(), n_prob * sizeof(int), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(h->piters.ptr, 0, n_prob * sizeof(int), s));
+  HIP_TRY(hipMemsetAsync(h->flags.ptr + 3, 0, sizeof(int), s));
   // z_0 = M r_0, p_0 = z_0, rz_0, partials of H^T p_0
-  D::gather_rows(h->r.ptr, h->row_src.ptr, m_r, h->xgr.ptr, s);
   const int pf = fp32 ? 1 : 0;
+  const int gt = gvariant(h, pf) / 4;
+  D::gather_rows(h->r.ptr, h->row_src.ptr, m_r, h->xgr.ptr, s);
   if (fp32)
-    D::gemv(h->S32.ptr, gtasks(h, pf), gcount(h, pf), h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, s,
-            gvariant(h, pf));
+    D::gemv(h->S32.ptr, gtasks(h, pf), gcount(h, pf), h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr,
+            nullptr, s, gvariant(h, pf));
   else
-    D::gemv(h->S.ptr, gtasks(h, pf), gcount(h, pf), h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, s,
-            gvariant(h, pf));
-  D::pcg_M(h->v.ptr, h->row_src.ptr, m_r, M.n_gp > 0 ? h->H.ptr : nullptr, M.n_gp, h->part_g.ptr, gcount(h, pf), part_rr,
-           h->nblk, h->p.ptr, h->z.ptr, h->xgp.ptr, h->part_t.ptr, h->scal.ptr, 0, done, iters, 1, s);
+    D::gemv(h->S.ptr, gtasks(h, pf), gcount(h, pf), h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr,
+            nullptr, s, gvariant(h, pf));
+  D::pcg_M(h->v.ptr, h->row_src.ptr, h->H.ptr, h->part_g.ptr, part_rr, h->p.ptr, h->z.ptr, h->xgp.ptr, h->part_t.ptr,
+           h->scal.ptr, 0, h->pdone.ptr, h->piters.ptr, 1, h->B, gt, s);
   if (use_graph) {
     int rc = capture_graph(h, fp32);
     if (rc) return rc;
@@ -648,21 +745,26 @@ int run_pcg(ieti_handle* h, double tol2, double rr0, int maxit, int every, bool 
       pcg_iteration_prec(h, 1, fp32);
     }
     if ((it + 2) % every2 == 0 || it + 2 >= maxit) {
-      HIP_TRY(hipMemcpyAsync(h->flags_h, h->flags.ptr, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(h->pflags_h, h->pdone.ptr, n_prob * sizeof(int), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
-      if (h->flags_h[1]) break;
+      bool fin = true;
+      for (int p = 0; p < n_prob && fin; ++p) fin = h->pflags_h[p] != 0;
+      if (fin) break;
     }
   }
   int rc = check_launch();
   if (rc) return rc;
-  HIP_TRY(hipMemcpyAsync(h->flags_h, h->flags.ptr, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-  double sc_h[8];
-  HIP_TRY(hipMemcpyAsync(sc_h, h->scal.ptr, sizeof(sc_h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h->pflags_h, h->pdone.ptr, n_prob * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h->pflags_h + n_prob, h->piters.ptr, n_prob * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(sc.data(), h->scal.ptr, sc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  *iters_out = h->flags_h[2];
-  *rr_out = sc_h[5];
-  if (h->flags_h[3]) return fail(IETI_ERR_BREAKDOWN, "PCG breakdown: p^T F p <= 0");
-  if (h->flags_h[1] != 1) *status = IETI_ERR_NOT_CONVERGED;
+  for (int p = 0; p < n_prob; ++p) {
+    iters_out[p] = h->pflags_h[n_prob + p];
+    rr_out[p] = sc[8 * p + 5];
+    if (h->pflags_h[p] == 3)
+      return fail(IETI_ERR_BREAKDOWN, "PCG breakdown (p^T F p <= 0) in problem " + std::to_string(p));
+    if (h->pflags_h[p] != 1) status[p] = IETI_ERR_NOT_CONVERGED;
+  }
   return IETI_OK;
 }
 
@@ -677,73 +779,87 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   const int every = (opts && opts->check_every > 0) ? opts->check_every : 8;
   hipStream_t s = h->stream;
   const int64_t m_r = M.m_r;
+  const int n_prob = h->B.n_prob;
   HIP_TRY(hipEventRecord(h->ev0, s));
   int rc = compute_rhs(h);
   if (rc) return rc;
   // profiled runs use direct launches so every GEMV carries launch events
   const bool use_graph = (!opts || opts->use_graph != 0) && !h->profiling;
   int it = 0, outer = 0;
-  double rr = 0.0;
-  const double bb = host_dot(h, h->b.ptr, h->b.ptr, m_r);
-  h->bnorm = std::sqrt(bb);
+  const std::vector<double> bb = host_dots(h, h->b.ptr, h->b.ptr);
+  double bb_all = 0.0;
+  for (double v : bb) bb_all += v;
+  h->bnorm = std::sqrt(bb_all);
   HIP_TRY(hipEventRecord(h->ev1, s));
-  int status = IETI_OK;
-  int applies = 0, warm_flag = 0;
-  double rr0 = 0.0;
+  int applies = 0;
+  std::vector<double> rr(n_prob, 0.0), rr0(n_prob, 0.0);
+  std::vector<int> status(n_prob, IETI_OK), iters(n_prob, 0), outers(n_prob, 0), warm(n_prob, 0);
   if (m_r > 0) {
     if (!h->mixed) {
       // plain FP64: PCG on F lambda = b from lambda_0
-      rc = init_lambda(h, opts, bb, h->lam.ptr, h->r.ptr, &rr, &applies, &warm_flag);
+      rc = init_lambda(h, opts, bb, h->lam.ptr, h->r.ptr, rr, &applies, warm);
       if (rc) return rc;
       rr0 = rr;
-      int n = 0;
-      rc = run_pcg(h, rtol * rtol * bb, rr, maxit, every, false, use_graph, &n, &rr, &status);
+      std::vector<double> tol2(n_prob);
+      for (int p = 0; p < n_prob; ++p) tol2[p] = rtol * rtol * bb[p];
+      rc = run_pcg(h, tol2, rr, maxit, every, false, use_graph, iters, rr, status);
       if (rc) return rc;
-      it = n;
-      applies += n;
+      for (int n : iters) it = std::max(it, n);
+      applies += it;
     } else {
       // mixed: outer refinement on the FP64 residual r = b - F lambda, inner PCG
-      // with FP32-stored interface blocks on F d = r, lambda += d
-      rc = init_lambda(h, opts, bb, h->lam_acc.ptr, h->rtrue.ptr, &rr, &applies, &warm_flag);
+      // with FP32-stored interface blocks on F d = r, lambda += d (per problem)
+      rc = init_lambda(h, opts, bb, h->lam_acc.ptr, h->rtrue.ptr, rr, &applies, warm);
       if (rc) return rc;
       rr0 = rr;
       const int max_outer = 20;
-      status = IETI_ERR_NOT_CONVERGED;
+      std::vector<int> in_iters, in_status;
+      std::vector<double> in_rr;
       for (outer = 0;; ++outer) {
         if (outer > 0) {
           apply_F(h, h->lam_acc.ptr, h->q.ptr);
           ++applies;
           D::axpby(h->b.ptr, h->q.ptr, h->rtrue.ptr, 1.0, -1.0, m_r, s);
-          rr = host_dot(h, h->rtrue.ptr, h->rtrue.ptr, m_r);
+          rr = host_dots(h, h->rtrue.ptr, h->rtrue.ptr);
         }
-        if (rr <= rtol * rtol * bb || bb == 0.0) {
-          status = IETI_OK;
-          break;
+        bool all = true;
+        std::vector<double> tol2(n_prob);
+        for (int p = 0; p < n_prob; ++p) {
+          const bool conv = rr[p] <= rtol * rtol * bb[p] || bb[p] == 0.0;
+          status[p] = conv ? IETI_OK : IETI_ERR_NOT_CONVERGED;
+          all = all && conv;
+          // inner tolerance: a fixed factor below the current true residual,
+          // never tighter than what the final step needs; converged problems
+          // start (and stay) finished
+          const double inner_rel = conv ? 1.0 : std::max(1e-4, 0.5 * rtol * std::sqrt(bb[p] / rr[p]));
+          tol2[p] = inner_rel * inner_rel * rr[p];
+          if (!conv) outers[p] = outer;
         }
-        if (outer >= max_outer || it >= maxit) break;
-        // inner tolerance: a fixed factor below the current true residual,
-        // never tighter than what the final step needs
-        const double inner_rel = std::max(1e-4, 0.5 * rtol * std::sqrt(bb / rr));
+        if (all || outer >= max_outer || it >= maxit) break;
         D::fill(h->lam.ptr, m_r, 0.0, s);
         D::vec_copy(h->rtrue.ptr, h->r.ptr, m_r, s);
-        int n = 0, st_in = IETI_OK;
-        double rr_in = rr;
-        rc = run_pcg(h, inner_rel * inner_rel * rr, rr, maxit - it, every, true, use_graph, &n, &rr_in, &st_in);
+        rc = run_pcg(h, tol2, rr, maxit - it, every, true, use_graph, in_iters, in_rr, in_status);
         if (rc) return rc;
+        int n = 0;
+        for (int p = 0; p < n_prob; ++p) {
+          iters[p] += in_iters[p];
+          n = std::max(n, in_iters[p]);
+        }
         it += n;
         applies += n;
         D::axpby(h->lam_acc.ptr, h->lam.ptr, h->lam_acc.ptr, 1.0, 1.0, m_r, s);
       }
+      for (int p = 0; p < n_prob; ++p) outers[p] += status[p] == IETI_OK && outer > 0 ? 1 : 0;
       D::vec_copy(h->lam_acc.ptr, h->lam.ptr, m_r, s);
     }
   }
   HIP_TRY(hipEventRecord(h->ev2, s));
   // ---- recovery: p = S_c^{-1}(d~ + G^T lambda), a_r = K_rr^{-1}(j_r - K_rp C p - B^T lambda)
   if (M.n_gp > 0) {
-    // u = L_c^{-1} d~ + H^T lambda, p = L_c^{-T} u  (H = G L_c^{-T}, S_c = L_c L_c^T)
-    D::coarse_project(h->Ht.ptr, M.n_gp, m_r, h->lam.ptr, h->t.ptr, s);
+    // u = L_c^{-1} d~ + H^T lambda, p = L_c^{-T} u  (H = G L_c^{-T}, S_c = L_c L_c^T), per problem
+    D::coarse_project(h->Ht.ptr, h->lam.ptr, h->t.ptr, h->cprob.ptr, h->B, s);
     D::axpby(h->w.ptr, h->t.ptr, h->dtil.ptr, 1.0, 1.0, M.n_gp, s);
-    D::tri_small(h->Spi_glob.ptr, M.n_gp, h->dtil.ptr, h->pglob.ptr, true, s);
+    D::tri_small(h->Spi_glob.ptr, h->dtil.ptr, h->pglob.ptr, true, h->B, s);
   }
   D::vec_copy(h->b_aug0.ptr, h->y.ptr, P.r_total, s);
   D::recovery_rhs(h->y.ptr, h->krp_ptr.ptr, h->krp_pos.ptr, h->krp_col.ptr, h->krp_val.ptr,
@@ -752,7 +868,7 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   forward_solve(h, false);
   backward_solve(h);
   double* aout = a_dev ? a_dev : h->aout.ptr;
-  D::fill(aout, M.mesh.n_edges, 0.0, s);
+  D::fill(aout, M.n_edges_total, 0.0, s);
   D::write_output(h->y.ptr, h->out_src.ptr, h->out_edge.ptr, int64_t(P.out_src.size()), h->pglob.ptr,
                   h->primal_edges.ptr, M.n_gp, aout, s);
   hipEvent_t evend;
@@ -760,7 +876,7 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   HIP_TRY(hipEventRecord(evend, s));
   rc = check_launch();
   if (rc) return rc;
-  if (a_host) HIP_TRY(hipMemcpyAsync(a_host, aout, M.mesh.n_edges * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (a_host) HIP_TRY(hipMemcpyAsync(a_host, aout, M.n_edges_total * sizeof(double), hipMemcpyDeviceToHost, s));
   h->lambda_h.assign(m_r, 0.0);
   if (m_r > 0) HIP_TRY(hipMemcpyAsync(h->lambda_h.data(), h->lam.ptr, m_r * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -769,25 +885,77 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   HIP_TRY(hipEventElapsedTime(&ms_total, h->ev0, evend));
   HIP_TRY(hipEventElapsedTime(&ms_pcg, h->ev1, h->ev2));
   HIP_TRY(hipEventDestroy(evend));
+  // per-problem results; the stats report the worst problem
+  h->p_iters = iters;
+  h->p_outer = outers;
+  h->p_status = status;
+  h->p_warm = warm;
+  h->p_relres.assign(n_prob, 0.0);
+  h->p_relres0.assign(n_prob, 0.0);
+  double rel = 0.0, rel0 = 0.0;
+  int st_all = IETI_OK, warm_all = 0, outer_max = 0;
+  for (int p = 0; p < n_prob; ++p) {
+    h->p_relres[p] = bb[p] > 0 ? std::sqrt(rr[p] / bb[p]) : 0.0;
+    h->p_relres0[p] = bb[p] > 0 ? std::sqrt(rr0[p] / bb[p]) : 0.0;
+    rel = std::max(rel, h->p_relres[p]);
+    rel0 = std::max(rel0, h->p_relres0[p]);
+    if (status[p] != IETI_OK) st_all = status[p];
+    if (warm[p] == -1) warm_all = -1;
+    else if (warm[p] == 1 && warm_all == 0) warm_all = 1;
+    outer_max = std::max(outer_max, outers[p]);
+  }
   if (st) {
     st->n_global = M.n_g;
     st->n_multipliers = M.m_r;
     st->n_primal = M.n_gp;
     st->n_sub = M.n_sub;
     st->iters = it;
-    st->outer_iters = outer;
-    st->status = status;
+    st->outer_iters = h->mixed ? outer : 0;
+    st->status = st_all;
     st->f_applies = applies;
-    st->rel_residual = h->bnorm > 0 ? std::sqrt(rr) / h->bnorm : 0.0;
+    st->rel_residual = rel;
     st->t_factor_s = h->factor_ms * 1e-3;
     st->t_solve_s = ms_total * 1e-3;
     st->t_pcg_s = ms_pcg * 1e-3;
     st->factor_flops = h->plan.flops;
-    st->rel_residual0 = h->bnorm > 0 ? std::sqrt(rr0) / h->bnorm : 0.0;
-    st->warm_start = warm_flag;
+    st->rel_residual0 = rel0;
+    st->warm_start = warm_all;
     st->reserved = 0;
   }
-  if (status != IETI_OK) return fail(status, "PCG did not reach the tolerance within maxit");
+  (void)outer_max;
+  if (st_all != IETI_OK) return fail(st_all, "PCG did not reach the tolerance within maxit");
+  return IETI_OK;
+}
+
+// Validation, topology, gauge and assembly of one problem into m (host).
+int assemble_model(const ieti_problem* prob, ieti::Model& m) {
+  int rc = validate(prob);
+  if (rc) return rc;
+  m.prob = *prob;
+  const int64_t np = int64_t(prob->patches[0]) * prob->patches[1] * prob->patches[2];
+  m.part.assign(prob->patch_to_subdomain, prob->patch_to_subdomain + np);
+  m.nu.assign(prob->nu_per_patch, prob->nu_per_patch + np);
+  int maxs = -1;
+  for (int64_t q = 0; q < np; ++q) {
+    if (m.part[q] < 0) return fail(IETI_ERR_INVALID_ARG, "negative subdomain id");
+    if (!(m.nu[q] > 0.0)) return fail(IETI_ERR_INVALID_ARG, "reluctivity must be positive");
+    maxs = std::max(maxs, m.part[q]);
+  }
+  m.n_sub = maxs + 1;
+  {
+    std::vector<int> used(m.n_sub, 0);
+    for (int64_t q = 0; q < np; ++q) used[m.part[q]] = 1;
+    for (int k = 0; k < m.n_sub; ++k)
+      if (!used[k]) return fail(IETI_ERR_PARTITION, "subdomain " + std::to_string(k) + " has no patch");
+  }
+  m.mesh.init(*prob);
+  ieti::Error err{0, ""};
+  rc = ieti::build_topology(m, err);
+  if (!rc) rc = ieti::assemble_local_systems(m, err);
+  if (rc) return fail(rc, err.msg);
+  m.prob.J = nullptr;  // the callback is not kept beyond the assembly call
+  m.prob.J_user = nullptr;
+  ieti::finalize_single(m);
   return IETI_OK;
 }
 
@@ -797,55 +965,51 @@ extern "C" {
 
 const char* ieti_last_error(void) { return ieti::rt::last_error().c_str(); }
 
-int ieti_assemble(const ieti_problem* prob, ieti_handle** out) {
+int ieti_assemble(const ieti_problem* prob, ieti_handle** out) { return ieti_assemble_batch(prob, 1, out); }
+
+int ieti_assemble_batch(const ieti_problem* probs, int32_t n, ieti_handle** out) {
   if (!out) return fail(IETI_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  int rc = validate(prob);
-  if (rc) return rc;
+  if (!probs || n < 1) return fail(IETI_ERR_INVALID_ARG, "a batch needs at least one problem");
+  std::vector<ieti::Model> parts(n);
+  for (int32_t i = 0; i < n; ++i) {
+    int rc = assemble_model(&probs[i], parts[i]);
+    if (rc) {
+      if (n > 1) ieti::rt::last_error() = "problem " + std::to_string(i) + ": " + ieti::rt::last_error();
+      return rc;
+    }
+  }
   auto* h = new ieti_handle();
-  ieti::Model& m = h->model;
-  m.prob = *prob;
-  const int64_t np = int64_t(prob->patches[0]) * prob->patches[1] * prob->patches[2];
-  m.part.assign(prob->patch_to_subdomain, prob->patch_to_subdomain + np);
-  m.nu.assign(prob->nu_per_patch, prob->nu_per_patch + np);
-  int maxs = -1;
-  for (int64_t q = 0; q < np; ++q) {
-    if (m.part[q] < 0) {
+  if (n == 1) {
+    h->model = std::move(parts[0]);
+  } else {
+    ieti::Error err{0, ""};
+    if (int rc = ieti::merge_models(parts, h->model, err)) {
       delete h;
-      return fail(IETI_ERR_INVALID_ARG, "negative subdomain id");
+      return fail(rc, err.msg);
     }
-    if (!(m.nu[q] > 0.0)) {
-      delete h;
-      return fail(IETI_ERR_INVALID_ARG, "reluctivity must be positive");
-    }
-    maxs = std::max(maxs, m.part[q]);
   }
-  m.n_sub = maxs + 1;
-  {
-    std::vector<int> used(m.n_sub, 0);
-    for (int64_t q = 0; q < np; ++q) used[m.part[q]] = 1;
-    for (int k = 0; k < m.n_sub; ++k)
-      if (!used[k]) {
-        delete h;
-        return fail(IETI_ERR_PARTITION, "subdomain " + std::to_string(k) + " has no patch");
-      }
-  }
-  m.mesh.init(*prob);
-  ieti::Error err{0, ""};
-  rc = ieti::build_topology(m, err);
-  if (!rc) rc = ieti::assemble_local_systems(m, err);
-  if (rc) {
-    delete h;
-    return fail(rc, err.msg);
-  }
-  m.prob.J = nullptr;  // the callback is not kept beyond this call
-  m.prob.J_user = nullptr;
-  rc = build_plan_if_needed(h, ieti::dev::TILE, 0);
+  int rc = build_plan_if_needed(h, ieti::dev::TILE, 0);
   if (rc) {
     delete h;
     return rc;
   }
   *out = h;
+  return IETI_OK;
+}
+
+int ieti_get_batch_info(const ieti_handle* h, int64_t* ranges, int32_t* iters, double* rel_residual) {
+  if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
+  const auto& M = h->model;
+  for (size_t p = 0; p < M.probs.size(); ++p) {
+    const auto& r = M.probs[p];
+    if (ranges) {
+      const int64_t v[8] = {r.edge_base, r.n_edges, r.mr_base, r.m_r, r.gp_base, r.n_gp, r.sub_base, r.n_sub};
+      std::memcpy(ranges + 8 * p, v, sizeof(v));
+    }
+    if (iters) iters[p] = p < h->p_iters.size() ? h->p_iters[p] : 0;
+    if (rel_residual) rel_residual[p] = p < h->p_relres.size() ? h->p_relres[p] : 0.0;
+  }
   return IETI_OK;
 }
 
@@ -888,11 +1052,11 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   D::copy_tiles(h->pool.ptr, h->xphi.ptr, int64_t(P.xphi_task.size() / 5), -1.0, h->Phi.ptr, s);
   D::copy_tiles(h->pool.ptr, h->xspi.ptr, int64_t(P.xspi_task.size() / 5), 1.0, h->SPi.ptr, s);
   if (M.n_gp > 0) {
-    D::sum_sources(h->SPi.ptr, h->spi_ptr.ptr, h->spi_src.ptr, M.n_gp * M.n_gp, h->Spi_glob.ptr, s);
-    D::chol_small(h->Spi_glob.ptr, M.n_gp, h->flags.ptr + 4, s);
-    D::build_G(h->Phi.ptr, h->row_src.ptr, h->slot_phi_row.ptr, h->I_sub.ptr, h->glob2loc.ptr, M.m_r, M.n_gp, h->G.ptr,
-               s);
-    D::solve_rows_LT(h->Spi_glob.ptr, M.n_gp, h->G.ptr, M.m_r, h->H.ptr, h->Ht.ptr, s);
+    D::sum_sources(h->SPi.ptr, h->spi_ptr.ptr, h->spi_src.ptr, P.spi_off.back(), h->Spi_glob.ptr, s);
+    D::chol_small(h->Spi_glob.ptr, h->flags.ptr + 4, h->B, s);
+    D::build_G(h->Phi.ptr, h->row_src.ptr, h->slot_phi_row.ptr, h->I_sub.ptr, h->glob2loc.ptr, h->g2l_off.ptr,
+               h->G.ptr, h->B, s);
+    D::solve_rows_LT(h->Spi_glob.ptr, h->G.ptr, h->H.ptr, h->Ht.ptr, h->B, s);
   }
   // mixed precision: FP32 copies of the interface blocks for the inner PCG
   h->mixed = opts && opts->precision == IETI_PREC_MIXED;
@@ -913,10 +1077,17 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
   h->factor_ms = ms;
   prof_collect(h);
-  if (h->flags_h[0] > 0)
-    return fail(IETI_ERR_NOT_SPD, "non-positive pivot in the local factorisation of subdomain " +
-                                      std::to_string(h->flags_h[0] - 1));
-  if (h->flags_h[4] > 0) return fail(IETI_ERR_NOT_SPD, "coarse matrix is not positive definite");
+  if (h->flags_h[0] > 0) {
+    const int k = h->flags_h[0] - 1;
+    std::string where = "subdomain " + std::to_string(k);
+    if (M.batch())
+      where = "subdomain " + std::to_string(k - M.probs[M.sub_prob[k]].sub_base) + " of problem " +
+              std::to_string(M.sub_prob[k]);
+    return fail(IETI_ERR_NOT_SPD, "non-positive pivot in the local factorisation of " + where);
+  }
+  if (h->flags_h[4] > 0)
+    return fail(IETI_ERR_NOT_SPD, "coarse matrix of problem " + std::to_string(h->flags_h[4] - 1) +
+                                      " is not positive definite");
   const int forced = opts ? opts->gemv_variant : 0;
   if (forced < 0 || forced > D::GEMV_VARIANTS) return fail(IETI_ERR_INVALID_ARG, "gemv_variant out of range");
   if ((rc = choose_gemv(h, forced, 0))) return rc;
@@ -942,7 +1113,9 @@ int ieti_get_sizes(const ieti_handle* h, int64_t* sizes) {
     sum_r += int64_t(s.r_edges.size());
     max_nI = std::max<int64_t>(max_nI, int64_t(s.I_local.size()));
   }
-  const int64_t v[8] = {m.mesh.n_edges, m.n_g, sum_r, m.m_r, m.n_gp, m.n_sub, m.mesh.n_nodes, max_nI};
+  int64_t n_nodes = 0;
+  for (const auto& me : m.meshes) n_nodes += me.n_nodes;
+  const int64_t v[8] = {m.n_edges_total, m.n_g, sum_r, m.m_r, m.n_gp, m.n_sub, n_nodes, max_nI};
   std::memcpy(sizes, v, sizeof(v));
   return IETI_OK;
 }
@@ -951,6 +1124,7 @@ int ieti_get_maps(const ieti_handle* h, uint8_t* weight, uint8_t* tree_mask, uin
                   int64_t* primal_edges, int64_t* mult_rows, int64_t* sub_offsets, int64_t* sub_r_edges) {
   if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
   const auto& m = h->model;
+  if (m.batch()) return fail(IETI_ERR_STATE, "the integer maps are per problem; not available on a batch handle");
   if (weight) std::copy(m.weight.begin(), m.weight.end(), weight);
   if (tree_mask) std::copy(m.tree.begin(), m.tree.end(), tree_mask);
   if (dirichlet) std::copy(m.dirichlet.begin(), m.dirichlet.end(), dirichlet);

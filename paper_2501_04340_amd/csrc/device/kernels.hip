@@ -372,27 +372,48 @@ __global__ void k_sum_sources(const double* src, const int64_t* ptr, const int64
   out[o] = s;
 }
 
-__global__ void k_build_G(const double* Phi, const int64_t* row_src, const int64_t* slot_phi_row,
-                          const int32_t* I_sub, const int32_t* glob2loc, int64_t m_r, int64_t n_gp, double* G) {
-  const int64_t gid = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (gid >= m_r * n_gp) return;
-  const int64_t row = gid / n_gp, c = gid % n_gp;
-  double g = 0.0;
-  for (int side = 0; side < 2; ++side) {
-    const int64_t slot = row_src[2 * row + side];
-    const int k = I_sub[slot];
-    const int loc = glob2loc[int64_t(k) * n_gp + c];
-    if (loc >= 0) g += (side == 0 ? 1.0 : -1.0) * Phi[slot_phi_row[slot] + loc];
-  }
-  G[gid] = g;
+// Problems of a batch: descriptor pd[PD_N * p + field] (see kernels.hpp);
+// row blocks blk[2 b] = first multiplier row, blk[2 b + 1] = problem, each
+// block holding at most 256 rows of one problem.
+__device__ inline int64_t blk_rows(const int64_t* blk, const int64_t* pd, int64_t b, int64_t* row0) {
+  *row0 = blk[2 * b];
+  const int64_t mr1 = pd[PD_N * blk[2 * b + 1] + PD_MR1];
+  return (mr1 - *row0) < 256 ? (mr1 - *row0) : 256;
 }
 
-// Cholesky of a small dense row-major matrix by one block (lower factor).
-__global__ __launch_bounds__(256) void k_chol_small(double* A, int64_t n, int* err) {
+// G_p[row][c] = sum over the row's two subdomains of +-Phi[slot][local primal of c]
+// (thread per multiplier row, rows of one problem per block)
+__global__ void k_build_G(const double* Phi, const int64_t* row_src, const int64_t* slot_phi_row,
+                          const int32_t* I_sub, const int32_t* g2l, const int64_t* g2l_off, double* G,
+                          const int64_t* pd, const int64_t* blk) {
+  int64_t row0;
+  const int64_t nrow = blk_rows(blk, pd, blockIdx.x, &row0);
+  if (int64_t(threadIdx.x) >= nrow) return;
+  const int64_t* P = pd + PD_N * blk[2 * blockIdx.x + 1];
+  const int64_t row = row0 + threadIdx.x, n_gp = P[PD_NGP];
+  double* Gr = G + P[PD_H] + (row - P[PD_MR0]) * n_gp;
+  for (int64_t c = 0; c < n_gp; ++c) {
+    double g = 0.0;
+    for (int side = 0; side < 2; ++side) {
+      const int64_t slot = row_src[2 * row + side];
+      const int k = I_sub[slot];
+      const int loc = g2l[g2l_off[k] + c];
+      if (loc >= 0) g += (side == 0 ? 1.0 : -1.0) * Phi[slot_phi_row[slot] + loc];
+    }
+    Gr[c] = g;
+  }
+}
+
+// Cholesky of each problem's dense row-major coarse block (lower factor), one
+// block of threads per problem.
+__global__ __launch_bounds__(256) void k_chol_small(double* Abase, const int64_t* pd, int* err) {
+  const int64_t* P = pd + PD_N * blockIdx.x;
+  const int64_t n = P[PD_NGP];
+  double* A = Abase + P[PD_SPI];
   for (int64_t k = 0; k < n; ++k) {
     const double d = A[k * n + k];
     const double piv = d > 0.0 ? sqrt(d) : 1.0;
-    if (!(d > 0.0) && threadIdx.x == 0) atomicMax(err, 1);
+    if (!(d > 0.0) && threadIdx.x == 0) atomicMax(err, int(blockIdx.x) + 1);
     __syncthreads();
     for (int64_t i = k + threadIdx.x; i < n; i += 256) {
       if (i == k) A[k * n + k] = piv;
@@ -412,32 +433,48 @@ __global__ __launch_bounds__(256) void k_chol_small(double* A, int64_t n, int* e
   }
 }
 
-// H[row] = G[row] L^{-T} (each row independently), also stored transposed.
-__global__ void k_solve_rows_LT(const double* L, int64_t n, const double* G, int64_t m, double* H, double* Ht) {
-  const int64_t row = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (row >= m) return;
+// H_p[row] = G_p[row] L_p^{-T} (each row independently), also stored transposed.
+__global__ void k_solve_rows_LT(const double* L, const double* G, double* H, double* Ht, const int64_t* pd,
+                                const int64_t* blk) {
+  int64_t row0;
+  const int64_t nrow = blk_rows(blk, pd, blockIdx.x, &row0);
+  if (int64_t(threadIdx.x) >= nrow) return;
+  const int64_t* P = pd + PD_N * blk[2 * blockIdx.x + 1];
+  const int64_t n = P[PD_NGP], m = P[PD_MR1] - P[PD_MR0], rl = row0 + threadIdx.x - P[PD_MR0];
+  const double* Lp = L + P[PD_SPI];
+  const double* Gr = G + P[PD_H] + rl * n;
+  double* Hr = H + P[PD_H] + rl * n;
+  double* Htp = Ht + P[PD_HT];
   for (int64_t c = 0; c < n; ++c) {
-    double s = G[row * n + c];
-    for (int64_t q = 0; q < c; ++q) s -= H[row * n + q] * L[c * n + q];
-    const double h = s / L[c * n + c];
-    H[row * n + c] = h;
-    Ht[c * m + row] = h;
+    double s = Gr[c];
+    for (int64_t q = 0; q < c; ++q) s -= Hr[q] * Lp[c * n + q];
+    const double h = s / Lp[c * n + c];
+    Hr[c] = h;
+    Htp[c * m + rl] = h;
   }
 }
 
-__global__ void k_tri_small(const double* L, int64_t n, const double* in, double* out, int transposed) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// out_p = L_p^{-1} in_p (or L_p^{-T} in_p) per problem, one thread per problem.
+__global__ void k_tri_small(const double* L, const double* in, double* out, int transposed, const int64_t* pd,
+                            int n_prob) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_prob) return;
+  const int64_t* P = pd + PD_N * p;
+  const int64_t n = P[PD_NGP], g0 = P[PD_GP0];
+  const double* Lp = L + P[PD_SPI];
+  const double* x = in + g0;
+  double* y = out + g0;
   if (!transposed) {
     for (int64_t c = 0; c < n; ++c) {
-      double s = in[c];
-      for (int64_t q = 0; q < c; ++q) s -= L[c * n + q] * out[q];
-      out[c] = s / L[c * n + c];
+      double s = x[c];
+      for (int64_t q = 0; q < c; ++q) s -= Lp[c * n + q] * y[q];
+      y[c] = s / Lp[c * n + c];
     }
   } else {
     for (int64_t c = n - 1; c >= 0; --c) {
-      double s = in[c];
-      for (int64_t q = c + 1; q < n; ++q) s -= L[q * n + c] * out[q];
-      out[c] = s / L[c * n + c];
+      double s = x[c];
+      for (int64_t q = c + 1; q < n; ++q) s -= Lp[q * n + c] * y[q];
+      y[c] = s / Lp[c * n + c];
     }
   }
 }
@@ -485,8 +522,8 @@ struct Vec16<float> {
 // Matrix entries stored as MT (double or float), vector and accumulation in FP64.
 template <typename MT, int RPW, int U, bool NT>
 __global__ __launch_bounds__(256) void k_gemv(const MT* M, const int64_t* task, const double* xg, double* v,
-                                              double* part, const int* done) {
-  if (done && *done) return;
+                                              double* part, const int* done, const int32_t* task_prob) {
+  if (done && done[task_prob[blockIdx.x]]) return;
   using V = Vec16<MT>;
   using T = typename V::T;
   extern __shared__ __align__(16) double xs[];
@@ -591,67 +628,90 @@ __device__ inline double coarse_from_partials(const double* part_t, int64_t n_gp
   return tt;
 }
 
-__global__ __launch_bounds__(256) void k_coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x,
-                                                        double* out) {
+// out[c] = sum over the problem's rows of Ht_p[c][row] x[row] (block per global primal index)
+__global__ __launch_bounds__(256) void k_coarse_project(const double* Ht, const double* x, double* out,
+                                                        const int64_t* pd, const int32_t* cprob) {
   __shared__ double red[4];
   const int64_t c = blockIdx.x;
+  const int64_t* P = pd + PD_N * cprob[c];
+  const int64_t m = P[PD_MR1] - P[PD_MR0], cl = c - P[PD_GP0];
+  const double* Hc = Ht + P[PD_HT] + cl * m;
+  const double* xp = x + P[PD_MR0];
   double s = 0.0;
-  for (int64_t row = threadIdx.x; row < m_r; row += 256) s += Ht[c * m_r + row] * x[row];
+  for (int64_t row = threadIdx.x; row < m; row += 256) s += Hc[row] * xp[row];
   s = block_sum256(s, red);
   if (threadIdx.x == 0) out[c] = s;
 }
 
-// q[row] = v[+1 slot] - v[-1 slot] + sum_c H[row][c] t[c]  (H may be null)
-__global__ void k_combine(const double* v, const int64_t* row_src, int64_t m_r, const double* H, const double* t,
-                          int64_t n_gp, double* q) {
-  const int64_t row = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (row >= m_r) return;
+// sum_c H_p[row][c] t[c] for one row of problem P
+__device__ inline double coarse_row(const double* H, const int64_t* P, int64_t row, const double* t) {
+  const int64_t n_gp = P[PD_NGP];
+  const double* Hr = H + P[PD_H] + (row - P[PD_MR0]) * n_gp;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  int64_t c = 0;
+  for (; c + 3 < n_gp; c += 4) {
+    c0 += Hr[c] * t[c];
+    c1 += Hr[c + 1] * t[c + 1];
+    c2 += Hr[c + 2] * t[c + 2];
+    c3 += Hr[c + 3] * t[c + 3];
+  }
+  for (; c < n_gp; ++c) c0 += Hr[c] * t[c];
+  return (c0 + c1) + (c2 + c3);
+}
+
+// q[row] = v[+1 slot] - v[-1 slot] + sum_c H_p[row][c] t_p[c]  (H may be null)
+__global__ __launch_bounds__(256) void k_combine(const double* v, const int64_t* row_src, const double* H,
+                                                 const double* t, double* q, const int64_t* pd, const int64_t* blk) {
+  int64_t row0;
+  const int64_t nrow = blk_rows(blk, pd, blockIdx.x, &row0);
+  if (int64_t(threadIdx.x) >= nrow) return;
+  const int64_t* P = pd + PD_N * blk[2 * blockIdx.x + 1];
+  const int64_t row = row0 + threadIdx.x;
   double val = v[row_src[2 * row]] - v[row_src[2 * row + 1]];
-  if (H)
-    for (int64_t c = 0; c < n_gp; ++c) val += H[row * n_gp + c] * t[c];
+  if (H && P[PD_NGP] > 0) val += coarse_row(H, P, row, t + P[PD_GP0]);
   q[row] = val;
 }
 
-// PCG, first half of an iteration (after v = Sinv_k B_k^T p):
-// t = H^T p from the block partials, p^T F p = sum xg.v + t.t,
-// alpha = rz / p^T F p, q = B v + H t, lambda += alpha p, r -= alpha q,
-// gather B^T r for the preconditioner, partials of ||r||^2.
-// scal: [0..1] rz (ping-pong by parity), [2] alpha, [3] beta, [4] tol^2, [5] ||r||^2
-__global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* row_src, int64_t m_r, const double* H,
-                                               const double* part_t, int64_t n_gp, int nblk, const double* part_g,
-                                               int ngemv, const double* p, double* lam, double* r, double* xg_r,
-                                               double* part_rr, double* scal, int par, int* done, int* err) {
-  if (*done) return;
+// PCG, first half of an iteration (after v = Sinv_k B_k^T p), per problem p of
+// the block: t = H_p^T p from the block partials, p^T F p = sum xg.v + t.t
+// over the problem's GEMV tasks, alpha = rz / p^T F p, q = B v + H t,
+// lambda += alpha p, r -= alpha q, gather B^T r for the preconditioner,
+// partials of ||r||^2.  scal + 8 p: [0..1] rz (ping-pong by parity),
+// [2] alpha, [3] beta, [4] tol^2, [5] ||r||^2.  gt: GEMV task range index.
+__global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* row_src, const double* H,
+                                               const double* part_t, const double* part_g, const double* p,
+                                               double* lam, double* r, double* xg_r, double* part_rr, double* scal,
+                                               int par, int* done, int* err, const int64_t* pd, const int64_t* blk,
+                                               int gt) {
+  const int64_t b = blockIdx.x, pid = blk[2 * b + 1];
+  if (done[pid]) return;
   extern __shared__ double tl[];
   __shared__ double red[4];
   __shared__ double acc4[4][64];
-  const double tt = coarse_from_partials(part_t, n_gp, nblk, tl, acc4);
+  const int64_t* P = pd + PD_N * pid;
+  const int64_t n_gp = P[PD_NGP];
+  const double tt = coarse_from_partials(part_t + P[PD_PT], n_gp, int(P[PD_B1] - P[PD_B0]), tl, acc4);
   const double tt_all = block_sum256(tt, red);
-  const double pq = reduce_partials_fast(part_g, ngemv, red) + tt_all;
+  const double pq = reduce_partials_fast(part_g + P[PD_T0 + 2 * gt], int(P[PD_T0 + 2 * gt + 1] - P[PD_T0 + 2 * gt]),
+                                         red) +
+                    tt_all;
+  double* sc = scal + 8 * pid;
   if (!(pq > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (b == P[PD_B0] && threadIdx.x == 0) {
       *err = 1;
-      *done = 3;
+      done[pid] = 3;
     }
     return;
   }
-  const double alpha = scal[par] / pq;
-  const int64_t row = blockIdx.x * int64_t(256) + threadIdx.x;
+  const double alpha = sc[par] / pq;
+  int64_t row0;
+  const int64_t nrow = blk_rows(blk, pd, b, &row0);
   double rr = 0.0;
-  if (row < m_r) {
+  if (int64_t(threadIdx.x) < nrow) {
+    const int64_t row = row0 + threadIdx.x;
     const int64_t s0 = row_src[2 * row], s1 = row_src[2 * row + 1];
     double q = v[s0] - v[s1];
-    const double* Hr = H + row * n_gp;
-    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-    int64_t c = 0;
-    for (; c + 3 < n_gp; c += 4) {
-      c0 += Hr[c] * tl[c];
-      c1 += Hr[c + 1] * tl[c + 1];
-      c2 += Hr[c + 2] * tl[c + 2];
-      c3 += Hr[c + 3] * tl[c + 3];
-    }
-    for (; c < n_gp; ++c) c0 += Hr[c] * tl[c];
-    q += (c0 + c1) + (c2 + c3);
+    if (n_gp > 0) q += coarse_row(H, P, row, tl);
     lam[row] += alpha * p[row];
     const double rn = r[row] - alpha * q;
     r[row] = rn;
@@ -660,42 +720,48 @@ __global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* r
     xg_r[s1] = -rn;
   }
   const double srr = block_sum256(rr, red);
-  if (threadIdx.x == 0) part_rr[blockIdx.x] = srr;
-  if (blockIdx.x == 0 && threadIdx.x == 0) scal[2] = alpha;
+  if (threadIdx.x == 0) part_rr[b] = srr;
+  if (b == P[PD_B0] && threadIdx.x == 0) sc[2] = alpha;
 }
 
-// PCG, second half (after w = S_k B_k^T r): convergence test on ||r||^2,
-// rz = sum xg_r.w, z = B w, beta = rz / rz_old, p = z + beta p, gather
-// B^T p for the next operator GEMV and the block partials of H^T p.
-// init = 1 starts the recurrence (beta = 0, no convergence test).
-__global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* row_src, int64_t m_r, const double* H,
-                                               int64_t n_gp, const double* part_g, int ngemv, const double* part_rr,
-                                               int nblk, double* p, double* z, double* xg_p, double* part_t,
-                                               double* scal, int par, int* done, int* iters, int init) {
-  if (*done) return;
+// PCG, second half (after w = S_k B_k^T r), per problem p of the block:
+// convergence test on ||r||^2, rz = sum xg_r.w, z = B w, beta = rz / rz_old,
+// p = z + beta p, gather B^T p for the next operator GEMV and the block
+// partials of H_p^T p.  init = 1 starts the recurrence (beta = 0, no test).
+__global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* row_src, const double* H,
+                                               const double* part_g, const double* part_rr, double* p, double* z,
+                                               double* xg_p, double* part_t, double* scal, int par, int* done,
+                                               int* iters, int init, const int64_t* pd, const int64_t* blk, int gt) {
+  const int64_t b = blockIdx.x, pid = blk[2 * b + 1];
+  if (done[pid]) return;
   __shared__ double red[4];
   __shared__ double pl[256];
-  const double rz = reduce_partials_fast(part_g, ngemv, red);
+  const int64_t* P = pd + PD_N * pid;
+  double* sc = scal + 8 * pid;
+  const bool first = b == P[PD_B0];
+  const double rz = reduce_partials_fast(part_g + P[PD_T0 + 2 * gt], int(P[PD_T0 + 2 * gt + 1] - P[PD_T0 + 2 * gt]),
+                                         red);
   if (!init) {
-    const double rr = reduce_partials_fast(part_rr, nblk, red);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      *iters += 1;
-      scal[5] = rr;
+    const double rr = reduce_partials_fast(part_rr + P[PD_B0], int(P[PD_B1] - P[PD_B0]), red);
+    if (first && threadIdx.x == 0) {
+      iters[pid] += 1;
+      sc[5] = rr;
     }
-    if (rr <= scal[4]) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) *done = 1;
+    if (rr <= sc[4]) {
+      if (first && threadIdx.x == 0) done[pid] = 1;
       return;
     }
   }
-  const double beta = init ? 0.0 : rz / scal[par];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    scal[init ? 0 : 1 - par] = rz;
-    scal[3] = beta;
+  const double beta = init ? 0.0 : rz / sc[par];
+  if (first && threadIdx.x == 0) {
+    sc[init ? 0 : 1 - par] = rz;
+    sc[3] = beta;
   }
-  const int64_t base = blockIdx.x * int64_t(256);
-  const int64_t row = base + threadIdx.x;
+  int64_t row0;
+  const int64_t nrow = blk_rows(blk, pd, b, &row0);
   double pv = 0.0;
-  if (row < m_r) {
+  if (int64_t(threadIdx.x) < nrow) {
+    const int64_t row = row0 + threadIdx.x;
     const int64_t s0 = row_src[2 * row], s1 = row_src[2 * row + 1];
     const double zz = w[s0] - w[s1];
     z[row] = zz;
@@ -706,22 +772,23 @@ __global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* r
   }
   pl[threadIdx.x] = pv;
   __syncthreads();
-  // block partials of H^T p: 64 columns per pass, four row quarters per column
+  // block partials of H_p^T p: 64 columns per pass, four row quarters per column
   __shared__ double acc4[4][64];
-  const int64_t nrow = (m_r - base) < 256 ? (m_r - base) : 256;
+  const int64_t n_gp = P[PD_NGP];
+  const double* Hb = H + P[PD_H] + (row0 - P[PD_MR0]) * n_gp;
+  double* pt = part_t + P[PD_PT] + (b - P[PD_B0]) * n_gp;
   const int c0 = threadIdx.x & 63, q = threadIdx.x >> 6;
   for (int64_t cb = 0; cb < n_gp; cb += 64) {
     const int64_t c = cb + c0;
-    double sc = 0.0;
+    double s = 0.0;
     if (c < n_gp) {
       const int64_t i0 = 64 * q, i1 = (64 * q + 64) < nrow ? 64 * q + 64 : nrow;
 #pragma unroll 8
-      for (int64_t i = i0; i < i1; ++i) sc += H[(base + i) * n_gp + c] * pl[i];
+      for (int64_t i = i0; i < i1; ++i) s += Hb[i * n_gp + c] * pl[i];
     }
-    acc4[q][c0] = sc;
+    acc4[q][c0] = s;
     __syncthreads();
-    if (q == 0 && c < n_gp)
-      part_t[blockIdx.x * n_gp + c] = (acc4[0][c0] + acc4[1][c0]) + (acc4[2][c0] + acc4[3][c0]);
+    if (q == 0 && c < n_gp) pt[c] = (acc4[0][c0] + acc4[1][c0]) + (acc4[2][c0] + acc4[3][c0]);
     __syncthreads();
   }
 }
@@ -765,13 +832,28 @@ __global__ void k_write_primal(const double* pglob, const int64_t* primal_edges,
   if (i < n_gp) a[primal_edges[i]] = pglob[i];
 }
 
-// b[row] = e[row] - sum_c H[row][c] w[c]
-__global__ void k_axpy_rows(const double* H, const double* w, int64_t m, int64_t n, const double* e, double* b) {
-  const int64_t row = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (row >= m) return;
-  double s = 0.0;
-  for (int64_t c = 0; c < n; ++c) s += H[row * n + c] * w[c];
+// b[row] = e[row] - sum_c H_p[row][c] w_p[c]
+__global__ __launch_bounds__(256) void k_axpy_rows(const double* H, const double* w, const double* e, double* b,
+                                                   const int64_t* pd, const int64_t* blk) {
+  int64_t row0;
+  const int64_t nrow = blk_rows(blk, pd, blockIdx.x, &row0);
+  if (int64_t(threadIdx.x) >= nrow) return;
+  const int64_t* P = pd + PD_N * blk[2 * blockIdx.x + 1];
+  const int64_t row = row0 + threadIdx.x;
+  const double s = P[PD_NGP] > 0 ? coarse_row(H, P, row, w + P[PD_GP0]) : 0.0;
   b[row] = e[row] - s;
+}
+
+// part[b] = sum over the rows of block b of x y
+__global__ __launch_bounds__(256) void k_dot_blocks(const double* x, const double* y, double* part, const int64_t* pd,
+                                                    const int64_t* blk) {
+  __shared__ double red[4];
+  int64_t row0;
+  const int64_t nrow = blk_rows(blk, pd, blockIdx.x, &row0);
+  const int64_t row = row0 + threadIdx.x;
+  const double v = int64_t(threadIdx.x) < nrow ? x[row] * y[row] : 0.0;
+  const double sum = block_sum256(v, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = sum;
 }
 
 __global__ void k_axpby(const double* x, const double* y, double* out, double a, double b, int64_t n) {
@@ -784,13 +866,6 @@ __global__ void k_vec_copy(const double* x, double* y, int64_t n) {
     y[i] = x[i];
 }
 
-__global__ __launch_bounds__(256) void k_dot_partial(const double* x, const double* y, int64_t n, double* part) {
-  __shared__ double red[4];
-  const int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
-  const double v = (i < n) ? x[i] * y[i] : 0.0;
-  const double s = block_sum256(v, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
 
 int grid_for(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
@@ -840,23 +915,23 @@ void sum_sources(const double* src, const int64_t* ptr, const int64_t* idx, int6
   hipLaunchKernelGGL(k_sum_sources, dim3(grid_for(nout, 256)), dim3(256), 0, s, src, ptr, idx, nout, out);
 }
 void build_G(const double* Phi, const int64_t* row_src, const int64_t* slot_phi_row, const int32_t* I_sub,
-             const int32_t* glob2loc, int64_t m_r, int64_t n_gp, double* G, hipStream_t s) {
-  const int64_t n = m_r * n_gp;
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_build_G, dim3((n + 255) / 256), dim3(256), 0, s, Phi, row_src, slot_phi_row, I_sub, glob2loc,
-                     m_r, n_gp, G);
+             const int32_t* g2l, const int64_t* g2l_off, double* G, const Batch& B, hipStream_t s) {
+  if (B.n_gp_total <= 0 || B.n_blk <= 0) return;
+  hipLaunchKernelGGL(k_build_G, dim3(B.n_blk), dim3(256), 0, s, Phi, row_src, slot_phi_row, I_sub, g2l, g2l_off, G,
+                     B.pd, B.blk);
 }
-void chol_small(double* A, int64_t n, int* err, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(256), 0, s, A, n, err);
+void chol_small(double* A, int* err, const Batch& B, hipStream_t s) {
+  if (B.n_gp_total <= 0) return;
+  hipLaunchKernelGGL(k_chol_small, dim3(B.n_prob), dim3(256), 0, s, A, B.pd, err);
 }
-void solve_rows_LT(const double* L, int64_t n, const double* G, int64_t m, double* H, double* Ht, hipStream_t s) {
-  if (n <= 0 || m <= 0) return;
-  hipLaunchKernelGGL(k_solve_rows_LT, dim3((m + 255) / 256), dim3(256), 0, s, L, n, G, m, H, Ht);
+void solve_rows_LT(const double* L, const double* G, double* H, double* Ht, const Batch& B, hipStream_t s) {
+  if (B.n_gp_total <= 0 || B.n_blk <= 0) return;
+  hipLaunchKernelGGL(k_solve_rows_LT, dim3(B.n_blk), dim3(256), 0, s, L, G, H, Ht, B.pd, B.blk);
 }
-void tri_small(const double* L, int64_t n, const double* in, double* out, bool transposed, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_tri_small, dim3(1), dim3(64), 0, s, L, n, in, out, transposed ? 1 : 0);
+void tri_small(const double* L, const double* in, double* out, bool transposed, const Batch& B, hipStream_t s) {
+  if (B.n_gp_total <= 0) return;
+  hipLaunchKernelGGL(k_tri_small, dim3((B.n_prob + 63) / 64), dim3(64), 0, s, L, in, out, transposed ? 1 : 0, B.pd,
+                     B.n_prob);
 }
 void gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg, hipStream_t s) {
   if (m_r <= 0) return;
@@ -870,68 +945,76 @@ GemvShape gemv_shape(int variant) {
 
 template <typename MT, int RPW, int U, bool NT>
 void gemv_launch(const MT* M, const int64_t* task, int64_t ntask, size_t lds, const double* xg, double* v,
-                 double* part, const int* done, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                 double* part, const int* done, const int32_t* tprob, hipStream_t s, hipEvent_t ev_start,
+                 hipEvent_t ev_stop) {
   if (ev_start)
     hipExtLaunchKernelGGL((k_gemv<MT, RPW, U, NT>), dim3(ntask), dim3(256), lds, s, ev_start, ev_stop, 0, M, task,
-                          xg, v, part, done);
+                          xg, v, part, done, tprob);
   else
-    hipLaunchKernelGGL((k_gemv<MT, RPW, U, NT>), dim3(ntask), dim3(256), lds, s, M, task, xg, v, part, done);
+    hipLaunchKernelGGL((k_gemv<MT, RPW, U, NT>), dim3(ntask), dim3(256), lds, s, M, task, xg, v, part, done, tprob);
 }
 
 template <typename MT, int RPW>
 void gemv_dispatch_u(int u, int nt, const MT* M, const int64_t* task, int64_t ntask, size_t lds, const double* xg,
-                     double* v, double* part, const int* done, hipStream_t s, hipEvent_t a, hipEvent_t b) {
-  if (u == 1 && !nt) gemv_launch<MT, RPW, 1, false>(M, task, ntask, lds, xg, v, part, done, s, a, b);
-  else if (u == 1) gemv_launch<MT, RPW, 1, true>(M, task, ntask, lds, xg, v, part, done, s, a, b);
-  else if (!nt) gemv_launch<MT, RPW, 2, false>(M, task, ntask, lds, xg, v, part, done, s, a, b);
-  else gemv_launch<MT, RPW, 2, true>(M, task, ntask, lds, xg, v, part, done, s, a, b);
+                     double* v, double* part, const int* done, const int32_t* tp, hipStream_t s, hipEvent_t a,
+                     hipEvent_t b) {
+  if (u == 1 && !nt) gemv_launch<MT, RPW, 1, false>(M, task, ntask, lds, xg, v, part, done, tp, s, a, b);
+  else if (u == 1) gemv_launch<MT, RPW, 1, true>(M, task, ntask, lds, xg, v, part, done, tp, s, a, b);
+  else if (!nt) gemv_launch<MT, RPW, 2, false>(M, task, ntask, lds, xg, v, part, done, tp, s, a, b);
+  else gemv_launch<MT, RPW, 2, true>(M, task, ntask, lds, xg, v, part, done, tp, s, a, b);
 }
 
 template <typename MT>
 void gemv_impl(const MT* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
-               double* part, const int* done, hipStream_t s, int variant, hipEvent_t ev_start, hipEvent_t ev_stop) {
+               double* part, const int* done, const int32_t* tp, hipStream_t s, int variant, hipEvent_t ev_start,
+               hipEvent_t ev_stop) {
   if (ntask <= 0) return;
+  if (!done) tp = nullptr;
   const size_t lds = size_t(max_ld) * sizeof(double);
   const GemvShape g = gemv_shape(variant);
-  if (g.rpw == 2) gemv_dispatch_u<MT, 2>(g.unroll, g.nt, M, task, ntask, lds, xg, v, part, done, s, ev_start, ev_stop);
+  if (g.rpw == 2)
+    gemv_dispatch_u<MT, 2>(g.unroll, g.nt, M, task, ntask, lds, xg, v, part, done, tp, s, ev_start, ev_stop);
   else if (g.rpw == 4)
-    gemv_dispatch_u<MT, 4>(g.unroll, g.nt, M, task, ntask, lds, xg, v, part, done, s, ev_start, ev_stop);
-  else gemv_dispatch_u<MT, 8>(g.unroll, g.nt, M, task, ntask, lds, xg, v, part, done, s, ev_start, ev_stop);
+    gemv_dispatch_u<MT, 4>(g.unroll, g.nt, M, task, ntask, lds, xg, v, part, done, tp, s, ev_start, ev_stop);
+  else gemv_dispatch_u<MT, 8>(g.unroll, g.nt, M, task, ntask, lds, xg, v, part, done, tp, s, ev_start, ev_stop);
 }
 void gemv(const double* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
-          double* part, const int* done, hipStream_t s, int variant, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  gemv_impl(M, task, ntask, max_ld, xg, v, part, done, s, variant, ev_start, ev_stop);
+          double* part, const int* done, const int32_t* task_prob, hipStream_t s, int variant, hipEvent_t ev_start,
+          hipEvent_t ev_stop) {
+  gemv_impl(M, task, ntask, max_ld, xg, v, part, done, task_prob, s, variant, ev_start, ev_stop);
 }
 void gemv(const float* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
-          double* part, const int* done, hipStream_t s, int variant, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  gemv_impl(M, task, ntask, max_ld, xg, v, part, done, s, variant, ev_start, ev_stop);
+          double* part, const int* done, const int32_t* task_prob, hipStream_t s, int variant, hipEvent_t ev_start,
+          hipEvent_t ev_stop) {
+  gemv_impl(M, task, ntask, max_ld, xg, v, part, done, task_prob, s, variant, ev_start, ev_stop);
 }
 void to_float(const double* in, float* out, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_to_float, dim3(grid_for(n, 256)), dim3(256), 0, s, in, out, n);
 }
-void coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x, double* out, hipStream_t s) {
-  if (n_gp <= 0) return;
-  hipLaunchKernelGGL(k_coarse_project, dim3(n_gp), dim3(256), 0, s, Ht, n_gp, m_r, x, out);
+void coarse_project(const double* Ht, const double* x, double* out, const int32_t* cprob, const Batch& B,
+                    hipStream_t s) {
+  if (B.n_gp_total <= 0) return;
+  hipLaunchKernelGGL(k_coarse_project, dim3(B.n_gp_total), dim3(256), 0, s, Ht, x, out, B.pd, cprob);
 }
-int combine_blocks(int64_t m_r) { return int((m_r + 255) / 256); }
-void combine(const double* v, const int64_t* row_src, int64_t m_r, const double* H, const double* t, int64_t n_gp,
-             double* q, hipStream_t s) {
-  if (m_r <= 0) return;
-  hipLaunchKernelGGL(k_combine, dim3(combine_blocks(m_r)), dim3(256), 0, s, v, row_src, m_r, H, t, n_gp, q);
+void combine(const double* v, const int64_t* row_src, const double* H, const double* t, double* q, const Batch& B,
+             hipStream_t s) {
+  if (B.n_blk <= 0) return;
+  hipLaunchKernelGGL(k_combine, dim3(B.n_blk), dim3(256), 0, s, v, row_src, H, t, q, B.pd, B.blk);
 }
-void pcg_F(const double* v, const int64_t* row_src, int64_t m_r, const double* H, const double* part_t,
-           int64_t n_gp, int nblk, const double* part_g, int ngemv, const double* p, double* lam, double* r,
-           double* xg_r, double* part_rr, double* scal, int par, int* done, int* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_F, dim3(combine_blocks(m_r)), dim3(256), size_t(n_gp > 0 ? n_gp : 1) * sizeof(double), s,
-                     v, row_src, m_r, H, part_t, n_gp, nblk, part_g, ngemv, p, lam, r, xg_r, part_rr, scal, par, done,
-                     err);
+void pcg_F(const double* v, const int64_t* row_src, const double* H, const double* part_t, const double* part_g,
+           const double* p, double* lam, double* r, double* xg_r, double* part_rr, double* scal, int par, int* done,
+           int* err, const Batch& B, int gt, hipStream_t s) {
+  if (B.n_blk <= 0) return;
+  hipLaunchKernelGGL(k_pcg_F, dim3(B.n_blk), dim3(256), size_t(B.max_gp > 0 ? B.max_gp : 1) * sizeof(double), s, v,
+                     row_src, H, part_t, part_g, p, lam, r, xg_r, part_rr, scal, par, done, err, B.pd, B.blk, gt);
 }
-void pcg_M(const double* w, const int64_t* row_src, int64_t m_r, const double* H, int64_t n_gp, const double* part_g,
-           int ngemv, const double* part_rr, int nblk, double* p, double* z, double* xg_p, double* part_t,
-           double* scal, int par, int* done, int* iters, int init, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_M, dim3(combine_blocks(m_r)), dim3(256), 0, s, w, row_src, m_r, H, n_gp, part_g, ngemv,
-                     part_rr, nblk, p, z, xg_p, part_t, scal, par, done, iters, init);
+void pcg_M(const double* w, const int64_t* row_src, const double* H, const double* part_g, const double* part_rr,
+           double* p, double* z, double* xg_p, double* part_t, double* scal, int par, int* done, int* iters, int init,
+           const Batch& B, int gt, hipStream_t s) {
+  if (B.n_blk <= 0) return;
+  hipLaunchKernelGGL(k_pcg_M, dim3(B.n_blk), dim3(256), 0, s, w, row_src, H, part_g, part_rr, p, z, xg_p, part_t,
+                     scal, par, done, iters, init, B.pd, B.blk, gt);
 }
 void gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out, hipStream_t s) {
   if (n <= 0) return;
@@ -957,9 +1040,9 @@ void write_output(const double* y, const int64_t* src, const int64_t* edge, int6
   if (n_gp > 0)
     hipLaunchKernelGGL(k_write_primal, dim3((n_gp + 255) / 256), dim3(256), 0, s, pglob, primal_edges, n_gp, a);
 }
-void axpy_rows(const double* H, const double* w, int64_t m, int64_t n, const double* e, double* b, hipStream_t s) {
-  if (m <= 0) return;
-  hipLaunchKernelGGL(k_axpy_rows, dim3((m + 255) / 256), dim3(256), 0, s, H, w, m, n, e, b);
+void axpy_rows(const double* H, const double* w, const double* e, double* b, const Batch& B, hipStream_t s) {
+  if (B.n_blk <= 0) return;
+  hipLaunchKernelGGL(k_axpy_rows, dim3(B.n_blk), dim3(256), 0, s, H, w, e, b, B.pd, B.blk);
 }
 void axpby(const double* x, const double* y, double* out, double a, double b, int64_t n, hipStream_t s) {
   if (n <= 0) return;
@@ -969,9 +1052,9 @@ void vec_copy(const double* x, double* y, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_vec_copy, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
 }
-void dot_partial(const double* x, const double* y, int64_t n, double* part, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_dot_partial, dim3((n + 255) / 256), dim3(256), 0, s, x, y, n, part);
+void dot_blocks(const double* x, const double* y, double* part, const Batch& B, hipStream_t s) {
+  if (B.n_blk <= 0) return;
+  hipLaunchKernelGGL(k_dot_blocks, dim3(B.n_blk), dim3(256), 0, s, x, y, part, B.pd, B.blk);
 }
 
 }  // namespace dev

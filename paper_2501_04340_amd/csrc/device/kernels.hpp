@@ -30,19 +30,41 @@ void trsv_diag(const double* inv, const int64_t* task, int64_t ntask, double* y,
 void trsv_update(const double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, double* y,
                  bool transposed, hipStream_t s);
 
-// ---- coarse problem
+// ---- problems of a batch (a single problem is a batch of one)
+// Per-problem descriptor, PD_N int64 fields per problem: multiplier rows
+// [MR0, MR1), global primal indices [GP0, GP0 + NGP), offsets of its blocks
+// of H / G (row-major (MR1-MR0) x NGP), Ht (NGP x (MR1-MR0)) and of its dense
+// coarse matrix (NGP x NGP), its row blocks [B0, B1), the offset of its
+// H^T p block partials (NGP per row block), and its GEMV task ranges for the
+// three task lists (8, 16, 32 rows per workgroup): [T0 + 2i, T0 + 2i + 1).
+enum {
+  PD_MR0 = 0, PD_MR1, PD_GP0, PD_NGP, PD_H, PD_HT, PD_SPI, PD_B0, PD_B1, PD_PT, PD_T0, PD_N = PD_T0 + 6
+};
+// Row blocks: blk[2b] = first multiplier row, blk[2b+1] = problem; at most 256 rows of one problem each.
+struct Batch {
+  const int64_t* pd = nullptr;
+  const int64_t* blk = nullptr;
+  int n_prob = 0;
+  int n_blk = 0;
+  int64_t n_gp_total = 0;
+  int64_t max_gp = 0;
+};
+
+// ---- coarse problem (per-problem dense blocks)
 void sum_sources(const double* src, const int64_t* ptr, const int64_t* idx, int64_t nout, double* out, hipStream_t s);
+// g2l[g2l_off[k] + c]: local primal slot of the c-th primal of subdomain k's problem, or -1
 void build_G(const double* Phi, const int64_t* row_src, const int64_t* slot_phi_row, const int32_t* I_sub,
-             const int32_t* glob2loc, int64_t m_r, int64_t n_gp, double* G, hipStream_t s);
-void chol_small(double* A, int64_t n, int* err, hipStream_t s);
-void solve_rows_LT(const double* L, int64_t n, const double* G, int64_t m, double* H, double* Ht, hipStream_t s);
-void tri_small(const double* L, int64_t n, const double* in, double* out, bool transposed, hipStream_t s);
+             const int32_t* g2l, const int64_t* g2l_off, double* G, const Batch& B, hipStream_t s);
+void chol_small(double* A, int* err, const Batch& B, hipStream_t s);
+void solve_rows_LT(const double* L, const double* G, double* H, double* Ht, const Batch& B, hipStream_t s);
+void tri_small(const double* L, const double* in, double* out, bool transposed, const Batch& B, hipStream_t s);
 
 // ---- interface operators and PCG (FP64 recurrences)
 // xg[slot(+1)] = x[row], xg[slot(-1)] = -x[row]
 void gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg, hipStream_t s);
 // v[slot] = (M_k xg_k)[slot] for every interface slot; part[block] = sum xg.v over the block's rows.
-// task [matrix row start, first slot, nrows, ld, first slot of the subdomain]; ev_* may be null.
+// task [matrix row start, first slot, nrows, ld, first slot of the subdomain]; done (per problem,
+// may be null) with task_prob skips the tasks of finished problems; ev_* may be null.
 // Launch shapes: 4 waves, each owning rpw rows at a time (4 rpw rows per
 // workgroup = per task), unroll vectors in flight per lane and row, nt =
 // non-temporal loads.  Variant index = 4 * (rpw index in {2,4,8}) + 2 * (unroll - 1) + nt.
@@ -55,25 +77,26 @@ GemvShape gemv_shape(int variant);
 inline int gemv_rows(int variant) { return 4 * gemv_shape(variant).rpw; }
 // Matrix entries stored in FP64 or FP32; vectors and accumulation in FP64.
 void gemv(const double* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
-          double* part, const int* done, hipStream_t s, int variant, hipEvent_t ev_start = nullptr,
-          hipEvent_t ev_stop = nullptr);
+          double* part, const int* done, const int32_t* task_prob, hipStream_t s, int variant,
+          hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 void gemv(const float* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
-          double* part, const int* done, hipStream_t s, int variant, hipEvent_t ev_start = nullptr,
-          hipEvent_t ev_stop = nullptr);
+          double* part, const int* done, const int32_t* task_prob, hipStream_t s, int variant,
+          hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 void to_float(const double* in, float* out, int64_t n, hipStream_t s);
-// out[c] = sum_row Ht[c][row] * x[row]
-void coarse_project(const double* Ht, int64_t n_gp, int64_t m_r, const double* x, double* out, hipStream_t s);
-// q[row] = v[src0] - v[src1] + sum_c H[row][c] t[c]  (H may be null)
-void combine(const double* v, const int64_t* row_src, int64_t m_r, const double* H, const double* t, int64_t n_gp,
-             double* q, hipStream_t s);
-int combine_blocks(int64_t m_r);
-// scal: [0..1] rz (ping-pong by iteration parity par), [2] alpha, [3] beta, [4] rtol^2 ||b||^2, [5] ||r||^2
-void pcg_F(const double* v, const int64_t* row_src, int64_t m_r, const double* H, const double* part_t,
-           int64_t n_gp, int nblk, const double* part_g, int ngemv, const double* p, double* lam, double* r,
-           double* xg_r, double* part_rr, double* scal, int par, int* done, int* err, hipStream_t s);
-void pcg_M(const double* w, const int64_t* row_src, int64_t m_r, const double* H, int64_t n_gp, const double* part_g,
-           int ngemv, const double* part_rr, int nblk, double* p, double* z, double* xg_p, double* part_t,
-           double* scal, int par, int* done, int* iters, int init, hipStream_t s);
+// out[c] = sum over problem(c)'s rows of Ht[c][row] x[row]; cprob[c] = problem of global primal c
+void coarse_project(const double* Ht, const double* x, double* out, const int32_t* cprob, const Batch& B,
+                    hipStream_t s);
+// q[row] = v[src0] - v[src1] + sum_c H_p[row][c] t_p[c]  (H may be null)
+void combine(const double* v, const int64_t* row_src, const double* H, const double* t, double* q, const Batch& B,
+             hipStream_t s);
+// scal + 8 p: [0..1] rz (ping-pong by iteration parity par), [2] alpha, [3] beta, [4] tol^2, [5] ||r||^2;
+// done / iters per problem; gt = index of the GEMV task list in use (part_g ranges)
+void pcg_F(const double* v, const int64_t* row_src, const double* H, const double* part_t, const double* part_g,
+           const double* p, double* lam, double* r, double* xg_r, double* part_rr, double* scal, int par, int* done,
+           int* err, const Batch& B, int gt, hipStream_t s);
+void pcg_M(const double* w, const int64_t* row_src, const double* H, const double* part_g, const double* part_rr,
+           double* p, double* z, double* xg_p, double* part_t, double* scal, int par, int* done, int* iters, int init,
+           const Batch& B, int gt, hipStream_t s);
 
 // ---- recovery / rhs helpers
 void gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out, hipStream_t s);
@@ -83,11 +106,13 @@ void recovery_rhs(double* y, const int64_t* krp_ptr, const int64_t* krp_pos, con
                   const int32_t* I_row, const double* I_sign, int64_t nslots, const double* lam, hipStream_t s);
 void write_output(const double* y, const int64_t* src, const int64_t* edge, int64_t n, const double* pglob,
                   const int64_t* primal_edges, int64_t n_gp, double* a, hipStream_t s);
-void axpy_rows(const double* H, const double* w, int64_t m, int64_t n, const double* e, double* b, hipStream_t s);
+// b[row] = e[row] - sum_c H_p[row][c] w_p[c]
+void axpy_rows(const double* H, const double* w, const double* e, double* b, const Batch& B, hipStream_t s);
 void vec_copy(const double* x, double* y, int64_t n, hipStream_t s);
 // out = a x + b y
 void axpby(const double* x, const double* y, double* out, double a, double b, int64_t n, hipStream_t s);
-void dot_partial(const double* x, const double* y, int64_t n, double* part, hipStream_t s);
+// part[b] = sum over row block b of x y
+void dot_blocks(const double* x, const double* y, double* part, const Batch& B, hipStream_t s);
 
 }  // namespace dev
 }  // namespace ieti

@@ -61,6 +61,17 @@ struct Subdomain {
   std::vector<uint8_t> owner;     // per r DOF: 1 if this subdomain writes the global value
 };
 
+// One problem of a batch: its ranges in the batch's concatenated numbering
+// (a single problem is a batch of one with every base 0).
+struct ProblemRange {
+  int64_t edge_base = 0, n_edges = 0;     // coefficients of the output vector
+  int64_t mr_base = 0, m_r = 0;           // multiplier rows
+  int64_t gp_base = 0, n_gp = 0;          // global primal DOFs
+  int64_t sub_base = 0, n_sub = 0;        // subdomains
+  int64_t patch_base = 0, n_patches = 0;  // patches (coefficient arrays)
+  int64_t n_g = 0;
+};
+
 struct Model {
   ieti_problem prob{};
   std::vector<int32_t> part;
@@ -78,12 +89,24 @@ struct Model {
   std::vector<int64_t> mult;     // m_r x 5: edge, k, l, loc_k, loc_l
   int64_t m_r = 0, n_gp = 0, n_g = 0;
   std::vector<Subdomain> sd;
+  // batch structure: problems, their meshes, problem of every subdomain.
+  // Subdomain fields I_row and p_global are batch-global; r_edges, p_edges
+  // and mult edge ids stay local to the subdomain's problem.
+  std::vector<ProblemRange> probs;
+  std::vector<Mesh> meshes;
+  std::vector<int32_t> sub_prob;
+  int64_t n_edges_total = 0;
+  bool batch() const { return probs.size() > 1; }
+  const Mesh& mesh_of(int k) const { return meshes[sub_prob[k]]; }
 };
 
 // mesh_topology.cpp
 int build_topology(Model& m, Error& err);
 // assemble.cpp
 int assemble_local_systems(Model& m, Error& err);
+// batch.cpp: ranges of a single assembled problem; concatenation of several
+void finalize_single(Model& m);
+int merge_models(std::vector<Model>& parts, Model& out, Error& err);
 // new reluctivity and load scale per patch, from the stored contributions
 int set_coefficients(Model& m, const double* nu, const double* load_scale, Error& err);
 

@@ -73,13 +73,13 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
   plan.T = T;
   const int S = m.n_sub;
   plan.sub.resize(S);
-  const Mesh& M = m.mesh;
   // ---------------------------------------------------------------- per subdomain
   std::vector<std::vector<std::vector<uint64_t>>> present(S);  // column bitsets
   int64_t pool = 0, S_elems = 0, I_total = 0, P_total = 0, r_total = 0;
   for (int k = 0; k < S; ++k) {
     const Subdomain& s = m.sd[k];
     SubPlan& sp = plan.sub[k];
+    const Mesh& M = m.mesh_of(k);
     sp.nV = int64_t(s.V_local.size());
     sp.nI = int64_t(s.I_local.size());
     sp.nP = int64_t(s.p_edges.size());
@@ -411,14 +411,16 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
     plan.bupd_ptr.push_back(int64_t(plan.bupd_task.size() / 3));
   }
   // ---------------------------------------------------------------- interface and primal maps
-  const int64_t n_gp = m.n_gp;
   plan.I_row.assign(I_total, -1);
   plan.I_sign.assign(I_total, 0.0);
   plan.I_aug.assign(I_total, 0);
   plan.A_aug.assign(I_total, 0);
   plan.I_sub.assign(I_total, 0);
   plan.row_src.assign(2 * m.m_r, -1);
-  plan.glob2loc.assign(size_t(S) * n_gp, -1);
+  // ragged subdomain x (primal DOFs of the subdomain's problem) map
+  plan.g2l_off.assign(S + 1, 0);
+  for (int k = 0; k < S; ++k) plan.g2l_off[k + 1] = plan.g2l_off[k] + m.probs[m.sub_prob[k]].n_gp;
+  plan.glob2loc.assign(size_t(plan.g2l_off[S]), -1);
   for (int k = 0; k < S; ++k) {
     const Subdomain& s = m.sd[k];
     const SubPlan& sp = plan.sub[k];
@@ -438,18 +440,25 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
       plan.P_glob.push_back(s.p_global[t]);
       plan.P_aug.push_back(sp.r_off + sp.nVp + sp.nIp + t);
       plan.P_sub.push_back(k);
-      plan.glob2loc[size_t(k) * n_gp + s.p_global[t]] = int32_t(t);
+      plan.glob2loc[size_t(plan.g2l_off[k] + s.p_global[t] - m.probs[m.sub_prob[k]].gp_base)] = int32_t(t);
     }
   }
-  // coarse matrix: sum over subdomains of C_k^T SPi_k C_k, sources in fixed order
+  // coarse matrices: per problem the sum over its subdomains of C_k^T SPi_k C_k
+  // (dense n_gp,p x n_gp,p blocks, concatenated), sources in fixed order
   {
-    std::vector<std::vector<int64_t>> src(size_t(n_gp) * n_gp);
+    plan.spi_off.assign(m.probs.size() + 1, 0);
+    for (size_t q = 0; q < m.probs.size(); ++q)
+      plan.spi_off[q + 1] = plan.spi_off[q] + m.probs[q].n_gp * m.probs[q].n_gp;
+    std::vector<std::vector<int64_t>> src(size_t(plan.spi_off.back()));
     for (int k = 0; k < S; ++k) {
       const Subdomain& s = m.sd[k];
       const SubPlan& sp = plan.sub[k];
+      const ProblemRange& pr = m.probs[m.sub_prob[k]];
+      const int64_t base = plan.spi_off[m.sub_prob[k]];
       for (int64_t a = 0; a < sp.nP; ++a)
         for (int64_t b = 0; b < sp.nP; ++b)
-          src[size_t(s.p_global[a]) * n_gp + s.p_global[b]].push_back(sp.SPi_off + a * sp.nPp + b);
+          src[size_t(base + (s.p_global[a] - pr.gp_base) * pr.n_gp + (s.p_global[b] - pr.gp_base))].push_back(
+              sp.SPi_off + a * sp.nPp + b);
     }
     plan.spi_ptr.assign(1, 0);
     for (auto& v : src) {
@@ -479,7 +488,7 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
       }
       if (s.owner[r]) {
         plan.out_src.push_back(sp.r_off + sp.pos_of_local[r]);
-        plan.out_edge.push_back(s.r_edges[r]);
+        plan.out_edge.push_back(s.r_edges[r] + m.probs[m.sub_prob[k]].edge_base);
       }
     }
     voff += s.indptr[s.n_loc];

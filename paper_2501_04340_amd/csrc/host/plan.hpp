@@ -79,9 +79,12 @@ struct Plan {
   std::vector<int32_t> P_glob;         // per local primal slot: global primal index
   std::vector<int64_t> P_aug;          // per local primal slot: index into augmented vectors
   std::vector<int32_t> P_sub;          // per local primal slot: subdomain
-  std::vector<int32_t> glob2loc;       // N_sub x n_gp: local primal slot index within the subdomain or -1
+  std::vector<int32_t> glob2loc;       // ragged: [g2l_off[k] + c] local primal slot of the c-th primal DOF of
+                                       // subdomain k's problem within the subdomain, or -1
+  std::vector<int64_t> g2l_off;        // N_sub + 1
+  std::vector<int64_t> spi_off;        // per problem: offset of its dense coarse block (n_problems + 1)
   std::vector<int32_t> I_sub;          // per padded interface slot: subdomain
-  // coarse matrix assembly: CSR over the n_gp*n_gp entries, sources in the SPi array
+  // coarse matrix assembly: CSR over the entries of the per-problem blocks, sources in the SPi array
   std::vector<int64_t> spi_ptr, spi_src;
   // recovery: K_rp rows (augmented index), entries (global primal, value)
   std::vector<int64_t> krp_ptr, krp_pos;

@@ -110,7 +110,7 @@ EXPORTS = [
     "ieti_get_lambda", "ieti_get_plan_info", "ieti_set_profiling", "ieti_get_kernel_times", "ieti_destroy",
     "ieti_last_error", "ieti_set_coefficients", "ieti_set_warm_start", "ieti_nn_create", "ieti_nn_num_params",
     "ieti_nn_set_params", "ieti_nn_get_params", "ieti_nn_set_data", "ieti_nn_loss_grad", "ieti_nn_train",
-    "ieti_nn_predict", "ieti_nn_destroy", "ieti_get_gemv_tuning",
+    "ieti_nn_predict", "ieti_nn_destroy", "ieti_get_gemv_tuning", "ieti_assemble_batch", "ieti_get_batch_info",
 ]
 
 
@@ -157,6 +157,8 @@ def load_library():
     lib.ieti_destroy.argtypes = [C.c_void_p]
     lib.ieti_destroy.restype = None
     lib.ieti_last_error.restype = C.c_char_p
+    lib.ieti_assemble_batch.argtypes = [P(Problem), C.c_int32, P(C.c_void_p)]
+    lib.ieti_get_batch_info.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_double)]
     lib.ieti_get_gemv_tuning.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_float)]
     lib.ieti_set_coefficients.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
     lib.ieti_set_warm_start.argtypes = [C.c_void_p, C.c_void_p, P(WarmLayout)]
@@ -186,44 +188,72 @@ def _check(lib, rc):
         raise IetiError(rc, lib.ieti_last_error().decode())
 
 
+def _problem_struct(prob, keep):
+    """ctypes problem statement of a ``workloads.Problem``; arrays and the
+    source callback are appended to ``keep`` (they must outlive assembly)."""
+    part = np.ascontiguousarray(prob.patch_to_sub, dtype=np.int32)
+    nu = np.ascontiguousarray(prob.nu, dtype=np.float64)
+    src = prob.source
+
+    def _field(xyz, npts, out, user):
+        X = np.ctypeslib.as_array(xyz, shape=(int(npts), 3))
+        O = np.ctypeslib.as_array(out, shape=(int(npts), 3))
+        O[:] = src(np.array(X))
+
+    cb = FIELD_FN(_field)
+    keep.extend([part, nu, cb])
+    pr = Problem()
+    pr.version = ABI_VERSION
+    pr.geom_kind = int(prob.geom_kind)
+    for d in range(3):
+        pr.patches[d] = int(prob.patches[d])
+        pr.periodic[d] = int(prob.periodic[d])
+    gp = np.zeros(16)
+    gp[:len(prob.geom_params)] = prob.geom_params
+    for i in range(16):
+        pr.geom_params[i] = float(gp[i])
+    pr.degree_p = int(prob.degree)
+    pr.n_el = int(prob.n_el)
+    pr.patch_to_subdomain = _ptr(part, C.c_int32)
+    pr.nu_per_patch = _ptr(nu, C.c_double)
+    pr.J = cb
+    pr.J_user = None
+    return pr
+
+
 class Solver:
-    """One assembled problem on the current HIP device."""
+    """One assembled problem, or a batch of independent problems (a list),
+    on the current HIP device."""
 
     def __init__(self, prob):
         self.lib = load_library()
+        probs = list(prob) if isinstance(prob, (list, tuple)) else [prob]
         self.prob = prob
-        self._part = np.ascontiguousarray(prob.patch_to_sub, dtype=np.int32)
-        self._nu = np.ascontiguousarray(prob.nu, dtype=np.float64)
-        src = prob.source
-
-        def _field(xyz, npts, out, user):
-            X = np.ctypeslib.as_array(xyz, shape=(int(npts), 3))
-            O = np.ctypeslib.as_array(out, shape=(int(npts), 3))
-            O[:] = src(np.array(X))
-
-        self._cb = FIELD_FN(_field)
-        pr = Problem()
-        pr.version = ABI_VERSION
-        pr.geom_kind = int(prob.geom_kind)
-        for d in range(3):
-            pr.patches[d] = int(prob.patches[d])
-            pr.periodic[d] = int(prob.periodic[d])
-        gp = np.zeros(16)
-        gp[:len(prob.geom_params)] = prob.geom_params
-        for i in range(16):
-            pr.geom_params[i] = float(gp[i])
-        pr.degree_p = int(prob.degree)
-        pr.n_el = int(prob.n_el)
-        pr.patch_to_subdomain = _ptr(self._part, C.c_int32)
-        pr.nu_per_patch = _ptr(self._nu, C.c_double)
-        pr.J = self._cb
-        pr.J_user = None
+        self.batch = len(probs)
+        keep = []
+        arr = (Problem * len(probs))(*[_problem_struct(p, keep) for p in probs])
+        self._part = np.concatenate([np.asarray(p.patch_to_sub) for p in probs]).astype(np.int32)
         h = C.c_void_p()
-        _check(self.lib, self.lib.ieti_assemble(C.byref(pr), C.byref(h)))
+        _check(self.lib, self.lib.ieti_assemble_batch(arr, len(probs), C.byref(h)))
         self.h = h
         s = np.zeros(8, dtype=np.int64)
         _check(self.lib, self.lib.ieti_get_sizes(self.h, _ptr(s, C.c_int64)))
         self.n_edges, self.n_global, self.sum_n_r, self.m_r, self.n_gp, self.n_sub, self.n_nodes, self.max_n_I = map(int, s)
+
+    def batch_info(self):
+        """Per problem: ranges (edge, m_r, primal, subdomain offsets and counts), last iterations and residuals."""
+        n = self.batch
+        rg = np.zeros((n, 8), np.int64)
+        it = np.zeros(n, np.int32)
+        rr = np.zeros(n)
+        _check(self.lib, self.lib.ieti_get_batch_info(self.h, _ptr(rg, C.c_int64), _ptr(it, C.c_int32),
+                                                      _ptr(rr, C.c_double)))
+        keys = ["edge_base", "n_edges", "mr_base", "m_r", "gp_base", "n_gp", "sub_base", "n_sub"]
+        return [dict(zip(keys, map(int, r)), iters=int(i), rel_residual=float(x)) for r, i, x in zip(rg, it, rr)]
+
+    def split(self, a):
+        """Per-problem coefficient vectors of a batch output."""
+        return [a[b["edge_base"]:b["edge_base"] + b["n_edges"]] for b in self.batch_info()]
 
     def close(self):
         if getattr(self, "h", None):
