@@ -33,6 +33,7 @@ WORKLOADS = {
     "cube8": "cube8: 2x2x2 patches, p=2, n_el=4, 8 subdomains, nu=1, manufactured polynomial A, FP64",
     "cube256": "cube256: 8x8x4 patches, p=2, n_el=6, 64 uneven subdomains, nu log-uniform [1e-3,1], trig J, FP64",
     "ring576": "ring576: NURBS annulus 48x3x4 patches, p=2, n_el=5, 48 sector subdomains, coil current, FP64",
+    "stream256": "stream256: 256 independent box problems in batches",
 }
 
 
@@ -218,6 +219,120 @@ def ring_warm_start(args):
     print(json.dumps(out), flush=True)
 
 
+def stream_batches(args):
+    """stream256: independent box problems, each solved alone (plain FP64,
+    one handle per problem) and in batches (one handle and one set of
+    launches per chunk, plain FP64 and mixed).  Host assembly is untimed."""
+    import concurrent.futures
+
+    import torch
+
+    from paper_2501_04340_amd import Solver
+    from paper_2501_04340_amd.ietidp import PREC_FP64, PREC_MIXED
+    from workloads import configs
+
+    torch.cuda.set_device(0)
+    n, chunk = args.stream_count, args.stream_chunk
+    lat_single, lat_bplain, lat_bmixed = [], [], []
+    t_single = t_bplain = t_bmixed = 0.0
+    iters_single, iters_batch, resid = [], [], []
+    roof = None
+    max_diff = 0.0
+    n_g_total = 0
+    t_host = 0.0
+    for c0 in range(0, n, chunk):
+        ids = list(range(c0, min(n, c0 + chunk)))
+        th = time.perf_counter()
+        probs = [configs.stream_problem(i) for i in ids]
+        with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
+            singles = list(ex.map(Solver, probs))
+        t_host += time.perf_counter() - th
+        # each problem alone, plain FP64 (first factor autotunes; one warm-up solve)
+        outs = []
+        for S in singles:
+            S.factor()
+            S.solve(rtol=args.rtol)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S.factor()
+            a, st = S.solve(rtol=args.rtol)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            lat_single.append(dt * 1e3)
+            t_single += dt
+            iters_single.append(st["iters"])
+            outs.append(a)
+            n_g_total += S.n_global
+        bytes_p = [S.kernel_times()["gemv_bytes"] for S in singles]  # interface blocks per application
+        B = Solver.batch_of(singles)
+        for S in singles:
+            S.close()
+        for prec, lat in ((PREC_FP64, lat_bplain), (PREC_MIXED, lat_bmixed)):
+            B.factor(precision=prec)
+            B.solve(rtol=args.rtol, maxit=3000)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.factor(precision=prec)
+            a, st = B.solve(rtol=args.rtol, maxit=3000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            lat.extend([dt * 1e3] * len(ids))
+            info = B.batch_info()
+            resid.extend(b["rel_residual"] for b in info)
+            if prec == PREC_FP64:
+                t_bplain += dt
+                iters_batch.extend(b["iters"] for b in info)
+                for ai, ao in zip(B.split(a), outs):
+                    max_diff = max(max_diff, float(np.abs(ai - ao).max() / max(np.abs(ao).max(), 1e-300)))
+            else:
+                t_bmixed += dt
+        if roof is None:
+            # a finished problem's GEMV tasks are skipped, so the bytes of the
+            # profiled solve are sum_p bytes_p * (2 iters_p + 1): one
+            # preconditioner application to start, two applications per iteration
+            B.factor()
+            B.set_profiling(True)
+            B.solve(rtol=args.rtol, maxit=3000)
+            kt = B.kernel_times()
+            B.set_profiling(False)
+            its = [b["iters"] for b in B.batch_info()]
+            total_bytes = float(sum(bp * (2 * it + 1) for bp, it in zip(bytes_p, its)))
+            ach = total_bytes / (kt["gemv_ms"] * 1e-3) / 1e9
+            roof = {"kernel": "k_gemv<double> (autotuned shape), one batch of "
+                              f"{len(ids)} problems", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                    "avg_launch_ms": kt["gemv_ms"] / max(kt["gemv_launches"], 1),
+                    "bytes_all_problems_active": kt["gemv_bytes"],
+                    "bytes_over_solve": total_bytes, "launches": kt["gemv_launches"]}
+        B.close()
+        log(f"problems {ids[0]}..{ids[-1]}: alone {np.sum(lat_single[-len(ids):]):.0f} ms total, batch plain "
+            f"{lat_bplain[-1]:.0f} ms, batch mixed {lat_bmixed[-1]:.0f} ms (host {t_host:.0f}s so far)")
+
+    def summ(lat, total):
+        return {"solves_per_s": n / total, "latency_ms_p50": float(np.percentile(lat, 50)),
+                "latency_ms_p99": float(np.percentile(lat, 99))}
+
+    out = {
+        "metric": "IETI-DP time-to-solution and F·λ applies/s at rtol 1e-8, mixed+warm vs plain FP64",
+        "value": n / t_bmixed, "unit": "solves/s", "n_gpus": 1, "steps": n, "warmup": 1,
+        "ms_per_step": t_bmixed * 1e3 / n, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"stream256: {n} independent box problems (2^a x 2^b x 2^c patches, p in {{2,3}}, "
+                               f"4-6 elements, nu in [1e-3,1]), batches of {chunk}, rtol {args.rtol}",
+                   "variant": "batched mixed precision (no warm start: no network is trained for this stream)",
+                   "n_g_total": n_g_total},
+        "variants": {"single_plain_fp64": summ(lat_single, t_single), "batch_plain_fp64": summ(lat_bplain, t_bplain),
+                     "batch_mixed": summ(lat_bmixed, t_bmixed)},
+        "speedup_batch_mixed_vs_single_plain": t_single / t_bmixed,
+        "pcg_iters": {"single_mean": float(np.mean(iters_single)), "batch_max_mean": float(np.mean(iters_batch))},
+        "max_rel_residual": float(np.max(resid)),
+        "batch_vs_single_max_rel_diff": max_diff,
+        "host_assembly_s": t_host,
+        "roofline": roof,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +344,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (HBM counter calibration) and exit")
+    ap.add_argument("--stream-count", type=int, default=256)
+    ap.add_argument("--stream-chunk", type=int, default=32)
     ap.add_argument("--ring-train", type=int, default=512)
     ap.add_argument("--ring-test", type=int, default=64)
     ap.add_argument("--nn-epochs", type=int, default=300)
@@ -257,6 +374,8 @@ def main():
         return
     if args.workload == "ring576":
         return ring_warm_start(args)
+    if args.workload == "stream256":
+        return stream_batches(args)
     torch.cuda.set_device(0)
     prob = configs.make_config(args.workload)
     t0 = time.perf_counter()

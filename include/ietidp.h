@@ -157,6 +157,12 @@ int ieti_assemble(const ieti_problem* prob, ieti_handle** out);
  * ieti_assemble_batch(p, 1, out). */
 int ieti_assemble_batch(const ieti_problem* probs, int32_t n, ieti_handle** out);
 
+/* Batch handle built from n single-problem handles (their assembled
+ * systems are copied; the inputs stay valid and independent).  Same as
+ * ieti_assemble_batch on the handles' problems, without repeating the
+ * assembly. */
+int ieti_batch_of(const ieti_handle* const* hs, int32_t n, ieti_handle** out);
+
 /* Per problem p of a handle (any argument may be NULL):
  *   ranges [8 p .. 8 p + 7] = {first output coefficient, n_edges, first
  *   multiplier row, m_r, first primal DOF, n_gp, first subdomain, N_sub},

@@ -339,8 +339,6 @@ int upload(ieti_handle* h) {
   if ((rc = dalloc(h->part, 3 * int64_t(h->nblk)))) return rc;
   if ((rc = dalloc(h->xgp, std::max<int64_t>(P.I_total, 1)))) return rc;
   if ((rc = dalloc(h->xgr, std::max<int64_t>(P.I_total, 1)))) return rc;
-  HIP_TRY(hipMemset(h->xgp.ptr, 0, h->xgp.n * sizeof(double)));
-  HIP_TRY(hipMemset(h->xgr.ptr, 0, h->xgr.n * sizeof(double)));
   if ((rc = dalloc(h->part_g, std::max(h->ngemv_r[0], 1)))) return rc;
   if ((rc = dalloc(h->part_t, std::max<int64_t>(ptoff, 1)))) return rc;
   if ((rc = dalloc(h->pdone, n_prob))) return rc;
@@ -998,6 +996,34 @@ int ieti_assemble_batch(const ieti_problem* probs, int32_t n, ieti_handle** out)
   return IETI_OK;
 }
 
+int ieti_batch_of(const ieti_handle* const* hs, int32_t n, ieti_handle** out) {
+  if (!out) return fail(IETI_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!hs || n < 1) return fail(IETI_ERR_INVALID_ARG, "a batch needs at least one handle");
+  std::vector<ieti::Model> parts;
+  parts.reserve(n);
+  for (int32_t i = 0; i < n; ++i) {
+    if (!hs[i]) return fail(IETI_ERR_INVALID_ARG, "handle " + std::to_string(i) + " is NULL");
+    if (hs[i]->model.batch()) return fail(IETI_ERR_INVALID_ARG, "handle " + std::to_string(i) + " is a batch");
+    parts.push_back(hs[i]->model);
+  }
+  auto* h = new ieti_handle();
+  ieti::Error err{0, ""};
+  int rc = ieti::merge_models(parts, h->model, err);
+  if (rc) {
+    delete h;
+    return fail(rc, err.msg);
+  }
+  if (n == 1) ieti::finalize_single(h->model);
+  rc = build_plan_if_needed(h, ieti::dev::TILE, 0);
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return IETI_OK;
+}
+
 int ieti_get_batch_info(const ieti_handle* h, int64_t* ranges, int32_t* iters, double* rel_residual) {
   if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
   const auto& M = h->model;
@@ -1031,6 +1057,10 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   h->factored = false;
   h->rhs_ready = false;
   HIP_TRY(hipMemsetAsync(h->flags.ptr, 0, 8 * sizeof(int), s));
+  // the padded interface slots of the gathered vectors must read 0 (gathers
+  // write the real slots only); cleared on the solve stream itself
+  D::fill(h->xgp.ptr, h->xgp.n, 0.0, s);
+  D::fill(h->xgr.ptr, h->xgr.n, 0.0, s);
   HIP_TRY(hipEventRecord(h->ev0, s));
   D::fill(h->pool.ptr, P.pool_elems, 0.0, s);
   D::scatter(h->pool.ptr, h->scatter_dst.ptr, h->scatter_val.ptr, int64_t(P.scatter_dst.size()), s);

@@ -765,7 +765,8 @@ __global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* r
     const int64_t s0 = row_src[2 * row], s1 = row_src[2 * row + 1];
     const double zz = w[s0] - w[s1];
     z[row] = zz;
-    pv = zz + beta * p[row];
+    // the first direction is z itself: p holds no value yet (not even a finite one)
+    pv = init ? zz : zz + beta * p[row];
     p[row] = pv;
     xg_p[s0] = pv;
     xg_p[s1] = -pv;

@@ -185,6 +185,7 @@ int ieti_nn_create(const ieti_nn_arch* arch, ieti_nn** out) {
   if (!rc) {
     for (auto* b : {&nn->theta, &nn->grad, &nn->m, &nn->v})
       if (hipMemset(b->ptr, 0, b->n * sizeof(float)) != hipSuccess) rc = fail(IETI_ERR_HIP, "hipMemset failed");
+    if (!rc && hipDeviceSynchronize() != hipSuccess) rc = fail(IETI_ERR_HIP, "hipDeviceSynchronize failed");
   }
   if (rc) {
     delete nn;
@@ -207,6 +208,7 @@ int ieti_nn_set_params(ieti_nn* nn, const float* params) {
   HIP_TRY(hipMemcpy(nn->theta.ptr, params, nn->mlp.n_params * sizeof(float), hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(nn->m.ptr, 0, nn->m.n * sizeof(float)));
   HIP_TRY(hipMemset(nn->v.ptr, 0, nn->v.n * sizeof(float)));
+  HIP_TRY(hipDeviceSynchronize());
   nn->adam_t = 0;
   return IETI_OK;
 }

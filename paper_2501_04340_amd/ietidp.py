@@ -111,6 +111,7 @@ EXPORTS = [
     "ieti_last_error", "ieti_set_coefficients", "ieti_set_warm_start", "ieti_nn_create", "ieti_nn_num_params",
     "ieti_nn_set_params", "ieti_nn_get_params", "ieti_nn_set_data", "ieti_nn_loss_grad", "ieti_nn_train",
     "ieti_nn_predict", "ieti_nn_destroy", "ieti_get_gemv_tuning", "ieti_assemble_batch", "ieti_get_batch_info",
+    "ieti_batch_of",
 ]
 
 
@@ -158,6 +159,7 @@ def load_library():
     lib.ieti_destroy.restype = None
     lib.ieti_last_error.restype = C.c_char_p
     lib.ieti_assemble_batch.argtypes = [P(Problem), C.c_int32, P(C.c_void_p)]
+    lib.ieti_batch_of.argtypes = [P(C.c_void_p), C.c_int32, P(C.c_void_p)]
     lib.ieti_get_batch_info.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_double)]
     lib.ieti_get_gemv_tuning.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_float)]
     lib.ieti_set_coefficients.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
@@ -239,6 +241,23 @@ class Solver:
         s = np.zeros(8, dtype=np.int64)
         _check(self.lib, self.lib.ieti_get_sizes(self.h, _ptr(s, C.c_int64)))
         self.n_edges, self.n_global, self.sum_n_r, self.m_r, self.n_gp, self.n_sub, self.n_nodes, self.max_n_I = map(int, s)
+
+    @classmethod
+    def batch_of(cls, solvers):
+        """Batch handle from single-problem solvers (their systems are copied)."""
+        self = cls.__new__(cls)
+        self.lib = load_library()
+        self.prob = [S.prob for S in solvers]
+        self.batch = len(solvers)
+        self._part = np.concatenate([S._part for S in solvers]).astype(np.int32)
+        arr = (C.c_void_p * len(solvers))(*[S.h.value for S in solvers])
+        h = C.c_void_p()
+        _check(self.lib, self.lib.ieti_batch_of(arr, len(solvers), C.byref(h)))
+        self.h = h
+        s = np.zeros(8, dtype=np.int64)
+        _check(self.lib, self.lib.ieti_get_sizes(self.h, _ptr(s, C.c_int64)))
+        self.n_edges, self.n_global, self.sum_n_r, self.m_r, self.n_gp, self.n_sub, self.n_nodes, self.max_n_I = map(int, s)
+        return self
 
     def batch_info(self):
         """Per problem: ranges (edge, m_r, primal, subdomain offsets and counts), last iterations and residuals."""

@@ -83,3 +83,20 @@ def test_batch_mixed_precision(batch):
     for info in B.batch_info():
         sl = slice(info["mr_base"], info["mr_base"] + info["m_r"])
         assert np.linalg.norm(res[sl]) <= 1e-10 * np.linalg.norm(b[sl])
+
+
+def test_first_solve_does_not_read_stale_device_memory(ietilib):
+    """Regression: the first PCG direction must not read the previous
+    contents of its buffer (0 * NaN from reused device memory made the first
+    p^T F p NaN).  Device memory is filled with NaN and released before the
+    handle allocates its buffers."""
+    import torch
+    from paper_2501_04340_amd import Solver
+    junk = torch.full((1 << 28,), float("nan"), dtype=torch.float64, device="cuda")
+    del junk
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    S = Solver(configs.stream_problem(118))
+    S.factor(gemv_variant=0)
+    a, st = S.solve(rtol=1e-8)
+    assert st["status"] == 0 and st["rel_residual"] <= 1e-8 and np.isfinite(a).all()

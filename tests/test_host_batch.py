@@ -71,3 +71,15 @@ def test_batch_coefficient_update_matches_single(batch):
         S.set_coefficients(nu[off:off + n], np.ones(n))
         off += n
     B.set_coefficients(nu, np.ones(len(nu)))
+
+
+def test_batch_of_handles_equals_assembled_batch(batch):
+    probs, B, singles = batch
+    from paper_2501_04340_amd import Solver
+    B2 = Solver.batch_of(singles)
+    assert B2.batch == B.batch and B2.m_r == B.m_r and B2.n_edges == B.n_edges
+    for k in range(B.n_sub):
+        K1, j1 = B.local_system(k)
+        K2, j2 = B2.local_system(k)
+        assert np.array_equal(K1.data, K2.data) and np.array_equal(j1, j2)
+    assert B2.batch_info() == B.batch_info()

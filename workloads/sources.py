@@ -110,7 +110,7 @@ class TrigCurlSource:
             dT[:, d, 2] = np.sum(a * pk[None, :, 2] * S[0] * S[1] * Cc[2], axis=1)
         return T, dT
 
-    def __call__(self, xyz):
+    def curl_numpy(self, xyz):
         xyz = np.asarray(xyz, dtype=np.float64)
         out = np.empty((xyz.shape[0], 3))
         step = 20000
@@ -119,6 +119,59 @@ class TrigCurlSource:
             out[s:s + step, 0] = dT[:, 2, 1] - dT[:, 1, 2]
             out[s:s + step, 1] = dT[:, 0, 2] - dT[:, 2, 0]
             out[s:s + step, 2] = dT[:, 1, 0] - dT[:, 0, 1]
+        return out
+
+    def _derivative_tensors(self):
+        """W[p] (2K x 2K x 2K) for the six derivatives dT_d/dx_j, d != j, in
+        the order of PAIRS: by angle addition every factor
+        sin(pi k_i x_i + th) is cos(th) sin(pi k_i x_i) + sin(th) cos(pi k_i x_i),
+        and its x_i-derivative pi k_i (cos(th) cos(pi k_i x_i) - sin(th) sin(pi k_i x_i)),
+        so each derivative is a trilinear form in the per-axis vectors
+        g_i = [sin(pi k x_i), cos(pi k x_i)]_{k=1..K}."""
+        if getattr(self, "_W", None) is not None:
+            return self._W
+        K = int(self.k.max())
+        W = np.zeros((len(self.PAIRS), 2 * K, 2 * K, 2 * K))
+        for q, (d, j) in enumerate(self.PAIRS):
+            for m in range(self.k.shape[0]):
+                e = []
+                for i in range(3):
+                    v = np.zeros(2 * K)
+                    ki = int(self.k[m, i]) - 1
+                    ct, st = np.cos(self.phase[d, m, i]), np.sin(self.phase[d, m, i])
+                    if i == j:
+                        f = np.pi * self.k[m, i]
+                        v[ki], v[K + ki] = -f * st, f * ct
+                    else:
+                        v[ki], v[K + ki] = ct, st
+                    e.append(v)
+                W[q] += self.amp[d, m] * np.einsum("a,b,c->abc", e[0], e[1], e[2])
+        self._W = W
+        return W
+
+    # (d, j) of dT_d/dx_j needed by curl T
+    PAIRS = ((2, 1), (1, 2), (0, 2), (2, 0), (1, 0), (0, 1))
+
+    def __call__(self, xyz):
+        xyz = np.asarray(xyz, dtype=np.float64)
+        W = self._derivative_tensors()
+        P, K2 = W.shape[0], W.shape[1]
+        K = K2 // 2
+        Wf = W.reshape(P * K2 * K2, K2)                    # [(q, a, b), c]
+        kr = np.arange(1, K + 1, dtype=np.float64)
+        out = np.empty((xyz.shape[0], 3))
+        step = 32768
+        for s in range(0, xyz.shape[0], step):
+            x = xyz[s:s + step]
+            n = x.shape[0]
+            ang = np.pi * x[:, :, None] * kr[None, None, :]   # (n,3,K)
+            g = np.concatenate([np.sin(ang), np.cos(ang)], axis=2)  # (n,3,2K)
+            Y = g[:, 2, :] @ Wf.T                              # (n, P*2K*2K): contract axis 2
+            Y = np.matmul(Y.reshape(n, P * K2, K2), g[:, 1, :, None])[..., 0]   # axis 1
+            D = np.matmul(Y.reshape(n, P, K2), g[:, 0, :, None])[..., 0]       # axis 0 -> (n, P)
+            out[s:s + step, 0] = D[:, 0] - D[:, 1]
+            out[s:s + step, 1] = D[:, 2] - D[:, 3]
+            out[s:s + step, 2] = D[:, 4] - D[:, 5]
         return out
 
 
