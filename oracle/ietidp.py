@@ -19,7 +19,15 @@ positive definite system (-S) lambda = e - G F^{-1} d.  The Dirichlet
 preconditioner is M_D^{-1} = D_s B_rI S_rIrI B_rI^T D_s with D_s = I
 (Eq. DirPrec; the paper's homogeneous-material choice), where
 S_rIrI = K_rIrI - K_rIrV K_rVrV^{-1} K_rVrI and r_I are the remaining
-DOFs on interface edges.
+DOFs on interface edges.  Optionally (beyond the paper, which keeps
+D_s = I) the jump operator of the preconditioner is scaled, B_D = D B:
+every multiplier row joins exactly two subdomains k (+1) and l (-1), and
+its entries become +delta_k and -delta_l with delta_k = rho_l / (rho_k +
+rho_l), delta_l = rho_k / (rho_k + rho_l) (a partition of unity, the
+rho-scaling of Klawonn & Widlund 2002, Farhat et al. 2000).  Here rho_k of a
+DOF is the diagonal entry of subdomain k's stiffness matrix there, which
+carries the local reluctivity ("stiffness" scaling); "multiplicity" takes
+delta = 1/2.
 
 Every subdomain is factorised with SuperLU (scipy.sparse.linalg.splu);
 everything else is plain NumPy in float64.
@@ -110,7 +118,32 @@ class IetiDP:
                                             topo.gp_index, topo.m_r, topo.mult))
         self.m_r = topo.m_r
         self.n_gp = topo.n_gp
+        self.scaling = "identity"
         self._coarse()
+
+    def set_scaling(self, kind):
+        """Scaling of the preconditioner's jump operator: identity (the
+        paper's D_s = I), multiplicity or stiffness (see the module doc)."""
+        if kind not in ("identity", "multiplicity", "stiffness"):
+            raise ValueError(kind)
+        self.scaling = kind
+        mult = self.topo.mult
+        if kind == "identity":
+            dk = dl = np.ones(self.m_r)
+        elif kind == "multiplicity":
+            dk = dl = np.full(self.m_r, 0.5)
+        else:
+            rk = np.array([self.locals[k].K_rr.diagonal()[i] for k, i in zip(mult[:, 1], mult[:, 3])])
+            rl = np.array([self.locals[l].K_rr.diagonal()[i] for l, i in zip(mult[:, 2], mult[:, 4])])
+            dk, dl = rl / (rk + rl), rk / (rk + rl)
+        self.delta = (dk, dl)
+        for L in self.locals:
+            rows_k = mult[:, 1] == L.k
+            rows_l = mult[:, 2] == L.k
+            bi = np.concatenate([np.flatnonzero(rows_k), np.flatnonzero(rows_l)])
+            bj = np.concatenate([mult[rows_k, 3], mult[rows_l, 4]])
+            bv = np.concatenate([dk[rows_k], -dl[rows_l]])
+            L.BD = sp.csr_matrix((bv, (bi, bj)), shape=(self.m_r, len(L.r)))
 
     # ---------------------------------------------------------------- setup
     def _coarse(self):
@@ -155,13 +188,14 @@ class IetiDP:
         return out
 
     def apply_MD(self, r):
-        """M_D^{-1} r = B_rI S_rIrI B_rI^T r with D_s = I."""
+        """M_D^{-1} r = B_D,rI S_rIrI B_D,rI^T r (B_D = B unless a scaling is set)."""
         out = np.zeros(self.m_r)
         for L in self.locals:
-            u = L.B.T @ r
+            Bk = L.B if self.scaling == "identity" else L.BD
+            u = Bk.T @ r
             v = np.zeros_like(u)
             v[L.I] = L.schur_I(u[L.I])
-            out += L.B @ v
+            out += Bk @ v
         return out
 
     # ---------------------------------------------------------------- PCG
