@@ -444,6 +444,22 @@ def main():
     torch.cuda.synchronize()
     ms_mixed = (time.perf_counter() - t0m) * 1e3 / args.steps
     chosen32, tune_ms32 = S.gemv_tuning()
+    # rho-scaled preconditioner (stiffness diagonal), plain and mixed
+    from paper_2501_04340_amd.ietidp import SCALE_STIFFNESS
+    scaled = {}
+    for tag, prec in (("plain_fp64_rho_scaling", PREC_FP64), ("mixed_rho_scaling", PREC_MIXED)):
+        S.factor(precision=prec, scaling=SCALE_STIFFNESS)
+        S.solve(rtol=args.rtol)
+        torch.cuda.synchronize()
+        t0s = time.perf_counter()
+        for k in range(args.steps):
+            S.factor(precision=prec, scaling=SCALE_STIFFNESS)
+            _, st_s = S.solve(rtol=args.rtol)
+        torch.cuda.synchronize()
+        ms_s = (time.perf_counter() - t0s) * 1e3 / args.steps
+        scaled[tag] = {"tts_ms": ms_s, "pcg_iters": int(st_s["iters"]), "rel_residual_fp64": float(st_s["rel_residual"]),
+                       "speedup_vs_plain": ms_per_step / ms_s}
+        log(f"{tag}: {ms_s:.2f} ms/step, iters {st_s['iters']}")
     S.factor(precision=PREC_FP64)
     log(f"mixed: {ms_mixed:.2f} ms/step, iters {mstats[-1]['iters']}, outer {mstats[-1]['outer_iters']}, "
         f"rel residual {mstats[-1]['rel_residual']:.2e}")
@@ -479,6 +495,7 @@ def main():
                 "outer_iters": int(mstats[-1]["outer_iters"]),
                 "rel_residual_fp64": float(mstats[-1]["rel_residual"]),
                 "speedup_vs_plain": ms_per_step / ms_mixed},
+            **scaled,
         },
     }
     if not args.no_cpu_baseline:

@@ -47,6 +47,14 @@ enum {
 
 enum { IETI_GEOM_BOX = 0, IETI_GEOM_ANNULUS = 1 };
 enum { IETI_PREC_FP64 = 0, IETI_PREC_MIXED = 1 };
+/* Scaling of the Dirichlet preconditioner's jump operator, B_D = D B
+ * (Eq. DirPrec takes D_s = I; the scaled variants follow the rho-scaling of
+ * the FETI-DP literature that the paper refers to for heterogeneous
+ * coefficients): on each multiplier row joining subdomains k and l,
+ * delta_k = rho_l / (rho_k + rho_l) and delta_l = rho_k / (rho_k + rho_l),
+ * with rho the diagonal entry of the subdomain's stiffness at the DOF
+ * (STIFFNESS), or delta = 1/2 (MULTIPLICITY). */
+enum { IETI_SCALE_IDENTITY = 0, IETI_SCALE_STIFFNESS = 1, IETI_SCALE_MULTIPLICITY = 2 };
 
 typedef struct ieti_handle ieti_handle; /* opaque, library-owned */
 
@@ -93,6 +101,8 @@ typedef struct {
   int32_t ordering;    /* 0 = nested dissection of r_V (default), 1 = natural order */
   int32_t gemv_variant; /* 0 = autotune the interface GEMV launch shape on the first factorisation
                            of the handle (kept afterwards); 1..12 = use shape gemv_variant - 1 */
+  int32_t scaling;     /* IETI_SCALE_* of the preconditioner (0 = D_s = I as in the paper) */
+  int32_t reserved;
   void* hip_stream;    /* hipStream_t to run on; NULL = the library's own stream */
 } ieti_factor_opts;
 

@@ -85,6 +85,8 @@ struct ieti_handle {
   ieti::dev::Batch B;
   std::vector<int64_t> pd_h, blk_h;
   DBuf<int> pdone, piters;                 // per problem: PCG finished (1 ok, 3 breakdown), iterations
+  DBuf<double> dscale;                     // per interface slot: scaling of the preconditioner's jump operator
+  int scaling = IETI_SCALE_IDENTITY;
   int* pflags_h = nullptr;                 // pinned host copy: done[n_prob], iters[n_prob]
   // per-problem results of the last solve
   std::vector<int> p_iters, p_outer, p_status, p_warm;
@@ -122,6 +124,7 @@ struct ieti_handle {
     for (auto& t : task_prob) t.release();
     pdone.release();
     piters.release();
+    dscale.release();
     if (pflags_h) (void)hipHostFree(pflags_h);
     glob2loc.release();
     krp_col.release();
@@ -421,6 +424,9 @@ int check_launch() {
   return IETI_OK;
 }
 
+// per-slot scaling of the preconditioner's jump operator, or null for D_s = I
+const double* dsc(const ieti_handle* h) { return h->scaling == IETI_SCALE_IDENTITY ? nullptr : h->dscale.ptr; }
+
 // GEMV launch shape in use for FP64 (fp32 = 0) or FP32 (1) blocks, its task list and task count
 int gvariant(const ieti_handle* h, int fp32) { return h->gvar[fp32] >= 0 ? h->gvar[fp32] : ieti::dev::GEMV_DEFAULT; }
 const int64_t* gtasks(const ieti_handle* h, int fp32) { return h->gemv_tasks[gvariant(h, fp32) / 4].ptr; }
@@ -460,9 +466,9 @@ void apply_M(ieti_handle* h, const double* x, double* out) {
   namespace D = ieti::dev;
   const auto& M = h->model;
   hipStream_t s = h->stream;
-  D::gather_rows(x, h->row_src.ptr, M.m_r, h->xgr.ptr, s);
+  D::gather_rows(x, h->row_src.ptr, M.m_r, h->xgr.ptr, s, dsc(h));
   gemv_timed(h, h->S.ptr, h->xgr.ptr, h->v.ptr);
-  D::combine(h->v.ptr, h->row_src.ptr, nullptr, nullptr, out, h->B, s);
+  D::combine(h->v.ptr, h->row_src.ptr, nullptr, nullptr, out, h->B, s, dsc(h));
 }
 
 // One PCG iteration of parity `par` as four launches, with the interface
@@ -479,10 +485,10 @@ void pcg_iteration(ieti_handle* h, int par, const MT* Sinv, const MT* S) {
   const int gt = gvariant(h, fp32) / 4;
   gemv_timed(h, Sinv, h->xgp.ptr, h->v.ptr, done);
   D::pcg_F(h->v.ptr, h->row_src.ptr, h->H.ptr, h->part_t.ptr, h->part_g.ptr, h->p.ptr, h->lam.ptr, h->r.ptr,
-           h->xgr.ptr, part_rr, h->scal.ptr, par, done, perr, h->B, gt, s);
+           h->xgr.ptr, part_rr, h->scal.ptr, par, done, perr, h->B, gt, s, dsc(h));
   gemv_timed(h, S, h->xgr.ptr, h->v.ptr, done);
   D::pcg_M(h->v.ptr, h->row_src.ptr, h->H.ptr, h->part_g.ptr, part_rr, h->p.ptr, h->z.ptr, h->xgp.ptr,
-           h->part_t.ptr, h->scal.ptr, par, done, iters, 0, h->B, gt, s);
+           h->part_t.ptr, h->scal.ptr, par, done, iters, 0, h->B, gt, s, dsc(h));
 }
 
 void pcg_iteration_prec(ieti_handle* h, int par, bool fp32) {
@@ -550,6 +556,51 @@ int choose_gemv(ieti_handle* h, int forced, int fp32) {
   }
   if (h->gvar[fp32] >= 0 || h->plan.S_elems == 0) return IETI_OK;
   return fp32 ? tune_gemv(h, h->Sinv32.ptr, h->S32.ptr, 1) : tune_gemv(h, h->Sinv.ptr, h->S.ptr, 0);
+}
+
+// Scaling of the preconditioner's jump operator (beyond the paper's
+// D_s = I): every multiplier row joins two interface slots s0 (+1) and s1
+// (-1); rho-scaling gives them delta_s0 = rho_s1 / (rho_s0 + rho_s1) and
+// delta_s1 = rho_s0 / (rho_s0 + rho_s1), with rho the diagonal entry of the
+// slot's subdomain stiffness at that DOF (it carries the local
+// reluctivity); multiplicity scaling gives 1/2.
+int set_scaling(ieti_handle* h, int kind) {
+  const double* before = dsc(h);
+  if (kind != IETI_SCALE_IDENTITY) {
+    const auto& P = h->plan;
+    const auto& M = h->model;
+    std::vector<double> rho(std::max<int64_t>(P.I_total, 1), 0.0), d(std::max<int64_t>(P.I_total, 1), 0.0);
+    for (size_t k = 0; k < P.sub.size(); ++k) {
+      const auto& s = M.sd[k];
+      for (int64_t t = 0; t < P.sub[k].nI; ++t) {
+        const int32_t r = s.I_local[t];
+        double dg = 0.0;
+        for (int64_t q = s.indptr[r]; q < s.indptr[r + 1]; ++q)
+          if (s.indices[q] == r) dg = s.values[q];
+        rho[P.sub[k].I_off + t] = dg;
+      }
+    }
+    for (int64_t row = 0; row < M.m_r; ++row) {
+      const int64_t s0 = P.row_src[2 * row], s1 = P.row_src[2 * row + 1];
+      if (kind == IETI_SCALE_MULTIPLICITY) {
+        d[s0] = d[s1] = 0.5;
+      } else {
+        const double a = rho[s0], b = rho[s1];
+        if (!(a > 0.0) || !(b > 0.0)) return fail(IETI_ERR_NOT_SPD, "non-positive stiffness diagonal on an interface");
+        d[s0] = b / (a + b);
+        d[s1] = a / (a + b);
+      }
+    }
+    if (h->dscale.ptr && h->dscale.n == int64_t(d.size())) {
+      HIP_TRY(hipMemcpy(h->dscale.ptr, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+      int rc = dupload(h->dscale, d);
+      if (rc) return rc;
+    }
+  }
+  h->scaling = kind;
+  if (dsc(h) != before) drop_graphs(h);  // captured graphs hold the scaling pointer (or its absence)
+  return IETI_OK;
 }
 
 // Capture two PCG iterations (parities 0 and 1) as one graph per precision.
@@ -721,7 +772,7 @@ int run_pcg(ieti_handle* h, const std::vector<double>& tol2, const std::vector<d
   // z_0 = M r_0, p_0 = z_0, rz_0, partials of H^T p_0
   const int pf = fp32 ? 1 : 0;
   const int gt = gvariant(h, pf) / 4;
-  D::gather_rows(h->r.ptr, h->row_src.ptr, m_r, h->xgr.ptr, s);
+  D::gather_rows(h->r.ptr, h->row_src.ptr, m_r, h->xgr.ptr, s, dsc(h));
   if (fp32)
     D::gemv(h->S32.ptr, gtasks(h, pf), gcount(h, pf), h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr,
             nullptr, s, gvariant(h, pf));
@@ -729,7 +780,7 @@ int run_pcg(ieti_handle* h, const std::vector<double>& tol2, const std::vector<d
     D::gemv(h->S.ptr, gtasks(h, pf), gcount(h, pf), h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr,
             nullptr, s, gvariant(h, pf));
   D::pcg_M(h->v.ptr, h->row_src.ptr, h->H.ptr, h->part_g.ptr, part_rr, h->p.ptr, h->z.ptr, h->xgp.ptr, h->part_t.ptr,
-           h->scal.ptr, 0, h->pdone.ptr, h->piters.ptr, 1, h->B, gt, s);
+           h->scal.ptr, 0, h->pdone.ptr, h->piters.ptr, 1, h->B, gt, s, dsc(h));
   if (use_graph) {
     int rc = capture_graph(h, fp32);
     if (rc) return rc;
@@ -1046,6 +1097,9 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   if (T != D::TILE) return fail(IETI_ERR_INVALID_ARG, "only tile size 64 is built");
   if (opts && opts->precision != IETI_PREC_FP64 && opts->precision != IETI_PREC_MIXED)
     return fail(IETI_ERR_INVALID_ARG, "unknown precision");
+  const int scaling = opts ? opts->scaling : IETI_SCALE_IDENTITY;
+  if (scaling != IETI_SCALE_IDENTITY && scaling != IETI_SCALE_STIFFNESS && scaling != IETI_SCALE_MULTIPLICITY)
+    return fail(IETI_ERR_INVALID_ARG, "unknown scaling");
   int rc = build_plan_if_needed(h, T, opts ? opts->ordering : 0);
   if (rc) return rc;
   rc = upload(h);
@@ -1122,6 +1176,8 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   if (forced < 0 || forced > D::GEMV_VARIANTS) return fail(IETI_ERR_INVALID_ARG, "gemv_variant out of range");
   if ((rc = choose_gemv(h, forced, 0))) return rc;
   if (h->mixed && (rc = choose_gemv(h, forced, 1))) return rc;
+  // recomputed on every factorisation: it follows the assembled stiffness (set_coefficients)
+  if ((rc = set_scaling(h, scaling))) return rc;
   h->factored = true;
   return IETI_OK;
 }

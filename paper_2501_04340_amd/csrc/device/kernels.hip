@@ -481,12 +481,13 @@ __global__ void k_tri_small(const double* L, const double* in, double* out, int 
 
 // Signed Boolean gather of a multiplier vector into interface slots:
 // xg[slot(+1 side)] = x[row], xg[slot(-1 side)] = -x[row]  (xg = B^T x).
-__global__ void k_gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg) {
+__global__ void k_gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg, const double* ds) {
   const int64_t row = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (row >= m_r) return;
   const double v = x[row];
-  xg[row_src[2 * row]] = v;
-  xg[row_src[2 * row + 1]] = -v;
+  const int64_t s0 = row_src[2 * row], s1 = row_src[2 * row + 1];
+  xg[s0] = ds ? ds[s0] * v : v;
+  xg[s1] = ds ? -ds[s1] * v : -v;
 }
 
 // Batched dense GEMV over the per-subdomain interface blocks, v = M_k xg_k
@@ -661,13 +662,15 @@ __device__ inline double coarse_row(const double* H, const int64_t* P, int64_t r
 
 // q[row] = v[+1 slot] - v[-1 slot] + sum_c H_p[row][c] t_p[c]  (H may be null)
 __global__ __launch_bounds__(256) void k_combine(const double* v, const int64_t* row_src, const double* H,
-                                                 const double* t, double* q, const int64_t* pd, const int64_t* blk) {
+                                                 const double* t, double* q, const int64_t* pd, const int64_t* blk,
+                                                 const double* ds) {
   int64_t row0;
   const int64_t nrow = blk_rows(blk, pd, blockIdx.x, &row0);
   if (int64_t(threadIdx.x) >= nrow) return;
   const int64_t* P = pd + PD_N * blk[2 * blockIdx.x + 1];
   const int64_t row = row0 + threadIdx.x;
-  double val = v[row_src[2 * row]] - v[row_src[2 * row + 1]];
+  const int64_t s0 = row_src[2 * row], s1 = row_src[2 * row + 1];
+  double val = ds ? ds[s0] * v[s0] - ds[s1] * v[s1] : v[s0] - v[s1];
   if (H && P[PD_NGP] > 0) val += coarse_row(H, P, row, t + P[PD_GP0]);
   q[row] = val;
 }
@@ -682,7 +685,7 @@ __global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* r
                                                const double* part_t, const double* part_g, const double* p,
                                                double* lam, double* r, double* xg_r, double* part_rr, double* scal,
                                                int par, int* done, int* err, const int64_t* pd, const int64_t* blk,
-                                               int gt) {
+                                               int gt, const double* ds) {
   const int64_t b = blockIdx.x, pid = blk[2 * b + 1];
   if (done[pid]) return;
   extern __shared__ double tl[];
@@ -716,8 +719,8 @@ __global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* r
     const double rn = r[row] - alpha * q;
     r[row] = rn;
     rr = rn * rn;
-    xg_r[s0] = rn;
-    xg_r[s1] = -rn;
+    xg_r[s0] = ds ? ds[s0] * rn : rn;
+    xg_r[s1] = ds ? -ds[s1] * rn : -rn;
   }
   const double srr = block_sum256(rr, red);
   if (threadIdx.x == 0) part_rr[b] = srr;
@@ -731,7 +734,8 @@ __global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* r
 __global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* row_src, const double* H,
                                                const double* part_g, const double* part_rr, double* p, double* z,
                                                double* xg_p, double* part_t, double* scal, int par, int* done,
-                                               int* iters, int init, const int64_t* pd, const int64_t* blk, int gt) {
+                                               int* iters, int init, const int64_t* pd, const int64_t* blk, int gt,
+                                               const double* ds) {
   const int64_t b = blockIdx.x, pid = blk[2 * b + 1];
   if (done[pid]) return;
   __shared__ double red[4];
@@ -763,7 +767,7 @@ __global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* r
   if (int64_t(threadIdx.x) < nrow) {
     const int64_t row = row0 + threadIdx.x;
     const int64_t s0 = row_src[2 * row], s1 = row_src[2 * row + 1];
-    const double zz = w[s0] - w[s1];
+    const double zz = ds ? ds[s0] * w[s0] - ds[s1] * w[s1] : w[s0] - w[s1];
     z[row] = zz;
     // the first direction is z itself: p holds no value yet (not even a finite one)
     pv = init ? zz : zz + beta * p[row];
@@ -934,9 +938,9 @@ void tri_small(const double* L, const double* in, double* out, bool transposed, 
   hipLaunchKernelGGL(k_tri_small, dim3((B.n_prob + 63) / 64), dim3(64), 0, s, L, in, out, transposed ? 1 : 0, B.pd,
                      B.n_prob);
 }
-void gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg, hipStream_t s) {
+void gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg, hipStream_t s, const double* ds) {
   if (m_r <= 0) return;
-  hipLaunchKernelGGL(k_gather_rows, dim3((m_r + 255) / 256), dim3(256), 0, s, x, row_src, m_r, xg);
+  hipLaunchKernelGGL(k_gather_rows, dim3((m_r + 255) / 256), dim3(256), 0, s, x, row_src, m_r, xg, ds);
 }
 GemvShape gemv_shape(int variant) {
   static const int rpw[3] = {2, 4, 8};
@@ -999,23 +1003,23 @@ void coarse_project(const double* Ht, const double* x, double* out, const int32_
   hipLaunchKernelGGL(k_coarse_project, dim3(B.n_gp_total), dim3(256), 0, s, Ht, x, out, B.pd, cprob);
 }
 void combine(const double* v, const int64_t* row_src, const double* H, const double* t, double* q, const Batch& B,
-             hipStream_t s) {
+             hipStream_t s, const double* ds) {
   if (B.n_blk <= 0) return;
-  hipLaunchKernelGGL(k_combine, dim3(B.n_blk), dim3(256), 0, s, v, row_src, H, t, q, B.pd, B.blk);
+  hipLaunchKernelGGL(k_combine, dim3(B.n_blk), dim3(256), 0, s, v, row_src, H, t, q, B.pd, B.blk, ds);
 }
 void pcg_F(const double* v, const int64_t* row_src, const double* H, const double* part_t, const double* part_g,
            const double* p, double* lam, double* r, double* xg_r, double* part_rr, double* scal, int par, int* done,
-           int* err, const Batch& B, int gt, hipStream_t s) {
+           int* err, const Batch& B, int gt, hipStream_t s, const double* ds) {
   if (B.n_blk <= 0) return;
   hipLaunchKernelGGL(k_pcg_F, dim3(B.n_blk), dim3(256), size_t(B.max_gp > 0 ? B.max_gp : 1) * sizeof(double), s, v,
-                     row_src, H, part_t, part_g, p, lam, r, xg_r, part_rr, scal, par, done, err, B.pd, B.blk, gt);
+                     row_src, H, part_t, part_g, p, lam, r, xg_r, part_rr, scal, par, done, err, B.pd, B.blk, gt, ds);
 }
 void pcg_M(const double* w, const int64_t* row_src, const double* H, const double* part_g, const double* part_rr,
            double* p, double* z, double* xg_p, double* part_t, double* scal, int par, int* done, int* iters, int init,
-           const Batch& B, int gt, hipStream_t s) {
+           const Batch& B, int gt, hipStream_t s, const double* ds) {
   if (B.n_blk <= 0) return;
   hipLaunchKernelGGL(k_pcg_M, dim3(B.n_blk), dim3(256), 0, s, w, row_src, H, part_g, part_rr, p, z, xg_p, part_t,
-                     scal, par, done, iters, init, B.pd, B.blk, gt);
+                     scal, par, done, iters, init, B.pd, B.blk, gt, ds);
 }
 void gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out, hipStream_t s) {
   if (n <= 0) return;

@@ -60,8 +60,10 @@ void solve_rows_LT(const double* L, const double* G, double* H, double* Ht, cons
 void tri_small(const double* L, const double* in, double* out, bool transposed, const Batch& B, hipStream_t s);
 
 // ---- interface operators and PCG (FP64 recurrences)
-// xg[slot(+1)] = x[row], xg[slot(-1)] = -x[row]
-void gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg, hipStream_t s);
+// xg[slot(+1)] = x[row], xg[slot(-1)] = -x[row]; with ds (per slot, may be null) the
+// scaled jump operator of the preconditioner: xg[slot] = +-ds[slot] x[row]
+void gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg, hipStream_t s,
+                 const double* ds = nullptr);
 // v[slot] = (M_k xg_k)[slot] for every interface slot; part[block] = sum xg.v over the block's rows.
 // task [matrix row start, first slot, nrows, ld, first slot of the subdomain]; done (per problem,
 // may be null) with task_prob skips the tasks of finished problems; ev_* may be null.
@@ -86,17 +88,19 @@ void to_float(const double* in, float* out, int64_t n, hipStream_t s);
 // out[c] = sum over problem(c)'s rows of Ht[c][row] x[row]; cprob[c] = problem of global primal c
 void coarse_project(const double* Ht, const double* x, double* out, const int32_t* cprob, const Batch& B,
                     hipStream_t s);
-// q[row] = v[src0] - v[src1] + sum_c H_p[row][c] t_p[c]  (H may be null)
+// q[row] = v[src0] - v[src1] + sum_c H_p[row][c] t_p[c]  (H may be null); with ds:
+// ds[src0] v[src0] - ds[src1] v[src1]
 void combine(const double* v, const int64_t* row_src, const double* H, const double* t, double* q, const Batch& B,
-             hipStream_t s);
+             hipStream_t s, const double* ds = nullptr);
 // scal + 8 p: [0..1] rz (ping-pong by iteration parity par), [2] alpha, [3] beta, [4] tol^2, [5] ||r||^2;
-// done / iters per problem; gt = index of the GEMV task list in use (part_g ranges)
+// done / iters per problem; gt = index of the GEMV task list in use (part_g ranges);
+// ds = per-slot scaling of the preconditioner's jump operator, or null (D_s = I)
 void pcg_F(const double* v, const int64_t* row_src, const double* H, const double* part_t, const double* part_g,
            const double* p, double* lam, double* r, double* xg_r, double* part_rr, double* scal, int par, int* done,
-           int* err, const Batch& B, int gt, hipStream_t s);
+           int* err, const Batch& B, int gt, hipStream_t s, const double* ds);
 void pcg_M(const double* w, const int64_t* row_src, const double* H, const double* part_g, const double* part_rr,
            double* p, double* z, double* xg_p, double* part_t, double* scal, int par, int* done, int* iters, int init,
-           const Batch& B, int gt, hipStream_t s);
+           const Batch& B, int gt, hipStream_t s, const double* ds);
 
 // ---- recovery / rhs helpers
 void gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out, hipStream_t s);

@@ -16,6 +16,7 @@ _lib = None
 
 ABI_VERSION = 1
 PREC_FP64, PREC_MIXED = 0, 1
+SCALE_IDENTITY, SCALE_STIFFNESS, SCALE_MULTIPLICITY = 0, 1, 2
 ERRORS = {
     -1: "INVALID_ARG", -2: "PARTITION", -3: "TREE", -4: "NOT_SPD", -5: "BREAKDOWN",
     -6: "NOT_CONVERGED", -7: "HIP", -8: "STATE",
@@ -46,6 +47,8 @@ class FactorOpts(C.Structure):
         ("tile", C.c_int32),
         ("ordering", C.c_int32),
         ("gemv_variant", C.c_int32),
+        ("scaling", C.c_int32),
+        ("reserved", C.c_int32),
         ("hip_stream", C.c_void_p),
     ]
 
@@ -323,9 +326,10 @@ class Solver:
         K = sp.csr_matrix((values[:nnz.value], indices[:nnz.value], indptr), shape=(n.value, n.value))
         return K, load[:n.value]
 
-    def factor(self, precision=PREC_FP64, ordering=0, stream=None, gemv_variant=None):
+    def factor(self, precision=PREC_FP64, ordering=0, stream=None, gemv_variant=None, scaling=SCALE_IDENTITY):
         o = FactorOpts()
         o.precision = precision
+        o.scaling = int(scaling)
         o.tile = 0
         o.ordering = ordering
         o.gemv_variant = 0 if gemv_variant is None else int(gemv_variant) + 1
