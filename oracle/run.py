@@ -19,6 +19,12 @@ class OracleRun:
         self.prob = prob
         self.space = Space(prob)
         self.mats, self.loads = self.space.assemble()
+        # non-homogeneous Dirichlet data: prescribed boundary coefficients and lifted loads
+        self.d_ids = np.zeros(0, dtype=np.int64)
+        self.d_vals = np.zeros(0)
+        if getattr(prob, "dirichlet_A", None) is not None:
+            self.d_ids, self.d_vals = self.space.dirichlet_values()
+            self.loads = self.space.lift_loads(self.mats, self.loads, self.d_ids, self.d_vals)
         t1 = time.perf_counter()
         self.topo = build_topology(self.space, primal_enabled=primal_enabled)
         t2 = time.perf_counter()
@@ -36,6 +42,7 @@ class OracleRun:
     def monolithic(self):
         t = time.perf_counter()
         a, K, j = solve_monolithic(self.space, self.topo, self.mats, self.loads)
+        a[self.d_ids] = self.d_vals
         self.timing["monolithic_s"] = time.perf_counter() - t
         self.K_g, self.j_g = K, j
         return a
@@ -45,6 +52,7 @@ class OracleRun:
         t = time.perf_counter()
         lam, info = D.pcg(rtol=rtol, maxit=maxit, lam0=lam0)
         a = D.recover(lam)
+        a[self.d_ids] = self.d_vals
         self.timing["pcg_s"] = time.perf_counter() - t
         info["kappa"] = lanczos_condition(info)
         return a, lam, info

@@ -30,6 +30,7 @@ from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from workloads.problem import patch_coords
 
@@ -301,6 +302,85 @@ class Space:
             mats.append(sp.csr_matrix((nu * K[r, c], (g[r], g[c])), shape=(self.n_edges, self.n_edges)))
             loads.append((g, j if with_load else np.zeros(g.size)))
         return mats, loads
+
+    def dirichlet_values(self):
+        """Boundary DOFs of n x A = n x A_D: the L2 projection of the
+        tangential trace of A_D onto the tangential traces of the boundary
+        basis functions, over every patch face on the boundary of the
+        domain.  Only functions of the two tangential components whose index
+        across the face is the first (or last) one have a tangential trace
+        there (open knot vectors); the normal component's push-forward is
+        normal to the face.  Returns (edge ids, values)."""
+        A_D = self.prob.dirichlet_A
+        p, n = self.p, self.n
+        xq, wq, N, dN, D = self._tables()
+        M = len(xq)
+        rows, cols, vals = [], [], []
+        rhs = np.zeros(self.n_edges)
+        P = self.P
+        for pidx in range(int(np.prod(P))):
+            pc = (pidx % P[0], (pidx // P[0]) % P[1], pidx // (P[0] * P[1]))
+            g = self.patch_local_edges(pidx)
+            for d in range(3):
+                if self.per[d]:
+                    continue
+                for side in (0, 1):
+                    if pc[d] != (0 if side == 0 else P[d] - 1):
+                        continue
+                    a, b = [x for x in range(3) if x != d]
+                    # face quadrature grid: xi_a fastest
+                    ia, ib = np.meshgrid(np.arange(M), np.arange(M), indexing="xy")
+                    ia, ib = ia.ravel(), ib.ravel()
+                    xi = np.zeros((ia.size, 3))
+                    xi[:, a], xi[:, b], xi[:, d] = xq[ia], xq[ib], float(side)
+                    W = wq[ia] * wq[ib]
+                    x, DF = patch_map(self.prob, pidx, xi)
+                    DFinvT = np.linalg.inv(DF).transpose(0, 2, 1)
+                    det = np.abs(np.linalg.det(DF))
+                    nvec = DFinvT[:, :, d]
+                    nn = np.linalg.norm(nvec, axis=1)
+                    nhat = nvec / nn[:, None]
+                    dS = W * det * nn
+                    fun_vals, fun_ids = [], []
+                    for c in (a, b):
+                        le = [n - 1 if q == c else n for q in range(3)]
+                        base = sum(int(np.prod([n - 1 if q == cc else n for q in range(3)])) for cc in range(c))
+                        ta = D if a == c else N       # (M, le[a])
+                        tb = D if b == c else N
+                        s_ab = (tb[ib][:, :, None] * ta[ia][:, None, :]).reshape(ia.size, -1)  # index i_a fastest
+                        ii_a, ii_b = np.meshgrid(np.arange(le[a]), np.arange(le[b]), indexing="xy")
+                        ii_a, ii_b = ii_a.ravel(), ii_b.ravel()
+                        idx = [None, None, None]
+                        idx[a], idx[b], idx[d] = ii_a, ii_b, np.full(ii_a.size, 0 if side == 0 else le[d] - 1)
+                        loc = base + idx[0] + le[0] * (idx[1] + le[1] * idx[2])
+                        w = DFinvT[:, :, c][:, :, None] * s_ab[:, None, :]          # (Q, 3, nf)
+                        wt = w - np.einsum("qa,qaf->qf", nhat, w)[:, None, :] * nhat[:, :, None]
+                        fun_vals.append(wt)
+                        fun_ids.append(g[loc])
+                    wt = np.concatenate(fun_vals, axis=2)
+                    ids = np.concatenate(fun_ids)
+                    Mf = np.einsum("qaf,qag,q->fg", wt, wt, dS)
+                    bf = np.einsum("qa,qaf,q->f", A_D(x), wt, dS)
+                    r, cc = np.meshgrid(ids, ids, indexing="ij")
+                    rows.append(r.ravel())
+                    cols.append(cc.ravel())
+                    vals.append(Mf.ravel())
+                    np.add.at(rhs, ids, bf)
+        rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+        ids = np.unique(rows)
+        if not np.all(self.dirichlet[ids]):
+            raise RuntimeError("a boundary function is not a Dirichlet DOF")
+        pos = np.full(self.n_edges, -1)
+        pos[ids] = np.arange(ids.size)
+        Mg = sp.csr_matrix((vals, (pos[rows], pos[cols])), shape=(ids.size, ids.size)).tocsc()
+        return ids, spla.spsolve(Mg, rhs[ids])
+
+    def lift_loads(self, mats, loads, d_ids, d_vals):
+        """Loads minus the coupling to the prescribed Dirichlet coefficients:
+        j - K a_D per patch (the Dirichlet rows themselves are never used)."""
+        aD = np.zeros(self.n_edges)
+        aD[d_ids] = d_vals
+        return [(g, j - (K @ aD)[g]) for K, (g, j) in zip(mats, loads)]
 
     def global_load(self, loads):
         jg = np.zeros(self.n_edges)

@@ -165,6 +165,21 @@ def stream_problem(i):
                        meta={"partition_attempts": attempts})
 
 
+def paper_cube(degree=2, n_el=2, n_sub=3, seed=None):
+    """The paper's experiment domain (Section 4): (0,3)^3 in 3x3x3 unit
+    patches, nu = 1, the closed-form A_ana with its tangential trace as
+    Dirichlet data, and an admissible seeded partition into n_sub
+    subdomains (greedy region growing in place of METIS)."""
+    P = (3, 3, 3)
+    seed = MASTER_SEEDS["cube8"] * 1000 + 27 * 100 + int(n_sub) if seed is None else int(seed)
+    part, attempts = greedy_partition(P, int(n_sub), seed=seed, smin=1, smax=27)
+    prob = box_problem(P, degree, n_el, part, np.ones(27), sources.paper_J, name=f"paper_cube[{n_sub}]",
+                       exact_A=sources.paper_A, exact_B=sources.paper_B, extent=(0.0, 3.0, 0.0, 3.0, 0.0, 3.0),
+                       seed=seed, meta={"partition_attempts": attempts})
+    prob.dirichlet_A = sources.paper_A
+    return prob
+
+
 def make_config(name, **kw):
     if name == "cube8":
         return cube8(**kw)
@@ -174,6 +189,8 @@ def make_config(name, **kw):
         return cube256(**kw)
     if name == "ring576":
         return ring576(**kw)
+    if name == "paper_cube":
+        return paper_cube(**kw)
     if name == "stream256":
         return [stream_problem(i) for i in range(kw.get("count", 256))]
     raise KeyError(name)

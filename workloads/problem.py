@@ -12,8 +12,9 @@ Conventions (the paper fixes none of them; both implementations follow these):
   ``geom_params = [z0, z1, r_0, r_1, ..., r_P1]``.
 * The reluctivity is constant per patch; the source J is given as a callable
   mapping physical points ``(n, 3)`` to vectors ``(n, 3)``.
-* Homogeneous Dirichlet data ``n x A = 0`` on the whole boundary (the
-  setting the paper's derivation uses, Section 2).
+* Dirichlet data ``n x A = n x A_D`` on the whole boundary, with ``A_D`` a
+  vector field (``dirichlet_A``); ``None`` means ``n x A = 0``, the setting
+  the paper's derivation uses (Section 2).
 """
 from __future__ import annotations
 
@@ -51,6 +52,8 @@ class Problem:
     source: Callable[[np.ndarray], np.ndarray]
     exact_A: Optional[Callable[[np.ndarray], np.ndarray]] = None
     exact_B: Optional[Callable[[np.ndarray], np.ndarray]] = None
+    # Dirichlet data: n x A = n x dirichlet_A on the whole boundary (None: n x A = 0)
+    dirichlet_A: Optional[Callable[[np.ndarray], np.ndarray]] = None
     seed: int = 0
     meta: dict = field(default_factory=dict)
 

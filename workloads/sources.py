@@ -197,3 +197,45 @@ class CoilSource:
         out[:, 0] = -c * xyz[:, 1] / rs
         out[:, 1] = c * xyz[:, 0] / rs
         return out
+
+
+# ---------------------------------------------------------------------------
+# Closed-form solution of the paper's numerical experiments on (0,3)^3
+# (Section 4), nu = 1: A is divergence free, so J = curl curl A = -Laplace A
+# = 3 A; B = curl A.
+# ---------------------------------------------------------------------------
+def paper_A(xyz):
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return np.stack([np.cos(y) * np.cos(z) * np.sin(x), -2.0 * np.cos(x) * np.cos(z) * np.sin(y),
+                     np.cos(x) * np.cos(y) * np.sin(z)], axis=1)
+
+
+def paper_B(xyz):
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return np.stack([-3.0 * np.cos(x) * np.sin(y) * np.sin(z), np.zeros_like(x),
+                     3.0 * np.cos(z) * np.sin(x) * np.sin(y)], axis=1)
+
+
+def paper_J(xyz):
+    return 3.0 * paper_A(xyz)
+
+
+# ---------------------------------------------------------------------------
+# A field of the degree-2 curl-conforming spline space with a non-zero
+# tangential trace: A = (y^2 z, x z^2, x^2 y) (each component has degree <= 1
+# along its own direction and <= 2 along the others), div A = 0, so with
+# nu = 1: J = -Laplace A = -2 (z, x, y), B = curl A.
+# ---------------------------------------------------------------------------
+def trace_A(xyz):
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return np.stack([y * y * z, x * z * z, x * x * y], axis=1)
+
+
+def trace_B(xyz):
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return np.stack([x * x - 2 * x * z, y * y - 2 * x * y, z * z - 2 * y * z], axis=1)
+
+
+def trace_J(xyz):
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return -2.0 * np.stack([z, x, y], axis=1)
