@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define IETI_ABI_VERSION 1
+#define IETI_ABI_VERSION 2
 
 enum {
   IETI_OK = 0,
@@ -79,7 +79,12 @@ typedef void (*ieti_field_fn)(const double* xyz, int64_t npts, double* out_vec3,
  *   degree_p   degree of the H^1 B-splines (curl components have degree p-1
  *              along their own direction), 1 <= p <= 6.
  *   patch_to_subdomain [n_patches] values 0..N_sub-1, every id used.
- *   nu_per_patch       [n_patches], > 0. */
+ *   nu_per_patch       [n_patches], > 0.
+ * Non-homogeneous Dirichlet data: the boundary coefficients are the L2
+ * projection of the tangential trace of A_D onto the tangential traces of
+ * the boundary basis functions (over every boundary patch face, Gauss points
+ * as in the volume); the loads are lifted by -K a_D and the boundary values
+ * are part of the returned coefficient vector. */
 typedef struct {
   int32_t version;             /* must equal IETI_ABI_VERSION */
   int32_t geom_kind;
@@ -92,6 +97,9 @@ typedef struct {
   const double* nu_per_patch;
   ieti_field_fn J;
   void* J_user;
+  ieti_field_fn A_D;           /* Dirichlet data n x A = n x A_D on the whole boundary (a vector
+                                  field called like J at boundary points); NULL: n x A = 0 */
+  void* A_D_user;
 } ieti_problem;
 
 typedef struct {

@@ -44,7 +44,8 @@ struct ieti_handle {
   DBuf<int64_t> scatter_dst, potrf, trsm, upd, upd_pair, copyS, xsinv, xphi, xspi, fdiag, ffull, ffull_pair, fr, fr_pair;
   DBuf<int64_t> bdiag, bupd, bupd_pair;
   DBuf<int64_t> spi_ptr, spi_src, row_src, I_aug, A_aug, slot_phi_row, dsrc_ptr, dsrc_idx, krp_ptr, krp_pos;
-  DBuf<int64_t> out_src, out_edge, primal_edges;
+  DBuf<int64_t> out_src, out_edge, primal_edges, d_edges;  // d_edges: prescribed boundary coefficients
+  DBuf<double> d_vals;
   DBuf<int64_t> gemv_tasks[3];
   int ngemv_r[3] = {0, 0, 0};
   int gvar[2] = {-1, -1};                              // GEMV launch shape for FP64 / FP32 blocks (-1 = untuned)
@@ -117,6 +118,8 @@ struct ieti_handle {
     for (auto* d : is) d->release();
     I_row.release();
     I_sub.release();
+    d_edges.release();
+    d_vals.release();
     pd.release();
     blk.release();
     g2l_off.release();
@@ -236,6 +239,8 @@ int upload(ieti_handle* h) {
   UP(out_src, P.out_src);
   UP(out_edge, P.out_edge);
   UP(primal_edges, M.primal_edges);
+  UP(d_edges, M.d_edges);
+  UP(d_vals, M.d_vals);
   UP(b_aug0, P.b_aug0);
   // per interface slot: start of its row in Phi
   std::vector<int64_t> phirow(P.I_total, 0);
@@ -920,6 +925,7 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   D::fill(aout, M.n_edges_total, 0.0, s);
   D::write_output(h->y.ptr, h->out_src.ptr, h->out_edge.ptr, int64_t(P.out_src.size()), h->pglob.ptr,
                   h->primal_edges.ptr, M.n_gp, aout, s);
+  if (!M.d_edges.empty()) D::scatter(aout, h->d_edges.ptr, h->d_vals.ptr, int64_t(M.d_edges.size()), s);
   hipEvent_t evend;
   HIP_TRY(hipEventCreate(&evend));
   HIP_TRY(hipEventRecord(evend, s));
@@ -1002,8 +1008,10 @@ int assemble_model(const ieti_problem* prob, ieti::Model& m) {
   rc = ieti::build_topology(m, err);
   if (!rc) rc = ieti::assemble_local_systems(m, err);
   if (rc) return fail(rc, err.msg);
-  m.prob.J = nullptr;  // the callback is not kept beyond the assembly call
+  m.prob.J = nullptr;  // the callbacks are not kept beyond the assembly call
   m.prob.J_user = nullptr;
+  m.prob.A_D = nullptr;
+  m.prob.A_D_user = nullptr;
   ieti::finalize_single(m);
   return IETI_OK;
 }

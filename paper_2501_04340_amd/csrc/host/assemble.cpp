@@ -170,6 +170,225 @@ void patch_map(const ieti_problem& pr, int64_t q, const double xi[3], double x[3
   DF[2][2] = hz;
 }
 
+// Boundary L2 projection of n x A_D: boundary DOFs a_D with
+// sum_e a_e int (w_e)_t . (w_f)_t dS = int (A_D)_t . (w_f)_t dS for every
+// boundary function f, over the patch faces on the boundary of the domain.
+// Only the two tangential components with index 0 (or last) across the face
+// have a tangential trace there (open knots; the normal component's
+// push-forward DF^{-T} e_d is normal to the face).  The mass system is
+// solved by Jacobi-preconditioned CG.  aD is indexed by global edge id.
+int dirichlet_projection(const Model& m, const Basis1D& bs, std::vector<double>& aD, Error& err) {
+  const Mesh& M = m.mesh;
+  const int p = M.p, n = M.n, n1 = n - 1, ne = M.n_el, nq = bs.nq;
+  const int64_t n_patches = int64_t(M.P[0]) * M.P[1] * M.P[2];
+  struct Face {
+    int64_t q;
+    int d, side;
+  };
+  std::vector<Face> faces;
+  for (int64_t q = 0; q < n_patches; ++q) {
+    const int64_t pc[3] = {q % M.P[0], (q / M.P[0]) % M.P[1], q / (int64_t(M.P[0]) * M.P[1])};
+    for (int d = 0; d < 3; ++d) {
+      if (M.per[d]) continue;
+      if (pc[d] == 0) faces.push_back({q, d, 0});
+      if (pc[d] == M.P[d] - 1) faces.push_back({q, d, 1});
+    }
+  }
+  const int64_t per_face = int64_t(ne) * ne * nq * nq;
+  // points of every face (element-major, then Gauss points; axis a fastest)
+  std::vector<double> pts(size_t(faces.size()) * per_face * 3), dfs(size_t(faces.size()) * per_face * 9);
+  for (size_t f = 0; f < faces.size(); ++f) {
+    const int d = faces[f].d, a = (d + 1) % 3 < (d + 2) % 3 ? (d + 1) % 3 : (d + 2) % 3;
+    const int b = 3 - d - a;
+    for (int64_t t = 0; t < per_face; ++t) {
+      const int qa = int(t % nq), qb = int((t / nq) % nq), ea = int((t / (nq * nq)) % ne), eb = int(t / (int64_t(nq) * nq * ne));
+      double xi[3], x[3], DF[3][3];
+      xi[a] = bs.xq[ea * nq + qa];
+      xi[b] = bs.xq[eb * nq + qb];
+      xi[d] = double(faces[f].side);
+      patch_map(m.prob, faces[f].q, xi, x, DF);
+      for (int c = 0; c < 3; ++c) pts[(f * per_face + t) * 3 + c] = x[c];
+      for (int r = 0; r < 9; ++r) dfs[(f * per_face + t) * 9 + r] = DF[r / 3][r % 3];
+    }
+  }
+  std::vector<double> Ad(pts.size(), 0.0);
+  m.prob.A_D(pts.data(), int64_t(pts.size() / 3), Ad.data(), m.prob.A_D_user);
+  for (double v : Ad)
+    if (!std::isfinite(v)) {
+      err = {IETI_ERR_INVALID_ARG, "Dirichlet data returned a non-finite value"};
+      return err.code;
+    }
+  // element face matrices -> global triplets over Dirichlet edges
+  std::vector<int64_t> pos(M.n_edges, -1), dofs;
+  for (int64_t e = 0; e < M.n_edges; ++e)
+    if (m.dirichlet[e]) {
+      pos[e] = int64_t(dofs.size());
+      dofs.push_back(e);
+    }
+  const int64_t nD = int64_t(dofs.size());
+  struct T3 {
+    int64_t r, c;
+    double v;
+  };
+  std::vector<T3> trip;
+  std::vector<double> rhs(nD, 0.0);
+  const int nfe = 2 * p * (p + 1);
+  std::vector<int64_t> fid(nfe);
+  std::vector<double> wt(size_t(nfe) * 3), Me(size_t(nfe) * nfe), be(nfe);
+  for (size_t f = 0; f < faces.size(); ++f) {
+    const int d = faces[f].d, a = (d + 1) % 3 < (d + 2) % 3 ? (d + 1) % 3 : (d + 2) % 3;
+    const int b = 3 - d - a;
+    const int64_t q = faces[f].q;
+    const int64_t pc[3] = {q % M.P[0], (q / M.P[0]) % M.P[1], q / (int64_t(M.P[0]) * M.P[1])};
+    for (int ea = 0; ea < ne; ++ea)
+      for (int eb = 0; eb < ne; ++eb) {
+        // element face functions: component c in {a, b}, active indices along a and b
+        int k = 0;
+        for (int c : {a, b}) {
+          const int ma = (a == c) ? p : p + 1, mb = (b == c) ? p : p + 1;
+          for (int ib = 0; ib < mb; ++ib)
+            for (int ia = 0; ia < ma; ++ia, ++k) {
+              int64_t idx[3];
+              idx[a] = ea + ia;
+              idx[b] = eb + ib;
+              idx[d] = faces[f].side == 0 ? 0 : n - 1;  // c != d: n functions across the face
+              fid[k] = pos[M.edge_id(c, M.wrap(0, pc[0] * n1 + idx[0]), M.wrap(1, pc[1] * n1 + idx[1]),
+                                     M.wrap(2, pc[2] * n1 + idx[2]))];
+              if (fid[k] < 0) {
+                err = {IETI_ERR_TREE, "a boundary face function is not a Dirichlet DOF"};
+                return err.code;
+              }
+            }
+        }
+        std::fill(Me.begin(), Me.end(), 0.0);
+        std::fill(be.begin(), be.end(), 0.0);
+        for (int qb = 0; qb < nq; ++qb)
+          for (int qa = 0; qa < nq; ++qa) {
+            const int64_t t = qa + nq * (qb + int64_t(nq) * (ea + int64_t(ne) * eb));
+            const double* D9 = &dfs[(f * per_face + t) * 9];
+            double DF[3][3];
+            for (int r = 0; r < 9; ++r) DF[r / 3][r % 3] = D9[r];
+            const double det = DF[0][0] * (DF[1][1] * DF[2][2] - DF[1][2] * DF[2][1]) -
+                               DF[0][1] * (DF[1][0] * DF[2][2] - DF[1][2] * DF[2][0]) +
+                               DF[0][2] * (DF[1][0] * DF[2][1] - DF[1][1] * DF[2][0]);
+            // columns of DF^{-T}: G[:, c] = cof(DF)[:, c] / det
+            double G[3][3];
+            G[0][0] = (DF[1][1] * DF[2][2] - DF[1][2] * DF[2][1]) / det;
+            G[0][1] = -(DF[1][0] * DF[2][2] - DF[1][2] * DF[2][0]) / det;
+            G[0][2] = (DF[1][0] * DF[2][1] - DF[1][1] * DF[2][0]) / det;
+            G[1][0] = -(DF[0][1] * DF[2][2] - DF[0][2] * DF[2][1]) / det;
+            G[1][1] = (DF[0][0] * DF[2][2] - DF[0][2] * DF[2][0]) / det;
+            G[1][2] = -(DF[0][0] * DF[2][1] - DF[0][1] * DF[2][0]) / det;
+            G[2][0] = (DF[0][1] * DF[1][2] - DF[0][2] * DF[1][1]) / det;
+            G[2][1] = -(DF[0][0] * DF[1][2] - DF[0][2] * DF[1][0]) / det;
+            G[2][2] = (DF[0][0] * DF[1][1] - DF[0][1] * DF[1][0]) / det;
+            const double nv[3] = {G[0][d], G[1][d], G[2][d]};
+            const double nl = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            const double nh[3] = {nv[0] / nl, nv[1] / nl, nv[2] / nl};
+            const double dS = bs.wq[ea * nq + qa] * bs.wq[eb * nq + qb] * std::fabs(det) * nl;
+            int kk = 0;
+            for (int c : {a, b}) {
+              const int ma = (a == c) ? p : p + 1, mb = (b == c) ? p : p + 1;
+              for (int ib = 0; ib < mb; ++ib)
+                for (int ia = 0; ia < ma; ++ia, ++kk) {
+                  const double fa = (a == c) ? bs.D[(ea * nq + qa) * p + ia] : bs.N[(ea * nq + qa) * (p + 1) + ia];
+                  const double fb = (b == c) ? bs.D[(eb * nq + qb) * p + ib] : bs.N[(eb * nq + qb) * (p + 1) + ib];
+                  const double sv = fa * fb;
+                  double w[3] = {G[0][c] * sv, G[1][c] * sv, G[2][c] * sv};
+                  const double wn = w[0] * nh[0] + w[1] * nh[1] + w[2] * nh[2];
+                  for (int r = 0; r < 3; ++r) wt[kk * 3 + r] = w[r] - wn * nh[r];
+                }
+            }
+            const double* A = &Ad[(f * per_face + t) * 3];
+            for (int i = 0; i < nfe; ++i) {
+              const double* wi = &wt[i * 3];
+              be[i] += dS * (A[0] * wi[0] + A[1] * wi[1] + A[2] * wi[2]);
+              for (int j = 0; j < nfe; ++j) {
+                const double* wj = &wt[j * 3];
+                Me[size_t(i) * nfe + j] += dS * (wi[0] * wj[0] + wi[1] * wj[1] + wi[2] * wj[2]);
+              }
+            }
+          }
+        for (int i = 0; i < nfe; ++i) {
+          rhs[fid[i]] += be[i];
+          for (int j = 0; j < nfe; ++j)
+            if (Me[size_t(i) * nfe + j] != 0.0) trip.push_back({fid[i], fid[j], Me[size_t(i) * nfe + j]});
+        }
+      }
+  }
+  // CSR (duplicates summed in a fixed order)
+  std::sort(trip.begin(), trip.end(), [](const T3& x, const T3& y) { return x.r != y.r ? x.r < y.r : x.c < y.c; });
+  std::vector<int64_t> ptr(nD + 1, 0), col;
+  std::vector<double> val;
+  for (size_t i = 0; i < trip.size();) {
+    size_t j = i;
+    double v = 0.0;
+    while (j < trip.size() && trip[j].r == trip[i].r && trip[j].c == trip[i].c) v += trip[j++].v;
+    col.push_back(trip[i].c);
+    val.push_back(v);
+    ptr[trip[i].r + 1]++;
+    i = j;
+  }
+  for (int64_t r = 0; r < nD; ++r) ptr[r + 1] += ptr[r];
+  std::vector<double> dg(nD, 0.0);
+  for (int64_t r = 0; r < nD; ++r)
+    for (int64_t k = ptr[r]; k < ptr[r + 1]; ++k)
+      if (col[k] == r) dg[r] = val[k];
+  for (int64_t r = 0; r < nD; ++r)
+    if (!(dg[r] > 0.0)) {
+      err = {IETI_ERR_TREE, "a Dirichlet DOF has no tangential trace on the boundary"};
+      return err.code;
+    }
+  auto matvec = [&](const std::vector<double>& x, std::vector<double>& y) {
+    for (int64_t r = 0; r < nD; ++r) {
+      double s = 0.0;
+      for (int64_t k = ptr[r]; k < ptr[r + 1]; ++k) s += val[k] * x[col[k]];
+      y[r] = s;
+    }
+  };
+  std::vector<double> x(nD, 0.0), r = rhs, z(nD), pv(nD), Ap(nD);
+  double bnorm = 0.0;
+  for (double v : rhs) bnorm += v * v;
+  bnorm = std::sqrt(bnorm);
+  for (int64_t i = 0; i < nD; ++i) z[i] = r[i] / dg[i];
+  pv = z;
+  double rz = 0.0;
+  for (int64_t i = 0; i < nD; ++i) rz += r[i] * z[i];
+  const int max_it = int(std::min<int64_t>(20 * nD + 100, 1000000));
+  bool conv = bnorm == 0.0;
+  for (int it = 0; it < max_it && !conv; ++it) {
+    matvec(pv, Ap);
+    double pAp = 0.0;
+    for (int64_t i = 0; i < nD; ++i) pAp += pv[i] * Ap[i];
+    const double al = rz / pAp;
+    double rr = 0.0;
+    for (int64_t i = 0; i < nD; ++i) {
+      x[i] += al * pv[i];
+      r[i] -= al * Ap[i];
+      rr += r[i] * r[i];
+    }
+    if (std::sqrt(rr) <= 1e-15 * bnorm) {
+      conv = true;
+      break;
+    }
+    double rz2 = 0.0;
+    for (int64_t i = 0; i < nD; ++i) {
+      z[i] = r[i] / dg[i];
+      rz2 += r[i] * z[i];
+    }
+    const double be2 = rz2 / rz;
+    rz = rz2;
+    for (int64_t i = 0; i < nD; ++i) pv[i] = z[i] + be2 * pv[i];
+  }
+  if (!conv) {
+    err = {IETI_ERR_NOT_CONVERGED, "the boundary projection of the Dirichlet data did not converge"};
+    return err.code;
+  }
+  aD.assign(M.n_edges, 0.0);
+  for (int64_t i = 0; i < nD; ++i) aD[dofs[i]] = x[i];
+  return IETI_OK;
+}
+
 }  // namespace
 
 int assemble_local_systems(Model& m, Error& err) {
@@ -238,8 +457,22 @@ int assemble_local_systems(Model& m, Error& err) {
     m.sd[k].load.assign(m.sd[k].n_loc, 0.0);
   }
 
+  // non-homogeneous Dirichlet data: prescribed boundary coefficients
+  std::vector<double> aD;
+  const bool lift = m.prob.A_D != nullptr;
+  m.d_edges.clear();
+  m.d_vals.clear();
+  if (lift) {
+    if (int rc = dirichlet_projection(m, bs, aD, err)) return rc;
+    for (int64_t e = 0; e < M.n_edges; ++e)
+      if (m.dirichlet[e]) {
+        m.d_edges.push_back(e);
+        m.d_vals.push_back(aD[e]);
+      }
+  }
+
   int failed = 0;
-  std::vector<std::vector<std::pair<int32_t, double>>> patch_load(n_patches);
+  std::vector<std::vector<std::pair<int32_t, double>>> patch_load(n_patches), patch_lift(n_patches);
 #pragma omp parallel
   {
     std::vector<double> Kp;       // dense patch matrix (nu = 1)
@@ -379,6 +612,17 @@ int assemble_local_systems(Model& m, Error& err) {
       auto& PL = patch_load[q];
       for (int64_t a = 0; a < nloc; ++a)
         if (lid[a] >= 0) PL.emplace_back(lid[a], jp[a]);
+      if (lift) {
+        auto& LF = patch_lift[q];
+        for (int64_t a = 0; a < nloc; ++a) {
+          if (lid[a] < 0) continue;
+          const double* row = &Kp[size_t(a) * nloc];
+          double v = 0.0;
+          for (int64_t b = 0; b < nloc; ++b)
+            if (row[b] != 0.0 && m.dirichlet[gid[b]]) v += row[b] * aD[gid[b]];
+          if (v != 0.0) LF.emplace_back(lid[a], v);
+        }
+      }
 #pragma omp critical
       {
         auto& T = trips[k];
@@ -391,6 +635,7 @@ int assemble_local_systems(Model& m, Error& err) {
     return err.code;
   }
   m.patch_load = std::move(patch_load);
+  m.patch_lift = std::move(patch_lift);
   // ---- merge triplets into CSR per subdomain (deterministic order)
 #pragma omp parallel for schedule(dynamic, 1)
   for (int k = 0; k < m.n_sub; ++k) {
@@ -453,6 +698,8 @@ int set_coefficients(Model& m, const double* nu, const double* load_scale, Error
     Subdomain& s = m.sd[m.part[q]];
     const double c = m.load_scale[q];
     for (const auto& pr : m.patch_load[q]) s.load[pr.first] += c * pr.second;
+    if (!m.patch_lift.empty())
+      for (const auto& pr : m.patch_lift[q]) s.load[pr.first] -= m.nu[q] * pr.second;
   }
   return IETI_OK;
 }

@@ -67,6 +67,12 @@ int merge_models(std::vector<Model>& parts, Model& out, Error& err) {
     out.nu.insert(out.nu.end(), m.nu.begin(), m.nu.end());
     out.load_scale.insert(out.load_scale.end(), m.load_scale.begin(), m.load_scale.end());
     for (auto& pl : m.patch_load) out.patch_load.push_back(std::move(pl));
+    if (m.patch_lift.empty()) m.patch_lift.assign(m.part.size(), {});
+    for (auto& pl : m.patch_lift) out.patch_lift.push_back(std::move(pl));
+    for (size_t i = 0; i < m.d_edges.size(); ++i) {
+      out.d_edges.push_back(m.d_edges[i] + r.edge_base);
+      out.d_vals.push_back(m.d_vals[i]);
+    }
     acc.edge_base += r.n_edges;
     acc.mr_base += r.m_r;
     acc.gp_base += r.n_gp;

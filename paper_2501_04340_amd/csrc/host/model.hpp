@@ -79,6 +79,11 @@ struct Model {
   std::vector<double> load_scale;  // per patch, multiplies the patch's assembled load
   // per patch: unscaled load entries (local DOF in the patch's subdomain, value)
   std::vector<std::vector<std::pair<int32_t, double>>> patch_load;
+  // per patch: Dirichlet lifting (K a_D with nu = 1) at local DOFs; load -= nu * lift
+  std::vector<std::vector<std::pair<int32_t, double>>> patch_lift;
+  // prescribed boundary coefficients (non-homogeneous Dirichlet data), edge ids batch-global
+  std::vector<int64_t> d_edges;
+  std::vector<double> d_vals;
   Mesh mesh;
   int n_sub = 0;
   // per edge

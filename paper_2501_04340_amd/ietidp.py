@@ -14,7 +14,7 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libietidp.so")
 _lib = None
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 PREC_FP64, PREC_MIXED = 0, 1
 SCALE_IDENTITY, SCALE_STIFFNESS, SCALE_MULTIPLICITY = 0, 1, 2
 ERRORS = {
@@ -38,6 +38,8 @@ class Problem(C.Structure):
         ("nu_per_patch", C.POINTER(C.c_double)),
         ("J", FIELD_FN),
         ("J_user", C.c_void_p),
+        ("A_D", FIELD_FN),
+        ("A_D_user", C.c_void_p),
     ]
 
 
@@ -207,6 +209,15 @@ def _problem_struct(prob, keep):
 
     cb = FIELD_FN(_field)
     keep.extend([part, nu, cb])
+    dirichlet = getattr(prob, "dirichlet_A", None)
+    if dirichlet is not None:
+        def _dfield(xyz, npts, out, user):
+            X = np.ctypeslib.as_array(xyz, shape=(int(npts), 3))
+            O = np.ctypeslib.as_array(out, shape=(int(npts), 3))
+            O[:] = dirichlet(np.array(X))
+
+        dcb = FIELD_FN(_dfield)
+        keep.append(dcb)
     pr = Problem()
     pr.version = ABI_VERSION
     pr.geom_kind = int(prob.geom_kind)
@@ -223,6 +234,9 @@ def _problem_struct(prob, keep):
     pr.nu_per_patch = _ptr(nu, C.c_double)
     pr.J = cb
     pr.J_user = None
+    if dirichlet is not None:
+        pr.A_D = dcb
+    pr.A_D_user = None
     return pr
 
 

@@ -25,6 +25,7 @@ def _probs():
         configs.small_cube(P=(3, 2, 2), part=part, degree=2, n_el=2, source="trig",
                            nu=np.where(np.arange(12) % 3 == 0, 1e-3, 1.0)),
         configs.ring576(degree=2, n_el=1, n_theta=12),
+        configs.paper_cube(degree=2, n_el=2, n_sub=4),  # prescribed boundary values at an edge offset
         configs.cube8(degree=3, n_el=4),
         configs.cube64(degree=2, n_el=2),
     ]

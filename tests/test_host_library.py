@@ -35,6 +35,8 @@ def _problems():
                                       nu=np.where(np.arange(12) % 3 == 0, 1e-3, 1.0))),
         ("cube64_p1", configs.cube64(degree=1, n_el=2)),
         ("ring_coarse", configs.ring576(degree=2, n_el=1, n_theta=12)),
+        # non-homogeneous Dirichlet data: the loads carry the lifting -K a_D
+        ("paper_cube", configs.paper_cube(degree=2, n_el=2, n_sub=4)),
     ]
 
 
