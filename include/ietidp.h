@@ -283,6 +283,21 @@ int ieti_get_kernel_times(const ieti_handle* h, double* times);
  * ieti_factor. */
 int ieti_set_coefficients(ieti_handle* h, const double* nu_per_patch, const double* load_scale);
 
+/* Record the PCG step lengths alpha_i and direction updates beta_i of the
+ * first cap iterations of every problem (device memory of 16 cap bytes per
+ * problem, owned by the handle); cap = 0 stops recording and frees it.  The
+ * coefficients define the Lanczos tridiagonal of the preconditioned operator
+ * (Section 4 estimates the condition number from it): diagonal 1/alpha_i +
+ * beta_{i-1}/alpha_{i-1}, off-diagonal sqrt(beta_i)/alpha_i.  Captured
+ * launch graphs are rebuilt on the next solve. */
+int ieti_record_pcg(ieti_handle* h, int32_t cap);
+
+/* Coefficients of problem prob's last PCG run (in mixed precision: its last
+ * inner run): *n_out = min(iterations, cap), alpha[n_out] and beta[n_out]
+ * (either may be NULL; beta of an iteration that met the tolerance is 0).
+ * IETI_ERR_STATE if recording is off or no solve ran since it was enabled. */
+int ieti_get_pcg_coefficients(const ieti_handle* h, int32_t prob, double* alpha, double* beta, int32_t* n_out);
+
 /* Multipliers of the last solve [m_r]. */
 int ieti_get_lambda(const ieti_handle* h, double* lambda_out);
 

@@ -84,6 +84,8 @@ struct ieti_handle {
   DBuf<int64_t> pd, blk, g2l_off;
   DBuf<int32_t> cprob, task_prob[3];
   ieti::dev::Batch B;
+  DBuf<double> hist;               // PCG coefficient record (B.hist), 2 * B.hcap per problem
+  std::vector<int> hist_n;         // iterations of each problem's last PCG run
   std::vector<int64_t> pd_h, blk_h;
   DBuf<int> pdone, piters;                 // per problem: PCG finished (1 ok, 3 breakdown), iterations
   DBuf<double> dscale;                     // per interface slot: scaling of the preconditioner's jump operator
@@ -120,6 +122,7 @@ struct ieti_handle {
     I_sub.release();
     d_edges.release();
     d_vals.release();
+    hist.release();
     pd.release();
     blk.release();
     g2l_off.release();
@@ -774,6 +777,7 @@ int run_pcg(ieti_handle* h, const std::vector<double>& tol2, const std::vector<d
   HIP_TRY(hipMemcpyAsync(h->pdone.ptr, done0.data(), n_prob * sizeof(int), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(h->piters.ptr, 0, n_prob * sizeof(int), s));
   HIP_TRY(hipMemsetAsync(h->flags.ptr + 3, 0, sizeof(int), s));
+  if (h->B.hist) D::fill(h->B.hist, 2 * int64_t(h->B.hcap) * n_prob, 0.0, s);
   // z_0 = M r_0, p_0 = z_0, rz_0, partials of H^T p_0
   const int pf = fp32 ? 1 : 0;
   const int gt = gvariant(h, pf) / 4;
@@ -812,8 +816,10 @@ int run_pcg(ieti_handle* h, const std::vector<double>& tol2, const std::vector<d
   HIP_TRY(hipMemcpyAsync(h->pflags_h + n_prob, h->piters.ptr, n_prob * sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(sc.data(), h->scal.ptr, sc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  h->hist_n.assign(n_prob, 0);
   for (int p = 0; p < n_prob; ++p) {
     iters_out[p] = h->pflags_h[n_prob + p];
+    h->hist_n[p] = std::min(iters_out[p], h->B.hcap);
     rr_out[p] = sc[8 * p + 5];
     if (h->pflags_h[p] == 3)
       return fail(IETI_ERR_BREAKDOWN, "PCG breakdown (p^T F p <= 0) in problem " + std::to_string(p));
@@ -1339,6 +1345,41 @@ int ieti_set_profiling(ieti_handle* h, int32_t enable) {
   h->upd_tasks = 0.0;
   h->ev_marks.clear();
   h->ev_used = 0;
+  return IETI_OK;
+}
+
+int ieti_record_pcg(ieti_handle* h, int32_t cap) {
+  if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
+  if (cap < 0 || cap > (1 << 20)) return fail(IETI_ERR_INVALID_ARG, "cap must lie in [0, 2^20]");
+  drop_graphs(h);  // captured launches carry the record pointer
+  h->hist.release();
+  h->B.hist = nullptr;
+  h->B.hcap = 0;
+  h->hist_n.clear();
+  if (cap == 0) return IETI_OK;
+  const int n_prob = std::max<int>(1, int(h->model.probs.size()));
+  int rc = dalloc(h->hist, 2 * int64_t(cap) * n_prob);
+  if (rc) return rc;
+  h->B.hist = h->hist.ptr;
+  h->B.hcap = cap;
+  return IETI_OK;
+}
+
+int ieti_get_pcg_coefficients(const ieti_handle* h, int32_t prob, double* alpha, double* beta, int32_t* n_out) {
+  if (!h || !n_out) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  if (!h->B.hist) return fail(IETI_ERR_STATE, "PCG recording is off (ieti_record_pcg)");
+  if (prob < 0 || prob >= int(h->hist_n.size())) return fail(IETI_ERR_STATE, "no recorded solve for this problem");
+  const int n = h->hist_n[prob];
+  *n_out = n;
+  if (n == 0 || (!alpha && !beta)) return IETI_OK;
+  std::vector<double> v(2 * size_t(n));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(v.data(), h->B.hist + 2 * int64_t(prob) * h->B.hcap, v.size() * sizeof(double),
+                    hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) {
+    if (alpha) alpha[i] = v[2 * i];
+    if (beta) beta[i] = v[2 * i + 1];
+  }
   return IETI_OK;
 }
 

@@ -735,7 +735,7 @@ __global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* r
                                                const double* part_g, const double* part_rr, double* p, double* z,
                                                double* xg_p, double* part_t, double* scal, int par, int* done,
                                                int* iters, int init, const int64_t* pd, const int64_t* blk, int gt,
-                                               const double* ds) {
+                                               const double* ds, double* hist, int hcap) {
   const int64_t b = blockIdx.x, pid = blk[2 * b + 1];
   if (done[pid]) return;
   __shared__ double red[4];
@@ -748,8 +748,10 @@ __global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* r
   if (!init) {
     const double rr = reduce_partials_fast(part_rr + P[PD_B0], int(P[PD_B1] - P[PD_B0]), red);
     if (first && threadIdx.x == 0) {
-      iters[pid] += 1;
+      const int it = iters[pid];
+      iters[pid] = it + 1;
       sc[5] = rr;
+      if (hist && it < hcap) hist[(pid * hcap + it) * 2] = sc[2];
     }
     if (rr <= sc[4]) {
       if (first && threadIdx.x == 0) done[pid] = 1;
@@ -760,6 +762,7 @@ __global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* r
   if (first && threadIdx.x == 0) {
     sc[init ? 0 : 1 - par] = rz;
     sc[3] = beta;
+    if (hist && !init && iters[pid] - 1 < hcap) hist[(pid * hcap + iters[pid] - 1) * 2 + 1] = beta;
   }
   int64_t row0;
   const int64_t nrow = blk_rows(blk, pd, b, &row0);
@@ -1019,7 +1022,7 @@ void pcg_M(const double* w, const int64_t* row_src, const double* H, const doubl
            const Batch& B, int gt, hipStream_t s, const double* ds) {
   if (B.n_blk <= 0) return;
   hipLaunchKernelGGL(k_pcg_M, dim3(B.n_blk), dim3(256), 0, s, w, row_src, H, part_g, part_rr, p, z, xg_p, part_t,
-                     scal, par, done, iters, init, B.pd, B.blk, gt, ds);
+                     scal, par, done, iters, init, B.pd, B.blk, gt, ds, B.hist, B.hcap);
 }
 void gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out, hipStream_t s) {
   if (n <= 0) return;

@@ -48,6 +48,9 @@ struct Batch {
   int n_blk = 0;
   int64_t n_gp_total = 0;
   int64_t max_gp = 0;
+  // optional PCG coefficient record: hist[(p * hcap + i) * 2 + {0, 1}] = (alpha_i, beta_i)
+  double* hist = nullptr;
+  int hcap = 0;
 };
 
 // ---- coarse problem (per-problem dense blocks)

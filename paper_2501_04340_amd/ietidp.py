@@ -116,7 +116,7 @@ EXPORTS = [
     "ieti_last_error", "ieti_set_coefficients", "ieti_set_warm_start", "ieti_nn_create", "ieti_nn_num_params",
     "ieti_nn_set_params", "ieti_nn_get_params", "ieti_nn_set_data", "ieti_nn_loss_grad", "ieti_nn_train",
     "ieti_nn_predict", "ieti_nn_destroy", "ieti_get_gemv_tuning", "ieti_assemble_batch", "ieti_get_batch_info",
-    "ieti_batch_of",
+    "ieti_batch_of", "ieti_record_pcg", "ieti_get_pcg_coefficients",
 ]
 
 
@@ -165,6 +165,8 @@ def load_library():
     lib.ieti_last_error.restype = C.c_char_p
     lib.ieti_assemble_batch.argtypes = [P(Problem), C.c_int32, P(C.c_void_p)]
     lib.ieti_batch_of.argtypes = [P(C.c_void_p), C.c_int32, P(C.c_void_p)]
+    lib.ieti_record_pcg.argtypes = [C.c_void_p, C.c_int32]
+    lib.ieti_get_pcg_coefficients.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double), P(C.c_int32)]
     lib.ieti_get_batch_info.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_double)]
     lib.ieti_get_gemv_tuning.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_float)]
     lib.ieti_set_coefficients.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
@@ -461,6 +463,35 @@ class Solver:
         lam = np.zeros(self.m_r)
         _check(self.lib, self.lib.ieti_get_lambda(self.h, _ptr(lam, C.c_double)))
         return lam
+
+    def record_pcg(self, cap):
+        """Record alpha/beta of the first ``cap`` PCG iterations (0 = off)."""
+        _check(self.lib, self.lib.ieti_record_pcg(self.h, int(cap)))
+
+    def pcg_coefficients(self, prob=0):
+        """(alpha, beta) of problem ``prob``'s last PCG run."""
+        n = C.c_int32()
+        _check(self.lib, self.lib.ieti_get_pcg_coefficients(self.h, int(prob), None, None, C.byref(n)))
+        a, b = np.zeros(n.value), np.zeros(n.value)
+        if n.value:
+            _check(self.lib, self.lib.ieti_get_pcg_coefficients(self.h, int(prob), _ptr(a, C.c_double),
+                                                                _ptr(b, C.c_double), C.byref(n)))
+        return a, b
+
+    def condition(self, prob=0):
+        """(lambda_min, lambda_max) of the Lanczos tridiagonal of the recorded
+        PCG run: extreme eigenvalues of the preconditioned interface operator."""
+        a, b = self.pcg_coefficients(prob)
+        k = len(a)
+        if k == 0:
+            return 1.0, 1.0
+        T = np.diag(1.0 / a)
+        T[np.arange(1, k), np.arange(1, k)] += b[:k - 1] / a[:k - 1]
+        off = np.sqrt(b[:k - 1]) / a[:k - 1]
+        T[np.arange(k - 1), np.arange(1, k)] = off
+        T[np.arange(1, k), np.arange(k - 1)] = off
+        ev = np.linalg.eigvalsh(T)
+        return float(ev.min()), float(ev.max())
 
 
 class NN:

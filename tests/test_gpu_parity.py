@@ -19,6 +19,7 @@ factorisation of matrices with condition numbers up to ~1e5 in float64).
 import numpy as np
 import pytest
 
+from oracle.ietidp import lanczos_condition
 from oracle.post import b_error
 from oracle.run import OracleRun
 from workloads import configs
@@ -121,6 +122,30 @@ def test_dirichlet_data_and_discretisation_error(runs):
     print(f"[gpu-parity] paper_cube: rel B error vs closed form gpu={e_gpu:.6e} oracle={e_ora:.6e}")
     assert 0.0 < e_ora < 0.2
     assert abs(e_gpu - e_ora) <= 1e-8 * e_ora
+
+
+@pytest.mark.parametrize("name", ["cube8", "uneven_nu", "paper_cube"])
+def test_recorded_pcg_coefficients_and_condition(runs, name):
+    """The recorded alpha/beta equal the oracle PCG's, so the Lanczos
+    condition estimates (Section 4) agree; D_s = I puts the smallest
+    eigenvalue at >= 4 (every multiplier joins two subdomains)."""
+    prob, S, O = _get(runs, name)
+    S.record_pcg(4000)
+    try:
+        _, st = S.solve(rtol=1e-10, maxit=2000)
+        a, b = S.pcg_coefficients()
+        lo, hi = S.condition()
+    finally:
+        S.record_pcg(0)
+    _, info = O.ieti.pcg(rtol=1e-10, maxit=2000)
+    assert len(a) == st["iters"] and abs(len(a) - info["iters"]) <= 1
+    k = min(8, len(a), len(info["alpha"]))
+    np.testing.assert_allclose(a[:k], info["alpha"][:k], rtol=1e-8)
+    np.testing.assert_allclose(b[:k - 1], info["beta"][:k - 1], rtol=1e-8)
+    lo_o, hi_o = lanczos_condition(info)
+    print(f"[gpu-parity] {name}: kappa gpu={hi / lo:.6f} oracle={hi_o / lo_o:.6f} lambda_min={lo:.4f}")
+    assert abs(hi / lo - hi_o / lo_o) <= 1e-4 * (hi_o / lo_o)
+    assert lo >= 4.0 * (1 - 1e-6)
 
 
 def test_warm_start_from_solution_takes_no_iterations(runs):
