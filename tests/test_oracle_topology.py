@@ -142,3 +142,49 @@ def test_dirichlet_tree_consistency_on_workloads():
     T = build_topology(Space(prob))
     assert T.tree_consistent
     assert T.n_gp > 0
+
+
+def _subdomain_edges(space, T):
+    """Maximal runs of consecutive weight-2 control edges on one patch-line
+    with one subdomain set: the subdomain edges (cross-edges) of Section 3."""
+    groups = {}
+    for e in np.flatnonzero(T.weight == 2):
+        d = int(space.edge_dir[e])
+        X = space.edge_coord[e]
+        u, v = [c for c in range(3) if c != d]
+        groups.setdefault((d, int(X[u]), int(X[v]), tuple(T.subsets[e])), []).append((int(X[d]), int(e)))
+    runs = []
+    for lst in groups.values():
+        lst.sort()
+        cur = [lst[0][1]]
+        for a, b in zip(lst[:-1], lst[1:]):
+            if b[0] == a[0] + 1:
+                cur.append(b[1])
+            else:
+                runs.append(cur)
+                cur = [b[1]]
+        runs.append(cur)
+    return runs
+
+
+@pytest.mark.parametrize("name,prob", [
+    ("cube8", configs.cube8()),
+    ("cube64_p2", configs.cube64(degree=2, n_el=2)),
+    ("paper_cube6", configs.paper_cube(degree=2, n_el=2, n_sub=6)),
+    ("paper_cube12", configs.paper_cube(degree=1, n_el=3, n_sub=12)),
+    ("stream5", configs.stream_problem(5)),
+])
+def test_edge_average_primal_coincides_with_cotree_primal(name, prob):
+    """Whole-edge tangential averages as primal constraints (the alternative
+    to Section 3's single cotree DOFs) impose the same continuity under the
+    tree gauge: every subdomain edge carries at most one cotree edge, the
+    others are tree edges fixed to zero in every subdomain, so its average
+    is that DOF divided by the edge count (or identically zero)."""
+    space = Space(prob)
+    T = build_topology(space)
+    runs = _subdomain_edges(space, T)
+    counts = [int(np.count_nonzero(T.primal[r])) for r in runs]
+    assert max(counts) <= 1
+    assert sum(counts) == T.n_gp
+    for r in runs:
+        assert np.all(T.tree[r] | T.primal[r])
