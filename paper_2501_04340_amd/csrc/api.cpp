@@ -41,17 +41,17 @@ struct ieti_handle {
   std::vector<int64_t> gemv_task_h[3];  // GEMV task lists for 8, 16 and 32 rows per workgroup
   // device buffers
   DBuf<double> pool, inv, scatter_val, S, Sinv, Phi, SPi, Spi_glob, G, H, Ht, I_sign, b_aug0, y;
-  DBuf<int64_t> scatter_dst, potrf, trsm, upd, upd_pair, copyS, xsinv, xphi, xspi, fdiag, ffull, ffull_pair, fr, fr_pair;
+  DBuf<int64_t> scatter_dst, potrf, trsm, upd, upd_pair, copyS, xsinv, xphi, xspi, fdiag, ffull, ffull_pair, rec_task, rec_pair;
   DBuf<int64_t> bdiag, bupd, bupd_pair;
-  DBuf<int64_t> spi_ptr, spi_src, row_src, I_aug, A_aug, slot_phi_row, dsrc_ptr, dsrc_idx, krp_ptr, krp_pos;
+  DBuf<int64_t> spi_ptr, spi_src, row_src, I_aug, A_aug, slot_phi_row, dsrc_ptr, dsrc_idx, recP_pos, recP_glob;
   DBuf<int64_t> out_src, out_edge, primal_edges, d_edges;  // d_edges: prescribed boundary coefficients
   DBuf<double> d_vals;
   DBuf<int64_t> gemv_tasks[3];
   int ngemv_r[3] = {0, 0, 0};
   int gvar[2] = {-1, -1};                              // GEMV launch shape for FP64 / FP32 blocks (-1 = untuned)
   float gtime[2][ieti::dev::GEMV_VARIANTS] = {};      // autotuner: ms per launch of each shape
-  DBuf<int32_t> I_row, I_sub, glob2loc, krp_col;
-  DBuf<double> krp_val;
+  DBuf<int32_t> I_row, I_sub, glob2loc;
+  DBuf<double> yj;  // L_rr^{-1} j_r of the right-hand side's forward solve (augmented layout)
   DBuf<double> lam, r, z, p, q, v, b, e, dtil, w, t, pglob, part, scal, aout, tmp;
   DBuf<double> xgp, xgr, part_g, part_t;  // gathered B^T p and B^T r, GEMV and coarse partials
   DBuf<double> lam_acc, rtrue;            // outer multipliers and FP64 residual (mixed precision)
@@ -110,12 +110,12 @@ struct ieti_handle {
 
   ~ieti_handle() {
     DBuf<double>* ds[] = {&pool, &inv, &scatter_val, &S, &Sinv, &Phi, &SPi, &Spi_glob, &G, &H, &Ht, &I_sign, &b_aug0, &y,
-                          &krp_val, &lam, &r, &z, &p, &q, &v, &b, &e, &dtil, &w, &t, &pglob, &part, &scal, &aout,
+                          &yj, &lam, &r, &z, &p, &q, &v, &b, &e, &dtil, &w, &t, &pglob, &part, &scal, &aout,
                           &tmp, &xgp, &xgr, &part_g, &part_t, &lam_acc, &rtrue};
     for (auto* d : ds) d->release();
     DBuf<int64_t>* is[] = {&scatter_dst, &potrf, &trsm, &upd, &upd_pair, &copyS, &xsinv, &xphi, &xspi, &fdiag,
-                           &ffull, &ffull_pair, &fr, &fr_pair, &bdiag, &bupd, &bupd_pair, &spi_ptr, &spi_src, &row_src, &I_aug, &A_aug, &slot_phi_row, &dsrc_ptr,
-                           &dsrc_idx, &krp_ptr, &krp_pos, &out_src, &out_edge, &primal_edges,
+                           &ffull, &ffull_pair, &rec_task, &rec_pair, &bdiag, &bupd, &bupd_pair, &spi_ptr, &spi_src, &row_src, &I_aug, &A_aug, &slot_phi_row, &dsrc_ptr,
+                           &dsrc_idx, &recP_pos, &recP_glob, &out_src, &out_edge, &primal_edges,
                            &gemv_tasks[0], &gemv_tasks[1], &gemv_tasks[2]};
     for (auto* d : is) d->release();
     I_row.release();
@@ -133,7 +133,6 @@ struct ieti_handle {
     dscale.release();
     if (pflags_h) (void)hipHostFree(pflags_h);
     glob2loc.release();
-    krp_col.release();
     flags.release();
     if (flags_h) (void)hipHostFree(flags_h);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
@@ -212,7 +211,7 @@ int upload(ieti_handle* h) {
   UP(upd, P.upd_task);
   UP(upd_pair, P.upd_pair);
   UP(ffull_pair, P.ffull_pair);
-  UP(fr_pair, P.fr_pair);
+  UP(rec_pair, P.rec_pair);
   UP(bupd_pair, P.bupd_pair);
   UP(copyS, P.copy_task);
   UP(xsinv, P.xsinv_task);
@@ -220,7 +219,7 @@ int upload(ieti_handle* h) {
   UP(xspi, P.xspi_task);
   UP(fdiag, P.fdiag_task);
   UP(ffull, P.ffull_task);
-  UP(fr, P.fr_task);
+  UP(rec_task, P.rec_task);
   UP(bdiag, P.bdiag_task);
   UP(bupd, P.bupd_task);
   UP(spi_ptr, P.spi_ptr);
@@ -235,10 +234,9 @@ int upload(ieti_handle* h) {
   UP(I_sub, P.I_sub);
   UP(glob2loc, P.glob2loc);
   UP(g2l_off, P.g2l_off);
-  UP(krp_ptr, P.krp_ptr);
-  UP(krp_pos, P.krp_pos);
-  UP(krp_col, P.krp_col);
-  UP(krp_val, P.krp_val);
+  UP(recP_pos, P.recP_pos);
+  UP(recP_glob, P.recP_glob);
+  if ((rc = dalloc(h->yj, P.r_total))) return rc;
   UP(out_src, P.out_src);
   UP(out_edge, P.out_edge);
   UP(primal_edges, M.primal_edges);
@@ -625,18 +623,14 @@ int capture_graph(ieti_handle* h, bool fp32) {
 }
 
 // Forward solve with the factor over all augmented rows (full) or r rows only.
-void forward_solve(ieti_handle* h, bool full) {
+void forward_solve(ieti_handle* h) {
   namespace D = ieti::dev;
   const auto& P = h->plan;
   for (int64_t j = 0; j < P.n_steps; ++j) {
     D::trsv_diag(h->inv.ptr, h->fdiag.ptr + 2 * P.fdiag_ptr[j], P.fdiag_ptr[j + 1] - P.fdiag_ptr[j], h->y.ptr, false,
                  h->stream);
-    if (full)
-      D::trsv_update(h->pool.ptr, h->ffull.ptr + 3 * P.ffull_ptr[j], h->ffull_pair.ptr,
-                     P.ffull_ptr[j + 1] - P.ffull_ptr[j], h->y.ptr, false, h->stream);
-    else
-      D::trsv_update(h->pool.ptr, h->fr.ptr + 3 * P.fr_ptr[j], h->fr_pair.ptr, P.fr_ptr[j + 1] - P.fr_ptr[j],
-                     h->y.ptr, false, h->stream);
+    D::trsv_update(h->pool.ptr, h->ffull.ptr + 3 * P.ffull_ptr[j], h->ffull_pair.ptr,
+                   P.ffull_ptr[j + 1] - P.ffull_ptr[j], h->y.ptr, false, h->stream);
   }
 }
 
@@ -658,7 +652,8 @@ int compute_rhs(ieti_handle* h) {
   const auto& M = h->model;
   hipStream_t s = h->stream;
   D::vec_copy(h->b_aug0.ptr, h->y.ptr, P.r_total, s);
-  forward_solve(h, true);
+  forward_solve(h);
+  D::vec_copy(h->y.ptr, h->yj.ptr, P.r_total, s);  // kept for the recovery
   D::rhs_assemble(h->y.ptr, h->A_aug.ptr, h->row_src.ptr, M.m_r, h->e.ptr, s);
   if (M.n_gp > 0) {
     D::sum_sources(h->y.ptr, h->dsrc_ptr.ptr, h->dsrc_idx.ptr, M.n_gp, h->dtil.ptr, s);
@@ -921,11 +916,13 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
     D::axpby(h->w.ptr, h->t.ptr, h->dtil.ptr, 1.0, 1.0, M.n_gp, s);
     D::tri_small(h->Spi_glob.ptr, h->dtil.ptr, h->pglob.ptr, true, h->B, s);
   }
-  D::vec_copy(h->b_aug0.ptr, h->y.ptr, P.r_total, s);
-  D::recovery_rhs(h->y.ptr, h->krp_ptr.ptr, h->krp_pos.ptr, h->krp_col.ptr, h->krp_val.ptr,
-                  int64_t(P.krp_pos.size()), h->pglob.ptr, h->I_aug.ptr, h->I_row.ptr, h->I_sign.ptr, P.I_total,
-                  h->lam.ptr, s);
-  forward_solve(h, false);
+  // y = L_rr^{-1} (j_r - K_rp a_p - B_r^T lambda) = y_j - L_pr^T a_p - L_Er^T u (no forward sweep), then
+  // the backward sweep
+  D::vec_copy(h->yj.ptr, h->y.ptr, P.r_total, s);
+  D::recovery_sources(h->y.ptr, h->recP_pos.ptr, h->recP_glob.ptr, int64_t(P.recP_pos.size()),
+                      M.n_gp > 0 ? h->pglob.ptr : nullptr, h->A_aug.ptr, h->I_row.ptr, h->I_sign.ptr, P.I_total,
+                      h->lam.ptr, s);
+  D::trsv_update(h->pool.ptr, h->rec_task.ptr, h->rec_pair.ptr, int64_t(P.rec_task.size() / 3), h->y.ptr, true, s);
   backward_solve(h);
   double* aout = a_dev ? a_dev : h->aout.ptr;
   D::fill(aout, M.n_edges_total, 0.0, s);
@@ -1417,8 +1414,6 @@ int ieti_set_coefficients(ieti_handle* h, const double* nu_per_patch, const doub
       const auto& P = h->plan;
       HIP_TRY(hipMemcpy(h->scatter_val.ptr, P.scatter_val.data(), P.scatter_val.size() * sizeof(double),
                         hipMemcpyHostToDevice));
-      if (!P.krp_val.empty())
-        HIP_TRY(hipMemcpy(h->krp_val.ptr, P.krp_val.data(), P.krp_val.size() * sizeof(double), hipMemcpyHostToDevice));
       HIP_TRY(hipMemcpy(h->b_aug0.ptr, P.b_aug0.data(), P.b_aug0.size() * sizeof(double), hipMemcpyHostToDevice));
     }
   }

@@ -813,21 +813,21 @@ __global__ void k_rhs_assemble(const double* y, const int64_t* A_aug, const int6
   e[row] = -(y[A_aug[row_src[2 * row]]] - y[A_aug[row_src[2 * row + 1]]]);
 }
 
-__global__ void k_recovery_rhs_krp(double* y, const int64_t* krp_ptr, const int64_t* krp_pos, const int32_t* krp_col,
-                                   const double* krp_val, int64_t nrows, const double* pglob) {
+// Sources of the recovery's transposed update: the local primal values
+// a_p = C_k p at every padded primal position (0 on padding) and the jump
+// u = (B_r^T lambda)_I at every padded E_I position (0 on padding).
+__global__ void k_recovery_sources(double* y, const int64_t* p_pos, const int64_t* p_glob, int64_t np,
+                                   const double* pglob, const int64_t* A_aug, const int32_t* I_row,
+                                   const double* I_sign, int64_t nslots, const double* lam) {
   const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= nrows) return;
-  double s = 0.0;
-  for (int64_t q = krp_ptr[i]; q < krp_ptr[i + 1]; ++q) s += krp_val[q] * pglob[krp_col[q]];
-  y[krp_pos[i]] -= s;
-}
-
-__global__ void k_recovery_rhs_lam(double* y, const int64_t* I_aug, const int32_t* I_row, const double* I_sign,
-                                   int64_t nslots, const double* lam) {
-  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= nslots) return;
-  const int32_t row = I_row[i];
-  if (row >= 0) y[I_aug[i]] -= I_sign[i] * lam[row];
+  if (i < np) {
+    const int64_t g = p_glob[i];
+    y[p_pos[i]] = g >= 0 ? pglob[g] : 0.0;
+  } else if (i < np + nslots) {
+    const int64_t t = i - np;
+    const int32_t row = I_row[t];
+    y[A_aug[t]] = row >= 0 ? I_sign[t] * lam[row] : 0.0;
+  }
 }
 
 __global__ void k_write_output(const double* y, const int64_t* src, const int64_t* edge, int64_t n, double* a) {
@@ -1032,15 +1032,13 @@ void rhs_assemble(const double* y, const int64_t* A_aug, const int64_t* row_src,
   if (m_r <= 0) return;
   hipLaunchKernelGGL(k_rhs_assemble, dim3((m_r + 255) / 256), dim3(256), 0, s, y, A_aug, row_src, m_r, e);
 }
-void recovery_rhs(double* y, const int64_t* krp_ptr, const int64_t* krp_pos, const int32_t* krp_col,
-                  const double* krp_val, int64_t nrows, const double* pglob, const int64_t* I_aug,
-                  const int32_t* I_row, const double* I_sign, int64_t nslots, const double* lam, hipStream_t s) {
-  if (nrows > 0)
-    hipLaunchKernelGGL(k_recovery_rhs_krp, dim3((nrows + 255) / 256), dim3(256), 0, s, y, krp_ptr, krp_pos, krp_col,
-                       krp_val, nrows, pglob);
-  if (nslots > 0)
-    hipLaunchKernelGGL(k_recovery_rhs_lam, dim3((nslots + 255) / 256), dim3(256), 0, s, y, I_aug, I_row, I_sign,
-                       nslots, lam);
+void recovery_sources(double* y, const int64_t* p_pos, const int64_t* p_glob, int64_t np, const double* pglob,
+                      const int64_t* A_aug, const int32_t* I_row, const double* I_sign, int64_t nslots,
+                      const double* lam, hipStream_t s) {
+  const int64_t n = np + nslots;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_recovery_sources, dim3(grid_for(n, 256)), dim3(256), 0, s, y, p_pos, p_glob, np, pglob, A_aug,
+                     I_row, I_sign, nslots, lam);
 }
 void write_output(const double* y, const int64_t* src, const int64_t* edge, int64_t n, const double* pglob,
                   const int64_t* primal_edges, int64_t n_gp, double* a, hipStream_t s) {

@@ -108,9 +108,10 @@ void pcg_M(const double* w, const int64_t* row_src, const double* H, const doubl
 // ---- recovery / rhs helpers
 void gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out, hipStream_t s);
 void rhs_assemble(const double* y, const int64_t* A_aug, const int64_t* row_src, int64_t m_r, double* e, hipStream_t s);
-void recovery_rhs(double* y, const int64_t* krp_ptr, const int64_t* krp_pos, const int32_t* krp_col,
-                  const double* krp_val, int64_t nrows, const double* pglob, const int64_t* I_aug,
-                  const int32_t* I_row, const double* I_sign, int64_t nslots, const double* lam, hipStream_t s);
+// y[p_pos[i]] = pglob[p_glob[i]] (0 where p_glob < 0), y[A_aug[t]] = I_sign[t] lam[I_row[t]] (0 where I_row < 0)
+void recovery_sources(double* y, const int64_t* p_pos, const int64_t* p_glob, int64_t np, const double* pglob,
+                      const int64_t* A_aug, const int32_t* I_row, const double* I_sign, int64_t nslots,
+                      const double* lam, hipStream_t s);
 void write_output(const double* y, const int64_t* src, const int64_t* edge, int64_t n, const double* pglob,
                   const int64_t* primal_edges, int64_t n_gp, double* a, hipStream_t s);
 // b[row] = e[row] - sum_c H_p[row][c] w_p[c]

@@ -353,7 +353,6 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
   // Backward: levels in reverse, x_j = L_jj^{-T} y_j, then y_k -= sum_j L_jk^T x_j.
   plan.fdiag_ptr.assign(1, 0);
   plan.ffull_ptr.assign(1, 0);
-  plan.fr_ptr.assign(1, 0);
   auto emit_targets = [&](std::vector<std::pair<int64_t, std::pair<int64_t, int64_t>>>& c, std::vector<int64_t>& task,
                           std::vector<int64_t>& pair) {
     std::stable_sort(c.begin(), c.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
@@ -373,22 +372,19 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
     for (int k = 0; k < S; ++k) {
       const SubPlan& sp = plan.sub[k];
       const int64_t nt = sp.nt;
-      std::vector<std::pair<int64_t, std::pair<int64_t, int64_t>>> full, ronly;  // (vec_i, (tile, vec_j))
+      std::vector<std::pair<int64_t, std::pair<int64_t, int64_t>>> full;  // (vec_i, (tile, vec_j))
       for (int64_t j : cols[k][lv]) {
         plan.fdiag_task.insert(plan.fdiag_task.end(), {inv_off[k][j], sp.r_off + j * T});
         for (int64_t i = j + 1; i < nt; ++i) {
           const int64_t o = sp.tile_off[i * nt + j];
           if (o < 0) continue;
           full.push_back({sp.r_off + i * T, {o, sp.r_off + j * T}});
-          if (i < sp.ntr) ronly.push_back({sp.r_off + i * T, {o, sp.r_off + j * T}});
         }
       }
       emit_targets(full, plan.ffull_task, plan.ffull_pair);
-      emit_targets(ronly, plan.fr_task, plan.fr_pair);
     }
     plan.fdiag_ptr.push_back(int64_t(plan.fdiag_task.size() / 2));
     plan.ffull_ptr.push_back(int64_t(plan.ffull_task.size() / 3));
-    plan.fr_ptr.push_back(int64_t(plan.fr_task.size() / 3));
   }
   plan.bdiag_ptr.assign(1, 0);
   plan.bupd_ptr.assign(1, 0);
@@ -409,6 +405,29 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
     }
     plan.bdiag_ptr.push_back(int64_t(plan.bdiag_task.size() / 2));
     plan.bupd_ptr.push_back(int64_t(plan.bupd_task.size() / 3));
+  }
+  // Recovery (Eq. localProb) without a forward sweep: the factor's primal rows
+  // are L_pr = K_pr L_rr^{-T} and its E_I rows L_Er = E_I^T L_rr^{-T}, so
+  // L_rr^{-1} (j_r - K_rp a_p - E_I u) = y_j - L_pr^T a_p - L_Er^T u with
+  // y_j = L_rr^{-1} j_r from the right-hand side's forward solve: one
+  // transposed update per r column tile over the primal and E_I row tiles.
+  for (int k = 0; k < S; ++k) {
+    const SubPlan& sp = plan.sub[k];
+    const int64_t nt = sp.nt;
+    for (int64_t c = 0; c < sp.ntr; ++c) {
+      const int64_t p0 = int64_t(plan.rec_pair.size() / 2);
+      for (int64_t i = sp.ntr; i < nt; ++i) {
+        const int64_t o = sp.tile_off[i * nt + c];
+        if (o >= 0) plan.rec_pair.insert(plan.rec_pair.end(), {o, sp.r_off + i * T});
+      }
+      const int64_t np = int64_t(plan.rec_pair.size() / 2) - p0;
+      if (np > 0) plan.rec_task.insert(plan.rec_task.end(), {sp.r_off + c * T, p0, np});
+    }
+    const Subdomain& s = m.sd[k];
+    for (int64_t t = 0; t < sp.nPp; ++t) {
+      plan.recP_pos.push_back(sp.r_off + sp.nVp + sp.nIp + t);
+      plan.recP_glob.push_back(t < sp.nP ? s.p_global[t] : -1);
+    }
   }
   // ---------------------------------------------------------------- interface and primal maps
   plan.I_row.assign(I_total, -1);
@@ -466,32 +485,16 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
       plan.spi_ptr.push_back(int64_t(plan.spi_src.size()));
     }
   }
-  // recovery rows of K_rp and the output map
-  plan.krp_ptr.assign(1, 0);
-  for (int64_t k = 0, voff = 0; k < S; ++k) {
+  // output map: augmented index and edge id of every owned r DOF
+  for (int64_t k = 0; k < S; ++k) {
     const Subdomain& s = m.sd[k];
     const SubPlan& sp = plan.sub[k];
     const int64_t nr = int64_t(s.r_edges.size());
-    for (int64_t r = 0; r < nr; ++r) {
-      bool any = false;
-      for (int64_t q = s.indptr[r]; q < s.indptr[r + 1]; ++q) {
-        const int32_t c = s.indices[q];
-        if (c >= nr) {
-          plan.krp_col.push_back(s.p_global[c - nr]);
-          plan.krp_src.push_back(voff + q);
-          any = true;
-        }
-      }
-      if (any) {
-        plan.krp_pos.push_back(sp.r_off + sp.pos_of_local[r]);
-        plan.krp_ptr.push_back(int64_t(plan.krp_col.size()));
-      }
+    for (int64_t r = 0; r < nr; ++r)
       if (s.owner[r]) {
         plan.out_src.push_back(sp.r_off + sp.pos_of_local[r]);
         plan.out_edge.push_back(s.r_edges[r] + m.probs[m.sub_prob[k]].edge_base);
       }
-    }
-    voff += s.indptr[s.n_loc];
   }
   refill_values(m, plan);
   for (const auto& sp : plan.sub) {
@@ -517,8 +520,6 @@ void refill_values(const Model& m, Plan& plan) {
   plan.scatter_val.resize(plan.scatter_src.size());
   for (size_t i = 0; i < plan.scatter_src.size(); ++i)
     plan.scatter_val[i] = plan.scatter_src[i] < 0 ? 1.0 : value(plan.scatter_src[i]);
-  plan.krp_val.resize(plan.krp_src.size());
-  for (size_t i = 0; i < plan.krp_src.size(); ++i) plan.krp_val[i] = value(plan.krp_src[i]);
   plan.b_aug0.assign(plan.r_total, 0.0);
   for (size_t k = 0; k < m.sd.size(); ++k) {
     const Subdomain& s = m.sd[k];

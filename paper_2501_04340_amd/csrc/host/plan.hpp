@@ -67,7 +67,7 @@ struct Plan {
   std::vector<int64_t> xsinv_task, xphi_task, xspi_task;
   // triangular solves with the factor, per level: diag [off of L_jj^{-1}, vec_j],
   // update targets [vec_dst, first pair, pair count] with pairs [off_tile, vec_src]
-  std::vector<int64_t> fdiag_ptr, fdiag_task, ffull_ptr, ffull_task, ffull_pair, fr_ptr, fr_task, fr_pair;
+  std::vector<int64_t> fdiag_ptr, fdiag_task, ffull_ptr, ffull_task, ffull_pair;
   std::vector<int64_t> bdiag_ptr, bdiag_task, bupd_ptr, bupd_task, bupd_pair;
   // interface gather/scatter: per padded interface slot, multiplier row (-1 = pad) and sign
   std::vector<int32_t> I_row;
@@ -86,11 +86,11 @@ struct Plan {
   std::vector<int32_t> I_sub;          // per padded interface slot: subdomain
   // coarse matrix assembly: CSR over the entries of the per-problem blocks, sources in the SPi array
   std::vector<int64_t> spi_ptr, spi_src;
-  // recovery: K_rp rows (augmented index), entries (global primal, value)
-  std::vector<int64_t> krp_ptr, krp_pos;
-  std::vector<int32_t> krp_col;
-  std::vector<double> krp_val;
-  std::vector<int64_t> krp_src;        // per entry: index into the concatenated CSR values
+  // recovery without a forward sweep (one transposed update launch): target r column tile c,
+  // pairs [tile (i, c) of a primal or E_I row tile i, vec of row tile i]
+  std::vector<int64_t> rec_task, rec_pair;
+  // every padded primal position of the augmented vectors and its global primal index (-1: padding)
+  std::vector<int64_t> recP_pos, recP_glob;
   // output: augmented index and edge id of every owned r DOF
   std::vector<int64_t> out_src, out_edge;
   // initial augmented right-hand side [j_r; j_p; 0]
