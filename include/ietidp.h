@@ -108,7 +108,7 @@ typedef struct {
   int32_t tile;        /* factor tile size: 0 = default (64) */
   int32_t ordering;    /* 0 = nested dissection of r_V (default), 1 = natural order */
   int32_t gemv_variant; /* 0 = autotune the interface GEMV launch shape on the first factorisation
-                           of the handle (kept afterwards); 1..12 = use shape gemv_variant - 1 */
+                           of the handle (kept afterwards); 1..13 = use shape gemv_variant - 1 */
   int32_t scaling;     /* IETI_SCALE_* of the preconditioner (0 = D_s = I as in the paper) */
   int32_t reserved;
   void* hip_stream;    /* hipStream_t to run on; NULL = the library's own stream */
@@ -260,15 +260,20 @@ int ieti_set_profiling(ieti_handle* h, int32_t enable);
 
 /* Launch shape of the interface GEMV chosen for FP64 (variant[0]) and FP32
  * (variant[1]) blocks, -1 if not chosen yet, and the autotuner's average
- * launch time in ms of each of the 12 shapes (timed alternating the
- * operator and preconditioner blocks), ms[12 * precision + shape]
- * (0 if not timed).  Shape s: 4 waves of rows_per_wave = {2,4,8}[s / 4]
- * rows, (s / 2) % 2 + 1 16-byte vectors in flight per lane and row,
- * non-temporal loads if s is odd.  Either argument may be NULL. */
+ * time in ms of one application with each of the 13 shapes (timed
+ * alternating the operator and preconditioner blocks), ms[13 * precision +
+ * shape] (0 if not timed).  Shapes 0..11 stream whole rows of the dense
+ * blocks: 4 waves of rows_per_wave = {2,4,8}[s / 4] rows, (s / 2) % 2 + 1
+ * 16-byte vectors in flight per lane and row, non-temporal loads if s is
+ * odd; they give bitwise identical results.  Shape 12 uses the symmetry of
+ * the blocks: it reads every lower 64x64 tile once (half the bytes) and
+ * sums the transposed contributions through partials, in another (fixed)
+ * order.  Either argument may be NULL. */
 int ieti_get_gemv_tuning(const ieti_handle* h, int32_t* variant, float* ms);
 
 /* times[0..5] = {GEMV launches, GEMV total ms, update launches, update total
- * ms, update tasks executed, interface-block bytes read per GEMV launch}. */
+ * ms, update tasks executed, FP64 interface-block bytes read per GEMV
+ * application with the chosen FP64 shape}. */
 int ieti_get_kernel_times(const ieti_handle* h, double* times);
 
 /* Change the reluctivity of every patch and scale every patch's load

@@ -49,7 +49,13 @@ struct ieti_handle {
   DBuf<int64_t> gemv_tasks[3];
   int ngemv_r[3] = {0, 0, 0};
   int gvar[2] = {-1, -1};                              // GEMV launch shape for FP64 / FP32 blocks (-1 = untuned)
-  float gtime[2][ieti::dev::GEMV_VARIANTS] = {};      // autotuner: ms per launch of each shape
+  float gtime[2][ieti::dev::GEMV_SHAPES] = {};        // autotuner: ms per launch of each shape
+  // symmetric GEMV: tasks over lower tiles, output blocks, partial lists and buffer
+  DBuf<int64_t> sym_task, sym_blk, sym_csr;
+  DBuf<int32_t> sym_tprob, sym_bprob;
+  DBuf<double> sym_part;
+  ieti::dev::SymGemv symg;
+  double sym_elems = 0.0;  // matrix entries read per symmetric application (lower tiles)
   DBuf<int32_t> I_row, I_sub, glob2loc;
   DBuf<double> yj;  // L_rr^{-1} j_r of the right-hand side's forward solve (augmented layout)
   DBuf<double> lam, r, z, p, q, v, b, e, dtil, w, t, pglob, part, scal, aout, tmp;
@@ -59,6 +65,9 @@ struct ieti_handle {
   bool mixed = false;
   hipGraph_t graph = nullptr, graph32 = nullptr;
   hipGraphExec_t graph_exec = nullptr, graph_exec32 = nullptr;
+  // launch sequences replayed every solve: [0] right-hand side, [1] recovery
+  hipGraph_t seq_graph[2] = {nullptr, nullptr};
+  hipGraphExec_t seq_exec[2] = {nullptr, nullptr};
 
   // learned warm start: a copy of the network, its row layout and work space
   struct Warm {
@@ -123,6 +132,12 @@ struct ieti_handle {
     d_edges.release();
     d_vals.release();
     hist.release();
+    sym_task.release();
+    sym_blk.release();
+    sym_csr.release();
+    sym_tprob.release();
+    sym_bprob.release();
+    sym_part.release();
     pd.release();
     blk.release();
     g2l_off.release();
@@ -143,6 +158,10 @@ struct ieti_handle {
     if (graph) (void)hipGraphDestroy(graph);
     if (graph_exec32) (void)hipGraphExecDestroy(graph_exec32);
     if (graph32) (void)hipGraphDestroy(graph32);
+    for (int i = 0; i < 2; ++i) {
+      if (seq_exec[i]) (void)hipGraphExecDestroy(seq_exec[i]);
+      if (seq_graph[i]) (void)hipGraphDestroy(seq_graph[i]);
+    }
     S32.release();
     Sinv32.release();
     warm.release();
@@ -186,6 +205,38 @@ int build_plan_if_needed(ieti_handle* h, int T, int ordering) {
   h->plan_ordering = ordering;
   h->uploaded = false;
   h->factored = false;
+  return IETI_OK;
+}
+
+void drop_graphs(ieti_handle* h) {
+  for (hipGraphExec_t* g : {&h->graph_exec, &h->graph_exec32, &h->seq_exec[0], &h->seq_exec[1]})
+    if (*g) {
+      (void)hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
+  for (hipGraph_t* g : {&h->graph, &h->graph32, &h->seq_graph[0], &h->seq_graph[1]})
+    if (*g) {
+      (void)hipGraphDestroy(*g);
+      *g = nullptr;
+    }
+}
+
+// Runs a launch sequence that is identical in every solve: captured into a
+// graph on first use and replayed after that (direct launches if use_graph
+// is false).
+template <class F>
+int run_sequence(ieti_handle* h, int which, bool use_graph, F&& body) {
+  if (!use_graph) {
+    body();
+    return IETI_OK;
+  }
+  if (!h->seq_exec[which]) {
+    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    body();
+    HIP_TRY(hipStreamEndCapture(h->stream, &h->seq_graph[which]));
+    HIP_TRY(hipGraphInstantiate(&h->seq_exec[which], h->seq_graph[which], nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipGraphLaunch(h->seq_exec[which], h->stream));
   return IETI_OK;
 }
 
@@ -267,6 +318,61 @@ int upload(ieti_handle* h) {
   }
   for (int p = 1; p <= n_prob; ++p)  // problems without interface tasks inherit the previous end
     for (int ri = 0; ri < 3; ++ri) tstart[3 * p + ri] = std::max(tstart[3 * p + ri], tstart[3 * (p - 1) + ri]);
+  // symmetric GEMV: per subdomain with nt = n_Ip / 64 tile rows, tasks (I, t0) over the lower tiles
+  // t0 .. min(t0 + SYM_TILES, I + 1) - 1 of tile row I; output block J sums the row partials of its
+  // tasks (t0 ascending), then the column partials of tiles (I, J), I > J (I ascending)
+  std::vector<int64_t> sym_task_h, sym_blk_h, sym_csr_h, bstart(n_prob + 1, 0);
+  std::vector<int32_t> sym_tprob_h, sym_bprob_h;
+  {
+    const int64_t ST = ieti::dev::SYM_TILES;
+    int64_t poff = 0;
+    h->sym_elems = 0.0;
+    for (size_t k = 0; k < P.sub.size(); ++k) {
+      const auto& sp = P.sub[k];
+      const int pk = M.sub_prob[k];
+      const int64_t nt = sp.nIp / 64;
+      std::vector<int64_t> task_of(size_t(nt * nt), -1), first(nt + 1, 0);
+      std::vector<int64_t> toff;
+      for (int64_t I = 0; I < nt; ++I)
+        for (int64_t t0 = 0; t0 <= I; t0 += ST) {
+          const int64_t ntile = std::min(ST, I + 1 - t0);
+          toff.push_back(poff);
+          for (int64_t t = t0; t < t0 + ntile; ++t) task_of[size_t(I * nt + t)] = int64_t(toff.size()) - 1;
+          sym_task_h.insert(sym_task_h.end(), {sp.S_off + 64 * I * sp.nIp + 64 * t0, sp.nIp, 64 * ntile,
+                                               sp.I_off + 64 * I, sp.I_off + 64 * t0, poff});
+          sym_tprob_h.push_back(pk);
+          poff += 64 + 64 * ntile;
+          h->sym_elems += double(64 * 64) * double(ntile);
+        }
+      for (int64_t J = 0; J < nt; ++J) {
+        const int64_t c0 = int64_t(sym_csr_h.size());
+        for (int64_t t0 = 0; t0 <= J; t0 += ST) sym_csr_h.push_back(toff[size_t(task_of[size_t(J * nt + t0)])]);
+        for (int64_t I = J + 1; I < nt; ++I) {
+          const int64_t tk = task_of[size_t(I * nt + J)];
+          const int64_t t0 = (J / ST) * ST;
+          sym_csr_h.push_back(toff[size_t(tk)] + 64 + 64 * (J - t0));
+        }
+        sym_blk_h.insert(sym_blk_h.end(), {sp.I_off + 64 * J, c0, int64_t(sym_csr_h.size())});
+        sym_bprob_h.push_back(pk);
+      }
+      bstart[pk + 1] = int64_t(sym_blk_h.size() / 3);
+    }
+    for (int p = 1; p <= n_prob; ++p) bstart[p] = std::max(bstart[p], bstart[p - 1]);
+    UP(sym_task, sym_task_h);
+    UP(sym_tprob, sym_tprob_h);
+    UP(sym_blk, sym_blk_h);
+    UP(sym_bprob, sym_bprob_h);
+    UP(sym_csr, sym_csr_h);
+    if ((rc = dalloc(h->sym_part, std::max<int64_t>(poff, 1)))) return rc;
+    h->symg.task = h->sym_task.ptr;
+    h->symg.task_prob = h->sym_tprob.ptr;
+    h->symg.ntask = int64_t(sym_task_h.size() / 6);
+    h->symg.blk = h->sym_blk.ptr;
+    h->symg.blk_prob = h->sym_bprob.ptr;
+    h->symg.nblk = int64_t(sym_blk_h.size() / 3);
+    h->symg.csr = h->sym_csr.ptr;
+    h->symg.part = h->sym_part.ptr;
+  }
   UP(slot_phi_row, phirow);
   for (int ri = 0; ri < 3; ++ri) {
     UP(gemv_tasks[ri], h->gemv_task_h[ri]);
@@ -297,6 +403,8 @@ int upload(ieti_handle* h) {
       d[D::PD_T0 + 2 * ri] = tstart[3 * p + ri];
       d[D::PD_T0 + 2 * ri + 1] = tstart[3 * (p + 1) + ri];
     }
+    d[D::PD_T0 + 6] = bstart[p];
+    d[D::PD_T0 + 7] = bstart[p + 1];
     hoff += pr.m_r * pr.n_gp;
     ptoff += (d[D::PD_B1] - d[D::PD_B0]) * pr.n_gp;
     max_gp = std::max(max_gp, pr.n_gp);
@@ -348,7 +456,7 @@ int upload(ieti_handle* h) {
   if ((rc = dalloc(h->part, 3 * int64_t(h->nblk)))) return rc;
   if ((rc = dalloc(h->xgp, std::max<int64_t>(P.I_total, 1)))) return rc;
   if ((rc = dalloc(h->xgr, std::max<int64_t>(P.I_total, 1)))) return rc;
-  if ((rc = dalloc(h->part_g, std::max(h->ngemv_r[0], 1)))) return rc;
+  if ((rc = dalloc(h->part_g, std::max<int64_t>({int64_t(h->ngemv_r[0]), h->symg.nblk, int64_t(1)})))) return rc;
   if ((rc = dalloc(h->part_t, std::max<int64_t>(ptoff, 1)))) return rc;
   if ((rc = dalloc(h->pdone, n_prob))) return rc;
   if ((rc = dalloc(h->piters, n_prob))) return rc;
@@ -357,24 +465,7 @@ int upload(ieti_handle* h) {
   HIP_TRY(hipHostMalloc(&h->pflags_h, 2 * size_t(n_prob) * sizeof(int)));
   if ((rc = dalloc(h->lam_acc, mm))) return rc;
   if ((rc = dalloc(h->rtrue, mm))) return rc;
-  for (hipGraphExec_t* g : {&h->graph_exec, &h->graph_exec32})
-    if (*g) {
-      (void)hipGraphExecDestroy(*g);
-      *g = nullptr;
-    }
-  for (hipGraph_t* g : {&h->graph, &h->graph32})
-    if (*g) {
-      (void)hipGraphDestroy(*g);
-      *g = nullptr;
-    }
-  if (h->graph_exec) {
-    (void)hipGraphExecDestroy(h->graph_exec);
-    h->graph_exec = nullptr;
-  }
-  if (h->graph) {
-    (void)hipGraphDestroy(h->graph);
-    h->graph = nullptr;
-  }
+  drop_graphs(h);
   if ((rc = dalloc(h->scal, 8 * int64_t(n_prob)))) return rc;
   if ((rc = dalloc(h->flags, 8))) return rc;
   if ((rc = dalloc(h->aout, M.n_edges_total))) return rc;
@@ -435,14 +526,27 @@ const double* dsc(const ieti_handle* h) { return h->scaling == IETI_SCALE_IDENTI
 
 // GEMV launch shape in use for FP64 (fp32 = 0) or FP32 (1) blocks, its task list and task count
 int gvariant(const ieti_handle* h, int fp32) { return h->gvar[fp32] >= 0 ? h->gvar[fp32] : ieti::dev::GEMV_DEFAULT; }
-const int64_t* gtasks(const ieti_handle* h, int fp32) { return h->gemv_tasks[gvariant(h, fp32) / 4].ptr; }
-int gcount(const ieti_handle* h, int fp32) { return h->ngemv_r[gvariant(h, fp32) / 4]; }
+
+// One interface GEMV application with launch shape `variant` (row-streaming
+// shapes, or the symmetric lower-tile kernel); partials in part_g by the
+// variant's task list (index variant / 4 in the problem descriptors).
+template <typename MT>
+void launch_gemv(ieti_handle* h, const MT* M, int variant, const double* xg, double* v, const int* done,
+                 hipEvent_t a = nullptr, hipEvent_t b = nullptr) {
+  namespace D = ieti::dev;
+  if (variant == D::GEMV_SYM) {
+    D::gemv_sym(M, h->symg, xg, v, h->part_g.ptr, done, h->stream, a, b);
+    return;
+  }
+  const int ri = variant / 4;
+  D::gemv(M, h->gemv_tasks[ri].ptr, h->ngemv_r[ri], h->max_ld, xg, v, h->part_g.ptr, done, h->task_prob[ri].ptr,
+          h->stream, variant, a, b);
+}
 
 // Interface GEMV over all subdomains, timed with launch events when profiling.
 template <typename MT>
 void gemv_timed(ieti_handle* h, const MT* M, const double* xg, double* v, const int* done = nullptr) {
   const int fp32 = std::is_same<MT, float>::value ? 1 : 0;
-  const int32_t* tprob = h->task_prob[gvariant(h, fp32) / 4].ptr;
   hipEvent_t a = nullptr, b = nullptr;
   size_t slot = SIZE_MAX;
   if (h->profiling) {
@@ -451,8 +555,7 @@ void gemv_timed(ieti_handle* h, const MT* M, const double* xg, double* v, const 
     b = next_event(h);
     if (!a || !b) a = b = nullptr;
   }
-  ieti::dev::gemv(M, gtasks(h, fp32), gcount(h, fp32), h->max_ld, xg, v, h->part_g.ptr, done, tprob, h->stream,
-                  gvariant(h, fp32), a, b);
+  launch_gemv(h, M, gvariant(h, fp32), xg, v, done, a, b);
   if (a) h->ev_marks.emplace_back(0, slot);
 }
 
@@ -502,18 +605,6 @@ void pcg_iteration_prec(ieti_handle* h, int par, bool fp32) {
   else pcg_iteration<double>(h, par, h->Sinv.ptr, h->S.ptr);
 }
 
-void drop_graphs(ieti_handle* h) {
-  for (hipGraphExec_t* g : {&h->graph_exec, &h->graph_exec32})
-    if (*g) {
-      (void)hipGraphExecDestroy(*g);
-      *g = nullptr;
-    }
-  for (hipGraph_t* g : {&h->graph, &h->graph32})
-    if (*g) {
-      (void)hipGraphDestroy(*g);
-      *g = nullptr;
-    }
-}
 
 // Autotuner of the interface GEMV: every launch shape is timed on the
 // handle's own blocks, alternating the operator and preconditioner blocks as
@@ -527,11 +618,10 @@ int tune_gemv(ieti_handle* h, const MT* Ma, const MT* Mb, int fp32) {
   hipStream_t s = h->stream;
   float best = 1e30f;
   int bv = D::GEMV_DEFAULT;
-  for (int v = 0; v < D::GEMV_VARIANTS; ++v) {
-    const int ri = v / 4;
+  for (int v = 0; v < D::GEMV_SHAPES; ++v) {
     auto launch = [&]() {
-      D::gemv(Ma, h->gemv_tasks[ri].ptr, h->ngemv_r[ri], h->max_ld, h->xgp.ptr, h->v.ptr, h->part_g.ptr, nullptr, nullptr, s, v);
-      D::gemv(Mb, h->gemv_tasks[ri].ptr, h->ngemv_r[ri], h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr, nullptr, s, v);
+      launch_gemv(h, Ma, v, h->xgp.ptr, h->v.ptr, nullptr);
+      launch_gemv(h, Mb, v, h->xgr.ptr, h->v.ptr, nullptr);
     };
     launch();
     launch();
@@ -646,22 +736,25 @@ void backward_solve(ieti_handle* h) {
 }
 
 // Right-hand side b = e - G S_c^{-1} d~ (positive definite form of Eq. intProb).
-int compute_rhs(ieti_handle* h) {
+int compute_rhs(ieti_handle* h, bool use_graph) {
   namespace D = ieti::dev;
   const auto& P = h->plan;
   const auto& M = h->model;
   hipStream_t s = h->stream;
-  D::vec_copy(h->b_aug0.ptr, h->y.ptr, P.r_total, s);
-  forward_solve(h);
-  D::vec_copy(h->y.ptr, h->yj.ptr, P.r_total, s);  // kept for the recovery
-  D::rhs_assemble(h->y.ptr, h->A_aug.ptr, h->row_src.ptr, M.m_r, h->e.ptr, s);
-  if (M.n_gp > 0) {
-    D::sum_sources(h->y.ptr, h->dsrc_ptr.ptr, h->dsrc_idx.ptr, M.n_gp, h->dtil.ptr, s);
-    D::tri_small(h->Spi_glob.ptr, h->dtil.ptr, h->w.ptr, false, h->B, s);
-    D::axpy_rows(h->H.ptr, h->w.ptr, h->e.ptr, h->b.ptr, h->B, s);
-  } else {
-    D::vec_copy(h->e.ptr, h->b.ptr, M.m_r, s);
-  }
+  int rc = run_sequence(h, 0, use_graph, [&]() {
+    D::vec_copy(h->b_aug0.ptr, h->y.ptr, P.r_total, s);
+    forward_solve(h);
+    D::vec_copy(h->y.ptr, h->yj.ptr, P.r_total, s);  // kept for the recovery
+    D::rhs_assemble(h->y.ptr, h->A_aug.ptr, h->row_src.ptr, M.m_r, h->e.ptr, s);
+    if (M.n_gp > 0) {
+      D::sum_sources(h->y.ptr, h->dsrc_ptr.ptr, h->dsrc_idx.ptr, M.n_gp, h->dtil.ptr, s);
+      D::tri_small(h->Spi_glob.ptr, h->dtil.ptr, h->w.ptr, false, h->B, s);
+      D::axpy_rows(h->H.ptr, h->w.ptr, h->e.ptr, h->b.ptr, h->B, s);
+    } else {
+      D::vec_copy(h->e.ptr, h->b.ptr, M.m_r, s);
+    }
+  });
+  if (rc) return rc;
   h->rhs_ready = true;
   return check_launch();
 }
@@ -777,12 +870,8 @@ int run_pcg(ieti_handle* h, const std::vector<double>& tol2, const std::vector<d
   const int pf = fp32 ? 1 : 0;
   const int gt = gvariant(h, pf) / 4;
   D::gather_rows(h->r.ptr, h->row_src.ptr, m_r, h->xgr.ptr, s, dsc(h));
-  if (fp32)
-    D::gemv(h->S32.ptr, gtasks(h, pf), gcount(h, pf), h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr,
-            nullptr, s, gvariant(h, pf));
-  else
-    D::gemv(h->S.ptr, gtasks(h, pf), gcount(h, pf), h->max_ld, h->xgr.ptr, h->v.ptr, h->part_g.ptr, nullptr,
-            nullptr, s, gvariant(h, pf));
+  if (fp32) launch_gemv(h, h->S32.ptr, gvariant(h, pf), h->xgr.ptr, h->v.ptr, nullptr);
+  else launch_gemv(h, h->S.ptr, gvariant(h, pf), h->xgr.ptr, h->v.ptr, nullptr);
   D::pcg_M(h->v.ptr, h->row_src.ptr, h->H.ptr, h->part_g.ptr, part_rr, h->p.ptr, h->z.ptr, h->xgp.ptr, h->part_t.ptr,
            h->scal.ptr, 0, h->pdone.ptr, h->piters.ptr, 1, h->B, gt, s, dsc(h));
   if (use_graph) {
@@ -835,11 +924,11 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   hipStream_t s = h->stream;
   const int64_t m_r = M.m_r;
   const int n_prob = h->B.n_prob;
-  HIP_TRY(hipEventRecord(h->ev0, s));
-  int rc = compute_rhs(h);
-  if (rc) return rc;
   // profiled runs use direct launches so every GEMV carries launch events
   const bool use_graph = (!opts || opts->use_graph != 0) && !h->profiling;
+  HIP_TRY(hipEventRecord(h->ev0, s));
+  int rc = compute_rhs(h, use_graph);
+  if (rc) return rc;
   int it = 0, outer = 0;
   const std::vector<double> bb = host_dots(h, h->b.ptr, h->b.ptr);
   double bb_all = 0.0;
@@ -910,20 +999,24 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   }
   HIP_TRY(hipEventRecord(h->ev2, s));
   // ---- recovery: p = S_c^{-1}(d~ + G^T lambda), a_r = K_rr^{-1}(j_r - K_rp C p - B^T lambda)
-  if (M.n_gp > 0) {
-    // u = L_c^{-1} d~ + H^T lambda, p = L_c^{-T} u  (H = G L_c^{-T}, S_c = L_c L_c^T), per problem
-    D::coarse_project(h->Ht.ptr, h->lam.ptr, h->t.ptr, h->cprob.ptr, h->B, s);
-    D::axpby(h->w.ptr, h->t.ptr, h->dtil.ptr, 1.0, 1.0, M.n_gp, s);
-    D::tri_small(h->Spi_glob.ptr, h->dtil.ptr, h->pglob.ptr, true, h->B, s);
-  }
-  // y = L_rr^{-1} (j_r - K_rp a_p - B_r^T lambda) = y_j - L_pr^T a_p - L_Er^T u (no forward sweep), then
-  // the backward sweep
-  D::vec_copy(h->yj.ptr, h->y.ptr, P.r_total, s);
-  D::recovery_sources(h->y.ptr, h->recP_pos.ptr, h->recP_glob.ptr, int64_t(P.recP_pos.size()),
-                      M.n_gp > 0 ? h->pglob.ptr : nullptr, h->A_aug.ptr, h->I_row.ptr, h->I_sign.ptr, P.I_total,
-                      h->lam.ptr, s);
-  D::trsv_update(h->pool.ptr, h->rec_task.ptr, h->rec_pair.ptr, int64_t(P.rec_task.size() / 3), h->y.ptr, true, s);
-  backward_solve(h);
+  rc = run_sequence(h, 1, use_graph, [&]() {
+    if (M.n_gp > 0) {
+      // u = L_c^{-1} d~ + H^T lambda, p = L_c^{-T} u  (H = G L_c^{-T}, S_c = L_c L_c^T), per problem
+      D::coarse_project(h->Ht.ptr, h->lam.ptr, h->t.ptr, h->cprob.ptr, h->B, s);
+      D::axpby(h->w.ptr, h->t.ptr, h->dtil.ptr, 1.0, 1.0, M.n_gp, s);
+      D::tri_small(h->Spi_glob.ptr, h->dtil.ptr, h->pglob.ptr, true, h->B, s);
+    }
+    // y = L_rr^{-1} (j_r - K_rp a_p - B_r^T lambda) = y_j - L_pr^T a_p - L_Er^T u (no forward sweep),
+    // then the backward sweep
+    D::vec_copy(h->yj.ptr, h->y.ptr, P.r_total, s);
+    D::recovery_sources(h->y.ptr, h->recP_pos.ptr, h->recP_glob.ptr, int64_t(P.recP_pos.size()),
+                        M.n_gp > 0 ? h->pglob.ptr : nullptr, h->A_aug.ptr, h->I_row.ptr, h->I_sign.ptr, P.I_total,
+                        h->lam.ptr, s);
+    D::trsv_update(h->pool.ptr, h->rec_task.ptr, h->rec_pair.ptr, int64_t(P.rec_task.size() / 3), h->y.ptr, true,
+                   s);
+    backward_solve(h);
+  });
+  if (rc) return rc;
   double* aout = a_dev ? a_dev : h->aout.ptr;
   D::fill(aout, M.n_edges_total, 0.0, s);
   D::write_output(h->y.ptr, h->out_src.ptr, h->out_edge.ptr, int64_t(P.out_src.size()), h->pglob.ptr,
@@ -1184,7 +1277,7 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
     return fail(IETI_ERR_NOT_SPD, "coarse matrix of problem " + std::to_string(h->flags_h[4] - 1) +
                                       " is not positive definite");
   const int forced = opts ? opts->gemv_variant : 0;
-  if (forced < 0 || forced > D::GEMV_VARIANTS) return fail(IETI_ERR_INVALID_ARG, "gemv_variant out of range");
+  if (forced < 0 || forced > D::GEMV_SHAPES) return fail(IETI_ERR_INVALID_ARG, "gemv_variant out of range");
   if ((rc = choose_gemv(h, forced, 0))) return rc;
   if (h->mixed && (rc = choose_gemv(h, forced, 1))) return rc;
   // recomputed on every factorisation: it follows the assembled stiffness (set_coefficients)
@@ -1300,7 +1393,7 @@ int ieti_apply_M(ieti_handle* h, const double* r, double* z) {
 int ieti_get_rhs(ieti_handle* h, double* b) {
   if (!h || !b) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
   if (!h->factored) return fail(IETI_ERR_STATE, "not factored");
-  int rc = compute_rhs(h);
+  int rc = compute_rhs(h, false);
   if (rc) return rc;
   const int64_t m_r = h->model.m_r;
   if (m_r > 0) HIP_TRY(hipMemcpyAsync(b, h->b.ptr, m_r * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -1330,7 +1423,7 @@ int ieti_get_gemv_tuning(const ieti_handle* h, int32_t* variant, float* ms) {
   }
   if (ms)
     for (int f = 0; f < 2; ++f)
-      for (int v = 0; v < ieti::dev::GEMV_VARIANTS; ++v) ms[f * ieti::dev::GEMV_VARIANTS + v] = h->gtime[f][v];
+      for (int v = 0; v < ieti::dev::GEMV_SHAPES; ++v) ms[f * ieti::dev::GEMV_SHAPES + v] = h->gtime[f][v];
   return IETI_OK;
 }
 
@@ -1383,7 +1476,9 @@ int ieti_get_pcg_coefficients(const ieti_handle* h, int32_t prob, double* alpha,
 int ieti_get_kernel_times(const ieti_handle* h, double* times) {
   if (!h || !times) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
   double bytes = 0.0;
-  for (const auto& sp : h->plan.sub) bytes += double(sp.nIp) * double(sp.nIp) * sizeof(double);
+  if (h->gvar[0] == ieti::dev::GEMV_SYM) bytes = h->sym_elems * sizeof(double);
+  else
+    for (const auto& sp : h->plan.sub) bytes += double(sp.nIp) * double(sp.nIp) * sizeof(double);
   const double v[6] = {h->k_count[0], h->k_ms[0], h->k_count[1], h->k_ms[1], h->upd_tasks, bytes};
   std::memcpy(times, v, sizeof(v));
   return IETI_OK;

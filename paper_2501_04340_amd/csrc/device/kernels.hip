@@ -319,49 +319,114 @@ __global__ void k_copy_tiles(const double* pool, const int64_t* task, double sca
   }
 }
 
+// Triangular-solve tiles are read straight into registers: lane l of wave q
+// loads entries l + 64 (16 q + k), k < 16, of a column-major 64x64 tile, i.e.
+// 16 coalesced 512-byte column segments per wave; the wave index is made
+// uniform so that the per-pair offsets and (forward) the 16 x values come
+// through scalar loads.
+//   forward (y -= L x):    lane = tile row a, the wave owns columns 16q..16q+15;
+//                          per-lane partial sum over those columns, waves
+//                          combined in LDS in fixed order.
+//   transposed (y -= L^T x): lane = tile row b (x[b] per lane), the wave owns
+//                          output entries a = 16q + k; per-lane products summed
+//                          over the 64 lanes through LDS in fixed order.
+constexpr int TRSV_CHUNK = 4;  // pairs whose tiles are in flight together
+
+template <bool TR>
+__device__ inline void trsv_tile_accumulate(const double* __restrict__ Lg, const double* __restrict__ xs, int lane,
+                                            int q, double& accf, double (&acct)[16]) {
+  double v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = Lg[lane + 64 * (16 * q + k)];
+  if (!TR) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) accf += v[k] * xs[16 * q + k];
+  } else {
+    const double xb = xs[lane];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acct[k] += v[k] * xb;
+  }
+}
+
+// Combine the per-thread partials into the 64 entries of the target vector:
+// out[a] = (forward) sum over waves of accf, (transposed) sum over lanes of acct.
+template <bool TR>
+__device__ inline double trsv_combine(double accf, const double (&acct)[16], int lane, int q, double* red) {
+  if (!TR) {
+    red[q * 64 + lane] = accf;
+    __syncthreads();
+    return (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+  }
+  // red: 64 outputs x 65 (padded) lane partials
+#pragma unroll
+  for (int k = 0; k < 16; ++k) red[(16 * q + k) * 65 + lane] = acct[k];
+  __syncthreads();
+  // thread t: output a = t & 63, lanes 16 (t >> 6) .. +15
+  const int a = threadIdx.x & 63, part = threadIdx.x >> 6;
+  double sum = 0.0;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) sum += red[a * 65 + 16 * part + b];
+  __syncthreads();
+  red[part * 64 + a] = sum;
+  __syncthreads();
+  return (red[a] + red[64 + a]) + (red[128 + a] + red[192 + a]);
+}
+
 // y_j <- L_jj^{-1} y_j (or L_jj^{-T} y_j) with the inverted diagonal tile.
-__global__ __launch_bounds__(256) void k_trsv_diag_inv(const double* inv, const int64_t* task, double* y,
-                                                       int transposed) {
-  __shared__ double L[T][T + 1];
-  __shared__ double x[T];
-  __shared__ double part[4][T];
+template <bool TR>
+__global__ __launch_bounds__(256) void k_trsv_diag_inv(const double* inv, const int64_t* task, double* y) {
+  __shared__ double red[64 * 65];
+  const int lane = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const double* Lg = inv + task[2 * blockIdx.x];
   double* yv = y + task[2 * blockIdx.x + 1];
-  for (int idx = threadIdx.x; idx < T * T; idx += 256) L[idx & (T - 1)][idx >> 6] = Lg[idx];
-  if (threadIdx.x < T) x[threadIdx.x] = yv[threadIdx.x];
-  __syncthreads();
-  const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
-  double s = 0.0;
-  for (int b = 16 * q; b < 16 * q + 16; ++b) s += (transposed ? L[b][a] : L[a][b]) * x[b];
-  part[q][a] = s;
-  __syncthreads();
-  if (threadIdx.x < T) yv[a] = (part[0][a] + part[1][a]) + (part[2][a] + part[3][a]);
+  double accf = 0.0, acct[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acct[k] = 0.0;
+  trsv_tile_accumulate<TR>(Lg, yv, lane, q, accf, acct);
+  const double out = trsv_combine<TR>(accf, acct, lane, q, red);
+  if (threadIdx.x < 64) yv[threadIdx.x] = out;
 }
 
 // y_dst -= sum_p L_p x_p (forward) or sum_p L_p^T x_p (transposed) over the
-// pairs [tile, vec_src] of one target.
+// pairs [tile, vec_src] of one target, TRSV_CHUNK pairs in flight.
+template <bool TR>
 __global__ __launch_bounds__(256) void k_trsv_update_multi(const double* pool, const int64_t* task,
-                                                           const int64_t* pair, double* y, int transposed) {
-  __shared__ double L[T][T + 1];
-  __shared__ double x[T];
-  __shared__ double part[4][T];
+                                                           const int64_t* pair, double* y) {
+  __shared__ double red[64 * 65];
   const int64_t* tk = task + 3 * blockIdx.x;
   double* yd = y + tk[0];
   const int64_t p0 = tk[1], np = tk[2];
-  const int a = threadIdx.x & 63, q = threadIdx.x >> 6;
-  double s = 0.0;
-  for (int64_t pp = 0; pp < np; ++pp) {
-    const double* Lg = pool + pair[2 * (p0 + pp)];
-    const double* ys = y + pair[2 * (p0 + pp) + 1];
-    for (int idx = threadIdx.x; idx < T * T; idx += 256) L[idx & (T - 1)][idx >> 6] = Lg[idx];
-    if (threadIdx.x < T) x[threadIdx.x] = ys[threadIdx.x];
-    __syncthreads();
-    for (int b = 16 * q; b < 16 * q + 16; ++b) s += (transposed ? L[b][a] : L[a][b]) * x[b];
-    __syncthreads();
+  const int lane = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double accf = 0.0, acct[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acct[k] = 0.0;
+  int64_t pp = 0;
+  for (; pp + TRSV_CHUNK <= np; pp += TRSV_CHUNK) {
+    double v[TRSV_CHUNK][16];
+    const double* xs[TRSV_CHUNK];
+#pragma unroll
+    for (int c = 0; c < TRSV_CHUNK; ++c) {
+      const double* Lg = pool + pair[2 * (p0 + pp + c)];
+      xs[c] = y + pair[2 * (p0 + pp + c) + 1];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[c][k] = Lg[lane + 64 * (16 * q + k)];
+    }
+#pragma unroll
+    for (int c = 0; c < TRSV_CHUNK; ++c) {
+      if (!TR) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) accf += v[c][k] * xs[c][16 * q + k];
+      } else {
+        const double xb = xs[c][lane];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acct[k] += v[c][k] * xb;
+      }
+    }
   }
-  part[q][a] = s;
-  __syncthreads();
-  if (threadIdx.x < T) yd[a] -= (part[0][a] + part[1][a]) + (part[2][a] + part[3][a]);
+  for (; pp < np; ++pp)
+    trsv_tile_accumulate<TR>(pool + pair[2 * (p0 + pp)], y + pair[2 * (p0 + pp) + 1], lane, q, accf, acct);
+  const double out = trsv_combine<TR>(accf, acct, lane, q, red);
+  if (threadIdx.x < 64) yd[threadIdx.x] -= out;
 }
 
 __global__ void k_sum_sources(const double* src, const int64_t* ptr, const int64_t* idx, int64_t nout, double* out) {
@@ -581,6 +646,136 @@ __global__ __launch_bounds__(256) void k_gemv(const MT* M, const int64_t* task, 
   if (lane == 0) red[w] = dsum;
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Symmetric interface GEMV (S_rIrI and (K_rr^{-1})_II are symmetric): only
+// the lower 64x64 tiles of a block are read, each once; the diagonal tile is
+// stored whole.  task: [matrix offset of tile (I, t0), ld, ncols (64 per
+// tile, <= SYM_TILES tiles of tile row I starting at tile column t0), first
+// slot of tile row I, first slot of tile column t0, partial offset].  Row
+// role: y_I += A_{I,t} x_t over the task's tiles (a row partial of 64).
+// Column role: y_t += A_{I,t}^T x_I from the same loaded entries (a column
+// partial of 64 per tile; the diagonal tile's is not used).  Lane l holds
+// the columns N (l + 64 j) + e of its vectors for every row, so the column
+// role needs no cross-lane sum; wave q takes rows 16q..16q+15, four at a
+// time, and sums each row across the lanes (fixed butterfly order).
+// Sums of R values (R a power of two, <= 64) over the 64 lanes of a wave at
+// once: each butterfly step exchanges the half of the values a lane does not
+// keep, so R values cost R - 1 + log2(64 / R) exchanges instead of 6 R.  On
+// return lane l holds the total of value r = l >> (6 - log2 R) (fixed order).
+template <int R>
+__device__ inline double multi_wave_sum(double (&v)[R]) {
+  const int lane = threadIdx.x & 63;
+  int n = R, off = 32;
+#pragma unroll
+  for (; n > 1; n >>= 1, off >>= 1) {
+    const bool hi = (lane & off) != 0;
+#pragma unroll
+    for (int i = 0; i < n / 2; ++i) {
+      const double send = hi ? v[i] : v[i + n / 2];
+      const double keep = hi ? v[i + n / 2] : v[i];
+      v[i] = keep + __shfl_xor(send, off, 64);
+    }
+  }
+  double t = v[0];
+#pragma unroll
+  for (; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  return t;
+}
+
+template <typename MT>
+__global__ __launch_bounds__(256) void k_gemv_sym(const MT* M, const int64_t* task, const double* xg, double* part,
+                                                  const int* done, const int32_t* task_prob) {
+  if (done && done[task_prob[blockIdx.x]]) return;
+  using V = Vec16<MT>;
+  using T = typename V::T;
+  constexpr int NJ = SYM_TILES * 64 / (64 * V::N);  // vectors per lane and row
+  constexpr int RB = 16 / NJ;                        // rows per batch: 16 vectors in flight per lane
+  __shared__ double rows[64];
+  __shared__ double cred[4][SYM_TILES * 64];
+  const int64_t* tk = task + 6 * blockIdx.x;
+  const MT* A = M + tk[0];
+  const int64_t ld = tk[1];
+  const int ncols = int(tk[2]);
+  const double* xr = xg + tk[3];
+  const double* xc = xg + tk[4];
+  double* pr = part + tk[5];
+  const int lane = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double x[NJ][V::N], cacc[NJ][V::N];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int c0 = V::N * (lane + 64 * j);
+#pragma unroll
+    for (int e = 0; e < V::N; ++e) {
+      x[j][e] = c0 < ncols ? xc[c0 + e] : 0.0;
+      cacc[j][e] = 0.0;
+    }
+  }
+  constexpr int SH = RB == 16 ? 2 : RB == 8 ? 3 : RB == 4 ? 4 : RB == 2 ? 5 : 6;  // lane >> SH = row of a batch
+#pragma unroll 1
+  for (int i = 0; i < 16; i += RB) {
+    T mv[RB][NJ];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const T* row = reinterpret_cast<const T*>(A + (16 * q + i + r) * ld);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        mv[r][j] = V::N * (lane + 64 * j) < ncols ? __builtin_nontemporal_load(row + lane + 64 * j) : T(0);
+    }
+    double racc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const double xa = xr[16 * q + i + r];
+      double sacc = 0.0;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        sacc += V::dot(mv[r][j], x[j]);
+#pragma unroll
+        for (int e = 0; e < V::N; ++e) cacc[j][e] += double(mv[r][j][e]) * xa;
+      }
+      racc[r] = sacc;
+    }
+    // the batch's row sums: lane l ends with row l >> SH of the batch
+    const double rsum = multi_wave_sum<RB>(racc);
+    if ((lane & ((1 << SH) - 1)) == 0) rows[16 * q + i + (lane >> SH)] = rsum;
+  }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int e = 0; e < V::N; ++e) cred[q][V::N * (lane + 64 * j) + e] = cacc[j][e];
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncols; c += 256) pr[64 + c] = (cred[0][c] + cred[1][c]) + (cred[2][c] + cred[3][c]);
+  if (threadIdx.x < 64) pr[threadIdx.x] = rows[threadIdx.x];
+}
+
+// Output block of 64 slots: v = sum of its partials, split into four
+// groups (partials c0 + g, c0 + g + 4, ...) summed by the four waves and
+// combined in fixed order; the block's dot partial part_g[b] = sum_slots xg v.
+// blk: [first slot, csr begin, csr end]; csr: offsets of 64-entry partials.
+__global__ __launch_bounds__(256) void k_gemv_sym_reduce(const double* part, const int64_t* blk, const int64_t* csr,
+                                                         const double* xg, double* v, double* part_g, const int* done,
+                                                         const int32_t* blk_prob) {
+  if (done && done[blk_prob[blockIdx.x]]) return;
+  __shared__ double red[4][64];
+  const int64_t* b = blk + 3 * blockIdx.x;
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t c1 = b[2];
+  double s0 = 0.0, s1 = 0.0;
+  int64_t c = b[1] + g;
+  for (; c + 4 < c1; c += 8) {
+    s0 += part[csr[c] + lane];
+    s1 += part[csr[c + 4] + lane];
+  }
+  if (c < c1) s0 += part[csr[c] + lane];
+  red[g][lane] = s0 + s1;
+  __syncthreads();
+  if (g == 0) {
+    const int64_t slot = b[0] + lane;
+    const double val = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    v[slot] = val;
+    const double d = wave_sum(val * xg[slot]);
+    if (lane == 0) part_g[blockIdx.x] = d;
+  }
 }
 
 __global__ void k_to_float(const double* in, float* out, int64_t n) {
@@ -911,12 +1106,18 @@ void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double s
 }
 void trsv_diag(const double* inv, const int64_t* task, int64_t ntask, double* y, bool transposed, hipStream_t s) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(k_trsv_diag_inv, dim3(ntask), dim3(256), 0, s, inv, task, y, transposed ? 1 : 0);
+  if (transposed)
+    hipLaunchKernelGGL(k_trsv_diag_inv<true>, dim3(ntask), dim3(256), 0, s, inv, task, y);
+  else
+    hipLaunchKernelGGL(k_trsv_diag_inv<false>, dim3(ntask), dim3(256), 0, s, inv, task, y);
 }
 void trsv_update(const double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, double* y,
                  bool transposed, hipStream_t s) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(k_trsv_update_multi, dim3(ntask), dim3(256), 0, s, pool, task, pair, y, transposed ? 1 : 0);
+  if (transposed)
+    hipLaunchKernelGGL(k_trsv_update_multi<true>, dim3(ntask), dim3(256), 0, s, pool, task, pair, y);
+  else
+    hipLaunchKernelGGL(k_trsv_update_multi<false>, dim3(ntask), dim3(256), 0, s, pool, task, pair, y);
 }
 void sum_sources(const double* src, const int64_t* ptr, const int64_t* idx, int64_t nout, double* out, hipStream_t s) {
   if (nout <= 0) return;
@@ -995,6 +1196,32 @@ void gemv(const float* M, const int64_t* task, int64_t ntask, int64_t max_ld, co
           double* part, const int* done, const int32_t* task_prob, hipStream_t s, int variant, hipEvent_t ev_start,
           hipEvent_t ev_stop) {
   gemv_impl(M, task, ntask, max_ld, xg, v, part, done, task_prob, s, variant, ev_start, ev_stop);
+}
+template <typename MT>
+void gemv_sym_impl(const MT* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
+                   hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  if (g.ntask <= 0 || g.nblk <= 0) return;
+  const int32_t* tp = done ? g.task_prob : nullptr;
+  const int32_t* bp = done ? g.blk_prob : nullptr;
+  if (ev_start)
+    hipExtLaunchKernelGGL(k_gemv_sym<MT>, dim3(g.ntask), dim3(256), 0, s, ev_start, nullptr, 0, M, g.task, xg, g.part,
+                          done, tp);
+  else
+    hipLaunchKernelGGL(k_gemv_sym<MT>, dim3(g.ntask), dim3(256), 0, s, M, g.task, xg, g.part, done, tp);
+  if (ev_stop)
+    hipExtLaunchKernelGGL(k_gemv_sym_reduce, dim3(g.nblk), dim3(256), 0, s, nullptr, ev_stop, 0, g.part, g.blk,
+                          g.csr, xg, v, part_g, done, bp);
+  else
+    hipLaunchKernelGGL(k_gemv_sym_reduce, dim3(g.nblk), dim3(256), 0, s, g.part, g.blk, g.csr, xg, v, part_g, done,
+                       bp);
+}
+void gemv_sym(const double* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
+              hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  gemv_sym_impl(M, g, xg, v, part_g, done, s, ev_start, ev_stop);
+}
+void gemv_sym(const float* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
+              hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  gemv_sym_impl(M, g, xg, v, part_g, done, s, ev_start, ev_stop);
 }
 void to_float(const double* in, float* out, int64_t n, hipStream_t s) {
   if (n <= 0) return;

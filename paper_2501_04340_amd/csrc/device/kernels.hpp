@@ -35,10 +35,11 @@ void trsv_update(const double* pool, const int64_t* task, const int64_t* pair, i
 // [MR0, MR1), global primal indices [GP0, GP0 + NGP), offsets of its blocks
 // of H / G (row-major (MR1-MR0) x NGP), Ht (NGP x (MR1-MR0)) and of its dense
 // coarse matrix (NGP x NGP), its row blocks [B0, B1), the offset of its
-// H^T p block partials (NGP per row block), and its GEMV task ranges for the
-// three task lists (8, 16, 32 rows per workgroup): [T0 + 2i, T0 + 2i + 1).
+// H^T p block partials (NGP per row block), and its ranges of GEMV partials
+// for the three row-streaming task lists (8, 16, 32 rows per workgroup) and
+// the symmetric GEMV's output blocks: [T0 + 2i, T0 + 2i + 1), i < 4.
 enum {
-  PD_MR0 = 0, PD_MR1, PD_GP0, PD_NGP, PD_H, PD_HT, PD_SPI, PD_B0, PD_B1, PD_PT, PD_T0, PD_N = PD_T0 + 6
+  PD_MR0 = 0, PD_MR1, PD_GP0, PD_NGP, PD_H, PD_HT, PD_SPI, PD_B0, PD_B1, PD_PT, PD_T0, PD_N = PD_T0 + 8
 };
 // Row blocks: blk[2b] = first multiplier row, blk[2b+1] = problem; at most 256 rows of one problem each.
 struct Batch {
@@ -87,6 +88,28 @@ void gemv(const double* M, const int64_t* task, int64_t ntask, int64_t max_ld, c
 void gemv(const float* M, const int64_t* task, int64_t ntask, int64_t max_ld, const double* xg, double* v,
           double* part, const int* done, const int32_t* task_prob, hipStream_t s, int variant,
           hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// Symmetric variant: reads each lower 64x64 tile of the dense blocks once (the
+// diagonal tile whole), SYM_TILES tiles of one tile row per task, writing a row
+// partial for y_I and a column partial per tile for y_t (t < I); the reduction
+// sums each 64-slot output block's partials in list order and forms part_g per
+// block.  Variant index GEMV_SYM (after the row-streaming shapes).
+constexpr int SYM_TILES = 8;
+constexpr int GEMV_SYM = GEMV_VARIANTS;
+constexpr int GEMV_SHAPES = GEMV_VARIANTS + 1;
+struct SymGemv {
+  const int64_t* task = nullptr;      // [matrix offset of tile (I, t0), ld, ncols, slot I, slot t0, partial offset]
+  const int32_t* task_prob = nullptr;
+  int64_t ntask = 0;
+  const int64_t* blk = nullptr;       // [first slot, csr begin, csr end] per output block of 64 slots
+  const int32_t* blk_prob = nullptr;
+  int64_t nblk = 0;
+  const int64_t* csr = nullptr;       // offsets of the 64-entry partials of each block
+  double* part = nullptr;
+};
+void gemv_sym(const double* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
+              hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+void gemv_sym(const float* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
+              hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 void to_float(const double* in, float* out, int64_t n, hipStream_t s);
 // out[c] = sum over problem(c)'s rows of Ht[c][row] x[row]; cprob[c] = problem of global primal c
 void coarse_project(const double* Ht, const double* x, double* out, const int32_t* cprob, const Batch& B,

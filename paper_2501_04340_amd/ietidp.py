@@ -15,6 +15,8 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "lib
 _lib = None
 
 ABI_VERSION = 2
+GEMV_SHAPES = 13   # interface GEMV launch shapes: 0..11 row streaming, 12 symmetric (lower tiles)
+GEMV_SYM = 12
 PREC_FP64, PREC_MIXED = 0, 1
 SCALE_IDENTITY, SCALE_STIFFNESS, SCALE_MULTIPLICITY = 0, 1, 2
 ERRORS = {
@@ -444,11 +446,11 @@ class Solver:
         return dict(zip(keys, v.tolist()))
 
     def gemv_tuning(self):
-        """(chosen shape for FP64 and FP32 blocks, ms per shape [2, 12]) of the GEMV autotuner."""
+        """(chosen shape for FP64 and FP32 blocks, ms per shape [2, GEMV_SHAPES]) of the GEMV autotuner."""
         v = np.zeros(2, np.int32)
-        ms = np.zeros(24, np.float32)
+        ms = np.zeros(2 * GEMV_SHAPES, np.float32)
         _check(self.lib, self.lib.ieti_get_gemv_tuning(self.h, _ptr(v, C.c_int32), _ptr(ms, C.c_float)))
-        return v.tolist(), ms.reshape(2, 12)
+        return v.tolist(), ms.reshape(2, GEMV_SHAPES)
 
     def set_profiling(self, enable=True):
         _check(self.lib, self.lib.ieti_set_profiling(self.h, 1 if enable else 0))

@@ -58,6 +58,20 @@ def test_batch_equals_individual_solves_bitwise(batch):
     assert st["iters"] == max(b["iters"] for b in info)
 
 
+def test_batch_equals_individual_solves_bitwise_symmetric_gemv(batch):
+    from paper_2501_04340_amd.ietidp import GEMV_SYM
+    probs, B, singles = batch
+    B.factor(gemv_variant=GEMV_SYM)
+    a, st = B.solve(rtol=1e-10)
+    parts = B.split(a)
+    info = B.batch_info()
+    for i, S in enumerate(singles):
+        S.factor(gemv_variant=GEMV_SYM)
+        a_i, st_i = S.solve(rtol=1e-10)
+        assert info[i]["iters"] == st_i["iters"], i
+        assert np.array_equal(parts[i], a_i), i
+
+
 def test_batch_solution_matches_oracle(batch):
     probs, B, singles = batch
     B.factor()

@@ -208,19 +208,50 @@ def test_gemv_launch_shapes_agree_bitwise(runs):
     """Every GEMV launch shape sums each row in the same order: the operator
     and preconditioner applications are bitwise identical across shapes, and
     the autotuner timed every shape."""
+    from paper_2501_04340_amd.ietidp import GEMV_SHAPES, GEMV_SYM
     prob, S, O = _get(runs, "cube64_small")
     chosen, ms = S.gemv_tuning()
-    assert 0 <= chosen[0] < 12 and np.all(ms[0] > 0)
+    assert 0 <= chosen[0] < GEMV_SHAPES and np.all(ms[0] > 0)
     x = np.random.default_rng(5).standard_normal(S.m_r)
     ref = None
-    for v in range(12):
+    for v in range(GEMV_SYM):
         S.factor(gemv_variant=v)
         assert S.gemv_tuning()[0][0] == v
         out = (S.apply_F(x), S.apply_M(x))
         if ref is None:
             ref = out
         assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
+    # the symmetric lower-tile GEMV sums in another order: equal to rounding
+    S.factor(gemv_variant=GEMV_SYM)
+    out = (S.apply_F(x), S.apply_M(x))
+    for a, b in zip(out, ref):
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
     S.factor(gemv_variant=chosen[0])
+
+
+@pytest.mark.parametrize("name", ["cube8", "uneven_nu", "cube8_p3", "ring_coarse", "paper_cube"])
+def test_symmetric_gemv_matches_oracle(runs, name):
+    """The symmetric interface GEMV (each lower tile read once, transposed
+    contributions through partials): operator, preconditioner and solution
+    against the oracle, with the same tolerances as the row-streaming path."""
+    from paper_2501_04340_amd.ietidp import GEMV_SYM
+    prob, S, O = _get(runs, name)
+    chosen = S.gemv_tuning()[0][0]
+    D = O.ieti
+    S.factor(gemv_variant=GEMV_SYM)
+    try:
+        x = np.random.default_rng(17).standard_normal(D.m_r)
+        qF, qF_o = S.apply_F(x), D.apply_negS(x)
+        assert np.abs(qF - qF_o).max() <= 1e-10 * np.abs(qF_o).max()
+        qM, qM_o = S.apply_M(x), D.apply_MD(x)
+        assert np.abs(qM - qM_o).max() <= 1e-10 * np.abs(qM_o).max()
+        a, st = S.solve(rtol=1e-12, maxit=2000)
+        assert st["status"] == 0
+        assert b_error(O.space, a, a_ref=O.monolithic())[1] <= 1e-9
+        a2, _ = S.solve(rtol=1e-12, maxit=2000, use_graph=False)
+        assert np.array_equal(a, a2)
+    finally:
+        S.factor(gemv_variant=chosen)
 
 
 @pytest.mark.parametrize("name", ["uneven_nu", "cube64_small", "ring_coarse"])
