@@ -68,6 +68,14 @@ __global__ void k_scatter(double* pool, const int64_t* dst, const double* val, i
 // transposed LDS copy and multiplying by the stored reciprocal pivots.  A
 // non-positive pivot records the subdomain (1-based) in err and continues
 // with pivot 1.
+// Value of lane `src` (wave-uniform) of a double, through two readlanes.
+__device__ inline double readlane_f64(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), src);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 __global__ __launch_bounds__(256) void k_potrf_inv(double* pool, double* inv, const int64_t* task, int* err) {
   __shared__ __align__(16) double Lt[T][T + 2];  // Lt[j][i] = L[i][j]; later X staging
   __shared__ __align__(16) double bc[2][T];
@@ -76,39 +84,50 @@ __global__ __launch_bounds__(256) void k_potrf_inv(double* pool, double* inv, co
   double* t = pool + tk[0];
   const int sub = int(tk[1]);
   double* tinv = inv + tk[2];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c0 = 16 * w;
   double a[16];
 #pragma unroll
   for (int jj = 0; jj < 16; ++jj) a[jj] = t[(c0 + jj) * T + lane];
   bool bad = false;
+  // 64 column steps as 4 x 16: the inner steps are unrolled so that register
+  // indices stay static, the outer loop is not (keeps the code in the
+  // instruction cache)
+#pragma unroll 1
+  for (int kb = 0; kb < T; kb += 16)
 #pragma unroll
-  for (int k = 0; k < T; ++k) {
-    double* col = bc[k & 1];
-    if (w == (k >> 4)) {
-      const double akk = __shfl(a[k & 15], k, 64);
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = kb + kk;
+    double* col = bc[kk & 1];
+    if (w == (kb >> 4)) {
+      const double akk = readlane_f64(a[kk], k);
       const bool ok = akk > 0.0;
       bad = bad || !ok;
       const double piv = sqrt(ok ? akk : 1.0);
       const double rp = 1.0 / piv;
-      const double lik = (lane == k) ? piv : (lane > k ? a[k & 15] * rp : 0.0);
-      a[k & 15] = lik;
+      const double lik = (lane == k) ? piv : (lane > k ? a[kk] * rp : 0.0);
+      a[kk] = lik;
       col[lane] = lik;
       if (lane == 0) dinv[k] = rp;
     }
     __syncthreads();
-    const double li = col[lane];
-    double cj[16];
+    // trailing update of the wave's columns c0 + jj > k (wave-uniform cases)
+    if (w >= (kb >> 4)) {
+      const double li = col[lane];
+      double cj[16];
 #pragma unroll
-    for (int jj = 0; jj < 16; jj += 2) {
-      const double2 v = *reinterpret_cast<const double2*>(&col[c0 + jj]);
-      cj[jj] = v.x;
-      cj[jj + 1] = v.y;
-    }
+      for (int jj = 0; jj < 16; jj += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(&col[c0 + jj]);
+        cj[jj] = v.x;
+        cj[jj + 1] = v.y;
+      }
+      if (w > (kb >> 4)) {
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-      const double u = a[jj] - li * cj[jj];
-      a[jj] = (c0 + jj > k) ? u : a[jj];
+        for (int jj = 0; jj < 16; ++jj) a[jj] -= li * cj[jj];
+      } else {
+#pragma unroll
+        for (int jj = kk + 1; jj < 16; ++jj) a[jj] -= li * cj[jj];
+      }
     }
   }
 #pragma unroll
@@ -121,27 +140,34 @@ __global__ __launch_bounds__(256) void k_potrf_inv(double* pool, double* inv, co
   double x[16];
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) x[rr] = (c0 + rr == lane) ? 1.0 : 0.0;
+#pragma unroll 1
+  for (int kb = 0; kb < T; kb += 16)
 #pragma unroll
-  for (int k = 0; k < T; ++k) {
-    double* xk = bc[k & 1];
-    if (w == (k >> 4)) {
-      const double v = x[k & 15] * dinv[k];
-      x[k & 15] = v;
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = kb + kk;
+    double* xk = bc[kk & 1];
+    if (w == (kb >> 4)) {
+      const double v = x[kk] * dinv[k];
+      x[kk] = v;
       xk[lane] = v;
     }
     __syncthreads();
-    const double xv = xk[lane];
-    double lk[16];
+    if (w >= (kb >> 4)) {
+      const double xv = xk[lane];
+      double lk[16];
 #pragma unroll
-    for (int rr = 0; rr < 16; rr += 2) {
-      const double2 v = *reinterpret_cast<const double2*>(&Lt[k][c0 + rr]);
-      lk[rr] = v.x;
-      lk[rr + 1] = v.y;
-    }
+      for (int rr = 0; rr < 16; rr += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(&Lt[k][c0 + rr]);
+        lk[rr] = v.x;
+        lk[rr + 1] = v.y;
+      }
+      if (w > (kb >> 4)) {
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) {
-      const double u = x[rr] - lk[rr] * xv;
-      x[rr] = (c0 + rr > k) ? u : x[rr];
+        for (int rr = 0; rr < 16; ++rr) x[rr] -= lk[rr] * xv;
+      } else {
+#pragma unroll
+        for (int rr = kk + 1; rr < 16; ++rr) x[rr] -= lk[rr] * xv;
+      }
     }
   }
   __syncthreads();
