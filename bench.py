@@ -41,17 +41,19 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "cube64_hbm_traffic_pmc.md")
 KERNELS_SRC = os.path.join(ROOT, "paper_2501_04340_amd", "csrc", "device", "kernels.hip")
 
 
-def measured_gemv_traffic():
-    """HBM bytes per FP64 GEMV launch from the committed PMC summary, or None
-    when the kernel source changed since the counters were taken."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` ("k_update_multi", "k_gemv_sym<double>"
+    or "k_gemv<double>") from the committed PMC summary, or None when the
+    kernel source changed since the counters were taken."""
     import hashlib
     import re
     try:
         text = open(TRAFFIC_PROFILE).read()
-        m = re.search(r"traffic_per_launch k_gemv fp64: .*total_bytes=(\d+) kernels_hip_sha256=([0-9a-f]+)", text)
         sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
     except OSError:
         return None
+    m = re.search(r"traffic_per_launch " + re.escape(kernel) + r": .*total_bytes=(\d+) kernels_hip_sha256=([0-9a-f]+)",
+                  text)
     if not m or m.group(2) != sha:
         return None
     return float(m.group(1))
@@ -228,7 +230,7 @@ def stream_batches(args):
     import torch
 
     from paper_2501_04340_amd import Solver
-    from paper_2501_04340_amd.ietidp import PREC_FP64, PREC_MIXED
+    from paper_2501_04340_amd.ietidp import GEMV_SYM, PREC_FP64, PREC_MIXED
     from workloads import configs
 
     torch.cuda.set_device(0)
@@ -263,7 +265,7 @@ def stream_batches(args):
             iters_single.append(st["iters"])
             outs.append(a)
             n_g_total += S.n_global
-        bytes_p = [S.kernel_times()["gemv_bytes"] for S in singles]  # interface blocks per application
+        kts = [S.kernel_times() for S in singles]  # interface-block bytes per application, both layouts
         B = Solver.batch_of(singles)
         for S in singles:
             S.close()
@@ -296,9 +298,12 @@ def stream_batches(args):
             kt = B.kernel_times()
             B.set_profiling(False)
             its = [b["iters"] for b in B.batch_info()]
+            bsym = int(B.gemv_tuning()[0][0]) == GEMV_SYM
+            bytes_p = [k["gemv_bytes_lower" if bsym else "gemv_bytes_full"] for k in kts]
             total_bytes = float(sum(bp * (2 * it + 1) for bp, it in zip(bytes_p, its)))
             ach = total_bytes / (kt["gemv_ms"] * 1e-3) / 1e9
-            roof = {"kernel": "k_gemv<double> (autotuned shape), one batch of "
+            kname = "k_gemv_sym<double>" if bsym else "k_gemv<double>"
+            roof = {"kernel": f"{kname} (autotuned shape), one batch of "
                               f"{len(ids)} problems", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
                     "avg_launch_ms": kt["gemv_ms"] / max(kt["gemv_launches"], 1),
@@ -360,6 +365,7 @@ def main():
     import torch
 
     from paper_2501_04340_amd import Solver
+    from paper_2501_04340_amd.ietidp import GEMV_SYM
     from workloads import configs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -410,24 +416,27 @@ def main():
     solve_ms = float(np.median([s["t_solve_s"] for s in stats])) * 1e3
     log(f"timed: {ms_per_step:.2f} ms/step, iters {iters}, factor {factor_ms:.2f} ms, solve {solve_ms:.2f} ms, "
         f"kernels {kt}")
-    # dominant kernel roofline
-    gemv_ms = kt["gemv_ms"] / max(kt["gemv_launches"], 1)
-    upd_ms_total, gemv_ms_total = kt["update_ms"], kt["gemv_ms"]
-    if gemv_ms_total >= upd_ms_total:
-        achieved = kt["gemv_bytes"] / (gemv_ms * 1e-3) / 1e9
-        roof = {"kernel": "k_gemv<double> (autotuned shape)", "bound": "hbm", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_gemv_traffic(),
-                "avg_launch_ms": gemv_ms, "bytes_per_launch": kt["gemv_bytes"]}
-    else:
-        flops_per_task = 2.0 * 64 ** 3
-        per_launch = kt["update_tasks"] / max(kt["update_launches"], 1) * flops_per_task
-        avg = kt["update_ms"] / max(kt["update_launches"], 1)
-        achieved = per_launch / (avg * 1e-3) / 1e12
-        roof = {"kernel": "k_update", "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
-                "avg_launch_ms": avg, "flops_per_launch": per_launch}
+    # roofline of the dominant kernel (largest total time per step): the
+    # factorisation's tile update (FP64 MFMA) or the interface GEMV (HBM)
     chosen, tune_ms = S.gemv_tuning()
+    sym = int(chosen[0]) == GEMV_SYM
+    gemv_name = "k_gemv_sym<double>" if sym else "k_gemv<double>"
+    gemv_ms = kt["gemv_ms"] / max(kt["gemv_launches"], 1)
+    gemv_ach = kt["gemv_bytes"] / (gemv_ms * 1e-3) / 1e9
+    roof_gemv = {"kernel": gemv_name, "bound": "hbm", "achieved": gemv_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": gemv_ach / HBM_PEAK_GBS, "traffic": measured_traffic(gemv_name),
+                 "avg_launch_ms": gemv_ms, "bytes_per_launch": kt["gemv_bytes"],
+                 "launches_per_step": kt["gemv_launches"], "ms_per_step": kt["gemv_ms"]}
+    flops_per_task = 2.0 * 64 ** 3
+    upd_avg = kt["update_ms"] / max(kt["update_launches"], 1)
+    upd_flops = kt["update_tasks"] / max(kt["update_launches"], 1) * flops_per_task
+    upd_ach = upd_flops / (upd_avg * 1e-3) / 1e12
+    roof_upd = {"kernel": "k_update_multi", "bound": "mfma", "achieved": upd_ach, "peak": FP64_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": upd_ach / FP64_MFMA_PEAK_TFLOPS, "traffic": measured_traffic("k_update_multi"),
+                "avg_launch_ms": upd_avg, "flops_per_launch": upd_flops,
+                "launches_per_step": kt["update_launches"], "ms_per_step": kt["update_ms"]}
+    roof = dict(roof_gemv if kt["gemv_ms"] >= kt["update_ms"] else roof_upd)
+    roof["other"] = roof_upd if roof["kernel"] == gemv_name else roof_gemv
     log(f"GEMV autotuner (FP64 blocks): chosen shape {chosen[0]}, ms per shape {np.round(tune_ms[0], 4).tolist()}")
     # mixed-precision variant of the same step (FP32-stored interface blocks in
     # the inner PCG, outer refinement on the FP64 residual)

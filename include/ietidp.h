@@ -271,9 +271,12 @@ int ieti_set_profiling(ieti_handle* h, int32_t enable);
  * order.  Either argument may be NULL. */
 int ieti_get_gemv_tuning(const ieti_handle* h, int32_t* variant, float* ms);
 
-/* times[0..5] = {GEMV launches, GEMV total ms, update launches, update total
+/* times[0..7] = {GEMV launches, GEMV total ms, update launches, update total
  * ms, update tasks executed, FP64 interface-block bytes read per GEMV
- * application with the chosen FP64 shape}. */
+ * application with the chosen FP64 shape, the same for the row-streaming
+ * shapes (whole blocks), the same for the symmetric shape (lower tiles)}.
+ * With the symmetric shape the GEMV launches and times are those of its
+ * tile kernel (the block reduction is a separate small launch). */
 int ieti_get_kernel_times(const ieti_handle* h, double* times);
 
 /* Change the reluctivity of every patch and scale every patch's load

@@ -1475,11 +1475,11 @@ int ieti_get_pcg_coefficients(const ieti_handle* h, int32_t prob, double* alpha,
 
 int ieti_get_kernel_times(const ieti_handle* h, double* times) {
   if (!h || !times) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
-  double bytes = 0.0;
-  if (h->gvar[0] == ieti::dev::GEMV_SYM) bytes = h->sym_elems * sizeof(double);
-  else
-    for (const auto& sp : h->plan.sub) bytes += double(sp.nIp) * double(sp.nIp) * sizeof(double);
-  const double v[6] = {h->k_count[0], h->k_ms[0], h->k_count[1], h->k_ms[1], h->upd_tasks, bytes};
+  double full = 0.0;
+  for (const auto& sp : h->plan.sub) full += double(sp.nIp) * double(sp.nIp) * sizeof(double);
+  const double lower = h->sym_elems * sizeof(double);
+  const double bytes = h->gvar[0] == ieti::dev::GEMV_SYM ? lower : full;
+  const double v[8] = {h->k_count[0], h->k_ms[0], h->k_count[1], h->k_ms[1], h->upd_tasks, bytes, full, lower};
   std::memcpy(times, v, sizeof(v));
   return IETI_OK;
 }

@@ -1229,17 +1229,14 @@ void gemv_sym_impl(const MT* M, const SymGemv& g, const double* xg, double* v, d
   if (g.ntask <= 0 || g.nblk <= 0) return;
   const int32_t* tp = done ? g.task_prob : nullptr;
   const int32_t* bp = done ? g.blk_prob : nullptr;
+  // the events bracket the tile kernel (the streaming part); the block
+  // reduction is a separate small launch
   if (ev_start)
-    hipExtLaunchKernelGGL(k_gemv_sym<MT>, dim3(g.ntask), dim3(256), 0, s, ev_start, nullptr, 0, M, g.task, xg, g.part,
+    hipExtLaunchKernelGGL(k_gemv_sym<MT>, dim3(g.ntask), dim3(256), 0, s, ev_start, ev_stop, 0, M, g.task, xg, g.part,
                           done, tp);
   else
     hipLaunchKernelGGL(k_gemv_sym<MT>, dim3(g.ntask), dim3(256), 0, s, M, g.task, xg, g.part, done, tp);
-  if (ev_stop)
-    hipExtLaunchKernelGGL(k_gemv_sym_reduce, dim3(g.nblk), dim3(256), 0, s, nullptr, ev_stop, 0, g.part, g.blk,
-                          g.csr, xg, v, part_g, done, bp);
-  else
-    hipLaunchKernelGGL(k_gemv_sym_reduce, dim3(g.nblk), dim3(256), 0, s, g.part, g.blk, g.csr, xg, v, part_g, done,
-                       bp);
+  hipLaunchKernelGGL(k_gemv_sym_reduce, dim3(g.nblk), dim3(256), 0, s, g.part, g.blk, g.csr, xg, v, part_g, done, bp);
 }
 void gemv_sym(const double* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
               hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {

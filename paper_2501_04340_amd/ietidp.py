@@ -456,9 +456,10 @@ class Solver:
         _check(self.lib, self.lib.ieti_set_profiling(self.h, 1 if enable else 0))
 
     def kernel_times(self):
-        v = np.zeros(6)
+        v = np.zeros(8)
         _check(self.lib, self.lib.ieti_get_kernel_times(self.h, _ptr(v, C.c_double)))
-        keys = ["gemv_launches", "gemv_ms", "update_launches", "update_ms", "update_tasks", "gemv_bytes"]
+        keys = ["gemv_launches", "gemv_ms", "update_launches", "update_ms", "update_tasks", "gemv_bytes",
+                "gemv_bytes_full", "gemv_bytes_lower"]
         return dict(zip(keys, v.tolist()))
 
     def lambda_(self):
