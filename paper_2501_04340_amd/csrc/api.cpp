@@ -51,7 +51,7 @@ struct ieti_handle {
   int gvar[2] = {-1, -1};                              // GEMV launch shape for FP64 / FP32 blocks (-1 = untuned)
   float gtime[2][ieti::dev::GEMV_SHAPES] = {};        // autotuner: ms per launch of each shape
   // symmetric GEMV: tasks over lower tiles, output blocks, partial lists and buffer
-  DBuf<int64_t> sym_task, sym_blk, sym_csr;
+  DBuf<int64_t> sym_task, sym_blk;
   DBuf<int32_t> sym_tprob, sym_bprob;
   DBuf<double> sym_part;
   ieti::dev::SymGemv symg;
@@ -134,7 +134,6 @@ struct ieti_handle {
     hist.release();
     sym_task.release();
     sym_blk.release();
-    sym_csr.release();
     sym_tprob.release();
     sym_bprob.release();
     sym_part.release();
@@ -319,58 +318,62 @@ int upload(ieti_handle* h) {
   for (int p = 1; p <= n_prob; ++p)  // problems without interface tasks inherit the previous end
     for (int ri = 0; ri < 3; ++ri) tstart[3 * p + ri] = std::max(tstart[3 * p + ri], tstart[3 * (p - 1) + ri]);
   // symmetric GEMV: per subdomain with nt = n_Ip / 64 tile rows, tasks (I, t0) over the lower tiles
-  // t0 .. min(t0 + SYM_TILES, I + 1) - 1 of tile row I; output block J sums the row partials of its
-  // tasks (t0 ascending), then the column partials of tiles (I, J), I > J (I ascending)
-  std::vector<int64_t> sym_task_h, sym_blk_h, sym_csr_h, bstart(n_prob + 1, 0);
+  // t0 .. min(t0 + SYM_TILES, I + 1) - 1 of tile row I.  Output block J (64 slots) keeps its partials
+  // contiguous: the row partials of its tasks (t0 ascending), then the column partials of tiles (I, J),
+  // I > J (I ascending); its value is their sum in that order.  The tasks are launched largest first
+  // (fewer tiles at the end of the launch).
+  std::vector<int64_t> sym_task_h, sym_blk_h, bstart(n_prob + 1, 0);
   std::vector<int32_t> sym_tprob_h, sym_bprob_h;
   {
     const int64_t ST = ieti::dev::SYM_TILES;
     int64_t poff = 0;
     h->sym_elems = 0.0;
+    std::vector<std::vector<int64_t>> by_size(ST + 1);  // task records by tile count
+    std::vector<std::vector<int32_t>> prob_by_size(ST + 1);
     for (size_t k = 0; k < P.sub.size(); ++k) {
       const auto& sp = P.sub[k];
       const int pk = M.sub_prob[k];
       const int64_t nt = sp.nIp / 64;
-      std::vector<int64_t> task_of(size_t(nt * nt), -1), first(nt + 1, 0);
-      std::vector<int64_t> toff;
-      for (int64_t I = 0; I < nt; ++I)
-        for (int64_t t0 = 0; t0 <= I; t0 += ST) {
-          const int64_t ntile = std::min(ST, I + 1 - t0);
-          toff.push_back(poff);
-          for (int64_t t = t0; t < t0 + ntile; ++t) task_of[size_t(I * nt + t)] = int64_t(toff.size()) - 1;
-          sym_task_h.insert(sym_task_h.end(), {sp.S_off + 64 * I * sp.nIp + 64 * t0, sp.nIp, 64 * ntile,
-                                               sp.I_off + 64 * I, sp.I_off + 64 * t0, poff});
-          sym_tprob_h.push_back(pk);
-          poff += 64 + 64 * ntile;
-          h->sym_elems += double(64 * 64) * double(ntile);
-        }
+      std::vector<int64_t> pbase(nt, 0);
       for (int64_t J = 0; J < nt; ++J) {
-        const int64_t c0 = int64_t(sym_csr_h.size());
-        for (int64_t t0 = 0; t0 <= J; t0 += ST) sym_csr_h.push_back(toff[size_t(task_of[size_t(J * nt + t0)])]);
-        for (int64_t I = J + 1; I < nt; ++I) {
-          const int64_t tk = task_of[size_t(I * nt + J)];
-          const int64_t t0 = (J / ST) * ST;
-          sym_csr_h.push_back(toff[size_t(tk)] + 64 + 64 * (J - t0));
-        }
-        sym_blk_h.insert(sym_blk_h.end(), {sp.I_off + 64 * J, c0, int64_t(sym_csr_h.size())});
+        const int64_t cnt = (J + ST) / ST + (nt - 1 - J);  // row partials + column partials
+        pbase[J] = poff;
+        poff += 64 * cnt;
+        sym_blk_h.insert(sym_blk_h.end(), {sp.I_off + 64 * J, pbase[J], cnt});
         sym_bprob_h.push_back(pk);
       }
       bstart[pk + 1] = int64_t(sym_blk_h.size() / 3);
+      for (int64_t I = 0; I < nt; ++I)
+        for (int64_t t0 = 0; t0 <= I; t0 += ST) {
+          const int64_t ntile = std::min(ST, I + 1 - t0);
+          auto& rec = by_size[ntile];
+          rec.insert(rec.end(), {sp.S_off + 64 * I * sp.nIp + 64 * t0, sp.nIp, 64 * ntile, sp.I_off + 64 * I,
+                                 sp.I_off + 64 * t0, pbase[I] + 64 * (t0 / ST)});
+          for (int64_t c = 0; c < ST; ++c) {
+            const int64_t t = t0 + c;
+            // column partial of tile (I, t), t < I: entry (t / ST + 1) + (I - t - 1) of block t
+            rec.push_back(c < ntile && t < I ? pbase[t] + 64 * ((t + ST) / ST + (I - t - 1)) : -1);
+          }
+          prob_by_size[ntile].push_back(pk);
+          h->sym_elems += double(64 * 64) * double(ntile);
+        }
+    }
+    for (int64_t n = ST; n >= 1; --n) {
+      sym_task_h.insert(sym_task_h.end(), by_size[n].begin(), by_size[n].end());
+      sym_tprob_h.insert(sym_tprob_h.end(), prob_by_size[n].begin(), prob_by_size[n].end());
     }
     for (int p = 1; p <= n_prob; ++p) bstart[p] = std::max(bstart[p], bstart[p - 1]);
     UP(sym_task, sym_task_h);
     UP(sym_tprob, sym_tprob_h);
     UP(sym_blk, sym_blk_h);
     UP(sym_bprob, sym_bprob_h);
-    UP(sym_csr, sym_csr_h);
     if ((rc = dalloc(h->sym_part, std::max<int64_t>(poff, 1)))) return rc;
     h->symg.task = h->sym_task.ptr;
     h->symg.task_prob = h->sym_tprob.ptr;
-    h->symg.ntask = int64_t(sym_task_h.size() / 6);
+    h->symg.ntask = int64_t(sym_tprob_h.size());
     h->symg.blk = h->sym_blk.ptr;
     h->symg.blk_prob = h->sym_bprob.ptr;
     h->symg.nblk = int64_t(sym_blk_h.size() / 3);
-    h->symg.csr = h->sym_csr.ptr;
     h->symg.part = h->sym_part.ptr;
   }
   UP(slot_phi_row, phirow);

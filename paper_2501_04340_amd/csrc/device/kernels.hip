@@ -719,13 +719,12 @@ __global__ __launch_bounds__(256) void k_gemv_sym(const MT* M, const int64_t* ta
   constexpr int RB = 16 / NJ;                        // rows per batch: 16 vectors in flight per lane
   __shared__ double rows[64];
   __shared__ double cred[4][SYM_TILES * 64];
-  const int64_t* tk = task + 6 * blockIdx.x;
+  const int64_t* tk = task + SYM_TASK * blockIdx.x;
   const MT* A = M + tk[0];
   const int64_t ld = tk[1];
   const int ncols = int(tk[2]);
   const double* xr = xg + tk[3];
   const double* xc = xg + tk[4];
-  double* pr = part + tk[5];
   const int lane = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double x[NJ][V::N], cacc[NJ][V::N];
 #pragma unroll
@@ -770,29 +769,33 @@ __global__ __launch_bounds__(256) void k_gemv_sym(const MT* M, const int64_t* ta
 #pragma unroll
     for (int e = 0; e < V::N; ++e) cred[q][V::N * (lane + 64 * j) + e] = cacc[j][e];
   __syncthreads();
-  for (int c = threadIdx.x; c < ncols; c += 256) pr[64 + c] = (cred[0][c] + cred[1][c]) + (cred[2][c] + cred[3][c]);
-  if (threadIdx.x < 64) pr[threadIdx.x] = rows[threadIdx.x];
+  for (int c = threadIdx.x; c < ncols; c += 256) {
+    const int64_t dst = tk[6 + (c >> 6)];
+    if (dst >= 0) part[dst + (c & 63)] = (cred[0][c] + cred[1][c]) + (cred[2][c] + cred[3][c]);
+  }
+  if (threadIdx.x < 64) part[tk[5] + threadIdx.x] = rows[threadIdx.x];
 }
 
-// Output block of 64 slots: v = sum of its partials, split into four
-// groups (partials c0 + g, c0 + g + 4, ...) summed by the four waves and
-// combined in fixed order; the block's dot partial part_g[b] = sum_slots xg v.
-// blk: [first slot, csr begin, csr end]; csr: offsets of 64-entry partials.
-__global__ __launch_bounds__(256) void k_gemv_sym_reduce(const double* part, const int64_t* blk, const int64_t* csr,
-                                                         const double* xg, double* v, double* part_g, const int* done,
+// Output block of 64 slots: v = sum of its contiguous partials (64 entries
+// apiece), split into four groups (partials g, g + 4, ...) summed by the four
+// waves and combined in fixed order; the block's dot partial
+// part_g[b] = sum_slots xg v.  blk: [first slot, first partial, count].
+__global__ __launch_bounds__(256) void k_gemv_sym_reduce(const double* part, const int64_t* blk, const double* xg,
+                                                         double* v, double* part_g, const int* done,
                                                          const int32_t* blk_prob) {
   if (done && done[blk_prob[blockIdx.x]]) return;
   __shared__ double red[4][64];
   const int64_t* b = blk + 3 * blockIdx.x;
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int64_t c1 = b[2];
+  const double* p = part + b[1] + lane;
+  const int n = int(b[2]);
   double s0 = 0.0, s1 = 0.0;
-  int64_t c = b[1] + g;
-  for (; c + 4 < c1; c += 8) {
-    s0 += part[csr[c] + lane];
-    s1 += part[csr[c + 4] + lane];
+  int k = g;
+  for (; k + 4 < n; k += 8) {
+    s0 += p[64 * k];
+    s1 += p[64 * (k + 4)];
   }
-  if (c < c1) s0 += part[csr[c] + lane];
+  if (k < n) s0 += p[64 * k];
   red[g][lane] = s0 + s1;
   __syncthreads();
   if (g == 0) {
@@ -1236,7 +1239,7 @@ void gemv_sym_impl(const MT* M, const SymGemv& g, const double* xg, double* v, d
                           done, tp);
   else
     hipLaunchKernelGGL(k_gemv_sym<MT>, dim3(g.ntask), dim3(256), 0, s, M, g.task, xg, g.part, done, tp);
-  hipLaunchKernelGGL(k_gemv_sym_reduce, dim3(g.nblk), dim3(256), 0, s, g.part, g.blk, g.csr, xg, v, part_g, done, bp);
+  hipLaunchKernelGGL(k_gemv_sym_reduce, dim3(g.nblk), dim3(256), 0, s, g.part, g.blk, xg, v, part_g, done, bp);
 }
 void gemv_sym(const double* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
               hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {

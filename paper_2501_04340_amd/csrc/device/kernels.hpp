@@ -90,21 +90,24 @@ void gemv(const float* M, const int64_t* task, int64_t ntask, int64_t max_ld, co
           hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // Symmetric variant: reads each lower 64x64 tile of the dense blocks once (the
 // diagonal tile whole), SYM_TILES tiles of one tile row per task, writing a row
-// partial for y_I and a column partial per tile for y_t (t < I); the reduction
-// sums each 64-slot output block's partials in list order and forms part_g per
-// block.  Variant index GEMV_SYM (after the row-streaming shapes).
+// partial for y_I and a column partial per tile for y_t (t < I) into the output
+// blocks' contiguous partial lists; the reduction sums each 64-slot block's
+// partials in list order and forms part_g per block.  Variant index GEMV_SYM
+// (after the row-streaming shapes).
 constexpr int SYM_TILES = 8;
 constexpr int GEMV_SYM = GEMV_VARIANTS;
 constexpr int GEMV_SHAPES = GEMV_VARIANTS + 1;
+constexpr int SYM_TASK = 6 + SYM_TILES;  // int64 per task
 struct SymGemv {
-  const int64_t* task = nullptr;      // [matrix offset of tile (I, t0), ld, ncols, slot I, slot t0, partial offset]
+  // task: [matrix offset of tile (I, t0), ld, ncols, slot of tile row I, slot of tile column t0,
+  //        destination of the row partial, destinations of the SYM_TILES column partials (-1: none)]
+  const int64_t* task = nullptr;
   const int32_t* task_prob = nullptr;
   int64_t ntask = 0;
-  const int64_t* blk = nullptr;       // [first slot, csr begin, csr end] per output block of 64 slots
+  const int64_t* blk = nullptr;       // [first slot, first partial, partial count] per output block of 64 slots
   const int32_t* blk_prob = nullptr;
   int64_t nblk = 0;
-  const int64_t* csr = nullptr;       // offsets of the 64-entry partials of each block
-  double* part = nullptr;
+  double* part = nullptr;             // each block's partials contiguous: 64 entries apiece
 };
 void gemv_sym(const double* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
               hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
