@@ -408,6 +408,12 @@ def main():
     S.solve(rtol=args.rtol)
     kt = S.kernel_times()
     S.set_profiling(False)
+    # condition number of the preconditioned interface operator (Section 4)
+    # from the recorded PCG coefficients of one more (untimed) solve
+    S.record_pcg(4000)
+    S.solve(rtol=args.rtol)
+    lo, hi = S.condition()
+    S.record_pcg(0)
     ms_per_step = (t_end - t_begin) * 1e3 / args.steps
     iters = int(np.median([s["iters"] for s in stats]))
     applies = sum(s["f_applies"] for s in stats)
@@ -491,6 +497,7 @@ def main():
         "factor_ms": factor_ms,
         "solve_ms": solve_ms,
         "pcg_iters": iters,
+        "kappa_lanczos": hi / lo,
         "f_applies_per_s": applies / pcg_s if pcg_s > 0 else None,
         "rel_residual": float(stats[-1]["rel_residual"]),
         "factor_tflops": info["flops"] / (factor_ms * 1e-3) / 1e12,
