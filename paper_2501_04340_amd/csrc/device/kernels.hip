@@ -710,15 +710,16 @@ __device__ inline double multi_wave_sum(double (&v)[R]) {
 }
 
 template <typename MT>
-__global__ __launch_bounds__(256) void k_gemv_sym(const MT* M, const int64_t* task, const double* xg, double* part,
+__global__ __launch_bounds__(64 * SYM_WAVES) void k_gemv_sym(const MT* M, const int64_t* task, const double* xg, double* part,
                                                   const int* done, const int32_t* task_prob) {
   if (done && done[task_prob[blockIdx.x]]) return;
   using V = Vec16<MT>;
   using T = typename V::T;
   constexpr int NJ = SYM_TILES * 64 / (64 * V::N);  // vectors per lane and row
-  constexpr int RB = 16 / NJ;                        // rows per batch: 16 vectors in flight per lane
+  constexpr int RW = 64 / SYM_WAVES;                 // rows per wave
+  constexpr int RB = 16 / NJ < RW ? 16 / NJ : RW;    // rows per batch: up to 16 vectors in flight per lane
   __shared__ double rows[64];
-  __shared__ double cred[4][SYM_TILES * 64];
+  __shared__ double cred[SYM_WAVES][SYM_TILES * 64];
   const int64_t* tk = task + SYM_TASK * blockIdx.x;
   const MT* A = M + tk[0];
   const int64_t ld = tk[1];
@@ -738,11 +739,11 @@ __global__ __launch_bounds__(256) void k_gemv_sym(const MT* M, const int64_t* ta
   }
   constexpr int SH = RB == 16 ? 2 : RB == 8 ? 3 : RB == 4 ? 4 : RB == 2 ? 5 : 6;  // lane >> SH = row of a batch
 #pragma unroll 1
-  for (int i = 0; i < 16; i += RB) {
+  for (int i = 0; i < RW; i += RB) {
     T mv[RB][NJ];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      const T* row = reinterpret_cast<const T*>(A + (16 * q + i + r) * ld);
+      const T* row = reinterpret_cast<const T*>(A + (RW * q + i + r) * ld);
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
         mv[r][j] = V::N * (lane + 64 * j) < ncols ? __builtin_nontemporal_load(row + lane + 64 * j) : T(0);
@@ -750,7 +751,7 @@ __global__ __launch_bounds__(256) void k_gemv_sym(const MT* M, const int64_t* ta
     double racc[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      const double xa = xr[16 * q + i + r];
+      const double xa = xr[RW * q + i + r];
       double sacc = 0.0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
@@ -762,16 +763,21 @@ __global__ __launch_bounds__(256) void k_gemv_sym(const MT* M, const int64_t* ta
     }
     // the batch's row sums: lane l ends with row l >> SH of the batch
     const double rsum = multi_wave_sum<RB>(racc);
-    if ((lane & ((1 << SH) - 1)) == 0) rows[16 * q + i + (lane >> SH)] = rsum;
+    if ((lane & ((1 << SH) - 1)) == 0) rows[RW * q + i + (lane >> SH)] = rsum;
   }
 #pragma unroll
   for (int j = 0; j < NJ; ++j)
 #pragma unroll
     for (int e = 0; e < V::N; ++e) cred[q][V::N * (lane + 64 * j) + e] = cacc[j][e];
   __syncthreads();
-  for (int c = threadIdx.x; c < ncols; c += 256) {
+  for (int c = threadIdx.x; c < ncols; c += 64 * SYM_WAVES) {
     const int64_t dst = tk[6 + (c >> 6)];
-    if (dst >= 0) part[dst + (c & 63)] = (cred[0][c] + cred[1][c]) + (cred[2][c] + cred[3][c]);
+    if (dst >= 0) {
+      double sum = 0.0;
+#pragma unroll
+      for (int g = 0; g < SYM_WAVES; g += 2) sum += cred[g][c] + cred[g + 1][c];
+      part[dst + (c & 63)] = sum;
+    }
   }
   if (threadIdx.x < 64) part[tk[5] + threadIdx.x] = rows[threadIdx.x];
 }
@@ -1235,10 +1241,10 @@ void gemv_sym_impl(const MT* M, const SymGemv& g, const double* xg, double* v, d
   // the events bracket the tile kernel (the streaming part); the block
   // reduction is a separate small launch
   if (ev_start)
-    hipExtLaunchKernelGGL(k_gemv_sym<MT>, dim3(g.ntask), dim3(256), 0, s, ev_start, ev_stop, 0, M, g.task, xg, g.part,
-                          done, tp);
+    hipExtLaunchKernelGGL(k_gemv_sym<MT>, dim3(g.ntask), dim3(64 * SYM_WAVES), 0, s, ev_start, ev_stop, 0, M, g.task,
+                          xg, g.part, done, tp);
   else
-    hipLaunchKernelGGL(k_gemv_sym<MT>, dim3(g.ntask), dim3(256), 0, s, M, g.task, xg, g.part, done, tp);
+    hipLaunchKernelGGL(k_gemv_sym<MT>, dim3(g.ntask), dim3(64 * SYM_WAVES), 0, s, M, g.task, xg, g.part, done, tp);
   hipLaunchKernelGGL(k_gemv_sym_reduce, dim3(g.nblk), dim3(256), 0, s, g.part, g.blk, xg, v, part_g, done, bp);
 }
 void gemv_sym(const double* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,

@@ -95,6 +95,7 @@ void gemv(const float* M, const int64_t* task, int64_t ntask, int64_t max_ld, co
 // partials in list order and forms part_g per block.  Variant index GEMV_SYM
 // (after the row-streaming shapes).
 constexpr int SYM_TILES = 8;
+constexpr int SYM_WAVES = 8;  // waves per task (64 / SYM_WAVES rows each)
 constexpr int GEMV_SYM = GEMV_VARIANTS;
 constexpr int GEMV_SHAPES = GEMV_VARIANTS + 1;
 constexpr int SYM_TASK = 6 + SYM_TILES;  // int64 per task
