@@ -611,36 +611,40 @@ void pcg_iteration_prec(ieti_handle* h, int par, bool fp32) {
 
 // Autotuner of the interface GEMV: every launch shape is timed on the
 // handle's own blocks, alternating the operator and preconditioner blocks as
-// the PCG does (so the caches see the same working set), 2 warm-up and 5
-// timed pairs each, HIP events on the solve stream; the fastest is kept.
-// Runs once per handle and precision, after the first factorisation, so
-// later solves are repeatable.
+// the PCG does (so the caches see the same working set): 2 warm-up and 5
+// timed pairs per shape, HIP events on the solve stream, in three rounds
+// over all shapes; a shape's time is its fastest round (the shapes differ by
+// a few per cent, less than the spread of a single round) and the fastest
+// shape is kept.  Runs once per handle and precision, after the first
+// factorisation, so later solves are repeatable.
 template <typename MT>
 int tune_gemv(ieti_handle* h, const MT* Ma, const MT* Mb, int fp32) {
   namespace D = ieti::dev;
   hipStream_t s = h->stream;
-  float best = 1e30f;
+  float tmin[D::GEMV_SHAPES];
+  for (int v = 0; v < D::GEMV_SHAPES; ++v) tmin[v] = 1e30f;
+  for (int round = 0; round < 3; ++round)
+    for (int v = 0; v < D::GEMV_SHAPES; ++v) {
+      auto launch = [&]() {
+        launch_gemv(h, Ma, v, h->xgp.ptr, h->v.ptr, nullptr);
+        launch_gemv(h, Mb, v, h->xgr.ptr, h->v.ptr, nullptr);
+      };
+      launch();
+      launch();
+      HIP_TRY(hipEventRecord(h->ev0, s));
+      for (int k = 0; k < 5; ++k) launch();
+      HIP_TRY(hipEventRecord(h->ev1, s));
+      HIP_TRY(hipEventSynchronize(h->ev1));
+      int rc = check_launch();
+      if (rc) return rc;
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      tmin[v] = std::min(tmin[v], ms / 10.f);
+    }
   int bv = D::GEMV_DEFAULT;
   for (int v = 0; v < D::GEMV_SHAPES; ++v) {
-    auto launch = [&]() {
-      launch_gemv(h, Ma, v, h->xgp.ptr, h->v.ptr, nullptr);
-      launch_gemv(h, Mb, v, h->xgr.ptr, h->v.ptr, nullptr);
-    };
-    launch();
-    launch();
-    HIP_TRY(hipEventRecord(h->ev0, s));
-    for (int k = 0; k < 5; ++k) launch();
-    HIP_TRY(hipEventRecord(h->ev1, s));
-    HIP_TRY(hipEventSynchronize(h->ev1));
-    int rc = check_launch();
-    if (rc) return rc;
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-    h->gtime[fp32][v] = ms / 10.f;
-    if (ms < best) {
-      best = ms;
-      bv = v;
-    }
+    h->gtime[fp32][v] = tmin[v];
+    if (tmin[v] < tmin[bv]) bv = v;
   }
   if (h->gvar[fp32] != bv) drop_graphs(h);
   h->gvar[fp32] = bv;

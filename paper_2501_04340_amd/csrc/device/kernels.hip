@@ -923,6 +923,21 @@ __global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* r
   __shared__ double acc4[4][64];
   const int64_t* P = pd + PD_N * pid;
   const int64_t n_gp = P[PD_NGP];
+  // the row's operands do not depend on the reductions: their loads go first
+  int64_t row0;
+  const int64_t nrow = blk_rows(blk, pd, b, &row0);
+  const bool act = int64_t(threadIdx.x) < nrow;
+  const int64_t row = row0 + threadIdx.x;
+  int64_t s0 = 0, s1 = 0;
+  double vd = 0.0, pr = 0.0, lr = 0.0, rv = 0.0;
+  if (act) {
+    s0 = row_src[2 * row];
+    s1 = row_src[2 * row + 1];
+    vd = v[s0] - v[s1];
+    pr = p[row];
+    lr = lam[row];
+    rv = r[row];
+  }
   const double tt = coarse_from_partials(part_t + P[PD_PT], n_gp, int(P[PD_B1] - P[PD_B0]), tl, acc4);
   const double tt_all = block_sum256(tt, red);
   const double pq = reduce_partials_fast(part_g + P[PD_T0 + 2 * gt], int(P[PD_T0 + 2 * gt + 1] - P[PD_T0 + 2 * gt]),
@@ -937,16 +952,12 @@ __global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* r
     return;
   }
   const double alpha = sc[par] / pq;
-  int64_t row0;
-  const int64_t nrow = blk_rows(blk, pd, b, &row0);
   double rr = 0.0;
-  if (int64_t(threadIdx.x) < nrow) {
-    const int64_t row = row0 + threadIdx.x;
-    const int64_t s0 = row_src[2 * row], s1 = row_src[2 * row + 1];
-    double q = v[s0] - v[s1];
+  if (act) {
+    double q = vd;
     if (n_gp > 0) q += coarse_row(H, P, row, tl);
-    lam[row] += alpha * p[row];
-    const double rn = r[row] - alpha * q;
+    lam[row] = lr + alpha * pr;
+    const double rn = rv - alpha * q;
     r[row] = rn;
     rr = rn * rn;
     xg_r[s0] = ds ? ds[s0] * rn : rn;
@@ -973,6 +984,19 @@ __global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* r
   const int64_t* P = pd + PD_N * pid;
   double* sc = scal + 8 * pid;
   const bool first = b == P[PD_B0];
+  // the row's operands do not depend on the reductions: their loads go first
+  int64_t row0;
+  const int64_t nrow = blk_rows(blk, pd, b, &row0);
+  const bool act = int64_t(threadIdx.x) < nrow;
+  const int64_t row = row0 + threadIdx.x;
+  int64_t s0 = 0, s1 = 0;
+  double zz = 0.0, pold = 0.0;
+  if (act) {
+    s0 = row_src[2 * row];
+    s1 = row_src[2 * row + 1];
+    zz = ds ? ds[s0] * w[s0] - ds[s1] * w[s1] : w[s0] - w[s1];
+    if (!init) pold = p[row];
+  }
   const double rz = reduce_partials_fast(part_g + P[PD_T0 + 2 * gt], int(P[PD_T0 + 2 * gt + 1] - P[PD_T0 + 2 * gt]),
                                          red);
   if (!init) {
@@ -994,16 +1018,11 @@ __global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* r
     sc[3] = beta;
     if (hist && !init && iters[pid] - 1 < hcap) hist[(pid * hcap + iters[pid] - 1) * 2 + 1] = beta;
   }
-  int64_t row0;
-  const int64_t nrow = blk_rows(blk, pd, b, &row0);
   double pv = 0.0;
-  if (int64_t(threadIdx.x) < nrow) {
-    const int64_t row = row0 + threadIdx.x;
-    const int64_t s0 = row_src[2 * row], s1 = row_src[2 * row + 1];
-    const double zz = ds ? ds[s0] * w[s0] - ds[s1] * w[s1] : w[s0] - w[s1];
+  if (act) {
     z[row] = zz;
     // the first direction is z itself: p holds no value yet (not even a finite one)
-    pv = init ? zz : zz + beta * p[row];
+    pv = init ? zz : zz + beta * pold;
     p[row] = pv;
     xg_p[s0] = pv;
     xg_p[s1] = -pv;
