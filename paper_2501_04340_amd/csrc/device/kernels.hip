@@ -818,19 +818,19 @@ __global__ void k_to_float(const double* in, float* out, int64_t n) {
     out[i] = float(in[i]);
 }
 
-// Sum of n partials by one block with several loads in flight per thread;
-// the result (fixed summation order) is returned to every thread.
+// Sum of n partials by one block: the first 3072 are loaded all at once (12
+// per thread, one memory round trip), any further ones in a loop; the result
+// (fixed summation order) is returned to every thread.
 __device__ inline double reduce_partials_fast(const double* part, int n, double* red) {
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int i = threadIdx.x;
-  for (; i + 768 < n; i += 1024) {
-    a0 += part[i];
-    a1 += part[i + 256];
-    a2 += part[i + 512];
-    a3 += part[i + 768];
+  double a[12];
+#pragma unroll
+  for (int u = 0; u < 12; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    a[u] = i < n ? part[i] : 0.0;
   }
-  for (; i < n; i += 256) a0 += part[i];
-  return block_sum256((a0 + a1) + (a2 + a3), red);
+  double s = (((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]))) + ((a[8] + a[9]) + (a[10] + a[11]));
+  for (int i = threadIdx.x + 3072; i < n; i += 256) s += part[i];
+  return block_sum256(s, red);
 }
 
 // t[c] = sum_b part_t[b][c] into LDS, 64 columns per pass, four thread
