@@ -710,14 +710,14 @@ __device__ inline double multi_wave_sum(double (&v)[R]) {
 }
 
 template <typename MT>
-__global__ __launch_bounds__(64 * SYM_WAVES) void k_gemv_sym(const MT* M, const int64_t* task, const double* xg, double* part,
+__global__ __launch_bounds__(64 * SYM_WAVES, 2) void k_gemv_sym(const MT* M, const int64_t* task, const double* xg, double* part,
                                                   const int* done, const int32_t* task_prob) {
   if (done && done[task_prob[blockIdx.x]]) return;
   using V = Vec16<MT>;
   using T = typename V::T;
   constexpr int NJ = SYM_TILES * 64 / (64 * V::N);  // vectors per lane and row
   constexpr int RW = 64 / SYM_WAVES;                 // rows per wave
-  constexpr int RB = 16 / NJ < RW ? 16 / NJ : RW;    // rows per batch: up to 16 vectors in flight per lane
+  constexpr int RB = 4 < RW ? 4 : RW;                // rows per batch (4 NJ vectors in flight per lane)
   __shared__ double rows[64];
   __shared__ double cred[SYM_WAVES][SYM_TILES * 64];
   const int64_t* tk = task + SYM_TASK * blockIdx.x;
