@@ -365,6 +365,13 @@ int ieti_nn_train(ieti_nn* nn, const ieti_nn_train_opts* opts, double* epoch_los
 /* pred [n][n_out] for host inputs X [n][n_in], C [n][n_comb]. */
 int ieti_nn_predict(ieti_nn* nn, const float* X, const float* C, int64_t n, float* pred);
 void ieti_nn_destroy(ieti_nn* nn);
+/* Write the architecture and parameters (FP32) to a file / create a network
+ * on the current device from such a file.  IETI_ERR_INVALID_ARG if the file
+ * cannot be opened, is not a network file of this library (tag, sizes and
+ * parameter count are checked before any device allocation) or is
+ * truncated.  Adam's state is not stored: a loaded network starts afresh. */
+int ieti_nn_save(const ieti_nn* nn, const char* path);
+int ieti_nn_load(const char* path, ieti_nn** out);
 
 /* How the solver forms the network's rows and places its predictions: one
  * row per facet f (e.g. one interface facet of two subdomains), features

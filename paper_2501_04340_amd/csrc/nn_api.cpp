@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -332,6 +333,59 @@ int ieti_nn_predict(ieti_nn* nn, const float* X, const float* C, int64_t n, floa
 }
 
 void ieti_nn_destroy(ieti_nn* nn) { delete nn; }
+
+// File: 8-byte tag, the five int32 sizes of ieti_nn_arch, the int64
+// parameter count, the parameters as FP32 (host byte order).
+static const char kNNTag[8] = {'I', 'E', 'T', 'I', 'N', 'N', '0', '1'};
+
+int ieti_nn_save(const ieti_nn* nn, const char* path) {
+  if (!nn || !path) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  std::vector<float> theta(size_t(nn->mlp.n_params));
+  int rc = ieti_nn_get_params(nn, theta.data());
+  if (rc) return rc;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(IETI_ERR_INVALID_ARG, std::string("cannot open ") + path + " for writing");
+  const ieti_nn_arch& a = nn->mlp.arch;
+  const int32_t sizes[5] = {a.n_in, a.n_hidden, a.n_layers, a.n_comb, a.n_out};
+  const int64_t n = nn->mlp.n_params;
+  bool ok = std::fwrite(kNNTag, 1, 8, f) == 8 && std::fwrite(sizes, sizeof(int32_t), 5, f) == 5 &&
+            std::fwrite(&n, sizeof(int64_t), 1, f) == 1 &&
+            std::fwrite(theta.data(), sizeof(float), theta.size(), f) == theta.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(IETI_ERR_INVALID_ARG, std::string("writing ") + path + " failed");
+  return IETI_OK;
+}
+
+int ieti_nn_load(const char* path, ieti_nn** out) {
+  if (!path || !out) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(IETI_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  char tag[8];
+  int32_t sizes[5];
+  int64_t n = -1;
+  bool ok = std::fread(tag, 1, 8, f) == 8 && std::equal(tag, tag + 8, kNNTag) &&
+            std::fread(sizes, sizeof(int32_t), 5, f) == 5 && std::fread(&n, sizeof(int64_t), 1, f) == 1;
+  ieti_nn_arch a{sizes[0], sizes[1], sizes[2], sizes[3], sizes[4]};
+  ieti::nn::Mlp check;
+  if (!ok || check.init(&a) != IETI_OK || check.n_params != n) {
+    std::fclose(f);
+    return fail(IETI_ERR_INVALID_ARG, std::string(path) + " is not a network file of this library");
+  }
+  std::vector<float> theta(static_cast<size_t>(n));
+  ok = std::fread(theta.data(), sizeof(float), theta.size(), f) == theta.size();
+  std::fclose(f);
+  if (!ok) return fail(IETI_ERR_INVALID_ARG, std::string(path) + " is truncated");
+  ieti_nn* nn = nullptr;
+  int rc = ieti_nn_create(&a, &nn);
+  if (!rc) rc = ieti_nn_set_params(nn, theta.data());
+  if (rc) {
+    ieti_nn_destroy(nn);
+    return rc;
+  }
+  *out = nn;
+  return IETI_OK;
+}
 
 }  // extern "C"
 

@@ -118,7 +118,7 @@ EXPORTS = [
     "ieti_last_error", "ieti_set_coefficients", "ieti_set_warm_start", "ieti_nn_create", "ieti_nn_num_params",
     "ieti_nn_set_params", "ieti_nn_get_params", "ieti_nn_set_data", "ieti_nn_loss_grad", "ieti_nn_train",
     "ieti_nn_predict", "ieti_nn_destroy", "ieti_get_gemv_tuning", "ieti_assemble_batch", "ieti_get_batch_info",
-    "ieti_batch_of", "ieti_record_pcg", "ieti_get_pcg_coefficients",
+    "ieti_batch_of", "ieti_record_pcg", "ieti_get_pcg_coefficients", "ieti_nn_save", "ieti_nn_load",
 ]
 
 
@@ -168,6 +168,8 @@ def load_library():
     lib.ieti_assemble_batch.argtypes = [P(Problem), C.c_int32, P(C.c_void_p)]
     lib.ieti_batch_of.argtypes = [P(C.c_void_p), C.c_int32, P(C.c_void_p)]
     lib.ieti_record_pcg.argtypes = [C.c_void_p, C.c_int32]
+    lib.ieti_nn_save.argtypes = [C.c_void_p, C.c_char_p]
+    lib.ieti_nn_load.argtypes = [C.c_char_p, P(C.c_void_p)]
     lib.ieti_get_pcg_coefficients.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double), P(C.c_int32)]
     lib.ieti_get_batch_info.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_double)]
     lib.ieti_get_gemv_tuning.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_float)]
@@ -515,6 +517,28 @@ class NN:
         if getattr(self, "h", None):
             self.lib.ieti_nn_destroy(self.h)
             self.h = None
+
+    def save(self, path):
+        """Architecture and parameters to a file (``ieti_nn_save``)."""
+        _check(self.lib, self.lib.ieti_nn_save(self.h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path):
+        """Network on the current device from a file written by ``save``."""
+        self = cls.__new__(cls)
+        self.lib = load_library()
+        h = C.c_void_p()
+        _check(self.lib, self.lib.ieti_nn_load(os.fsencode(path), C.byref(h)))
+        self.h = h
+        a = np.zeros(5, np.int32)
+        with open(path, "rb") as f:
+            f.seek(8)
+            a[:] = np.frombuffer(f.read(20), dtype=np.int32)
+        self.arch = tuple(int(x) for x in a)
+        n = C.c_int64()
+        _check(self.lib, self.lib.ieti_nn_num_params(self.h, C.byref(n)))
+        self.n_params = int(n.value)
+        return self
 
     def __del__(self):
         try:

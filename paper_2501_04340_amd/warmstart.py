@@ -158,6 +158,28 @@ class RingWarmStart:
         self.net.set_data(Xn, Cc.reshape(-1, self.n_comb), T.reshape(-1, self.n_out) / self.out_scale)
         return self.net.train(epochs, lr, batch=batch, seed=seed)
 
+    # ---- persistence
+    def save(self, prefix):
+        """The trained network (``prefix + '.net'``, the library's file) and
+        the normalisation of its rows (``prefix + '.npz'``).  The facet layout
+        itself follows from the problem and is rebuilt on load."""
+        self.net.save(str(prefix) + ".net")
+        np.savez(str(prefix) + ".npz", shift=self.shift, scale=self.scale, out_scale=self.out_scale,
+                 window=self.window, hidden=self.hidden, layers=self.layers)
+
+    @classmethod
+    def load(cls, solver, prob, prefix):
+        """A warm start saved by ``save`` for the same ring layout."""
+        z = np.load(str(prefix) + ".npz", allow_pickle=False)
+        self = cls(solver, prob, window=int(z["window"]), hidden=int(z["hidden"]), layers=int(z["layers"]))
+        net = NN.load(str(prefix) + ".net")
+        if net.arch != (self.n_feat, self.hidden, self.layers, self.n_comb, self.n_out):
+            raise ValueError("the saved network does not fit this problem's layout")
+        self.net = net
+        self.shift, self.scale = z["shift"], z["scale"]
+        self.out_scale = float(z["out_scale"])
+        return self
+
     def attach(self, solver=None):
         (solver or self.solver).set_warm_start(self.net, self.feat_patch, self.shift, self.scale, self.comb_patch,
                                                self.out_row, self.out_sign, self.out_scale)

@@ -168,3 +168,36 @@ def test_layout_mismatch_is_rejected(ring):
     other = NN(W.n_feat + 1, 8, 1, W.n_comb, W.n_out)
     with pytest.raises(Exception, match="INVALID_ARG"):
         S.set_warm_start(other, W.feat_patch, W.shift, W.scale, W.comb_patch, W.out_row, W.out_sign, 1.0)
+
+
+def test_network_file_round_trip(ietilib, tmp_path):
+    """ieti_nn_save / ieti_nn_load: the loaded network has the same
+    architecture and parameters bit for bit, and predicts the same values."""
+    from paper_2501_04340_amd import NN
+    net, theta, X, Cc, T = _setup(seed=5)
+    path = tmp_path / "net.bin"
+    net.save(path)
+    back = NN.load(path)
+    assert back.arch == net.arch and back.n_params == net.n_params
+    assert np.array_equal(back.params(), net.params())
+    assert np.array_equal(back.predict(X, Cc), net.predict(X, Cc))
+
+
+def test_saved_warm_start_drives_the_solver_identically(ring, tmp_path):
+    """A ring warm start written to files and loaded into a fresh layout
+    gives the same initial multipliers, and the solver the same result."""
+    from paper_2501_04340_amd.warmstart import RingWarmStart
+    prob, S, W, held = ring
+    nu, scale = held[2]
+    W.save(tmp_path / "ring")
+    W2 = RingWarmStart.load(S, prob, tmp_path / "ring")
+    assert np.array_equal(W2.predict_lambda(nu, scale), W.predict_lambda(nu, scale))
+    S.set_coefficients(nu, scale)
+    S.factor()
+    a1, st1 = S.solve(rtol=1e-8, warm_start=True)
+    W2.attach()
+    try:
+        a2, st2 = S.solve(rtol=1e-8, warm_start=True)
+    finally:
+        W.attach()
+    assert st1["iters"] == st2["iters"] and np.array_equal(a1, a2)

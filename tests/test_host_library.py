@@ -111,3 +111,25 @@ def test_plan_accounts_for_every_tile(ietilib):
     assert info["tile"] == 64
     assert 0 < info["flops"] <= info["dense_flops"] * 1.0000001
     assert info["sum_nI2"] == 8 * 72 * 72
+
+
+def test_network_file_is_checked_before_any_device_work(ietilib, tmp_path):
+    """ieti_nn_load rejects a missing, foreign, inconsistent or truncated
+    file from its header alone (no device allocation happens, so this runs
+    without a GPU)."""
+    import ctypes as C
+    import struct
+    lib = ietilib
+    out = C.c_void_p()
+    assert lib.ieti_nn_load(str(tmp_path / "missing.bin").encode(), C.byref(out)) == -1
+    p = tmp_path / "foreign.bin"
+    p.write_bytes(b"NOTANET!" + bytes(28))
+    assert lib.ieti_nn_load(str(p).encode(), C.byref(out)) == -1
+    # right tag, sizes of a 2x3x1 network (1 layer of 3, 1 coefficient, 2 outputs) but a wrong count
+    good_n = 3 * (2 + 1) + 2 * (3 + 1)
+    p.write_bytes(b"IETINN01" + struct.pack("<5iq", 2, 3, 1, 1, 2, good_n + 1) + bytes(4 * good_n))
+    assert lib.ieti_nn_load(str(p).encode(), C.byref(out)) == -1
+    # consistent header, parameters cut short
+    p.write_bytes(b"IETINN01" + struct.pack("<5iq", 2, 3, 1, 1, 2, good_n) + bytes(4 * (good_n - 1)))
+    assert lib.ieti_nn_load(str(p).encode(), C.byref(out)) == -1
+    assert out.value is None
