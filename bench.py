@@ -38,21 +38,32 @@ WORKLOADS = {
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "cube64_hbm_traffic_pmc.md")
-KERNELS_SRC = os.path.join(ROOT, "paper_2501_04340_amd", "csrc", "device", "kernels.hip")
+# the per-launch traffic depends on the kernels and on the factorisation's task lists
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2501_04340_amd", "csrc", "device", "kernels.hip"),
+                   os.path.join(ROOT, "paper_2501_04340_amd", "csrc", "host", "plan.cpp")]
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` ("k_update_multi", "k_gemv_sym<double>"
     or "k_gemv<double>") from the committed PMC summary, or None when the
-    kernel source changed since the counters were taken."""
-    import hashlib
+    kernel source or the task-list builder changed since the counters were
+    taken."""
     import re
     try:
         text = open(TRAFFIC_PROFILE).read()
-        sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+        sha = sources_sha256()
     except OSError:
         return None
-    m = re.search(r"traffic_per_launch " + re.escape(kernel) + r": .*total_bytes=(\d+) kernels_hip_sha256=([0-9a-f]+)",
+    m = re.search(r"traffic_per_launch " + re.escape(kernel) + r": .*total_bytes=(\d+) sources_sha256=([0-9a-f]+)",
                   text)
     if not m or m.group(2) != sha:
         return None

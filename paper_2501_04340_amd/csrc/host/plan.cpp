@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <numeric>
 
 namespace ieti {
@@ -65,6 +66,9 @@ void nested_dissection(const std::vector<std::vector<int32_t>>& adj, const std::
 }
 
 int64_t round_up(int64_t x, int64_t t) { return (x + t - 1) / t * t; }
+
+// pending contributions at which a target tile's deferred update is issued
+constexpr int64_t UPDATE_DEFER = 8;
 
 }  // namespace
 
@@ -260,6 +264,21 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
   plan.upd_ptr.assign(1, 0);
   plan.copy_ptr.assign(1, 0);
   const double T3 = double(T) * T * T;
+  // Deferred updates: the contribution L_ij L_lj^T of column j to the target
+  // tile (i, l) may be applied at any level from level(j) up to the last level
+  // before the target is read (level(l) - 1 for a column of r, the level
+  // before the S copy for r_V contributions to the r_I block, the
+  // subdomain's last level for the trailing p / E_I columns).  Contributions
+  // are held back until UPDATE_DEFER of them are pending or the deadline is
+  // reached, so that a target tile is read and written once per batch of
+  // contributions instead of once per contributing level.  The decision
+  // depends on the subdomain alone, so a subdomain gets the same tasks in a
+  // batch as on its own.
+  struct Pending {
+    std::vector<int64_t> cols;  // contributing columns in order of arrival
+    int64_t deadline = 0;
+  };
+  std::vector<std::map<int64_t, Pending>> pend(S);  // per subdomain, keyed by target i * nt + l
   for (int64_t lv = 0; lv < n_levels; ++lv) {
     for (int k = 0; k < S; ++k) {
       const SubPlan& sp = plan.sub[k];
@@ -275,8 +294,7 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
                                   {o, sp.S_off + r0 * sp.nIp + c0, sp.S_off + c0 * sp.nIp + r0, sp.nIp, i == l ? 1 : 0});
           }
       }
-      // targets of this level's updates, each with its contributing columns
-      std::vector<std::pair<int64_t, int64_t>> contrib;  // (target index i*nt+l, column j)
+      auto& P = pend[k];
       for (int64_t j : cols[k][lv]) {
         plan.potrf_task.insert(plan.potrf_task.end(), {off(j, j), int64_t(k), inv_off[k][j]});
         plan.flops += T3 / 3.0;
@@ -289,26 +307,30 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
         }
         for (size_t x = 0; x < rows.size(); ++x)
           for (size_t y = 0; y <= x; ++y) {
-            contrib.emplace_back(rows[x] * nt + rows[y], j);
+            const int64_t i = rows[x], l = rows[y];
+            int64_t dl = l < sp.ntr ? lev[k][l] - 1 : sp.nlev - 1;
+            if (j < sp.ntV && l >= sp.ntV && l < sp.ntr) dl = std::min<int64_t>(dl, sp.levS - 1);
+            auto it = P.find(i * nt + l);
+            if (it == P.end()) {
+              it = P.emplace(i * nt + l, Pending{}).first;
+              it->second.deadline = dl;
+            }
+            it->second.cols.push_back(j);
+            it->second.deadline = std::min(it->second.deadline, dl);
             plan.flops += 2.0 * T3;
           }
       }
-      std::stable_sort(contrib.begin(), contrib.end(),
-                       [](const std::pair<int64_t, int64_t>& a, const std::pair<int64_t, int64_t>& b) {
-                         return a.first < b.first;
-                       });
-      size_t q = 0;
-      while (q < contrib.size()) {
-        size_t e = q;
-        const int64_t tgt = contrib[q].first, i = tgt / nt, l = tgt % nt;
-        const int64_t p0 = int64_t(plan.upd_pair.size() / 2);
-        while (e < contrib.size() && contrib[e].first == tgt) {
-          const int64_t j = contrib[e].second;
-          plan.upd_pair.insert(plan.upd_pair.end(), {off(i, j), off(l, j)});
-          ++e;
+      for (auto it = P.begin(); it != P.end();) {
+        const Pending& q = it->second;
+        if (int64_t(q.cols.size()) < UPDATE_DEFER && q.deadline > lv) {
+          ++it;
+          continue;
         }
-        plan.upd_task.insert(plan.upd_task.end(), {off(i, l), p0, int64_t(e - q)});
-        q = e;
+        const int64_t i = it->first / nt, l = it->first % nt;
+        const int64_t p0 = int64_t(plan.upd_pair.size() / 2);
+        for (int64_t j : q.cols) plan.upd_pair.insert(plan.upd_pair.end(), {off(i, j), off(l, j)});
+        plan.upd_task.insert(plan.upd_task.end(), {off(i, l), p0, int64_t(q.cols.size())});
+        it = P.erase(it);
       }
     }
     plan.potrf_ptr.push_back(int64_t(plan.potrf_task.size() / 3));
@@ -316,6 +338,11 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
     plan.upd_ptr.push_back(int64_t(plan.upd_task.size() / 3));
     plan.copy_ptr.push_back(int64_t(plan.copy_task.size() / 5));
   }
+  for (int k = 0; k < S; ++k)
+    if (!pend[k].empty()) {
+      err = Error{IETI_ERR_STATE, "plan: deferred tile updates left at the end of the schedule"};
+      return err.code;
+    }
   plan.n_update_tasks = int64_t(plan.upd_pair.size() / 2);
   // ---------------------------------------------------------------- extraction lists
   for (int k = 0; k < S; ++k) {
