@@ -23,10 +23,33 @@ namespace {
 
 constexpr int T = TILE;
 
+// Value of lane `src` (wave-uniform) of a double, through two readlanes.
+__device__ inline double readlane_f64(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), src);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// A double moved across lanes by the DPP pattern CTRL (both halves alike).
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Sum over the 64 lanes of a wave (every lane active), result in every lane:
+// pairs, quads, half-rows and rows of 16 through DPP moves inside the VALU
+// (each step adds two values that every lane of the group sees in the same
+// order up to commutation), then the four row sums through readlanes.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 // Sum over a 256-thread block, result valid in every thread (fixed order).
@@ -68,13 +91,6 @@ __global__ void k_scatter(double* pool, const int64_t* dst, const double* val, i
 // transposed LDS copy and multiplying by the stored reciprocal pivots.  A
 // non-positive pivot records the subdomain (1-based) in err and continues
 // with pivot 1.
-// Value of lane `src` (wave-uniform) of a double, through two readlanes.
-__device__ inline double readlane_f64(double v, int src) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffLL), src);
-  const int hi = __builtin_amdgcn_readlane(int(b >> 32), src);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
 
 __global__ __launch_bounds__(256) void k_potrf_inv(double* pool, double* inv, const int64_t* task, int* err) {
   __shared__ __align__(16) double Lt[T][T + 2];  // Lt[j][i] = L[i][j]; later X staging

@@ -67,8 +67,12 @@ void nested_dissection(const std::vector<std::vector<int32_t>>& adj, const std::
 
 int64_t round_up(int64_t x, int64_t t) { return (x + t - 1) / t * t; }
 
-// pending contributions at which a target tile's deferred update is issued
+// pending contributions at which a target tile's deferred update is issued:
+// before a subdomain's dense r_I tail (many targets per level, throughput
+// bound) and inside it (one column per level, few targets: the task's
+// pairs run in series, so long tasks stretch every level)
 constexpr int64_t UPDATE_DEFER = 8;
+constexpr int64_t UPDATE_DEFER_TAIL = 4;
 
 }  // namespace
 
@@ -322,7 +326,7 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
       }
       for (auto it = P.begin(); it != P.end();) {
         const Pending& q = it->second;
-        if (int64_t(q.cols.size()) < UPDATE_DEFER && q.deadline > lv) {
+        if (int64_t(q.cols.size()) < (lv >= sp.levS ? UPDATE_DEFER_TAIL : UPDATE_DEFER) && q.deadline > lv) {
           ++it;
           continue;
         }
