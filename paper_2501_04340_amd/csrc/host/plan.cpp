@@ -225,6 +225,28 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
     for (int64_t t = 0; t < sp.nI; ++t) put(a0 + t, sp.nVp + t, -1);
     voff += s.indptr[s.n_loc];
   }
+  // Destination order, so that consecutive threads of the scatter write
+  // consecutive pool entries (CSR order writes one entry per 512-byte tile
+  // column): two stable counting passes, by offset inside the tile, then by
+  // tile.  Destinations are distinct, so the order changes no value.
+  {
+    const size_t n = plan.scatter_dst.size();
+    const int64_t TT = int64_t(T) * T, ntile = (pool + TT - 1) / TT;
+    std::vector<int64_t> d2(n), s2(n);
+    auto pass = [n](const std::vector<int64_t>& dk, const std::vector<int64_t>& sk, std::vector<int64_t>& dd,
+                    std::vector<int64_t>& sd, int64_t nb, auto key) {
+      std::vector<int64_t> cnt(size_t(nb) + 1, 0);
+      for (size_t i = 0; i < n; ++i) ++cnt[size_t(key(dk[i])) + 1];
+      for (int64_t b = 0; b < nb; ++b) cnt[size_t(b) + 1] += cnt[size_t(b)];
+      for (size_t i = 0; i < n; ++i) {
+        const int64_t q = cnt[size_t(key(dk[i]))]++;
+        dd[size_t(q)] = dk[i];
+        sd[size_t(q)] = sk[i];
+      }
+    };
+    pass(plan.scatter_dst, plan.scatter_src, d2, s2, TT, [TT](int64_t d) { return d % TT; });
+    pass(d2, s2, plan.scatter_dst, plan.scatter_src, ntile, [TT](int64_t d) { return d / TT; });
+  }
   // ---------------------------------------------------------------- level schedule
   // Column j of the tile factor depends on every column k < j with a tile
   // (j, k); level(j) = 1 + max level(k).  Columns of one level are
