@@ -320,8 +320,8 @@ int upload(ieti_handle* h) {
   // symmetric GEMV: per subdomain with nt = n_Ip / 64 tile rows, tasks (I, t0) over the lower tiles
   // t0 .. min(t0 + SYM_TILES, I + 1) - 1 of tile row I.  Output block J (64 slots) keeps its partials
   // contiguous: the row partials of its tasks (t0 ascending), then the column partials of tiles (I, J),
-  // I > J (I ascending); its value is their sum in that order.  The tasks are launched largest first
-  // (fewer tiles at the end of the launch).
+  // I > J (I ascending); its value is their sum in that order.  The launch order (below) only decides
+  // which workgroup runs a task, never where its partials go.
   std::vector<int64_t> sym_task_h, sym_blk_h, bstart(n_prob + 1, 0);
   std::vector<int32_t> sym_tprob_h, sym_bprob_h;
   {
@@ -358,9 +358,45 @@ int upload(ieti_handle* h) {
           h->sym_elems += double(64 * 64) * double(ntile);
         }
     }
-    for (int64_t n = ST; n >= 1; --n) {
-      sym_task_h.insert(sym_task_h.end(), by_size[n].begin(), by_size[n].end());
-      sym_tprob_h.insert(sym_tprob_h.end(), prob_by_size[n].begin(), prob_by_size[n].end());
+    // Launch order.  The tile kernel holds two workgroups per CU; the first
+    // n_cu workgroups take one CU each and the next n_cu the second slots in
+    // the same order.  When the tasks fit in those two rounds, round one takes
+    // the n_cu largest tasks and slot k of round two the task that evens out
+    // CU k's tiles (the largest remaining task goes with the smallest
+    // first-round task), with empty records (0 columns: the workgroup exits)
+    // where a CU gets no second task.  Otherwise the tasks go largest first.
+    {
+      const size_t rec = size_t(6 + ST);
+      std::vector<std::pair<int64_t, int64_t>> order;  // (tile count, index within its size class)
+      for (int64_t n = ST; n >= 1; --n)
+        for (size_t i = 0; i < prob_by_size[n].size(); ++i) order.emplace_back(n, int64_t(i));
+      int ncu = 0;
+      if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) ncu = 0;
+      const size_t nc = size_t(ncu > 0 ? ncu : 0), nt_all = order.size();
+      auto put = [&](const std::pair<int64_t, int64_t>& o) {
+        const auto& v = by_size[size_t(o.first)];
+        sym_task_h.insert(sym_task_h.end(), v.begin() + o.second * int64_t(rec), v.begin() + (o.second + 1) * int64_t(rec));
+        sym_tprob_h.push_back(prob_by_size[size_t(o.first)][size_t(o.second)]);
+      };
+      if (nc > 0 && nt_all > nc && nt_all <= 2 * nc) {
+        for (size_t k = 0; k < nc; ++k) put(order[k]);
+        std::vector<size_t> cu(nc);
+        for (size_t k = 0; k < nc; ++k) cu[k] = k;
+        std::stable_sort(cu.begin(), cu.end(), [&](size_t a, size_t b) { return order[a].first < order[b].first; });
+        std::vector<int64_t> second(nc, -1);
+        for (size_t j = nc; j < nt_all; ++j) second[cu[j - nc]] = int64_t(j);
+        for (size_t k = 0; k < nc; ++k) {
+          if (second[k] >= 0) {
+            put(order[size_t(second[k])]);
+          } else {
+            sym_task_h.insert(sym_task_h.end(), rec, int64_t(0));
+            for (size_t c = 0; c < size_t(ST); ++c) sym_task_h[sym_task_h.size() - size_t(ST) + c] = -1;
+            sym_tprob_h.push_back(0);
+          }
+        }
+      } else {
+        for (const auto& o : order) put(o);
+      }
     }
     for (int p = 1; p <= n_prob; ++p) bstart[p] = std::max(bstart[p], bstart[p - 1]);
     UP(sym_task, sym_task_h);

@@ -728,15 +728,17 @@ __device__ inline double multi_wave_sum(double (&v)[R]) {
 template <typename MT>
 __global__ __launch_bounds__(64 * SYM_WAVES, 2) void k_gemv_sym(const MT* M, const int64_t* task, const double* xg, double* part,
                                                   const int* done, const int32_t* task_prob) {
+  const int64_t* tk = task + SYM_TASK * blockIdx.x;
+  if (tk[2] == 0) return;  // empty record: a CU without a second task
   if (done && done[task_prob[blockIdx.x]]) return;
   using V = Vec16<MT>;
   using T = typename V::T;
+  static_assert(SYM_TILES % V::N == 0, "a lane's 16-byte vectors must tile the task's columns exactly");
   constexpr int NJ = SYM_TILES * 64 / (64 * V::N);  // vectors per lane and row
   constexpr int RW = 64 / SYM_WAVES;                 // rows per wave
   constexpr int RB = 4 < RW ? 4 : RW;                // rows per batch (4 NJ vectors in flight per lane)
   __shared__ double rows[64];
   __shared__ double cred[SYM_WAVES][SYM_TILES * 64];
-  const int64_t* tk = task + SYM_TASK * blockIdx.x;
   const MT* A = M + tk[0];
   const int64_t ld = tk[1];
   const int ncols = int(tk[2]);
