@@ -813,6 +813,8 @@ __global__ __launch_bounds__(256) void k_gemv_sym_reduce(const double* part, con
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const double* p = part + b[1] + lane;
   const int n = int(b[2]);
+  const int64_t slot = b[0] + lane;
+  const double xs = g == 0 ? xg[slot] : 0.0;  // needed after the sum: loaded with the partials
   double s0 = 0.0, s1 = 0.0;
   int k = g;
   for (; k + 4 < n; k += 8) {
@@ -823,10 +825,9 @@ __global__ __launch_bounds__(256) void k_gemv_sym_reduce(const double* part, con
   red[g][lane] = s0 + s1;
   __syncthreads();
   if (g == 0) {
-    const int64_t slot = b[0] + lane;
     const double val = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
     v[slot] = val;
-    const double d = wave_sum(val * xg[slot]);
+    const double d = wave_sum(val * xs);
     if (lane == 0) part_g[blockIdx.x] = d;
   }
 }
