@@ -100,6 +100,8 @@ struct ieti_handle {
   DBuf<double> dscale;                     // per interface slot: scaling of the preconditioner's jump operator
   int scaling = IETI_SCALE_IDENTITY;
   int* pflags_h = nullptr;                 // pinned host copy: done[n_prob], iters[n_prob]
+  int* pchk_h = nullptr;                   // pinned: two slots of done[n_prob] for the convergence checks
+  hipEvent_t ev_chk[2] = {nullptr, nullptr};
   // per-problem results of the last solve
   std::vector<int> p_iters, p_outer, p_status, p_warm;
   std::vector<double> p_relres, p_relres0;
@@ -146,6 +148,9 @@ struct ieti_handle {
     piters.release();
     dscale.release();
     if (pflags_h) (void)hipHostFree(pflags_h);
+    if (pchk_h) (void)hipHostFree(pchk_h);
+    for (auto e : ev_chk)
+      if (e) (void)hipEventDestroy(e);
     glob2loc.release();
     flags.release();
     if (flags_h) (void)hipHostFree(flags_h);
@@ -249,6 +254,8 @@ int upload(ieti_handle* h) {
     HIP_TRY(hipEventCreate(&h->ev0));
     HIP_TRY(hipEventCreate(&h->ev1));
     HIP_TRY(hipEventCreate(&h->ev2));
+    HIP_TRY(hipEventCreateWithFlags(&h->ev_chk[0], hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&h->ev_chk[1], hipEventDisableTiming));
   }
   if (!h->flags_h) HIP_TRY(hipHostMalloc(&h->flags_h, 8 * sizeof(int)));
   int rc = 0;
@@ -502,6 +509,9 @@ int upload(ieti_handle* h) {
   if (h->pflags_h) (void)hipHostFree(h->pflags_h);
   h->pflags_h = nullptr;
   HIP_TRY(hipHostMalloc(&h->pflags_h, 2 * size_t(n_prob) * sizeof(int)));
+  if (h->pchk_h) (void)hipHostFree(h->pchk_h);
+  h->pchk_h = nullptr;
+  HIP_TRY(hipHostMalloc(&h->pchk_h, 2 * size_t(n_prob) * sizeof(int)));
   if ((rc = dalloc(h->lam_acc, mm))) return rc;
   if ((rc = dalloc(h->rtrue, mm))) return rc;
   drop_graphs(h);
@@ -921,7 +931,16 @@ int run_pcg(ieti_handle* h, const std::vector<double>& tol2, const std::vector<d
     int rc = capture_graph(h, fp32);
     if (rc) return rc;
   }
+  // Convergence checks every `every2` iterations: the done flags are copied
+  // to one of two pinned slots behind an event, and a check is read only
+  // after the next interval's iterations are queued, so the GPU never waits
+  // for the host.  Iterations queued after a problem finishes exit at once
+  // (done flag), and the iteration count is kept on the device.  A profiled
+  // run reads each check at once instead, so that every timed launch is one
+  // that did its work.
   const int every2 = std::max(2, every + (every & 1));
+  const bool overlap = !h->profiling;
+  int slot = 0, pending = -1;
   for (int it = 0; it < maxit; it += 2) {
     if (use_graph) {
       HIP_TRY(hipGraphLaunch(fp32 ? h->graph_exec32 : h->graph_exec, s));
@@ -930,11 +949,23 @@ int run_pcg(ieti_handle* h, const std::vector<double>& tol2, const std::vector<d
       pcg_iteration_prec(h, 1, fp32);
     }
     if ((it + 2) % every2 == 0 || it + 2 >= maxit) {
-      HIP_TRY(hipMemcpyAsync(h->pflags_h, h->pdone.ptr, n_prob * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      bool fin = true;
-      for (int p = 0; p < n_prob && fin; ++p) fin = h->pflags_h[p] != 0;
-      if (fin) break;
+      if (pending >= 0) {
+        HIP_TRY(hipEventSynchronize(h->ev_chk[pending]));
+        bool fin = true;
+        for (int p = 0; p < n_prob && fin; ++p) fin = h->pchk_h[pending * n_prob + p] != 0;
+        if (fin) break;
+      }
+      HIP_TRY(hipMemcpyAsync(h->pchk_h + slot * n_prob, h->pdone.ptr, n_prob * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(h->ev_chk[slot], s));
+      pending = slot;
+      slot ^= 1;
+      if (!overlap) {
+        HIP_TRY(hipEventSynchronize(h->ev_chk[pending]));
+        bool fin = true;
+        for (int p = 0; p < n_prob && fin; ++p) fin = h->pchk_h[pending * n_prob + p] != 0;
+        if (fin) break;
+        pending = -1;
+      }
     }
   }
   int rc = check_launch();
