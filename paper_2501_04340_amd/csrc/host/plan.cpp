@@ -570,9 +570,13 @@ void refill_values(const Model& m, Plan& plan) {
     const int64_t k = std::upper_bound(voff.begin(), voff.end(), src) - voff.begin() - 1;
     return vals[k][src - voff[k]];
   };
+  // the list is in destination order, so its sources are read out of order:
+  // the entries are independent and split over the host threads
   plan.scatter_val.resize(plan.scatter_src.size());
-  for (size_t i = 0; i < plan.scatter_src.size(); ++i)
-    plan.scatter_val[i] = plan.scatter_src[i] < 0 ? 1.0 : value(plan.scatter_src[i]);
+  const int64_t ns = int64_t(plan.scatter_src.size());
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < ns; ++i)
+    plan.scatter_val[size_t(i)] = plan.scatter_src[size_t(i)] < 0 ? 1.0 : value(plan.scatter_src[size_t(i)]);
   plan.b_aug0.assign(plan.r_total, 0.0);
   for (size_t k = 0; k < m.sd.size(); ++k) {
     const Subdomain& s = m.sd[k];
