@@ -119,8 +119,14 @@ __global__ __launch_bounds__(256) void k_potrf_inv(double* pool, double* inv, co
       const double akk = readlane_f64(a[kk], k);
       const bool ok = akk > 0.0;
       bad = bad || !ok;
-      const double piv = sqrt(ok ? akk : 1.0);
-      const double rp = 1.0 / piv;
+      // 1/sqrt(a) from the hardware estimate and two Newton steps
+      // (y <- y (3 - a y^2) / 2), pivot sqrt(a) = a / sqrt(a): fewer dependent
+      // instructions on the pivot's chain than an IEEE square root and division
+      const double av = ok ? akk : 1.0;
+      double rp = __builtin_amdgcn_rsq(av);
+      rp = rp * (1.5 - 0.5 * av * rp * rp);
+      rp = rp * (1.5 - 0.5 * av * rp * rp);
+      const double piv = av * rp;
       const double lik = (lane == k) ? piv : (lane > k ? a[kk] * rp : 0.0);
       a[kk] = lik;
       col[lane] = lik;
