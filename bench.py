@@ -367,6 +367,10 @@ def main():
     ap.add_argument("--nn-epochs", type=int, default=300)
     ap.add_argument("--nn-hidden", type=int, default=256)
     ap.add_argument("--nn-lr", type=float, default=1e-3)
+    ap.add_argument("--gemv-variant", type=int, default=None, metavar="V",
+                    help="force the interface GEMV launch shape (0-11 row streaming, 12 symmetric) instead of "
+                         "the autotuner's choice; for profiled runs, where tracing adds a cost to every launch "
+                         "and so favours shapes with fewer launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU sharding "
@@ -397,12 +401,13 @@ def main():
     prob = configs.make_config(args.workload)
     t0 = time.perf_counter()
     S = Solver(prob)
+    fkw = {} if args.gemv_variant is None else {"gemv_variant": args.gemv_variant}
     log(f"host assembly {time.perf_counter() - t0:.1f}s sizes {S.sizes()}")
     info = S.plan_info()
     # the solution stays in HBM (a device buffer), as the inputs do
     a_dev = torch.empty(S.n_edges, dtype=torch.float64, device="cuda")
     for w in range(args.warmup):
-        S.factor()
+        S.factor(**fkw)
         st = S.solve_device(a_dev.data_ptr(), rtol=args.rtol)
         log(f"warmup {w}: iters {st['iters']} factor {st['t_factor_s'] * 1e3:.1f}ms solve {st['t_solve_s'] * 1e3:.1f}ms")
     torch.cuda.synchronize()
@@ -410,7 +415,7 @@ def main():
     t_begin = time.perf_counter()
     for k in range(args.steps):
         t_k = time.perf_counter()
-        S.factor()
+        S.factor(**fkw)
         st = S.solve_device(a_dev.data_ptr(), rtol=args.rtol)  # returns after a stream synchronisation
         step_ms.append((time.perf_counter() - t_k) * 1e3)
         stats.append(st)
@@ -419,7 +424,7 @@ def main():
     # kernel durations: one more step with launch events on every GEMV and
     # update launch (direct launches; the timed steps replay a hipGraph)
     S.set_profiling(True)
-    S.factor()
+    S.factor(**fkw)
     S.solve(rtol=args.rtol)
     kt = S.kernel_times()
     S.set_profiling(False)
@@ -462,20 +467,20 @@ def main():
     # mixed-precision variant of the same step (FP32-stored interface blocks in
     # the inner PCG, outer refinement on the FP64 residual)
     from paper_2501_04340_amd.ietidp import PREC_FP64, PREC_MIXED
-    S.factor(precision=PREC_MIXED)
+    S.factor(precision=PREC_MIXED, **fkw)
     S.solve(rtol=args.rtol)
     torch.cuda.synchronize()
     mstats = []
     t0m = time.perf_counter()
     for k in range(args.steps):
-        S.factor(precision=PREC_MIXED)
+        S.factor(precision=PREC_MIXED, **fkw)
         st_m = S.solve_device(a_dev.data_ptr(), rtol=args.rtol)
         mstats.append(st_m)
     torch.cuda.synchronize()
     ms_mixed = (time.perf_counter() - t0m) * 1e3 / args.steps
     chosen32, tune_ms32 = S.gemv_tuning()
     S.set_profiling(True)
-    S.factor(precision=PREC_MIXED)
+    S.factor(precision=PREC_MIXED, **fkw)
     _, st_mp = S.solve(rtol=args.rtol)
     kt_m = S.kernel_times()
     S.set_profiling(False)
@@ -485,19 +490,19 @@ def main():
     from paper_2501_04340_amd.ietidp import SCALE_STIFFNESS
     scaled = {}
     for tag, prec in (("plain_fp64_rho_scaling", PREC_FP64), ("mixed_rho_scaling", PREC_MIXED)):
-        S.factor(precision=prec, scaling=SCALE_STIFFNESS)
+        S.factor(precision=prec, scaling=SCALE_STIFFNESS, **fkw)
         S.solve(rtol=args.rtol)
         torch.cuda.synchronize()
         t0s = time.perf_counter()
         for k in range(args.steps):
-            S.factor(precision=prec, scaling=SCALE_STIFFNESS)
+            S.factor(precision=prec, scaling=SCALE_STIFFNESS, **fkw)
             st_s = S.solve_device(a_dev.data_ptr(), rtol=args.rtol)
         torch.cuda.synchronize()
         ms_s = (time.perf_counter() - t0s) * 1e3 / args.steps
         scaled[tag] = {"tts_ms": ms_s, "pcg_iters": int(st_s["iters"]), "rel_residual_fp64": float(st_s["rel_residual"]),
                        "speedup_vs_plain": ms_per_step / ms_s}
         log(f"{tag}: {ms_s:.2f} ms/step, iters {st_s['iters']}")
-    S.factor(precision=PREC_FP64)
+    S.factor(precision=PREC_FP64, **fkw)
     mfac = float(np.median([x["t_factor_s"] for x in mstats])) * 1e3
     msol = float(np.median([x["t_solve_s"] for x in mstats])) * 1e3
     mpcg = float(np.median([x["t_pcg_s"] for x in mstats])) * 1e3

@@ -353,18 +353,28 @@ __global__ __launch_bounds__(256) void k_update_multi(double* pool, const int64_
 }
 
 // Copy (scaled) tiles into dense row-major blocks; optional mirrored copy.
-__global__ void k_copy_tiles(const double* pool, const int64_t* task, double scale, double* dst) {
+// The tile is staged in LDS so that both the direct and the mirrored writes
+// run along rows of the destination (consecutive threads, consecutive entries).
+__global__ __launch_bounds__(256) void k_copy_tiles(const double* pool, const int64_t* task, double scale,
+                                                    double* dst) {
+  __shared__ double tl[T][T + 1];  // tl[b][a] = entry (a, b) of the tile
   const int64_t* tk = task + 5 * blockIdx.x;
   const double* t = pool + tk[0];
   const int64_t d0 = tk[1], dt = tk[2], ld = tk[3];
   const bool diag = tk[4] != 0;
+  for (int idx = threadIdx.x; idx < T * T; idx += blockDim.x) tl[idx >> 6][idx & (T - 1)] = scale * t[idx];
+  __syncthreads();
+  // entry (a, b) to row a, column b: b runs along the threads
   for (int idx = threadIdx.x; idx < T * T; idx += blockDim.x) {
-    const int a = idx & (T - 1), b = idx >> 6;
-    if (diag && a < b) continue;
-    const double v = scale * t[idx];
-    dst[d0 + a * ld + b] = v;
-    if (dt >= 0 && !(diag && a == b)) dst[dt + b * ld + a] = v;
+    const int a = idx >> 6, b = idx & (T - 1);
+    if (!(diag && a < b)) dst[d0 + a * ld + b] = tl[b][a];
   }
+  // entry (a, b) to row b, column a of the mirror: a runs along the threads
+  if (dt >= 0)
+    for (int idx = threadIdx.x; idx < T * T; idx += blockDim.x) {
+      const int b = idx >> 6, a = idx & (T - 1);
+      if (!(diag && a <= b)) dst[dt + b * ld + a] = tl[b][a];
+    }
 }
 
 // Triangular-solve tiles are read straight into registers: lane l of wave q
