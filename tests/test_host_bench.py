@@ -1,0 +1,81 @@
+"""Host-side logic of bench.py: the one-GPU guard and how the measured HBM
+traffic is taken from the committed PMC summary (and dropped once the kernel
+source or the task-list builder has changed since the counters were taken)."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stdout
+    assert "{" not in r.stdout  # no JSON line
+
+
+def _write_sources(tmp_path, texts):
+    files = []
+    for i, t in enumerate(texts):
+        p = tmp_path / f"src{i}.txt"
+        p.write_bytes(t)
+        files.append(str(p))
+    return files
+
+
+def test_sources_hash_covers_every_file_in_order(tmp_path, monkeypatch):
+    files = _write_sources(tmp_path, [b"kernel source", b"plan source"])
+    monkeypatch.setattr(bench, "TRAFFIC_SOURCES", files)
+    want = hashlib.sha256(b"kernel source" + b"plan source").hexdigest()
+    assert bench.sources_sha256() == want
+    (tmp_path / "src1.txt").write_bytes(b"plan source, changed")
+    assert bench.sources_sha256() != want
+
+
+def test_traffic_read_only_for_matching_sources(tmp_path, monkeypatch):
+    files = _write_sources(tmp_path, [b"a", b"b"])
+    monkeypatch.setattr(bench, "TRAFFIC_SOURCES", files)
+    sha = bench.sources_sha256()
+    prof = tmp_path / "traffic.md"
+    prof.write_text(
+        "header\n"
+        f"traffic_per_launch k_update_multi: fetch_bytes=10 write_bytes=5 total_bytes=15 sources_sha256={sha}\n"
+        f"traffic_per_launch k_gemv_sym<double>: fetch_bytes=7 write_bytes=1 total_bytes=8 sources_sha256={sha}\n"
+        "traffic_per_launch k_gemv<double>: fetch_bytes=7 write_bytes=1 total_bytes=9 sources_sha256=" + "0" * 64 + "\n")
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
+    assert bench.measured_traffic("k_update_multi") == 15.0
+    assert bench.measured_traffic("k_gemv_sym<double>") == 8.0
+    # stale hash, and a kernel the summary does not hold
+    assert bench.measured_traffic("k_gemv<double>") is None
+    assert bench.measured_traffic("k_trsm_inv") is None
+    # any change to the sources invalidates every figure
+    (tmp_path / "src0.txt").write_bytes(b"a2")
+    assert bench.measured_traffic("k_update_multi") is None
+
+
+def test_traffic_missing_profile(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "absent.md"))
+    assert bench.measured_traffic("k_update_multi") is None
+
+
+def test_committed_summary_parses():
+    """The committed summary carries a figure for both kernels bench.py
+    reports, each with a 64-digit source hash."""
+    import re
+    text = open(bench.TRAFFIC_PROFILE).read()
+    for k in ("k_update_multi", "k_gemv_sym<double>"):
+        m = re.search(r"traffic_per_launch " + re.escape(k) + r": .*total_bytes=(\d+) sources_sha256=([0-9a-f]{64})",
+                      text)
+        assert m, k
+        assert int(m.group(1)) > 0
+
+
+if __name__ == "__main__":
+    sys.exit(pytest.main([__file__, "-q"]))
