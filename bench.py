@@ -52,10 +52,11 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` ("k_update_multi", "k_gemv_sym<double>"
-    or "k_gemv<double>") from the committed PMC summary, or None when the
-    kernel source or the task-list builder changed since the counters were
+    or "k_gemv<double>") on `workload` from the committed PMC summary, or None
+    when the summary holds no figure for that kernel on that workload, or when
+    the kernel source or the task-list builder changed since the counters were
     taken."""
     import re
     try:
@@ -63,11 +64,12 @@ def measured_traffic(kernel):
         sha = sources_sha256()
     except OSError:
         return None
-    m = re.search(r"traffic_per_launch " + re.escape(kernel) + r": .*total_bytes=(\d+) sources_sha256=([0-9a-f]+)",
-                  text)
-    if not m or m.group(2) != sha:
-        return None
-    return float(m.group(1))
+    pat = (r"traffic_per_launch " + re.escape(kernel)
+           + r": workload=(\S+) .*total_bytes=(\d+) sources_sha256=([0-9a-f]+)")
+    for m in re.finditer(pat, text):
+        if m.group(1) == workload and m.group(3) == sha:
+            return float(m.group(2))
+    return None
 
 
 def log(msg):
@@ -450,7 +452,7 @@ def main():
     gemv_ms = kt["gemv_ms"] / max(kt["gemv_launches"], 1)
     gemv_ach = kt["gemv_bytes"] / (gemv_ms * 1e-3) / 1e9
     roof_gemv = {"kernel": gemv_name, "bound": "hbm", "achieved": gemv_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": gemv_ach / HBM_PEAK_GBS, "traffic": measured_traffic(gemv_name),
+                 "frac": gemv_ach / HBM_PEAK_GBS, "traffic": measured_traffic(gemv_name, args.workload),
                  "avg_launch_ms": gemv_ms, "bytes_per_launch": kt["gemv_bytes"],
                  "launches_per_step": kt["gemv_launches"], "ms_per_step": kt["gemv_ms"]}
     flops_per_task = 2.0 * 64 ** 3
@@ -458,7 +460,7 @@ def main():
     upd_flops = kt["update_tasks"] / max(kt["update_launches"], 1) * flops_per_task
     upd_ach = upd_flops / (upd_avg * 1e-3) / 1e12
     roof_upd = {"kernel": "k_update_multi", "bound": "mfma", "achieved": upd_ach, "peak": FP64_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": upd_ach / FP64_MFMA_PEAK_TFLOPS, "traffic": measured_traffic("k_update_multi"),
+                "unit": "TFLOP/s", "frac": upd_ach / FP64_MFMA_PEAK_TFLOPS, "traffic": measured_traffic("k_update_multi", args.workload),
                 "avg_launch_ms": upd_avg, "flops_per_launch": upd_flops,
                 "launches_per_step": kt["update_launches"], "ms_per_step": kt["update_ms"]}
     roof = dict(roof_gemv if kt["gemv_ms"] >= kt["update_ms"] else roof_upd)

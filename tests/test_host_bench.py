@@ -1,6 +1,7 @@
 """Host-side logic of bench.py: the one-GPU guard and how the measured HBM
-traffic is taken from the committed PMC summary (and dropped once the kernel
-source or the task-list builder has changed since the counters were taken)."""
+traffic is taken from the committed PMC summary (only for the workload the
+counters were taken on, and dropped once the kernel source or the task-list
+builder has changed since)."""
 import hashlib
 import os
 import subprocess
@@ -46,32 +47,40 @@ def test_traffic_read_only_for_matching_sources(tmp_path, monkeypatch):
     prof = tmp_path / "traffic.md"
     prof.write_text(
         "header\n"
-        f"traffic_per_launch k_update_multi: fetch_bytes=10 write_bytes=5 total_bytes=15 sources_sha256={sha}\n"
-        f"traffic_per_launch k_gemv_sym<double>: fetch_bytes=7 write_bytes=1 total_bytes=8 sources_sha256={sha}\n"
-        "traffic_per_launch k_gemv<double>: fetch_bytes=7 write_bytes=1 total_bytes=9 sources_sha256=" + "0" * 64 + "\n")
+        f"traffic_per_launch k_update_multi: workload=cube64 fetch_bytes=10 write_bytes=5 total_bytes=15 "
+        f"sources_sha256={sha}\n"
+        f"traffic_per_launch k_update_multi: workload=cube256 fetch_bytes=20 write_bytes=5 total_bytes=25 "
+        f"sources_sha256={sha}\n"
+        f"traffic_per_launch k_gemv_sym<double>: workload=cube64 fetch_bytes=7 write_bytes=1 total_bytes=8 "
+        f"sources_sha256={sha}\n"
+        "traffic_per_launch k_gemv<double>: workload=cube64 fetch_bytes=7 write_bytes=1 total_bytes=9 "
+        "sources_sha256=" + "0" * 64 + "\n")
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
-    assert bench.measured_traffic("k_update_multi") == 15.0
-    assert bench.measured_traffic("k_gemv_sym<double>") == 8.0
+    assert bench.measured_traffic("k_update_multi", "cube64") == 15.0
+    assert bench.measured_traffic("k_update_multi", "cube256") == 25.0
+    assert bench.measured_traffic("k_gemv_sym<double>", "cube64") == 8.0
+    # a workload the counters were not taken on
+    assert bench.measured_traffic("k_gemv_sym<double>", "cube256") is None
     # stale hash, and a kernel the summary does not hold
-    assert bench.measured_traffic("k_gemv<double>") is None
-    assert bench.measured_traffic("k_trsm_inv") is None
+    assert bench.measured_traffic("k_gemv<double>", "cube64") is None
+    assert bench.measured_traffic("k_trsm_inv", "cube64") is None
     # any change to the sources invalidates every figure
     (tmp_path / "src0.txt").write_bytes(b"a2")
-    assert bench.measured_traffic("k_update_multi") is None
+    assert bench.measured_traffic("k_update_multi", "cube64") is None
 
 
 def test_traffic_missing_profile(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "absent.md"))
-    assert bench.measured_traffic("k_update_multi") is None
+    assert bench.measured_traffic("k_update_multi", "cube64") is None
 
 
 def test_committed_summary_parses():
-    """The committed summary carries a figure for both kernels bench.py
-    reports, each with a 64-digit source hash."""
+    """The committed summary carries a cube64 figure for both kernels
+    bench.py reports, each with a 64-digit source hash."""
     import re
     text = open(bench.TRAFFIC_PROFILE).read()
     for k in ("k_update_multi", "k_gemv_sym<double>"):
-        m = re.search(r"traffic_per_launch " + re.escape(k) + r": .*total_bytes=(\d+) sources_sha256=([0-9a-f]{64})",
+        m = re.search(r"traffic_per_launch " + re.escape(k) + r": workload=cube64 .*total_bytes=(\d+) sources_sha256=([0-9a-f]{64})",
                       text)
         assert m, k
         assert int(m.group(1)) > 0
