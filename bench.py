@@ -159,6 +159,7 @@ def ring_warm_start(args):
     from workloads import configs
 
     torch.cuda.set_device(0)
+    fkw = {} if args.gemv_variant is None else {"gemv_variant": args.gemv_variant}
     prob = configs.ring576()
     t0 = time.perf_counter()
     S = Solver(prob)
@@ -190,7 +191,7 @@ def ring_warm_start(args):
         for name, (prec, warm) in variants.items():
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            S.factor(precision=prec)
+            S.factor(precision=prec, **fkw)
             _, st = S.solve(rtol=args.rtol, warm_start=warm)
             torch.cuda.synchronize()
             r = res[name]
@@ -208,7 +209,7 @@ def ring_warm_start(args):
         if (i - n_train + 1) % 16 == 0:
             log(f"held-out {i - n_train + 1}/{n_test}: " + ", ".join(
                 f"{k} {np.median(v['tts_ms']):.1f}ms/{np.mean(v['iters']):.1f}it" for k, v in res.items()))
-    S.factor(precision=PREC_FP64)
+    S.factor(precision=PREC_FP64, **fkw)
     summ = {}
     for k, v in res.items():
         summ[k] = {"tts_ms_p50": float(np.median(v["tts_ms"])), "tts_ms_p99": float(np.percentile(v["tts_ms"], 99)),
@@ -247,6 +248,7 @@ def stream_batches(args):
     from workloads import configs
 
     torch.cuda.set_device(0)
+    fkw = {} if args.gemv_variant is None else {"gemv_variant": args.gemv_variant}
     n, chunk = args.stream_count, args.stream_chunk
     lat_single, lat_bplain, lat_bmixed = [], [], []
     t_single = t_bplain = t_bmixed = 0.0
@@ -265,11 +267,11 @@ def stream_batches(args):
         # each problem alone, plain FP64 (first factor autotunes; one warm-up solve)
         outs = []
         for S in singles:
-            S.factor()
+            S.factor(**fkw)
             S.solve(rtol=args.rtol)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            S.factor()
+            S.factor(**fkw)
             a, st = S.solve(rtol=args.rtol)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
@@ -283,11 +285,11 @@ def stream_batches(args):
         for S in singles:
             S.close()
         for prec, lat in ((PREC_FP64, lat_bplain), (PREC_MIXED, lat_bmixed)):
-            B.factor(precision=prec)
+            B.factor(precision=prec, **fkw)
             B.solve(rtol=args.rtol, maxit=3000)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            B.factor(precision=prec)
+            B.factor(precision=prec, **fkw)
             a, st = B.solve(rtol=args.rtol, maxit=3000)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
@@ -305,7 +307,7 @@ def stream_batches(args):
             # a finished problem's GEMV tasks are skipped, so the bytes of the
             # profiled solve are sum_p bytes_p * (2 iters_p + 1): one
             # preconditioner application to start, two applications per iteration
-            B.factor()
+            B.factor(**fkw)
             B.set_profiling(True)
             B.solve(rtol=args.rtol, maxit=3000)
             kt = B.kernel_times()
@@ -316,7 +318,8 @@ def stream_batches(args):
             total_bytes = float(sum(bp * (2 * it + 1) for bp, it in zip(bytes_p, its)))
             ach = total_bytes / (kt["gemv_ms"] * 1e-3) / 1e9
             kname = "k_gemv_sym<double>" if bsym else "k_gemv<double>"
-            roof = {"kernel": f"{kname} (autotuned shape), one batch of "
+            shape = "autotuned shape" if args.gemv_variant is None else "pinned shape"
+            roof = {"kernel": f"{kname} ({shape}), one batch of "
                               f"{len(ids)} problems", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
                     "avg_launch_ms": kt["gemv_ms"] / max(kt["gemv_launches"], 1),
