@@ -36,7 +36,8 @@ extern "C" {
 enum {
   IETI_OK = 0,
   IETI_ERR_INVALID_ARG = -1,      /* bad sizes, version mismatch, NULL pointer */
-  IETI_ERR_PARTITION = -2,        /* a subdomain is empty or not face-connected */
+  IETI_ERR_PARTITION = -2,        /* a subdomain is empty, not connected through patch faces, or not
+                                     simply connected (Section 2's assumptions); message names it */
   IETI_ERR_TREE = -3,             /* tree restricted to the Dirichlet boundary is not a tree (Section 3) */
   IETI_ERR_NOT_SPD = -4,          /* non-positive pivot in a local factorisation; message names the subdomain */
   IETI_ERR_BREAKDOWN = -5,        /* PCG breakdown: p^T F p <= 0 */
@@ -142,7 +143,38 @@ typedef struct {
   double rel_residual0;  /* ||b - F lambda_0|| / ||b|| of the initial multipliers used */
   int32_t warm_start;    /* 1 = network prediction used, -1 = prediction rejected, 0 = not asked */
   int32_t reserved;
+  double pcg_bytes;      /* algorithmic bytes moved by the PCG phase (see ieti_problem_stats),
+                            summed over the problems; divided by t_pcg_s: the solve phase's
+                            algorithmic bandwidth */
 } ieti_stats;
+
+/* Per-problem results of the last solve of a handle.  The algorithmic byte
+ * model of one application of the interface operator F (Eq. intProb) or of
+ * the preconditioner M_D (Eq. DirPrec) with s-byte interface-block entries
+ * (s = 8 FP64, 4 FP32) is
+ *   M:  s sum_k n_I,k (n_I,k + 1) / 2  +  16 sum_k n_I,k  +  24 m_r
+ *   F:  the same  +  16 sum_k n_I,k n_p,k  +  8 n_gp^2
+ * (each symmetric interface block's lower triangle once; the interface
+ * vectors in and out; three multiplier vectors; the local primal coupling
+ * in and out and the coarse factor).  pcg_bytes = sum over the solve's
+ * applications of these figures. */
+typedef struct {
+  int32_t iters;          /* PCG iterations (MIXED: summed over the inner solves) */
+  int32_t outer_iters;    /* iterative-refinement steps (MIXED) */
+  int32_t status;         /* IETI_OK or IETI_ERR_NOT_CONVERGED */
+  int32_t warm_start;     /* as in ieti_stats */
+  int32_t f_applies[2];   /* applications of F with [0] FP64, [1] FP32 interface blocks */
+  int32_t m_applies[2];   /* applications of M_D, same split */
+  double rel_residual;    /* ||b - F lambda|| / ||b|| at exit (FP64 operator) */
+  double rel_residual0;   /* of the initial multipliers */
+  double block_entries;   /* sum_k n_I,k (n_I,k + 1) / 2 over the problem's subdomains */
+  double bytes_F[2];      /* algorithmic bytes of one F application, FP64 / FP32 blocks */
+  double bytes_M[2];      /* the same for M_D */
+  double pcg_bytes;       /* algorithmic bytes of the last solve's applications */
+} ieti_problem_stats;
+
+/* Results of problem prob (0 for a single-problem handle) of the last solve. */
+int ieti_get_problem_stats(const ieti_handle* h, int32_t prob, ieti_problem_stats* out);
 
 /* Assemble the problem on the host: spline spaces, Galerkin matrices of
  * Eq. discrMS per subdomain, facets and wire basket (Section 2), edge
@@ -271,12 +303,14 @@ int ieti_set_profiling(ieti_handle* h, int32_t enable);
  * order.  Either argument may be NULL. */
 int ieti_get_gemv_tuning(const ieti_handle* h, int32_t* variant, float* ms);
 
-/* times[0..7] = {GEMV launches, GEMV total ms, update launches, update total
- * ms, update tasks executed, FP64 interface-block bytes read per GEMV
- * application with the chosen FP64 shape, the same for the row-streaming
- * shapes (whole blocks), the same for the symmetric shape (lower tiles)}.
- * With the symmetric shape the GEMV launches and times are those of its
- * tile kernel (the block reduction is a separate small launch). */
+/* times[0..11] = {FP64 GEMV launches, FP64 GEMV total ms, update launches,
+ * update total ms, update tasks executed, FP64 interface-block bytes read per
+ * GEMV application with the chosen FP64 shape, the same for the
+ * row-streaming shapes (whole padded blocks), the same for the symmetric
+ * shape (padded lower tiles), the algorithmic FP64 bytes of one application
+ * (8 sum_k n_I,k (n_I,k + 1) / 2, no padding), FP32 GEMV launches, FP32
+ * GEMV total ms, 0}.  With the symmetric shape the GEMV launches and times
+ * are those of its tile kernel. */
 int ieti_get_kernel_times(const ieti_handle* h, double* times);
 
 /* Change the reluctivity of every patch and scale every patch's load
@@ -305,6 +339,14 @@ int ieti_record_pcg(ieti_handle* h, int32_t cap);
  * (either may be NULL; beta of an iteration that met the tolerance is 0).
  * IETI_ERR_STATE if recording is off or no solve ran since it was enabled. */
 int ieti_get_pcg_coefficients(const ieti_handle* h, int32_t prob, double* alpha, double* beta, int32_t* n_out);
+
+/* Extreme eigenvalues of the Lanczos tridiagonal built from problem prob's
+ * recorded PCG coefficients (ieti_get_pcg_coefficients): estimates of the
+ * extreme eigenvalues of the preconditioned interface operator, whose ratio
+ * is the condition number Section 4 reports.  Computed by bisection on the
+ * Sturm sequence of the tridiagonal (Gershgorin bounds, to relative width
+ * 1e-15).  1 and 1 when the run took no iteration. */
+int ieti_get_condition(const ieti_handle* h, int32_t prob, double* lambda_min, double* lambda_max);
 
 /* Multipliers of the last solve [m_r]. */
 int ieti_get_lambda(const ieti_handle* h, double* lambda_out);
@@ -365,35 +407,77 @@ int ieti_nn_train(ieti_nn* nn, const ieti_nn_train_opts* opts, double* epoch_los
 /* pred [n][n_out] for host inputs X [n][n_in], C [n][n_comb]. */
 int ieti_nn_predict(ieti_nn* nn, const float* X, const float* C, int64_t n, float* pred);
 void ieti_nn_destroy(ieti_nn* nn);
-/* Write the architecture and parameters (FP32) to a file / create a network
- * on the current device from such a file.  IETI_ERR_INVALID_ARG if the file
+/* Write the architecture, parameters (FP32) and normalisation to a file /
+ * create a network on the current device from such a file.  IETI_ERR_INVALID_ARG if the file
  * cannot be opened, is not a network file of this library (tag, sizes and
  * parameter count are checked before any device allocation) or is
  * truncated.  Adam's state is not stored: a loaded network starts afresh. */
 int ieti_nn_save(const ieti_nn* nn, const char* path);
 int ieti_nn_load(const char* path, ieti_nn** out);
 
+/* Initial parameters: every weight uniform in [-l, l] with
+ * l = sqrt(6 / (d_in + d_out)) of its layer (Glorot & Bengio 2010), biases
+ * 0, drawn from SplitMix64 (Steele et al. 2014) seeded with `seed` (53-bit
+ * uniforms, layers in order, rows of W'_l in order).  Resets Adam's state. */
+int ieti_nn_init_params(ieti_nn* nn, uint64_t seed);
+/* Input normalisation and output scale of the network: it computes on rows
+ * x' = (x - shift) * scale, and its predictions are out_scale times its
+ * output.  Training data (ieti_nn_set_data) and prediction inputs are raw
+ * rows; the targets are divided by out_scale for training, so loss and
+ * gradient are in the normalised coordinates.  A new network has the
+ * identity (shift 0, scale 1, out_scale 1); NULL arrays set the identity.
+ * Set it before ieti_nn_set_data. */
+int ieti_nn_set_normalisation(ieti_nn* nn, const float* shift, const float* scale, double out_scale);
+/* Normalisation fitted to rows X [n][n_in], Y [n][n_out]: shift = column
+ * means of X, scale = 1 / column standard deviation (1 where it is below
+ * 1e-12), out_scale = root mean square of Y (1 if 0). */
+int ieti_nn_fit_normalisation(ieti_nn* nn, const float* X, const float* Y, int64_t n);
+int ieti_nn_get_normalisation(const ieti_nn* nn, float* shift, float* scale, double* out_scale);
+/* Training rows in a file: appended to `path` (created with a header of
+ * the three row sizes on first use; rows of other sizes are rejected). */
+int ieti_nn_dataset_append(const char* path, const float* X, const float* C, const float* Y, int64_t n,
+                           int32_t n_in, int32_t n_comb, int32_t n_out);
+/* Train a network of architecture `arch` on every row of a dataset file:
+ * parameters from ieti_nn_init_params(opts->seed), normalisation fitted to
+ * the rows, Adam with `opts`, then written to `model_out` (ieti_nn_save).
+ * epoch_loss [opts->epochs] may be NULL. */
+int ieti_nn_train_file(const char* dataset_path, const ieti_nn_arch* arch, const ieti_nn_train_opts* opts,
+                       const char* model_out, double* epoch_loss);
+
 /* How the solver forms the network's rows and places its predictions: one
  * row per facet f (e.g. one interface facet of two subdomains), features
- * x[j] = (log(nu[feat_patch[f][j]]) - feat_shift[j]) * feat_scale[j],
+ * x[j] = log(nu[feat_patch[f][j]]) (normalised by the network),
  * coefficients c[r] = load_scale[comb_patch[f][r]], and
- * lambda_0[out_row[f][o]] = out_scale * out_sign[f][o] * pred[f][o]
- * (out_row -1 = unused output; rows not covered start at 0). */
+ * lambda_0[out_row[f][o]] = out_sign[f][o] * pred[f][o] with the network's
+ * (scaled) prediction (out_row -1 = unused output; rows not covered start
+ * at 0).  The training target of output o is out_sign[f][o] times the
+ * solved multiplier of row out_row[f][o]. */
 typedef struct {
   int32_t n_facets, n_feat, n_comb, n_out;
   const int32_t* feat_patch;   /* [n_facets * n_feat] */
-  const float* feat_shift;     /* [n_feat] */
-  const float* feat_scale;     /* [n_feat] */
   const int32_t* comb_patch;   /* [n_facets * n_comb] */
   const int32_t* out_row;      /* [n_facets * n_out], distinct rows in [0, m_r) or -1 */
   const int8_t* out_sign;      /* [n_facets * n_out], +1 or -1 */
-  double out_scale;
 } ieti_warm_layout;
 
-/* Attach a copy of the network's current parameters and the layout to the
- * handle (nn may be destroyed afterwards); solves with warm_start = 1 then
- * predict lambda_0 on the GPU. */
+/* Attach a copy of the network's current parameters and normalisation and
+ * the layout to the handle (nn may be destroyed afterwards); solves with
+ * warm_start = 1 then predict lambda_0 on the GPU. */
 int ieti_set_warm_start(ieti_handle* h, const ieti_nn* nn, const ieti_warm_layout* layout);
+/* The network's rows for the handle's current coefficients: X [n_facets][n_feat]
+ * raw features, C [n_facets][n_comb], and Y [n_facets][n_out] the targets
+ * from the multipliers of the last solve (IETI_ERR_STATE before a solve).
+ * Any of X, C, Y may be NULL. */
+int ieti_warm_rows(const ieti_handle* h, const ieti_warm_layout* layout, float* X, float* C, float* Y);
+/* ieti_warm_rows of the last solve appended to a dataset file
+ * (ieti_nn_dataset_append): the solver generating its own training data. */
+int ieti_warm_append(const ieti_handle* h, const ieti_warm_layout* layout, const char* dataset_path);
+/* Load a network file (ieti_nn_load) and attach it (ieti_set_warm_start). */
+int ieti_warm_load(ieti_handle* h, const char* model_path, const ieti_warm_layout* layout);
+/* The initial multipliers the attached network predicts for the handle's
+ * current coefficients, host lambda0 [m_r] (the warm start's lambda_0
+ * before its residual check). */
+int ieti_warm_predict(ieti_handle* h, double* lambda0);
 
 const char* ieti_last_error(void);
 

@@ -26,6 +26,7 @@ SOURCES = [
     os.path.join(CSRC, "host", "assemble.cpp"),
     os.path.join(CSRC, "host", "plan.cpp"),
     os.path.join(CSRC, "host", "batch.cpp"),
+    os.path.join(CSRC, "host", "partition_check.cpp"),
     os.path.join(CSRC, "device", "kernels.hip"),
     os.path.join(CSRC, "device", "nn_kernels.hip"),
 ]

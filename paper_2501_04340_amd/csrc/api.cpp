@@ -40,6 +40,7 @@ struct ieti_handle {
   int nblk = 0;
   std::vector<int64_t> gemv_task_h[3];  // GEMV task lists for 8, 16 and 32 rows per workgroup
   // device buffers
+  DBuf<double> piv_tol;  // per subdomain: pivot threshold of the factorisation
   DBuf<double> pool, inv, scatter_val, S, Sinv, Phi, SPi, Spi_glob, G, H, Ht, I_sign, b_aug0, y;
   DBuf<int64_t> scatter_dst, potrf, trsm, upd, upd_pair, copyS, xsinv, xphi, xspi, fdiag, ffull, ffull_pair, rec_task, rec_pair;
   DBuf<int64_t> bdiag, bupd, bupd_pair;
@@ -112,15 +113,21 @@ struct ieti_handle {
   double bnorm = 0.0;
   std::vector<double> lambda_h;
   bool rhs_ready = false;
-  // kernel timing (event pairs around launches); kind 0 = GEMV, 1 = update
+  // kernel timing (event pairs around launches); kind 0 = FP64 GEMV, 1 = update, 2 = FP32 GEMV
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;  // (kind, index of start event)
-  double k_count[2] = {0, 0}, k_ms[2] = {0, 0}, upd_tasks = 0;
+  double k_count[3] = {0, 0, 0}, k_ms[3] = {0, 0, 0}, upd_tasks = 0;
+  // per problem: sizes of the algorithmic byte model of one interface operator
+  // application (entries of the lower triangles of the interface blocks,
+  // sum n_I, sum n_I n_p) and the applications of the last solve by block
+  // precision ([0] FP64, [1] FP32)
+  std::vector<double> pb_entries, pb_sumI, pb_sumInp;
+  std::vector<int> cntF[2], cntM[2];
 
   ~ieti_handle() {
-    DBuf<double>* ds[] = {&pool, &inv, &scatter_val, &S, &Sinv, &Phi, &SPi, &Spi_glob, &G, &H, &Ht, &I_sign, &b_aug0, &y,
+    DBuf<double>* ds[] = {&piv_tol, &pool, &inv, &scatter_val, &S, &Sinv, &Phi, &SPi, &Spi_glob, &G, &H, &Ht, &I_sign, &b_aug0, &y,
                           &yj, &lam, &r, &z, &p, &q, &v, &b, &e, &dtil, &w, &t, &pglob, &part, &scal, &aout,
                           &tmp, &xgp, &xgr, &part_g, &part_t, &lam_acc, &rtrue};
     for (auto* d : ds) d->release();
@@ -263,6 +270,7 @@ int upload(ieti_handle* h) {
   if ((rc = dupload(h->buf, vec))) return rc;
   UP(scatter_dst, P.scatter_dst);
   UP(scatter_val, P.scatter_val);
+  UP(piv_tol, P.piv_tol);
   UP(potrf, P.potrf_task);
   UP(trsm, P.trsm_task);
   UP(upd, P.upd_task);
@@ -305,6 +313,16 @@ int upload(ieti_handle* h) {
   h->max_ld = 0;
   for (auto& v : h->gemv_task_h) v.clear();
   const int n_prob = int(M.probs.size());
+  h->pb_entries.assign(n_prob, 0.0);
+  h->pb_sumI.assign(n_prob, 0.0);
+  h->pb_sumInp.assign(n_prob, 0.0);
+  for (size_t k = 0; k < P.sub.size(); ++k) {
+    const auto& sp = P.sub[k];
+    const int pk = M.sub_prob[k];
+    h->pb_entries[pk] += 0.5 * double(sp.nI) * double(sp.nI + 1);
+    h->pb_sumI[pk] += double(sp.nI);
+    h->pb_sumInp[pk] += double(sp.nI) * double(sp.nP);
+  }
   std::vector<int32_t> tprob[3];
   std::vector<int64_t> tstart(3 * (n_prob + 1), 0);  // per task list: first task of each problem
   for (size_t k = 0; k < P.sub.size(); ++k) {
@@ -573,6 +591,34 @@ int check_launch() {
 // per-slot scaling of the preconditioner's jump operator, or null for D_s = I
 const double* dsc(const ieti_handle* h) { return h->scaling == IETI_SCALE_IDENTITY ? nullptr : h->dscale.ptr; }
 
+// Algorithmic bytes of one application of the interface operator (is_F) or
+// of the preconditioner for problem p, with s-byte interface-block entries:
+// the lower triangle of every symmetric interface block once
+// (s sum n_I (n_I + 1) / 2), the interface vectors in and out (16 sum n_I),
+// three multiplier vectors (24 m_r), and for the operator the local primal
+// coupling in and out (16 sum n_I n_p) and the coarse factor (8 n_gp^2).
+double alg_bytes(const ieti_handle* h, int p, double s, bool is_F) {
+  const auto& pr = h->model.probs[p];
+  double b = s * h->pb_entries[p] + 16.0 * h->pb_sumI[p] + 24.0 * double(pr.m_r);
+  if (is_F) b += 16.0 * h->pb_sumInp[p] + 8.0 * double(pr.n_gp) * double(pr.n_gp);
+  return b;
+}
+
+double problem_pcg_bytes(const ieti_handle* h, int p) {
+  double b = 0.0;
+  for (int f = 0; f < 2; ++f) {
+    const double s = f ? 4.0 : 8.0;
+    if (p < int(h->cntF[f].size())) b += h->cntF[f][p] * alg_bytes(h, p, s, true);
+    if (p < int(h->cntM[f].size())) b += h->cntM[f][p] * alg_bytes(h, p, s, false);
+  }
+  return b;
+}
+
+// one more application on every problem of the batch
+void count_all(std::vector<int>& c) {
+  for (int& v : c) ++v;
+}
+
 // GEMV launch shape in use for FP64 (fp32 = 0) or FP32 (1) blocks, its task list and task count
 int gvariant(const ieti_handle* h, int fp32) { return h->gvar[fp32] >= 0 ? h->gvar[fp32] : ieti::dev::GEMV_DEFAULT; }
 
@@ -605,7 +651,7 @@ void gemv_timed(ieti_handle* h, const MT* M, const double* xg, double* v, const 
     if (!a || !b) a = b = nullptr;
   }
   launch_gemv(h, M, gvariant(h, fp32), xg, v, done, a, b);
-  if (a) h->ev_marks.emplace_back(0, slot);
+  if (a) h->ev_marks.emplace_back(fp32 ? 2 : 0, slot);
 }
 
 // q = F x = sum_k B_k (K_rr^(k))^{-1}_II B_k^T x + H (H^T x)
@@ -867,6 +913,7 @@ int init_lambda(ieti_handle* h, const ieti_solve_opts* opts, const std::vector<d
   if (have) {
     apply_F(h, lam0, h->q.ptr);
     ++*applies;
+    count_all(h->cntF[0]);
     D::axpby(h->b.ptr, h->q.ptr, r0, 1.0, -1.0, m_r, s);
     rr0 = host_dots(h, r0, r0);
     for (int p = 0; p < n_prob; ++p)
@@ -909,6 +956,7 @@ int run_pcg(ieti_handle* h, const std::vector<double>& tol2, const std::vector<d
     all = all && done0[p];
   }
   if (all) return IETI_OK;
+  count_all(h->cntM[fp32 ? 1 : 0]);  // z_0 = M r_0 below, every problem
   std::vector<double> sc(8 * size_t(n_prob), 0.0);
   for (int p = 0; p < n_prob; ++p) {
     sc[8 * p + 4] = tol2[p];
@@ -942,7 +990,9 @@ int run_pcg(ieti_handle* h, const std::vector<double>& tol2, const std::vector<d
   const bool overlap = !h->profiling;
   int slot = 0, pending = -1;
   for (int it = 0; it < maxit; it += 2) {
-    if (use_graph) {
+    if (it + 1 == maxit) {
+      pcg_iteration_prec(h, 0, fp32);  // an odd cap: the last iteration alone
+    } else if (use_graph) {
       HIP_TRY(hipGraphLaunch(fp32 ? h->graph_exec32 : h->graph_exec, s));
     } else {
       pcg_iteration_prec(h, 0, fp32);
@@ -977,6 +1027,9 @@ int run_pcg(ieti_handle* h, const std::vector<double>& tol2, const std::vector<d
   h->hist_n.assign(n_prob, 0);
   for (int p = 0; p < n_prob; ++p) {
     iters_out[p] = h->pflags_h[n_prob + p];
+    // an iteration applies F and M to the problem until its done flag is set
+    h->cntF[fp32 ? 1 : 0][p] += iters_out[p];
+    h->cntM[fp32 ? 1 : 0][p] += iters_out[p];
     h->hist_n[p] = std::min(iters_out[p], h->B.hcap);
     rr_out[p] = sc[8 * p + 5];
     if (h->pflags_h[p] == 3)
@@ -1000,6 +1053,10 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   const int n_prob = h->B.n_prob;
   // profiled runs use direct launches so every GEMV carries launch events
   const bool use_graph = (!opts || opts->use_graph != 0) && !h->profiling;
+  for (int f = 0; f < 2; ++f) {
+    h->cntF[f].assign(n_prob, 0);
+    h->cntM[f].assign(n_prob, 0);
+  }
   HIP_TRY(hipEventRecord(h->ev0, s));
   int rc = compute_rhs(h, use_graph);
   if (rc) return rc;
@@ -1037,6 +1094,7 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
         if (outer > 0) {
           apply_F(h, h->lam_acc.ptr, h->q.ptr);
           ++applies;
+          count_all(h->cntF[0]);
           D::axpby(h->b.ptr, h->q.ptr, h->rtrue.ptr, 1.0, -1.0, m_r, s);
           rr = host_dots(h, h->rtrue.ptr, h->rtrue.ptr);
         }
@@ -1146,6 +1204,8 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
     st->rel_residual0 = rel0;
     st->warm_start = warm_all;
     st->reserved = 0;
+    st->pcg_bytes = 0.0;
+    for (int p = 0; p < n_prob; ++p) st->pcg_bytes += problem_pcg_bytes(h, p);
   }
   (void)outer_max;
   if (st_all != IETI_OK) return fail(st_all, "PCG did not reach the tolerance within maxit");
@@ -1167,14 +1227,9 @@ int assemble_model(const ieti_problem* prob, ieti::Model& m) {
     maxs = std::max(maxs, m.part[q]);
   }
   m.n_sub = maxs + 1;
-  {
-    std::vector<int> used(m.n_sub, 0);
-    for (int64_t q = 0; q < np; ++q) used[m.part[q]] = 1;
-    for (int k = 0; k < m.n_sub; ++k)
-      if (!used[k]) return fail(IETI_ERR_PARTITION, "subdomain " + std::to_string(k) + " has no patch");
-  }
-  m.mesh.init(*prob);
   ieti::Error err{0, ""};
+  if (ieti::check_partition(*prob, m.part, m.n_sub, err)) return fail(err.code, err.msg);
+  m.mesh.init(*prob);
   rc = ieti::build_topology(m, err);
   if (!rc) rc = ieti::assemble_local_systems(m, err);
   if (rc) return fail(rc, err.msg);
@@ -1268,6 +1323,32 @@ int ieti_get_batch_info(const ieti_handle* h, int64_t* ranges, int32_t* iters, d
   return IETI_OK;
 }
 
+int ieti_get_problem_stats(const ieti_handle* h, int32_t prob, ieti_problem_stats* out) {
+  if (!h || !out) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  if (prob < 0 || prob >= int32_t(h->model.probs.size())) return fail(IETI_ERR_INVALID_ARG, "problem out of range");
+  if (!h->uploaded) return fail(IETI_ERR_STATE, "not factored");
+  std::memset(out, 0, sizeof(*out));
+  const size_t p = size_t(prob);
+  auto at = [p](const std::vector<int>& v) { return p < v.size() ? v[p] : 0; };
+  auto atd = [p](const std::vector<double>& v) { return p < v.size() ? v[p] : 0.0; };
+  out->iters = at(h->p_iters);
+  out->outer_iters = at(h->p_outer);
+  out->status = at(h->p_status);
+  out->warm_start = at(h->p_warm);
+  for (int f = 0; f < 2; ++f) {
+    out->f_applies[f] = at(h->cntF[f]);
+    out->m_applies[f] = at(h->cntM[f]);
+    const double sz = f ? 4.0 : 8.0;
+    out->bytes_F[f] = alg_bytes(h, prob, sz, true);
+    out->bytes_M[f] = alg_bytes(h, prob, sz, false);
+  }
+  out->rel_residual = atd(h->p_relres);
+  out->rel_residual0 = atd(h->p_relres0);
+  out->block_entries = h->pb_entries[p];
+  out->pcg_bytes = problem_pcg_bytes(h, prob);
+  return IETI_OK;
+}
+
 int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   namespace D = ieti::dev;
   if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
@@ -1299,7 +1380,7 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   for (int64_t j = 0; j < P.n_steps; ++j) {
     D::copy_tiles(h->pool.ptr, h->copyS.ptr + 5 * P.copy_ptr[j], P.copy_ptr[j + 1] - P.copy_ptr[j], 1.0, h->S.ptr, s);
     D::potrf_tiles(h->pool.ptr, h->inv.ptr, h->potrf.ptr + 3 * P.potrf_ptr[j], P.potrf_ptr[j + 1] - P.potrf_ptr[j],
-                   h->flags.ptr, s);
+                   h->piv_tol.ptr, h->flags.ptr, s);
     D::trsm_tiles(h->pool.ptr, h->inv.ptr, h->trsm.ptr + 2 * P.trsm_ptr[j], P.trsm_ptr[j + 1] - P.trsm_ptr[j], s);
     const int64_t nupd = P.upd_ptr[j + 1] - P.upd_ptr[j];
     const size_t ev = nupd > 0 ? prof_begin(h) : SIZE_MAX;
@@ -1345,7 +1426,9 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
     if (M.batch())
       where = "subdomain " + std::to_string(k - M.probs[M.sub_prob[k]].sub_base) + " of problem " +
               std::to_string(M.sub_prob[k]);
-    return fail(IETI_ERR_NOT_SPD, "non-positive pivot in the local factorisation of " + where);
+    return fail(IETI_ERR_NOT_SPD, "pivot at or below " + std::to_string(ieti::Plan::PIVOT_REL) +
+                                      " of the largest diagonal entry (K_rr numerically singular) in the local "
+                                      "factorisation of " + where);
   }
   if (h->flags_h[4] > 0)
     return fail(IETI_ERR_NOT_SPD, "coarse matrix of problem " + std::to_string(h->flags_h[4] - 1) +
@@ -1504,8 +1587,7 @@ int ieti_get_gemv_tuning(const ieti_handle* h, int32_t* variant, float* ms) {
 int ieti_set_profiling(ieti_handle* h, int32_t enable) {
   if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
   h->profiling = enable != 0;
-  h->k_count[0] = h->k_count[1] = 0.0;
-  h->k_ms[0] = h->k_ms[1] = 0.0;
+  for (int k = 0; k < 3; ++k) h->k_count[k] = h->k_ms[k] = 0.0;
   h->upd_tasks = 0.0;
   h->ev_marks.clear();
   h->ev_used = 0;
@@ -1547,13 +1629,69 @@ int ieti_get_pcg_coefficients(const ieti_handle* h, int32_t prob, double* alpha,
   return IETI_OK;
 }
 
+int ieti_get_condition(const ieti_handle* h, int32_t prob, double* lambda_min, double* lambda_max) {
+  if (!lambda_min || !lambda_max) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  int32_t k = 0;
+  int rc = ieti_get_pcg_coefficients(h, prob, nullptr, nullptr, &k);
+  if (rc) return rc;
+  if (k == 0) {
+    *lambda_min = *lambda_max = 1.0;
+    return IETI_OK;
+  }
+  std::vector<double> al(k), be(k);
+  if ((rc = ieti_get_pcg_coefficients(h, prob, al.data(), be.data(), &k))) return rc;
+  // Lanczos tridiagonal of the preconditioned operator from the PCG
+  // coefficients: d_i = 1/alpha_i + beta_{i-1}/alpha_{i-1}, e_i = sqrt(beta_i)/alpha_i
+  std::vector<double> d(k), e2(k > 1 ? k - 1 : 1, 0.0);
+  for (int i = 0; i < k; ++i) {
+    if (!(al[i] > 0.0)) return fail(IETI_ERR_STATE, "recorded step lengths are not positive");
+    d[i] = 1.0 / al[i] + (i > 0 ? be[i - 1] / al[i - 1] : 0.0);
+  }
+  for (int i = 0; i + 1 < k; ++i) e2[i] = be[i] / (al[i] * al[i]);
+  // eigenvalues below x: sign changes of the LDL^T pivots of T - x I (Sturm count)
+  auto below = [&](double x) {
+    int c = 0;
+    double q = d[0] - x;
+    const double tiny = 1e-300;
+    for (int i = 0;; ++i) {
+      if (q == 0.0) q = -tiny;
+      if (q < 0.0) ++c;
+      if (i + 1 == k) break;
+      q = d[i + 1] - x - e2[i] / q;
+    }
+    return c;
+  };
+  double lo = d[0], hi = d[0];
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::sqrt(e2[i - 1]) : 0.0) + (i + 1 < k ? std::sqrt(e2[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  // the j-th smallest eigenvalue by bisection on the Sturm count
+  auto eig = [&](int j) {
+    double a = lo, b = hi;
+    for (int it = 0; it < 200 && b - a > 1e-15 * std::max(std::abs(a), std::abs(b)); ++it) {
+      const double m = 0.5 * (a + b);
+      if (below(m) > j) b = m;
+      else a = m;
+    }
+    return 0.5 * (a + b);
+  };
+  *lambda_min = eig(0);
+  *lambda_max = eig(k - 1);
+  return IETI_OK;
+}
+
 int ieti_get_kernel_times(const ieti_handle* h, double* times) {
   if (!h || !times) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
   double full = 0.0;
   for (const auto& sp : h->plan.sub) full += double(sp.nIp) * double(sp.nIp) * sizeof(double);
   const double lower = h->sym_elems * sizeof(double);
   const double bytes = h->gvar[0] == ieti::dev::GEMV_SYM ? lower : full;
-  const double v[8] = {h->k_count[0], h->k_ms[0], h->k_count[1], h->k_ms[1], h->upd_tasks, bytes, full, lower};
+  double entries = 0.0;
+  for (double e : h->pb_entries) entries += e;
+  const double v[12] = {h->k_count[0], h->k_ms[0], h->k_count[1], h->k_ms[1], h->upd_tasks, bytes, full, lower,
+                        entries * sizeof(double), h->k_count[2], h->k_ms[2], 0.0};
   std::memcpy(times, v, sizeof(v));
   return IETI_OK;
 }
@@ -1584,6 +1722,7 @@ int ieti_set_coefficients(ieti_handle* h, const double* nu_per_patch, const doub
       HIP_TRY(hipMemcpy(h->scatter_val.ptr, P.scatter_val.data(), P.scatter_val.size() * sizeof(double),
                         hipMemcpyHostToDevice));
       HIP_TRY(hipMemcpy(h->b_aug0.ptr, P.b_aug0.data(), P.b_aug0.size() * sizeof(double), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(h->piv_tol.ptr, P.piv_tol.data(), P.piv_tol.size() * sizeof(double), hipMemcpyHostToDevice));
     }
   }
   if (h->nu_d.ptr) {
@@ -1594,14 +1733,18 @@ int ieti_set_coefficients(ieti_handle* h, const double* nu_per_patch, const doub
   return IETI_OK;
 }
 
-int ieti_set_warm_start(ieti_handle* h, const ieti_nn* nn, const ieti_warm_layout* L) {
-  if (!h || !nn || !L) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
-  const auto& mlp = ieti::nn::mlp_of(nn);
+namespace {
+
+// Checks a warm-start layout against the handle (and the network's sizes when given).
+int check_layout(const ieti_handle* h, const ieti_warm_layout* L, const ieti::nn::Mlp* mlp) {
   const auto& M = h->model;
   const int64_t np = int64_t(M.part.size());
-  if (L->n_facets < 1 || L->n_feat != mlp.arch.n_in || L->n_comb != mlp.arch.n_comb || L->n_out != mlp.arch.n_out)
+  if (!L) return fail(IETI_ERR_INVALID_ARG, "layout is NULL");
+  if (L->n_facets < 1 || L->n_feat < 1 || L->n_comb < 1 || L->n_out < 1)
+    return fail(IETI_ERR_INVALID_ARG, "layout sizes must be >= 1");
+  if (mlp && (L->n_feat != mlp->arch.n_in || L->n_comb != mlp->arch.n_comb || L->n_out != mlp->arch.n_out))
     return fail(IETI_ERR_INVALID_ARG, "layout sizes do not match the network");
-  if (!L->feat_patch || !L->feat_shift || !L->feat_scale || !L->comb_patch || !L->out_row || !L->out_sign)
+  if (!L->feat_patch || !L->comb_patch || !L->out_row || !L->out_sign)
     return fail(IETI_ERR_INVALID_ARG, "layout arrays are required");
   const int64_t nf = L->n_facets;
   for (int64_t i = 0; i < nf * L->n_feat; ++i)
@@ -1616,7 +1759,18 @@ int ieti_set_warm_start(ieti_handle* h, const ieti_nn* nn, const ieti_warm_layou
     if (r >= 0 && seen[r]++) return fail(IETI_ERR_INVALID_ARG, "output rows must be distinct");
     if (L->out_sign[i] != 1 && L->out_sign[i] != -1) return fail(IETI_ERR_INVALID_ARG, "output signs must be +-1");
   }
-  if (!std::isfinite(L->out_scale)) return fail(IETI_ERR_INVALID_ARG, "output scale must be finite");
+  return IETI_OK;
+}
+
+}  // namespace
+
+int ieti_set_warm_start(ieti_handle* h, const ieti_nn* nn, const ieti_warm_layout* L) {
+  if (!h || !nn || !L) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  const auto& mlp = ieti::nn::mlp_of(nn);
+  const auto& M = h->model;
+  int rc = check_layout(h, L, &mlp);
+  if (rc) return rc;
+  const int64_t nf = L->n_facets;
   auto& W = h->warm;
   W.release();
   W.mlp = mlp;
@@ -1624,14 +1778,13 @@ int ieti_set_warm_start(ieti_handle* h, const ieti_nn* nn, const ieti_warm_layou
   W.n_feat = L->n_feat;
   W.n_comb = L->n_comb;
   W.n_out = L->n_out;
-  W.out_scale = L->out_scale;
-  int rc = 0;
+  W.out_scale = ieti::nn::out_scale_of(nn);
   HIP_TRY(hipStreamSynchronize(ieti::nn::stream_of(nn)));
   if ((rc = dalloc(W.theta, mlp.n_params))) return rc;
   HIP_TRY(hipMemcpy(W.theta.ptr, ieti::nn::params_of(nn), mlp.n_params * sizeof(float), hipMemcpyDeviceToDevice));
   if ((rc = dupload(W.feat_patch, L->feat_patch, nf * L->n_feat))) return rc;
-  if ((rc = dupload(W.shift, L->feat_shift, L->n_feat))) return rc;
-  if ((rc = dupload(W.scale, L->feat_scale, L->n_feat))) return rc;
+  if ((rc = dupload(W.shift, ieti::nn::shift_of(nn)))) return rc;
+  if ((rc = dupload(W.scale, ieti::nn::scale_of(nn)))) return rc;
   if ((rc = dupload(W.comb_patch, L->comb_patch, nf * L->n_comb))) return rc;
   if ((rc = dupload(W.out_row, L->out_row, nf * L->n_out))) return rc;
   if ((rc = dupload(W.out_sign, L->out_sign, nf * L->n_out))) return rc;
@@ -1642,6 +1795,58 @@ int ieti_set_warm_start(ieti_handle* h, const ieti_nn* nn, const ieti_warm_layou
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(nullptr));
   W.on = true;
+  return IETI_OK;
+}
+
+int ieti_warm_rows(const ieti_handle* h, const ieti_warm_layout* L, float* X, float* C, float* Y) {
+  if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
+  int rc = check_layout(h, L, nullptr);
+  if (rc) return rc;
+  const auto& M = h->model;
+  const int64_t nf = L->n_facets;
+  if (X)
+    for (int64_t i = 0; i < nf * L->n_feat; ++i) X[i] = float(std::log(M.nu[L->feat_patch[i]]));
+  if (C)
+    for (int64_t i = 0; i < nf * L->n_comb; ++i) C[i] = float(M.load_scale[L->comb_patch[i]]);
+  if (Y) {
+    if (int64_t(h->lambda_h.size()) != M.m_r) return fail(IETI_ERR_STATE, "no solve has produced multipliers");
+    for (int64_t i = 0; i < nf * L->n_out; ++i)
+      Y[i] = L->out_row[i] >= 0 ? float(double(L->out_sign[i]) * h->lambda_h[L->out_row[i]]) : 0.f;
+  }
+  return IETI_OK;
+}
+
+int ieti_warm_append(const ieti_handle* h, const ieti_warm_layout* L, const char* dataset_path) {
+  if (!h || !dataset_path) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  int rc = check_layout(h, L, nullptr);
+  if (rc) return rc;
+  const int64_t nf = L->n_facets;
+  std::vector<float> X(nf * L->n_feat), C(nf * L->n_comb), Y(nf * L->n_out);
+  if ((rc = ieti_warm_rows(h, L, X.data(), C.data(), Y.data()))) return rc;
+  return ieti_nn_dataset_append(dataset_path, X.data(), C.data(), Y.data(), nf, L->n_feat, L->n_comb, L->n_out);
+}
+
+int ieti_warm_load(ieti_handle* h, const char* model_path, const ieti_warm_layout* L) {
+  if (!h || !model_path || !L) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  ieti_nn* nn = nullptr;
+  int rc = ieti_nn_load(model_path, &nn);
+  if (rc) return rc;
+  rc = ieti_set_warm_start(h, nn, L);
+  ieti_nn_destroy(nn);
+  return rc;
+}
+
+int ieti_warm_predict(ieti_handle* h, double* lambda0) {
+  if (!h || !lambda0) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  if (!h->warm.on) return fail(IETI_ERR_STATE, "no network is attached");
+  if (!h->factored) return fail(IETI_ERR_STATE, "not factored");
+  const int64_t m_r = h->model.m_r;
+  if (m_r == 0) return IETI_OK;
+  warm_predict(h, h->tmp.ptr);
+  int rc = check_launch();
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(lambda0, h->tmp.ptr, m_r * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
   return IETI_OK;
 }
 

@@ -89,16 +89,19 @@ __global__ void k_scatter(double* pool, const int64_t* dst, const double* val, i
 // The inverse runs the same way column-oriented: lane c holds column c of
 // L^{-1}, wave w its rows 16w..16w+15, reading column k of L from a
 // transposed LDS copy and multiplying by the stored reciprocal pivots.  A
-// non-positive pivot records the subdomain (1-based) in err and continues
-// with pivot 1.
+// pivot not above the subdomain's threshold piv_tol[sub] (a fixed fraction
+// of the largest diagonal entry of its K_rr: numerically singular) records
+// the subdomain (1-based) in err and continues with pivot 1.
 
-__global__ __launch_bounds__(256) void k_potrf_inv(double* pool, double* inv, const int64_t* task, int* err) {
+__global__ __launch_bounds__(256) void k_potrf_inv(double* pool, double* inv, const int64_t* task,
+                                                   const double* piv_tol, int* err) {
   __shared__ __align__(16) double Lt[T][T + 2];  // Lt[j][i] = L[i][j]; later X staging
   __shared__ __align__(16) double bc[2][T];
   __shared__ double dinv[T];
   const int64_t* tk = task + 3 * blockIdx.x;
   double* t = pool + tk[0];
   const int sub = int(tk[1]);
+  const double tol = piv_tol[sub];
   double* tinv = inv + tk[2];
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c0 = 16 * w;
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(256) void k_potrf_inv(double* pool, double* inv, co
     double* col = bc[kk & 1];
     if (w == (kb >> 4)) {
       const double akk = readlane_f64(a[kk], k);
-      const bool ok = akk > 0.0;
+      const bool ok = akk > tol;
       bad = bad || !ok;
       // 1/sqrt(a) from the hardware estimate and two Newton steps
       // (y <- y (3 - a y^2) / 2), pivot sqrt(a) = a / sqrt(a): fewer dependent
@@ -1176,9 +1179,10 @@ void scatter(double* pool, const int64_t* dst, const double* val, int64_t n, hip
   if (n <= 0) return;
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, pool, dst, val, n);
 }
-void potrf_tiles(double* pool, double* inv, const int64_t* task, int64_t ntask, int* err, hipStream_t s) {
+void potrf_tiles(double* pool, double* inv, const int64_t* task, int64_t ntask, const double* piv_tol, int* err,
+                 hipStream_t s) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(k_potrf_inv, dim3(ntask), dim3(256), 0, s, pool, inv, task, err);
+  hipLaunchKernelGGL(k_potrf_inv, dim3(ntask), dim3(256), 0, s, pool, inv, task, piv_tol, err);
 }
 void trsm_tiles(double* pool, const double* inv, const int64_t* task, int64_t ntask, hipStream_t s) {
   if (ntask <= 0) return;

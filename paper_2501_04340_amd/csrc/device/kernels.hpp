@@ -13,8 +13,10 @@ constexpr int TILE = 64;
 // ---- factorisation (tile pool, column-major 64x64 tiles)
 void fill(double* p, int64_t n, double v, hipStream_t s);
 void scatter(double* pool, const int64_t* dst, const double* val, int64_t n, hipStream_t s);
-// potrf task [off_jj, subdomain, off of the inverse]; writes L_jj and L_jj^{-1}
-void potrf_tiles(double* pool, double* inv, const int64_t* task, int64_t ntask, int* err, hipStream_t s);
+// potrf task [off_jj, subdomain, off of the inverse]; writes L_jj and L_jj^{-1}; a pivot not
+// above piv_tol[subdomain] flags the subdomain in err
+void potrf_tiles(double* pool, double* inv, const int64_t* task, int64_t ntask, const double* piv_tol, int* err,
+                 hipStream_t s);
 // trsm task [off_ij, off of L_jj^{-1}]: L_ij = A_ij L_jj^{-T}
 void trsm_tiles(double* pool, const double* inv, const int64_t* task, int64_t ntask, hipStream_t s);
 // update task [off_C, first pair, pair count], pairs [off_A, off_B]: C -= sum A B^T;

@@ -105,6 +105,9 @@ struct Model {
   const Mesh& mesh_of(int k) const { return meshes[sub_prob[k]]; }
 };
 
+// partition_check.cpp: every subdomain non-empty, connected through patch
+// faces and simply connected (IETI_ERR_PARTITION otherwise)
+int check_partition(const ieti_problem& pr, const std::vector<int32_t>& part, int n_sub, Error& err);
 // mesh_topology.cpp
 int build_topology(Model& m, Error& err);
 // assemble.cpp

@@ -219,8 +219,8 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
         if (pr / T > pc / T || (pr / T == pc / T)) put(pr, pc, voff + q);
       }
     }
-    for (int64_t q : sp.vdummy) put(q, q, -1);
-    for (int64_t t = sp.nVp + sp.nI; t < sp.nVp + sp.nIp; ++t) put(t, t, -1);
+    for (int64_t q : sp.vdummy) put(q, q, -2 - k);
+    for (int64_t t = sp.nVp + sp.nI; t < sp.nVp + sp.nIp; ++t) put(t, t, -2 - k);
     const int64_t a0 = sp.nVp + sp.nIp + sp.nPp;
     for (int64_t t = 0; t < sp.nI; ++t) put(a0 + t, sp.nVp + t, -1);
     voff += s.indptr[s.n_loc];
@@ -570,13 +570,27 @@ void refill_values(const Model& m, Plan& plan) {
     const int64_t k = std::upper_bound(voff.begin(), voff.end(), src) - voff.begin() - 1;
     return vals[k][src - voff[k]];
   };
+  // largest diagonal entry of each K_rr (local numbering [r, p], r first)
+  std::vector<double> dmax(m.sd.size(), 0.0);
+  for (size_t k = 0; k < m.sd.size(); ++k) {
+    const Subdomain& s = m.sd[k];
+    const int64_t nr = int64_t(s.r_edges.size());
+    for (int64_t r = 0; r < nr; ++r)
+      for (int64_t q = s.indptr[r]; q < s.indptr[r + 1]; ++q)
+        if (s.indices[q] == r) dmax[k] = std::max(dmax[k], std::abs(s.values[q]));
+    if (!(dmax[k] > 0.0)) dmax[k] = 1.0;
+  }
+  plan.piv_tol.resize(m.sd.size());
+  for (size_t k = 0; k < m.sd.size(); ++k) plan.piv_tol[k] = Plan::PIVOT_REL * dmax[k];
   // the list is in destination order, so its sources are read out of order:
   // the entries are independent and split over the host threads
   plan.scatter_val.resize(plan.scatter_src.size());
   const int64_t ns = int64_t(plan.scatter_src.size());
 #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < ns; ++i)
-    plan.scatter_val[size_t(i)] = plan.scatter_src[size_t(i)] < 0 ? 1.0 : value(plan.scatter_src[size_t(i)]);
+  for (int64_t i = 0; i < ns; ++i) {
+    const int64_t src = plan.scatter_src[size_t(i)];
+    plan.scatter_val[size_t(i)] = src >= 0 ? value(src) : src == -1 ? 1.0 : dmax[size_t(-2 - src)];
+  }
   plan.b_aug0.assign(plan.r_total, 0.0);
   for (size_t k = 0; k < m.sd.size(); ++k) {
     const Subdomain& s = m.sd[k];

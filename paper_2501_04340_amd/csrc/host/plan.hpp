@@ -57,6 +57,7 @@ struct Plan {
   std::vector<int64_t> scatter_dst;
   std::vector<double> scatter_val;
   std::vector<int64_t> scatter_src;  // per entry: index into the concatenated CSR values, -1 = constant 1
+                                     // (E_I), -2 - k = identity dummy of subdomain k
   // dense S / Sinv storage
   int64_t S_elems = 0;
   int64_t I_total = 0;   // sum nIp
@@ -95,6 +96,11 @@ struct Plan {
   std::vector<int64_t> out_src, out_edge;
   // initial augmented right-hand side [j_r; j_p; 0]
   std::vector<double> b_aug0;
+  // per subdomain: pivot threshold of the factorisation, PIVOT_REL times the
+  // largest diagonal entry of K_rr (also the value of its identity dummies,
+  // which keeps them above the threshold at any scale)
+  std::vector<double> piv_tol;
+  static constexpr double PIVOT_REL = 1e-13;
   double flops = 0.0;    // algorithmic flops of the tile factorisation
   double dense_flops = 0.0;
   int64_t n_update_tasks = 0;

@@ -121,6 +121,10 @@ struct ieti_nn {
   DBuf<int32_t> idx;
   DBuf<double> loss;
   ieti::nn::Work work;
+  // input normalisation x' = (x - shift) * scale and output scale: the
+  // network computes on normalised rows, predictions are out_scale * output
+  std::vector<float> shift, scale;
+  double out_scale = 1.0;
   ~ieti_nn() {
     for (auto* b : {&theta, &grad, &m, &v, &X, &C, &T, &Cb, &Tb}) b->release();
     idx.release();
@@ -133,6 +137,17 @@ struct ieti_nn {
 namespace {
 
 namespace N = ieti::nn;
+
+// rows [n][n_in] -> normalised rows [n][n_in + 1] with the trailing 1 of the bias column
+std::vector<float> normalised_inputs(const ieti_nn* nn, const float* X, int64_t n) {
+  const int64_t d = nn->mlp.arch.n_in;
+  std::vector<float> xo(size_t(n) * (d + 1));
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = 0; j < d; ++j) xo[i * (d + 1) + j] = (X[i * d + j] - nn->shift[j]) * nn->scale[j];
+    xo[i * (d + 1) + d] = 1.f;
+  }
+  return xo;
+}
 
 // SplitMix64 (Steele, Lea & Flood 2014): the shuffling generator.
 uint64_t splitmix64(uint64_t& state) {
@@ -176,6 +191,10 @@ int ieti_nn_create(const ieti_nn_arch* arch, ieti_nn** out) {
   *out = nullptr;
   ieti_nn* nn = new ieti_nn();
   int rc = nn->mlp.init(arch);
+  if (!rc) {
+    nn->shift.assign(size_t(arch->n_in), 0.f);
+    nn->scale.assign(size_t(arch->n_in), 1.f);
+  }
   if (!rc) {
     hipError_t e = hipStreamCreateWithFlags(&nn->stream, hipStreamNonBlocking);
     if (e != hipSuccess) rc = fail(IETI_ERR_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
@@ -225,14 +244,13 @@ int ieti_nn_set_data(ieti_nn* nn, const float* X, const float* C, const float* Y
   if (!nn || !X || !C || !Y || n < 1) return fail(IETI_ERR_INVALID_ARG, "NULL data or n < 1");
   if (n > (int64_t(1) << 30)) return fail(IETI_ERR_INVALID_ARG, "too many rows");
   const auto& a = nn->mlp.arch;
-  std::vector<float> xo(size_t(n) * (a.n_in + 1));
-  for (int64_t i = 0; i < n; ++i) {
-    std::copy(X + i * a.n_in, X + (i + 1) * a.n_in, xo.begin() + i * (a.n_in + 1));
-    xo[i * (a.n_in + 1) + a.n_in] = 1.f;
-  }
+  std::vector<float> xo = normalised_inputs(nn, X, n);
+  std::vector<float> yo(size_t(n) * a.n_out);
+  const double inv = 1.0 / nn->out_scale;
+  for (size_t i = 0; i < yo.size(); ++i) yo[i] = float(double(Y[i]) * inv);
   int rc = dupload(nn->X, xo);
   if (!rc) rc = dupload(nn->C, C, n * a.n_comb);
-  if (!rc) rc = dupload(nn->T, Y, n * a.n_out);
+  if (!rc) rc = dupload(nn->T, yo);
   if (rc) return rc;
   nn->n_data = n;
   return IETI_OK;
@@ -317,11 +335,7 @@ int ieti_nn_predict(ieti_nn* nn, const float* X, const float* C, int64_t n, floa
   if (rc) return rc;
   hipStream_t s = nn->stream;
   auto& w = nn->work;
-  std::vector<float> xo(size_t(n) * (a.n_in + 1));
-  for (int64_t i = 0; i < n; ++i) {
-    std::copy(X + i * a.n_in, X + (i + 1) * a.n_in, xo.begin() + i * (a.n_in + 1));
-    xo[i * (a.n_in + 1) + a.n_in] = 1.f;
-  }
+  std::vector<float> xo = normalised_inputs(nn, X, n);
   HIP_TRY(hipMemcpyAsync(w.H[0].ptr, xo.data(), xo.size() * sizeof(float), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(nn->Cb.ptr, C, size_t(n) * a.n_comb * sizeof(float), hipMemcpyHostToDevice, s));
   N::forward(nn->mlp, nn->theta.ptr, n, w, s);
@@ -329,14 +343,78 @@ int ieti_nn_predict(ieti_nn* nn, const float* X, const float* C, int64_t n, floa
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(pred, w.pred.ptr, size_t(n) * a.n_out * sizeof(float), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (nn->out_scale != 1.0)
+    for (int64_t i = 0; i < n * a.n_out; ++i) pred[i] = float(double(pred[i]) * nn->out_scale);
+  return IETI_OK;
+}
+
+int ieti_nn_init_params(ieti_nn* nn, uint64_t seed) {
+  if (!nn) return fail(IETI_ERR_INVALID_ARG, "network is NULL");
+  const auto& m = nn->mlp;
+  std::vector<float> theta(size_t(m.n_params), 0.f);
+  uint64_t state = seed;
+  for (int l = 1; l < int(m.dims.size()); ++l) {
+    const int64_t din = m.dims[l - 1], dout = m.dims[l];
+    const double lim = std::sqrt(6.0 / double(din + dout));
+    for (int64_t i = 0; i < dout; ++i)
+      for (int64_t j = 0; j < din; ++j) {
+        const double u = double(splitmix64(state) >> 11) * (1.0 / 9007199254740992.0);  // [0, 1), 53 bits
+        theta[size_t(m.woff[l - 1] + i * (din + 1) + j)] = float((2.0 * u - 1.0) * lim);
+      }
+  }
+  return ieti_nn_set_params(nn, theta.data());
+}
+
+int ieti_nn_set_normalisation(ieti_nn* nn, const float* shift, const float* scale, double out_scale) {
+  if (!nn) return fail(IETI_ERR_INVALID_ARG, "network is NULL");
+  const int64_t d = nn->mlp.arch.n_in;
+  if (!(out_scale > 0.0) || !std::isfinite(out_scale)) return fail(IETI_ERR_INVALID_ARG, "output scale must be > 0");
+  for (int64_t j = 0; j < d; ++j)
+    if ((shift && !std::isfinite(shift[j])) || (scale && !std::isfinite(scale[j])))
+      return fail(IETI_ERR_INVALID_ARG, "normalisation must be finite");
+  for (int64_t j = 0; j < d; ++j) {
+    nn->shift[j] = shift ? shift[j] : 0.f;
+    nn->scale[j] = scale ? scale[j] : 1.f;
+  }
+  nn->out_scale = out_scale;
+  return IETI_OK;
+}
+
+int ieti_nn_fit_normalisation(ieti_nn* nn, const float* X, const float* Y, int64_t n) {
+  if (!nn || !X || !Y || n < 1) return fail(IETI_ERR_INVALID_ARG, "NULL data or n < 1");
+  const int64_t d = nn->mlp.arch.n_in, no = nn->mlp.arch.n_out;
+  std::vector<float> sh(d), sc(d);
+  for (int64_t j = 0; j < d; ++j) {
+    double mean = 0.0, var = 0.0;
+    for (int64_t i = 0; i < n; ++i) mean += X[i * d + j];
+    mean /= double(n);
+    for (int64_t i = 0; i < n; ++i) var += (X[i * d + j] - mean) * (X[i * d + j] - mean);
+    const double sd = std::sqrt(var / double(n));
+    sh[j] = float(mean);
+    sc[j] = float(sd > 1e-12 ? 1.0 / sd : 1.0);
+  }
+  double sq = 0.0;
+  for (int64_t i = 0; i < n * no; ++i) sq += double(Y[i]) * double(Y[i]);
+  const double rms = std::sqrt(sq / double(n * no));
+  return ieti_nn_set_normalisation(nn, sh.data(), sc.data(), rms > 0.0 && std::isfinite(rms) ? rms : 1.0);
+}
+
+int ieti_nn_get_normalisation(const ieti_nn* nn, float* shift, float* scale, double* out_scale) {
+  if (!nn) return fail(IETI_ERR_INVALID_ARG, "network is NULL");
+  if (shift) std::copy(nn->shift.begin(), nn->shift.end(), shift);
+  if (scale) std::copy(nn->scale.begin(), nn->scale.end(), scale);
+  if (out_scale) *out_scale = nn->out_scale;
   return IETI_OK;
 }
 
 void ieti_nn_destroy(ieti_nn* nn) { delete nn; }
 
 // File: 8-byte tag, the five int32 sizes of ieti_nn_arch, the int64
-// parameter count, the parameters as FP32 (host byte order).
-static const char kNNTag[8] = {'I', 'E', 'T', 'I', 'N', 'N', '0', '1'};
+// parameter count, the parameters as FP32, then (version 02) the n_in
+// feature shifts and scales as FP32 and the output scale as FP64 (host byte
+// order).  Version 01 files (no normalisation) load with the identity.
+static const char kNNTag[8] = {'I', 'E', 'T', 'I', 'N', 'N', '0', '2'};
+static const char kNNTag1[8] = {'I', 'E', 'T', 'I', 'N', 'N', '0', '1'};
 
 int ieti_nn_save(const ieti_nn* nn, const char* path) {
   if (!nn || !path) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
@@ -350,7 +428,10 @@ int ieti_nn_save(const ieti_nn* nn, const char* path) {
   const int64_t n = nn->mlp.n_params;
   bool ok = std::fwrite(kNNTag, 1, 8, f) == 8 && std::fwrite(sizes, sizeof(int32_t), 5, f) == 5 &&
             std::fwrite(&n, sizeof(int64_t), 1, f) == 1 &&
-            std::fwrite(theta.data(), sizeof(float), theta.size(), f) == theta.size();
+            std::fwrite(theta.data(), sizeof(float), theta.size(), f) == theta.size() &&
+            std::fwrite(nn->shift.data(), sizeof(float), nn->shift.size(), f) == nn->shift.size() &&
+            std::fwrite(nn->scale.data(), sizeof(float), nn->scale.size(), f) == nn->scale.size() &&
+            std::fwrite(&nn->out_scale, sizeof(double), 1, f) == 1;
   ok = (std::fclose(f) == 0) && ok;
   if (!ok) return fail(IETI_ERR_INVALID_ARG, std::string("writing ") + path + " failed");
   return IETI_OK;
@@ -364,21 +445,27 @@ int ieti_nn_load(const char* path, ieti_nn** out) {
   char tag[8];
   int32_t sizes[5];
   int64_t n = -1;
-  bool ok = std::fread(tag, 1, 8, f) == 8 && std::equal(tag, tag + 8, kNNTag) &&
+  bool ok = std::fread(tag, 1, 8, f) == 8 && (std::equal(tag, tag + 8, kNNTag) || std::equal(tag, tag + 8, kNNTag1)) &&
             std::fread(sizes, sizeof(int32_t), 5, f) == 5 && std::fread(&n, sizeof(int64_t), 1, f) == 1;
+  const bool v2 = ok && std::equal(tag, tag + 8, kNNTag);
   ieti_nn_arch a{sizes[0], sizes[1], sizes[2], sizes[3], sizes[4]};
   ieti::nn::Mlp check;
   if (!ok || check.init(&a) != IETI_OK || check.n_params != n) {
     std::fclose(f);
     return fail(IETI_ERR_INVALID_ARG, std::string(path) + " is not a network file of this library");
   }
-  std::vector<float> theta(static_cast<size_t>(n));
+  std::vector<float> theta(static_cast<size_t>(n)), sh(size_t(a.n_in), 0.f), sc(size_t(a.n_in), 1.f);
+  double osc = 1.0;
   ok = std::fread(theta.data(), sizeof(float), theta.size(), f) == theta.size();
+  if (ok && v2)
+    ok = std::fread(sh.data(), sizeof(float), sh.size(), f) == sh.size() &&
+         std::fread(sc.data(), sizeof(float), sc.size(), f) == sc.size() && std::fread(&osc, sizeof(double), 1, f) == 1;
   std::fclose(f);
   if (!ok) return fail(IETI_ERR_INVALID_ARG, std::string(path) + " is truncated");
   ieti_nn* nn = nullptr;
   int rc = ieti_nn_create(&a, &nn);
   if (!rc) rc = ieti_nn_set_params(nn, theta.data());
+  if (!rc) rc = ieti_nn_set_normalisation(nn, sh.data(), sc.data(), osc);
   if (rc) {
     ieti_nn_destroy(nn);
     return rc;
@@ -387,12 +474,88 @@ int ieti_nn_load(const char* path, ieti_nn** out) {
   return IETI_OK;
 }
 
+// Dataset file: 8-byte tag, int32 n_in, n_comb, n_out, then rows of
+// n_in + n_comb + n_out FP32 values (features, coefficients, targets).
+static const char kDSTag[8] = {'I', 'E', 'T', 'I', 'D', 'S', '0', '1'};
+
+int ieti_nn_dataset_append(const char* path, const float* X, const float* C, const float* Y, int64_t n, int32_t n_in,
+                           int32_t n_comb, int32_t n_out) {
+  if (!path || !X || !C || !Y || n < 1 || n_in < 1 || n_comb < 1 || n_out < 1)
+    return fail(IETI_ERR_INVALID_ARG, "NULL argument or empty rows");
+  int32_t sz[3] = {0, 0, 0};
+  FILE* f = std::fopen(path, "rb");
+  bool fresh = f == nullptr;
+  if (f) {
+    char tag[8];
+    const bool ok = std::fread(tag, 1, 8, f) == 8 && std::equal(tag, tag + 8, kDSTag) &&
+                    std::fread(sz, sizeof(int32_t), 3, f) == 3;
+    std::fclose(f);
+    if (!ok) return fail(IETI_ERR_INVALID_ARG, std::string(path) + " is not a dataset file of this library");
+    if (sz[0] != n_in || sz[1] != n_comb || sz[2] != n_out)
+      return fail(IETI_ERR_INVALID_ARG, std::string(path) + " holds rows of other sizes");
+  }
+  f = std::fopen(path, fresh ? "wb" : "ab");
+  if (!f) return fail(IETI_ERR_INVALID_ARG, std::string("cannot open ") + path + " for writing");
+  bool ok = true;
+  if (fresh) {
+    const int32_t h[3] = {n_in, n_comb, n_out};
+    ok = std::fwrite(kDSTag, 1, 8, f) == 8 && std::fwrite(h, sizeof(int32_t), 3, f) == 3;
+  }
+  for (int64_t i = 0; i < n && ok; ++i)
+    ok = std::fwrite(X + i * n_in, sizeof(float), size_t(n_in), f) == size_t(n_in) &&
+         std::fwrite(C + i * n_comb, sizeof(float), size_t(n_comb), f) == size_t(n_comb) &&
+         std::fwrite(Y + i * n_out, sizeof(float), size_t(n_out), f) == size_t(n_out);
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(IETI_ERR_INVALID_ARG, std::string("writing ") + path + " failed");
+  return IETI_OK;
+}
+
+int ieti_nn_train_file(const char* dataset_path, const ieti_nn_arch* arch, const ieti_nn_train_opts* opts,
+                       const char* model_out, double* epoch_loss) {
+  if (!dataset_path || !arch || !opts || !model_out) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  FILE* f = std::fopen(dataset_path, "rb");
+  if (!f) return fail(IETI_ERR_INVALID_ARG, std::string("cannot open ") + dataset_path);
+  char tag[8];
+  int32_t sz[3];
+  bool ok = std::fread(tag, 1, 8, f) == 8 && std::equal(tag, tag + 8, kDSTag) && std::fread(sz, sizeof(int32_t), 3, f) == 3;
+  if (!ok || sz[0] != arch->n_in || sz[1] != arch->n_comb || sz[2] != arch->n_out) {
+    std::fclose(f);
+    return fail(IETI_ERR_INVALID_ARG, std::string(dataset_path) + " is not a dataset for this architecture");
+  }
+  const size_t w = size_t(sz[0]) + size_t(sz[1]) + size_t(sz[2]);
+  std::vector<float> rows;
+  std::vector<float> buf(w);
+  while (std::fread(buf.data(), sizeof(float), w, f) == w) rows.insert(rows.end(), buf.begin(), buf.end());
+  std::fclose(f);
+  const int64_t n = int64_t(rows.size() / w);
+  if (n < 1) return fail(IETI_ERR_INVALID_ARG, std::string(dataset_path) + " holds no rows");
+  std::vector<float> X(size_t(n) * sz[0]), C(size_t(n) * sz[1]), Y(size_t(n) * sz[2]);
+  for (int64_t i = 0; i < n; ++i) {
+    const float* r = rows.data() + size_t(i) * w;
+    std::copy(r, r + sz[0], X.begin() + i * sz[0]);
+    std::copy(r + sz[0], r + sz[0] + sz[1], C.begin() + i * sz[1]);
+    std::copy(r + sz[0] + sz[1], r + w, Y.begin() + i * sz[2]);
+  }
+  ieti_nn* nn = nullptr;
+  int rc = ieti_nn_create(arch, &nn);
+  if (!rc) rc = ieti_nn_init_params(nn, opts->seed);
+  if (!rc) rc = ieti_nn_fit_normalisation(nn, X.data(), Y.data(), n);
+  if (!rc) rc = ieti_nn_set_data(nn, X.data(), C.data(), Y.data(), n);
+  if (!rc) rc = ieti_nn_train(nn, opts, epoch_loss);
+  if (!rc) rc = ieti_nn_save(nn, model_out);
+  ieti_nn_destroy(nn);
+  return rc;
+}
+
 }  // extern "C"
 
 // used by the solver to copy a network's parameters
 namespace ieti {
 namespace nn {
 const Mlp& mlp_of(const ieti_nn* nn) { return nn->mlp; }
+const std::vector<float>& shift_of(const ieti_nn* nn) { return nn->shift; }
+const std::vector<float>& scale_of(const ieti_nn* nn) { return nn->scale; }
+double out_scale_of(const ieti_nn* nn) { return nn->out_scale; }
 const float* params_of(const ieti_nn* nn) { return nn->theta.ptr; }
 hipStream_t stream_of(const ieti_nn* nn) { return nn->stream; }
 }  // namespace nn

@@ -43,6 +43,9 @@ namespace ieti {
 namespace nn {
 // accessors of a network object (defined with it)
 const Mlp& mlp_of(const ieti_nn* nn);
+const std::vector<float>& shift_of(const ieti_nn* nn);
+const std::vector<float>& scale_of(const ieti_nn* nn);
+double out_scale_of(const ieti_nn* nn);
 const float* params_of(const ieti_nn* nn);
 hipStream_t stream_of(const ieti_nn* nn);
 }  // namespace nn

@@ -86,10 +86,27 @@ class Stats(C.Structure):
         ("rel_residual0", C.c_double),
         ("warm_start", C.c_int32),
         ("reserved", C.c_int32),
+        ("pcg_bytes", C.c_double),
     ]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ProblemStats(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int32), ("outer_iters", C.c_int32), ("status", C.c_int32), ("warm_start", C.c_int32),
+        ("f_applies", C.c_int32 * 2), ("m_applies", C.c_int32 * 2),
+        ("rel_residual", C.c_double), ("rel_residual0", C.c_double), ("block_entries", C.c_double),
+        ("bytes_F", C.c_double * 2), ("bytes_M", C.c_double * 2), ("pcg_bytes", C.c_double),
+    ]
+
+    def as_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
 
 
 class NNArch(C.Structure):
@@ -105,9 +122,8 @@ class NNTrainOpts(C.Structure):
 class WarmLayout(C.Structure):
     _fields_ = [
         ("n_facets", C.c_int32), ("n_feat", C.c_int32), ("n_comb", C.c_int32), ("n_out", C.c_int32),
-        ("feat_patch", C.POINTER(C.c_int32)), ("feat_shift", C.POINTER(C.c_float)),
-        ("feat_scale", C.POINTER(C.c_float)), ("comb_patch", C.POINTER(C.c_int32)),
-        ("out_row", C.POINTER(C.c_int32)), ("out_sign", C.POINTER(C.c_int8)), ("out_scale", C.c_double),
+        ("feat_patch", C.POINTER(C.c_int32)), ("comb_patch", C.POINTER(C.c_int32)),
+        ("out_row", C.POINTER(C.c_int32)), ("out_sign", C.POINTER(C.c_int8)),
     ]
 
 
@@ -119,6 +135,9 @@ EXPORTS = [
     "ieti_nn_set_params", "ieti_nn_get_params", "ieti_nn_set_data", "ieti_nn_loss_grad", "ieti_nn_train",
     "ieti_nn_predict", "ieti_nn_destroy", "ieti_get_gemv_tuning", "ieti_assemble_batch", "ieti_get_batch_info",
     "ieti_batch_of", "ieti_record_pcg", "ieti_get_pcg_coefficients", "ieti_nn_save", "ieti_nn_load",
+    "ieti_get_problem_stats", "ieti_nn_init_params", "ieti_nn_set_normalisation", "ieti_nn_fit_normalisation",
+    "ieti_nn_get_normalisation", "ieti_nn_dataset_append", "ieti_nn_train_file", "ieti_warm_rows",
+    "ieti_warm_append", "ieti_warm_load", "ieti_warm_predict", "ieti_get_condition",
 ]
 
 
@@ -172,6 +191,7 @@ def load_library():
     lib.ieti_nn_load.argtypes = [C.c_char_p, P(C.c_void_p)]
     lib.ieti_get_pcg_coefficients.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double), P(C.c_int32)]
     lib.ieti_get_batch_info.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_double)]
+    lib.ieti_get_problem_stats.argtypes = [C.c_void_p, C.c_int32, P(ProblemStats)]
     lib.ieti_get_gemv_tuning.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_float)]
     lib.ieti_set_coefficients.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
     lib.ieti_set_warm_start.argtypes = [C.c_void_p, C.c_void_p, P(WarmLayout)]
@@ -185,6 +205,18 @@ def load_library():
     lib.ieti_nn_predict.argtypes = [C.c_void_p, P(C.c_float), P(C.c_float), C.c_int64, P(C.c_float)]
     lib.ieti_nn_destroy.argtypes = [C.c_void_p]
     lib.ieti_nn_destroy.restype = None
+    lib.ieti_nn_init_params.argtypes = [C.c_void_p, C.c_uint64]
+    lib.ieti_nn_set_normalisation.argtypes = [C.c_void_p, P(C.c_float), P(C.c_float), C.c_double]
+    lib.ieti_nn_fit_normalisation.argtypes = [C.c_void_p, P(C.c_float), P(C.c_float), C.c_int64]
+    lib.ieti_nn_get_normalisation.argtypes = [C.c_void_p, P(C.c_float), P(C.c_float), P(C.c_double)]
+    lib.ieti_nn_dataset_append.argtypes = [C.c_char_p, P(C.c_float), P(C.c_float), P(C.c_float), C.c_int64,
+                                           C.c_int32, C.c_int32, C.c_int32]
+    lib.ieti_nn_train_file.argtypes = [C.c_char_p, P(NNArch), P(NNTrainOpts), C.c_char_p, P(C.c_double)]
+    lib.ieti_warm_rows.argtypes = [C.c_void_p, P(WarmLayout), P(C.c_float), P(C.c_float), P(C.c_float)]
+    lib.ieti_warm_append.argtypes = [C.c_void_p, P(WarmLayout), C.c_char_p]
+    lib.ieti_warm_load.argtypes = [C.c_void_p, C.c_char_p, P(WarmLayout)]
+    lib.ieti_warm_predict.argtypes = [C.c_void_p, P(C.c_double)]
+    lib.ieti_get_condition.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double)]
     for name in EXPORTS:
         if name not in ("ieti_destroy", "ieti_last_error", "ieti_nn_destroy"):
             getattr(lib, name).restype = C.c_int
@@ -365,26 +397,55 @@ class Solver:
         args = [None if v is None else _ptr(v, C.c_double) for v in self._coef]
         _check(self.lib, self.lib.ieti_set_coefficients(self.h, *args))
 
-    def set_warm_start(self, net, feat_patch, feat_shift, feat_scale, comb_patch, out_row, out_sign, out_scale):
-        """Attach a copy of ``net`` (an NN) with the row layout of the warm start."""
+    def _layout(self, feat_patch, comb_patch, out_row, out_sign):
         fp = np.ascontiguousarray(feat_patch, dtype=np.int32)
         cp = np.ascontiguousarray(comb_patch, dtype=np.int32)
         orow = np.ascontiguousarray(out_row, dtype=np.int32)
         osg = np.ascontiguousarray(out_sign, dtype=np.int8)
-        fsh = np.ascontiguousarray(feat_shift, dtype=np.float32)
-        fsc = np.ascontiguousarray(feat_scale, dtype=np.float32)
+        if fp.ndim != 2 or cp.ndim != 2 or orow.ndim != 2:
+            raise ValueError("layout arrays are [n_facets, k]")
+        if cp.shape[0] != fp.shape[0] or orow.shape != osg.shape or orow.shape[0] != fp.shape[0]:
+            raise ValueError("layout arrays disagree in the number of facets")
         L = WarmLayout()
         L.n_facets, L.n_feat = fp.shape
         L.n_comb = cp.shape[1]
         L.n_out = orow.shape[1]
-        if cp.shape[0] != fp.shape[0] or orow.shape != osg.shape or orow.shape[0] != fp.shape[0]:
-            raise ValueError("layout arrays disagree in the number of facets")
-        if fsh.shape != (L.n_feat,) or fsc.shape != (L.n_feat,):
-            raise ValueError("one shift and scale per feature expected")
-        L.feat_patch, L.feat_shift, L.feat_scale = _ptr(fp, C.c_int32), _ptr(fsh, C.c_float), _ptr(fsc, C.c_float)
-        L.comb_patch, L.out_row, L.out_sign = _ptr(cp, C.c_int32), _ptr(orow, C.c_int32), _ptr(osg, C.c_int8)
-        L.out_scale = float(out_scale)
+        L.feat_patch, L.comb_patch = _ptr(fp, C.c_int32), _ptr(cp, C.c_int32)
+        L.out_row, L.out_sign = _ptr(orow, C.c_int32), _ptr(osg, C.c_int8)
+        L._keep = (fp, cp, orow, osg)
+        return L
+
+    def set_warm_start(self, net, feat_patch, comb_patch, out_row, out_sign):
+        """Attach a copy of ``net`` (an NN, with its normalisation) and the row layout of the warm start."""
+        L = self._layout(feat_patch, comb_patch, out_row, out_sign)
         _check(self.lib, self.lib.ieti_set_warm_start(self.h, net.h, C.byref(L)))
+
+    def warm_rows(self, feat_patch, comb_patch, out_row, out_sign, targets=True):
+        """(X, C, Y) network rows of the current coefficients and, with
+        ``targets``, of the last solve's multipliers (``ieti_warm_rows``)."""
+        L = self._layout(feat_patch, comb_patch, out_row, out_sign)
+        X = np.zeros((L.n_facets, L.n_feat), np.float32)
+        Cc = np.zeros((L.n_facets, L.n_comb), np.float32)
+        Y = np.zeros((L.n_facets, L.n_out), np.float32)
+        _check(self.lib, self.lib.ieti_warm_rows(self.h, C.byref(L), _ptr(X, C.c_float), _ptr(Cc, C.c_float),
+                                                 _ptr(Y, C.c_float) if targets else None))
+        return X, Cc, (Y if targets else None)
+
+    def warm_append(self, path, feat_patch, comb_patch, out_row, out_sign):
+        """Append the last solve's rows to a dataset file (``ieti_warm_append``)."""
+        L = self._layout(feat_patch, comb_patch, out_row, out_sign)
+        _check(self.lib, self.lib.ieti_warm_append(self.h, C.byref(L), os.fsencode(path)))
+
+    def warm_load(self, model_path, feat_patch, comb_patch, out_row, out_sign):
+        """Load a network file and attach it (``ieti_warm_load``)."""
+        L = self._layout(feat_patch, comb_patch, out_row, out_sign)
+        _check(self.lib, self.lib.ieti_warm_load(self.h, os.fsencode(model_path), C.byref(L)))
+
+    def warm_predict(self):
+        """The attached network's lambda_0 for the current coefficients (``ieti_warm_predict``)."""
+        lam = np.zeros(self.m_r)
+        _check(self.lib, self.lib.ieti_warm_predict(self.h, _ptr(lam, C.c_double)))
+        return lam
 
     def _solve_opts(self, rtol, maxit, lambda0, check_every, use_graph=True, warm_start=False):
         o = SolveOpts()
@@ -458,11 +519,17 @@ class Solver:
         _check(self.lib, self.lib.ieti_set_profiling(self.h, 1 if enable else 0))
 
     def kernel_times(self):
-        v = np.zeros(8)
+        v = np.zeros(12)
         _check(self.lib, self.lib.ieti_get_kernel_times(self.h, _ptr(v, C.c_double)))
         keys = ["gemv_launches", "gemv_ms", "update_launches", "update_ms", "update_tasks", "gemv_bytes",
-                "gemv_bytes_full", "gemv_bytes_lower"]
+                "gemv_bytes_full", "gemv_bytes_lower", "gemv_bytes_alg", "gemv32_launches", "gemv32_ms"]
         return dict(zip(keys, v.tolist()))
+
+    def problem_stats(self, prob=0):
+        """Per-problem results of the last solve (``ieti_get_problem_stats``)."""
+        st = ProblemStats()
+        _check(self.lib, self.lib.ieti_get_problem_stats(self.h, int(prob), C.byref(st)))
+        return st.as_dict()
 
     def lambda_(self):
         lam = np.zeros(self.m_r)
@@ -485,18 +552,11 @@ class Solver:
 
     def condition(self, prob=0):
         """(lambda_min, lambda_max) of the Lanczos tridiagonal of the recorded
-        PCG run: extreme eigenvalues of the preconditioned interface operator."""
-        a, b = self.pcg_coefficients(prob)
-        k = len(a)
-        if k == 0:
-            return 1.0, 1.0
-        T = np.diag(1.0 / a)
-        T[np.arange(1, k), np.arange(1, k)] += b[:k - 1] / a[:k - 1]
-        off = np.sqrt(b[:k - 1]) / a[:k - 1]
-        T[np.arange(k - 1), np.arange(1, k)] = off
-        T[np.arange(1, k), np.arange(k - 1)] = off
-        ev = np.linalg.eigvalsh(T)
-        return float(ev.min()), float(ev.max())
+        PCG run: extreme eigenvalues of the preconditioned interface operator
+        (``ieti_get_condition``)."""
+        lo, hi = C.c_double(), C.c_double()
+        _check(self.lib, self.lib.ieti_get_condition(self.h, int(prob), C.byref(lo), C.byref(hi)))
+        return float(lo.value), float(hi.value)
 
 
 class NN:
@@ -546,6 +606,32 @@ class NN:
         except Exception:
             pass
 
+    def init_params(self, seed):
+        """Seeded Glorot-uniform weights and zero biases (``ieti_nn_init_params``)."""
+        _check(self.lib, self.lib.ieti_nn_init_params(self.h, int(seed)))
+
+    def set_normalisation(self, shift=None, scale=None, out_scale=1.0):
+        n_in = self.arch[0]
+        self._norm = [None if v is None else np.ascontiguousarray(v, dtype=np.float32).reshape(n_in)
+                      for v in (shift, scale)]
+        args = [None if v is None else _ptr(v, C.c_float) for v in self._norm]
+        _check(self.lib, self.lib.ieti_nn_set_normalisation(self.h, *args, float(out_scale)))
+
+    def fit_normalisation(self, X, Y):
+        """Feature means / inverse deviations and output RMS of the rows (``ieti_nn_fit_normalisation``)."""
+        n_in, _, _, _, n_out = self.arch
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, n_in)
+        Y = np.ascontiguousarray(Y, dtype=np.float32).reshape(X.shape[0], n_out)
+        _check(self.lib, self.lib.ieti_nn_fit_normalisation(self.h, _ptr(X, C.c_float), _ptr(Y, C.c_float),
+                                                            X.shape[0]))
+
+    def normalisation(self):
+        n_in = self.arch[0]
+        sh, sc, o = np.zeros(n_in, np.float32), np.zeros(n_in, np.float32), C.c_double()
+        _check(self.lib, self.lib.ieti_nn_get_normalisation(self.h, _ptr(sh, C.c_float), _ptr(sc, C.c_float),
+                                                            C.byref(o)))
+        return sh, sc, float(o.value)
+
     def set_params(self, theta):
         theta = np.ascontiguousarray(theta, dtype=np.float32)
         if theta.shape != (self.n_params,):
@@ -589,3 +675,27 @@ class NN:
         _check(self.lib, self.lib.ieti_nn_predict(self.h, _ptr(X, C.c_float), _ptr(Cc, C.c_float), n,
                                                   _ptr(out, C.c_float)))
         return out
+
+
+def dataset_append(path, X, Cc, Y):
+    """Append rows to a dataset file (``ieti_nn_dataset_append``)."""
+    lib = load_library()
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n = X.shape[0]
+    Cc = np.ascontiguousarray(Cc, dtype=np.float32).reshape(n, -1)
+    Y = np.ascontiguousarray(Y, dtype=np.float32).reshape(n, -1)
+    _check(lib, lib.ieti_nn_dataset_append(os.fsencode(path), _ptr(X, C.c_float), _ptr(Cc, C.c_float),
+                                           _ptr(Y, C.c_float), n, X.shape[1], Cc.shape[1], Y.shape[1]))
+
+
+def train_file(dataset_path, arch, model_out, epochs, lr, batch=256, seed=0, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Train a network of ``arch`` = (n_in, n_hidden, n_layers, n_comb, n_out)
+    on a dataset file and write it to ``model_out`` (``ieti_nn_train_file``);
+    returns the epoch losses."""
+    lib = load_library()
+    a = NNArch(*[int(v) for v in arch])
+    o = NNTrainOpts(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps), int(seed))
+    losses = np.zeros(max(int(epochs), 1))
+    _check(lib, lib.ieti_nn_train_file(os.fsencode(dataset_path), C.byref(a), C.byref(o), os.fsencode(model_out),
+                                       _ptr(losses, C.c_double)))
+    return losses[:int(epochs)]

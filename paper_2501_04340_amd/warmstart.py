@@ -11,10 +11,12 @@ the lower sector.  Every facet of the ring has the same multiplier pattern
 (checked here), so one set of weights serves all facets.
 
 The library does the data generation (assembly with new coefficients,
-factorisation, solve), the training (forward, backward and Adam kernels)
-and the inference inside ``ieti_solve``.  This module marshals arrays:
-edge-id decoding for the layout, the feature normalisation and the seeded
-initial weights, which are inputs of the training.
+factorisation, solve, and the network rows: log-reluctivity features,
+coefficients, signed multiplier targets), the normalisation of the rows,
+the seeded initial weights, the training (forward, backward and Adam
+kernels) and the inference inside ``ieti_solve``.  This module only builds
+the layout (which patches feed a facet's row, which multiplier rows it
+predicts) from the problem's numbering and marshals arrays.
 """
 from __future__ import annotations
 
@@ -22,7 +24,7 @@ import time
 
 import numpy as np
 
-from .ietidp import NN
+from .ietidp import NN, train_file
 
 
 def decode_edges(edge_ids, patches, periodic, degree, n_el):
@@ -103,69 +105,63 @@ class RingWarmStart:
         self.n_comb = self.P2
         self.net = None
 
-    # ---- rows of the network
-    def features(self, nu):
-        return np.log(np.asarray(nu, dtype=np.float64))[self.feat_patch]
-
-    def coefficients(self, load_scale):
-        return np.asarray(load_scale, dtype=np.float64)[self.comb_patch]
-
-    def targets(self, lam):
-        return self.out_sign * np.asarray(lam)[self.out_row]
+    def layout(self):
+        return self.feat_patch, self.comb_patch, self.out_row, self.out_sign
 
     # ---- data from the solver itself
-    def generate(self, draws, rtol=1e-10, log=None):
-        """Solve every (nu, load_scale) draw; returns features, coefficients,
-        targets and the solve statistics."""
+    def generate(self, draws, rtol=1e-10, log=None, dataset=None):
+        """Solve every (nu, load_scale) draw; returns the network rows
+        (features, coefficients, targets) built by the library from each
+        solve, and the solve statistics.  With ``dataset`` the rows are also
+        appended to that dataset file."""
         X, Cc, T, stats = [], [], [], []
         t0 = time.perf_counter()
         for i, (nu, scale) in enumerate(draws):
             self.solver.set_coefficients(nu, scale)
             self.solver.factor()
             _, st = self.solver.solve(rtol=rtol, maxit=5000)
-            lam = self.solver.lambda_()
-            X.append(self.features(nu))
-            Cc.append(self.coefficients(scale))
-            T.append(self.targets(lam))
+            x, c, y = self.solver.warm_rows(*self.layout())
+            if dataset is not None:
+                self.solver.warm_append(dataset, *self.layout())
+            X.append(x)
+            Cc.append(c)
+            T.append(y)
             stats.append(st)
             if log and (i + 1) % 32 == 0:
                 log(f"generated {i + 1}/{len(draws)} solves ({time.perf_counter() - t0:.1f}s)")
         return np.array(X), np.array(Cc), np.array(T), stats
 
     # ---- training
-    def init_params(self, seed):
-        """Glorot-uniform weights and zero biases, seeded; layout of ieti_nn."""
-        rng = np.random.default_rng(seed)
-        dims = [self.n_feat] + [self.hidden] * self.layers + [self.n_comb * self.n_out]
-        parts = []
-        for a, b in zip(dims[:-1], dims[1:]):
-            lim = np.sqrt(6.0 / (a + b))
-            W = np.zeros((b, a + 1))
-            W[:, :a] = rng.uniform(-lim, lim, size=(b, a))
-            parts.append(W.ravel())
-        return np.concatenate(parts).astype(np.float32)
+    def arch(self):
+        return (self.n_feat, self.hidden, self.layers, self.n_comb, self.n_out)
 
     def fit(self, X, Cc, T, epochs=200, lr=1e-3, batch=256, seed=0):
-        """Normalise, initialise and train on the GPU; returns the epoch losses."""
-        Xf = X.reshape(-1, self.n_feat)
-        self.shift = Xf.mean(axis=0)
-        sd = Xf.std(axis=0)
-        self.scale = 1.0 / np.where(sd > 1e-12, sd, 1.0)
-        self.out_scale = float(np.sqrt(np.mean(T ** 2))) or 1.0
-        Xn = (Xf - self.shift) * self.scale
-        self.net = NN(self.n_feat, self.hidden, self.layers, self.n_comb, self.n_out)
-        self.net.set_params(self.init_params(seed))
-        self.net.set_data(Xn, Cc.reshape(-1, self.n_comb), T.reshape(-1, self.n_out) / self.out_scale)
+        """Seeded initial weights, normalisation fitted to the rows, Adam on
+        the GPU (all in the library); returns the epoch losses."""
+        Xf = np.asarray(X, dtype=np.float32).reshape(-1, self.n_feat)
+        Cf = np.asarray(Cc, dtype=np.float32).reshape(-1, self.n_comb)
+        Tf = np.asarray(T, dtype=np.float32).reshape(-1, self.n_out)
+        self.net = NN(*self.arch())
+        self.net.init_params(seed)
+        self.net.fit_normalisation(Xf, Tf)
+        self.net.set_data(Xf, Cf, Tf)
         return self.net.train(epochs, lr, batch=batch, seed=seed)
+
+    def fit_file(self, dataset, model_out, epochs=200, lr=1e-3, batch=256, seed=0):
+        """The same training from a dataset file written by ``generate``;
+        the trained network is written to ``model_out`` and loaded."""
+        losses = train_file(dataset, self.arch(), model_out, epochs, lr, batch=batch, seed=seed)
+        self.net = NN.load(model_out)
+        return losses
 
     # ---- persistence
     def save(self, prefix):
-        """The trained network (``prefix + '.net'``, the library's file) and
-        the normalisation of its rows (``prefix + '.npz'``).  The facet layout
-        itself follows from the problem and is rebuilt on load."""
+        """The trained network with its normalisation (``prefix + '.net'``,
+        the library's file) and the layout parameters (``prefix + '.npz'``);
+        the facet layout itself follows from the problem and is rebuilt on
+        load."""
         self.net.save(str(prefix) + ".net")
-        np.savez(str(prefix) + ".npz", shift=self.shift, scale=self.scale, out_scale=self.out_scale,
-                 window=self.window, hidden=self.hidden, layers=self.layers)
+        np.savez(str(prefix) + ".npz", window=self.window, hidden=self.hidden, layers=self.layers)
 
     @classmethod
     def load(cls, solver, prob, prefix):
@@ -173,21 +169,15 @@ class RingWarmStart:
         z = np.load(str(prefix) + ".npz", allow_pickle=False)
         self = cls(solver, prob, window=int(z["window"]), hidden=int(z["hidden"]), layers=int(z["layers"]))
         net = NN.load(str(prefix) + ".net")
-        if net.arch != (self.n_feat, self.hidden, self.layers, self.n_comb, self.n_out):
+        if net.arch != self.arch():
             raise ValueError("the saved network does not fit this problem's layout")
         self.net = net
-        self.shift, self.scale = z["shift"], z["scale"]
-        self.out_scale = float(z["out_scale"])
         return self
 
     def attach(self, solver=None):
-        (solver or self.solver).set_warm_start(self.net, self.feat_patch, self.shift, self.scale, self.comb_patch,
-                                               self.out_row, self.out_sign, self.out_scale)
+        (solver or self.solver).set_warm_start(self.net, *self.layout())
 
-    def predict_lambda(self, nu, load_scale):
-        """The multipliers the attached network predicts (host copy), for tests."""
-        Xn = (self.features(nu) - self.shift) * self.scale
-        pred = self.net.predict(Xn, self.coefficients(load_scale)).astype(np.float64)
-        lam = np.zeros(self.solver.m_r)
-        lam[self.out_row] = self.out_scale * self.out_sign * pred
-        return lam
+    def predict_lambda(self, solver=None):
+        """The multipliers the attached network predicts for the solver's
+        current coefficients (host copy, ``ieti_warm_predict``), for tests."""
+        return (solver or self.solver).warm_predict()

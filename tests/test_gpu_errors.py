@@ -1,0 +1,125 @@
+"""Error returns of the library on the GPU: every condition is forced from
+the host with valid inputs, every kernel exits normally, and the handle
+stays usable afterwards.
+
+* IETI_ERR_NOT_SPD: a local stiffness that is numerically singular (a patch
+  with reluctivity 1e-300 next to one with 1: its pivots fall below the
+  factorisation's threshold, 1e-13 of the largest diagonal entry of K_rr);
+  the message names the subdomain, and in a batch its problem.
+* IETI_ERR_NOT_CONVERGED: maxit = 2 at rtol 1e-12; outputs and per-problem
+  statistics are still filled, single and batched.
+* IETI_ERR_BREAKDOWN: initial multipliers that are not finite make the first
+  step's p^T F p not positive.
+"""
+import numpy as np
+import pytest
+
+from paper_2501_04340_amd.ietidp import IetiError
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def _bad_nu_problem():
+    P = (3, 1, 1)
+    return configs.box_problem(P, 2, 2, np.array([0, 1, 1], dtype=np.int32), np.array([1.0, 1.0, 1e-300]),
+                               lambda x: np.ones_like(x))
+
+
+def test_numerically_singular_stiffness_is_not_spd(ietilib):
+    from paper_2501_04340_amd import Solver
+    print("[gpu-errors] NOT_SPD single", flush=True)
+    S = Solver(_bad_nu_problem())
+    try:
+        with pytest.raises(IetiError, match="NOT_SPD") as e:
+            S.factor()
+        assert e.value.code == -4 and "subdomain 1" in str(e.value)
+        # the same handle with an admissible reluctivity factors and solves
+        S.set_coefficients(np.ones(3), None)
+        S.factor()
+        _, st = S.solve(rtol=1e-10)
+        assert st["status"] == 0
+    finally:
+        S.close()
+
+
+def test_not_spd_names_the_problem_of_a_batch(ietilib):
+    from paper_2501_04340_amd import Solver
+    print("[gpu-errors] NOT_SPD batch", flush=True)
+    good = Solver(configs.cube8())
+    bad = Solver(_bad_nu_problem())
+    B = Solver.batch_of([good, bad])
+    good.close()
+    bad.close()
+    try:
+        with pytest.raises(IetiError, match="NOT_SPD") as e:
+            B.factor()
+        assert "subdomain 1 of problem 1" in str(e.value)
+    finally:
+        B.close()
+
+
+def test_not_converged_fills_outputs_and_status(ietilib):
+    from paper_2501_04340_amd import Solver
+    print("[gpu-errors] NOT_CONVERGED", flush=True)
+    S = Solver(configs.cube8())
+    try:
+        S.factor()
+        with pytest.raises(IetiError, match="NOT_CONVERGED"):
+            S.solve(rtol=1e-12, maxit=2)
+        a, st = S.solve(rtol=1e-12, maxit=2, raise_on_nonconv=False)
+        assert st["status"] == -6 and st["iters"] == 2 and np.isfinite(st["rel_residual"]) and st["rel_residual"] > 1e-12
+        assert np.all(np.isfinite(a)) and np.abs(a).max() > 0
+        ps = S.problem_stats(0)
+        assert ps["status"] == -6 and ps["iters"] == 2
+        assert ps["f_applies"][0] == 2 and ps["m_applies"][0] == 3
+        lam = S.lambda_()
+        assert np.all(np.isfinite(lam))
+        # converged afterwards on the same handle
+        _, st2 = S.solve(rtol=1e-10)
+        assert st2["status"] == 0 and S.problem_stats(0)["status"] == 0
+    finally:
+        S.close()
+
+
+def test_not_converged_in_a_batch_is_per_problem(ietilib):
+    """A batch at maxit = 12: the small problem converges within it, the
+    other does not; the call reports NOT_CONVERGED and each problem's own
+    status and iteration count."""
+    from paper_2501_04340_amd import Solver
+    print("[gpu-errors] NOT_CONVERGED batch", flush=True)
+    a1 = Solver(configs.small_cube(P=(2, 1, 1), degree=2, n_el=2))
+    a2 = Solver(configs.cube64(degree=2, n_el=2))
+    B = Solver.batch_of([a1, a2])
+    try:
+        a1.factor()
+        _, st1 = a1.solve(rtol=1e-10)
+        n1 = st1["iters"]
+        B.factor()
+        maxit = n1 + 2
+        _, st = B.solve(rtol=1e-10, maxit=maxit, raise_on_nonconv=False)
+        assert st["status"] == -6
+        p0, p1 = B.problem_stats(0), B.problem_stats(1)
+        assert p0["status"] == 0 and p0["iters"] == n1 and p0["rel_residual"] <= 1e-10
+        assert p1["status"] == -6 and p1["iters"] == maxit
+        info = B.batch_info()
+        assert info[0]["iters"] == n1 and info[1]["iters"] == maxit
+    finally:
+        for s in (a1, a2, B):
+            s.close()
+
+
+def test_non_finite_initial_multipliers_break_down(ietilib):
+    from paper_2501_04340_amd import Solver
+    print("[gpu-errors] BREAKDOWN", flush=True)
+    S = Solver(configs.cube8())
+    try:
+        S.factor()
+        lam0 = np.full(S.m_r, np.nan)
+        with pytest.raises(IetiError, match="BREAKDOWN") as e:
+            S.solve(rtol=1e-10, lambda0=lam0)
+        assert e.value.code == -5 and "problem 0" in str(e.value)
+        _, st = S.solve(rtol=1e-10)
+        assert st["status"] == 0 and st["rel_residual"] <= 1e-10
+    finally:
+        S.close()

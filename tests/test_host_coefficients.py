@@ -77,11 +77,24 @@ def test_ring_layout_covers_every_multiplier_once(nominal):
     assert W.feat_patch.shape == (W.P0, 4 * W.P1 * W.P2) and W.n_out * W.P0 == S.m_r
 
 
-def test_targets_and_prediction_scatter_are_inverse(nominal):
+def test_library_builds_the_network_rows(nominal):
+    """ieti_warm_rows: the features are log(nu) of the layout's patches and the
+    coefficients the patches' load scales; the targets need a solve."""
     prob, S = nominal
     W = RingWarmStart(S, prob, window=1)
-    lam = np.random.default_rng(0).standard_normal(S.m_r)
-    T = W.targets(lam)
-    back = np.zeros(S.m_r)
-    back[W.out_row] = W.out_sign * T
-    assert np.array_equal(back, lam)
+    nu0 = np.array(prob.nu, dtype=np.float64)
+    nu = nu0 * np.linspace(0.8, 1.2, nu0.size)
+    scale = np.linspace(0.7, 1.3, nu0.size)
+    S.set_coefficients(nu, scale)
+    try:
+        X, Cc, _ = S.warm_rows(*W.layout(), targets=False)
+        np.testing.assert_allclose(X, np.log(nu)[W.feat_patch], rtol=1e-7, atol=1e-7)
+        assert np.array_equal(Cc, scale[W.comb_patch].astype(np.float32))
+        with pytest.raises(Exception, match="STATE"):
+            S.warm_rows(*W.layout())
+        bad = W.out_row.copy()
+        bad[0, 0] = bad[1, 0]
+        with pytest.raises(Exception, match="INVALID_ARG"):
+            S.warm_rows(W.feat_patch, W.comb_patch, bad, W.out_sign, targets=False)
+    finally:
+        S.set_coefficients(nu0, np.ones(nu0.size))
