@@ -78,6 +78,23 @@ def measured_traffic(kernel, workload):
     return None
 
 
+def factor_summary(info, factor_s):
+    """The factorisation's rate against the FP64 matrix peak, counted three
+    ways: the 64x64 tile products it executes (padding and tile-level fill
+    included), and the scalar Cholesky work sum_j c_j^2 in the same
+    elimination order, of K_rr alone (the method's local factorisations) and
+    with the augmented trailing rows that yield the explicit interface
+    blocks."""
+    out = {"factor_ms": factor_s * 1e3, "tile_flops": info["flops"],
+           "scalar_flops_krr": info["flops_scalar_rr"], "scalar_flops_augmented": info["flops_scalar_aug"]}
+    for key, f in (("tile", info["flops"]), ("scalar_krr", info["flops_scalar_rr"]),
+                   ("scalar_augmented", info["flops_scalar_aug"])):
+        tf = f / factor_s / 1e12 if factor_s > 0 else 0.0
+        out[f"{key}_tflops"] = tf
+        out[f"{key}_frac_fp64_mfma"] = tf / FP64_MFMA_PEAK_TFLOPS
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -351,6 +368,8 @@ def stream_batches(args):
     lat = {k: [] for k in variants}
     pcg_s = {k: 0.0 for k in variants}
     pcg_bytes = {k: 0.0 for k in variants}
+    fac_s = {k: 0.0 for k in variants}
+    plan_sum = {"flops": 0.0, "flops_scalar_rr": 0.0, "flops_scalar_aug": 0.0}
     applies = {k: 0 for k in variants}
     lat_single, t_single = [], 0.0
     iters = {k: [] for k in variants}
@@ -386,6 +405,9 @@ def stream_batches(args):
         for S in singles:
             S.close()
         info = B.batch_info()
+        pinfo = B.plan_info()
+        for key in plan_sum:
+            plan_sum[key] += pinfo[key]
         a_dev = torch.empty(B.n_edges, dtype=torch.float64, device="cuda")
         for name, prec in variants.items():
             # the headline variant runs W warm-up and K timed passes, the
@@ -405,6 +427,7 @@ def stream_batches(args):
                 lat[name].extend([dt * 1e3] * len(ids))
                 pcg_s[name] += st["t_pcg_s"]
                 pcg_bytes[name] += st["pcg_bytes"]
+                fac_s[name] += st["t_factor_s"]
                 applies[name] += st["f_applies"]
             ps = [B.problem_stats(p) for p in range(len(ids))]
             iters[name].extend(x["iters"] for x in ps)
@@ -505,6 +528,7 @@ def stream_batches(args):
         "speedup_batch_mixed_vs_batch_plain": vs["batch_mixed"]["solves_per_s"] / vs["batch_plain_fp64"]["solves_per_s"],
         "speedup_batch_mixed_vs_single_plain": (t_single * K) / t_var["batch_mixed"],
         "mixed_outer_iters_mean": float(np.mean(outer)) if outer else None,
+        "factorisation": factor_summary(plan_sum, fac_s["batch_mixed"] / K),
         "b_error_vs_oracle": b_err,
         "host_assembly_s": t_host,
         "roofline": roof,
@@ -708,6 +732,7 @@ def main():
         "f_applies_per_s": applies / pcg_s if pcg_s > 0 else None,
         "rel_residual": float(stats[-1]["rel_residual"]),
         "factor_tflops": info["flops"] / (factor_ms * 1e-3) / 1e12,
+        "factorisation": factor_summary(info, factor_ms * 1e-3),
         "roofline": roof,
         "gemv_autotune": {"fp64_shape": int(chosen[0]), "fp64_ms": [float(x) for x in tune_ms[0]],
                           "fp32_shape": int(chosen32[1]), "fp32_ms": [float(x) for x in tune_ms32[1]]},

@@ -280,7 +280,12 @@ int ieti_get_rhs(ieti_handle* h, double* b);
  * elements, algorithmic flops of the tile factorisation, flops of the same
  * factorisation done densely, sequential steps, update tasks, sum of n_I^2
  * (interface-block entries read per operator application), number of
- * interface slots (padded), max padded n_I, tile size}. */
+ * interface slots (padded), max padded n_I, tile size}, info[10..11] = the
+ * scalar work sum_j c_j^2 of the Cholesky factorisation in the same
+ * elimination order without tiles or padding (c_j: off-diagonal entries of
+ * column j of the factor), of K_rr alone (the local factorisations of
+ * Section 2.1) and with the augmented trailing rows that yield the explicit
+ * interface blocks.  info holds 12 doubles. */
 int ieti_get_plan_info(const ieti_handle* h, double* info);
 
 /* Kernel timing for roofline measurements.  enable = 1 clears the counters

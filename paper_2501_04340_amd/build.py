@@ -97,7 +97,7 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     rpath = ":".join(_runtime_dirs())
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-fopenmp", "-shared", "-o", tmp, *objs,
-           "-Wl,--disable-new-dtags", f"-Wl,-rpath,{rpath}"]
+           "-Wl,--disable-new-dtags", f"-Wl,-rpath,{rpath}", "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed:\n" + res.stdout + res.stderr)

@@ -10,6 +10,8 @@
 #include <type_traits>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "common.hpp"
 #include "device/kernels.hpp"
 #include "device/nn.hpp"
@@ -24,6 +26,15 @@ using ieti::rt::DBuf;
 using ieti::rt::dalloc;
 using ieti::rt::dupload;
 using ieti::rt::fail;
+
+// Named phase range for rocprofv3's marker trace (--marker-trace): pushed on
+// construction, popped when the scope ends.
+struct Phase {
+  explicit Phase(const char* name) { roctxRangePushA(name); }
+  ~Phase() { roctxRangePop(); }
+  Phase(const Phase&) = delete;
+  Phase& operator=(const Phase&) = delete;
+};
 
 }  // namespace
 
@@ -42,6 +53,12 @@ struct ieti_handle {
   // device buffers
   DBuf<double> piv_tol;  // per subdomain: pivot threshold of the factorisation
   DBuf<double> pool, inv, scatter_val, S, Sinv, Phi, SPi, Spi_glob, G, H, Ht, I_sign, b_aug0, y;
+  // coarse problem as a tile factorisation: its tile pool, diagonal-tile
+  // inverses, pivot thresholds (per problem), U = L_c^{-T} (dense per problem,
+  // at the offsets of Spi_glob) and the task lists of CoarsePlan
+  ieti::CoarsePlan cplan;
+  DBuf<double> cpool, cinv, ctol, Lti;
+  DBuf<int64_t> cfill, cpotrf, ctrsm, cupd, cupd_pair, cout_h, cout_l;
   DBuf<int64_t> scatter_dst, potrf, trsm, upd, upd_pair, copyS, xsinv, xphi, xspi, fdiag, ffull, ffull_pair, rec_task, rec_pair;
   DBuf<int64_t> bdiag, bupd, bupd_pair;
   DBuf<int64_t> spi_ptr, spi_src, row_src, I_aug, A_aug, slot_phi_row, dsrc_ptr, dsrc_idx, recP_pos, recP_glob;
@@ -129,12 +146,13 @@ struct ieti_handle {
   ~ieti_handle() {
     DBuf<double>* ds[] = {&piv_tol, &pool, &inv, &scatter_val, &S, &Sinv, &Phi, &SPi, &Spi_glob, &G, &H, &Ht, &I_sign, &b_aug0, &y,
                           &yj, &lam, &r, &z, &p, &q, &v, &b, &e, &dtil, &w, &t, &pglob, &part, &scal, &aout,
-                          &tmp, &xgp, &xgr, &part_g, &part_t, &lam_acc, &rtrue};
+                          &tmp, &xgp, &xgr, &part_g, &part_t, &lam_acc, &rtrue, &cpool, &cinv, &ctol, &Lti};
     for (auto* d : ds) d->release();
     DBuf<int64_t>* is[] = {&scatter_dst, &potrf, &trsm, &upd, &upd_pair, &copyS, &xsinv, &xphi, &xspi, &fdiag,
                            &ffull, &ffull_pair, &rec_task, &rec_pair, &bdiag, &bupd, &bupd_pair, &spi_ptr, &spi_src, &row_src, &I_aug, &A_aug, &slot_phi_row, &dsrc_ptr,
                            &dsrc_idx, &recP_pos, &recP_glob, &out_src, &out_edge, &primal_edges,
-                           &gemv_tasks[0], &gemv_tasks[1], &gemv_tasks[2]};
+                           &gemv_tasks[0], &gemv_tasks[1], &gemv_tasks[2], &cfill, &cpotrf, &ctrsm, &cupd,
+                           &cupd_pair, &cout_h, &cout_l};
     for (auto* d : is) d->release();
     I_row.release();
     I_sub.release();
@@ -477,6 +495,27 @@ int upload(ieti_handle* h) {
   UP(pd, h->pd_h);
   UP(blk, h->blk_h);
   UP(cprob, cprob_h);
+  {
+    std::vector<ieti::CoarseDims> cd(static_cast<size_t>(n_prob));
+    for (int p = 0; p < n_prob; ++p) {
+      const int64_t* d = &h->pd_h[size_t(D::PD_N) * p];
+      cd[size_t(p)].m = d[D::PD_MR1] - d[D::PD_MR0];
+      cd[size_t(p)].n = d[D::PD_NGP];
+      cd[size_t(p)].spi_off = d[D::PD_SPI];
+      cd[size_t(p)].g_off = d[D::PD_H];
+    }
+    ieti::build_coarse_plan(cd, D::TILE, h->cplan);
+    const auto& C = h->cplan;
+    UP(cfill, C.fill_task);
+    UP(cpotrf, C.potrf_task);
+    UP(ctrsm, C.trsm_task);
+    UP(cupd, C.upd_task);
+    UP(cupd_pair, C.upd_pair);
+    UP(cout_h, C.out_h_task);
+    UP(cout_l, C.out_l_task);
+    // only non-positive pivots are flagged in the coarse matrix
+    UP(ctol, std::vector<double>(size_t(n_prob), 0.0));
+  }
   h->B.pd = h->pd.ptr;
   h->B.blk = h->blk.ptr;
   h->B.n_prob = n_prob;
@@ -505,6 +544,9 @@ int upload(ieti_handle* h) {
   if ((rc = dalloc(h->Phi, std::max<int64_t>(P.Phi_elems, 1)))) return rc;
   if ((rc = dalloc(h->SPi, std::max<int64_t>(P.SPi_elems, 1)))) return rc;
   if ((rc = dalloc(h->Spi_glob, std::max<int64_t>(P.spi_off.back(), 1)))) return rc;
+  if ((rc = dalloc(h->Lti, std::max<int64_t>(P.spi_off.back(), 1)))) return rc;
+  if ((rc = dalloc(h->cpool, std::max<int64_t>(h->cplan.pool_elems, 1)))) return rc;
+  if ((rc = dalloc(h->cinv, std::max<int64_t>(h->cplan.inv_elems, 1)))) return rc;
   if ((rc = dalloc(h->G, std::max<int64_t>(hoff, 1)))) return rc;
   if ((rc = dalloc(h->H, std::max<int64_t>(hoff, 1)))) return rc;
   if ((rc = dalloc(h->Ht, std::max<int64_t>(hoff, 1)))) return rc;
@@ -847,7 +889,7 @@ int compute_rhs(ieti_handle* h, bool use_graph) {
     D::rhs_assemble(h->y.ptr, h->A_aug.ptr, h->row_src.ptr, M.m_r, h->e.ptr, s);
     if (M.n_gp > 0) {
       D::sum_sources(h->y.ptr, h->dsrc_ptr.ptr, h->dsrc_idx.ptr, M.n_gp, h->dtil.ptr, s);
-      D::tri_small(h->Spi_glob.ptr, h->dtil.ptr, h->w.ptr, false, h->B, s);
+      D::tri_small_inv(h->Lti.ptr, h->dtil.ptr, h->w.ptr, false, h->B, s);
       D::axpy_rows(h->H.ptr, h->w.ptr, h->e.ptr, h->b.ptr, h->B, s);
     } else {
       D::vec_copy(h->e.ptr, h->b.ptr, M.m_r, s);
@@ -1057,8 +1099,13 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
     h->cntF[f].assign(n_prob, 0);
     h->cntM[f].assign(n_prob, 0);
   }
+  Phase ph_solve("ieti_solve");
   HIP_TRY(hipEventRecord(h->ev0, s));
-  int rc = compute_rhs(h, use_graph);
+  int rc = 0;
+  {
+    Phase ph("ieti_solve: right-hand side");
+    rc = compute_rhs(h, use_graph);
+  }
   if (rc) return rc;
   int it = 0, outer = 0;
   const std::vector<double> bb = host_dots(h, h->b.ptr, h->b.ptr);
@@ -1070,6 +1117,7 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   std::vector<double> rr(n_prob, 0.0), rr0(n_prob, 0.0);
   std::vector<int> status(n_prob, IETI_OK), iters(n_prob, 0), outers(n_prob, 0), warm(n_prob, 0);
   if (m_r > 0) {
+    Phase ph("ieti_solve: PCG on the multipliers");
     if (!h->mixed) {
       // plain FP64: PCG on F lambda = b from lambda_0
       rc = init_lambda(h, opts, bb, h->lam.ptr, h->r.ptr, rr, &applies, warm);
@@ -1131,12 +1179,13 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
   }
   HIP_TRY(hipEventRecord(h->ev2, s));
   // ---- recovery: p = S_c^{-1}(d~ + G^T lambda), a_r = K_rr^{-1}(j_r - K_rp C p - B^T lambda)
+  Phase ph_rec("ieti_solve: recovery");
   rc = run_sequence(h, 1, use_graph, [&]() {
     if (M.n_gp > 0) {
       // u = L_c^{-1} d~ + H^T lambda, p = L_c^{-T} u  (H = G L_c^{-T}, S_c = L_c L_c^T), per problem
       D::coarse_project(h->Ht.ptr, h->lam.ptr, h->t.ptr, h->cprob.ptr, h->B, s);
       D::axpby(h->w.ptr, h->t.ptr, h->dtil.ptr, 1.0, 1.0, M.n_gp, s);
-      D::tri_small(h->Spi_glob.ptr, h->dtil.ptr, h->pglob.ptr, true, h->B, s);
+      D::tri_small_inv(h->Lti.ptr, h->dtil.ptr, h->pglob.ptr, true, h->B, s);
     }
     // y = L_rr^{-1} (j_r - K_rp a_p - B_r^T lambda) = y_j - L_pr^T a_p - L_Er^T u (no forward sweep),
     // then the backward sweep
@@ -1250,6 +1299,7 @@ const char* ieti_last_error(void) { return ieti::rt::last_error().c_str(); }
 int ieti_assemble(const ieti_problem* prob, ieti_handle** out) { return ieti_assemble_batch(prob, 1, out); }
 
 int ieti_assemble_batch(const ieti_problem* probs, int32_t n, ieti_handle** out) {
+  Phase ph("ieti_assemble");
   if (!out) return fail(IETI_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!probs || n < 1) return fail(IETI_ERR_INVALID_ARG, "a batch needs at least one problem");
@@ -1352,6 +1402,7 @@ int ieti_get_problem_stats(const ieti_handle* h, int32_t prob, ieti_problem_stat
 int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   namespace D = ieti::dev;
   if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
+  Phase ph("ieti_factor");
   const int T = (opts && opts->tile) ? opts->tile : D::TILE;
   if (T != D::TILE) return fail(IETI_ERR_INVALID_ARG, "only tile size 64 is built");
   if (opts && opts->precision != IETI_PREC_FP64 && opts->precision != IETI_PREC_MIXED)
@@ -1396,10 +1447,22 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   D::copy_tiles(h->pool.ptr, h->xspi.ptr, int64_t(P.xspi_task.size() / 5), 1.0, h->SPi.ptr, s);
   if (M.n_gp > 0) {
     D::sum_sources(h->SPi.ptr, h->spi_ptr.ptr, h->spi_src.ptr, P.spi_off.back(), h->Spi_glob.ptr, s);
-    D::chol_small(h->Spi_glob.ptr, h->flags.ptr + 4, h->B, s);
     D::build_G(h->Phi.ptr, h->row_src.ptr, h->slot_phi_row.ptr, h->I_sub.ptr, h->glob2loc.ptr, h->g2l_off.ptr,
                h->G.ptr, h->B, s);
-    D::solve_rows_LT(h->Spi_glob.ptr, h->G.ptr, h->H.ptr, h->Ht.ptr, h->B, s);
+    // Cholesky of S_c with H = G L_c^{-T} and U = L_c^{-T} as one tile
+    // factorisation of the column block [S_c; G; I]
+    const auto& C = h->cplan;
+    D::fill(h->cpool.ptr, C.pool_elems, 0.0, s);
+    D::dense_to_tiles(h->cpool.ptr, h->cfill.ptr, int64_t(C.fill_task.size() / 7), h->Spi_glob.ptr, h->G.ptr, s);
+    for (int64_t c = 0; c < C.n_levels; ++c) {
+      D::potrf_tiles(h->cpool.ptr, h->cinv.ptr, h->cpotrf.ptr + 3 * C.potrf_ptr[c], C.potrf_ptr[c + 1] - C.potrf_ptr[c],
+                     h->ctol.ptr, h->flags.ptr + 4, s);
+      D::trsm_tiles(h->cpool.ptr, h->cinv.ptr, h->ctrsm.ptr + 2 * C.trsm_ptr[c], C.trsm_ptr[c + 1] - C.trsm_ptr[c], s);
+      D::update_tiles(h->cpool.ptr, h->cupd.ptr + 3 * C.upd_ptr[c], h->cupd_pair.ptr, C.upd_ptr[c + 1] - C.upd_ptr[c],
+                      s);
+    }
+    D::tiles_to_dense(h->cpool.ptr, h->cout_h.ptr, int64_t(C.out_h_task.size() / 7), h->H.ptr, h->Ht.ptr, s);
+    D::tiles_to_dense(h->cpool.ptr, h->cout_l.ptr, int64_t(C.out_l_task.size() / 7), h->Lti.ptr, nullptr, s);
   }
   // mixed precision: FP32 copies of the interface blocks for the inner PCG
   h->mixed = opts && opts->precision == IETI_PREC_MIXED;
@@ -1566,8 +1629,9 @@ int ieti_get_plan_info(const ieti_handle* h, double* info) {
     sum_nI2 += double(sp.nI) * double(sp.nI);
     max_ld = std::max(max_ld, double(sp.nIp));
   }
-  const double v[10] = {double(P.pool_elems), double(P.S_elems), P.flops, P.dense_flops, double(P.n_steps),
-                        double(P.n_update_tasks), sum_nI2, double(P.I_total), max_ld, double(P.T)};
+  const double v[12] = {double(P.pool_elems), double(P.S_elems), P.flops, P.dense_flops, double(P.n_steps),
+                        double(P.n_update_tasks), sum_nI2, double(P.I_total), max_ld, double(P.T),
+                        P.flops_scalar_rr, P.flops_scalar_aug};
   std::memcpy(info, v, sizeof(v));
   return IETI_OK;
 }

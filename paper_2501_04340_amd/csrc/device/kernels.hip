@@ -530,77 +530,90 @@ __global__ void k_build_G(const double* Phi, const int64_t* row_src, const int64
   }
 }
 
-// Cholesky of each problem's dense row-major coarse block (lower factor), one
-// block of threads per problem.
-__global__ __launch_bounds__(256) void k_chol_small(double* Abase, const int64_t* pd, int* err) {
+// ---- coarse problem as a tile factorisation (see CoarsePlan in the host plan)
+//
+// Tile fill: task [off_tile, source (0: S, 1: G, -1: none), source offset, ld,
+// rows, cols, identity]; entry (a, b) of the column-major tile is
+// source[off + a ld + b] for a < rows, b < cols, else 1 on the diagonal of an
+// identity tile and 0.  Rows of the source are read along the threads and
+// turned into tile columns through LDS.
+__global__ __launch_bounds__(256) void k_dense_to_tiles(double* pool, const int64_t* task, const double* S,
+                                                        const double* G) {
+  __shared__ double tl[T][T + 1];  // tl[a][b] = entry (a, b)
+  const int64_t* tk = task + 7 * blockIdx.x;
+  double* t = pool + tk[0];
+  const int64_t sel = tk[1], off = tk[2], ld = tk[3], rows = tk[4], cols = tk[5];
+  const bool ident = tk[6] != 0;
+  const double* src = sel == 0 ? S : (sel == 1 ? G : nullptr);
+  for (int idx = threadIdx.x; idx < T * T; idx += blockDim.x) {
+    const int a = idx >> 6, b = idx & (T - 1);
+    double v = (ident && a == b) ? 1.0 : 0.0;
+    if (src && a < rows && b < cols) v = src[off + a * ld + b];
+    tl[a][b] = v;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < T * T; idx += blockDim.x) {
+    const int b = idx >> 6, a = idx & (T - 1);
+    t[idx] = tl[a][b];
+  }
+}
+
+// Tile extraction: task [off_tile, dst offset, transposed dst offset or -1,
+// ld, transposed ld, rows, cols]; entry (a, b), a < rows, b < cols, goes to
+// dst[off + a ld + b] and to dst_t[off_t + b ld_t + a].
+__global__ __launch_bounds__(256) void k_tiles_to_dense(const double* pool, const int64_t* task, double* dst,
+                                                        double* dst_t) {
+  __shared__ double tl[T][T + 1];  // tl[b][a] = entry (a, b)
+  const int64_t* tk = task + 7 * blockIdx.x;
+  const double* t = pool + tk[0];
+  const int64_t off = tk[1], off_t = tk[2], ld = tk[3], ldt = tk[4], rows = tk[5], cols = tk[6];
+  for (int idx = threadIdx.x; idx < T * T; idx += blockDim.x) tl[idx >> 6][idx & (T - 1)] = t[idx];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < T * T; idx += blockDim.x) {
+    const int a = idx >> 6, b = idx & (T - 1);
+    if (a < rows && b < cols) dst[off + a * ld + b] = tl[b][a];
+  }
+  if (off_t >= 0 && dst_t)
+    for (int idx = threadIdx.x; idx < T * T; idx += blockDim.x) {
+      const int b = idx >> 6, a = idx & (T - 1);
+      if (a < rows && b < cols) dst_t[off_t + b * ldt + a] = tl[b][a];
+    }
+}
+
+// Triangular solves with the coarse factor through its explicit inverse
+// U = L_c^{-T} (row-major n x n per problem, upper triangular), one
+// workgroup per problem:
+//   transposed = 0: out = L_c^{-1} in = U^T in, out[c] = sum_{i <= c} U[i][c] in[i]
+//                   (a thread per output, rows of U read along the threads);
+//   transposed = 1: out = L_c^{-T} in = U in,   out[i] = sum_{c >= i} U[i][c] in[c]
+//                   (a wave per output, lanes along the row, fixed-order wave sum).
+__global__ __launch_bounds__(256) void k_tri_small_inv(const double* U, const double* in, double* out,
+                                                       int transposed, const int64_t* pd) {
   const int64_t* P = pd + PD_N * blockIdx.x;
-  const int64_t n = P[PD_NGP];
-  double* A = Abase + P[PD_SPI];
-  for (int64_t k = 0; k < n; ++k) {
-    const double d = A[k * n + k];
-    const double piv = d > 0.0 ? sqrt(d) : 1.0;
-    if (!(d > 0.0) && threadIdx.x == 0) atomicMax(err, int(blockIdx.x) + 1);
-    __syncthreads();
-    for (int64_t i = k + threadIdx.x; i < n; i += 256) {
-      if (i == k) A[k * n + k] = piv;
-      else A[i * n + k] /= piv;
-    }
-    __syncthreads();
-    const int64_t m = n - 1 - k;
-    for (int64_t idx = threadIdx.x; idx < m * m; idx += 256) {
-      const int64_t i = k + 1 + idx / m, j = k + 1 + idx % m;
-      if (j <= i) A[i * n + j] -= A[i * n + k] * A[j * n + k];
-    }
-    __syncthreads();
-  }
-  for (int64_t idx = threadIdx.x; idx < n * n; idx += 256) {
-    const int64_t i = idx / n, j = idx % n;
-    if (j > i) A[idx] = 0.0;
-  }
-}
-
-// H_p[row] = G_p[row] L_p^{-T} (each row independently), also stored transposed.
-__global__ void k_solve_rows_LT(const double* L, const double* G, double* H, double* Ht, const int64_t* pd,
-                                const int64_t* blk) {
-  int64_t row0;
-  const int64_t nrow = blk_rows(blk, pd, blockIdx.x, &row0);
-  if (int64_t(threadIdx.x) >= nrow) return;
-  const int64_t* P = pd + PD_N * blk[2 * blockIdx.x + 1];
-  const int64_t n = P[PD_NGP], m = P[PD_MR1] - P[PD_MR0], rl = row0 + threadIdx.x - P[PD_MR0];
-  const double* Lp = L + P[PD_SPI];
-  const double* Gr = G + P[PD_H] + rl * n;
-  double* Hr = H + P[PD_H] + rl * n;
-  double* Htp = Ht + P[PD_HT];
-  for (int64_t c = 0; c < n; ++c) {
-    double s = Gr[c];
-    for (int64_t q = 0; q < c; ++q) s -= Hr[q] * Lp[c * n + q];
-    const double h = s / Lp[c * n + c];
-    Hr[c] = h;
-    Htp[c * m + rl] = h;
-  }
-}
-
-// out_p = L_p^{-1} in_p (or L_p^{-T} in_p) per problem, one thread per problem.
-__global__ void k_tri_small(const double* L, const double* in, double* out, int transposed, const int64_t* pd,
-                            int n_prob) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_prob) return;
-  const int64_t* P = pd + PD_N * p;
   const int64_t n = P[PD_NGP], g0 = P[PD_GP0];
-  const double* Lp = L + P[PD_SPI];
+  if (n <= 0) return;
+  const double* Up = U + P[PD_SPI];
   const double* x = in + g0;
   double* y = out + g0;
   if (!transposed) {
-    for (int64_t c = 0; c < n; ++c) {
-      double s = x[c];
-      for (int64_t q = 0; q < c; ++q) s -= Lp[c * n + q] * y[q];
-      y[c] = s / Lp[c * n + c];
+    for (int64_t c = threadIdx.x; c < n; c += 256) {
+      double s0 = 0.0, s1 = 0.0;
+      int64_t i = 0;
+      for (; i + 1 <= c; i += 2) {
+        s0 += Up[i * n + c] * x[i];
+        s1 += Up[(i + 1) * n + c] * x[i + 1];
+      }
+      for (; i <= c; ++i) s0 += Up[i * n + c] * x[i];
+      y[c] = s0 + s1;
     }
   } else {
-    for (int64_t c = n - 1; c >= 0; --c) {
-      double s = x[c];
-      for (int64_t q = c + 1; q < n; ++q) s -= Lp[q * n + c] * y[q];
-      y[c] = s / Lp[c * n + c];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int64_t i = w; i < n; i += 4) {
+      double s = 0.0;
+      for (int64_t c = i + lane; c < n; c += 64) s += Up[i * n + c] * x[c];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+      if (lane == 0) y[i] = s;
     }
   }
 }
@@ -1222,18 +1235,18 @@ void build_G(const double* Phi, const int64_t* row_src, const int64_t* slot_phi_
   hipLaunchKernelGGL(k_build_G, dim3(B.n_blk), dim3(256), 0, s, Phi, row_src, slot_phi_row, I_sub, g2l, g2l_off, G,
                      B.pd, B.blk);
 }
-void chol_small(double* A, int* err, const Batch& B, hipStream_t s) {
-  if (B.n_gp_total <= 0) return;
-  hipLaunchKernelGGL(k_chol_small, dim3(B.n_prob), dim3(256), 0, s, A, B.pd, err);
+void dense_to_tiles(double* pool, const int64_t* task, int64_t ntask, const double* S, const double* G,
+                    hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(k_dense_to_tiles, dim3(ntask), dim3(256), 0, s, pool, task, S, G);
 }
-void solve_rows_LT(const double* L, const double* G, double* H, double* Ht, const Batch& B, hipStream_t s) {
-  if (B.n_gp_total <= 0 || B.n_blk <= 0) return;
-  hipLaunchKernelGGL(k_solve_rows_LT, dim3(B.n_blk), dim3(256), 0, s, L, G, H, Ht, B.pd, B.blk);
+void tiles_to_dense(const double* pool, const int64_t* task, int64_t ntask, double* dst, double* dst_t, hipStream_t s) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(k_tiles_to_dense, dim3(ntask), dim3(256), 0, s, pool, task, dst, dst_t);
 }
-void tri_small(const double* L, const double* in, double* out, bool transposed, const Batch& B, hipStream_t s) {
-  if (B.n_gp_total <= 0) return;
-  hipLaunchKernelGGL(k_tri_small, dim3((B.n_prob + 63) / 64), dim3(64), 0, s, L, in, out, transposed ? 1 : 0, B.pd,
-                     B.n_prob);
+void tri_small_inv(const double* U, const double* in, double* out, bool transposed, const Batch& B, hipStream_t s) {
+  if (B.n_gp_total <= 0 || B.n_prob <= 0) return;
+  hipLaunchKernelGGL(k_tri_small_inv, dim3(B.n_prob), dim3(256), 0, s, U, in, out, transposed ? 1 : 0, B.pd);
 }
 void gather_rows(const double* x, const int64_t* row_src, int64_t m_r, double* xg, hipStream_t s, const double* ds) {
   if (m_r <= 0) return;

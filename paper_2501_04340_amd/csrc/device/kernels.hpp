@@ -61,9 +61,13 @@ void sum_sources(const double* src, const int64_t* ptr, const int64_t* idx, int6
 // g2l[g2l_off[k] + c]: local primal slot of the c-th primal of subdomain k's problem, or -1
 void build_G(const double* Phi, const int64_t* row_src, const int64_t* slot_phi_row, const int32_t* I_sub,
              const int32_t* g2l, const int64_t* g2l_off, double* G, const Batch& B, hipStream_t s);
-void chol_small(double* A, int* err, const Batch& B, hipStream_t s);
-void solve_rows_LT(const double* L, const double* G, double* H, double* Ht, const Batch& B, hipStream_t s);
-void tri_small(const double* L, const double* in, double* out, bool transposed, const Batch& B, hipStream_t s);
+// coarse tile factorisation helpers (tasks of CoarsePlan): dense row-major
+// S_c / G blocks into tiles, tiles back into dense H, H^T and U = L_c^{-T}
+void dense_to_tiles(double* pool, const int64_t* task, int64_t ntask, const double* S, const double* G,
+                    hipStream_t s);
+void tiles_to_dense(const double* pool, const int64_t* task, int64_t ntask, double* dst, double* dst_t, hipStream_t s);
+// out_p = L_p^{-1} in_p (transposed = false) or L_p^{-T} in_p through U_p = L_p^{-T}
+void tri_small_inv(const double* U, const double* in, double* out, bool transposed, const Batch& B, hipStream_t s);
 
 // ---- interface operators and PCG (FP64 recurrences)
 // xg[slot(+1)] = x[row], xg[slot(-1)] = -x[row]; with ds (per slot, may be null) the

@@ -74,6 +74,80 @@ int64_t round_up(int64_t x, int64_t t) { return (x + t - 1) / t * t; }
 constexpr int64_t UPDATE_DEFER = 8;
 constexpr int64_t UPDATE_DEFER_TAIL = 4;
 
+// Scalar-level work of the Cholesky factorisation in the plan's elimination
+// order (r_V by nested dissection, then r_I), from the elimination tree and
+// the row subtrees (no tiles, no padding):
+//   rr  = sum_j c_j^2 over the r columns, c_j the off-diagonal count of
+//         column j of L with L L^T = K_rr (the local factorisation itself);
+//   aug = the same sum when the columns also carry the trailing rows of the
+//         augmented matrix (K_pr and E_I^T), i.e. the scalar work of the
+//         partial factorisation that yields the explicit interface blocks.
+void scalar_factor_work(const Subdomain& s, const SubPlan& sp, double& rr, double& aug) {
+  const int64_t nr = int64_t(s.r_edges.size());
+  rr = aug = 0.0;
+  if (nr == 0) return;
+  // elimination order of the r DOFs: increasing augmented position
+  std::vector<int32_t> order(nr);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return sp.pos_of_local[a] < sp.pos_of_local[b]; });
+  std::vector<int32_t> newi(nr);
+  for (int64_t q = 0; q < nr; ++q) newi[order[q]] = int32_t(q);
+  // lower entries of each row (columns before it) in the new order
+  std::vector<std::vector<int32_t>> lower(nr);
+  for (int64_t r = 0; r < nr; ++r)
+    for (int64_t q = s.indptr[r]; q < s.indptr[r + 1]; ++q) {
+      const int32_t c = s.indices[q];
+      if (c < nr && newi[c] < newi[r]) lower[newi[r]].push_back(newi[c]);
+    }
+  // elimination tree (Liu, with path compression through `anc`)
+  std::vector<int32_t> parent(nr, -1), anc(nr, -1);
+  for (int32_t i = 0; i < int32_t(nr); ++i)
+    for (int32_t j : lower[i])
+      while (j != -1 && j < i) {
+        const int32_t nx = anc[j];
+        anc[j] = i;
+        if (nx == -1) {
+          parent[j] = i;
+          break;
+        }
+        j = nx;
+      }
+  // column counts: row i of L is the union of the tree paths from its
+  // entries up to i; trailing rows take the paths up to the root
+  std::vector<int64_t> cnt(nr, 0), tcnt(nr, 0);
+  std::vector<int32_t> mark(nr, -1);
+  for (int32_t i = 0; i < int32_t(nr); ++i) {
+    mark[i] = i;
+    for (int32_t j : lower[i])
+      for (int32_t k = j; k != -1 && mark[k] != i; k = parent[k]) {
+        mark[k] = i;
+        ++cnt[k];
+      }
+  }
+  int32_t tag = int32_t(nr);
+  auto trailing_row = [&](const std::vector<int32_t>& cols) {
+    std::vector<int32_t>& mk = mark;
+    for (int32_t j : cols)
+      for (int32_t k = j; k != -1 && mk[k] != tag; k = parent[k]) {
+        mk[k] = tag;
+        ++tcnt[k];
+      }
+    ++tag;
+  };
+  std::fill(mark.begin(), mark.end(), -1);
+  const int64_t np = s.n_loc - nr;
+  std::vector<std::vector<int32_t>> prow(np);
+  for (int64_t r = 0; r < nr; ++r)
+    for (int64_t q = s.indptr[r]; q < s.indptr[r + 1]; ++q)
+      if (s.indices[q] >= nr) prow[s.indices[q] - nr].push_back(newi[r]);
+  for (auto& row : prow) trailing_row(row);
+  for (int32_t t : s.I_local) trailing_row(std::vector<int32_t>{newi[t]});
+  for (int64_t j = 0; j < nr; ++j) {
+    rr += double(cnt[j]) * double(cnt[j]);
+    aug += double(cnt[j] + tcnt[j]) * double(cnt[j] + tcnt[j]);
+  }
+}
+
 }  // namespace
 
 int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
@@ -198,6 +272,12 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
   }
   plan.pool_elems = pool;
   plan.S_elems = S_elems;
+  for (int k = 0; k < S; ++k) {
+    double rr = 0.0, aug = 0.0;
+    scalar_factor_work(m.sd[k], plan.sub[k], rr, aug);
+    plan.flops_scalar_rr += rr;
+    plan.flops_scalar_aug += aug;
+  }
   plan.I_total = I_total;
   plan.P_total = P_total;
   plan.r_total = r_total;
@@ -596,6 +676,103 @@ void refill_values(const Model& m, Plan& plan) {
     const Subdomain& s = m.sd[k];
     const SubPlan& sp = plan.sub[k];
     for (int64_t r = 0; r < s.n_loc; ++r) plan.b_aug0[sp.r_off + sp.pos_of_local[r]] = s.load[r];
+  }
+}
+
+void build_coarse_plan(const std::vector<CoarseDims>& dims, int T, CoarsePlan& cp) {
+  cp = CoarsePlan();
+  const int64_t TT = int64_t(T) * T;
+  struct Prob {
+    int64_t nc = 0, mt = 0;
+    std::vector<int64_t> D, G, E;  // tile offsets: D[ci * nc + cj] (cj <= ci), G[r * nc + c], E[i * nc + c] (i <= c)
+    int64_t inv0 = 0;
+  };
+  std::vector<Prob> pr(dims.size());
+  int64_t off = 0, inv = 0;
+  for (size_t p = 0; p < dims.size(); ++p) {
+    const auto& d = dims[p];
+    auto& q = pr[p];
+    if (d.n <= 0) continue;
+    q.nc = (d.n + T - 1) / T;
+    q.mt = (d.m + T - 1) / T;
+    q.D.assign(size_t(q.nc * q.nc), -1);
+    q.G.assign(size_t(q.mt * q.nc), -1);
+    q.E.assign(size_t(q.nc * q.nc), -1);
+    for (int64_t ci = 0; ci < q.nc; ++ci)
+      for (int64_t cj = 0; cj <= ci; ++cj) {
+        q.D[size_t(ci * q.nc + cj)] = off;
+        off += TT;
+      }
+    for (int64_t r = 0; r < q.mt; ++r)
+      for (int64_t c = 0; c < q.nc; ++c) {
+        q.G[size_t(r * q.nc + c)] = off;
+        off += TT;
+      }
+    for (int64_t i = 0; i < q.nc; ++i)
+      for (int64_t c = i; c < q.nc; ++c) {
+        q.E[size_t(i * q.nc + c)] = off;
+        off += TT;
+      }
+    q.inv0 = inv;
+    inv += q.nc * TT;
+    cp.n_levels = std::max(cp.n_levels, q.nc);
+    // tile fill
+    for (int64_t ci = 0; ci < q.nc; ++ci)
+      for (int64_t cj = 0; cj <= ci; ++cj)
+        cp.fill_task.insert(cp.fill_task.end(),
+                            {q.D[size_t(ci * q.nc + cj)], 0, d.spi_off + ci * T * d.n + cj * T, d.n,
+                             std::min<int64_t>(T, d.n - ci * T), std::min<int64_t>(T, d.n - cj * T), ci == cj ? 1 : 0});
+    for (int64_t r = 0; r < q.mt; ++r)
+      for (int64_t c = 0; c < q.nc; ++c)
+        cp.fill_task.insert(cp.fill_task.end(),
+                            {q.G[size_t(r * q.nc + c)], 1, d.g_off + r * T * d.n + c * T, d.n,
+                             std::min<int64_t>(T, d.m - r * T), std::min<int64_t>(T, d.n - c * T), 0});
+    for (int64_t i = 0; i < q.nc; ++i)
+      for (int64_t c = i; c < q.nc; ++c)
+        cp.fill_task.insert(cp.fill_task.end(), {q.E[size_t(i * q.nc + c)], -1, 0, 0, 0, 0, c == i ? 1 : 0});
+    // extraction
+    for (int64_t r = 0; r < q.mt; ++r)
+      for (int64_t c = 0; c < q.nc; ++c)
+        cp.out_h_task.insert(cp.out_h_task.end(),
+                             {q.G[size_t(r * q.nc + c)], d.g_off + r * T * d.n + c * T, d.g_off + c * T * d.m + r * T,
+                              d.n, d.m, std::min<int64_t>(T, d.m - r * T), std::min<int64_t>(T, d.n - c * T)});
+    for (int64_t i = 0; i < q.nc; ++i)
+      for (int64_t c = i; c < q.nc; ++c)
+        cp.out_l_task.insert(cp.out_l_task.end(),
+                             {q.E[size_t(i * q.nc + c)], d.spi_off + i * T * d.n + c * T, -1, d.n, 0,
+                              std::min<int64_t>(T, d.n - i * T), std::min<int64_t>(T, d.n - c * T)});
+  }
+  cp.pool_elems = off;
+  cp.inv_elems = inv;
+  // level c: Cholesky of D(c, c); panel solves of every tile of column c below it
+  // (D(ci, c), ci > c; G(r, c); E(i, c), i <= c); one update per target tile of a
+  // later column c' with the column-c contribution X(., c) D(c', c)^T
+  cp.potrf_ptr.push_back(0);
+  cp.trsm_ptr.push_back(0);
+  cp.upd_ptr.push_back(0);
+  for (int64_t c = 0; c < cp.n_levels; ++c) {
+    for (size_t p = 0; p < pr.size(); ++p) {
+      const auto& q = pr[p];
+      if (c >= q.nc) continue;
+      cp.potrf_task.insert(cp.potrf_task.end(), {q.D[size_t(c * q.nc + c)], int64_t(p), q.inv0 + c * TT});
+      const int64_t iv = q.inv0 + c * TT;
+      for (int64_t ci = c + 1; ci < q.nc; ++ci) cp.trsm_task.insert(cp.trsm_task.end(), {q.D[size_t(ci * q.nc + c)], iv});
+      for (int64_t r = 0; r < q.mt; ++r) cp.trsm_task.insert(cp.trsm_task.end(), {q.G[size_t(r * q.nc + c)], iv});
+      for (int64_t i = 0; i <= c; ++i) cp.trsm_task.insert(cp.trsm_task.end(), {q.E[size_t(i * q.nc + c)], iv});
+      for (int64_t c2 = c + 1; c2 < q.nc; ++c2) {
+        const int64_t B = q.D[size_t(c2 * q.nc + c)];
+        auto add = [&](int64_t target, int64_t A) {
+          cp.upd_task.insert(cp.upd_task.end(), {target, int64_t(cp.upd_pair.size() / 2), 1});
+          cp.upd_pair.insert(cp.upd_pair.end(), {A, B});
+        };
+        for (int64_t ci = c2; ci < q.nc; ++ci) add(q.D[size_t(ci * q.nc + c2)], q.D[size_t(ci * q.nc + c)]);
+        for (int64_t r = 0; r < q.mt; ++r) add(q.G[size_t(r * q.nc + c2)], q.G[size_t(r * q.nc + c)]);
+        for (int64_t i = 0; i <= c; ++i) add(q.E[size_t(i * q.nc + c2)], q.E[size_t(i * q.nc + c)]);
+      }
+    }
+    cp.potrf_ptr.push_back(int64_t(cp.potrf_task.size() / 3));
+    cp.trsm_ptr.push_back(int64_t(cp.trsm_task.size() / 2));
+    cp.upd_ptr.push_back(int64_t(cp.upd_task.size() / 3));
   }
 }
 

@@ -102,9 +102,46 @@ struct Plan {
   std::vector<double> piv_tol;
   static constexpr double PIVOT_REL = 1e-13;
   double flops = 0.0;    // algorithmic flops of the tile factorisation
+  // scalar-level work in the same elimination order, sum_j c_j^2 (no tiles,
+  // no padding): of K_rr alone, and with the augmented trailing rows
+  double flops_scalar_rr = 0.0, flops_scalar_aug = 0.0;
   double dense_flops = 0.0;
   int64_t n_update_tasks = 0;
 };
+
+// The coarse problem of every problem of a batch as a tile factorisation
+// run by the same kernels as the local ones: the column block
+//
+//     [ S_c ]   n_gp x n_gp, symmetric positive definite (lower tiles)
+//     [ G   ]   m_r  x n_gp
+//     [ I   ]   n_gp x n_gp
+//
+// in 64x64 tiles; eliminating its n_gp columns (Cholesky of S_c, panel solves
+// of the rows below, updates of the later columns) leaves L_c in the S_c
+// tiles, H = G L_c^{-T} in the G tiles and L_c^{-T} in the identity tiles.
+struct CoarseDims {
+  int64_t m = 0, n = 0;       // multiplier rows and primal DOFs of the problem
+  int64_t spi_off = 0;        // its dense row-major S_c (n x n) in the assembled coarse array
+  int64_t g_off = 0;          // its dense row-major G / H (m x n); H^T (n x m) at the same offset
+};
+struct CoarsePlan {
+  int64_t pool_elems = 0, inv_elems = 0;
+  int64_t n_levels = 0;
+  // tile fill: [off_tile, source (0: S_c, 1: G, -1: none), source offset, ld, rows, cols, identity]
+  //   entry (a, b) = source[off + a ld + b] for a < rows, b < cols, else (identity && a == b)
+  std::vector<int64_t> fill_task;
+  // per level: ranges into the task arrays (formats of the local factorisation)
+  std::vector<int64_t> potrf_ptr, trsm_ptr, upd_ptr;
+  std::vector<int64_t> potrf_task;  // [off_cc, problem, off of L_cc^{-1}]
+  std::vector<int64_t> trsm_task;   // [off_xc, off of L_cc^{-1}]
+  std::vector<int64_t> upd_task;    // [off_target, first pair, pair count]
+  std::vector<int64_t> upd_pair;    // [off_A, off_B]
+  // extraction: [off_tile, dst offset, transposed dst offset or -1, ld, transposed ld, rows, cols]
+  //   H and H^T from the G tiles (into the H / Ht arrays), L_c^{-T} (row-major n x n at
+  //   spi_off) from the identity tiles
+  std::vector<int64_t> out_h_task, out_l_task;
+};
+void build_coarse_plan(const std::vector<CoarseDims>& dims, int T, CoarsePlan& cp);
 
 // ordering: 0 = nested dissection, 1 = natural
 int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err);

@@ -502,10 +502,10 @@ class Solver:
         return b
 
     def plan_info(self):
-        v = np.zeros(10)
+        v = np.zeros(12)
         _check(self.lib, self.lib.ieti_get_plan_info(self.h, _ptr(v, C.c_double)))
         keys = ["pool_elems", "S_elems", "flops", "dense_flops", "n_steps", "n_update_tasks", "sum_nI2",
-                "I_total", "max_ld", "tile"]
+                "I_total", "max_ld", "tile", "flops_scalar_rr", "flops_scalar_aug"]
         return dict(zip(keys, v.tolist()))
 
     def gemv_tuning(self):

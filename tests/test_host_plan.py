@@ -48,3 +48,23 @@ def test_factor_schedule_matches_definition(plan_check, cfg):
     assert res.returncode == 0, res.stdout + res.stderr
     m = re.search(r"factor residual ([0-9.e+-]+) S residual ([0-9.e+-]+)", res.stdout)
     assert m and float(m.group(1)) < 1e-12 and float(m.group(2)) < 1e-12, res.stdout
+
+
+def test_coarse_tile_plan_matches_definition(tmp_path):
+    """The coarse problem's tile plan (tests/native/coarse_check.cpp): its
+    task lists run in plain loops give L_c L_c^T = S_c, H L_c^T = G and
+    L_c^T U = I for problems with n_gp = 0, 1, 3, 64, 65, 150 and row counts
+    that are and are not multiples of the tile size."""
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "coarse_check")
+    srcs = [os.path.join(ROOT, "tests", "native", "coarse_check.cpp")]
+    srcs += sorted(os.path.join(HOST, f) for f in os.listdir(HOST) if f.endswith(".cpp"))
+    cmd = [cxx, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I",
+           os.path.join(ROOT, "paper_2501_04340_amd", "csrc"), "-o", exe, *srcs, "-lpthread"]
+    res = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert res.returncode == 0, res.stderr[-4000:]
+    res = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert "pivots ok" in res.stdout
