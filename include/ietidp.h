@@ -273,6 +273,23 @@ int ieti_apply_F(ieti_handle* h, const double* lambda, double* q);
 /* One application z = M_D^{-1} r of the Dirichlet preconditioner (Eq. DirPrec). */
 int ieti_apply_M(ieti_handle* h, const double* r, double* z);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * application q = F lambda as ieti_apply_F, on device vectors d_lambda [m_r]
+ * and d_q [m_r] (distinct, caller-owned) and on `hip_stream` (NULL: the
+ * handle's stream), with no allocation, copy or synchronisation.  Its work
+ * vectors (gathered interface values, local products, GEMV partial sums,
+ * coarse projections) live in one fixed device array of
+ * IETI_NOALLOC_SCRATCH_BYTES per GPU, created with the library's code object
+ * and held until the process ends; a handle whose work vectors do not fit
+ * gets IETI_ERR_INVALID_ARG (ieti_apply_F has no such limit).  Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (several
+ * streams or threads) race, and the caller must serialise them.  The handle
+ * must be factored and its device current; the result is returned
+ * asynchronously on the stream. */
+#define IETI_NOALLOC_SCRATCH_BYTES (32ll << 20)
+int ieti_apply_F_noalloc(ieti_handle* h, const double* d_lambda, double* d_q, void* hip_stream);
+
 /* Right-hand side b = e - G S_c^{-1} d of the interface problem [m_r]. */
 int ieti_get_rhs(ieti_handle* h, double* b);
 

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1292,6 +1293,42 @@ int assemble_model(const ieti_problem* prob, ieti::Model& m) {
 
 }  // namespace
 
+// ---- allocation-free operator application
+//
+// The work vectors of ieti_apply_F_noalloc live in this array, one copy per
+// GPU (part of the library's code object, so it exists from the moment the
+// library is loaded on a device until the process ends).  Host code never
+// uses the symbol itself as an address: each device's copy is resolved once
+// with hipGetSymbolAddress while that device is current, and that address
+// is what the kernels receive.
+static constexpr int64_t NOALLOC_DOUBLES = IETI_NOALLOC_SCRATCH_BYTES / int64_t(sizeof(double));
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_for_device(int dev, double** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(IETI_ERR_INVALID_ARG, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(IETI_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return IETI_OK;
+}
+
+// 256-byte aligned carve-outs of the scratch array, in doubles
+int64_t carve(int64_t n) { return (std::max<int64_t>(n, 1) + 31) / 32 * 32; }
+
+}  // namespace
+
 extern "C" {
 
 const char* ieti_last_error(void) { return ieti::rt::last_error().c_str(); }
@@ -1608,6 +1645,56 @@ int ieti_apply_M(ieti_handle* h, const double* r, double* z) {
   HIP_TRY(hipMemcpyAsync(z, h->z.ptr, m_r * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   return IETI_OK;
+}
+
+int ieti_apply_F_noalloc(ieti_handle* h, const double* d_lambda, double* d_q, void* hip_stream) {
+  namespace D = ieti::dev;
+  if (!h || !d_lambda || !d_q) return fail(IETI_ERR_INVALID_ARG, "NULL argument");
+  if (d_lambda == d_q) return fail(IETI_ERR_INVALID_ARG, "d_lambda and d_q must be distinct");
+  if (!h->factored) return fail(IETI_ERR_STATE, "not factored");
+  const auto& M = h->model;
+  if (M.m_r == 0) return IETI_OK;
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != h->device)
+    return fail(IETI_ERR_STATE, "the handle's device " + std::to_string(h->device) + " is not current");
+  // work vectors: gathered values and local products per interface slot,
+  // GEMV partials (the symmetric kernel's partial lists, the per-block sums)
+  // and the coarse projection
+  const int variant = gvariant(h, 0);
+  const bool sym = variant == D::GEMV_SYM;
+  const int64_t n_xg = carve(h->xgp.n), n_v = carve(h->v.n), n_pg = carve(h->part_g.n);
+  const int64_t n_sp = sym ? carve(h->sym_part.n) : 0, n_t = M.n_gp > 0 ? carve(M.n_gp) : 0;
+  const int64_t need = n_xg + n_v + n_pg + n_sp + n_t;
+  if (need > NOALLOC_DOUBLES)
+    return fail(IETI_ERR_INVALID_ARG, "the work vectors of this handle need " + std::to_string(need * 8) +
+                                          " bytes; the allocation-free path holds " +
+                                          std::to_string(int64_t(IETI_NOALLOC_SCRATCH_BYTES)));
+  double* base = nullptr;
+  int rc = scratch_for_device(cur, &base);
+  if (rc) return rc;
+  double* xg = base;
+  double* v = xg + n_xg;
+  double* part_g = v + n_v;
+  double* sym_part = part_g + n_pg;
+  double* t = sym_part + n_sp;
+  hipStream_t s = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : h->stream;
+  // padding slots are read by the GEMV and written by no gather: clear the
+  // whole gathered vector (a fill kernel, which graph capture accepts)
+  D::fill(xg, h->xgp.n, 0.0, s);
+  D::gather_rows(d_lambda, h->row_src.ptr, M.m_r, xg, s);
+  if (sym) {
+    D::SymGemv g = h->symg;
+    g.part = sym_part;
+    D::gemv_sym(h->Sinv.ptr, g, xg, v, part_g, nullptr, s);
+  } else {
+    const int ri = variant / 4;
+    D::gemv(h->Sinv.ptr, h->gemv_tasks[ri].ptr, h->ngemv_r[ri], h->max_ld, xg, v, part_g, nullptr,
+            h->task_prob[ri].ptr, s, variant);
+  }
+  if (M.n_gp > 0) D::coarse_project(h->Ht.ptr, d_lambda, t, h->cprob.ptr, h->B, s);
+  D::combine(v, h->row_src.ptr, M.n_gp > 0 ? h->H.ptr : nullptr, t, d_q, h->B, s);
+  return check_launch();
 }
 
 int ieti_get_rhs(ieti_handle* h, double* b) {

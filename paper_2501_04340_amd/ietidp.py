@@ -137,7 +137,7 @@ EXPORTS = [
     "ieti_batch_of", "ieti_record_pcg", "ieti_get_pcg_coefficients", "ieti_nn_save", "ieti_nn_load",
     "ieti_get_problem_stats", "ieti_nn_init_params", "ieti_nn_set_normalisation", "ieti_nn_fit_normalisation",
     "ieti_nn_get_normalisation", "ieti_nn_dataset_append", "ieti_nn_train_file", "ieti_warm_rows",
-    "ieti_warm_append", "ieti_warm_load", "ieti_warm_predict", "ieti_get_condition",
+    "ieti_warm_append", "ieti_warm_load", "ieti_warm_predict", "ieti_get_condition", "ieti_apply_F_noalloc",
 ]
 
 
@@ -176,6 +176,7 @@ def load_library():
     lib.ieti_get_schur.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)]
     lib.ieti_apply_F.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
     lib.ieti_apply_M.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
+    lib.ieti_apply_F_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.ieti_get_rhs.argtypes = [C.c_void_p, P(C.c_double)]
     lib.ieti_get_lambda.argtypes = [C.c_void_p, P(C.c_double)]
     lib.ieti_get_plan_info.argtypes = [C.c_void_p, P(C.c_double)]
@@ -489,6 +490,13 @@ class Solver:
         q = np.zeros(self.m_r)
         _check(self.lib, self.lib.ieti_apply_F(self.h, _ptr(lam, C.c_double), _ptr(q, C.c_double)))
         return q
+
+    def apply_F_noalloc(self, d_lam, d_q, stream=None):
+        """q = F lambda on device vectors (addresses of m_r doubles) without
+        any allocation, on `stream` (a HIP stream handle, None = the
+        handle's stream); asynchronous."""
+        _check(self.lib, self.lib.ieti_apply_F_noalloc(self.h, C.c_void_p(d_lam), C.c_void_p(d_q),
+                                                       C.c_void_p(stream) if stream else None))
 
     def apply_M(self, r):
         r = np.ascontiguousarray(r, dtype=np.float64)
