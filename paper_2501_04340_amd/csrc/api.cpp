@@ -79,6 +79,10 @@ struct ieti_handle {
   DBuf<double> yj;  // L_rr^{-1} j_r of the right-hand side's forward solve (augmented layout)
   DBuf<double> lam, r, z, p, q, v, b, e, dtil, w, t, pglob, part, scal, aout, tmp;
   DBuf<double> xgp, xgr, part_g, part_t;  // gathered B^T p and B^T r, GEMV and coarse partials
+  // reduction of the coarse partials into t = H^T p once per iteration: 64-column chunks per problem
+  DBuf<int64_t> ctask_red;
+  DBuf<double> tvec;
+  ieti::dev::CoarseReduce cred;
   DBuf<double> lam_acc, rtrue;            // outer multipliers and FP64 residual (mixed precision)
   DBuf<float> S32, Sinv32;                // FP32 copies of S_rIrI and (K_rr^{-1})_II (mixed precision)
   bool mixed = false;
@@ -147,13 +151,13 @@ struct ieti_handle {
   ~ieti_handle() {
     DBuf<double>* ds[] = {&piv_tol, &pool, &inv, &scatter_val, &S, &Sinv, &Phi, &SPi, &Spi_glob, &G, &H, &Ht, &I_sign, &b_aug0, &y,
                           &yj, &lam, &r, &z, &p, &q, &v, &b, &e, &dtil, &w, &t, &pglob, &part, &scal, &aout,
-                          &tmp, &xgp, &xgr, &part_g, &part_t, &lam_acc, &rtrue, &cpool, &cinv, &ctol, &Lti};
+                          &tmp, &xgp, &xgr, &part_g, &part_t, &lam_acc, &rtrue, &cpool, &cinv, &ctol, &Lti, &tvec};
     for (auto* d : ds) d->release();
     DBuf<int64_t>* is[] = {&scatter_dst, &potrf, &trsm, &upd, &upd_pair, &copyS, &xsinv, &xphi, &xspi, &fdiag,
                            &ffull, &ffull_pair, &rec_task, &rec_pair, &bdiag, &bupd, &bupd_pair, &spi_ptr, &spi_src, &row_src, &I_aug, &A_aug, &slot_phi_row, &dsrc_ptr,
                            &dsrc_idx, &recP_pos, &recP_glob, &out_src, &out_edge, &primal_edges,
                            &gemv_tasks[0], &gemv_tasks[1], &gemv_tasks[2], &cfill, &cpotrf, &ctrsm, &cupd,
-                           &cupd_pair, &cout_h, &cout_l};
+                           &cupd_pair, &cout_h, &cout_l, &ctask_red};
     for (auto* d : is) d->release();
     I_row.release();
     I_sub.release();
@@ -516,6 +520,10 @@ int upload(ieti_handle* h) {
     UP(cout_l, C.out_l_task);
     // only non-positive pivots are flagged in the coarse matrix
     UP(ctol, std::vector<double>(size_t(n_prob), 0.0));
+    std::vector<int64_t> ct;
+    for (int p = 0; p < n_prob; ++p)
+      for (int64_t c0 = 0; c0 < cd[size_t(p)].n; c0 += 64) ct.insert(ct.end(), {int64_t(p), c0});
+    UP(ctask_red, ct);
   }
   h->B.pd = h->pd.ptr;
   h->B.blk = h->blk.ptr;
@@ -565,6 +573,11 @@ int upload(ieti_handle* h) {
   if ((rc = dalloc(h->xgr, std::max<int64_t>(P.I_total, 1)))) return rc;
   if ((rc = dalloc(h->part_g, std::max<int64_t>({int64_t(h->ngemv_r[0]), h->symg.nblk, int64_t(1)})))) return rc;
   if ((rc = dalloc(h->part_t, std::max<int64_t>(ptoff, 1)))) return rc;
+  if ((rc = dalloc(h->tvec, std::max<int64_t>(M.n_gp, 1)))) return rc;
+  h->cred.part_t = h->part_t.ptr;
+  h->cred.task = h->ctask_red.ptr;
+  h->cred.ntask = h->ctask_red.n / 2;
+  h->cred.t = h->tvec.ptr;
   if ((rc = dalloc(h->pdone, n_prob))) return rc;
   if ((rc = dalloc(h->piters, n_prob))) return rc;
   if (h->pflags_h) (void)hipHostFree(h->pflags_h);
@@ -668,22 +681,28 @@ int gvariant(const ieti_handle* h, int fp32) { return h->gvar[fp32] >= 0 ? h->gv
 // One interface GEMV application with launch shape `variant` (row-streaming
 // shapes, or the symmetric lower-tile kernel); partials in part_g by the
 // variant's task list (index variant / 4 in the problem descriptors).
+// With coarse = true the same step also reduces the coarse partials of the
+// PCG (t = H^T p, for the operator's second half): in extra workgroups of the
+// symmetric kernel's block reduction, else in a launch of its own.
 template <typename MT>
 void launch_gemv(ieti_handle* h, const MT* M, int variant, const double* xg, double* v, const int* done,
-                 hipEvent_t a = nullptr, hipEvent_t b = nullptr) {
+                 hipEvent_t a = nullptr, hipEvent_t b = nullptr, bool coarse = false) {
   namespace D = ieti::dev;
+  const bool cr = coarse && h->cred.ntask > 0;
   if (variant == D::GEMV_SYM) {
-    D::gemv_sym(M, h->symg, xg, v, h->part_g.ptr, done, h->stream, a, b);
+    D::gemv_sym(M, h->symg, xg, v, h->part_g.ptr, done, h->stream, a, b, cr ? &h->cred : nullptr, &h->B);
     return;
   }
   const int ri = variant / 4;
   D::gemv(M, h->gemv_tasks[ri].ptr, h->ngemv_r[ri], h->max_ld, xg, v, h->part_g.ptr, done, h->task_prob[ri].ptr,
           h->stream, variant, a, b);
+  if (cr) D::coarse_reduce(h->cred, done, h->B, h->stream);
 }
 
 // Interface GEMV over all subdomains, timed with launch events when profiling.
 template <typename MT>
-void gemv_timed(ieti_handle* h, const MT* M, const double* xg, double* v, const int* done = nullptr) {
+void gemv_timed(ieti_handle* h, const MT* M, const double* xg, double* v, const int* done = nullptr,
+                bool coarse = false) {
   const int fp32 = std::is_same<MT, float>::value ? 1 : 0;
   hipEvent_t a = nullptr, b = nullptr;
   size_t slot = SIZE_MAX;
@@ -693,7 +712,7 @@ void gemv_timed(ieti_handle* h, const MT* M, const double* xg, double* v, const 
     b = next_event(h);
     if (!a || !b) a = b = nullptr;
   }
-  launch_gemv(h, M, gvariant(h, fp32), xg, v, done, a, b);
+  launch_gemv(h, M, gvariant(h, fp32), xg, v, done, a, b, coarse);
   if (a) h->ev_marks.emplace_back(fp32 ? 2 : 0, slot);
 }
 
@@ -705,7 +724,7 @@ void apply_F(ieti_handle* h, const double* x, double* out) {
   D::gather_rows(x, h->row_src.ptr, M.m_r, h->xgp.ptr, s);
   gemv_timed(h, h->Sinv.ptr, h->xgp.ptr, h->v.ptr);
   if (M.n_gp > 0) D::coarse_project(h->Ht.ptr, x, h->t.ptr, h->cprob.ptr, h->B, s);
-  D::combine(h->v.ptr, h->row_src.ptr, M.n_gp > 0 ? h->H.ptr : nullptr, h->t.ptr, out, h->B, s);
+  D::combine(h->v.ptr, h->row_src.ptr, M.n_gp > 0 ? h->Ht.ptr : nullptr, h->t.ptr, out, h->B, s);
 }
 
 // z = M_D^{-1} x = sum_k B_k S_rIrI^(k) B_k^T x  (D_s = I)
@@ -730,8 +749,8 @@ void pcg_iteration(ieti_handle* h, int par, const MT* Sinv, const MT* S) {
   double* part_rr = h->part.ptr + h->nblk;
   const int fp32 = std::is_same<MT, float>::value ? 1 : 0;
   const int gt = gvariant(h, fp32) / 4;
-  gemv_timed(h, Sinv, h->xgp.ptr, h->v.ptr, done);
-  D::pcg_F(h->v.ptr, h->row_src.ptr, h->H.ptr, h->part_t.ptr, h->part_g.ptr, h->p.ptr, h->lam.ptr, h->r.ptr,
+  gemv_timed(h, Sinv, h->xgp.ptr, h->v.ptr, done, true);
+  D::pcg_F(h->v.ptr, h->row_src.ptr, h->Ht.ptr, h->tvec.ptr, h->part_g.ptr, h->p.ptr, h->lam.ptr, h->r.ptr,
            h->xgr.ptr, part_rr, h->scal.ptr, par, done, perr, h->B, gt, s, dsc(h));
   gemv_timed(h, S, h->xgr.ptr, h->v.ptr, done);
   D::pcg_M(h->v.ptr, h->row_src.ptr, h->H.ptr, h->part_g.ptr, part_rr, h->p.ptr, h->z.ptr, h->xgp.ptr,
@@ -891,7 +910,7 @@ int compute_rhs(ieti_handle* h, bool use_graph) {
     if (M.n_gp > 0) {
       D::sum_sources(h->y.ptr, h->dsrc_ptr.ptr, h->dsrc_idx.ptr, M.n_gp, h->dtil.ptr, s);
       D::tri_small_inv(h->Lti.ptr, h->dtil.ptr, h->w.ptr, false, h->B, s);
-      D::axpy_rows(h->H.ptr, h->w.ptr, h->e.ptr, h->b.ptr, h->B, s);
+      D::axpy_rows(h->Ht.ptr, h->w.ptr, h->e.ptr, h->b.ptr, h->B, s);
     } else {
       D::vec_copy(h->e.ptr, h->b.ptr, M.m_r, s);
     }
@@ -1693,7 +1712,7 @@ int ieti_apply_F_noalloc(ieti_handle* h, const double* d_lambda, double* d_q, vo
             h->task_prob[ri].ptr, s, variant);
   }
   if (M.n_gp > 0) D::coarse_project(h->Ht.ptr, d_lambda, t, h->cprob.ptr, h->B, s);
-  D::combine(v, h->row_src.ptr, M.n_gp > 0 ? h->H.ptr : nullptr, t, d_q, h->B, s);
+  D::combine(v, h->row_src.ptr, M.n_gp > 0 ? h->Ht.ptr : nullptr, t, d_q, h->B, s);
   return check_launch();
 }
 

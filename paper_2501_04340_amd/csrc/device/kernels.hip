@@ -832,13 +832,47 @@ __global__ __launch_bounds__(64 * SYM_WAVES, 2) void k_gemv_sym(const MT* M, con
   if (threadIdx.x < 64) part[tk[5] + threadIdx.x] = rows[threadIdx.x];
 }
 
+// t_p[c] = sum over the problem's row blocks b of part_t[b][c] for the 64
+// columns c0..c0+63 of one problem (chunk task [problem, c0]): four thread
+// groups split the blocks, combined in fixed order.  Once per iteration,
+// before the operator's second half reads t.
+__device__ inline void coarse_reduce_chunk(const double* part_t, const int64_t* pd, const int64_t* ctask,
+                                           double* t, const int* done) {
+  __shared__ double acc4[4][64];
+  const int64_t pid = ctask[0], c0 = ctask[1];
+  if (done && done[pid]) return;
+  const int64_t* P = pd + PD_N * pid;
+  const int64_t n_gp = P[PD_NGP], nb = P[PD_B1] - P[PD_B0];
+  const double* pt = part_t + P[PD_PT];
+  const int cl = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t c = c0 + cl;
+  double s0 = 0.0, s1 = 0.0;
+  if (c < n_gp) {
+    int64_t b = q;
+    for (; b + 4 < nb; b += 8) {
+      s0 += pt[b * n_gp + c];
+      s1 += pt[(b + 4) * n_gp + c];
+    }
+    if (b < nb) s0 += pt[b * n_gp + c];
+  }
+  acc4[q][cl] = s0 + s1;
+  __syncthreads();
+  if (q == 0 && c < n_gp) t[P[PD_GP0] + c] = (acc4[0][cl] + acc4[1][cl]) + (acc4[2][cl] + acc4[3][cl]);
+}
+
 // Output block of 64 slots: v = sum of its contiguous partials (64 entries
 // apiece), split into four groups (partials g, g + 4, ...) summed by the four
 // waves and combined in fixed order; the block's dot partial
 // part_g[b] = sum_slots xg v.  blk: [first slot, first partial, count].
 __global__ __launch_bounds__(256) void k_gemv_sym_reduce(const double* part, const int64_t* blk, const double* xg,
                                                          double* v, double* part_g, const int* done,
-                                                         const int32_t* blk_prob) {
+                                                         const int32_t* blk_prob, int64_t nblk, const double* part_t,
+                                                         const int64_t* pd, const int64_t* ctask, double* tvec) {
+  // workgroups past the output blocks reduce the coarse partials (t = H^T p)
+  if (int64_t(blockIdx.x) >= nblk) {
+    coarse_reduce_chunk(part_t, pd, ctask + 2 * (blockIdx.x - nblk), tvec, done);
+    return;
+  }
   if (done && done[blk_prob[blockIdx.x]]) return;
   __shared__ double red[4][64];
   const int64_t* b = blk + 3 * blockIdx.x;
@@ -884,30 +918,9 @@ __device__ inline double reduce_partials_fast(const double* part, int n, double*
   return block_sum256(s, red);
 }
 
-// t[c] = sum_b part_t[b][c] into LDS, 64 columns per pass, four thread
-// groups splitting the blocks and combined in fixed order; returns the
-// calling thread's share of t.t.
-__device__ inline double coarse_from_partials(const double* part_t, int64_t n_gp, int nblk, double* tl,
-                                              double (*acc4)[64]) {
-  double tt = 0.0;
-  const int c0 = threadIdx.x & 63, q = threadIdx.x >> 6;
-  for (int64_t cb = 0; cb < n_gp; cb += 64) {
-    const int64_t c = cb + c0;
-    double sc = 0.0;
-    if (c < n_gp) {
-#pragma unroll 4
-      for (int b = q; b < nblk; b += 4) sc += part_t[int64_t(b) * n_gp + c];
-    }
-    acc4[q][c0] = sc;
-    __syncthreads();
-    if (q == 0 && c < n_gp) {
-      const double vv = (acc4[0][c0] + acc4[1][c0]) + (acc4[2][c0] + acc4[3][c0]);
-      tl[c] = vv;
-      tt += vv * vv;
-    }
-    __syncthreads();
-  }
-  return tt;
+__global__ __launch_bounds__(256) void k_coarse_reduce(const double* part_t, const int64_t* pd, const int64_t* ctask,
+                                                       double* t, const int* done) {
+  coarse_reduce_chunk(part_t, pd, ctask + 2 * blockIdx.x, t, done);
 }
 
 // out[c] = sum over the problem's rows of Ht_p[c][row] x[row] (block per global primal index)
@@ -925,24 +938,25 @@ __global__ __launch_bounds__(256) void k_coarse_project(const double* Ht, const 
   if (threadIdx.x == 0) out[c] = s;
 }
 
-// sum_c H_p[row][c] t[c] for one row of problem P
-__device__ inline double coarse_row(const double* H, const int64_t* P, int64_t row, const double* t) {
-  const int64_t n_gp = P[PD_NGP];
-  const double* Hr = H + P[PD_H] + (row - P[PD_MR0]) * n_gp;
+// sum_c H_p[row][c] t[c] for one row of problem P, read from the transposed
+// copy Ht_p (n_gp x m): consecutive rows of a wave read consecutive entries
+__device__ inline double coarse_row(const double* Ht, const int64_t* P, int64_t row, const double* t) {
+  const int64_t n_gp = P[PD_NGP], m = P[PD_MR1] - P[PD_MR0];
+  const double* Hc = Ht + P[PD_HT] + (row - P[PD_MR0]);
   double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
   int64_t c = 0;
   for (; c + 3 < n_gp; c += 4) {
-    c0 += Hr[c] * t[c];
-    c1 += Hr[c + 1] * t[c + 1];
-    c2 += Hr[c + 2] * t[c + 2];
-    c3 += Hr[c + 3] * t[c + 3];
+    c0 += Hc[c * m] * t[c];
+    c1 += Hc[(c + 1) * m] * t[c + 1];
+    c2 += Hc[(c + 2) * m] * t[c + 2];
+    c3 += Hc[(c + 3) * m] * t[c + 3];
   }
-  for (; c < n_gp; ++c) c0 += Hr[c] * t[c];
+  for (; c < n_gp; ++c) c0 += Hc[c * m] * t[c];
   return (c0 + c1) + (c2 + c3);
 }
 
 // q[row] = v[+1 slot] - v[-1 slot] + sum_c H_p[row][c] t_p[c]  (H may be null)
-__global__ __launch_bounds__(256) void k_combine(const double* v, const int64_t* row_src, const double* H,
+__global__ __launch_bounds__(256) void k_combine(const double* v, const int64_t* row_src, const double* Ht,
                                                  const double* t, double* q, const int64_t* pd, const int64_t* blk,
                                                  const double* ds) {
   int64_t row0;
@@ -952,18 +966,18 @@ __global__ __launch_bounds__(256) void k_combine(const double* v, const int64_t*
   const int64_t row = row0 + threadIdx.x;
   const int64_t s0 = row_src[2 * row], s1 = row_src[2 * row + 1];
   double val = ds ? ds[s0] * v[s0] - ds[s1] * v[s1] : v[s0] - v[s1];
-  if (H && P[PD_NGP] > 0) val += coarse_row(H, P, row, t + P[PD_GP0]);
+  if (Ht && P[PD_NGP] > 0) val += coarse_row(Ht, P, row, t + P[PD_GP0]);
   q[row] = val;
 }
 
 // PCG, first half of an iteration (after v = Sinv_k B_k^T p), per problem p of
-// the block: t = H_p^T p from the block partials, p^T F p = sum xg.v + t.t
+// the block: t = H_p^T p (reduced from pcg_M's block partials), p^T F p = sum xg.v + t.t
 // over the problem's GEMV tasks, alpha = rz / p^T F p, q = B v + H t,
 // lambda += alpha p, r -= alpha q, gather B^T r for the preconditioner,
 // partials of ||r||^2.  scal + 8 p: [0..1] rz (ping-pong by parity),
 // [2] alpha, [3] beta, [4] tol^2, [5] ||r||^2.  gt: GEMV task range index.
-__global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* row_src, const double* H,
-                                               const double* part_t, const double* part_g, const double* p,
+__global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* row_src, const double* Ht,
+                                               const double* tvec, const double* part_g, const double* p,
                                                double* lam, double* r, double* xg_r, double* part_rr, double* scal,
                                                int par, int* done, int* err, const int64_t* pd, const int64_t* blk,
                                                int gt, const double* ds) {
@@ -971,7 +985,6 @@ __global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* r
   if (done[pid]) return;
   extern __shared__ double tl[];
   __shared__ double red[4];
-  __shared__ double acc4[4][64];
   const int64_t* P = pd + PD_N * pid;
   const int64_t n_gp = P[PD_NGP];
   // the row's operands do not depend on the reductions: their loads go first
@@ -989,7 +1002,13 @@ __global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* r
     lr = lam[row];
     rv = r[row];
   }
-  const double tt = coarse_from_partials(part_t + P[PD_PT], n_gp, int(P[PD_B1] - P[PD_B0]), tl, acc4);
+  // t = H_p^T p (reduced once per iteration by the coarse reduction) into LDS
+  double tt = 0.0;
+  for (int64_t c = threadIdx.x; c < n_gp; c += 256) {
+    const double tc = tvec[P[PD_GP0] + c];
+    tl[c] = tc;
+    tt += tc * tc;
+  }
   const double tt_all = block_sum256(tt, red);
   const double pq = reduce_partials_fast(part_g + P[PD_T0 + 2 * gt], int(P[PD_T0 + 2 * gt + 1] - P[PD_T0 + 2 * gt]),
                                          red) +
@@ -1006,7 +1025,7 @@ __global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* r
   double rr = 0.0;
   if (act) {
     double q = vd;
-    if (n_gp > 0) q += coarse_row(H, P, row, tl);
+    if (n_gp > 0) q += coarse_row(Ht, P, row, tl);
     lam[row] = lr + alpha * pr;
     const double rn = rv - alpha * q;
     r[row] = rn;
@@ -1141,14 +1160,14 @@ __global__ void k_write_primal(const double* pglob, const int64_t* primal_edges,
 }
 
 // b[row] = e[row] - sum_c H_p[row][c] w_p[c]
-__global__ __launch_bounds__(256) void k_axpy_rows(const double* H, const double* w, const double* e, double* b,
+__global__ __launch_bounds__(256) void k_axpy_rows(const double* Ht, const double* w, const double* e, double* b,
                                                    const int64_t* pd, const int64_t* blk) {
   int64_t row0;
   const int64_t nrow = blk_rows(blk, pd, blockIdx.x, &row0);
   if (int64_t(threadIdx.x) >= nrow) return;
   const int64_t* P = pd + PD_N * blk[2 * blockIdx.x + 1];
   const int64_t row = row0 + threadIdx.x;
-  const double s = P[PD_NGP] > 0 ? coarse_row(H, P, row, w + P[PD_GP0]) : 0.0;
+  const double s = P[PD_NGP] > 0 ? coarse_row(Ht, P, row, w + P[PD_GP0]) : 0.0;
   b[row] = e[row] - s;
 }
 
@@ -1305,7 +1324,7 @@ void gemv(const float* M, const int64_t* task, int64_t ntask, int64_t max_ld, co
 }
 template <typename MT>
 void gemv_sym_impl(const MT* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
-                   hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                   hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop, const CoarseReduce* cr, const Batch* B) {
   if (g.ntask <= 0 || g.nblk <= 0) return;
   const int32_t* tp = done ? g.task_prob : nullptr;
   const int32_t* bp = done ? g.blk_prob : nullptr;
@@ -1316,15 +1335,22 @@ void gemv_sym_impl(const MT* M, const SymGemv& g, const double* xg, double* v, d
                           xg, g.part, done, tp);
   else
     hipLaunchKernelGGL(k_gemv_sym<MT>, dim3(g.ntask), dim3(64 * SYM_WAVES), 0, s, M, g.task, xg, g.part, done, tp);
-  hipLaunchKernelGGL(k_gemv_sym_reduce, dim3(g.nblk), dim3(256), 0, s, g.part, g.blk, xg, v, part_g, done, bp);
+  const int64_t nc = (cr && B) ? cr->ntask : 0;
+  hipLaunchKernelGGL(k_gemv_sym_reduce, dim3(g.nblk + nc), dim3(256), 0, s, g.part, g.blk, xg, v, part_g, done, bp,
+                     g.nblk, nc ? cr->part_t : nullptr, nc ? B->pd : nullptr, nc ? cr->task : nullptr,
+                     nc ? cr->t : nullptr);
 }
 void gemv_sym(const double* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
-              hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  gemv_sym_impl(M, g, xg, v, part_g, done, s, ev_start, ev_stop);
+              hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop, const CoarseReduce* cr, const Batch* B) {
+  gemv_sym_impl(M, g, xg, v, part_g, done, s, ev_start, ev_stop, cr, B);
 }
 void gemv_sym(const float* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
-              hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  gemv_sym_impl(M, g, xg, v, part_g, done, s, ev_start, ev_stop);
+              hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop, const CoarseReduce* cr, const Batch* B) {
+  gemv_sym_impl(M, g, xg, v, part_g, done, s, ev_start, ev_stop, cr, B);
+}
+void coarse_reduce(const CoarseReduce& c, const int* done, const Batch& B, hipStream_t s) {
+  if (c.ntask <= 0) return;
+  hipLaunchKernelGGL(k_coarse_reduce, dim3(c.ntask), dim3(256), 0, s, c.part_t, B.pd, c.task, c.t, done);
 }
 void to_float(const double* in, float* out, int64_t n, hipStream_t s) {
   if (n <= 0) return;
@@ -1340,12 +1366,12 @@ void combine(const double* v, const int64_t* row_src, const double* H, const dou
   if (B.n_blk <= 0) return;
   hipLaunchKernelGGL(k_combine, dim3(B.n_blk), dim3(256), 0, s, v, row_src, H, t, q, B.pd, B.blk, ds);
 }
-void pcg_F(const double* v, const int64_t* row_src, const double* H, const double* part_t, const double* part_g,
+void pcg_F(const double* v, const int64_t* row_src, const double* Ht, const double* tvec, const double* part_g,
            const double* p, double* lam, double* r, double* xg_r, double* part_rr, double* scal, int par, int* done,
            int* err, const Batch& B, int gt, hipStream_t s, const double* ds) {
   if (B.n_blk <= 0) return;
   hipLaunchKernelGGL(k_pcg_F, dim3(B.n_blk), dim3(256), size_t(B.max_gp > 0 ? B.max_gp : 1) * sizeof(double), s, v,
-                     row_src, H, part_t, part_g, p, lam, r, xg_r, part_rr, scal, par, done, err, B.pd, B.blk, gt, ds);
+                     row_src, Ht, tvec, part_g, p, lam, r, xg_r, part_rr, scal, par, done, err, B.pd, B.blk, gt, ds);
 }
 void pcg_M(const double* w, const int64_t* row_src, const double* H, const double* part_g, const double* part_rr,
            double* p, double* z, double* xg_p, double* part_t, double* scal, int par, int* done, int* iters, int init,

@@ -116,22 +116,36 @@ struct SymGemv {
   int64_t nblk = 0;
   double* part = nullptr;             // each block's partials contiguous: 64 entries apiece
 };
+// Reduction of the PCG's coarse block partials, t_p = H_p^T p = sum over the
+// problem's row blocks of part_t, one task [problem, first column] per 64
+// columns of a problem's n_gp; run by extra workgroups of the symmetric
+// GEMV's block reduction (cr) or on its own (coarse_reduce).
+struct CoarseReduce {
+  const double* part_t = nullptr;
+  const int64_t* task = nullptr;
+  int64_t ntask = 0;
+  double* t = nullptr;
+};
 void gemv_sym(const double* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
-              hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+              hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
+              const CoarseReduce* cr = nullptr, const Batch* B = nullptr);
 void gemv_sym(const float* M, const SymGemv& g, const double* xg, double* v, double* part_g, const int* done,
-              hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+              hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
+              const CoarseReduce* cr = nullptr, const Batch* B = nullptr);
+void coarse_reduce(const CoarseReduce& c, const int* done, const Batch& B, hipStream_t s);
 void to_float(const double* in, float* out, int64_t n, hipStream_t s);
 // out[c] = sum over problem(c)'s rows of Ht[c][row] x[row]; cprob[c] = problem of global primal c
 void coarse_project(const double* Ht, const double* x, double* out, const int32_t* cprob, const Batch& B,
                     hipStream_t s);
-// q[row] = v[src0] - v[src1] + sum_c H_p[row][c] t_p[c]  (H may be null); with ds:
+// q[row] = v[src0] - v[src1] + sum_c H_p[row][c] t_p[c], H_p read from its transpose Ht (may be null); with ds:
 // ds[src0] v[src0] - ds[src1] v[src1]
-void combine(const double* v, const int64_t* row_src, const double* H, const double* t, double* q, const Batch& B,
+void combine(const double* v, const int64_t* row_src, const double* Ht, const double* t, double* q, const Batch& B,
              hipStream_t s, const double* ds = nullptr);
 // scal + 8 p: [0..1] rz (ping-pong by iteration parity par), [2] alpha, [3] beta, [4] tol^2, [5] ||r||^2;
 // done / iters per problem; gt = index of the GEMV task list in use (part_g ranges);
 // ds = per-slot scaling of the preconditioner's jump operator, or null (D_s = I)
-void pcg_F(const double* v, const int64_t* row_src, const double* H, const double* part_t, const double* part_g,
+// Ht: the transposed coarse rows (n_gp x m per problem); tvec: t = H^T p reduced by coarse_reduce
+void pcg_F(const double* v, const int64_t* row_src, const double* Ht, const double* tvec, const double* part_g,
            const double* p, double* lam, double* r, double* xg_r, double* part_rr, double* scal, int par, int* done,
            int* err, const Batch& B, int gt, hipStream_t s, const double* ds);
 void pcg_M(const double* w, const int64_t* row_src, const double* H, const double* part_g, const double* part_rr,
@@ -147,8 +161,8 @@ void recovery_sources(double* y, const int64_t* p_pos, const int64_t* p_glob, in
                       const double* lam, hipStream_t s);
 void write_output(const double* y, const int64_t* src, const int64_t* edge, int64_t n, const double* pglob,
                   const int64_t* primal_edges, int64_t n_gp, double* a, hipStream_t s);
-// b[row] = e[row] - sum_c H_p[row][c] w_p[c]
-void axpy_rows(const double* H, const double* w, const double* e, double* b, const Batch& B, hipStream_t s);
+// b[row] = e[row] - sum_c H_p[row][c] w_p[c] (H_p read from its transpose Ht)
+void axpy_rows(const double* Ht, const double* w, const double* e, double* b, const Batch& B, hipStream_t s);
 void vec_copy(const double* x, double* y, int64_t n, hipStream_t s);
 // out = a x + b y
 void axpby(const double* x, const double* y, double* out, double a, double b, int64_t n, hipStream_t s);
