@@ -379,6 +379,7 @@ def stream_batches(args):
     roof = None
     kprof = None
     n_g_total, t_host = 0, 0.0
+    ftune = None
     for c0 in range(0, n, chunk):
         ids = list(range(c0, min(n, c0 + chunk)))
         th = time.perf_counter()
@@ -404,6 +405,15 @@ def stream_batches(args):
         B = Solver.batch_of(singles)
         for S in singles:
             S.close()
+        if ftune is not None:
+            B.set_factor_params(*ftune["params"])
+        elif not args.no_factor_tune:
+            # the factorisation autotuner runs on the first batch; later batches reuse its choice
+            B.factor(precision=PREC_MIXED, tune=True, **fkw)
+            prm, flog = B.factor_tuning()
+            ftune = {"params": prm, "batch": [ids[0], ids[-1]],
+                     "log_defer_tail_wgs_ms": [[float(x) for x in r] for r in flog]}
+            log(f"factorisation autotuner: defer {prm[0]}, tail {prm[1]}, update workgroups {prm[2]}")
         info = B.batch_info()
         pinfo = B.plan_info()
         for key in plan_sum:
@@ -529,6 +539,7 @@ def stream_batches(args):
         "speedup_batch_mixed_vs_single_plain": (t_single * K) / t_var["batch_mixed"],
         "mixed_outer_iters_mean": float(np.mean(outer)) if outer else None,
         "factorisation": factor_summary(plan_sum, fac_s["batch_mixed"] / K),
+        "factor_autotune": ftune,
         "b_error_vs_oracle": b_err,
         "host_assembly_s": t_host,
         "roofline": roof,
@@ -559,6 +570,8 @@ def main():
     ap.add_argument("--nn-epochs", type=int, default=300)
     ap.add_argument("--nn-hidden", type=int, default=256)
     ap.add_argument("--nn-lr", type=float, default=1e-3)
+    ap.add_argument("--no-factor-tune", action="store_true",
+                    help="keep the default factorisation parameters (no autotuning of the update schedule)")
     ap.add_argument("--gemv-variant", type=int, default=None, metavar="V",
                     help="force the interface GEMV launch shape (0-11 row streaming, 12 symmetric) instead of "
                          "the autotuner's choice; for profiled runs, where tracing adds a cost to every launch "
@@ -605,6 +618,8 @@ def main():
     info = S.plan_info()
     # the solution stays in HBM (a device buffer), as the inputs do
     a_dev = torch.empty(S.n_edges, dtype=torch.float64, device="cuda")
+    if not args.no_factor_tune:
+        S.factor(tune=True, **fkw)  # the factorisation autotuner; its choice is kept by the handle
     for w in range(args.warmup):
         S.factor(**fkw)
         st = S.solve_device(a_dev.data_ptr(), rtol=args.rtol)
@@ -731,8 +746,10 @@ def main():
         "kappa_lanczos": hi / lo,
         "f_applies_per_s": applies / pcg_s if pcg_s > 0 else None,
         "rel_residual": float(stats[-1]["rel_residual"]),
-        "factor_tflops": info["flops"] / (factor_ms * 1e-3) / 1e12,
-        "factorisation": factor_summary(info, factor_ms * 1e-3),
+        "factor_tflops": S.plan_info()["flops"] / (factor_ms * 1e-3) / 1e12,
+        "factorisation": factor_summary(S.plan_info(), factor_ms * 1e-3),
+        "factor_autotune": {"params": list(S.factor_tuning()[0]),
+                            "log_defer_tail_wgs_ms": S.factor_tuning()[1].tolist()},
         "roofline": roof,
         "gemv_autotune": {"fp64_shape": int(chosen[0]), "fp64_ms": [float(x) for x in tune_ms[0]],
                           "fp32_shape": int(chosen32[1]), "fp32_ms": [float(x) for x in tune_ms32[1]]},

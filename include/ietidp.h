@@ -111,7 +111,9 @@ typedef struct {
   int32_t gemv_variant; /* 0 = autotune the interface GEMV launch shape on the first factorisation
                            of the handle (kept afterwards); 1..13 = use shape gemv_variant - 1 */
   int32_t scaling;     /* IETI_SCALE_* of the preconditioner (0 = D_s = I as in the paper) */
-  int32_t reserved;
+  int32_t factor_tune; /* 1 = autotune the factorisation's parameters (deferral thresholds of the
+                          tile updates, persistent update workgroups) on the first factorisation of
+                          the handle, kept afterwards; 0 = the handle's current parameters */
   void* hip_stream;    /* hipStream_t to run on; NULL = the library's own stream */
 } ieti_factor_opts;
 
@@ -292,6 +294,21 @@ int ieti_apply_F_noalloc(ieti_handle* h, const double* d_lambda, double* d_q, vo
 
 /* Right-hand side b = e - G S_c^{-1} d of the interface problem [m_r]. */
 int ieti_get_rhs(ieti_handle* h, double* b);
+
+/* Parameters of the local factorisations' schedule (Section 2.1, the blocks
+ * of K_rr): a target tile's deferred updates are issued once `defer` of them
+ * are pending (`defer_tail` inside a subdomain's dense r_I tail) or at the
+ * target's deadline; the update launches use at most `update_wgs`
+ * persistent workgroups.  Defaults 8, 4, 1024.  Takes effect at the next
+ * ieti_factor (a changed threshold rebuilds the plan) and turns that
+ * handle's autotuning off.  A subdomain gets the same tasks, and bitwise the
+ * same factor, in any batch factored with the same parameters. */
+int ieti_set_factor_params(ieti_handle* h, int32_t defer, int32_t defer_tail, int32_t update_wgs);
+/* The parameters in use, params[3] = {defer, defer_tail, update_wgs}, and
+ * the autotuner's record log [n_log][4] = {defer, defer_tail, update_wgs,
+ * milliseconds per local factorisation} (n_log = 0 when it has not run);
+ * any output may be NULL. */
+int ieti_get_factor_tuning(const ieti_handle* h, int32_t* params, double* log, int32_t* n_log);
 
 /* Factorisation plan statistics, info[0..9] = {tile pool elements, S/Sinv
  * elements, algorithmic flops of the tile factorisation, flops of the same

@@ -43,6 +43,13 @@ struct ieti_handle {
   ieti::Model model;
   ieti::Plan plan;
   int plan_T = 0, plan_ordering = -1;
+  // factorisation parameters (deferral thresholds of the plan, persistent
+  // update workgroups): in use, those the current plan was built with, and
+  // the autotuner's record [defer, defer_tail, update workgroups, ms]
+  ieti::PlanParams pparams, plan_pp;
+  int64_t upd_wgs = ieti::dev::UPDATE_WGS;
+  bool ftuned = false;
+  std::vector<double> ftune_log;
   bool uploaded = false, factored = false;
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
@@ -231,12 +238,15 @@ int validate(const ieti_problem* pr) {
 }
 
 int build_plan_if_needed(ieti_handle* h, int T, int ordering) {
-  if (h->plan_T == T && h->plan_ordering == ordering) return IETI_OK;
+  if (h->plan_T == T && h->plan_ordering == ordering && h->plan_pp.defer == h->pparams.defer &&
+      h->plan_pp.defer_tail == h->pparams.defer_tail)
+    return IETI_OK;
   ieti::Error err{0, ""};
-  int rc = ieti::build_plan(h->model, T, ordering, h->plan, err);
+  int rc = ieti::build_plan(h->model, T, ordering, h->plan, err, h->pparams);
   if (rc) return fail(rc, err.msg);
   h->plan_T = T;
   h->plan_ordering = ordering;
+  h->plan_pp = h->pparams;
   h->uploaded = false;
   h->factored = false;
   return IETI_OK;
@@ -636,6 +646,93 @@ void prof_collect(ieti_handle* h) {
   }
   h->ev_marks.clear();
   h->ev_used = 0;
+}
+
+// The local factorisations of every subdomain (Section 2.1, the blocks of
+// K_rr): tile pool from the assembled values, then per level of the schedule
+// the S_rIrI copies, diagonal-tile Cholesky, panel solves and deferred updates.
+void enqueue_local_factor(ieti_handle* h, hipStream_t s) {
+  namespace D = ieti::dev;
+  const auto& P = h->plan;
+  D::fill(h->pool.ptr, P.pool_elems, 0.0, s);
+  D::scatter(h->pool.ptr, h->scatter_dst.ptr, h->scatter_val.ptr, int64_t(P.scatter_dst.size()), s);
+  for (int64_t j = 0; j < P.n_steps; ++j) {
+    D::copy_tiles(h->pool.ptr, h->copyS.ptr + 5 * P.copy_ptr[j], P.copy_ptr[j + 1] - P.copy_ptr[j], 1.0, h->S.ptr, s);
+    D::potrf_tiles(h->pool.ptr, h->inv.ptr, h->potrf.ptr + 3 * P.potrf_ptr[j], P.potrf_ptr[j + 1] - P.potrf_ptr[j],
+                   h->piv_tol.ptr, h->flags.ptr, s);
+    D::trsm_tiles(h->pool.ptr, h->inv.ptr, h->trsm.ptr + 2 * P.trsm_ptr[j], P.trsm_ptr[j + 1] - P.trsm_ptr[j], s);
+    const int64_t nupd = P.upd_ptr[j + 1] - P.upd_ptr[j];
+    const size_t ev = nupd > 0 ? prof_begin(h) : SIZE_MAX;
+    D::update_tiles(h->pool.ptr, h->upd.ptr + 3 * P.upd_ptr[j], h->upd_pair.ptr, nupd, s, h->upd_wgs);
+    prof_end(h, ev, 1);
+    if (ev != SIZE_MAX) {
+      const int64_t* t = P.upd_task.data() + 3 * P.upd_ptr[j];
+      for (int64_t q = 0; q < nupd; ++q) h->upd_tasks += double(t[3 * q + 2]);
+    }
+  }
+}
+
+// Autotuner of the factorisation's own parameters, run on the first
+// factorisation of a handle that asks for it: the persistent update launch's
+// workgroup count, then the deferral threshold before and inside the dense
+// r_I tail (each a new plan), one parameter at a time, each candidate timed
+// as the faster of two factorisations (after a warm-up run) on the handle's
+// own matrices.  The
+// winner is kept for the life of the handle (later factorisations are
+// bitwise repeatable).
+int tune_factor(ieti_handle* h, int T, int ordering, void* user_stream) {
+  h->ftune_log.clear();
+  auto time_it = [&](double* ms_out) -> int {
+    int rc = build_plan_if_needed(h, T, ordering);
+    if (rc) return rc;
+    rc = upload(h);
+    if (rc) return rc;
+    hipStream_t s = pick_stream(h, user_stream);
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIP_TRY(hipEventRecord(h->ev0, s));
+      enqueue_local_factor(h, s);
+      HIP_TRY(hipEventRecord(h->ev1, s));
+      HIP_TRY(hipEventSynchronize(h->ev1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      if (rep > 0) best = std::min(best, ms);  // the first run warms the caches and the code
+    }
+    *ms_out = double(best);
+    h->ftune_log.insert(h->ftune_log.end(),
+                        {double(h->pparams.defer), double(h->pparams.defer_tail), double(h->upd_wgs), *ms_out});
+    return IETI_OK;
+  };
+  double best_ms = 0.0, ms = 0.0;
+  int rc = time_it(&best_ms);
+  if (rc) return rc;
+  int64_t best_w = h->upd_wgs;
+  for (int64_t w : {int64_t(512), int64_t(2048)}) {
+    h->upd_wgs = w;
+    if ((rc = time_it(&ms))) return rc;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_w = w;
+    }
+  }
+  h->upd_wgs = best_w;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int cand[3] = {pass == 0 ? 4 : 2, pass == 0 ? 12 : 6, pass == 0 ? 16 : 8};
+    ieti::PlanParams best_p = h->pparams;
+    for (int c : cand) {
+      ieti::PlanParams tryp = best_p;
+      (pass == 0 ? tryp.defer : tryp.defer_tail) = c;
+      h->pparams = tryp;
+      if ((rc = time_it(&ms))) return rc;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_p = tryp;
+      }
+    }
+    h->pparams = best_p;
+  }
+  h->ftuned = true;
+  return IETI_OK;
 }
 
 int check_launch() {
@@ -1466,7 +1563,12 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   const int scaling = opts ? opts->scaling : IETI_SCALE_IDENTITY;
   if (scaling != IETI_SCALE_IDENTITY && scaling != IETI_SCALE_STIFFNESS && scaling != IETI_SCALE_MULTIPLICITY)
     return fail(IETI_ERR_INVALID_ARG, "unknown scaling");
-  int rc = build_plan_if_needed(h, T, opts ? opts->ordering : 0);
+  int rc = 0;
+  if (opts && opts->factor_tune == 1 && !h->ftuned) {
+    rc = tune_factor(h, T, opts->ordering, opts->hip_stream);
+    if (rc) return rc;
+  }
+  rc = build_plan_if_needed(h, T, opts ? opts->ordering : 0);
   if (rc) return rc;
   rc = upload(h);
   if (rc) return rc;
@@ -1482,22 +1584,7 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   D::fill(h->xgp.ptr, h->xgp.n, 0.0, s);
   D::fill(h->xgr.ptr, h->xgr.n, 0.0, s);
   HIP_TRY(hipEventRecord(h->ev0, s));
-  D::fill(h->pool.ptr, P.pool_elems, 0.0, s);
-  D::scatter(h->pool.ptr, h->scatter_dst.ptr, h->scatter_val.ptr, int64_t(P.scatter_dst.size()), s);
-  for (int64_t j = 0; j < P.n_steps; ++j) {
-    D::copy_tiles(h->pool.ptr, h->copyS.ptr + 5 * P.copy_ptr[j], P.copy_ptr[j + 1] - P.copy_ptr[j], 1.0, h->S.ptr, s);
-    D::potrf_tiles(h->pool.ptr, h->inv.ptr, h->potrf.ptr + 3 * P.potrf_ptr[j], P.potrf_ptr[j + 1] - P.potrf_ptr[j],
-                   h->piv_tol.ptr, h->flags.ptr, s);
-    D::trsm_tiles(h->pool.ptr, h->inv.ptr, h->trsm.ptr + 2 * P.trsm_ptr[j], P.trsm_ptr[j + 1] - P.trsm_ptr[j], s);
-    const int64_t nupd = P.upd_ptr[j + 1] - P.upd_ptr[j];
-    const size_t ev = nupd > 0 ? prof_begin(h) : SIZE_MAX;
-    D::update_tiles(h->pool.ptr, h->upd.ptr + 3 * P.upd_ptr[j], h->upd_pair.ptr, nupd, s);
-    prof_end(h, ev, 1);
-    if (ev != SIZE_MAX) {
-      const int64_t* t = P.upd_task.data() + 3 * P.upd_ptr[j];
-      for (int64_t q = 0; q < nupd; ++q) h->upd_tasks += double(t[3 * q + 2]);
-    }
-  }
+  enqueue_local_factor(h, s);
   D::copy_tiles(h->pool.ptr, h->xsinv.ptr, int64_t(P.xsinv_task.size() / 5), -1.0, h->Sinv.ptr, s);
   D::copy_tiles(h->pool.ptr, h->xphi.ptr, int64_t(P.xphi_task.size() / 5), -1.0, h->Phi.ptr, s);
   D::copy_tiles(h->pool.ptr, h->xspi.ptr, int64_t(P.xspi_task.size() / 5), 1.0, h->SPi.ptr, s);
@@ -1739,6 +1826,29 @@ int ieti_get_plan_info(const ieti_handle* h, double* info) {
                         double(P.n_update_tasks), sum_nI2, double(P.I_total), max_ld, double(P.T),
                         P.flops_scalar_rr, P.flops_scalar_aug};
   std::memcpy(info, v, sizeof(v));
+  return IETI_OK;
+}
+
+int ieti_set_factor_params(ieti_handle* h, int32_t defer, int32_t defer_tail, int32_t update_wgs) {
+  if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
+  if (defer < 1 || defer > 64 || defer_tail < 1 || defer_tail > 64 || update_wgs < 1 || update_wgs > 65536)
+    return fail(IETI_ERR_INVALID_ARG, "factorisation parameters out of range");
+  h->pparams.defer = defer;
+  h->pparams.defer_tail = defer_tail;
+  h->upd_wgs = update_wgs;
+  h->ftuned = true;  // explicit parameters: no autotuning on this handle
+  return IETI_OK;
+}
+
+int ieti_get_factor_tuning(const ieti_handle* h, int32_t* params, double* log, int32_t* n_log) {
+  if (!h) return fail(IETI_ERR_INVALID_ARG, "handle is NULL");
+  if (params) {
+    params[0] = h->pparams.defer;
+    params[1] = h->pparams.defer_tail;
+    params[2] = int32_t(h->upd_wgs);
+  }
+  if (n_log) *n_log = int32_t(h->ftune_log.size() / 4);
+  if (log) std::copy(h->ftune_log.begin(), h->ftune_log.end(), log);
   return IETI_OK;
 }
 

@@ -1220,9 +1220,11 @@ void trsm_tiles(double* pool, const double* inv, const int64_t* task, int64_t nt
   if (ntask <= 0) return;
   hipLaunchKernelGGL(k_trsm_inv, dim3(ntask), dim3(256), 0, s, pool, inv, task);
 }
-void update_tiles(double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, hipStream_t s) {
+void update_tiles(double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, hipStream_t s,
+                  int64_t max_wgs) {
   if (ntask <= 0) return;
-  const int64_t nwg = ntask < UPDATE_WGS ? ntask : UPDATE_WGS;
+  const int64_t cap = max_wgs > 0 ? max_wgs : UPDATE_WGS;
+  const int64_t nwg = ntask < cap ? ntask : cap;
   hipLaunchKernelGGL(k_update_multi, dim3(nwg), dim3(256), 0, s, pool, task, pair, ntask);
 }
 void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s) {

@@ -20,9 +20,10 @@ void potrf_tiles(double* pool, double* inv, const int64_t* task, int64_t ntask, 
 // trsm task [off_ij, off of L_jj^{-1}]: L_ij = A_ij L_jj^{-T}
 void trsm_tiles(double* pool, const double* inv, const int64_t* task, int64_t ntask, hipStream_t s);
 // update task [off_C, first pair, pair count], pairs [off_A, off_B]: C -= sum A B^T;
-// at most UPDATE_WGS workgroups, each walking its share of the tasks
+// at most max_wgs workgroups (persistent), each walking its share of the tasks
 constexpr int64_t UPDATE_WGS = 1024;
-void update_tiles(double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, hipStream_t s);
+void update_tiles(double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, hipStream_t s,
+                  int64_t max_wgs = UPDATE_WGS);
 void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s);
 
 // ---- triangular solves with the tile factor (augmented vectors)

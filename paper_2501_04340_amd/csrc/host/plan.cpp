@@ -67,12 +67,6 @@ void nested_dissection(const std::vector<std::vector<int32_t>>& adj, const std::
 
 int64_t round_up(int64_t x, int64_t t) { return (x + t - 1) / t * t; }
 
-// pending contributions at which a target tile's deferred update is issued:
-// before a subdomain's dense r_I tail (many targets per level, throughput
-// bound) and inside it (one column per level, few targets: the task's
-// pairs run in series, so long tasks stretch every level)
-constexpr int64_t UPDATE_DEFER = 8;
-constexpr int64_t UPDATE_DEFER_TAIL = 4;
 
 // Scalar-level work of the Cholesky factorisation in the plan's elimination
 // order (r_V by nested dissection, then r_I), from the elimination tree and
@@ -150,7 +144,7 @@ void scalar_factor_work(const Subdomain& s, const SubPlan& sp, double& rr, doubl
 
 }  // namespace
 
-int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
+int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, const PlanParams& pp) {
   plan = Plan();
   plan.T = T;
   const int S = m.n_sub;
@@ -375,11 +369,13 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
   // before the target is read (level(l) - 1 for a column of r, the level
   // before the S copy for r_V contributions to the r_I block, the
   // subdomain's last level for the trailing p / E_I columns).  Contributions
-  // are held back until UPDATE_DEFER of them are pending or the deadline is
-  // reached, so that a target tile is read and written once per batch of
-  // contributions instead of once per contributing level.  The decision
-  // depends on the subdomain alone, so a subdomain gets the same tasks in a
-  // batch as on its own.
+  // are held back until pp.defer of them are pending (pp.defer_tail inside
+  // the subdomain's dense r_I tail, where one column per level leaves few
+  // targets and a task's pairs run in series) or the deadline is reached, so
+  // that a target tile is read and written once per batch of contributions
+  // instead of once per contributing level.  The decision depends on the
+  // subdomain and the parameters alone, so a subdomain gets the same tasks in
+  // a batch as on its own.
   struct Pending {
     std::vector<int64_t> cols;  // contributing columns in order of arrival
     int64_t deadline = 0;
@@ -428,7 +424,7 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err) {
       }
       for (auto it = P.begin(); it != P.end();) {
         const Pending& q = it->second;
-        if (int64_t(q.cols.size()) < (lv >= sp.levS ? UPDATE_DEFER_TAIL : UPDATE_DEFER) && q.deadline > lv) {
+        if (int64_t(q.cols.size()) < (lv >= sp.levS ? pp.defer_tail : pp.defer) && q.deadline > lv) {
           ++it;
           continue;
         }

@@ -143,8 +143,15 @@ struct CoarsePlan {
 };
 void build_coarse_plan(const std::vector<CoarseDims>& dims, int T, CoarsePlan& cp);
 
+// Deferred tile updates: a target's pending contributions are issued once
+// `defer` of them are pending (`defer_tail` inside a subdomain's dense r_I
+// tail) or at the target's deadline.
+struct PlanParams {
+  int defer = 8;
+  int defer_tail = 4;
+};
 // ordering: 0 = nested dissection, 1 = natural
-int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err);
+int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, const PlanParams& pp = PlanParams());
 // recompute the value arrays (scatter_val, krp_val, b_aug0) from the model's
 // current matrix values and loads; the structure is unchanged
 void refill_values(const Model& m, Plan& plan);

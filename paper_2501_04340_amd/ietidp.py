@@ -52,7 +52,7 @@ class FactorOpts(C.Structure):
         ("ordering", C.c_int32),
         ("gemv_variant", C.c_int32),
         ("scaling", C.c_int32),
-        ("reserved", C.c_int32),
+        ("factor_tune", C.c_int32),
         ("hip_stream", C.c_void_p),
     ]
 
@@ -138,6 +138,7 @@ EXPORTS = [
     "ieti_get_problem_stats", "ieti_nn_init_params", "ieti_nn_set_normalisation", "ieti_nn_fit_normalisation",
     "ieti_nn_get_normalisation", "ieti_nn_dataset_append", "ieti_nn_train_file", "ieti_warm_rows",
     "ieti_warm_append", "ieti_warm_load", "ieti_warm_predict", "ieti_get_condition", "ieti_apply_F_noalloc",
+    "ieti_set_factor_params", "ieti_get_factor_tuning",
 ]
 
 
@@ -177,6 +178,8 @@ def load_library():
     lib.ieti_apply_F.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
     lib.ieti_apply_M.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
     lib.ieti_apply_F_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.ieti_set_factor_params.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+    lib.ieti_get_factor_tuning.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_double), P(C.c_int32)]
     lib.ieti_get_rhs.argtypes = [C.c_void_p, P(C.c_double)]
     lib.ieti_get_lambda.argtypes = [C.c_void_p, P(C.c_double)]
     lib.ieti_get_plan_info.argtypes = [C.c_void_p, P(C.c_double)]
@@ -379,10 +382,12 @@ class Solver:
         K = sp.csr_matrix((values[:nnz.value], indices[:nnz.value], indptr), shape=(n.value, n.value))
         return K, load[:n.value]
 
-    def factor(self, precision=PREC_FP64, ordering=0, stream=None, gemv_variant=None, scaling=SCALE_IDENTITY):
+    def factor(self, precision=PREC_FP64, ordering=0, stream=None, gemv_variant=None, scaling=SCALE_IDENTITY,
+               tune=False):
         o = FactorOpts()
         o.precision = precision
         o.scaling = int(scaling)
+        o.factor_tune = 1 if tune else 0
         o.tile = 0
         o.ordering = ordering
         o.gemv_variant = 0 if gemv_variant is None else int(gemv_variant) + 1
@@ -515,6 +520,19 @@ class Solver:
         keys = ["pool_elems", "S_elems", "flops", "dense_flops", "n_steps", "n_update_tasks", "sum_nI2",
                 "I_total", "max_ld", "tile", "flops_scalar_rr", "flops_scalar_aug"]
         return dict(zip(keys, v.tolist()))
+
+    def set_factor_params(self, defer, defer_tail, update_wgs):
+        _check(self.lib, self.lib.ieti_set_factor_params(self.h, int(defer), int(defer_tail), int(update_wgs)))
+
+    def factor_tuning(self):
+        """(defer, defer_tail, update_wgs) in use and the autotuner's record
+        [n, 4] = (defer, defer_tail, update_wgs, ms per local factorisation)."""
+        prm = np.zeros(3, np.int32)
+        n = C.c_int32(0)
+        _check(self.lib, self.lib.ieti_get_factor_tuning(self.h, _ptr(prm, C.c_int32), None, C.byref(n)))
+        log = np.zeros(max(n.value, 1) * 4)
+        _check(self.lib, self.lib.ieti_get_factor_tuning(self.h, None, _ptr(log, C.c_double), None))
+        return tuple(int(x) for x in prm), log[:n.value * 4].reshape(-1, 4)
 
     def gemv_tuning(self):
         """(chosen shape for FP64 and FP32 blocks, ms per shape [2, GEMV_SHAPES]) of the GEMV autotuner."""

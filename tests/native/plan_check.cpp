@@ -12,8 +12,9 @@
 // and the lists are checked for offsets inside the pool, no target twice in
 // one update launch, and no tile both written and read by one update launch.
 //
-// usage: plan_check P0 P1 P2 p n_el n_sub   (patches per direction, degree,
-// elements per patch, subdomains as contiguous ranges of patches)
+// usage: plan_check P0 P1 P2 p n_el n_sub [defer defer_tail]   (patches per
+// direction, degree, elements per patch, subdomains as contiguous ranges of
+// patches, deferral thresholds of the updates)
 // prints one line and exits 0 when every check holds.
 #include <cmath>
 #include <cstdio>
@@ -35,8 +36,8 @@ static void source(const double* x, int64_t n, double* o, void*) {
 }
 
 int main(int argc, char** argv) {
-  if (argc != 7) {
-    std::fprintf(stderr, "usage: plan_check P0 P1 P2 p n_el n_sub\n");
+  if (argc != 7 && argc != 9) {
+    std::fprintf(stderr, "usage: plan_check P0 P1 P2 p n_el n_sub [defer defer_tail]\n");
     return 2;
   }
   const int P0 = std::atoi(argv[1]), P1 = std::atoi(argv[2]), P2 = std::atoi(argv[3]);
@@ -72,7 +73,12 @@ int main(int argc, char** argv) {
   }
   finalize_single(m);
   Plan plan;
-  if (build_plan(m, 64, 0, plan, err)) {
+  PlanParams pp;
+  if (argc == 9) {
+    pp.defer = std::atoi(argv[7]);
+    pp.defer_tail = std::atoi(argv[8]);
+  }
+  if (build_plan(m, 64, 0, plan, err, pp)) {
     std::printf("plan failed: %s\n", err.msg.c_str());
     return 1;
   }

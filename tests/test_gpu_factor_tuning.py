@@ -1,0 +1,82 @@
+"""The factorisation autotuner and explicit schedule parameters, through the
+C ABI, against the FP64 oracle.
+
+The deferral thresholds of the tile updates and the persistent update
+workgroup count change the order in which a tile's contributions are
+summed, not the factorisation: every parameter set the autotuner tries, and
+the one it keeps, must give the oracle's interface blocks and solution.
+"""
+import numpy as np
+import pytest
+
+from oracle.post import b_error
+from oracle.run import OracleRun
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def _prob():
+    # deep enough for targets with more than 8 pending contributions
+    return configs.cube8(degree=3, n_el=4)
+
+
+def test_autotuned_factorisation_matches_oracle(ietilib):
+    import torch
+
+    from paper_2501_04340_amd import Solver
+
+    torch.cuda.set_device(0)
+    prob = _prob()
+    print("[factor-tuning] cube8 p=3 n_el=4, autotuned", flush=True)
+    S = Solver(prob)
+    try:
+        S.factor(tune=True)
+        params, log = S.factor_tuning()
+        # base point, two workgroup counts, three thresholds before and three inside the tail
+        assert log.shape == (9, 4), log
+        assert np.all(log[:, 3] > 0)
+        # every candidate is recorded once; the kept parameters are the fastest
+        assert len({tuple(r[:3]) for r in log.tolist()}) == 9
+        assert tuple(params) == tuple(int(v) for v in log[int(np.argmin(log[:, 3])), :3])
+        a1, st = S.solve(rtol=1e-12)
+        S.factor(tune=True)  # kept: no second tuning, bitwise the same factor
+        _, log2 = S.factor_tuning()
+        assert log2.shape == log.shape
+        a2, _ = S.solve(rtol=1e-12)
+        assert np.array_equal(a1, a2)
+        O = OracleRun(prob)
+        _, rel = b_error(O.space, a1, a_ref=O.monolithic())
+        assert rel <= 1e-9, rel
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("params", [(2, 1, 512), (16, 8, 2048)])
+def test_explicit_schedule_parameters_match_oracle(ietilib, params):
+    import torch
+
+    from paper_2501_04340_amd import Solver
+
+    torch.cuda.set_device(0)
+    prob = _prob()
+    print(f"[factor-tuning] cube8 p=3 n_el=4, parameters {params}", flush=True)
+    S = Solver(prob)
+    try:
+        S.set_factor_params(*params)
+        S.factor()
+        assert S.factor_tuning()[0] == params
+        O = OracleRun(prob)
+        D = O.ieti
+        for k in range(S.n_sub):
+            L = D.locals[k]
+            Sk, Sinv_k = S.schur(k)
+            K = L.K_rr.toarray()
+            Kinv = np.linalg.inv(K)
+            ref = Kinv[np.ix_(L.I, L.I)]
+            assert np.max(np.abs(Sinv_k - ref)) <= 1e-10 * np.max(np.abs(ref))
+        a, _ = S.solve(rtol=1e-12)
+        _, rel = b_error(O.space, a, a_ref=O.monolithic())
+        assert rel <= 1e-9, rel
+    finally:
+        S.close()

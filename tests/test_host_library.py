@@ -133,3 +133,22 @@ def test_network_file_is_checked_before_any_device_work(ietilib, tmp_path):
     p.write_bytes(b"IETINN01" + struct.pack("<5iq", 2, 3, 1, 1, 2, good_n) + bytes(4 * (good_n - 1)))
     assert lib.ieti_nn_load(str(p).encode(), C.byref(out)) == -1
     assert out.value is None
+
+
+def test_schedule_parameters_are_validated(ietilib):
+    """ieti_set_factor_params refuses thresholds and workgroup counts out of
+    range (host-side checks, no GPU) and reads back what it accepted."""
+    from paper_2501_04340_amd import Solver
+    from paper_2501_04340_amd.ietidp import IetiError
+    from workloads import configs
+
+    S = Solver(configs.cube8())
+    try:
+        for bad in [(0, 4, 1024), (8, 0, 1024), (8, 4, 0), (100, 4, 1024)]:
+            with pytest.raises(IetiError):
+                S.set_factor_params(*bad)
+        S.set_factor_params(12, 6, 512)
+        params, log = S.factor_tuning()
+        assert params == (12, 6, 512) and log.shape == (0, 4)
+    finally:
+        S.close()

@@ -42,6 +42,8 @@ def plan_check(tmp_path_factory):
     (2, 2, 2, 2, 4, 8),   # eight one-patch subdomains (the smallest box workload)
     (3, 2, 2, 2, 5, 3),   # uneven subdomains of four patches
     (2, 2, 2, 3, 6, 2),   # deep nested dissection: targets with more than 8 contributions
+    (2, 2, 2, 3, 6, 2, 2, 1),    # the autotuner's extreme thresholds: every contribution early ...
+    (2, 2, 2, 3, 6, 2, 16, 8),   # ... or most of them at their deadline
 ])
 def test_factor_schedule_matches_definition(plan_check, cfg):
     res = subprocess.run([plan_check, *map(str, cfg)], capture_output=True, text=True, timeout=300)
