@@ -43,7 +43,9 @@ WORKLOADS = {
 }
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "cube64_hbm_traffic_pmc.md")
+# PMC traffic summaries (rocprofv3 FETCH_SIZE / WRITE_SIZE passes) by workload
+TRAFFIC_PROFILES = [os.path.join(ROOT, "profiles", "cube64_hbm_traffic_pmc.md"),
+                    os.path.join(ROOT, "profiles", "stream256_batch32_hbm_traffic_pmc.md")]
 # the per-launch traffic depends on the kernels and on the factorisation's task lists
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2501_04340_amd", "csrc", "device", "kernels.hip"),
                    os.path.join(ROOT, "paper_2501_04340_amd", "csrc", "host", "plan.cpp")]
@@ -66,10 +68,15 @@ def measured_traffic(kernel, workload):
     taken."""
     import re
     try:
-        text = open(TRAFFIC_PROFILE).read()
         sha = sources_sha256()
     except OSError:
         return None
+    text = ""
+    for f in TRAFFIC_PROFILES:
+        try:
+            text += open(f).read() + "\n"
+        except OSError:
+            pass
     pat = (r"traffic_per_launch " + re.escape(kernel)
            + r": workload=(\S+) .*total_bytes=(\d+) sources_sha256=([0-9a-f]+)")
     for m in re.finditer(pat, text):
@@ -380,6 +387,7 @@ def stream_batches(args):
     kprof = None
     n_g_total, t_host = 0, 0.0
     ftune = None
+    pinned = tuple(int(x) for x in args.factor_params.split(",")) if args.factor_params else None
     for c0 in range(0, n, chunk):
         ids = list(range(c0, min(n, c0 + chunk)))
         th = time.perf_counter()
@@ -390,7 +398,7 @@ def stream_batches(args):
         n_g_total += sum(S.n_global for S in singles)
         # each problem alone (plain FP64): one untimed factor + solve, then a timed one
         buf = torch.empty(max(S.n_edges for S in singles), dtype=torch.float64, device="cuda")
-        for S in singles:
+        for S in ([] if args.no_single else singles):
             S.factor(**fkw)
             S.solve_device(buf.data_ptr(), rtol=args.rtol)
             torch.cuda.synchronize()
@@ -405,7 +413,10 @@ def stream_batches(args):
         B = Solver.batch_of(singles)
         for S in singles:
             S.close()
-        if ftune is not None:
+        if pinned is not None:
+            B.set_factor_params(*pinned)
+            ftune = {"params": list(pinned), "pinned": True}
+        elif ftune is not None:
             B.set_factor_params(*ftune["params"])
         elif not args.no_factor_tune:
             # the factorisation autotuner runs on the first batch; later batches reuse its choice
@@ -463,7 +474,7 @@ def stream_batches(args):
             kprof = {"kt": kt, "ps": ps, "chosen": chosen, "ids": (ids[0], ids[-1]), "plan": B.plan_info()}
         B.close()
         del a_dev
-        log(f"problems {ids[0]}..{ids[-1]}: alone {np.sum(lat_single[-len(ids):]):.0f} ms, batch mixed "
+        log(f"problems {ids[0]}..{ids[-1]}: alone {np.sum(lat_single[-len(ids):]) if lat_single else 0:.0f} ms, batch mixed "
             f"{lat['batch_mixed'][-1]:.0f} ms, batch plain {lat['batch_plain_fp64'][-1]:.0f} ms "
             f"(host assembly {t_host:.0f}s so far)")
 
@@ -507,8 +518,10 @@ def stream_batches(args):
                                 "frac_of_hbm_peak": (pcg_bytes[name] / pcg_s[name] / 1e9 / HBM_PEAK_GBS
                                                      if pcg_s[name] else None)}}
     vs = {k: summ(k) for k in variants}
-    vs["single_plain_fp64"] = {"solves_per_s": n / t_single, "latency_ms_p50": float(np.percentile(lat_single, 50)),
-                               "latency_ms_p99": float(np.percentile(lat_single, 99)), "passes": 1}
+    if lat_single:
+        vs["single_plain_fp64"] = {"solves_per_s": n / t_single,
+                                   "latency_ms_p50": float(np.percentile(lat_single, 50)),
+                                   "latency_ms_p99": float(np.percentile(lat_single, 99)), "passes": 1}
     # B error of the headline's solutions against the oracle's direct solves
     errs = {}
     for i, a in a_sample.items():
@@ -536,7 +549,7 @@ def stream_batches(args):
                    "n_g_total": n_g_total},
         "variants": vs,
         "speedup_batch_mixed_vs_batch_plain": vs["batch_mixed"]["solves_per_s"] / vs["batch_plain_fp64"]["solves_per_s"],
-        "speedup_batch_mixed_vs_single_plain": (t_single * K) / t_var["batch_mixed"],
+        "speedup_batch_mixed_vs_single_plain": (t_single * K) / t_var["batch_mixed"] if lat_single else None,
         "mixed_outer_iters_mean": float(np.mean(outer)) if outer else None,
         "factorisation": factor_summary(plan_sum, fac_s["batch_mixed"] / K),
         "factor_autotune": ftune,
@@ -572,6 +585,11 @@ def main():
     ap.add_argument("--nn-lr", type=float, default=1e-3)
     ap.add_argument("--no-factor-tune", action="store_true",
                     help="keep the default factorisation parameters (no autotuning of the update schedule)")
+    ap.add_argument("--factor-params", default=None, metavar="D,DT,W",
+                    help="pin the factorisation parameters (deferral thresholds, update workgroups) instead of "
+                         "autotuning them, e.g. for profiled runs")
+    ap.add_argument("--no-single", action="store_true",
+                    help="stream256: skip the each-problem-alone comparison (profiled runs of the batches)")
     ap.add_argument("--gemv-variant", type=int, default=None, metavar="V",
                     help="force the interface GEMV launch shape (0-11 row streaming, 12 symmetric) instead of "
                          "the autotuner's choice; for profiled runs, where tracing adds a cost to every launch "
@@ -618,7 +636,9 @@ def main():
     info = S.plan_info()
     # the solution stays in HBM (a device buffer), as the inputs do
     a_dev = torch.empty(S.n_edges, dtype=torch.float64, device="cuda")
-    if not args.no_factor_tune:
+    if args.factor_params:
+        S.set_factor_params(*(int(x) for x in args.factor_params.split(",")))
+    elif not args.no_factor_tune:
         S.factor(tune=True, **fkw)  # the factorisation autotuner; its choice is kept by the handle
     for w in range(args.warmup):
         S.factor(**fkw)

@@ -55,7 +55,7 @@ def test_traffic_read_only_for_matching_sources(tmp_path, monkeypatch):
         f"sources_sha256={sha}\n"
         "traffic_per_launch k_gemv<double>: workload=cube64 fetch_bytes=7 write_bytes=1 total_bytes=9 "
         "sources_sha256=" + "0" * 64 + "\n")
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILES", [str(prof)])
     assert bench.measured_traffic("k_update_multi", "cube64") == 15.0
     assert bench.measured_traffic("k_update_multi", "cube256") == 25.0
     assert bench.measured_traffic("k_gemv_sym<double>", "cube64") == 8.0
@@ -70,7 +70,7 @@ def test_traffic_read_only_for_matching_sources(tmp_path, monkeypatch):
 
 
 def test_traffic_missing_profile(tmp_path, monkeypatch):
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "absent.md"))
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILES", [str(tmp_path / "absent.md")])
     assert bench.measured_traffic("k_update_multi", "cube64") is None
 
 
@@ -78,7 +78,7 @@ def test_committed_summary_parses():
     """The committed summary carries a cube64 figure for both kernels
     bench.py reports, each with a 64-digit source hash."""
     import re
-    text = open(bench.TRAFFIC_PROFILE).read()
+    text = open(bench.TRAFFIC_PROFILES[0]).read()
     for k in ("k_update_multi", "k_gemv_sym<double>"):
         m = re.search(r"traffic_per_launch " + re.escape(k) + r": workload=cube64 .*total_bytes=(\d+) sources_sha256=([0-9a-f]{64})",
                       text)
