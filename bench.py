@@ -8,7 +8,7 @@ region.
 
 The default workload is ``stream256``: 256 independent box problems
 (2^a x 2^b x 2^c patches, p in {2, 3}, 4-6 elements, random reluctivity and
-source), solved in batches of 32 problems per handle, batched mixed
+source), solved in batches of 64 problems per handle, batched mixed
 precision against batched plain FP64 and each problem alone; a step is one
 pass over the whole stream and value = problems solved per second.
 ``--workload cube64`` (and cube8, cube256, ring576) time single problems:
@@ -395,6 +395,7 @@ def stream_batches(args):
         with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
             singles = list(ex.map(Solver, probs))
         t_host += time.perf_counter() - th
+        log(f"problems {ids[0]}..{ids[-1]}: assembled")
         n_g_total += sum(S.n_global for S in singles)
         # each problem alone (plain FP64): one untimed factor + solve, then a timed one
         buf = torch.empty(max(S.n_edges for S in singles), dtype=torch.float64, device="cuda")
@@ -410,21 +411,26 @@ def stream_batches(args):
             lat_single.append(dt * 1e3)
             t_single += dt
         del buf
+        if pinned is None and ftune is None and not args.no_factor_tune:
+            # the factorisation autotuner runs once, on a batch of (at most) the
+            # first 32 problems; every batch then uses its choice
+            nt = min(32, len(singles))
+            Bt = Solver.batch_of(singles[:nt])
+            Bt.factor(precision=PREC_MIXED, tune=True, **fkw)
+            prm, flog = Bt.factor_tuning()
+            Bt.close()
+            ftune = {"params": list(prm), "tuned_on_problems": [ids[0], ids[nt - 1]],
+                     "log_defer_tail_wgs_ms": [[float(x) for x in r] for r in flog]}
+            log(f"factorisation autotuner: defer {prm[0]}, tail {prm[1]}, update workgroups {prm[2]}")
         B = Solver.batch_of(singles)
         for S in singles:
             S.close()
+        log(f"problems {ids[0]}..{ids[-1]}: batch handle built")
         if pinned is not None:
             B.set_factor_params(*pinned)
             ftune = {"params": list(pinned), "pinned": True}
         elif ftune is not None:
             B.set_factor_params(*ftune["params"])
-        elif not args.no_factor_tune:
-            # the factorisation autotuner runs on the first batch; later batches reuse its choice
-            B.factor(precision=PREC_MIXED, tune=True, **fkw)
-            prm, flog = B.factor_tuning()
-            ftune = {"params": prm, "batch": [ids[0], ids[-1]],
-                     "log_defer_tail_wgs_ms": [[float(x) for x in r] for r in flog]}
-            log(f"factorisation autotuner: defer {prm[0]}, tail {prm[1]}, update workgroups {prm[2]}")
         info = B.batch_info()
         pinfo = B.plan_info()
         for key in plan_sum:
@@ -450,6 +456,7 @@ def stream_batches(args):
                 pcg_bytes[name] += st["pcg_bytes"]
                 fac_s[name] += st["t_factor_s"]
                 applies[name] += st["f_applies"]
+            log(f"problems {ids[0]}..{ids[-1]}: {name} timed")
             ps = [B.problem_stats(p) for p in range(len(ids))]
             iters[name].extend(x["iters"] for x in ps)
             resid[name].extend(x["rel_residual"] for x in ps)
@@ -572,12 +579,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle work in the cpu_baseline leg (wall time of the worker pool on stream256)")
-    ap.add_argument("--cpu-max-edges", type=int, default=40000,
+    ap.add_argument("--cpu-max-edges", type=int, default=25000,
                     help="stream256 cpu_baseline: largest problem (coefficients) the oracle sample takes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     ap.add_argument("--stream-count", type=int, default=256)
-    ap.add_argument("--stream-chunk", type=int, default=32)
+    ap.add_argument("--stream-chunk", type=int, default=64,
+                    help="stream256: problems per batch handle (64: the host-side plan of a batch takes about "
+                         "1 GB per problem, so the whole stream of 256 in one handle does not fit host memory)")
     ap.add_argument("--ring-train", type=int, default=512)
     ap.add_argument("--ring-test", type=int, default=64)
     ap.add_argument("--nn-epochs", type=int, default=300)

@@ -209,6 +209,19 @@ int ieti_assemble(const ieti_problem* prob, ieti_handle** out);
  * ieti_assemble_batch(p, 1, out). */
 int ieti_assemble_batch(const ieti_problem* probs, int32_t n, ieti_handle** out);
 
+/* Assembly options.  primal = 1: the primal DOFs of Section 3 (every cotree
+ * edge of weight 2), as ieti_assemble; primal = 0: no primal DOFs, which makes
+ * the local matrices K_rr of subdomains whose remaining DOFs do not pin the
+ * gradient kernel singular (Section 3) -- for checking that; an edge of three
+ * or more subdomains then gets one multiplier, between its first two
+ * subdomains, so the interface problem is not the paper's. */
+typedef struct {
+  int32_t version;   /* must equal IETI_ABI_VERSION */
+  int32_t primal;    /* 1 (default) or 0 */
+  int32_t reserved[6];
+} ieti_assemble_opts;
+int ieti_assemble_ex(const ieti_problem* prob, const ieti_assemble_opts* opts, ieti_handle** out);
+
 /* Batch handle built from n single-problem handles (their assembled
  * systems are copied; the inputs stay valid and independent).  Same as
  * ieti_assemble_batch on the handles' problems, without repeating the

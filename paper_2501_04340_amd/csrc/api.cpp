@@ -92,6 +92,7 @@ struct ieti_handle {
   ieti::dev::CoarseReduce cred;
   DBuf<double> lam_acc, rtrue;            // outer multipliers and FP64 residual (mixed precision)
   DBuf<float> S32, Sinv32;                // FP32 copies of S_rIrI and (K_rr^{-1})_II (mixed precision)
+  DBuf<float> H32, Ht32;                  // FP32 copies of the coarse rows H and H^T (mixed precision)
   bool mixed = false;
   hipGraph_t graph = nullptr, graph32 = nullptr;
   hipGraphExec_t graph_exec = nullptr, graph_exec32 = nullptr;
@@ -205,6 +206,8 @@ struct ieti_handle {
     }
     S32.release();
     Sinv32.release();
+    H32.release();
+    Ht32.release();
     warm.release();
     nu_d.release();
     lscale_d.release();
@@ -238,10 +241,22 @@ int validate(const ieti_problem* pr) {
 }
 
 int build_plan_if_needed(ieti_handle* h, int T, int ordering) {
-  if (h->plan_T == T && h->plan_ordering == ordering && h->plan_pp.defer == h->pparams.defer &&
-      h->plan_pp.defer_tail == h->pparams.defer_tail)
-    return IETI_OK;
+  const bool same_structure = h->plan_T == T && h->plan_ordering == ordering;
+  const bool same_params = h->plan_pp.defer == h->pparams.defer && h->plan_pp.defer_tail == h->pparams.defer_tail;
+  if (same_structure && same_params) return IETI_OK;
   ieti::Error err{0, ""};
+  if (same_structure) {
+    // new deferral thresholds: only the update task lists change
+    int rc = ieti::build_update_tasks(h->plan, h->pparams, err);
+    if (rc) return fail(rc, err.msg);
+    h->plan_pp = h->pparams;
+    h->factored = false;
+    if (h->uploaded) {
+      if ((rc = dupload(h->upd, h->plan.upd_task))) return rc;
+      if ((rc = dupload(h->upd_pair, h->plan.upd_pair))) return rc;
+    }
+    return IETI_OK;
+  }
   int rc = ieti::build_plan(h->model, T, ordering, h->plan, err, h->pparams);
   if (rc) return fail(rc, err.msg);
   h->plan_T = T;
@@ -834,6 +849,18 @@ void apply_M(ieti_handle* h, const double* x, double* out) {
   D::combine(h->v.ptr, h->row_src.ptr, nullptr, nullptr, out, h->B, s, dsc(h));
 }
 
+// Coarse rows H (or H^T) stored in the precision MT of the interface blocks.
+template <typename MT>
+const MT* coarse_rows(const ieti_handle* h, bool transposed);
+template <>
+const double* coarse_rows<double>(const ieti_handle* h, bool transposed) {
+  return transposed ? h->Ht.ptr : h->H.ptr;
+}
+template <>
+const float* coarse_rows<float>(const ieti_handle* h, bool transposed) {
+  return transposed ? h->Ht32.ptr : h->H32.ptr;
+}
+
 // One PCG iteration of parity `par` as four launches, with the interface
 // blocks stored as MT (FP64, or FP32 in the inner solves of the mixed path).
 template <typename MT>
@@ -846,11 +873,14 @@ void pcg_iteration(ieti_handle* h, int par, const MT* Sinv, const MT* S) {
   double* part_rr = h->part.ptr + h->nblk;
   const int fp32 = std::is_same<MT, float>::value ? 1 : 0;
   const int gt = gvariant(h, fp32) / 4;
+  // the coarse rows in the blocks' precision (the inner solves of the mixed path read FP32 copies)
+  const MT* H = coarse_rows<MT>(h, false);
+  const MT* Ht = coarse_rows<MT>(h, true);
   gemv_timed(h, Sinv, h->xgp.ptr, h->v.ptr, done, true);
-  D::pcg_F(h->v.ptr, h->row_src.ptr, h->Ht.ptr, h->tvec.ptr, h->part_g.ptr, h->p.ptr, h->lam.ptr, h->r.ptr,
+  D::pcg_F(h->v.ptr, h->row_src.ptr, Ht, h->tvec.ptr, h->part_g.ptr, h->p.ptr, h->lam.ptr, h->r.ptr,
            h->xgr.ptr, part_rr, h->scal.ptr, par, done, perr, h->B, gt, s, dsc(h));
   gemv_timed(h, S, h->xgr.ptr, h->v.ptr, done);
-  D::pcg_M(h->v.ptr, h->row_src.ptr, h->H.ptr, h->part_g.ptr, part_rr, h->p.ptr, h->z.ptr, h->xgp.ptr,
+  D::pcg_M(h->v.ptr, h->row_src.ptr, H, h->part_g.ptr, part_rr, h->p.ptr, h->z.ptr, h->xgp.ptr,
            h->part_t.ptr, h->scal.ptr, par, done, iters, 0, h->B, gt, s, dsc(h));
 }
 
@@ -1132,8 +1162,12 @@ int run_pcg(ieti_handle* h, const std::vector<double>& tol2, const std::vector<d
   D::gather_rows(h->r.ptr, h->row_src.ptr, m_r, h->xgr.ptr, s, dsc(h));
   if (fp32) launch_gemv(h, h->S32.ptr, gvariant(h, pf), h->xgr.ptr, h->v.ptr, nullptr);
   else launch_gemv(h, h->S.ptr, gvariant(h, pf), h->xgr.ptr, h->v.ptr, nullptr);
-  D::pcg_M(h->v.ptr, h->row_src.ptr, h->H.ptr, h->part_g.ptr, part_rr, h->p.ptr, h->z.ptr, h->xgp.ptr, h->part_t.ptr,
-           h->scal.ptr, 0, h->pdone.ptr, h->piters.ptr, 1, h->B, gt, s, dsc(h));
+  if (fp32)
+    D::pcg_M(h->v.ptr, h->row_src.ptr, h->H32.ptr, h->part_g.ptr, part_rr, h->p.ptr, h->z.ptr, h->xgp.ptr,
+             h->part_t.ptr, h->scal.ptr, 0, h->pdone.ptr, h->piters.ptr, 1, h->B, gt, s, dsc(h));
+  else
+    D::pcg_M(h->v.ptr, h->row_src.ptr, h->H.ptr, h->part_g.ptr, part_rr, h->p.ptr, h->z.ptr, h->xgp.ptr,
+             h->part_t.ptr, h->scal.ptr, 0, h->pdone.ptr, h->piters.ptr, 1, h->B, gt, s, dsc(h));
   if (use_graph) {
     int rc = capture_graph(h, fp32);
     if (rc) return rc;
@@ -1379,10 +1413,11 @@ int solve_impl(ieti_handle* h, const ieti_solve_opts* opts, double* a_host, doub
 }
 
 // Validation, topology, gauge and assembly of one problem into m (host).
-int assemble_model(const ieti_problem* prob, ieti::Model& m) {
+int assemble_model(const ieti_problem* prob, ieti::Model& m, bool primal = true) {
   int rc = validate(prob);
   if (rc) return rc;
   m.prob = *prob;
+  m.primal_enabled = primal;
   const int64_t np = int64_t(prob->patches[0]) * prob->patches[1] * prob->patches[2];
   m.part.assign(prob->patch_to_subdomain, prob->patch_to_subdomain + np);
   m.nu.assign(prob->nu_per_patch, prob->nu_per_patch + np);
@@ -1475,6 +1510,28 @@ int ieti_assemble_batch(const ieti_problem* probs, int32_t n, ieti_handle** out)
     }
   }
   int rc = build_plan_if_needed(h, ieti::dev::TILE, 0);
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return IETI_OK;
+}
+
+int ieti_assemble_ex(const ieti_problem* prob, const ieti_assemble_opts* opts, ieti_handle** out) {
+  Phase ph("ieti_assemble");
+  if (!out) return fail(IETI_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!prob) return fail(IETI_ERR_INVALID_ARG, "problem is NULL");
+  bool primal = true;
+  if (opts) {
+    if (opts->version != IETI_ABI_VERSION) return fail(IETI_ERR_INVALID_ARG, "ieti_assemble_opts version mismatch");
+    if (opts->primal != 0 && opts->primal != 1) return fail(IETI_ERR_INVALID_ARG, "primal must be 0 or 1");
+    primal = opts->primal == 1;
+  }
+  auto* h = new ieti_handle();
+  int rc = assemble_model(prob, h->model, primal);
+  if (!rc) rc = build_plan_if_needed(h, ieti::dev::TILE, 0);
   if (rc) {
     delete h;
     return rc;
@@ -1616,6 +1673,14 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
     }
     D::to_float(h->S.ptr, h->S32.ptr, P.S_elems, s);
     D::to_float(h->Sinv.ptr, h->Sinv32.ptr, P.S_elems, s);
+    if (M.n_gp > 0) {
+      if (h->H32.n != h->H.n) {
+        if ((rc = dalloc(h->H32, h->H.n))) return rc;
+        if ((rc = dalloc(h->Ht32, h->Ht.n))) return rc;
+      }
+      D::to_float(h->H.ptr, h->H32.ptr, h->H.n, s);
+      D::to_float(h->Ht.ptr, h->Ht32.ptr, h->Ht.n, s);
+    }
   }
   HIP_TRY(hipEventRecord(h->ev1, s));
   rc = check_launch();

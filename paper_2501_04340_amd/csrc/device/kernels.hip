@@ -940,18 +940,19 @@ __global__ __launch_bounds__(256) void k_coarse_project(const double* Ht, const 
 
 // sum_c H_p[row][c] t[c] for one row of problem P, read from the transposed
 // copy Ht_p (n_gp x m): consecutive rows of a wave read consecutive entries
-__device__ inline double coarse_row(const double* Ht, const int64_t* P, int64_t row, const double* t) {
+template <typename HT>
+__device__ inline double coarse_row(const HT* Ht, const int64_t* P, int64_t row, const double* t) {
   const int64_t n_gp = P[PD_NGP], m = P[PD_MR1] - P[PD_MR0];
-  const double* Hc = Ht + P[PD_HT] + (row - P[PD_MR0]);
+  const HT* Hc = Ht + P[PD_HT] + (row - P[PD_MR0]);
   double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
   int64_t c = 0;
   for (; c + 3 < n_gp; c += 4) {
-    c0 += Hc[c * m] * t[c];
-    c1 += Hc[(c + 1) * m] * t[c + 1];
-    c2 += Hc[(c + 2) * m] * t[c + 2];
-    c3 += Hc[(c + 3) * m] * t[c + 3];
+    c0 += double(Hc[c * m]) * t[c];
+    c1 += double(Hc[(c + 1) * m]) * t[c + 1];
+    c2 += double(Hc[(c + 2) * m]) * t[c + 2];
+    c3 += double(Hc[(c + 3) * m]) * t[c + 3];
   }
-  for (; c < n_gp; ++c) c0 += Hc[c * m] * t[c];
+  for (; c < n_gp; ++c) c0 += double(Hc[c * m]) * t[c];
   return (c0 + c1) + (c2 + c3);
 }
 
@@ -976,7 +977,8 @@ __global__ __launch_bounds__(256) void k_combine(const double* v, const int64_t*
 // lambda += alpha p, r -= alpha q, gather B^T r for the preconditioner,
 // partials of ||r||^2.  scal + 8 p: [0..1] rz (ping-pong by parity),
 // [2] alpha, [3] beta, [4] tol^2, [5] ||r||^2.  gt: GEMV task range index.
-__global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* row_src, const double* Ht,
+template <typename HT>
+__global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* row_src, const HT* Ht,
                                                const double* tvec, const double* part_g, const double* p,
                                                double* lam, double* r, double* xg_r, double* part_rr, double* scal,
                                                int par, int* done, int* err, const int64_t* pd, const int64_t* blk,
@@ -1042,7 +1044,8 @@ __global__ __launch_bounds__(256) void k_pcg_F(const double* v, const int64_t* r
 // convergence test on ||r||^2, rz = sum xg_r.w, z = B w, beta = rz / rz_old,
 // p = z + beta p, gather B^T p for the next operator GEMV and the block
 // partials of H_p^T p.  init = 1 starts the recurrence (beta = 0, no test).
-__global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* row_src, const double* H,
+template <typename HT>
+__global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* row_src, const HT* H,
                                                const double* part_g, const double* part_rr, double* p, double* z,
                                                double* xg_p, double* part_t, double* scal, int par, int* done,
                                                int* iters, int init, const int64_t* pd, const int64_t* blk, int gt,
@@ -1102,7 +1105,7 @@ __global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* r
   // block partials of H_p^T p: 64 columns per pass, four row quarters per column
   __shared__ double acc4[4][64];
   const int64_t n_gp = P[PD_NGP];
-  const double* Hb = H + P[PD_H] + (row0 - P[PD_MR0]) * n_gp;
+  const HT* Hb = H + P[PD_H] + (row0 - P[PD_MR0]) * n_gp;
   double* pt = part_t + P[PD_PT] + (b - P[PD_B0]) * n_gp;
   const int c0 = threadIdx.x & 63, q = threadIdx.x >> 6;
   for (int64_t cb = 0; cb < n_gp; cb += 64) {
@@ -1111,7 +1114,7 @@ __global__ __launch_bounds__(256) void k_pcg_M(const double* w, const int64_t* r
     if (c < n_gp) {
       const int64_t i0 = 64 * q, i1 = (64 * q + 64) < nrow ? 64 * q + 64 : nrow;
 #pragma unroll 8
-      for (int64_t i = i0; i < i1; ++i) s += Hb[i * n_gp + c] * pl[i];
+      for (int64_t i = i0; i < i1; ++i) s += double(Hb[i * n_gp + c]) * pl[i];
     }
     acc4[q][c0] = s;
     __syncthreads();
@@ -1368,19 +1371,41 @@ void combine(const double* v, const int64_t* row_src, const double* H, const dou
   if (B.n_blk <= 0) return;
   hipLaunchKernelGGL(k_combine, dim3(B.n_blk), dim3(256), 0, s, v, row_src, H, t, q, B.pd, B.blk, ds);
 }
+template <typename HT>
+void pcg_F_impl(const double* v, const int64_t* row_src, const HT* Ht, const double* tvec, const double* part_g,
+                const double* p, double* lam, double* r, double* xg_r, double* part_rr, double* scal, int par, int* done,
+                int* err, const Batch& B, int gt, hipStream_t s, const double* ds) {
+  if (B.n_blk <= 0) return;
+  hipLaunchKernelGGL(k_pcg_F<HT>, dim3(B.n_blk), dim3(256), size_t(B.max_gp > 0 ? B.max_gp : 1) * sizeof(double), s,
+                     v, row_src, Ht, tvec, part_g, p, lam, r, xg_r, part_rr, scal, par, done, err, B.pd, B.blk, gt, ds);
+}
 void pcg_F(const double* v, const int64_t* row_src, const double* Ht, const double* tvec, const double* part_g,
            const double* p, double* lam, double* r, double* xg_r, double* part_rr, double* scal, int par, int* done,
            int* err, const Batch& B, int gt, hipStream_t s, const double* ds) {
+  pcg_F_impl(v, row_src, Ht, tvec, part_g, p, lam, r, xg_r, part_rr, scal, par, done, err, B, gt, s, ds);
+}
+void pcg_F(const double* v, const int64_t* row_src, const float* Ht, const double* tvec, const double* part_g,
+           const double* p, double* lam, double* r, double* xg_r, double* part_rr, double* scal, int par, int* done,
+           int* err, const Batch& B, int gt, hipStream_t s, const double* ds) {
+  pcg_F_impl(v, row_src, Ht, tvec, part_g, p, lam, r, xg_r, part_rr, scal, par, done, err, B, gt, s, ds);
+}
+template <typename HT>
+void pcg_M_impl(const double* w, const int64_t* row_src, const HT* H, const double* part_g, const double* part_rr,
+                double* p, double* z, double* xg_p, double* part_t, double* scal, int par, int* done, int* iters,
+                int init, const Batch& B, int gt, hipStream_t s, const double* ds) {
   if (B.n_blk <= 0) return;
-  hipLaunchKernelGGL(k_pcg_F, dim3(B.n_blk), dim3(256), size_t(B.max_gp > 0 ? B.max_gp : 1) * sizeof(double), s, v,
-                     row_src, Ht, tvec, part_g, p, lam, r, xg_r, part_rr, scal, par, done, err, B.pd, B.blk, gt, ds);
+  hipLaunchKernelGGL(k_pcg_M<HT>, dim3(B.n_blk), dim3(256), 0, s, w, row_src, H, part_g, part_rr, p, z, xg_p, part_t,
+                     scal, par, done, iters, init, B.pd, B.blk, gt, ds, B.hist, B.hcap);
 }
 void pcg_M(const double* w, const int64_t* row_src, const double* H, const double* part_g, const double* part_rr,
            double* p, double* z, double* xg_p, double* part_t, double* scal, int par, int* done, int* iters, int init,
            const Batch& B, int gt, hipStream_t s, const double* ds) {
-  if (B.n_blk <= 0) return;
-  hipLaunchKernelGGL(k_pcg_M, dim3(B.n_blk), dim3(256), 0, s, w, row_src, H, part_g, part_rr, p, z, xg_p, part_t,
-                     scal, par, done, iters, init, B.pd, B.blk, gt, ds, B.hist, B.hcap);
+  pcg_M_impl(w, row_src, H, part_g, part_rr, p, z, xg_p, part_t, scal, par, done, iters, init, B, gt, s, ds);
+}
+void pcg_M(const double* w, const int64_t* row_src, const float* H, const double* part_g, const double* part_rr,
+           double* p, double* z, double* xg_p, double* part_t, double* scal, int par, int* done, int* iters, int init,
+           const Batch& B, int gt, hipStream_t s, const double* ds) {
+  pcg_M_impl(w, row_src, H, part_g, part_rr, p, z, xg_p, part_t, scal, par, done, iters, init, B, gt, s, ds);
 }
 void gather_add(const double* y, const int64_t* idx, double sgn, int64_t n, double* out, hipStream_t s) {
   if (n <= 0) return;

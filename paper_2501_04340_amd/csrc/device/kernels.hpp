@@ -149,7 +149,14 @@ void combine(const double* v, const int64_t* row_src, const double* Ht, const do
 void pcg_F(const double* v, const int64_t* row_src, const double* Ht, const double* tvec, const double* part_g,
            const double* p, double* lam, double* r, double* xg_r, double* part_rr, double* scal, int par, int* done,
            int* err, const Batch& B, int gt, hipStream_t s, const double* ds);
+// the same with FP32-stored coarse rows (inner PCG of the mixed path)
+void pcg_F(const double* v, const int64_t* row_src, const float* Ht, const double* tvec, const double* part_g,
+           const double* p, double* lam, double* r, double* xg_r, double* part_rr, double* scal, int par, int* done,
+           int* err, const Batch& B, int gt, hipStream_t s, const double* ds);
 void pcg_M(const double* w, const int64_t* row_src, const double* H, const double* part_g, const double* part_rr,
+           double* p, double* z, double* xg_p, double* part_t, double* scal, int par, int* done, int* iters, int init,
+           const Batch& B, int gt, hipStream_t s, const double* ds);
+void pcg_M(const double* w, const int64_t* row_src, const float* H, const double* part_g, const double* part_rr,
            double* p, double* z, double* xg_p, double* part_t, double* scal, int par, int* done, int* iters, int init,
            const Batch& B, int gt, hipStream_t s, const double* ds);
 

@@ -296,7 +296,7 @@ int build_topology(Model& m, Error& err) {
   for (int64_t e = 0; e < ne; ++e) {
     const bool free_dof = !m.dirichlet[e] && !m.tree[e];
     if (free_dof) ++m.n_g;
-    if (free_dof && m.weight[e] == 2) {
+    if (free_dof && m.weight[e] == 2 && m.primal_enabled) {
       m.primal[e] = 1;
       gp[e] = int32_t(m.primal_edges.size());
       m.primal_edges.push_back(e);
@@ -314,7 +314,9 @@ int build_topology(Model& m, Error& err) {
         s.p_global.push_back(gp[e]);
       } else {
         s.r_edges.push_back(e);
-        s.is_I.push_back(m.nsubs[e] >= 2 ? 1 : 0);
+        // without primal DOFs an edge of three or more subdomains gets one
+        // multiplier between its first two; the others keep it interior
+        s.is_I.push_back(m.nsubs[e] >= 2 && t < 2 ? 1 : 0);
         s.owner.push_back(t == 0 ? 1 : 0);
       }
     }
@@ -329,7 +331,7 @@ int build_topology(Model& m, Error& err) {
   m.mult.clear();
   for (int64_t e = 0; e < ne; ++e) {
     if (m.dirichlet[e] || m.tree[e] || m.primal[e] || m.nsubs[e] < 2) continue;
-    if (m.nsubs[e] != 2) {
+    if (m.nsubs[e] != 2 && m.primal_enabled) {
       err = {IETI_ERR_TREE, "a dual DOF is shared by more than two subdomains"};
       return err.code;
     }

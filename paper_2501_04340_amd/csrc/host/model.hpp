@@ -86,6 +86,9 @@ struct Model {
   std::vector<double> d_vals;
   Mesh mesh;
   int n_sub = 0;
+  // Section 3's primal DOFs (cotree edges of weight 2); false: none, the local
+  // problems the paper shows to be singular (only for checking that)
+  bool primal_enabled = true;
   // per edge
   std::vector<uint8_t> dirichlet, weight, tree, primal;
   std::vector<int32_t> subs;     // up to 4 subdomain ids per edge (-1 padded), sorted

@@ -144,6 +144,99 @@ void scalar_factor_work(const Subdomain& s, const SubPlan& sp, double& rr, doubl
 
 }  // namespace
 
+// Deferred updates: the contribution L_ij L_lj^T of column j to the target
+// tile (i, l) may be applied at any level from level(j) up to the last level
+// before the target is read (level(l) - 1 for a column of r, the level
+// before the S copy for r_V contributions to the r_I block, the subdomain's
+// last level for the trailing p / E_I columns).  Contributions are held back
+// until pp.defer of them are pending (pp.defer_tail inside the subdomain's
+// dense r_I tail, where one column per level leaves few targets and a task's
+// pairs run in series) or the deadline is reached, so that a target tile is
+// read and written once per batch of contributions instead of once per
+// contributing level.  The decision depends on the subdomain and the
+// parameters alone, so a subdomain gets the same tasks in a batch as on its
+// own.  Only these lists depend on the parameters.
+int build_update_tasks(Plan& plan, const PlanParams& pp, Error& err) {
+  const int S = int(plan.sub.size());
+  const int64_t n_levels = plan.n_steps;
+  plan.upd_task.clear();
+  plan.upd_pair.clear();
+  plan.upd_ptr.assign(1, 0);
+  struct Pending {
+    std::vector<int64_t> cols;  // contributing columns in order of arrival
+    int64_t deadline = 0;
+  };
+  struct LevelUpdates {
+    std::vector<int64_t> upd, pair;
+  };
+  std::vector<std::vector<LevelUpdates>> lt(S);
+  std::vector<int> left_over(S, 0);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < S; ++k) {
+    const SubPlan& sp = plan.sub[k];
+    const int64_t nt = sp.nt;
+    const auto& lev = plan.col_level[k];
+    auto off = [&](int64_t i, int64_t l) { return sp.tile_off[i * nt + l]; };
+    std::vector<std::vector<int64_t>> cols(size_t(sp.nlev));
+    for (int64_t j = 0; j < sp.ntr; ++j) cols[size_t(lev[j])].push_back(j);
+    std::map<int64_t, Pending> P;  // keyed by target i * nt + l
+    lt[k].resize(size_t(sp.nlev));
+    for (int64_t lv = 0; lv < sp.nlev; ++lv) {
+      LevelUpdates& out = lt[k][size_t(lv)];
+      for (int64_t j : cols[size_t(lv)]) {
+        std::vector<int64_t> rows;
+        for (int64_t i = j + 1; i < nt; ++i)
+          if (off(i, j) >= 0) rows.push_back(i);
+        for (size_t x = 0; x < rows.size(); ++x)
+          for (size_t y = 0; y <= x; ++y) {
+            const int64_t i = rows[x], l = rows[y];
+            int64_t dl = l < sp.ntr ? lev[l] - 1 : sp.nlev - 1;
+            if (j < sp.ntV && l >= sp.ntV && l < sp.ntr) dl = std::min<int64_t>(dl, sp.levS - 1);
+            auto it = P.find(i * nt + l);
+            if (it == P.end()) {
+              it = P.emplace(i * nt + l, Pending{}).first;
+              it->second.deadline = dl;
+            }
+            it->second.cols.push_back(j);
+            it->second.deadline = std::min(it->second.deadline, dl);
+          }
+      }
+      for (auto it = P.begin(); it != P.end();) {
+        const Pending& q = it->second;
+        if (int64_t(q.cols.size()) < (lv >= sp.levS ? pp.defer_tail : pp.defer) && q.deadline > lv) {
+          ++it;
+          continue;
+        }
+        const int64_t i = it->first / nt, l = it->first % nt;
+        const int64_t p0 = int64_t(out.pair.size() / 2);  // local; made global when concatenated
+        for (int64_t j : q.cols) out.pair.insert(out.pair.end(), {off(i, j), off(l, j)});
+        out.upd.insert(out.upd.end(), {off(i, l), p0, int64_t(q.cols.size())});
+        it = P.erase(it);
+      }
+    }
+    left_over[k] = P.empty() ? 0 : 1;
+  }
+  for (int k = 0; k < S; ++k)
+    if (left_over[k]) {
+      err = Error{IETI_ERR_STATE, "plan: deferred tile updates left at the end of the schedule"};
+      return err.code;
+    }
+  for (int64_t lv = 0; lv < n_levels; ++lv) {
+    for (int k = 0; k < S; ++k) {
+      if (lv >= int64_t(lt[k].size())) continue;
+      const LevelUpdates& t = lt[k][size_t(lv)];
+      const int64_t base = int64_t(plan.upd_pair.size() / 2);
+      plan.upd_pair.insert(plan.upd_pair.end(), t.pair.begin(), t.pair.end());
+      for (size_t q = 0; q < t.upd.size(); q += 3)
+        plan.upd_task.insert(plan.upd_task.end(), {t.upd[q], t.upd[q + 1] + base, t.upd[q + 2]});
+    }
+    plan.upd_ptr.push_back(int64_t(plan.upd_task.size() / 3));
+  }
+  plan.n_update_tasks = int64_t(plan.upd_pair.size() / 2);
+  plan.params = pp;
+  return IETI_OK;
+}
+
 int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, const PlanParams& pp) {
   plan = Plan();
   plan.T = T;
@@ -152,6 +245,9 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, cons
   // ---------------------------------------------------------------- per subdomain
   std::vector<std::vector<std::vector<uint64_t>>> present(S);  // column bitsets
   int64_t pool = 0, S_elems = 0, I_total = 0, P_total = 0, r_total = 0;
+  // ordering and tile structure are independent per subdomain (host threads);
+  // offsets are assigned afterwards in subdomain order
+#pragma omp parallel for schedule(dynamic, 1)
   for (int k = 0; k < S; ++k) {
     const Subdomain& s = m.sd[k];
     SubPlan& sp = plan.sub[k];
@@ -243,6 +339,12 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, cons
       for (size_t x = 0; x < rows.size(); ++x)
         for (size_t y = 0; y <= x; ++y) mark(rows[x], rows[y]);
     }
+  }
+  for (int k = 0; k < S; ++k) {
+    SubPlan& sp = plan.sub[k];
+    const int64_t nt = sp.nt;
+    const auto& col = present[k];
+    auto has = [&](int64_t i, int64_t j) { return (col[j][i >> 6] >> (i & 63)) & 1; };
     // ---- pool offsets
     sp.tile_off.assign(nt * nt, -1);
     for (int64_t j = 0; j < nt; ++j)
@@ -266,25 +368,34 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, cons
   }
   plan.pool_elems = pool;
   plan.S_elems = S_elems;
-  for (int k = 0; k < S; ++k) {
-    double rr = 0.0, aug = 0.0;
-    scalar_factor_work(m.sd[k], plan.sub[k], rr, aug);
-    plan.flops_scalar_rr += rr;
-    plan.flops_scalar_aug += aug;
+  {
+    std::vector<double> rr(S, 0.0), aug(S, 0.0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < S; ++k) scalar_factor_work(m.sd[k], plan.sub[k], rr[k], aug[k]);
+    for (int k = 0; k < S; ++k) {
+      plan.flops_scalar_rr += rr[k];
+      plan.flops_scalar_aug += aug[k];
+    }
   }
   plan.I_total = I_total;
   plan.P_total = P_total;
   plan.r_total = r_total;
   // ---------------------------------------------------------------- scatter list
-  for (int64_t k = 0, voff = 0; k < S; ++k) {
+  {
+  std::vector<int64_t> voffs(S + 1, 0);
+  for (int k = 0; k < S; ++k) voffs[k + 1] = voffs[k] + m.sd[k].indptr[m.sd[k].n_loc];
+  std::vector<std::vector<int64_t>> sdst(S), ssrc(S);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < S; ++k) {
     const Subdomain& s = m.sd[k];
     const SubPlan& sp = plan.sub[k];
     const int64_t nt = sp.nt;
+    const int64_t voff = voffs[k];
     auto put = [&](int64_t pr, int64_t pc, int64_t src) {
       const int64_t ti = pr / T, tj = pc / T;
       const int64_t off = sp.tile_off[ti * nt + tj];
-      plan.scatter_dst.push_back(off + (pc % T) * T + (pr % T));
-      plan.scatter_src.push_back(src);
+      sdst[k].push_back(off + (pc % T) * T + (pr % T));
+      ssrc[k].push_back(src);
     };
     for (int64_t r = 0; r < s.n_loc; ++r) {
       const int64_t pr = sp.pos_of_local[r];
@@ -297,29 +408,50 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, cons
     for (int64_t t = sp.nVp + sp.nI; t < sp.nVp + sp.nIp; ++t) put(t, t, -2 - k);
     const int64_t a0 = sp.nVp + sp.nIp + sp.nPp;
     for (int64_t t = 0; t < sp.nI; ++t) put(a0 + t, sp.nVp + t, -1);
-    voff += s.indptr[s.n_loc];
-  }
-  // Destination order, so that consecutive threads of the scatter write
-  // consecutive pool entries (CSR order writes one entry per 512-byte tile
-  // column): two stable counting passes, by offset inside the tile, then by
-  // tile.  Destinations are distinct, so the order changes no value.
-  {
-    const size_t n = plan.scatter_dst.size();
-    const int64_t TT = int64_t(T) * T, ntile = (pool + TT - 1) / TT;
-    std::vector<int64_t> d2(n), s2(n);
-    auto pass = [n](const std::vector<int64_t>& dk, const std::vector<int64_t>& sk, std::vector<int64_t>& dd,
-                    std::vector<int64_t>& sd, int64_t nb, auto key) {
-      std::vector<int64_t> cnt(size_t(nb) + 1, 0);
-      for (size_t i = 0; i < n; ++i) ++cnt[size_t(key(dk[i])) + 1];
-      for (int64_t b = 0; b < nb; ++b) cnt[size_t(b) + 1] += cnt[size_t(b)];
-      for (size_t i = 0; i < n; ++i) {
-        const int64_t q = cnt[size_t(key(dk[i]))]++;
-        dd[size_t(q)] = dk[i];
-        sd[size_t(q)] = sk[i];
+    // Destination order, so that consecutive threads of the scatter write
+    // consecutive pool entries (CSR order writes one entry per 512-byte tile
+    // column): two stable counting passes, by offset inside the tile, then by
+    // tile.  A subdomain's tiles occupy a range of the pool of their own, so
+    // sorting each subdomain's entries sorts the whole list; destinations are
+    // distinct, so the order changes no value.
+    auto& dk = sdst[k];
+    auto& sk = ssrc[k];
+    const size_t n = dk.size();
+    if (n > 0) {
+      const int64_t TT = int64_t(T) * T;
+      int64_t t0 = dk[0] / TT, t1 = t0;
+      for (int64_t d : dk) {
+        t0 = std::min(t0, d / TT);
+        t1 = std::max(t1, d / TT);
       }
-    };
-    pass(plan.scatter_dst, plan.scatter_src, d2, s2, TT, [TT](int64_t d) { return d % TT; });
-    pass(d2, s2, plan.scatter_dst, plan.scatter_src, ntile, [TT](int64_t d) { return d / TT; });
+      std::vector<int64_t> d2(n), s2(n);
+      auto pass = [n](const std::vector<int64_t>& da, const std::vector<int64_t>& sa, std::vector<int64_t>& dd,
+                      std::vector<int64_t>& sd, int64_t nb, auto key) {
+        std::vector<int64_t> cnt(size_t(nb) + 1, 0);
+        for (size_t i = 0; i < n; ++i) ++cnt[size_t(key(da[i])) + 1];
+        for (int64_t b = 0; b < nb; ++b) cnt[size_t(b) + 1] += cnt[size_t(b)];
+        for (size_t i = 0; i < n; ++i) {
+          const int64_t q = cnt[size_t(key(da[i]))]++;
+          dd[size_t(q)] = da[i];
+          sd[size_t(q)] = sa[i];
+        }
+      };
+      pass(dk, sk, d2, s2, TT, [TT](int64_t d) { return d % TT; });
+      pass(d2, s2, dk, sk, t1 - t0 + 1, [TT, t0](int64_t d) { return d / TT - t0; });
+    }
+  }
+  {
+    size_t total = 0;
+    for (int k = 0; k < S; ++k) total += sdst[k].size();
+    plan.scatter_dst.reserve(total);
+    plan.scatter_src.reserve(total);
+  }
+  for (int k = 0; k < S; ++k) {
+    plan.scatter_dst.insert(plan.scatter_dst.end(), sdst[k].begin(), sdst[k].end());
+    plan.scatter_src.insert(plan.scatter_src.end(), ssrc[k].begin(), ssrc[k].end());
+    std::vector<int64_t>().swap(sdst[k]);
+    std::vector<int64_t>().swap(ssrc[k]);
+  }
   }
   // ---------------------------------------------------------------- level schedule
   // Column j of the tile factor depends on every column k < j with a tile
@@ -330,6 +462,7 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, cons
   std::vector<std::vector<int32_t>> lev(S);
   std::vector<std::vector<int64_t>> inv_off(S);
   int64_t n_levels = 0, inv_elems = 0;
+#pragma omp parallel for schedule(dynamic, 1)
   for (int k = 0; k < S; ++k) {
     SubPlan& sp = plan.sub[k];
     const int64_t nt = sp.nt;
@@ -344,6 +477,9 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, cons
     for (int64_t j = sp.ntV; j < sp.ntr; ++j) L[j] = maxV + 1 + int32_t(j - sp.ntV);
     sp.levS = maxV + 1;
     sp.nlev = sp.ntr > 0 ? (sp.ntr > sp.ntV ? L[sp.ntr - 1] + 1 : maxV + 1) : 0;
+  }
+  for (int k = 0; k < S; ++k) {
+    const SubPlan& sp = plan.sub[k];
     n_levels = std::max<int64_t>(n_levels, sp.nlev);
     inv_off[k].assign(sp.ntr, 0);
     for (int64_t j = 0; j < sp.ntr; ++j) {
@@ -361,91 +497,65 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, cons
   }
   plan.potrf_ptr.assign(1, 0);
   plan.trsm_ptr.assign(1, 0);
-  plan.upd_ptr.assign(1, 0);
   plan.copy_ptr.assign(1, 0);
   const double T3 = double(T) * T * T;
-  // Deferred updates: the contribution L_ij L_lj^T of column j to the target
-  // tile (i, l) may be applied at any level from level(j) up to the last level
-  // before the target is read (level(l) - 1 for a column of r, the level
-  // before the S copy for r_V contributions to the r_I block, the
-  // subdomain's last level for the trailing p / E_I columns).  Contributions
-  // are held back until pp.defer of them are pending (pp.defer_tail inside
-  // the subdomain's dense r_I tail, where one column per level leaves few
-  // targets and a task's pairs run in series) or the deadline is reached, so
-  // that a target tile is read and written once per batch of contributions
-  // instead of once per contributing level.  The decision depends on the
-  // subdomain and the parameters alone, so a subdomain gets the same tasks in
-  // a batch as on its own.
-  struct Pending {
-    std::vector<int64_t> cols;  // contributing columns in order of arrival
-    int64_t deadline = 0;
+  // Each subdomain's task lists are built on its own (host threads), level
+  // by level, then concatenated level by level in subdomain order.
+  struct LevelTasks {
+    std::vector<int64_t> copy, potrf, trsm;
   };
-  std::vector<std::map<int64_t, Pending>> pend(S);  // per subdomain, keyed by target i * nt + l
-  for (int64_t lv = 0; lv < n_levels; ++lv) {
-    for (int k = 0; k < S; ++k) {
-      const SubPlan& sp = plan.sub[k];
-      const int64_t nt = sp.nt;
-      auto off = [&](int64_t i, int64_t l) { return sp.tile_off[i * nt + l]; };
+  std::vector<std::vector<LevelTasks>> lt(S);
+  std::vector<double> sub_flops(S, 0.0);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < S; ++k) {
+    const SubPlan& sp = plan.sub[k];
+    const int64_t nt = sp.nt;
+    auto off = [&](int64_t i, int64_t l) { return sp.tile_off[i * nt + l]; };
+    lt[k].resize(size_t(sp.nlev));
+    double fl = 0.0;
+    for (int64_t lv = 0; lv < sp.nlev; ++lv) {
+      LevelTasks& out = lt[k][size_t(lv)];
       if (lv == sp.levS && sp.nIp > 0) {
         for (int64_t i = sp.ntV; i < sp.ntr; ++i)
           for (int64_t l = sp.ntV; l <= i; ++l) {
             const int64_t o = off(i, l);
             if (o < 0) continue;
             const int64_t r0 = (i - sp.ntV) * T, c0 = (l - sp.ntV) * T;
-            plan.copy_task.insert(plan.copy_task.end(),
-                                  {o, sp.S_off + r0 * sp.nIp + c0, sp.S_off + c0 * sp.nIp + r0, sp.nIp, i == l ? 1 : 0});
+            out.copy.insert(out.copy.end(),
+                            {o, sp.S_off + r0 * sp.nIp + c0, sp.S_off + c0 * sp.nIp + r0, sp.nIp, i == l ? 1 : 0});
           }
       }
-      auto& P = pend[k];
       for (int64_t j : cols[k][lv]) {
-        plan.potrf_task.insert(plan.potrf_task.end(), {off(j, j), int64_t(k), inv_off[k][j]});
-        plan.flops += T3 / 3.0;
-        std::vector<int64_t> rows;
+        out.potrf.insert(out.potrf.end(), {off(j, j), int64_t(k), inv_off[k][j]});
+        fl += T3 / 3.0;
+        int64_t nrow = 0;
         for (int64_t i = j + 1; i < nt; ++i)
-          if (off(i, j) >= 0) rows.push_back(i);
-        for (int64_t i : rows) {
-          plan.trsm_task.insert(plan.trsm_task.end(), {off(i, j), inv_off[k][j]});
-          plan.flops += T3;
-        }
-        for (size_t x = 0; x < rows.size(); ++x)
-          for (size_t y = 0; y <= x; ++y) {
-            const int64_t i = rows[x], l = rows[y];
-            int64_t dl = l < sp.ntr ? lev[k][l] - 1 : sp.nlev - 1;
-            if (j < sp.ntV && l >= sp.ntV && l < sp.ntr) dl = std::min<int64_t>(dl, sp.levS - 1);
-            auto it = P.find(i * nt + l);
-            if (it == P.end()) {
-              it = P.emplace(i * nt + l, Pending{}).first;
-              it->second.deadline = dl;
-            }
-            it->second.cols.push_back(j);
-            it->second.deadline = std::min(it->second.deadline, dl);
-            plan.flops += 2.0 * T3;
+          if (off(i, j) >= 0) {
+            out.trsm.insert(out.trsm.end(), {off(i, j), inv_off[k][j]});
+            fl += T3;
+            ++nrow;
           }
+        fl += 2.0 * T3 * double(nrow) * double(nrow + 1) / 2.0;  // one product per target (i, l), l <= i
       }
-      for (auto it = P.begin(); it != P.end();) {
-        const Pending& q = it->second;
-        if (int64_t(q.cols.size()) < (lv >= sp.levS ? pp.defer_tail : pp.defer) && q.deadline > lv) {
-          ++it;
-          continue;
-        }
-        const int64_t i = it->first / nt, l = it->first % nt;
-        const int64_t p0 = int64_t(plan.upd_pair.size() / 2);
-        for (int64_t j : q.cols) plan.upd_pair.insert(plan.upd_pair.end(), {off(i, j), off(l, j)});
-        plan.upd_task.insert(plan.upd_task.end(), {off(i, l), p0, int64_t(q.cols.size())});
-        it = P.erase(it);
-      }
+    }
+    sub_flops[k] = fl;
+  }
+  for (int k = 0; k < S; ++k) plan.flops += sub_flops[k];
+  for (int64_t lv = 0; lv < n_levels; ++lv) {
+    for (int k = 0; k < S; ++k) {
+      if (lv >= int64_t(lt[k].size())) continue;
+      const LevelTasks& t = lt[k][size_t(lv)];
+      plan.copy_task.insert(plan.copy_task.end(), t.copy.begin(), t.copy.end());
+      plan.potrf_task.insert(plan.potrf_task.end(), t.potrf.begin(), t.potrf.end());
+      plan.trsm_task.insert(plan.trsm_task.end(), t.trsm.begin(), t.trsm.end());
     }
     plan.potrf_ptr.push_back(int64_t(plan.potrf_task.size() / 3));
     plan.trsm_ptr.push_back(int64_t(plan.trsm_task.size() / 2));
-    plan.upd_ptr.push_back(int64_t(plan.upd_task.size() / 3));
     plan.copy_ptr.push_back(int64_t(plan.copy_task.size() / 5));
   }
-  for (int k = 0; k < S; ++k)
-    if (!pend[k].empty()) {
-      err = Error{IETI_ERR_STATE, "plan: deferred tile updates left at the end of the schedule"};
-      return err.code;
-    }
-  plan.n_update_tasks = int64_t(plan.upd_pair.size() / 2);
+  std::vector<std::vector<LevelTasks>>().swap(lt);
+  plan.col_level = lev;
+  if (int rc = build_update_tasks(plan, pp, err)) return rc;
   // ---------------------------------------------------------------- extraction lists
   for (int k = 0; k < S; ++k) {
     const SubPlan& sp = plan.sub[k];
@@ -497,41 +607,56 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, cons
       q = e;
     }
   };
-  for (int64_t lv = 0; lv < n_levels; ++lv) {
-    for (int k = 0; k < S; ++k) {
-      const SubPlan& sp = plan.sub[k];
-      const int64_t nt = sp.nt;
+  // per subdomain and level (host threads), concatenated level by level in subdomain order
+  struct SweepTasks {
+    std::vector<int64_t> diag, task, pair;
+  };
+  std::vector<std::vector<SweepTasks>> fw(S), bw(S);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < S; ++k) {
+    const SubPlan& sp = plan.sub[k];
+    const int64_t nt = sp.nt;
+    fw[k].resize(size_t(sp.nlev));
+    bw[k].resize(size_t(sp.nlev));
+    for (int64_t lv = 0; lv < sp.nlev; ++lv) {
       std::vector<std::pair<int64_t, std::pair<int64_t, int64_t>>> full;  // (vec_i, (tile, vec_j))
+      std::vector<std::pair<int64_t, std::pair<int64_t, int64_t>>> c;     // (vec_k, (tile (j,k), vec_j))
       for (int64_t j : cols[k][lv]) {
-        plan.fdiag_task.insert(plan.fdiag_task.end(), {inv_off[k][j], sp.r_off + j * T});
+        fw[k][size_t(lv)].diag.insert(fw[k][size_t(lv)].diag.end(), {inv_off[k][j], sp.r_off + j * T});
+        bw[k][size_t(lv)].diag.insert(bw[k][size_t(lv)].diag.end(), {inv_off[k][j], sp.r_off + j * T});
         for (int64_t i = j + 1; i < nt; ++i) {
           const int64_t o = sp.tile_off[i * nt + j];
           if (o < 0) continue;
           full.push_back({sp.r_off + i * T, {o, sp.r_off + j * T}});
         }
-      }
-      emit_targets(full, plan.ffull_task, plan.ffull_pair);
-    }
-    plan.fdiag_ptr.push_back(int64_t(plan.fdiag_task.size() / 2));
-    plan.ffull_ptr.push_back(int64_t(plan.ffull_task.size() / 3));
-  }
-  plan.bdiag_ptr.assign(1, 0);
-  plan.bupd_ptr.assign(1, 0);
-  for (int64_t lv = n_levels - 1; lv >= 0; --lv) {
-    for (int k = 0; k < S; ++k) {
-      const SubPlan& sp = plan.sub[k];
-      const int64_t nt = sp.nt;
-      std::vector<std::pair<int64_t, std::pair<int64_t, int64_t>>> c;  // (vec_k, (tile (j,k), vec_j))
-      for (int64_t j : cols[k][lv]) {
-        plan.bdiag_task.insert(plan.bdiag_task.end(), {inv_off[k][j], sp.r_off + j * T});
         for (int64_t i = 0; i < j; ++i) {
           const int64_t o = sp.tile_off[j * nt + i];
           if (o < 0) continue;
           c.push_back({sp.r_off + i * T, {o, sp.r_off + j * T}});
         }
       }
-      emit_targets(c, plan.bupd_task, plan.bupd_pair);
+      emit_targets(full, fw[k][size_t(lv)].task, fw[k][size_t(lv)].pair);
+      emit_targets(c, bw[k][size_t(lv)].task, bw[k][size_t(lv)].pair);
     }
+  }
+  auto append = [](const SweepTasks& t, std::vector<int64_t>& diag, std::vector<int64_t>& task,
+                   std::vector<int64_t>& pair) {
+    diag.insert(diag.end(), t.diag.begin(), t.diag.end());
+    const int64_t base = int64_t(pair.size() / 2);
+    pair.insert(pair.end(), t.pair.begin(), t.pair.end());
+    for (size_t q = 0; q < t.task.size(); q += 3) task.insert(task.end(), {t.task[q], t.task[q + 1] + base, t.task[q + 2]});
+  };
+  for (int64_t lv = 0; lv < n_levels; ++lv) {
+    for (int k = 0; k < S; ++k)
+      if (lv < int64_t(fw[k].size())) append(fw[k][size_t(lv)], plan.fdiag_task, plan.ffull_task, plan.ffull_pair);
+    plan.fdiag_ptr.push_back(int64_t(plan.fdiag_task.size() / 2));
+    plan.ffull_ptr.push_back(int64_t(plan.ffull_task.size() / 3));
+  }
+  plan.bdiag_ptr.assign(1, 0);
+  plan.bupd_ptr.assign(1, 0);
+  for (int64_t lv = n_levels - 1; lv >= 0; --lv) {
+    for (int k = 0; k < S; ++k)
+      if (lv < int64_t(bw[k].size())) append(bw[k][size_t(lv)], plan.bdiag_task, plan.bupd_task, plan.bupd_pair);
     plan.bdiag_ptr.push_back(int64_t(plan.bdiag_task.size() / 2));
     plan.bupd_ptr.push_back(int64_t(plan.bupd_task.size() / 3));
   }

@@ -40,6 +40,13 @@ struct SubPlan {
   int32_t nlev = 0;                    // number of levels of this subdomain
 };
 
+// Deferred tile updates: a target's pending contributions are issued once
+// `defer` of them are pending (`defer_tail` inside a subdomain's dense r_I
+// tail) or at the target's deadline.
+struct PlanParams {
+  int defer = 8;
+  int defer_tail = 4;
+};
 struct Plan {
   int T = 64;
   int64_t pool_elems = 0;
@@ -101,6 +108,10 @@ struct Plan {
   // which keeps them above the threshold at any scale)
   std::vector<double> piv_tol;
   static constexpr double PIVOT_REL = 1e-13;
+  // per subdomain: level of each r column tile (the schedule's step), and the
+  // parameters the update task lists were built with
+  std::vector<std::vector<int32_t>> col_level;
+  PlanParams params;
   double flops = 0.0;    // algorithmic flops of the tile factorisation
   // scalar-level work in the same elimination order, sum_j c_j^2 (no tiles,
   // no padding): of K_rr alone, and with the augmented trailing rows
@@ -143,15 +154,10 @@ struct CoarsePlan {
 };
 void build_coarse_plan(const std::vector<CoarseDims>& dims, int T, CoarsePlan& cp);
 
-// Deferred tile updates: a target's pending contributions are issued once
-// `defer` of them are pending (`defer_tail` inside a subdomain's dense r_I
-// tail) or at the target's deadline.
-struct PlanParams {
-  int defer = 8;
-  int defer_tail = 4;
-};
 // ordering: 0 = nested dissection, 1 = natural
 int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, const PlanParams& pp = PlanParams());
+// rebuild only the deferred-update task lists of a plan for new parameters
+int build_update_tasks(Plan& plan, const PlanParams& pp, Error& err);
 // recompute the value arrays (scatter_val, krp_val, b_aug0) from the model's
 // current matrix values and loads; the structure is unchanged
 void refill_values(const Model& m, Plan& plan);

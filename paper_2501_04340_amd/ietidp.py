@@ -119,6 +119,10 @@ class NNTrainOpts(C.Structure):
                 ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64)]
 
 
+class AssembleOpts(C.Structure):
+    _fields_ = [("version", C.c_int32), ("primal", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
 class WarmLayout(C.Structure):
     _fields_ = [
         ("n_facets", C.c_int32), ("n_feat", C.c_int32), ("n_comb", C.c_int32), ("n_out", C.c_int32),
@@ -138,7 +142,7 @@ EXPORTS = [
     "ieti_get_problem_stats", "ieti_nn_init_params", "ieti_nn_set_normalisation", "ieti_nn_fit_normalisation",
     "ieti_nn_get_normalisation", "ieti_nn_dataset_append", "ieti_nn_train_file", "ieti_warm_rows",
     "ieti_warm_append", "ieti_warm_load", "ieti_warm_predict", "ieti_get_condition", "ieti_apply_F_noalloc",
-    "ieti_set_factor_params", "ieti_get_factor_tuning",
+    "ieti_set_factor_params", "ieti_get_factor_tuning", "ieti_assemble_ex",
 ]
 
 
@@ -179,6 +183,7 @@ def load_library():
     lib.ieti_apply_M.argtypes = [C.c_void_p, P(C.c_double), P(C.c_double)]
     lib.ieti_apply_F_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.ieti_set_factor_params.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+    lib.ieti_assemble_ex.argtypes = [P(Problem), P(AssembleOpts), P(C.c_void_p)]
     lib.ieti_get_factor_tuning.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_double), P(C.c_int32)]
     lib.ieti_get_rhs.argtypes = [C.c_void_p, P(C.c_double)]
     lib.ieti_get_lambda.argtypes = [C.c_void_p, P(C.c_double)]
@@ -286,7 +291,9 @@ class Solver:
     """One assembled problem, or a batch of independent problems (a list),
     on the current HIP device."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, primal=True):
+        """primal=False (one problem only): no primal DOFs, the singular local
+        problems of Section 3 (``ieti_assemble_ex``), for checking that."""
         self.lib = load_library()
         probs = list(prob) if isinstance(prob, (list, tuple)) else [prob]
         self.prob = prob
@@ -295,7 +302,15 @@ class Solver:
         arr = (Problem * len(probs))(*[_problem_struct(p, keep) for p in probs])
         self._part = np.concatenate([np.asarray(p.patch_to_sub) for p in probs]).astype(np.int32)
         h = C.c_void_p()
-        _check(self.lib, self.lib.ieti_assemble_batch(arr, len(probs), C.byref(h)))
+        if primal:
+            _check(self.lib, self.lib.ieti_assemble_batch(arr, len(probs), C.byref(h)))
+        else:
+            if len(probs) != 1:
+                raise ValueError("primal=False takes one problem")
+            o = AssembleOpts()
+            o.version = ABI_VERSION
+            o.primal = 0
+            _check(self.lib, self.lib.ieti_assemble_ex(arr, C.byref(o), C.byref(h)))
         self.h = h
         s = np.zeros(8, dtype=np.int64)
         _check(self.lib, self.lib.ieti_get_sizes(self.h, _ptr(s, C.c_int64)))

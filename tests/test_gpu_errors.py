@@ -5,7 +5,10 @@ stays usable afterwards.
 * IETI_ERR_NOT_SPD: a local stiffness that is numerically singular (a patch
   with reluctivity 1e-300 next to one with 1: its pivots fall below the
   factorisation's threshold, 1e-13 of the largest diagonal entry of K_rr);
-  the message names the subdomain, and in a batch its problem.
+  the message names the subdomain, and in a batch its problem.  And the
+  case Section 3 predicts: without the primal DOFs (cotree edges of weight
+  2) the K_rr of some subdomains are singular; the subdomain named is the
+  highest one the oracle finds singular.
 * IETI_ERR_NOT_CONVERGED: maxit = 2 at rtol 1e-12; outputs and per-problem
   statistics are still filled, single and batched.
 * IETI_ERR_BREAKDOWN: initial multipliers that are not finite make the first
@@ -121,5 +124,35 @@ def test_non_finite_initial_multipliers_break_down(ietilib):
         assert e.value.code == -5 and "problem 0" in str(e.value)
         _, st = S.solve(rtol=1e-10)
         assert st["status"] == 0 and st["rel_residual"] <= 1e-10
+    finally:
+        S.close()
+
+
+def test_without_primal_dofs_local_problems_are_singular(ietilib):
+    from oracle.ietidp import LocalProblem, SubdomainNotInvertible
+    from oracle.run import OracleRun
+    from paper_2501_04340_amd import Solver
+
+    prob = configs.cube8()
+    print("[gpu-errors] NOT_SPD without primal DOFs (cube8)", flush=True)
+    O = OracleRun(prob, primal_enabled=False)
+    T = O.topo
+    singular = []
+    for k in range(T.n_sub):
+        Kk = None
+        jk = np.zeros(O.space.n_edges)
+        for q in np.flatnonzero(prob.patch_to_sub == k):
+            K = O.mats[int(q)]
+            Kk = K if Kk is None else Kk + K
+        try:
+            LocalProblem(k, Kk, jk, T.sub_r[k], T.sub_p[k], T.sub_I[k], T.gp_index, T.m_r, T.mult)
+        except SubdomainNotInvertible:
+            singular.append(k)
+    assert 0 < len(singular) < T.n_sub, singular
+    S = Solver(prob, primal=False)
+    try:
+        with pytest.raises(IetiError, match="NOT_SPD") as e:
+            S.factor()
+        assert e.value.code == -4 and f"subdomain {max(singular)}" in str(e.value), (str(e.value), singular)
     finally:
         S.close()

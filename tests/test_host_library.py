@@ -152,3 +152,29 @@ def test_schedule_parameters_are_validated(ietilib):
         assert params == (12, 6, 512) and log.shape == (0, 4)
     finally:
         S.close()
+
+
+def test_without_primal_dofs_maps_match_oracle(ietilib):
+    """ieti_assemble_ex with primal = 0 (the singular local problems of
+    Section 3): no primal DOFs, and the remaining DOFs and multiplier rows
+    bit-exact against the oracle's topology without primal DOFs (an edge of
+    three or more subdomains gets one row, between its first two)."""
+    from paper_2501_04340_amd import Solver
+
+    prob = configs.cube8()
+    S = Solver(prob, primal=False)
+    try:
+        mp = S.maps()
+        T = build_topology(Space(prob), primal_enabled=False)
+        assert S.n_gp == 0 and T.n_gp == 0
+        assert np.array_equal(mp["mult"], T.mult)
+        for k in range(T.n_sub):
+            assert np.array_equal(mp["sub_r"][k], T.sub_r[k])
+    finally:
+        S.close()
+    # with the default assembly the same problem has the paper's primal DOFs
+    S = Solver(prob)
+    try:
+        assert S.n_gp == 5
+    finally:
+        S.close()
