@@ -44,10 +44,12 @@ WORKLOADS = {
 
 
 # PMC traffic summaries (rocprofv3 FETCH_SIZE / WRITE_SIZE passes) by workload
-TRAFFIC_PROFILES = [os.path.join(ROOT, "profiles", "cube64_hbm_traffic_pmc.md"),
-                    os.path.join(ROOT, "profiles", "stream256_batch32_hbm_traffic_pmc.md")]
+TRAFFIC_PROFILES = [os.path.join(ROOT, "profiles", "stream256_batch64_hbm_traffic_pmc.md"),
+                    os.path.join(ROOT, "profiles", "cube64_hbm_traffic_pmc.md"),
+                    os.path.join(ROOT, "profiles", "cube256_hbm_traffic_pmc.md")]
 # the per-launch traffic depends on the kernels and on the factorisation's task lists
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2501_04340_amd", "csrc", "device", "kernels.hip"),
+                   os.path.join(ROOT, "paper_2501_04340_amd", "csrc", "device", "kernels.hpp"),
                    os.path.join(ROOT, "paper_2501_04340_amd", "csrc", "host", "plan.cpp")]
 
 
@@ -60,12 +62,14 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` ("k_update_multi", "k_gemv_sym<double>"
-    or "k_gemv<double>") on `workload` from the committed PMC summary, or None
-    when the summary holds no figure for that kernel on that workload, or when
-    the kernel source or the task-list builder changed since the counters were
-    taken."""
+def measured_traffic(kernel, workload, params=None):
+    """HBM bytes per launch of `kernel` ("k_update_multi", "k_gemv_sym<double>",
+    "k_gemv_sym<float>" or "k_gemv<double>") on `workload` from the committed
+    PMC summaries, or None when they hold no figure for that kernel on that
+    workload, when the kernel source or the task-list builder changed since
+    the counters were taken, or (for the tile update, whose launches are the
+    deferred-update groups) when the counters were taken with other schedule
+    parameters than `params` = (defer, defer_tail, update_wgs)."""
     import re
     try:
         sha = sources_sha256()
@@ -77,11 +81,15 @@ def measured_traffic(kernel, workload):
             text += open(f).read() + "\n"
         except OSError:
             pass
-    pat = (r"traffic_per_launch " + re.escape(kernel)
-           + r": workload=(\S+) .*total_bytes=(\d+) sources_sha256=([0-9a-f]+)")
+    pat = r"traffic_per_launch " + re.escape(kernel) + r": (.*)"
     for m in re.finditer(pat, text):
-        if m.group(1) == workload and m.group(3) == sha:
-            return float(m.group(2))
+        fields = dict(kv.split("=", 1) for kv in m.group(1).split() if "=" in kv)
+        if fields.get("workload") != workload or fields.get("sources_sha256") != sha:
+            continue
+        if kernel.startswith("k_update") and (params is None or fields.get("params")
+                                              != ",".join(str(int(x)) for x in params)):
+            continue
+        return float(fields["total_bytes"])
     return None
 
 
@@ -478,7 +486,8 @@ def stream_batches(args):
             B.set_profiling(False)
             ps = [B.problem_stats(p) for p in range(len(ids))]
             chosen = B.gemv_tuning()[0]
-            kprof = {"kt": kt, "ps": ps, "chosen": chosen, "ids": (ids[0], ids[-1]), "plan": B.plan_info()}
+            kprof = {"kt": kt, "ps": ps, "chosen": chosen, "ids": (ids[0], ids[-1]), "plan": B.plan_info(),
+                     "params": B.factor_tuning()[0]}
         B.close()
         del a_dev
         log(f"problems {ids[0]}..{ids[-1]}: alone {np.sum(lat_single[-len(ids):]) if lat_single else 0:.0f} ms, batch mixed "
@@ -487,6 +496,8 @@ def stream_batches(args):
 
     # roofline of the dominant kernel of the headline pass (largest total time)
     kt, ps = kprof["kt"], kprof["ps"]
+    # the PMC summary's figures are per launch of one batch: keyed by its problems
+    batch_key = f"stream256[{kprof['ids'][0]}..{kprof['ids'][1]}]"
     def gemv_roof(fp32):
         s_b = 4.0 if fp32 else 8.0
         nb = sum((x["f_applies"][fp32] + x["m_applies"][fp32]) * x["block_entries"] * s_b for x in ps)
@@ -496,7 +507,7 @@ def stream_batches(args):
         name = ("k_gemv_sym" if sym else "k_gemv") + ("<float>" if fp32 else "<double>")
         ach = nb / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(name, "stream256"),
+                "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(name, batch_key),
                 "avg_launch_ms": ms / max(nl, 1), "launches": nl, "total_ms": ms,
                 "alg_bytes_per_launch": nb / max(nl, 1)}
     upd_avg = kt["update_ms"] / max(kt["update_launches"], 1)
@@ -504,7 +515,7 @@ def stream_batches(args):
     upd_ach = upd_flops / (upd_avg * 1e-3) / 1e12 if upd_avg > 0 else 0.0
     roof_upd = {"kernel": "k_update_multi", "bound": "mfma", "achieved": upd_ach, "peak": FP64_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": upd_ach / FP64_MFMA_PEAK_TFLOPS,
-                "traffic": measured_traffic("k_update_multi", "stream256"), "avg_launch_ms": upd_avg,
+                "traffic": measured_traffic("k_update_multi", batch_key, kprof["params"]), "avg_launch_ms": upd_avg,
                 "launches": kt["update_launches"], "total_ms": kt["update_ms"],
                 "flops_per_launch": upd_flops, "flops_counted": "64x64x64 tile products (2 T^3 each)"}
     cands = [gemv_roof(1), gemv_roof(0), roof_upd]
@@ -701,7 +712,7 @@ def main():
     upd_flops = kt["update_tasks"] / max(kt["update_launches"], 1) * flops_per_task
     upd_ach = upd_flops / (upd_avg * 1e-3) / 1e12
     roof_upd = {"kernel": "k_update_multi", "bound": "mfma", "achieved": upd_ach, "peak": FP64_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": upd_ach / FP64_MFMA_PEAK_TFLOPS, "traffic": measured_traffic("k_update_multi", args.workload),
+                "unit": "TFLOP/s", "frac": upd_ach / FP64_MFMA_PEAK_TFLOPS, "traffic": measured_traffic("k_update_multi", args.workload, S.factor_tuning()[0]),
                 "avg_launch_ms": upd_avg, "flops_per_launch": upd_flops,
                 "launches_per_step": kt["update_launches"], "ms_per_step": kt["update_ms"]}
     roof = dict(roof_gemv if kt["gemv_ms"] >= kt["update_ms"] else roof_upd)

@@ -113,7 +113,8 @@ typedef struct {
   int32_t scaling;     /* IETI_SCALE_* of the preconditioner (0 = D_s = I as in the paper) */
   int32_t factor_tune; /* 1 = autotune the factorisation's parameters (deferral thresholds of the
                           tile updates, persistent update workgroups) on the first factorisation of
-                          the handle, kept afterwards; 0 = the handle's current parameters */
+                          the handle, kept afterwards; a candidate must be over 1% faster to replace
+                          the current choice; 0 = the handle's current parameters */
   void* hip_stream;    /* hipStream_t to run on; NULL = the library's own stream */
 } ieti_factor_opts;
 
@@ -312,7 +313,7 @@ int ieti_get_rhs(ieti_handle* h, double* b);
  * of K_rr): a target tile's deferred updates are issued once `defer` of them
  * are pending (`defer_tail` inside a subdomain's dense r_I tail) or at the
  * target's deadline; the update launches use at most `update_wgs`
- * persistent workgroups.  Defaults 8, 4, 1024.  Takes effect at the next
+ * persistent workgroups.  Defaults 8, 4, 2048.  Takes effect at the next
  * ieti_factor (a changed threshold rebuilds the plan) and turns that
  * handle's autotuning off.  A subdomain gets the same tasks, and bitwise the
  * same factor, in any batch factored with the same parameters. */

@@ -718,14 +718,19 @@ int tune_factor(ieti_handle* h, int T, int ordering, void* user_stream) {
                         {double(h->pparams.defer), double(h->pparams.defer_tail), double(h->upd_wgs), *ms_out});
     return IETI_OK;
   };
+  // a candidate replaces the current parameters only when it is faster by
+  // more than the timing noise, so that repeated tunings settle on the same
+  // choice (and so on the same task lists)
+  constexpr double margin = 0.99;
   double best_ms = 0.0, ms = 0.0;
   int rc = time_it(&best_ms);
   if (rc) return rc;
   int64_t best_w = h->upd_wgs;
-  for (int64_t w : {int64_t(512), int64_t(2048)}) {
+  for (int64_t w : {int64_t(512), int64_t(1024), int64_t(2048)}) {
+    if (w == best_w) continue;
     h->upd_wgs = w;
     if ((rc = time_it(&ms))) return rc;
-    if (ms < best_ms) {
+    if (ms < margin * best_ms) {
       best_ms = ms;
       best_w = w;
     }
@@ -739,7 +744,7 @@ int tune_factor(ieti_handle* h, int T, int ordering, void* user_stream) {
       (pass == 0 ? tryp.defer : tryp.defer_tail) = c;
       h->pparams = tryp;
       if ((rc = time_it(&ms))) return rc;
-      if (ms < best_ms) {
+      if (ms < margin * best_ms) {
         best_ms = ms;
         best_p = tryp;
       }

@@ -21,7 +21,7 @@ void potrf_tiles(double* pool, double* inv, const int64_t* task, int64_t ntask, 
 void trsm_tiles(double* pool, const double* inv, const int64_t* task, int64_t ntask, hipStream_t s);
 // update task [off_C, first pair, pair count], pairs [off_A, off_B]: C -= sum A B^T;
 // at most max_wgs workgroups (persistent), each walking its share of the tasks
-constexpr int64_t UPDATE_WGS = 1024;
+constexpr int64_t UPDATE_WGS = 2048;
 void update_tiles(double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, hipStream_t s,
                   int64_t max_wgs = UPDATE_WGS);
 void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s);

@@ -36,9 +36,13 @@ def test_autotuned_factorisation_matches_oracle(ietilib):
         # base point, two workgroup counts, three thresholds before and three inside the tail
         assert log.shape == (9, 4), log
         assert np.all(log[:, 3] > 0)
-        # every candidate is recorded once; the kept parameters are the fastest
-        assert len({tuple(r[:3]) for r in log.tolist()}) == 9
-        assert tuple(params) == tuple(int(v) for v in log[int(np.argmin(log[:, 3])), :3])
+        # every candidate is recorded once; the kept parameters are among them, and
+        # no candidate beat them by more than the 1% replacement margin
+        rows = [tuple(int(v) for v in r[:3]) for r in log.tolist()]
+        assert len(set(rows)) == 9
+        assert tuple(params) in rows
+        t_kept = log[rows.index(tuple(params)), 3]
+        assert np.min(log[:, 3]) >= 0.99 * t_kept, (params, log)
         a1, st = S.solve(rtol=1e-12)
         S.factor(tune=True)  # kept: no second tuning, bitwise the same factor
         _, log2 = S.factor_tuning()

@@ -47,17 +47,25 @@ def test_traffic_read_only_for_matching_sources(tmp_path, monkeypatch):
     prof = tmp_path / "traffic.md"
     prof.write_text(
         "header\n"
-        f"traffic_per_launch k_update_multi: workload=cube64 fetch_bytes=10 write_bytes=5 total_bytes=15 "
-        f"sources_sha256={sha}\n"
-        f"traffic_per_launch k_update_multi: workload=cube256 fetch_bytes=20 write_bytes=5 total_bytes=25 "
-        f"sources_sha256={sha}\n"
+        f"traffic_per_launch k_update_multi: workload=cube64 params=8,4,2048 fetch_bytes=10 write_bytes=5 "
+        f"total_bytes=15 sources_sha256={sha}\n"
+        f"traffic_per_launch k_update_multi: workload=cube256 params=8,4,2048 fetch_bytes=20 write_bytes=5 "
+        f"total_bytes=25 sources_sha256={sha}\n"
+        f"traffic_per_launch k_update_multi: workload=stream256[0..63] params=8,8,2048 fetch_bytes=30 "
+        f"write_bytes=5 total_bytes=35 sources_sha256={sha}\n"
         f"traffic_per_launch k_gemv_sym<double>: workload=cube64 fetch_bytes=7 write_bytes=1 total_bytes=8 "
         f"sources_sha256={sha}\n"
         "traffic_per_launch k_gemv<double>: workload=cube64 fetch_bytes=7 write_bytes=1 total_bytes=9 "
         "sources_sha256=" + "0" * 64 + "\n")
     monkeypatch.setattr(bench, "TRAFFIC_PROFILES", [str(prof)])
-    assert bench.measured_traffic("k_update_multi", "cube64") == 15.0
-    assert bench.measured_traffic("k_update_multi", "cube256") == 25.0
+    assert bench.measured_traffic("k_update_multi", "cube64", (8, 4, 2048)) == 15.0
+    assert bench.measured_traffic("k_update_multi", "cube256", (8, 4, 2048)) == 25.0
+    assert bench.measured_traffic("k_update_multi", "stream256[0..63]", (8, 8, 2048)) == 35.0
+    # the tile update's launches depend on the schedule parameters
+    assert bench.measured_traffic("k_update_multi", "cube64", (8, 4, 1024)) is None
+    assert bench.measured_traffic("k_update_multi", "cube64") is None
+    assert bench.measured_traffic("k_update_multi", "stream256[64..127]", (8, 8, 2048)) is None
+    # the GEMV's do not
     assert bench.measured_traffic("k_gemv_sym<double>", "cube64") == 8.0
     # a workload the counters were not taken on
     assert bench.measured_traffic("k_gemv_sym<double>", "cube256") is None
@@ -66,7 +74,7 @@ def test_traffic_read_only_for_matching_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic("k_trsm_inv", "cube64") is None
     # any change to the sources invalidates every figure
     (tmp_path / "src0.txt").write_bytes(b"a2")
-    assert bench.measured_traffic("k_update_multi", "cube64") is None
+    assert bench.measured_traffic("k_update_multi", "cube64", (8, 4, 2048)) is None
 
 
 def test_traffic_missing_profile(tmp_path, monkeypatch):
