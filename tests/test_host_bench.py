@@ -83,15 +83,24 @@ def test_traffic_missing_profile(tmp_path, monkeypatch):
 
 
 def test_committed_summary_parses():
-    """The committed summary carries a cube64 figure for both kernels
-    bench.py reports, each with a 64-digit source hash."""
+    """Each committed summary carries figures for the kernels bench.py reports
+    on its workload (the tile update with its schedule parameters), each with
+    a 64-digit source hash."""
     import re
-    text = open(bench.TRAFFIC_PROFILES[0]).read()
-    for k in ("k_update_multi", "k_gemv_sym<double>"):
-        m = re.search(r"traffic_per_launch " + re.escape(k) + r": workload=cube64 .*total_bytes=(\d+) sources_sha256=([0-9a-f]{64})",
-                      text)
-        assert m, k
-        assert int(m.group(1)) > 0
+    want = {"stream256_batch64": ("stream256[0..63]", ("k_update_multi", "k_gemv_sym<float>")),
+            "cube64_": ("cube64", ("k_update_multi", "k_gemv_sym<double>")),
+            "cube256_": ("cube256", ("k_update_multi", "k_gemv_sym<double>"))}
+    assert len(bench.TRAFFIC_PROFILES) == len(want)
+    for f in bench.TRAFFIC_PROFILES:
+        key = next(k for k in want if os.path.basename(f).startswith(k))
+        workload, kernels = want[key]
+        text = open(f).read()
+        for k in kernels:
+            params = r"params=\d+,\d+,\d+ " if k == "k_update_multi" else ""
+            m = re.search(r"traffic_per_launch " + re.escape(k) + r": workload=" + re.escape(workload) + " "
+                          + params + r".*total_bytes=(\d+) sources_sha256=([0-9a-f]{64})", text)
+            assert m, (f, k)
+            assert int(m.group(1)) > 0
 
 
 if __name__ == "__main__":
