@@ -270,29 +270,66 @@ __global__ __launch_bounds__(256) void k_trsm_inv(double* pool, const double* in
   store_quadrant(A, acc, 0.0, 1.0);
 }
 
-// C -= sum_p A_p B_p^T over the pairs of one target tile (all contributing
-// columns of one level), accumulated in registers and written once.  Each
-// workgroup walks tasks b, b + gridDim.x, ... and their pairs as one
-// sequence, software-pipelined: the next pair's two tiles are loaded into
-// registers while the matrix cores consume the current pair from LDS, so
-// the global latency hides behind the MFMAs (tasks mostly have one or two
-// pairs, so the pipeline runs across tasks).
-__device__ __attribute__((always_inline)) inline void load_pair(const double* A, const double* B, pd2 ra[8], pd2 rb[8]) {
-  const pd2* A2 = reinterpret_cast<const pd2*>(A);
-  const pd2* B2 = reinterpret_cast<const pd2*>(B);
+// C -= sum_p A_p B_p^T over the pairs of one target tile (all its pending
+// contributions), accumulated in registers and written once.  Each workgroup
+// walks tasks b, b + gridDim.x, ... and their pairs as one sequence of
+// stages, a stage being one half of k of one pair (columns 0..31 or 32..63 of
+// both column-major tiles: their two contiguous 16 KB halves).  The stage's
+// operands go through LDS (32 KB per workgroup, so four workgroups share a
+// CU) while the next two stages load into registers: 256 KB of operands in
+// flight per CU, twice what a one-pair-ahead pipeline with whole tiles in
+// LDS (64 KB per workgroup, two per CU) keeps, which hides more of the memory
+// latency behind the matrix cores.  Every target sums its pairs in order and
+// k ascending.
+constexpr int KHALF = T * T / 2;
+
+struct UpdCursor {
+  int64_t t, p0, np, q;
+  int h;
+};
+
+__device__ __attribute__((always_inline)) inline void upd_skip_empty(UpdCursor& c, const int64_t* task, int64_t ntask,
+                                                                     int64_t stride) {
+  while (c.t < ntask && task[3 * c.t + 2] == 0) c.t += stride;
+  if (c.t < ntask) {
+    c.p0 = task[3 * c.t + 1];
+    c.np = task[3 * c.t + 2];
+  }
+  c.q = 0;
+  c.h = 0;
+}
+
+__device__ __attribute__((always_inline)) inline void upd_advance(UpdCursor& c, const int64_t* task, int64_t ntask,
+                                                                  int64_t stride) {
+  if (++c.h < 2) return;
+  c.h = 0;
+  if (++c.q < c.np) return;
+  c.t += stride;
+  upd_skip_empty(c, task, ntask, stride);
+}
+
+__device__ __attribute__((always_inline)) inline void upd_load_half(const double* pool, const int64_t* pair,
+                                                                    const UpdCursor& c, pd2 r[8]) {
+  const int64_t* pr = pair + 2 * (c.p0 + c.q);
+  const pd2* A2 = reinterpret_cast<const pd2*>(pool + pr[0] + c.h * KHALF);
+  const pd2* B2 = reinterpret_cast<const pd2*>(pool + pr[1] + c.h * KHALF);
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    ra[s] = A2[threadIdx.x + 256 * s];
-    rb[s] = B2[threadIdx.x + 256 * s];
+  for (int s = 0; s < 4; ++s) {
+    r[s] = A2[threadIdx.x + 256 * s];
+    r[4 + s] = B2[threadIdx.x + 256 * s];
   }
 }
 
-__device__ __attribute__((always_inline)) inline void mfma_abt_lds(const double* As, const double* Bs, v4d acc[4]) {
+// acc += A B^T over one half of k of LDS-staged half tiles (the operand
+// layout of mfma_abt); unrolled by two only: at four waves per SIMD the
+// update kernel has 128 VGPRs, and a full unroll hoists every LDS operand
+// into registers and spills.
+__device__ __attribute__((always_inline)) inline void mfma_khalf_lds(const double* As, const double* Bs, v4d acc[4]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int li = lane & 15, lk = lane >> 4;
-#pragma unroll
-  for (int kk = 0; kk < T / 4; ++kk) {
+#pragma unroll 2
+  for (int kk = 0; kk < T / 8; ++kk) {
     const int k = 4 * kk + lk;
     const double a0 = As[k * T + 32 * wr + li];
     const double a1 = As[k * T + 32 * wr + 16 + li];
@@ -305,53 +342,49 @@ __device__ __attribute__((always_inline)) inline void mfma_abt_lds(const double*
   }
 }
 
-__global__ __launch_bounds__(256) void k_update_multi(double* pool, const int64_t* task, const int64_t* pair,
-                                                      int64_t ntask) {
-  __shared__ __align__(16) double As[T * T];
-  __shared__ __align__(16) double Bs[T * T];
+__global__ __launch_bounds__(256, 4) void k_update_multi(double* pool, const int64_t* task, const int64_t* pair,
+                                                        int64_t ntask) {
+  __shared__ __align__(16) double As[KHALF];
+  __shared__ __align__(16) double Bs[KHALF];
   pd2* As2 = reinterpret_cast<pd2*>(As);
   pd2* Bs2 = reinterpret_cast<pd2*>(Bs);
   const int64_t stride = gridDim.x;
-  int64_t t = blockIdx.x;
-  // first task with at least one pair
-  while (t < ntask && task[3 * t + 2] == 0) t += stride;
-  if (t >= ntask) return;
-  int64_t p0 = task[3 * t + 1], np = task[3 * t + 2], q = 0;
-  pd2 ra[8], rb[8];
-  load_pair(pool + pair[2 * p0], pool + pair[2 * p0 + 1], ra, rb);
+  UpdCursor cl;  // next stage to load
+  cl.t = blockIdx.x;
+  upd_skip_empty(cl, task, ntask, stride);
+  if (cl.t >= ntask) return;
+  UpdCursor cc = cl;  // stage whose operands the matrix cores consume next
+  pd2 r0[8], r1[8];
+  upd_load_half(pool, pair, cl, r0);
+  upd_advance(cl, task, ntask, stride);
+  if (cl.t < ntask) upd_load_half(pool, pair, cl, r1);
+  upd_advance(cl, task, ntask, stride);
   v4d acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-  while (true) {
+  // one stage: its registers to LDS, the stage two ahead into the same
+  // registers, the products, and the target's store after its last stage
+  auto stage = [&](pd2 (&r)[8]) {
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      As2[threadIdx.x + 256 * s] = ra[s];
-      Bs2[threadIdx.x + 256 * s] = rb[s];
+    for (int s = 0; s < 4; ++s) {
+      As2[threadIdx.x + 256 * s] = r[s];
+      Bs2[threadIdx.x + 256 * s] = r[4 + s];
     }
     __syncthreads();
-    // next item of this workgroup's sequence
-    int64_t tn = t, qn = q + 1, p0n = p0, npn = np;
-    if (qn == np) {
-      tn = t + stride;
-      while (tn < ntask && task[3 * tn + 2] == 0) tn += stride;
-      qn = 0;
-      if (tn < ntask) {
-        p0n = task[3 * tn + 1];
-        npn = task[3 * tn + 2];
-      }
-    }
-    const bool more = tn < ntask;
-    if (more) load_pair(pool + pair[2 * (p0n + qn)], pool + pair[2 * (p0n + qn) + 1], ra, rb);
-    mfma_abt_lds(As, Bs, acc);
-    if (q + 1 == np) {
-      store_quadrant(pool + task[3 * t], acc, 1.0, -1.0);
+    if (cl.t < ntask) upd_load_half(pool, pair, cl, r);
+    upd_advance(cl, task, ntask, stride);
+    mfma_khalf_lds(As, Bs, acc);
+    if (cc.h == 1 && cc.q + 1 == cc.np) {
+      store_quadrant(pool + task[3 * cc.t], acc, 1.0, -1.0);
 #pragma unroll
       for (int m = 0; m < 4; ++m) acc[m] = v4d{0, 0, 0, 0};
     }
-    if (!more) break;
-    t = tn;
-    q = qn;
-    p0 = p0n;
-    np = npn;
+    upd_advance(cc, task, ntask, stride);
+  };
+  while (true) {
+    stage(r0);
+    if (cc.t >= ntask) break;
+    stage(r1);
+    if (cc.t >= ntask) break;
   }
 }
 
