@@ -211,23 +211,19 @@ typedef double pd2 __attribute__((ext_vector_type(2)));
 // accumulators each.  Operand layout of v_mfma_f64_16x16x4f64 (lane l):
 //   A: row l%16, k l/16;  B: k l/16, col l%16;  accumulator element r:
 //   row l/16 + 4r, col l%16 (checked on gfx950 with an in-bounds probe).
-__device__ inline void mfma_abt(const double* A, const double* B, double* As, double* Bs, v4d acc[4]) {
-  const double2* A2 = reinterpret_cast<const double2*>(A);
-  const double2* B2 = reinterpret_cast<const double2*>(B);
-  double2* As2 = reinterpret_cast<double2*>(As);
-  double2* Bs2 = reinterpret_cast<double2*>(Bs);
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int idx = threadIdx.x + 256 * s;
-    As2[idx] = A2[idx];
-    Bs2[idx] = B2[idx];
-  }
-  __syncthreads();
+// The tiles pass through LDS one half of k at a time (columns 0..31 or
+// 32..63 of a column-major tile: its two contiguous 16 KB halves); this
+// accumulates one half.  Unrolled by two only: at four waves per SIMD the
+// kernels using it have 128 VGPRs, and a full unroll hoists every LDS
+// operand into registers and spills.
+constexpr int KHALF = T * T / 2;
+
+__device__ __attribute__((always_inline)) inline void mfma_khalf_lds(const double* As, const double* Bs, v4d acc[4]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int li = lane & 15, lk = lane >> 4;
-#pragma unroll
-  for (int kk = 0; kk < T / 4; ++kk) {
+#pragma unroll 2
+  for (int kk = 0; kk < T / 8; ++kk) {
     const int k = 4 * kk + lk;
     const double a0 = As[k * T + 32 * wr + li];
     const double a1 = As[k * T + 32 * wr + 16 + li];
@@ -238,7 +234,6 @@ __device__ inline void mfma_abt(const double* A, const double* B, double* As, do
     acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[2], 0, 0, 0);
     acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[3], 0, 0, 0);
   }
-  __syncthreads();
 }
 
 // C = beta * C + sign * acc for the calling wave's quadrant.
@@ -259,16 +254,6 @@ __device__ inline void store_quadrant(double* C, const v4d acc[4], double beta, 
   }
 }
 
-// Panel solve as a product with the inverted diagonal tile: X = A L_jj^{-T}.
-__global__ __launch_bounds__(256) void k_trsm_inv(double* pool, const double* inv, const int64_t* task) {
-  __shared__ __align__(16) double As[T * T];
-  __shared__ __align__(16) double Bs[T * T];
-  const int64_t* tk = task + 2 * blockIdx.x;
-  double* A = pool + tk[0];
-  v4d acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-  mfma_abt(A, inv + tk[1], As, Bs, acc);
-  store_quadrant(A, acc, 0.0, 1.0);
-}
 
 // C -= sum_p A_p B_p^T over the pairs of one target tile (all its pending
 // contributions), accumulated in registers and written once.  Each workgroup
@@ -281,8 +266,6 @@ __global__ __launch_bounds__(256) void k_trsm_inv(double* pool, const double* in
 // LDS (64 KB per workgroup, two per CU) keeps, which hides more of the memory
 // latency behind the matrix cores.  Every target sums its pairs in order and
 // k ascending.
-constexpr int KHALF = T * T / 2;
-
 struct UpdCursor {
   int64_t t, p0, np, q;
   int h;
@@ -320,27 +303,6 @@ __device__ __attribute__((always_inline)) inline void upd_load_half(const double
   }
 }
 
-// acc += A B^T over one half of k of LDS-staged half tiles (the operand
-// layout of mfma_abt); unrolled by two only: at four waves per SIMD the
-// update kernel has 128 VGPRs, and a full unroll hoists every LDS operand
-// into registers and spills.
-__device__ __attribute__((always_inline)) inline void mfma_khalf_lds(const double* As, const double* Bs, v4d acc[4]) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  const int li = lane & 15, lk = lane >> 4;
-#pragma unroll 2
-  for (int kk = 0; kk < T / 8; ++kk) {
-    const int k = 4 * kk + lk;
-    const double a0 = As[k * T + 32 * wr + li];
-    const double a1 = As[k * T + 32 * wr + 16 + li];
-    const double b0 = Bs[k * T + 32 * wc + li];
-    const double b1 = Bs[k * T + 32 * wc + 16 + li];
-    acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0], 0, 0, 0);
-    acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[1], 0, 0, 0);
-    acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[2], 0, 0, 0);
-    acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[3], 0, 0, 0);
-  }
-}
 
 __global__ __launch_bounds__(256, 4) void k_update_multi(double* pool, const int64_t* task, const int64_t* pair,
                                                         int64_t ntask) {
@@ -386,6 +348,41 @@ __global__ __launch_bounds__(256, 4) void k_update_multi(double* pool, const int
     stage(r1);
     if (cc.t >= ntask) break;
   }
+}
+
+// Panel solve as a product with the inverted diagonal tile, X = A L_jj^{-T},
+// one workgroup per tile: both operand tiles are loaded into registers at
+// once and pass through LDS one half of k at a time (32 KB of LDS, so four
+// workgroups share a CU and 256 KB of operands are in flight per CU, twice
+// what whole tiles in LDS allow).
+__global__ __launch_bounds__(256, 4) void k_trsm_inv(double* pool, const double* inv, const int64_t* task) {
+  __shared__ __align__(16) double As[KHALF];
+  __shared__ __align__(16) double Bs[KHALF];
+  pd2* As2 = reinterpret_cast<pd2*>(As);
+  pd2* Bs2 = reinterpret_cast<pd2*>(Bs);
+  const int64_t* tk = task + 2 * blockIdx.x;
+  double* A = pool + tk[0];
+  const pd2* A2 = reinterpret_cast<const pd2*>(A);
+  const pd2* B2 = reinterpret_cast<const pd2*>(inv + tk[1]);
+  pd2 ra[8], rb[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    ra[s] = A2[threadIdx.x + 256 * s];
+    rb[s] = B2[threadIdx.x + 256 * s];
+  }
+  v4d acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h) __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      As2[threadIdx.x + 256 * s] = ra[4 * h + s];
+      Bs2[threadIdx.x + 256 * s] = rb[4 * h + s];
+    }
+    __syncthreads();
+    mfma_khalf_lds(As, Bs, acc);
+  }
+  store_quadrant(A, acc, 0.0, 1.0);
 }
 
 // Copy (scaled) tiles into dense row-major blocks; optional mirrored copy.
