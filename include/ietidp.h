@@ -360,7 +360,7 @@ int ieti_get_gemv_tuning(const ieti_handle* h, int32_t* variant, float* ms);
  * update total ms, update tasks executed, FP64 interface-block bytes read per
  * GEMV application with the chosen FP64 shape, the same for the
  * row-streaming shapes (whole padded blocks), the same for the symmetric
- * shape (padded lower tiles), the algorithmic FP64 bytes of one application
+ * shape (lower tiles, the entries inside n_I), the algorithmic FP64 bytes of one application
  * (8 sum_k n_I,k (n_I,k + 1) / 2, no padding), FP32 GEMV launches, FP32
  * GEMV total ms, 0}.  With the symmetric shape the GEMV launches and times
  * are those of its tile kernel. */

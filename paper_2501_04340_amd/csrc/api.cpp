@@ -81,7 +81,7 @@ struct ieti_handle {
   DBuf<int32_t> sym_tprob, sym_bprob;
   DBuf<double> sym_part;
   ieti::dev::SymGemv symg;
-  double sym_elems = 0.0;  // matrix entries read per symmetric application (lower tiles)
+  double sym_elems = 0.0;  // matrix entries read per symmetric application (lower tiles inside n_I)
   DBuf<int32_t> I_row, I_sub, glob2loc;
   DBuf<double> yj;  // L_rr^{-1} j_r of the right-hand side's forward solve (augmented layout)
   DBuf<double> lam, r, z, p, q, v, b, e, dtil, w, t, pglob, part, scal, aout, tmp;
@@ -421,14 +421,16 @@ int upload(ieti_handle* h) {
           const int64_t ntile = std::min(ST, I + 1 - t0);
           auto& rec = by_size[ntile];
           rec.insert(rec.end(), {sp.S_off + 64 * I * sp.nIp + 64 * t0, sp.nIp, 64 * ntile, sp.I_off + 64 * I,
-                                 sp.I_off + 64 * t0, pbase[I] + 64 * (t0 / ST)});
+                                 sp.I_off + 64 * t0, pbase[I] + 64 * (t0 / ST),
+                                 std::min<int64_t>(64, sp.nI - 64 * I), std::min<int64_t>(64 * ntile, sp.nI - 64 * t0)});
           for (int64_t c = 0; c < ST; ++c) {
             const int64_t t = t0 + c;
             // column partial of tile (I, t), t < I: entry (t / ST + 1) + (I - t - 1) of block t
             rec.push_back(c < ntile && t < I ? pbase[t] + 64 * ((t + ST) / ST + (I - t - 1)) : -1);
           }
           prob_by_size[ntile].push_back(pk);
-          h->sym_elems += double(64 * 64) * double(ntile);
+          h->sym_elems += double(std::min<int64_t>(64, sp.nI - 64 * I)) *
+                          double(std::min<int64_t>(64 * ntile, sp.nI - 64 * t0));
         }
     }
     // Launch order.  The tile kernel holds two workgroups per CU; the first
@@ -439,7 +441,7 @@ int upload(ieti_handle* h) {
     // first-round task), with empty records (0 columns: the workgroup exits)
     // where a CU gets no second task.  Otherwise the tasks go largest first.
     {
-      const size_t rec = size_t(6 + ST);
+      const size_t rec = size_t(ieti::dev::SYM_TASK);
       std::vector<std::pair<int64_t, int64_t>> order;  // (tile count, index within its size class)
       for (int64_t n = ST; n >= 1; --n)
         for (size_t i = 0; i < prob_by_size[n].size(); ++i) order.emplace_back(n, int64_t(i));

@@ -804,6 +804,7 @@ __global__ __launch_bounds__(64 * SYM_WAVES, 2) void k_gemv_sym(const MT* M, con
   const MT* A = M + tk[0];
   const int64_t ld = tk[1];
   const int ncols = int(tk[2]);
+  const int nrows_in = int(tk[6]), ncols_in = int(tk[7]);  // inside n_I: the padding is not read
   const double* xr = xg + tk[3];
   const double* xc = xg + tk[4];
   const int lane = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -813,7 +814,7 @@ __global__ __launch_bounds__(64 * SYM_WAVES, 2) void k_gemv_sym(const MT* M, con
     const int c0 = V::N * (lane + 64 * j);
 #pragma unroll
     for (int e = 0; e < V::N; ++e) {
-      x[j][e] = c0 < ncols ? xc[c0 + e] : 0.0;
+      x[j][e] = c0 < ncols_in ? xc[c0 + e] : 0.0;
       cacc[j][e] = 0.0;
     }
   }
@@ -824,9 +825,10 @@ __global__ __launch_bounds__(64 * SYM_WAVES, 2) void k_gemv_sym(const MT* M, con
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const T* row = reinterpret_cast<const T*>(A + (RW * q + i + r) * ld);
+      const bool in = RW * q + i + r < nrows_in;
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
-        mv[r][j] = V::N * (lane + 64 * j) < ncols ? __builtin_nontemporal_load(row + lane + 64 * j) : T(0);
+        mv[r][j] = in && V::N * (lane + 64 * j) < ncols_in ? __builtin_nontemporal_load(row + lane + 64 * j) : T(0);
     }
     double racc[RB];
 #pragma unroll
@@ -851,7 +853,7 @@ __global__ __launch_bounds__(64 * SYM_WAVES, 2) void k_gemv_sym(const MT* M, con
     for (int e = 0; e < V::N; ++e) cred[q][V::N * (lane + 64 * j) + e] = cacc[j][e];
   __syncthreads();
   for (int c = threadIdx.x; c < ncols; c += 64 * SYM_WAVES) {
-    const int64_t dst = tk[6 + (c >> 6)];
+    const int64_t dst = tk[8 + (c >> 6)];
     if (dst >= 0) {
       double sum = 0.0;
 #pragma unroll

@@ -105,10 +105,12 @@ constexpr int SYM_TILES = 8;
 constexpr int SYM_WAVES = 8;  // waves per task (64 / SYM_WAVES rows each)
 constexpr int GEMV_SYM = GEMV_VARIANTS;
 constexpr int GEMV_SHAPES = GEMV_VARIANTS + 1;
-constexpr int SYM_TASK = 6 + SYM_TILES;  // int64 per task
+constexpr int SYM_TASK = 8 + SYM_TILES;  // int64 per task
 struct SymGemv {
   // task: [matrix offset of tile (I, t0), ld, ncols, slot of tile row I, slot of tile column t0,
-  //        destination of the row partial, destinations of the SYM_TILES column partials (-1: none)]
+  //        destination of the row partial, rows of tile row I inside n_I, columns from t0 inside
+  //        n_I, destinations of the SYM_TILES column partials (-1: none)]; the entries outside
+  //        n_I (the padding of the last tile row and column) are not read
   const int64_t* task = nullptr;
   const int32_t* task_prob = nullptr;
   int64_t ntask = 0;
