@@ -236,24 +236,47 @@ __device__ __attribute__((always_inline)) inline void mfma_khalf_lds(const doubl
   }
 }
 
-// C = beta * C + sign * acc for the calling wave's quadrant.
-__device__ inline void store_quadrant(double* C, const v4d acc[4], double beta, double sign) {
+// A 64x64 tile in LDS with columns padded to 65 entries: the MFMA layout's
+// lanes run along columns 64 entries apart, which the padding spreads over
+// the banks.  acc_to_lds writes the calling wave's accumulator quadrant
+// there; lds_to_tile then writes the tile to global memory (C = L, or
+// C = C - L) two entries of one column per thread and step, in whole
+// coalesced lines, where direct stores from the MFMA layout write 32-byte
+// pieces of 16 columns at once.
+constexpr int LDT = T + 1;
+
+__device__ __attribute__((always_inline)) inline void acc_to_lds(double* Ls, const v4d acc[4]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r0 = 32 * (w >> 1) + (lane >> 4), c0 = 32 * (w & 1) + (lane & 15);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int rr = r0 + 4 * r;
-    double* c00 = C + (c0)*T + rr;
-    double* c01 = C + (c0 + 16) * T + rr;
-    double* c10 = C + (c0)*T + rr + 16;
-    double* c11 = C + (c0 + 16) * T + rr + 16;
-    *c00 = beta * *c00 + sign * acc[0][r];
-    *c01 = beta * *c01 + sign * acc[1][r];
-    *c10 = beta * *c10 + sign * acc[2][r];
-    *c11 = beta * *c11 + sign * acc[3][r];
+    Ls[c0 * LDT + rr] = acc[0][r];
+    Ls[(c0 + 16) * LDT + rr] = acc[1][r];
+    Ls[c0 * LDT + rr + 16] = acc[2][r];
+    Ls[(c0 + 16) * LDT + rr + 16] = acc[3][r];
   }
 }
 
+template <bool SUB>
+__device__ __attribute__((always_inline)) inline void lds_to_tile(double* C, const double* Ls) {
+  pd2* C2 = reinterpret_cast<pd2*>(C);
+#pragma unroll 2
+  for (int s = 0; s < T * T / 512; ++s) {
+    const int v = threadIdx.x + 256 * s, e = 2 * v;  // entries e, e + 1 of one column
+    const double* l = Ls + (e >> 6) * LDT + (e & 63);
+    pd2 c;
+    if (SUB) {
+      c = C2[v];
+      c.x = c.x - l[0];
+      c.y = c.y - l[1];
+    } else {
+      c.x = l[0];
+      c.y = l[1];
+    }
+    C2[v] = c;
+  }
+}
 
 // C -= sum_p A_p B_p^T over the pairs of one target tile (all its pending
 // contributions), accumulated in registers and written once.  Each workgroup
@@ -306,8 +329,11 @@ __device__ __attribute__((always_inline)) inline void upd_load_half(const double
 
 __global__ __launch_bounds__(256, 4) void k_update_multi(double* pool, const int64_t* task, const int64_t* pair,
                                                         int64_t ntask) {
-  __shared__ __align__(16) double As[KHALF];
-  __shared__ __align__(16) double Bs[KHALF];
+  // the stage's two half tiles; at a target's end the same LDS holds its
+  // accumulated product (padded columns, acc_to_lds)
+  __shared__ __align__(16) double Ls[T * LDT];
+  double* As = Ls;
+  double* Bs = Ls + KHALF;
   pd2* As2 = reinterpret_cast<pd2*>(As);
   pd2* Bs2 = reinterpret_cast<pd2*>(Bs);
   const int64_t stride = gridDim.x;
@@ -336,7 +362,11 @@ __global__ __launch_bounds__(256, 4) void k_update_multi(double* pool, const int
     upd_advance(cl, task, ntask, stride);
     mfma_khalf_lds(As, Bs, acc);
     if (cc.h == 1 && cc.q + 1 == cc.np) {
-      store_quadrant(pool + task[3 * cc.t], acc, 1.0, -1.0);
+      // C -= acc through LDS (whole coalesced lines of C)
+      __syncthreads();
+      acc_to_lds(Ls, acc);
+      __syncthreads();
+      lds_to_tile<true>(pool + task[3 * cc.t], Ls);
 #pragma unroll
       for (int m = 0; m < 4; ++m) acc[m] = v4d{0, 0, 0, 0};
     }
@@ -352,12 +382,14 @@ __global__ __launch_bounds__(256, 4) void k_update_multi(double* pool, const int
 
 // Panel solve as a product with the inverted diagonal tile, X = A L_jj^{-T},
 // one workgroup per tile: both operand tiles are loaded into registers at
-// once and pass through LDS one half of k at a time (32 KB of LDS, so four
+// once and pass through LDS one half of k at a time (33 KB of LDS, so four
 // workgroups share a CU and 256 KB of operands are in flight per CU, twice
-// what whole tiles in LDS allow).
+// what whole tiles in LDS allow); X overwrites A through the same LDS in
+// whole lines, with no second read of A.
 __global__ __launch_bounds__(256, 4) void k_trsm_inv(double* pool, const double* inv, const int64_t* task) {
-  __shared__ __align__(16) double As[KHALF];
-  __shared__ __align__(16) double Bs[KHALF];
+  __shared__ __align__(16) double Ls[T * LDT];  // the half tiles, then the product
+  double* As = Ls;
+  double* Bs = Ls + KHALF;
   pd2* As2 = reinterpret_cast<pd2*>(As);
   pd2* Bs2 = reinterpret_cast<pd2*>(Bs);
   const int64_t* tk = task + 2 * blockIdx.x;
@@ -382,7 +414,10 @@ __global__ __launch_bounds__(256, 4) void k_trsm_inv(double* pool, const double*
     __syncthreads();
     mfma_khalf_lds(As, Bs, acc);
   }
-  store_quadrant(A, acc, 0.0, 1.0);
+  __syncthreads();
+  acc_to_lds(Ls, acc);
+  __syncthreads();
+  lds_to_tile<false>(A, Ls);
 }
 
 // Copy (scaled) tiles into dense row-major blocks; optional mirrored copy.
