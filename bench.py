@@ -220,7 +220,8 @@ def ring_warm_start(args):
     W.attach()
     variants = {"plain_cold": (PREC_FP64, False), "plain_warm": (PREC_FP64, True),
                 "mixed_cold": (PREC_MIXED, False), "mixed_warm": (PREC_MIXED, True)}
-    res = {k: {"tts_ms": [], "iters": [], "r0": [], "fallback": 0, "applies": 0, "pcg_s": 0.0} for k in variants}
+    res = {k: {"tts_ms": [], "iters": [], "r0": [], "fallback": 0, "applies": 0, "pcg_s": 0.0, "factor_ms": [],
+               "solve_ms": []} for k in variants}
     lam_err = []
     for i in range(n_train, n_train + n_test):
         nu, scale = draw(i)
@@ -239,6 +240,8 @@ def ring_warm_start(args):
             r["fallback"] += int(st["warm_start"] == -1)
             r["applies"] += st["f_applies"]
             r["pcg_s"] += st["t_pcg_s"]
+            r["factor_ms"].append(st["t_factor_s"] * 1e3)
+            r["solve_ms"].append(st["t_solve_s"] * 1e3)
             lam = S.lambda_()
             if lam_ref is None:
                 lam_ref = lam
@@ -248,11 +251,13 @@ def ring_warm_start(args):
             log(f"held-out {i - n_train + 1}/{n_test}: " + ", ".join(
                 f"{k} {np.median(v['tts_ms']):.1f}ms/{np.mean(v['iters']):.1f}it" for k, v in res.items()))
     S.factor(precision=PREC_FP64, **fkw)
+    chosen, tune_ms = S.gemv_tuning()
     summ = {}
     for k, v in res.items():
         summ[k] = {"tts_ms_p50": float(np.median(v["tts_ms"])), "tts_ms_p99": float(np.percentile(v["tts_ms"], 99)),
                    "pcg_iters_mean": float(np.mean(v["iters"])), "rel_residual0_median": float(np.median(v["r0"])),
-                   "fallbacks": v["fallback"], "f_applies_per_s": v["applies"] / v["pcg_s"] if v["pcg_s"] else None}
+                   "fallbacks": v["fallback"], "f_applies_per_s": v["applies"] / v["pcg_s"] if v["pcg_s"] else None,
+                   "factor_ms_p50": float(np.median(v["factor_ms"])), "solve_ms_p50": float(np.median(v["solve_ms"]))}
     base = summ["plain_cold"]["tts_ms_p50"]
     for k in summ:
         summ[k]["speedup_vs_plain_cold"] = base / summ[k]["tts_ms_p50"]
@@ -264,6 +269,8 @@ def ring_warm_start(args):
         "config": {"workload": WORKLOADS["ring576"], "variant": "mixed + warm start, held-out draws",
                    "n_g": S.n_global, "n_sub": S.n_sub, "m_r": S.m_r, "n_gp": S.n_gp, "rtol": args.rtol},
         "variants": summ,
+        "gemv_autotune": {"fp64_shape": int(chosen[0]), "fp64_ms": [float(x) for x in tune_ms[0]],
+                          "fp32_shape": int(chosen[1]), "fp32_ms": [float(x) for x in tune_ms[1]]},
         "warm_start": {"train_solves": n_train, "held_out": n_test, "data_s": t_gen, "train_s": t_train,
                        "epochs": args.nn_epochs, "hidden": args.nn_hidden, "params": W.net.n_params,
                        "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
