@@ -67,7 +67,7 @@ struct ieti_handle {
   ieti::CoarsePlan cplan;
   DBuf<double> cpool, cinv, ctol, Lti;
   DBuf<int64_t> cfill, cpotrf, ctrsm, cupd, cupd_pair, cout_h, cout_l;
-  DBuf<int64_t> scatter_dst, potrf, trsm, upd, upd_pair, copyS, xsinv, xphi, xspi, fdiag, ffull, ffull_pair, rec_task, rec_pair;
+  DBuf<int64_t> scatter_dst, tile_ptr, potrf, trsm, upd, upd_pair, copyS, xsinv, xphi, xspi, fdiag, ffull, ffull_pair, rec_task, rec_pair;
   DBuf<int64_t> bdiag, bupd, bupd_pair;
   DBuf<int64_t> spi_ptr, spi_src, row_src, I_aug, A_aug, slot_phi_row, dsrc_ptr, dsrc_idx, recP_pos, recP_glob;
   DBuf<int64_t> out_src, out_edge, primal_edges, d_edges;  // d_edges: prescribed boundary coefficients
@@ -161,7 +161,7 @@ struct ieti_handle {
                           &yj, &lam, &r, &z, &p, &q, &v, &b, &e, &dtil, &w, &t, &pglob, &part, &scal, &aout,
                           &tmp, &xgp, &xgr, &part_g, &part_t, &lam_acc, &rtrue, &cpool, &cinv, &ctol, &Lti, &tvec};
     for (auto* d : ds) d->release();
-    DBuf<int64_t>* is[] = {&scatter_dst, &potrf, &trsm, &upd, &upd_pair, &copyS, &xsinv, &xphi, &xspi, &fdiag,
+    DBuf<int64_t>* is[] = {&scatter_dst, &tile_ptr, &potrf, &trsm, &upd, &upd_pair, &copyS, &xsinv, &xphi, &xspi, &fdiag,
                            &ffull, &ffull_pair, &rec_task, &rec_pair, &bdiag, &bupd, &bupd_pair, &spi_ptr, &spi_src, &row_src, &I_aug, &A_aug, &slot_phi_row, &dsrc_ptr,
                            &dsrc_idx, &recP_pos, &recP_glob, &out_src, &out_edge, &primal_edges,
                            &gemv_tasks[0], &gemv_tasks[1], &gemv_tasks[2], &cfill, &cpotrf, &ctrsm, &cupd,
@@ -317,6 +317,7 @@ int upload(ieti_handle* h) {
 #define UP(buf, vec) \
   if ((rc = dupload(h->buf, vec))) return rc;
   UP(scatter_dst, P.scatter_dst);
+  UP(tile_ptr, P.tile_ptr);
   UP(scatter_val, P.scatter_val);
   UP(piv_tol, P.piv_tol);
   UP(potrf, P.potrf_task);
@@ -671,8 +672,8 @@ void prof_collect(ieti_handle* h) {
 void enqueue_local_factor(ieti_handle* h, hipStream_t s) {
   namespace D = ieti::dev;
   const auto& P = h->plan;
-  D::fill(h->pool.ptr, P.pool_elems, 0.0, s);
-  D::scatter(h->pool.ptr, h->scatter_dst.ptr, h->scatter_val.ptr, int64_t(P.scatter_dst.size()), s);
+  D::assemble_tiles(h->pool.ptr, h->scatter_dst.ptr, h->scatter_val.ptr, h->tile_ptr.ptr,
+                    int64_t(P.tile_ptr.size()) - 1, s);
   for (int64_t j = 0; j < P.n_steps; ++j) {
     D::copy_tiles(h->pool.ptr, h->copyS.ptr + 5 * P.copy_ptr[j], P.copy_ptr[j + 1] - P.copy_ptr[j], 1.0, h->S.ptr, s);
     D::potrf_tiles(h->pool.ptr, h->inv.ptr, h->potrf.ptr + 3 * P.potrf_ptr[j], P.potrf_ptr[j + 1] - P.potrf_ptr[j],

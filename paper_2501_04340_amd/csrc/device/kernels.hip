@@ -22,6 +22,8 @@ namespace dev {
 namespace {
 
 constexpr int T = TILE;
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double pd2 __attribute__((ext_vector_type(2)));
 
 // Value of lane `src` (wave-uniform) of a double, through two readlanes.
 __device__ inline double readlane_f64(double v, int src) {
@@ -75,9 +77,33 @@ __global__ void k_fill(double* p, int64_t n, double v) {
     p[i] = v;
 }
 
-__global__ void k_scatter(double* pool, const int64_t* dst, const double* val, int64_t n) {
+// out[dst[i]] = val[i] (distinct destinations).
+__global__ void k_scatter(double* out, const int64_t* dst, const double* val, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    pool[dst[i]] = val[i];
+    out[dst[i]] = val[i];
+}
+
+// The tile pool from the assembled entries: each tile is zeroed in LDS, its
+// entries (one range of the destination-ordered list) placed there, and the
+// tile written once in whole coalesced lines, in place of a fill of the
+// whole pool followed by scattered 8-byte writes.
+__global__ __launch_bounds__(256) void k_assemble_tiles(double* pool, const int64_t* dst, const double* val,
+                                                        const int64_t* tile_ptr, int64_t ntile) {
+  __shared__ __align__(16) double L[TILE * TILE];
+  pd2* L2 = reinterpret_cast<pd2*>(L);
+  constexpr int64_t TT = int64_t(TILE) * TILE;
+  for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+#pragma unroll
+    for (int s = 0; s < int(TT / 512); ++s) L2[threadIdx.x + 256 * s] = pd2{0.0, 0.0};
+    __syncthreads();
+    const int64_t base = t * TT;
+    for (int64_t i = tile_ptr[t] + threadIdx.x; i < tile_ptr[t + 1]; i += 256) L[dst[i] - base] = val[i];
+    __syncthreads();
+    pd2* out = reinterpret_cast<pd2*>(pool + base);
+#pragma unroll
+    for (int s = 0; s < int(TT / 512); ++s) out[threadIdx.x + 256 * s] = L2[threadIdx.x + 256 * s];
+    __syncthreads();
+  }
 }
 
 // Cholesky of one 64x64 diagonal tile followed by the inverse of its lower
@@ -203,8 +229,6 @@ __global__ __launch_bounds__(256) void k_potrf_inv(double* pool, double* inv, co
   if (bad && lane == 0) atomicMax(err, sub + 1);
 }
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef double pd2 __attribute__((ext_vector_type(2)));
 
 // Accumulate A B^T (64x64 tiles, column-major) into the calling wave's
 // 32x32 quadrant on the FP64 matrix cores.  Four waves, 2x2 blocks of 16x16
@@ -1277,9 +1301,15 @@ void fill(double* p, int64_t n, double v, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
 }
-void scatter(double* pool, const int64_t* dst, const double* val, int64_t n, hipStream_t s) {
+void scatter(double* out, const int64_t* dst, const double* val, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, pool, dst, val, n);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, out, dst, val, n);
+}
+void assemble_tiles(double* pool, const int64_t* dst, const double* val, const int64_t* tile_ptr, int64_t ntile,
+                    hipStream_t s) {
+  if (ntile <= 0) return;
+  const int64_t nwg = ntile < 4096 ? ntile : 4096;
+  hipLaunchKernelGGL(k_assemble_tiles, dim3(nwg), dim3(256), 0, s, pool, dst, val, tile_ptr, ntile);
 }
 void potrf_tiles(double* pool, double* inv, const int64_t* task, int64_t ntask, const double* piv_tol, int* err,
                  hipStream_t s) {

@@ -12,7 +12,12 @@ constexpr int TILE = 64;
 
 // ---- factorisation (tile pool, column-major 64x64 tiles)
 void fill(double* p, int64_t n, double v, hipStream_t s);
-void scatter(double* pool, const int64_t* dst, const double* val, int64_t n, hipStream_t s);
+// out[dst[i]] = val[i], i < n (distinct destinations)
+void scatter(double* out, const int64_t* dst, const double* val, int64_t n, hipStream_t s);
+// the tile pool from the assembled entries (destination-ordered, tile t's in
+// tile_ptr[t] .. tile_ptr[t + 1] - 1), every tile written whole
+void assemble_tiles(double* pool, const int64_t* dst, const double* val, const int64_t* tile_ptr, int64_t ntile,
+                    hipStream_t s);
 // potrf task [off_jj, subdomain, off of the inverse]; writes L_jj and L_jj^{-1}; a pivot not
 // above piv_tol[subdomain] flags the subdomain in err
 void potrf_tiles(double* pool, double* inv, const int64_t* task, int64_t ntask, const double* piv_tol, int* err,

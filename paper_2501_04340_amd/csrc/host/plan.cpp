@@ -452,6 +452,14 @@ int build_plan(const Model& m, int T, int ordering, Plan& plan, Error& err, cons
     std::vector<int64_t>().swap(sdst[k]);
     std::vector<int64_t>().swap(ssrc[k]);
   }
+  // the pool is whole tiles and the list is in destination order: each
+  // tile's entries form one range
+  {
+    const int64_t TT = int64_t(T) * T;
+    plan.tile_ptr.assign(size_t(plan.pool_elems / TT) + 1, 0);
+    for (int64_t d : plan.scatter_dst) ++plan.tile_ptr[size_t(d / TT) + 1];
+    for (size_t t = 1; t < plan.tile_ptr.size(); ++t) plan.tile_ptr[t] += plan.tile_ptr[t - 1];
+  }
   }
   // ---------------------------------------------------------------- level schedule
   // Column j of the tile factor depends on every column k < j with a tile

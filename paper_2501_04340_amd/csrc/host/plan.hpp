@@ -61,8 +61,9 @@ struct Plan {
   std::vector<int64_t> upd_pair;     // [off_ij, off_lj]
   std::vector<int64_t> copy_task;    // [off_tile, dst_offset_in_S, ld (= nIp), transpose-needed]
   // scatter of the assembled entries into the tile pool
-  std::vector<int64_t> scatter_dst;
+  std::vector<int64_t> scatter_dst;  // in destination order
   std::vector<double> scatter_val;
+  std::vector<int64_t> tile_ptr;     // pool tile t (offset T*T*t): entries tile_ptr[t] .. tile_ptr[t + 1] - 1
   std::vector<int64_t> scatter_src;  // per entry: index into the concatenated CSR values, -1 = constant 1
                                      // (E_I), -2 - k = identity dummy of subdomain k
   // dense S / Sinv storage

@@ -1,7 +1,9 @@
 // Host-side check of the factorisation schedule (test program, CPU only).
 //
 // Builds the library's plan for a box problem and runs its task lists in
-// plain loops, as the GPU kernels define them: per level the S_rIrI copies,
+// plain loops, as the GPU kernels define them (the tile pool from the
+// destination-ordered entries, each tile's entries one range of the list):
+// per level the S_rIrI copies,
 // the diagonal-tile Cholesky with the inverse of its factor, the panel
 // solves A L^{-T}, and the deferred updates C -= sum A B^T.  Then every tile
 // of every subdomain is compared with the definition of the partial
@@ -94,6 +96,18 @@ int main(int argc, char** argv) {
     }
     pool[size_t(plan.scatter_dst[i])] = plan.scatter_val[i];
   }
+  // the per-tile ranges of the destination-ordered list (the tile assembly's input)
+  if (plan.tile_ptr.size() != size_t(plan.pool_elems / TT) + 1 || plan.tile_ptr.front() != 0 ||
+      plan.tile_ptr.back() != int64_t(plan.scatter_dst.size())) {
+    std::printf("scatter: tile ranges do not cover the list\n");
+    return 1;
+  }
+  for (size_t t = 0; t + 1 < plan.tile_ptr.size(); ++t)
+    for (int64_t i = plan.tile_ptr[t]; i < plan.tile_ptr[t + 1]; ++i)
+      if (plan.scatter_dst[size_t(i)] / TT != int64_t(t)) {
+        std::printf("scatter: entry %ld outside its tile range\n", long(i));
+        return 1;
+      }
   const std::vector<double> A0 = pool;
   std::vector<double> S(size_t(plan.S_elems), 0.0);
   int64_t products = 0;
