@@ -307,12 +307,13 @@ __device__ __attribute__((always_inline)) inline void lds_to_tile(double* C, con
 // walks tasks b, b + gridDim.x, ... and their pairs as one sequence of
 // stages, a stage being one half of k of one pair (columns 0..31 or 32..63 of
 // both column-major tiles: their two contiguous 16 KB halves).  The stage's
-// operands go through LDS (32 KB per workgroup, so four workgroups share a
-// CU) while the next two stages load into registers: 256 KB of operands in
-// flight per CU, twice what a one-pair-ahead pipeline with whole tiles in
-// LDS (64 KB per workgroup, two per CU) keeps, which hides more of the memory
-// latency behind the matrix cores.  Every target sums its pairs in order and
-// k ascending.
+// operands go through LDS (32 KB, in a 33 KB tile buffer that also carries
+// the result out; four workgroups share a CU) while the next two stages load
+// into registers: 256 KB of operands in flight per CU, twice what a
+// one-pair-ahead pipeline with whole tiles in LDS (64 KB per workgroup, two
+// per CU) keeps, which hides more of the memory latency behind the matrix
+// cores.  Every target sums its pairs in order and k ascending, and leaves
+// through LDS in whole lines (acc_to_lds, lds_to_tile).
 struct UpdCursor {
   int64_t t, p0, np, q;
   int h;
@@ -349,7 +350,6 @@ __device__ __attribute__((always_inline)) inline void upd_load_half(const double
     r[4 + s] = B2[threadIdx.x + 256 * s];
   }
 }
-
 
 __global__ __launch_bounds__(256, 4) void k_update_multi(double* pool, const int64_t* task, const int64_t* pair,
                                                         int64_t ntask) {
