@@ -83,27 +83,32 @@ __global__ void k_scatter(double* out, const int64_t* dst, const double* val, in
     out[dst[i]] = val[i];
 }
 
-// The tile pool from the assembled entries: each tile is zeroed in LDS, its
-// entries (one range of the destination-ordered list) placed there, and the
-// tile written once in whole coalesced lines, in place of a fill of the
-// whole pool followed by scattered 8-byte writes.
+// The tile pool from the assembled entries: one workgroup per tile; the
+// tile is zeroed in LDS, its entries (one range of the destination-ordered
+// list) placed there, and the tile written once in whole coalesced lines, in
+// place of a fill of the whole pool followed by scattered 8-byte writes.  A
+// tile without entries (fill of the factorisation) is written as zeros
+// directly.
 __global__ __launch_bounds__(256) void k_assemble_tiles(double* pool, const int64_t* dst, const double* val,
-                                                        const int64_t* tile_ptr, int64_t ntile) {
+                                                        const int64_t* tile_ptr) {
   __shared__ __align__(16) double L[TILE * TILE];
   pd2* L2 = reinterpret_cast<pd2*>(L);
   constexpr int64_t TT = int64_t(TILE) * TILE;
-  for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+  const int64_t t = blockIdx.x, base = t * TT;
+  const int64_t p0 = tile_ptr[t], p1 = tile_ptr[t + 1];
+  pd2* out = reinterpret_cast<pd2*>(pool + base);
+  if (p0 == p1) {
 #pragma unroll
-    for (int s = 0; s < int(TT / 512); ++s) L2[threadIdx.x + 256 * s] = pd2{0.0, 0.0};
-    __syncthreads();
-    const int64_t base = t * TT;
-    for (int64_t i = tile_ptr[t] + threadIdx.x; i < tile_ptr[t + 1]; i += 256) L[dst[i] - base] = val[i];
-    __syncthreads();
-    pd2* out = reinterpret_cast<pd2*>(pool + base);
-#pragma unroll
-    for (int s = 0; s < int(TT / 512); ++s) out[threadIdx.x + 256 * s] = L2[threadIdx.x + 256 * s];
-    __syncthreads();
+    for (int s = 0; s < int(TT / 512); ++s) out[threadIdx.x + 256 * s] = pd2{0.0, 0.0};
+    return;
   }
+#pragma unroll
+  for (int s = 0; s < int(TT / 512); ++s) L2[threadIdx.x + 256 * s] = pd2{0.0, 0.0};
+  __syncthreads();
+  for (int64_t i = p0 + threadIdx.x; i < p1; i += 256) L[dst[i] - base] = val[i];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < int(TT / 512); ++s) out[threadIdx.x + 256 * s] = L2[threadIdx.x + 256 * s];
 }
 
 // Cholesky of one 64x64 diagonal tile followed by the inverse of its lower
@@ -1308,8 +1313,7 @@ void scatter(double* out, const int64_t* dst, const double* val, int64_t n, hipS
 void assemble_tiles(double* pool, const int64_t* dst, const double* val, const int64_t* tile_ptr, int64_t ntile,
                     hipStream_t s) {
   if (ntile <= 0) return;
-  const int64_t nwg = ntile < 4096 ? ntile : 4096;
-  hipLaunchKernelGGL(k_assemble_tiles, dim3(nwg), dim3(256), 0, s, pool, dst, val, tile_ptr, ntile);
+  hipLaunchKernelGGL(k_assemble_tiles, dim3(ntile), dim3(256), 0, s, pool, dst, val, tile_ptr);
 }
 void potrf_tiles(double* pool, double* inv, const int64_t* task, int64_t ntask, const double* piv_tol, int* err,
                  hipStream_t s) {
