@@ -669,13 +669,14 @@ void prof_collect(ieti_handle* h) {
 // The local factorisations of every subdomain (Section 2.1, the blocks of
 // K_rr): tile pool from the assembled values, then per level of the schedule
 // the S_rIrI copies, diagonal-tile Cholesky, panel solves and deferred updates.
-void enqueue_local_factor(ieti_handle* h, hipStream_t s) {
+void enqueue_local_factor(ieti_handle* h, hipStream_t s, float* S32 = nullptr) {
   namespace D = ieti::dev;
   const auto& P = h->plan;
   D::assemble_tiles(h->pool.ptr, h->scatter_dst.ptr, h->scatter_val.ptr, h->tile_ptr.ptr,
                     int64_t(P.tile_ptr.size()) - 1, s);
   for (int64_t j = 0; j < P.n_steps; ++j) {
-    D::copy_tiles(h->pool.ptr, h->copyS.ptr + 5 * P.copy_ptr[j], P.copy_ptr[j + 1] - P.copy_ptr[j], 1.0, h->S.ptr, s);
+    D::copy_tiles(h->pool.ptr, h->copyS.ptr + 5 * P.copy_ptr[j], P.copy_ptr[j + 1] - P.copy_ptr[j], 1.0, h->S.ptr, s,
+                  S32);
     D::potrf_tiles(h->pool.ptr, h->inv.ptr, h->potrf.ptr + 3 * P.potrf_ptr[j], P.potrf_ptr[j + 1] - P.potrf_ptr[j],
                    h->piv_tol.ptr, h->flags.ptr, s);
     D::trsm_tiles(h->pool.ptr, h->inv.ptr, h->trsm.ptr + 2 * P.trsm_ptr[j], P.trsm_ptr[j + 1] - P.trsm_ptr[j], s);
@@ -1648,9 +1649,21 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
   // write the real slots only); cleared on the solve stream itself
   D::fill(h->xgp.ptr, h->xgp.n, 0.0, s);
   D::fill(h->xgr.ptr, h->xgr.n, 0.0, s);
+  // mixed precision: FP32 copies of the interface blocks for the inner PCG,
+  // written by the same tile copies as the FP64 blocks
+  const bool mixed = opts && opts->precision == IETI_PREC_MIXED;
+  if (mixed && !h->S32.ptr) {
+    if ((rc = dalloc(h->S32, P.S_elems))) return rc;
+    if ((rc = dalloc(h->Sinv32, P.S_elems))) return rc;
+    if (P.S_elems > 0) {
+      HIP_TRY(hipMemset(h->S32.ptr, 0, size_t(P.S_elems) * sizeof(float)));
+      HIP_TRY(hipMemset(h->Sinv32.ptr, 0, size_t(P.S_elems) * sizeof(float)));
+    }
+  }
   HIP_TRY(hipEventRecord(h->ev0, s));
-  enqueue_local_factor(h, s);
-  D::copy_tiles(h->pool.ptr, h->xsinv.ptr, int64_t(P.xsinv_task.size() / 5), -1.0, h->Sinv.ptr, s);
+  enqueue_local_factor(h, s, mixed ? h->S32.ptr : nullptr);
+  D::copy_tiles(h->pool.ptr, h->xsinv.ptr, int64_t(P.xsinv_task.size() / 5), -1.0, h->Sinv.ptr, s,
+                mixed ? h->Sinv32.ptr : nullptr);
   D::copy_tiles(h->pool.ptr, h->xphi.ptr, int64_t(P.xphi_task.size() / 5), -1.0, h->Phi.ptr, s);
   D::copy_tiles(h->pool.ptr, h->xspi.ptr, int64_t(P.xspi_task.size() / 5), 1.0, h->SPi.ptr, s);
   if (M.n_gp > 0) {
@@ -1672,15 +1685,9 @@ int ieti_factor(ieti_handle* h, const ieti_factor_opts* opts) {
     D::tiles_to_dense(h->cpool.ptr, h->cout_h.ptr, int64_t(C.out_h_task.size() / 7), h->H.ptr, h->Ht.ptr, s);
     D::tiles_to_dense(h->cpool.ptr, h->cout_l.ptr, int64_t(C.out_l_task.size() / 7), h->Lti.ptr, nullptr, s);
   }
-  // mixed precision: FP32 copies of the interface blocks for the inner PCG
-  h->mixed = opts && opts->precision == IETI_PREC_MIXED;
+  // mixed precision: FP32 copies of the coarse rows
+  h->mixed = mixed;
   if (h->mixed) {
-    if (!h->S32.ptr) {
-      if ((rc = dalloc(h->S32, P.S_elems))) return rc;
-      if ((rc = dalloc(h->Sinv32, P.S_elems))) return rc;
-    }
-    D::to_float(h->S.ptr, h->S32.ptr, P.S_elems, s);
-    D::to_float(h->Sinv.ptr, h->Sinv32.ptr, P.S_elems, s);
     if (M.n_gp > 0) {
       if (h->H32.n != h->H.n) {
         if ((rc = dalloc(h->H32, h->H.n))) return rc;

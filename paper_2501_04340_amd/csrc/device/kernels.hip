@@ -449,11 +449,13 @@ __global__ __launch_bounds__(256, 4) void k_trsm_inv(double* pool, const double*
   lds_to_tile<false>(A, Ls);
 }
 
-// Copy (scaled) tiles into dense row-major blocks; optional mirrored copy.
+// Copy (scaled) tiles into dense row-major blocks; optional mirrored copy;
+// with dst32, the same entries rounded to FP32 into a second block of the
+// same layout (the mixed-precision copies, written while the tile is in LDS).
 // The tile is staged in LDS so that both the direct and the mirrored writes
 // run along rows of the destination (consecutive threads, consecutive entries).
 __global__ __launch_bounds__(256) void k_copy_tiles(const double* pool, const int64_t* task, double scale,
-                                                    double* dst) {
+                                                    double* dst, float* dst32) {
   __shared__ double tl[T][T + 1];  // tl[b][a] = entry (a, b) of the tile
   const int64_t* tk = task + 5 * blockIdx.x;
   const double* t = pool + tk[0];
@@ -464,13 +466,19 @@ __global__ __launch_bounds__(256) void k_copy_tiles(const double* pool, const in
   // entry (a, b) to row a, column b: b runs along the threads
   for (int idx = threadIdx.x; idx < T * T; idx += blockDim.x) {
     const int a = idx >> 6, b = idx & (T - 1);
-    if (!(diag && a < b)) dst[d0 + a * ld + b] = tl[b][a];
+    if (!(diag && a < b)) {
+      dst[d0 + a * ld + b] = tl[b][a];
+      if (dst32) dst32[d0 + a * ld + b] = float(tl[b][a]);
+    }
   }
   // entry (a, b) to row b, column a of the mirror: a runs along the threads
   if (dt >= 0)
     for (int idx = threadIdx.x; idx < T * T; idx += blockDim.x) {
       const int b = idx >> 6, a = idx & (T - 1);
-      if (!(diag && a <= b)) dst[dt + b * ld + a] = tl[b][a];
+      if (!(diag && a <= b)) {
+        dst[dt + b * ld + a] = tl[b][a];
+        if (dst32) dst32[dt + b * ld + a] = float(tl[b][a]);
+      }
     }
 }
 
@@ -1331,9 +1339,10 @@ void update_tiles(double* pool, const int64_t* task, const int64_t* pair, int64_
   const int64_t nwg = ntask < cap ? ntask : cap;
   hipLaunchKernelGGL(k_update_multi, dim3(nwg), dim3(256), 0, s, pool, task, pair, ntask);
 }
-void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s) {
+void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s,
+                float* dst32) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(k_copy_tiles, dim3(ntask), dim3(256), 0, s, pool, task, scale, dst);
+  hipLaunchKernelGGL(k_copy_tiles, dim3(ntask), dim3(256), 0, s, pool, task, scale, dst, dst32);
 }
 void trsv_diag(const double* inv, const int64_t* task, int64_t ntask, double* y, bool transposed, hipStream_t s) {
   if (ntask <= 0) return;

@@ -29,7 +29,9 @@ void trsm_tiles(double* pool, const double* inv, const int64_t* task, int64_t nt
 constexpr int64_t UPDATE_WGS = 2048;
 void update_tiles(double* pool, const int64_t* task, const int64_t* pair, int64_t ntask, hipStream_t s,
                   int64_t max_wgs = UPDATE_WGS);
-void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s);
+// dst32 (optional): the same entries rounded to FP32, same layout
+void copy_tiles(const double* pool, const int64_t* task, int64_t ntask, double scale, double* dst, hipStream_t s,
+                float* dst32 = nullptr);
 
 // ---- triangular solves with the tile factor (augmented vectors)
 // diag task [off of L_jj^{-1}, vec_j]: y_j <- L_jj^{-1} y_j (or ^{-T})
